@@ -1,0 +1,478 @@
+/*
+ * Oracle implicit radiation 4-force solve for one cell (Sec. 4.7-4.11).
+ *
+ * TEST INFRASTRUCTURE ONLY (see oracle.h).
+ *
+ * Solves the energy-momentum exchange between gas and radiation over one
+ * implicit sub-step of size dt with rho0 u^t and B^i held fixed (Sec. 4.7):
+ *   T^t_nu(new) - T^t_nu(i) = dt G_nu(new)   (eq. source3, PMHD iteration)
+ *   R^t_nu(new) - R^t_nu(i) = -dt G_nu(new)  (eq. source4, URAD iteration)
+ * with the radiation (gas) part following from total conservation.
+ *
+ * PMHD iterates x = (u_g, u~^i_gas); its Jacobian here is a centred finite
+ * difference.  URAD iterates x = R^t_nu with an MHD inversion inside each
+ * residual and a one-sided finite-difference Jacobian (Sec. 4.9).  Method
+ * order, guesses, pre/post-step checks, stopping rules and the acceptance
+ * cascade follow Sec. 4.10-4.11 in the order given there.
+ */
+#include <float.h>
+#include <math.h>
+#include <string.h>
+#include "oracle.h"
+#include "oracle_internal.h"
+
+#define EPS_M DBL_EPSILON
+#define MAXH 64
+
+typedef struct {
+  const orc_params *p;
+  const orc_geom *g;
+  double gij[3][3];
+  double rhout, B[3];
+  double Tgi[4]; /* explicit gas  (T^t_t + rho u^t, T^t_i), per sqrt(-g) */
+  double Ri[4];  /* explicit radiation R^t_nu, per sqrt(-g) */
+  double dt, chi_abs, chi_es;
+} ictx;
+
+typedef struct {
+  double x[4];
+  double P[12];
+  double Tg[4], Rr[4], G[4];
+  double Eg[4], Er[4];
+  double eT, eIg, eIr;
+  int radflags;
+  int ok;
+} ieval;
+
+enum { M_PMHD = 0, M_URAD = 1 };
+
+static void gas_cons(const ictx *c, const double *P, double Tg[4]) {
+  orc_gas s;
+  orc_gas_state(c->p, c->g, P, &s);
+  Tg[0] = orc_gas_energy_flux(&s, 0);
+  for (int i = 0; i < 3; i++) Tg[1 + i] = s.T[0][1 + i];
+}
+
+static void rad_cons(const ictx *c, const double *P, double Rr[4]) {
+  orc_rad r;
+  orc_rad_state(c->g, P, &r);
+  for (int m = 0; m < 4; m++) Rr[m] = r.R[0][m];
+}
+
+static double snorm(const ictx *c, const double V[4]) {
+  double s = 0.0;
+  for (int i = 0; i < 3; i++)
+    for (int j = 0; j < 3; j++) s += c->gij[i][j] * V[1 + i] * V[1 + j];
+  return sqrt(s > 0.0 ? s : 0.0);
+}
+
+/* Normalised errors (Sec. 4.8): each residual component is divided by the
+ * sum of magnitudes of the terms that build it and its sub-expressions.  The
+ * gas residual T - T(i) - dt G is normalised by gas-scale terms and dt|G|, the
+ * radiation residual R - R(i) + dt G by radiation-scale terms and dt|G|; the
+ * spatial components are merged in the normal observer's orthonormal basis
+ * and also carry the energy scale (so a state at rest is not 0/0).
+ * e_T = (1/4) sum over the four equations of the larger of the two. */
+static void errors(const ictx *c, ieval *e) {
+  double Gdt[4];
+  for (int m = 0; m < 4; m++) Gdt[m] = c->dt * e->G[m];
+  const double nG0 = fabs(Gdt[0]), nGs = snorm(c, Gdt);
+  double Ntg = fabs(e->Tg[0]) + fabs(c->Tgi[0]) + nG0;
+  double Ntr = fabs(e->Rr[0]) + fabs(c->Ri[0]) + nG0;
+  if (!(Ntg > 0.0)) Ntg = 1e-300;
+  if (!(Ntr > 0.0)) Ntr = 1e-300;
+  const double Nsg = snorm(c, e->Tg) + snorm(c, c->Tgi) + nGs + Ntg;
+  const double Nsr = snorm(c, e->Rr) + snorm(c, c->Ri) + nGs + Ntr;
+  double eg[4], er[4];
+  eg[0] = fabs(e->Eg[0]) / Ntg;
+  er[0] = fabs(e->Er[0]) / Ntr;
+  for (int i = 0; i < 3; i++) {
+    const double w = sqrt(c->gij[i][i]);
+    eg[1 + i] = fabs(e->Eg[1 + i]) * w / Nsg;
+    er[1 + i] = fabs(e->Er[1 + i]) * w / Nsr;
+  }
+  if (e->radflags & 1) eg[0] = er[0] = 0.0; /* TYPE2 met E_rad <= 0: energy excluded */
+  double eT = 0.0, eIg = 0.0, eIr = 0.0;
+  for (int m = 0; m < 4; m++) {
+    eT += (eg[m] > er[m] ? eg[m] : er[m]);
+    eIg += eg[m];
+    eIr += er[m];
+  }
+  e->eT = 0.25 * eT;
+  e->eIg = 0.25 * eIg;
+  e->eIr = 0.25 * eIr;
+  if (!isfinite(e->eT)) {
+    e->eT = INFINITY;
+    e->ok = 0;
+  }
+}
+
+static void finish_eval(const ictx *c, ieval *e) {
+  const double rho = e->P[0];
+  orc_four_force(c->p, c->g, e->P, c->chi_abs * rho, c->chi_es * rho, e->G);
+  for (int m = 0; m < 4; m++) {
+    e->Eg[m] = (e->Tg[m] - c->Tgi[m]) - c->dt * e->G[m];
+    e->Er[m] = (e->Rr[m] - c->Ri[m]) + c->dt * e->G[m];
+  }
+  errors(c, e);
+}
+
+/* PMHD residual (Sec. 4.8, PMHD steps in the listed order) */
+static void eval_pmhd(const ictx *c, const double x[4], ieval *e) {
+  memset(e, 0, sizeof(*e));
+  memcpy(e->x, x, sizeof(double) * 4);
+  e->ok = 1;
+  double *P = e->P;
+  P[1] = x[0];
+  for (int i = 0; i < 3; i++) {
+    P[2 + i] = x[1 + i];
+    P[5 + i] = c->B[i];
+  }
+  double ucon[4];
+  orc_ucon(c->g, P + 2, ucon);
+  P[0] = c->rhout / ucon[0];                       /* rho0 = U_1/u^t */
+  gas_cons(c, P, e->Tg);                           /* T^t_mu from gas P */
+  double U[12];
+  memset(U, 0, sizeof(U));
+  for (int m = 0; m < 4; m++)                      /* Delta R = -Delta T */
+    U[8 + m] = c->g->gdet * (c->Ri[m] - (e->Tg[m] - c->Tgi[m]));
+  e->radflags = orc_rad_invert(c->p, c->g, U, 1, P); /* TYPE2 while iterating */
+  rad_cons(c, P, e->Rr);                           /* recompute R for consistency */
+  finish_eval(c, e);
+}
+
+/* URAD residual (Sec. 4.8, URAD steps) */
+static void eval_urad(const ictx *c, const double x[4], const double *Pgas_guess, ieval *e) {
+  memset(e, 0, sizeof(*e));
+  memcpy(e->x, x, sizeof(double) * 4);
+  e->ok = 1;
+  double *P = e->P;
+  double U[12];
+  const double gd = c->g->gdet;
+  U[0] = gd * c->rhout;
+  for (int m = 0; m < 4; m++) U[1 + m] = gd * (c->Tgi[m] - (x[m] - c->Ri[m])); /* Delta T = -Delta R */
+  for (int i = 0; i < 3; i++) U[5 + i] = gd * c->B[i];
+  for (int m = 0; m < 4; m++) U[8 + m] = gd * x[m];
+  const int rc = orc_mhd_invert(c->p, c->g, U, Pgas_guess, P);
+  if (rc != 0) {
+    e->ok = 0;
+    e->eT = INFINITY;
+    return;
+  }
+  e->radflags = orc_rad_invert(c->p, c->g, U, 1, P);
+  gas_cons(c, P, e->Tg);
+  rad_cons(c, P, e->Rr);
+  finish_eval(c, e);
+}
+
+/* Gaussian elimination with partial pivoting: solves J dx = r. 0 on success */
+static int solve4(double J[4][4], const double r[4], double dx[4]) {
+  double A[4][5];
+  for (int i = 0; i < 4; i++) {
+    for (int j = 0; j < 4; j++) A[i][j] = J[i][j];
+    A[i][4] = r[i];
+  }
+  for (int k = 0; k < 4; k++) {
+    int piv = k;
+    for (int i = k + 1; i < 4; i++)
+      if (fabs(A[i][k]) > fabs(A[piv][k])) piv = i;
+    if (!(fabs(A[piv][k]) > 0.0) || !isfinite(A[piv][k])) return 1;
+    if (piv != k)
+      for (int j = 0; j < 5; j++) {
+        const double t = A[k][j];
+        A[k][j] = A[piv][j];
+        A[piv][j] = t;
+      }
+    for (int i = k + 1; i < 4; i++) {
+      const double f = A[i][k] / A[k][k];
+      for (int j = k; j < 5; j++) A[i][j] -= f * A[k][j];
+    }
+  }
+  for (int i = 3; i >= 0; i--) {
+    double s = A[i][4];
+    for (int j = i + 1; j < 4; j++) s -= A[i][j] * dx[j];
+    dx[i] = s / A[i][i];
+  }
+  for (int i = 0; i < 4; i++)
+    if (!isfinite(dx[i])) return 1;
+  return 0;
+}
+
+static double rad_energy_of(const ictx *c, const double R[4]) {
+  const double al = c->g->alpha;
+  double s = 0.0;
+  for (int i = 0; i < 3; i++) s += c->g->gcon[0][1 + i] * R[1 + i];
+  return -R[0] + al * al * s;
+}
+
+/* one Newton attempt with one method (Sec. 4.9-4.10 "normal" Newton, D = 1) */
+static void newton(const ictx *c, int method, const double x0[4], const double *Pgas0, ieval *best,
+                   int *iters) {
+  const orc_params *p = c->p;
+  const double tol = (method == M_PMHD) ? p->tol_pmhd : p->tol_urad;
+  double x[4];
+  memcpy(x, x0, sizeof(x));
+  double Pgas[12];
+  memcpy(Pgas, Pgas0, sizeof(Pgas));
+  ieval ev;
+  if (method == M_PMHD) eval_pmhd(c, x, &ev); else eval_urad(c, x, Pgas, &ev);
+  *best = ev;
+  if (!ev.ok) return;
+  double hist[MAXH];
+  int nh = 0;
+  hist[nh++] = ev.eT;
+  int nrise = 0, extra = 0, conv = 0, nneg = 0;
+  for (int it = 0; it < p->max_iter && nh < MAXH - 1; it++) {
+    /* pre-step checks (Sec. 4.10) */
+    if (ev.eT < tol) conv = 1;
+    if (conv) {
+      if (!p->roundoff || extra >= 3) break;
+      extra++;
+    }
+    if (!conv && it >= 5) {
+      const double avg = (hist[nh - 5] + hist[nh - 4] + hist[nh - 3]) / 3.0;
+      if (ev.eT > 0.5 * avg) break;
+    }
+    /* Jacobian */
+    const double eI = (method == M_PMHD) ? ev.eIg : ev.eIr;
+    const double delta = (eI < 1e-9) ? 1e-10 : 1e-8;
+    double J[4][4];
+    int jfail = 0;
+    if (method == M_PMHD) {
+      for (int j = 0; j < 4; j++) {
+        const double h = (j == 0) ? delta * fabs(x[0]) : delta * (1.0 + fabs(x[j]));
+        double xp[4], xm[4];
+        memcpy(xp, x, sizeof(x));
+        memcpy(xm, x, sizeof(x));
+        xp[j] += h;
+        xm[j] -= h;
+        ieval ep, em;
+        eval_pmhd(c, xp, &ep);
+        eval_pmhd(c, xm, &em);
+        for (int i = 0; i < 4; i++) J[i][j] = (ep.Eg[i] - em.Eg[i]) / (2.0 * h);
+      }
+    } else {
+      /* offsets normalised by the iterated radiation quantities themselves */
+      for (int j = 0; j < 4 && !jfail; j++) {
+        const double N = (j == 0) ? fabs(x[0]) : fabs(x[j]) + fabs(x[0]) / sqrt(c->gij[j - 1][j - 1]);
+        double h = delta * N;
+        int got = 0;
+        for (int tries = 0; tries < 12 && !got; tries++) {
+          double xp[4];
+          memcpy(xp, x, sizeof(x));
+          xp[j] += h;
+          ieval ep;
+          eval_urad(c, xp, ev.P, &ep);
+          if (ep.ok) {
+            for (int i = 0; i < 4; i++) J[i][j] = (ep.Er[i] - ev.Er[i]) / h;
+            got = 1;
+          } else {
+            h = (tries % 2 == 0) ? -h : -10.0 * h; /* other side, then larger */
+            if (fabs(h) > 0.3 * N) break;
+          }
+        }
+        if (!got) jfail = 1;
+      }
+    }
+    if (jfail) break;
+    double dx[4];
+    const double *res = (method == M_PMHD) ? ev.Eg : ev.Er;
+    if (solve4(J, res, dx)) break;
+    double xn[4];
+    for (int i = 0; i < 4; i++) xn[i] = x[i] - dx[i];
+    /* post-step checks (Sec. 4.10) */
+    if (method == M_PMHD) {
+      if (xn[0] < 0.0) xn[0] = 0.5 * fabs(xn[0]);
+    } else {
+      const double Er = rad_energy_of(c, xn);
+      if (Er <= 0.0) {
+        const double al = c->g->alpha;
+        double s = 0.0;
+        for (int i = 0; i < 3; i++) s += c->g->gcon[0][1 + i] * xn[1 + i];
+        xn[0] = -0.5 * fabs(Er) + al * al * s;
+      }
+    }
+    ieval en;
+    if (method == M_PMHD) {
+      eval_pmhd(c, xn, &en);
+    } else {
+      eval_urad(c, xn, ev.P, &en);
+      int back = 0;
+      while (!en.ok && back < 20) { /* back up half-way until the inversion succeeds */
+        nneg++;
+        for (int i = 0; i < 4; i++) xn[i] = 0.5 * (x[i] + xn[i]);
+        eval_urad(c, xn, ev.P, &en);
+        back++;
+      }
+      if (!en.ok || nneg > 3) {
+        (*iters)++;
+        break;
+      }
+    }
+    (*iters)++;
+    int small = 1;
+    for (int i = 0; i < 4; i++)
+      if (fabs(xn[i] - x[i]) > 10.0 * EPS_M * fabs(x[i])) small = 0;
+    memcpy(x, xn, sizeof(x));
+    const double prev = hist[nh - 1];
+    ev = en;
+    hist[nh++] = ev.eT;
+    if (ev.eT < best->eT) *best = ev;
+    if (it >= 5 && ev.eT > prev) {
+      nrise++;
+      if (nrise >= 5) break;
+    }
+    if (small) break;
+  }
+}
+
+void orc_implicit_cell(const orc_params *p, const orc_geom *g, const double *Ui,
+                       const double *Pguess, double dt, double chi_abs, double chi_es,
+                       double *Pout, double *Uout, orc_implicit_info *info) {
+  ictx c;
+  c.p = p;
+  c.g = g;
+  orc_spatial_gcon(g, c.gij);
+  const double gd = g->gdet;
+  c.rhout = Ui[0] / gd;
+  for (int i = 0; i < 3; i++) c.B[i] = Ui[5 + i] / gd;
+  for (int m = 0; m < 4; m++) {
+    c.Tgi[m] = Ui[1 + m] / gd;
+    c.Ri[m] = Ui[8 + m] / gd;
+  }
+  c.dt = dt;
+  c.chi_abs = chi_abs;
+  c.chi_es = chi_es;
+  int status = 0, iters = 0;
+
+  /* extreme radiation sub-dominance (Sec. 4.10): radiation energy, or the
+   * fluid-frame radiation energy against u_g, below 10 eps */
+  double Ehat;
+  {
+    orc_gas s;
+    orc_rad r;
+    orc_gas_state(p, g, Pguess, &s);
+    orc_rad_state(g, Pguess, &r);
+    Ehat = 0.0;
+    for (int a = 0; a < 4; a++)
+      for (int b = 0; b < 4; b++) Ehat += r.R[a][b] * s.ucov[a] * s.ucon[b];
+  }
+  const int extreme = (fabs(c.Ri[0]) <= 10.0 * EPS_M * (fabs(c.Tgi[0]) + fabs(c.Ri[0]))) ||
+                      (fabs(Ehat) <= 10.0 * EPS_M * (fabs(Pguess[1]) + fabs(Ehat)));
+  if (extreme) status |= ORC_ST_EXTREME;
+
+  /* PMHD guess: prior primitives, or the thin-limit inversion of U_(i) when
+   * the temporal optical depth dt kappa_tot(P_n) < 2/3 (Sec. 4.10) */
+  double Pthin[12];
+  memcpy(Pthin, Pguess, sizeof(Pthin));
+  const double tau = dt * (chi_abs + chi_es) * Pguess[0];
+  if (tau < 2.0 / 3.0) {
+    double Pt[12];
+    memcpy(Pt, Pguess, sizeof(Pt));
+    if (orc_mhd_invert(p, g, Ui, Pguess, Pt) == 0) memcpy(Pthin, Pt, sizeof(double) * 8);
+    else status |= ORC_ST_C2P_FAIL;
+  }
+
+  const int order[2] = {extreme ? M_URAD : M_PMHD, extreme ? M_PMHD : M_URAD};
+  ieval best;
+  memset(&best, 0, sizeof(best));
+  best.eT = INFINITY;
+  int best_method = -1;
+  for (int mi = 0; mi < 2; mi++) {
+    const int method = order[mi];
+    double x0[4];
+    double Pg[12];
+    const int use_prev = (best_method >= 0 && best.eT < 1e-4);
+    if (method == M_PMHD) {
+      const double *src = use_prev ? best.P : Pthin;
+      x0[0] = src[1];
+      for (int i = 0; i < 3; i++) x0[1 + i] = src[2 + i];
+      memcpy(Pg, src, sizeof(Pg));
+    } else {
+      if (use_prev) {
+        memcpy(x0, best.Rr, sizeof(x0));
+        memcpy(Pg, best.P, sizeof(Pg));
+      } else {
+        rad_cons(&c, Pguess, x0);
+        memcpy(Pg, Pguess, sizeof(Pg));
+      }
+    }
+    ieval bm;
+    newton(&c, method, x0, Pg, &bm, &iters);
+    if (bm.ok && bm.eT < best.eT) {
+      best = bm;
+      best_method = method;
+    }
+    if (best.eT < p->tol_accept) break;
+  }
+
+  memcpy(Pout, Pguess, sizeof(double) * 12);
+  for (int i = 0; i < 12; i++) Uout[i] = Ui[i];
+  if (best_method < 0) {
+    status |= ORC_ST_FAIL;
+    info->status = status;
+    info->iters = iters;
+    info->err = INFINITY;
+    return;
+  }
+  status |= (best_method == M_PMHD) ? ORC_ST_PMHD : ORC_ST_URAD;
+  if (best.eT > p->tol_fail) status |= ORC_ST_FAIL;
+  else if (best.eT > p->tol_accept) status |= ORC_ST_NOT_ACCEPT;
+  if (best.radflags & 1) status |= ORC_ST_TYPE2_NEG;
+
+  memcpy(Pout, best.P, sizeof(double) * 12);
+  double Ucons_rad[4], Ucons_gas[4];
+  for (int m = 0; m < 4; m++) {
+    if (best_method == M_PMHD) {
+      Ucons_gas[m] = best.Tg[m];
+      Ucons_rad[m] = c.Ri[m] - (best.Tg[m] - c.Tgi[m]);
+    } else {
+      Ucons_rad[m] = best.x[m];
+      Ucons_gas[m] = c.Tgi[m] - (best.x[m] - c.Ri[m]);
+    }
+  }
+  int rad_changed = (best.radflags != 0);
+  if (best_method == M_PMHD && (best.radflags & 1)) {
+    /* the accepted solution met E_rad < 0 under TYPE2: re-invert with BASIC */
+    double U[12];
+    memset(U, 0, sizeof(U));
+    for (int m = 0; m < 4; m++) U[8 + m] = gd * Ucons_rad[m];
+    orc_rad_invert(p, g, U, 0, Pout);
+    status |= ORC_ST_BASIC;
+    rad_changed = 1;
+  }
+  if (rad_changed) rad_cons(&c, Pout, Ucons_rad);
+  Uout[0] = Ui[0];
+  for (int m = 0; m < 4; m++) {
+    Uout[1 + m] = gd * Ucons_gas[m];
+    Uout[8 + m] = gd * Ucons_rad[m];
+  }
+  for (int i = 0; i < 3; i++) Uout[5 + i] = Ui[5 + i];
+  if (!(Pout[1] > 0.0)) status |= ORC_ST_FAIL;
+  info->status = status;
+  info->iters = iters;
+  info->err = best.eT;
+}
+
+void orc_implicit_batch(const orc_params *p, long n, const double *Ui, const double *Pg,
+                        const double *dtc, const double *chi_abs, const double *chi_es,
+                        double *Pout, double *Uout, int *iters, int *status) {
+  orc_geom g;
+  orc_geom_point(p, 0.0, 0.5, &g);
+#pragma omp parallel for schedule(dynamic, 256)
+  for (long c = 0; c < n; c++) {
+    double U[12], P[12], Po[12], Uo[12];
+    for (int q = 0; q < 12; q++) {
+      U[q] = Ui[q * n + c];
+      P[q] = Pg[q * n + c];
+    }
+    orc_implicit_info info;
+    orc_implicit_cell(p, &g, U, P, dtc[c], chi_abs[c], chi_es[c], Po, Uo, &info);
+    for (int q = 0; q < 12; q++) {
+      Pout[q * n + c] = Po[q];
+      Uout[q * n + c] = Uo[q];
+    }
+    if (iters) iters[c] = info.iters;
+    if (status) status[c] = info.status;
+  }
+}

@@ -1,0 +1,126 @@
+/*
+ * FP64 CPU oracle for one GRRMHD time step (HARMRAD method, McKinney,
+ * Tchekhovskoy, Sadowski & Narayan 2014).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library is the plain, slow reference that
+ * the GPU path is checked against.  Only the test-suite, the smoke check and
+ * the CPU-baseline timing may load it; the product path never does.  It
+ * shares no code, header, table or helper with the GPU library.
+ *
+ * Conventions (all quantities in code units c = G = M = 1):
+ *   primitives P[12]: 0 rho0, 1 u_g, 2-4 u~^i (gas velocity relative to the
+ *     normal observer, coordinate components), 5-7 B^i, 8 Ebar (radiation
+ *     rest-frame energy density), 9-11 u~^i_rad            (Sec. 4, list of P_q)
+ *   conserved U[12] = sqrt(-g) * { rho0 u^t, T^t_t + rho0 u^t, T^t_i, B^i,
+ *     R^t_t, R^t_i }                                        (Sec. 4, list of U_q)
+ *   grid arrays are structure-of-arrays [q][k][j][i], i fastest, ghosts
+ *   included; ghosts only along dimensions with more than one cell.
+ */
+#ifndef ORC_ORACLE_H
+#define ORC_ORACLE_H
+
+#include <stdint.h>
+
+#define ORC_NPRIM 12
+
+enum { ORC_MINKOWSKI = 0, ORC_KERR_SCHILD = 1 };
+enum { ORC_BC_OUTFLOW = 0, ORC_BC_PERIODIC = 1, ORC_BC_REFLECT = 2, ORC_BC_POLAR = 3 };
+enum { ORC_FLUX_LLF = 0, ORC_FLUX_HLL = 1 };
+
+/* per-cell status bits of the implicit solve and fix-ups */
+enum {
+  ORC_ST_PMHD = 1 << 0,        /* accepted solution came from PMHD iteration */
+  ORC_ST_URAD = 1 << 1,        /* accepted solution came from URAD iteration */
+  ORC_ST_TYPE2_NEG = 1 << 2,   /* TYPE2 limiter met negative radiation energy */
+  ORC_ST_BASIC = 1 << 3,       /* radiation re-inverted with BASIC limiter   */
+  ORC_ST_C2P_FAIL = 1 << 4,    /* thin-limit MHD inversion had no solution   */
+  ORC_ST_FLOOR = 1 << 5,       /* a floor changed the primitives             */
+  ORC_ST_NOT_ACCEPT = 1 << 6,  /* best e_T above the acceptance tolerance    */
+  ORC_ST_FAIL = 1 << 7,        /* no solution: primitives neighbour-averaged */
+  ORC_ST_NO_GOOD_NB = 1 << 8,  /* averaging found no good neighbour          */
+  ORC_ST_EXTREME = 1 << 9      /* radiation extremely sub-dominant: URAD first */
+};
+
+typedef struct {
+  int n[3];               /* interior cells per dimension (1 = inactive)      */
+  int ng;                 /* ghost width along active dimensions              */
+  int metric;             /* ORC_MINKOWSKI or ORC_KERR_SCHILD                 */
+  double a;               /* black-hole spin (Kerr-Schild)                    */
+  double R0;              /* radial map r = R0 + exp(x1)                      */
+  double xlo[3], xhi[3];  /* internal-coordinate extent of the interior       */
+  int bc_lo[3], bc_hi[3];
+  double gam;             /* adiabatic index                                  */
+  double arad;            /* radiation constant                               */
+  double gamma_max;       /* radiation Lorentz-factor cap                     */
+  double courant;
+  int flux;               /* ORC_FLUX_LLF or ORC_FLUX_HLL                     */
+  double tol_pmhd, tol_urad, tol_accept, tol_fail;
+  int max_iter;           /* Newton steps per method                          */
+  int roundoff;           /* keep iterating past tolerance to round-off       */
+  double rho_floor, u_floor, bsq_rho_max, bsq_u_max, u_rho_max, erad_floor;
+} orc_params;
+
+/* ---- geometry (Sec. 2; metric of the Kerr-Schild form) ---- */
+typedef struct {
+  double gcov[4][4];
+  double gcon[4][4];
+  double gdet;            /* sqrt(-g) */
+  double alpha;           /* lapse 1/sqrt(-g^tt) */
+} orc_geom;
+
+void orc_geom_point(const orc_params *p, double x1, double x2, orc_geom *g);
+/* connection Gamma^l_{m n} at internal coordinates (x1, x2) */
+void orc_connection(const orc_params *p, double x1, double x2, double conn[4][4][4]);
+
+/* ---- pointwise physics, exported for tests ---- */
+void orc_p2u(const orc_params *p, const orc_geom *g, const double *P, double *U);
+void orc_flux(const orc_params *p, const orc_geom *g, const double *P, int dir, double *F);
+void orc_source_geom(const orc_params *p, const orc_geom *g, const double conn[4][4][4],
+                     const double *P, double *S);
+void orc_four_force(const orc_params *p, const orc_geom *g, const double *P,
+                    double kabs, double kes, double Gcov[4]);
+void orc_fluid_frame_rad(const orc_geom *g, const double *P, double *Ehat, double Fhat[3],
+                         double Phat[3][3]);
+void orc_wavespeeds(const orc_params *p, const orc_geom *g, const double *P, int dir,
+                    double kappa_tot_dx, double vgas[2], double vrad[2]);
+int orc_mhd_invert(const orc_params *p, const orc_geom *g, const double *U, const double *Pguess,
+                   double *P);
+int orc_rad_invert(const orc_params *p, const orc_geom *g, const double *U, int limiter,
+                   double *P);
+
+/* ---- implicit 4-force solve for one cell (Sec. 4.7-4.11) ---- */
+typedef struct {
+  int status;
+  int iters;
+  double err;
+} orc_implicit_info;
+
+void orc_implicit_cell(const orc_params *p, const orc_geom *g, const double *Ui,
+                       const double *Pguess, double dt, double chi_abs, double chi_es,
+                       double *Pout, double *Uout, orc_implicit_info *info);
+
+/* batch of independent Minkowski cells, arrays [12][n] */
+void orc_implicit_batch(const orc_params *p, long n, const double *Ui, const double *Pg,
+                        const double *dtc, const double *chi_abs, const double *chi_es,
+                        double *Pout, double *Uout, int *iters, int *status);
+
+/* ---- grid-level pieces of one Runge-Kutta sub-step (Sec. 4.2) ---- */
+long orc_ncell_alloc(const orc_params *p);
+void orc_bc(const orc_params *p, double *P);
+void orc_prim_to_cons(const orc_params *p, const double *P, double *U);
+void orc_fluxes(const orc_params *p, const double *P, const double *chi_abs, const double *chi_es,
+                double *F /* [3][12][N] */, double *emf /* [3][N] */, double *vchar /* [3][N] */);
+double orc_timestep(const orc_params *p, const double *vchar);
+void orc_explicit_update(const orc_params *p, double a, double b, double c, double dt,
+                         const double *P, const double *Un, const double *Uprev, const double *F,
+                         const double *emf, double *Uexp);
+void orc_con2prim(const orc_params *p, const double *U, const double *Pguess, double *P, int *status);
+void orc_implicit_grid(const orc_params *p, const double *Uexp, const double *Pguess, double dt,
+                       const double *chi_abs, const double *chi_es, double *Pout, double *Uout,
+                       int *iters, int *status);
+void orc_fixup(const orc_params *p, double *P, double *U, int *status);
+/* full RK3-IMEX step; dt in/out (computed unless dt_fixed) */
+int orc_step(const orc_params *p, double *P, double *U, const double *chi_abs, const double *chi_es,
+             double *dt, int dt_fixed, int *status, int *iters);
+
+#endif

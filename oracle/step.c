@@ -1,0 +1,464 @@
+/*
+ * Oracle grid-level steps of one Runge-Kutta sub-step (Sec. 4.2, steps
+ * 1-13) and the third-order Shu-Osher RK3 with identical explicit and
+ * implicit coefficients that the paper uses (Sec. 4.1, last paragraphs).
+ *
+ * TEST INFRASTRUCTURE ONLY (see oracle.h).
+ *
+ * Reconstruction is piecewise linear with monotonised-central slopes; fluxes
+ * are HLL (eq. hll) or LAXF (eq. lax) with separate gas and radiation wave
+ * speeds (Sec. 4.4); the induction fluxes are corrected by flux-CT (corner
+ * EMF = average of the four adjacent face fluxes, face flux = average of the
+ * two adjacent corner EMFs); dt follows Sec. 4.4's last paragraph.
+ */
+#include <float.h>
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#include "oracle.h"
+#include "oracle_internal.h"
+
+int orc_ng(const orc_params *p, int d) { return p->n[d] > 1 ? p->ng : 0; }
+int orc_nalloc(const orc_params *p, int d) { return p->n[d] + 2 * orc_ng(p, d); }
+double orc_dx(const orc_params *p, int d) { return (p->xhi[d] - p->xlo[d]) / p->n[d]; }
+long orc_ncell_alloc(const orc_params *p) {
+  return (long)orc_nalloc(p, 0) * orc_nalloc(p, 1) * orc_nalloc(p, 2);
+}
+
+void orc_cell_x(const orc_params *p, int i, int j, double *x1, double *x2) {
+  *x1 = p->xlo[0] + (i - orc_ng(p, 0) + 0.5) * orc_dx(p, 0);
+  *x2 = p->xlo[1] + (j - orc_ng(p, 1) + 0.5) * orc_dx(p, 1);
+}
+
+void orc_face_x(const orc_params *p, int dir, int i, int j, double *x1, double *x2) {
+  orc_cell_x(p, i, j, x1, x2);
+  if (dir == 1) *x1 = p->xlo[0] + (i - orc_ng(p, 0)) * orc_dx(p, 0);
+  if (dir == 2) *x2 = p->xlo[1] + (j - orc_ng(p, 1)) * orc_dx(p, 1);
+}
+
+#define IDX(p, i, j, k) ((long)(i) + (long)orc_nalloc(p, 0) * ((long)(j) + (long)orc_nalloc(p, 1) * (long)(k)))
+
+/* ---- step 1: ghost cells (Sec. 4.2) ---- */
+static void copy_cell(double *P, long N, long dst, long src, const int *neg) {
+  for (int q = 0; q < 12; q++) P[q * N + dst] = P[q * N + src];
+  for (int m = 0; m < 3 && neg[m] >= 0; m++) P[neg[m] * N + dst] = -P[neg[m] * N + dst];
+}
+
+void orc_bc(const orc_params *p, double *P) {
+  const long N = orc_ncell_alloc(p);
+  const int NA[3] = {orc_nalloc(p, 0), orc_nalloc(p, 1), orc_nalloc(p, 2)};
+  for (int d = 0; d < 3; d++) {
+    const int ng = orc_ng(p, d);
+    if (ng == 0) continue;
+    const int n = p->n[d];
+    for (int side = 0; side < 2; side++) {
+      const int bc = side ? p->bc_hi[d] : p->bc_lo[d];
+      int neg[3] = {-1, -1, -1};
+      if (bc == ORC_BC_REFLECT || bc == ORC_BC_POLAR) {
+        neg[0] = 2 + d;
+        neg[1] = 5 + d;
+        neg[2] = 9 + d;
+      }
+      for (int a = 0; a < NA[(d + 1) % 3]; a++)
+        for (int b = 0; b < NA[(d + 2) % 3]; b++)
+          for (int m = 0; m < ng; m++) {
+            const int gidx = side ? ng + n + m : ng - 1 - m;
+            int sidx;
+            if (bc == ORC_BC_OUTFLOW) sidx = side ? ng + n - 1 : ng;
+            else if (bc == ORC_BC_PERIODIC) sidx = side ? ng + m : ng + n - 1 - m;
+            else sidx = side ? ng + n - 1 - m : ng + m;
+            int c[3], s[3];
+            c[d] = gidx;
+            s[d] = sidx;
+            c[(d + 1) % 3] = s[(d + 1) % 3] = a;
+            c[(d + 2) % 3] = s[(d + 2) % 3] = b;
+            if (bc == ORC_BC_POLAR && d == 1 && p->n[2] > 1) {
+              /* across the axis: same theta distance, phi shifted by pi */
+              const int ng3 = orc_ng(p, 2), n3 = p->n[2];
+              if (s[2] < ng3 || s[2] >= ng3 + n3) continue; /* phi ghosts filled later */
+              s[2] = ng3 + ((s[2] - ng3 + n3 / 2) % n3);
+            }
+            copy_cell(P, N, IDX(p, c[0], c[1], c[2]), IDX(p, s[0], s[1], s[2]),
+                      (bc == ORC_BC_REFLECT || bc == ORC_BC_POLAR) ? neg : (int[3]){-1, -1, -1});
+          }
+    }
+  }
+}
+
+void orc_prim_to_cons(const orc_params *p, const double *P, double *U) {
+  const long N = orc_ncell_alloc(p);
+#pragma omp parallel for collapse(2)
+  for (int k = 0; k < orc_nalloc(p, 2); k++)
+    for (int j = 0; j < orc_nalloc(p, 1); j++)
+      for (int i = 0; i < orc_nalloc(p, 0); i++) {
+        double x1, x2;
+        orc_cell_x(p, i, j, &x1, &x2);
+        orc_geom g;
+        orc_geom_point(p, x1, x2, &g);
+        const long c = IDX(p, i, j, k);
+        double Pc[12], Uc[12];
+        for (int q = 0; q < 12; q++) Pc[q] = P[q * N + c];
+        orc_p2u(p, &g, Pc, Uc);
+        for (int q = 0; q < 12; q++) U[q * N + c] = Uc[q];
+      }
+}
+
+/* monotonised-central limited slope */
+static double mc_slope(double l, double c, double r) {
+  const double dm = c - l, dp = r - c;
+  if (dm * dp <= 0.0) return 0.0;
+  const double dc = 0.5 * (dm + dp);
+  double s = fmin(fabs(2.0 * dm), fmin(fabs(2.0 * dp), fabs(dc)));
+  return dc > 0.0 ? s : -s;
+}
+
+/* ---- steps 4-9: reconstruction, face fluxes, wave speeds, Riemann, CT ---- */
+void orc_fluxes(const orc_params *p, const double *P, const double *chi_abs, const double *chi_es,
+                double *F, double *emf, double *vchar) {
+  const long N = orc_ncell_alloc(p);
+  memset(F, 0, sizeof(double) * 3 * 12 * N);
+  memset(emf, 0, sizeof(double) * 3 * N);
+  memset(vchar, 0, sizeof(double) * 3 * N);
+  const int NA[3] = {orc_nalloc(p, 0), orc_nalloc(p, 1), orc_nalloc(p, 2)};
+  for (int d = 0; d < 3; d++) {
+    if (p->n[d] == 1) continue;
+    int lo[3], hi[3];
+    for (int e = 0; e < 3; e++) {
+      const int ng = orc_ng(p, e);
+      if (e == d) { lo[e] = ng; hi[e] = ng + p->n[e]; }
+      else if (p->n[e] > 1) { lo[e] = ng - 1; hi[e] = ng + p->n[e]; }
+      else { lo[e] = 0; hi[e] = 0; }
+    }
+    long st = 1;
+    for (int e = 0; e < d; e++) st *= NA[e];
+    const double dxd = orc_dx(p, d);
+    double *Fd = F + (long)d * 12 * N;
+#pragma omp parallel for collapse(2)
+    for (int k = lo[2]; k <= hi[2]; k++)
+      for (int j = lo[1]; j <= hi[1]; j++)
+        for (int i = lo[0]; i <= hi[0]; i++) {
+          const long c = IDX(p, i, j, k);
+          const long m2 = c - 2 * st, m1 = c - st, p1 = c + st;
+          double PL[12], PR[12];
+          for (int q = 0; q < 12; q++) {
+            const double a = P[q * N + m2], b = P[q * N + m1], cc = P[q * N + c], e = P[q * N + p1];
+            PL[q] = b + 0.5 * mc_slope(a, b, cc);
+            PR[q] = cc - 0.5 * mc_slope(b, cc, e);
+          }
+          double x1, x2;
+          orc_face_x(p, d + 1, i, j, &x1, &x2);
+          orc_geom g;
+          orc_geom_point(p, x1, x2, &g);
+          const double sdx = sqrt(g.gcov[d + 1][d + 1]) * dxd;
+          double UL[12], UR[12], FL[12], FR[12], vgL[2], vrL[2], vgR[2], vrR[2];
+          orc_p2u(p, &g, PL, UL);
+          orc_p2u(p, &g, PR, UR);
+          orc_flux(p, &g, PL, d + 1, FL);
+          orc_flux(p, &g, PR, d + 1, FR);
+          orc_wavespeeds(p, &g, PL, d + 1, (chi_abs[m1] + chi_es[m1]) * PL[0] * sdx, vgL, vrL);
+          orc_wavespeeds(p, &g, PR, d + 1, (chi_abs[c] + chi_es[c]) * PR[0] * sdx, vgR, vrR);
+          /* eq. hll: v_min = -min(0, v-_L, v-_R), v_max = max(0, v+_L, v+_R) */
+          const double gmin = -fmin(0.0, fmin(vgL[0], vgR[0])), gmax = fmax(0.0, fmax(vgL[1], vgR[1]));
+          const double rmin = -fmin(0.0, fmin(vrL[0], vrR[0])), rmax = fmax(0.0, fmax(vrL[1], vrR[1]));
+          for (int q = 0; q < 12; q++) {
+            const double vmin = q < 8 ? gmin : rmin, vmax = q < 8 ? gmax : rmax;
+            double f;
+            if (p->flux == ORC_FLUX_HLL) {
+              if (vmin + vmax > 0.0)
+                f = (vmin * FR[q] + vmax * FL[q] - vmin * vmax * (UR[q] - UL[q])) / (vmin + vmax);
+              else
+                f = 0.5 * (FL[q] + FR[q]);
+            } else {
+              const double vt = fmax(vmin, vmax); /* eq. lax */
+              f = 0.5 * (FR[q] + FL[q] - vt * (UR[q] - UL[q]));
+            }
+            Fd[q * N + c] = f;
+          }
+          Fd[(5 + d) * N + c] = 0.0; /* induction flux of the normal component vanishes */
+          vchar[(long)d * N + c] = fmax(fmax(gmin, gmax), fmax(rmin, rmax));
+        }
+  }
+  /* flux-CT corner EMFs: emf_a = F_c[B_b] = -F_b[B_c], (a, b, c) cyclic */
+  for (int a = 0; a < 3; a++) {
+    const int b = (a + 1) % 3, cdim = (a + 2) % 3;
+    if (p->n[b] == 1 || p->n[cdim] == 1) continue;
+    int lo[3], hi[3];
+    lo[a] = orc_ng(p, a);
+    hi[a] = orc_ng(p, a) + p->n[a] - 1;
+    lo[b] = orc_ng(p, b); hi[b] = orc_ng(p, b) + p->n[b];
+    lo[cdim] = orc_ng(p, cdim); hi[cdim] = orc_ng(p, cdim) + p->n[cdim];
+    long stb = 1, stc = 1;
+    for (int e = 0; e < b; e++) stb *= NA[e];
+    for (int e = 0; e < cdim; e++) stc *= NA[e];
+    const double *Fb = F + (long)b * 12 * N, *Fc = F + (long)cdim * 12 * N;
+    for (int k = lo[2]; k <= hi[2]; k++)
+      for (int j = lo[1]; j <= hi[1]; j++)
+        for (int i = lo[0]; i <= hi[0]; i++) {
+          const long c = IDX(p, i, j, k);
+          double e = 0.25 * (Fc[(5 + b) * N + c] + Fc[(5 + b) * N + c - stb] -
+                             Fb[(5 + cdim) * N + c] - Fb[(5 + cdim) * N + c - stc]);
+          if (p->metric == ORC_KERR_SCHILD && (b == 1 || cdim == 1)) {
+            /* edges lying on the polar axis carry no EMF */
+            const int ng2 = orc_ng(p, 1);
+            const int onlo = (j == ng2) && (p->bc_lo[1] == ORC_BC_REFLECT || p->bc_lo[1] == ORC_BC_POLAR);
+            const int onhi = (j == ng2 + p->n[1]) &&
+                             (p->bc_hi[1] == ORC_BC_REFLECT || p->bc_hi[1] == ORC_BC_POLAR);
+            if (onlo || onhi) e = 0.0;
+          }
+          emf[(long)a * N + c] = e;
+        }
+  }
+}
+
+double orc_timestep(const orc_params *p, const double *vchar) {
+  const long N = orc_ncell_alloc(p);
+  const int NA[3] = {orc_nalloc(p, 0), orc_nalloc(p, 1), orc_nalloc(p, 2)};
+  double dtmin = INFINITY;
+  for (int k = orc_ng(p, 2); k < orc_ng(p, 2) + p->n[2]; k++)
+    for (int j = orc_ng(p, 1); j < orc_ng(p, 1) + p->n[1]; j++)
+      for (int i = orc_ng(p, 0); i < orc_ng(p, 0) + p->n[0]; i++) {
+        const long c = IDX(p, i, j, k);
+        double inv = 0.0;
+        long st = 1;
+        for (int d = 0; d < 3; d++) {
+          if (p->n[d] > 1) {
+            const double v = fmax(vchar[(long)d * N + c], vchar[(long)d * N + c + st]);
+            inv += v / orc_dx(p, d);
+          }
+          st *= NA[d];
+        }
+        const double dtc = 1.0 / inv;
+        if (dtc < dtmin) dtmin = dtc;
+      }
+  return p->courant * dtmin;
+}
+
+/* eps(a, b, d) = +1 for cyclic (a, b, d) of (0, 1, 2), -1 otherwise */
+static double levi(int a, int b, int d) {
+  return ((a + 1) % 3 == b && (b + 1) % 3 == d) ? 1.0 : -1.0;
+}
+
+/* ---- step 10: U_(i) = a U^n + b U^(k-1) + c dt (-div F + S_M) ---- */
+void orc_explicit_update(const orc_params *p, double a, double b, double c, double dt,
+                         const double *P, const double *Un, const double *Uprev, const double *F,
+                         const double *emf, double *Uexp) {
+  const long N = orc_ncell_alloc(p);
+  const int NA[3] = {orc_nalloc(p, 0), orc_nalloc(p, 1), orc_nalloc(p, 2)};
+  long st[3] = {1, NA[0], (long)NA[0] * NA[1]};
+#pragma omp parallel for collapse(2)
+  for (int k = orc_ng(p, 2); k < orc_ng(p, 2) + p->n[2]; k++)
+    for (int j = orc_ng(p, 1); j < orc_ng(p, 1) + p->n[1]; j++)
+      for (int i = orc_ng(p, 0); i < orc_ng(p, 0) + p->n[0]; i++) {
+        const long cc = IDX(p, i, j, k);
+        double x1, x2;
+        orc_cell_x(p, i, j, &x1, &x2);
+        orc_geom g;
+        orc_geom_point(p, x1, x2, &g);
+        double conn[4][4][4], Pc[12], S[12];
+        orc_connection(p, x1, x2, conn);
+        for (int q = 0; q < 12; q++) Pc[q] = P[q * N + cc];
+        orc_source_geom(p, &g, conn, Pc, S);
+        double div[12];
+        for (int q = 0; q < 12; q++) {
+          div[q] = 0.0;
+          if (q >= 5 && q <= 7) continue;
+          for (int d = 0; d < 3; d++) {
+            if (p->n[d] == 1) continue;
+            const double *Fd = F + (long)d * 12 * N;
+            div[q] += (Fd[q * N + cc + st[d]] - Fd[q * N + cc]) / orc_dx(p, d);
+          }
+        }
+        for (int bb = 0; bb < 3; bb++) {
+          const int q = 5 + bb;
+          for (int d = 0; d < 3; d++) {
+            if (p->n[d] == 1 || d == bb) continue;
+            double fm, fp;
+            if (p->n[bb] > 1) {
+              /* face flux = average of the two corner EMFs adjacent along bb */
+              const int aa = 3 - bb - d;
+              const double *E = emf + (long)aa * N;
+              const double s = levi(aa, bb, d);
+              fm = 0.5 * s * (E[cc] + E[cc + st[bb]]);
+              fp = 0.5 * s * (E[cc + st[d]] + E[cc + st[d] + st[bb]]);
+            } else {
+              const double *Fd = F + (long)d * 12 * N;
+              fm = Fd[q * N + cc];
+              fp = Fd[q * N + cc + st[d]];
+            }
+            div[q] += (fp - fm) / orc_dx(p, d);
+          }
+        }
+        for (int q = 0; q < 12; q++) {
+          const double un = Un[q * N + cc];
+          const double up = (b != 0.0) ? Uprev[q * N + cc] : 0.0;
+          Uexp[q * N + cc] = a * un + b * up + c * dt * (-div[q] + S[q]);
+        }
+      }
+}
+
+void orc_con2prim(const orc_params *p, const double *U, const double *Pguess, double *P, int *status) {
+  const long N = orc_ncell_alloc(p);
+#pragma omp parallel for collapse(2)
+  for (int k = orc_ng(p, 2); k < orc_ng(p, 2) + p->n[2]; k++)
+    for (int j = orc_ng(p, 1); j < orc_ng(p, 1) + p->n[1]; j++)
+      for (int i = orc_ng(p, 0); i < orc_ng(p, 0) + p->n[0]; i++) {
+        const long c = IDX(p, i, j, k);
+        double x1, x2;
+        orc_cell_x(p, i, j, &x1, &x2);
+        orc_geom g;
+        orc_geom_point(p, x1, x2, &g);
+        double Uc[12], Pg[12], Pc[12];
+        for (int q = 0; q < 12; q++) {
+          Uc[q] = U[q * N + c];
+          Pg[q] = Pguess[q * N + c];
+          Pc[q] = Pg[q];
+        }
+        int st = 0;
+        if (orc_mhd_invert(p, &g, Uc, Pg, Pc) != 0) st |= ORC_ST_C2P_FAIL;
+        orc_rad_invert(p, &g, Uc, 0, Pc);
+        for (int q = 0; q < 12; q++) P[q * N + c] = Pc[q];
+        if (status) status[c] = st;
+      }
+}
+
+void orc_implicit_grid(const orc_params *p, const double *Uexp, const double *Pguess, double dt,
+                       const double *chi_abs, const double *chi_es, double *Pout, double *Uout,
+                       int *iters, int *status) {
+  const long N = orc_ncell_alloc(p);
+#pragma omp parallel for collapse(2) schedule(dynamic, 4)
+  for (int k = orc_ng(p, 2); k < orc_ng(p, 2) + p->n[2]; k++)
+    for (int j = orc_ng(p, 1); j < orc_ng(p, 1) + p->n[1]; j++)
+      for (int i = orc_ng(p, 0); i < orc_ng(p, 0) + p->n[0]; i++) {
+        const long c = IDX(p, i, j, k);
+        double x1, x2;
+        orc_cell_x(p, i, j, &x1, &x2);
+        orc_geom g;
+        orc_geom_point(p, x1, x2, &g);
+        double Uc[12], Pg[12], Po[12], Uo[12];
+        for (int q = 0; q < 12; q++) {
+          Uc[q] = Uexp[q * N + c];
+          Pg[q] = Pguess[q * N + c];
+        }
+        orc_implicit_info info;
+        orc_implicit_cell(p, &g, Uc, Pg, dt, chi_abs[c], chi_es[c], Po, Uo, &info);
+        for (int q = 0; q < 12; q++) {
+          Pout[q * N + c] = Po[q];
+          Uout[q * N + c] = Uo[q];
+        }
+        if (iters) iters[c] = info.iters;
+        if (status) status[c] = info.status;
+      }
+}
+
+/* ---- step 13: backups (Sec. 4.11) and floors ---- */
+void orc_fixup(const orc_params *p, double *P, double *U, int *status) {
+  const long N = orc_ncell_alloc(p);
+  const int NA[3] = {orc_nalloc(p, 0), orc_nalloc(p, 1), orc_nalloc(p, 2)};
+  const long st[3] = {1, NA[0], (long)NA[0] * NA[1]};
+  double *P0 = malloc(sizeof(double) * 12 * N);
+  memcpy(P0, P, sizeof(double) * 12 * N);
+  for (int k = orc_ng(p, 2); k < orc_ng(p, 2) + p->n[2]; k++)
+    for (int j = orc_ng(p, 1); j < orc_ng(p, 1) + p->n[1]; j++)
+      for (int i = orc_ng(p, 0); i < orc_ng(p, 0) + p->n[0]; i++) {
+        const long c = IDX(p, i, j, k);
+        const int idx[3] = {i, j, k};
+        int changed = 0;
+        if (status[c] & ORC_ST_FAIL) {
+          /* average the primitives of face neighbours with a good solution;
+           * if none is good, of all interior face neighbours */
+          for (int pass = 0; pass < 2 && !changed; pass++) {
+            double acc[12] = {0};
+            int cnt = 0;
+            for (int d = 0; d < 3; d++) {
+              if (p->n[d] == 1) continue;
+              for (int s = -1; s <= 1; s += 2) {
+                const int nid = idx[d] + s;
+                if (nid < orc_ng(p, d) || nid >= orc_ng(p, d) + p->n[d]) continue;
+                const long nb = c + s * st[d];
+                if (pass == 0 && (status[nb] & ORC_ST_FAIL)) continue;
+                for (int q = 0; q < 12; q++) acc[q] += P0[q * N + nb];
+                cnt++;
+              }
+            }
+            if (cnt > 0) {
+              for (int q = 0; q < 12; q++) P[q * N + c] = acc[q] / cnt;
+              changed = 1;
+              if (pass == 1) status[c] |= ORC_ST_NO_GOOD_NB;
+            }
+          }
+        }
+        double x1, x2;
+        orc_cell_x(p, i, j, &x1, &x2);
+        orc_geom g;
+        orc_geom_point(p, x1, x2, &g);
+        double Pc[12];
+        for (int q = 0; q < 12; q++) Pc[q] = P[q * N + c];
+        /* floors: rho >= max(rho_floor, b^2/bsq_rho_max), u >= max(u_floor,
+         * b^2/bsq_u_max), u <= u_rho_max rho, Ebar >= erad_floor */
+        orc_gas s;
+        orc_gas_state(p, &g, Pc, &s);
+        const double rmin = fmax(p->rho_floor, s.bsq / p->bsq_rho_max);
+        const double umin = fmax(p->u_floor, s.bsq / p->bsq_u_max);
+        int fl = 0;
+        if (Pc[0] < rmin) { Pc[0] = rmin; fl = 1; }
+        if (Pc[1] < umin) { Pc[1] = umin; fl = 1; }
+        if (Pc[1] > p->u_rho_max * Pc[0]) { Pc[1] = p->u_rho_max * Pc[0]; fl = 1; }
+        if (!(Pc[8] >= p->erad_floor)) { Pc[8] = p->erad_floor; fl = 1; }
+        if (fl) status[c] |= ORC_ST_FLOOR;
+        if (fl || changed) {
+          double Uc[12];
+          orc_p2u(p, &g, Pc, Uc);
+          for (int q = 0; q < 12; q++) {
+            P[q * N + c] = Pc[q];
+            U[q * N + c] = Uc[q];
+          }
+        }
+      }
+  free(P0);
+}
+
+/* one full RK3-IMEX step (Sec. 4.1 RK3 with equal explicit and implicit
+ * coefficients; stage k is implicit in its own new value) */
+int orc_step(const orc_params *p, double *P, double *U, const double *chi_abs, const double *chi_es,
+             double *dt, int dt_fixed, int *status, int *iters) {
+  const long N = orc_ncell_alloc(p);
+  double *F = malloc(sizeof(double) * 3 * 12 * N);
+  double *emf = malloc(sizeof(double) * 3 * N);
+  double *vch = malloc(sizeof(double) * 3 * N);
+  double *Uexp = malloc(sizeof(double) * 12 * N);
+  double *Un = malloc(sizeof(double) * 12 * N);
+  double *Pk = malloc(sizeof(double) * 12 * N);
+  double *Uk = malloc(sizeof(double) * 12 * N);
+  int *st = calloc(N, sizeof(int));
+  int *stacc = calloc(N, sizeof(int));
+  int *it = calloc(N, sizeof(int));
+  memcpy(Un, U, sizeof(double) * 12 * N);
+  memcpy(Pk, P, sizeof(double) * 12 * N);
+  memcpy(Uk, U, sizeof(double) * 12 * N);
+  memcpy(Uexp, U, sizeof(double) * 12 * N);
+  const double A[3] = {1.0, 0.75, 1.0 / 3.0}, B[3] = {0.0, 0.25, 2.0 / 3.0},
+               C[3] = {1.0, 0.25, 2.0 / 3.0};
+  int nbad = 0;
+  if (iters) memset(iters, 0, sizeof(int) * N);
+  for (int s = 0; s < 3; s++) {
+    orc_bc(p, Pk);
+    orc_fluxes(p, Pk, chi_abs, chi_es, F, emf, vch);
+    if (s == 0 && !dt_fixed) *dt = orc_timestep(p, vch);
+    orc_explicit_update(p, A[s], B[s], C[s], *dt, Pk, Un, Uk, F, emf, Uexp);
+    orc_implicit_grid(p, Uexp, Pk, C[s] * (*dt), chi_abs, chi_es, Pk, Uk, it, st);
+    orc_fixup(p, Pk, Uk, st);
+    for (long c = 0; c < N; c++) {
+      stacc[c] |= st[c];
+      if (iters) iters[c] += it[c];
+    }
+  }
+  if (status) memcpy(status, stacc, sizeof(int) * N);
+  /* write back interior (ghost cells of P keep the last stage's fill) */
+  memcpy(P, Pk, sizeof(double) * 12 * N);
+  memcpy(U, Uk, sizeof(double) * 12 * N);
+  for (long c = 0; c < N; c++)
+    if (stacc[c] & ORC_ST_FAIL) nbad++;
+  free(F); free(emf); free(vch); free(Uexp); free(Un); free(Pk); free(Uk); free(st); free(stacc);
+  free(it);
+  return nbad;
+}
