@@ -1,0 +1,196 @@
+/*
+ * grrmhd.h -- C ABI of the MI355X (gfx950) GRRMHD time-step library.
+ *
+ * The library advances the general-relativistic radiation MHD equations of
+ * the HARMRAD method (McKinney, Tchekhovskoy, Sadowski & Narayan 2014) by one
+ * time step on a fixed Minkowski or Kerr-Schild grid: ghost fill, MC-limited
+ * reconstruction, HLL/LAXF fluxes with separate gas and M1-radiation wave
+ * speeds, flux-CT magnetic EMFs, the third-order Runge-Kutta update with the
+ * radiation 4-force treated implicitly per cell, and the conserved-to-
+ * primitive inversions (Sec. 4, 4.1-4.11 of the paper).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Units: c = G = M = 1; gas temperature T = p/rho0 (Sec. 4, code units).
+ * Primitives P, 12 per cell (Sec. 4 list of P_q, 13th slot not carried):
+ *   0 rho0, 1 u_g, 2-4 u~^i (gas 4-velocity relative to the normal observer,
+ *   coordinate components), 5-7 B^i, 8 Ebar (radiation rest-frame energy
+ *   density), 9-11 u~^i_rad.
+ * Conserved U, 12 per cell (Sec. 4 list of U_q):
+ *   sqrt(-g) * { rho0 u^t, T^t_t + rho0 u^t, T^t_i, B^i, R^t_t, R^t_i }.
+ * Layout: structure of arrays, field-major [q][k][j][i] with i fastest, over
+ *   the ALLOCATED grid, which adds ng ghost cells on both sides of every
+ *   dimension that has more than one interior cell.  N = grrmhd_ncell_alloc().
+ * Pointers: every array argument is DEVICE memory (hipMalloc or a PyTorch
+ *   CUDA/HIP tensor), 8-byte aligned, not aliased with another argument
+ *   unless stated.  The caller owns all state, opacity, status and workspace
+ *   buffers; the library owns the grid's geometry tables.
+ * Opacities: per-mass coefficients chi_abs, chi_es per allocated cell
+ *   (ghosts included); the local opacity is kappa = chi * rho0.
+ * Streams: all work is enqueued on the grid's HIP stream (set at init or by
+ *   grrmhd_set_stream) and is asynchronous; no entry point synchronises
+ *   except grrmhd_init_grid and grrmhd_free_grid.
+ * Errors: functions return 0 on success and a negative GRRMHD_E* code on
+ *   failure, with a message from grrmhd_last_error().  No C++ exception
+ *   crosses the ABI.  Launch errors are checked; errors raised later by a
+ *   kernel surface at the next synchronisation.
+ */
+#ifndef GRRMHD_H
+#define GRRMHD_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GRRMHD_NPRIM 12
+
+enum { GRRMHD_MINKOWSKI = 0, GRRMHD_KERR_SCHILD = 1 };
+enum { GRRMHD_BC_OUTFLOW = 0, GRRMHD_BC_PERIODIC = 1, GRRMHD_BC_REFLECT = 2, GRRMHD_BC_POLAR = 3 };
+enum { GRRMHD_FLUX_LLF = 0, GRRMHD_FLUX_HLL = 1 };
+enum { GRRMHD_EINVAL = -1, GRRMHD_EHIP = -2, GRRMHD_ENOMEM = -3 };
+
+/* per-cell status bits written by the implicit solve and the fix-ups */
+enum {
+  GRRMHD_ST_PMHD = 1 << 0,       /* solution from iterating gas primitives      */
+  GRRMHD_ST_URAD = 1 << 1,       /* solution from iterating R^t_nu              */
+  GRRMHD_ST_TYPE2_NEG = 1 << 2,  /* TYPE2 radiation limiter met E_rad <= 0       */
+  GRRMHD_ST_BASIC = 1 << 3,      /* radiation re-inverted with the BASIC limiter */
+  GRRMHD_ST_C2P_FAIL = 1 << 4,   /* MHD inversion of the explicit state failed   */
+  GRRMHD_ST_FLOOR = 1 << 5,      /* a floor modified the primitives              */
+  GRRMHD_ST_NOT_ACCEPT = 1 << 6, /* best error above tol_accept, below tol_fail  */
+  GRRMHD_ST_FAIL = 1 << 7,       /* no solution: neighbour-averaged primitives   */
+  GRRMHD_ST_NO_GOOD_NB = 1 << 8, /* averaging found no good neighbour            */
+  GRRMHD_ST_EXTREME = 1 << 9     /* radiation extremely sub-dominant: URAD first */
+};
+
+/* Numerical parameters.  Defaults (grrmhd_default_params) are the paper's
+ * fixed test parameters (Sec. 5 introduction; Sec. 4.10-4.11). */
+typedef struct {
+  int n[3];             /* interior cells per dimension (1 = inactive)        */
+  int ng;               /* ghost width on active dimensions (2 for MC)        */
+  int metric;           /* GRRMHD_MINKOWSKI or GRRMHD_KERR_SCHILD             */
+  double a;             /* black-hole spin (Kerr-Schild)                      */
+  double R0;            /* radial map r = R0 + exp(x1)                        */
+  double xlo[3], xhi[3];/* interior extent in internal coordinates; Kerr-
+                           Schild: x1 = ln(r - R0), x2 = theta/pi,
+                           x3 = phi/(2 pi)                                    */
+  int bc_lo[3], bc_hi[3];
+  double gam;           /* adiabatic index                                    */
+  double arad;          /* radiation constant                                 */
+  double gamma_max;     /* cap on the radiation frame's Lorentz factor        */
+  double courant;
+  int flux;             /* GRRMHD_FLUX_LLF or GRRMHD_FLUX_HLL                 */
+  double tol_pmhd;      /* stop tolerance of PMHD iterations (1e-12)          */
+  double tol_urad;      /* stop tolerance of URAD iterations (1e-9)           */
+  double tol_accept;    /* accepted without trying the next method (1e-9)     */
+  double tol_fail;      /* above this: no solution (1e-7)                     */
+  int max_iter;         /* Newton steps per method (20)                       */
+  int roundoff;         /* 1: after meeting the tolerance keep stepping (at
+                           most 3 steps) until the step is at round-off      */
+  double rho_floor, u_floor, bsq_rho_max, bsq_u_max, u_rho_max, erad_floor;
+} grrmhd_params;
+
+typedef struct grrmhd_grid grrmhd_grid;
+
+void grrmhd_default_params(grrmhd_params *p);
+const char *grrmhd_last_error(void);
+
+/* Geometry of the grid (metric, inverse, sqrt(-g), lapse at cell centres and
+ * faces, metric derivatives at centres; Sec. 2) is computed on the device by
+ * a kernel and kept by the library.  `device` is the HIP device ordinal,
+ * `hip_stream` a hipStream_t (NULL = default stream).  Synchronous.
+ * Errors: EINVAL for an invalid shape or parameter, ENOMEM, EHIP. */
+int grrmhd_init_grid(const grrmhd_params *p, int device, void *hip_stream, grrmhd_grid **out);
+int grrmhd_free_grid(grrmhd_grid *g);
+int grrmhd_set_stream(grrmhd_grid *g, void *hip_stream);
+long grrmhd_ncell_alloc(const grrmhd_grid *g);
+/* bytes of caller-provided workspace needed by grrmhd_step */
+size_t grrmhd_workspace_bytes(const grrmhd_grid *g);
+
+/* U = U(P) at every allocated cell (Sec. 4: U_q in closed form of P_q).
+ * P [12][N] in, U [12][N] out. */
+int grrmhd_prim_to_cons(grrmhd_grid *g, const double *P, double *U);
+
+/* Sub-step 1 of Sec. 4.2: fill the ghost cells of P [12][N] in place from
+ * the interior, dimension by dimension (x1, x2, x3) so corners are filled.
+ * OUTFLOW copies the edge cell, PERIODIC wraps, REFLECT mirrors and negates
+ * the normal vector components, POLAR (x2 in 3-D) maps across the axis to
+ * phi + pi and negates the theta components. */
+int grrmhd_apply_bc(grrmhd_grid *g, double *P);
+
+/* Sub-steps 4-9 of Sec. 4.2 on a P whose ghosts are filled: MC-limited
+ * reconstruction, face U and F, gas fast-magnetosonic and M1 radiation wave
+ * speeds (radiation limited by 4/(3 tau), eq. wavespeedlimit), HLL (eq. hll)
+ * or LAXF (eq. lax) fluxes, then flux-CT corner EMFs.
+ * F [3][12][N]: direction d face flux at index c = face between c - e_d and
+ *   c; the induction fluxes of the normal component are zero.
+ * emf [3][N]: EMF along a at the edge with the two other indices at -1/2.
+ * vchar [3][N]: largest characteristic speed magnitude at each face.
+ * Values outside the computed face ranges are zero. */
+int grrmhd_fluxes(grrmhd_grid *g, const double *P, const double *chi_abs, const double *chi_es,
+                  double *F, double *emf, double *vchar);
+
+/* Courant step (Sec. 4.4, last paragraph): dt = C min over interior cells of
+ * 1/sum_d(v_d/dx^d), v_d the larger face speed of the cell.  Writes one
+ * double to dt_dev (device). */
+int grrmhd_timestep(grrmhd_grid *g, const double *vchar, double *dt_dev);
+
+/* Sub-step 10: U_exp = a U^n + b U_prev + c dt (-div F + S_M(P)) at interior
+ * cells, with flux-CT face fluxes for B rebuilt from the corner EMFs and the
+ * geometric source S_M = sqrt(-g) T^k_l Gamma^l_{nu k} (Sec. 4 list of S_M).
+ * dt_dev is a device scalar.  Uprev is not read when b == 0. */
+int grrmhd_explicit_update(grrmhd_grid *g, double a, double b, double c, const double *dt_dev,
+                           const double *P, const double *Un, const double *Uprev,
+                           const double *F, const double *emf, double *Uexp);
+
+/* Conserved-to-primitive inversion at interior cells (Sec. 4.5 MHD 1-D W'
+ * equation; Sec. 4.6 analytic M1 with the BASIC limiter).  Pguess [12][N]
+ * starts the MHD iteration; P [12][N] out (may alias Pguess); status [N]
+ * gets GRRMHD_ST_C2P_FAIL where the MHD inversion has no physical root. */
+int grrmhd_con2prim(grrmhd_grid *g, const double *U, const double *Pguess, double *P, int *status);
+
+/* Sub-steps 11-12: implicit radiation 4-force solve at interior cells with
+ * time step dt_scale * (*dt_dev) (eq. source3/source4; PMHD then URAD,
+ * Sec. 4.7-4.11).  Uexp [12][N] explicit conserved state; Pguess [12][N]
+ * previous primitives (may alias P).  Out: P, U [12][N] (U may not alias
+ * Uexp), iters/status/err [N] (each may be NULL): Newton steps, status
+ * bits, final total normalised error e_T. */
+int grrmhd_implicit_grid(grrmhd_grid *g, const double *Uexp, const double *Pguess,
+                         double dt_scale, const double *dt_dev, const double *chi_abs,
+                         const double *chi_es, double *P, double *U, int *iters, int *status,
+                         double *err);
+
+/* Sub-step 13 and floors (Sec. 4.11): cells whose status has
+ * GRRMHD_ST_FAIL take the average primitives of their face neighbours with
+ * a good solution (of all face neighbours if none is good); then floors on
+ * rho0, u_g (b^2/rho0, b^2/u_g, u_g/rho0 limits) and Ebar; U is recomputed
+ * where P changed.  `scratch` is device memory of at least 12 N doubles. */
+int grrmhd_fixup(grrmhd_grid *g, double *P, double *U, int *status, double *scratch);
+
+/* One full RK3-IMEX time step (Sec. 4.1: third-order Shu-Osher stages with
+ * identical explicit and implicit coefficients; stage k implicit in its own
+ * value with dt_k = c_k dt).  P, U [12][N] in/out: U^n must hold the
+ * conserved state of P^n at interior cells; on return both hold the new
+ * state at interior cells (ghosts of P are stale).  dt_dev: device scalar,
+ * read when dt_fixed != 0, otherwise computed at stage 1 and written.
+ * status/iters [N] (nullable): OR of status bits / sum of Newton steps over
+ * the three stages.  workspace: device buffer of grrmhd_workspace_bytes(). */
+int grrmhd_step(grrmhd_grid *g, double *P, double *U, const double *chi_abs,
+                const double *chi_es, double *dt_dev, int dt_fixed, int *status, int *iters,
+                void *workspace, size_t ws_bytes);
+
+/* Implicit 4-force solve for n independent cells in flat space (Minkowski
+ * metric, no grid).  Arrays [12][n] (U_expl, P_guess, P_out, U_out) and [n]
+ * (dt_cell, chi_abs, chi_es, iters, status, err; the last three nullable),
+ * device memory.  Same algorithm as grrmhd_implicit_grid. */
+int grrmhd_implicit_source(const grrmhd_params *p, long n, const double *U_expl,
+                           const double *P_guess, const double *dt_cell, const double *chi_abs,
+                           const double *chi_es, double *P_out, double *U_out, int *iters,
+                           int *status, double *err, void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -403,7 +403,9 @@ void orc_implicit_cell(const orc_params *p, const orc_geom *g, const double *Ui,
       best = bm;
       best_method = method;
     }
-    if (best.eT < p->tol_accept) break;
+    /* acceptable: no further method (Sec. 4.10); when iterating to round-off
+     * the next method is tried until one meets the PMHD tolerance */
+    if (best.eT < (p->roundoff ? p->tol_pmhd : p->tol_accept)) break;
   }
 
   memcpy(Pout, Pguess, sizeof(double) * 12);

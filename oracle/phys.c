@@ -232,8 +232,12 @@ static void orc_char_roots(const orc_geom *g, const double u[4], double c2, int 
                            double *vp) {
   const double A = (1.0 - c2) * u[0] * u[0] - c2 * g->gcon[0][0];
   const double B = (1.0 - c2) * u[0] * u[dir] - c2 * g->gcon[0][dir];
-  const double C = (1.0 - c2) * u[dir] * u[dir] - c2 * g->gcon[dir][dir];
-  double disc = B * B - A * C;
+  /* B^2 - A C with the (1 - c^2)^2 (u^t u^d)^2 terms cancelled analytically,
+   * so the root separation keeps full precision when c^2 is tiny */
+  const double h = u[0] * u[0] * g->gcon[dir][dir] - 2.0 * u[0] * u[dir] * g->gcon[0][dir] +
+                   u[dir] * u[dir] * g->gcon[0][0];
+  const double k = g->gcon[0][dir] * g->gcon[0][dir] - g->gcon[0][0] * g->gcon[dir][dir];
+  double disc = c2 * ((1.0 - c2) * h + c2 * k);
   if (disc < 0.0) disc = 0.0;
   const double sq = sqrt(disc);
   const double v1 = (B + sq) / A, v2 = (B - sq) / A;

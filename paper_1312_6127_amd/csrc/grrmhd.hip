@@ -1,0 +1,469 @@
+// Host side of the GRRMHD library: grid set-up, launch shapes, the RK3-IMEX
+// step orchestration and the extern "C" entry points declared in
+// include/grrmhd.h.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+
+#include "kernels.h"
+
+struct grrmhd_grid {
+  grrmhd_params p;
+  Ctx C;
+  int device;
+  hipStream_t stream;
+  double* geo;          // one allocation: centre table, x1-face table, x2-face table
+  unsigned long long* dtslot;
+};
+
+static thread_local std::string g_err;
+
+static int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIPCHK(expr)                                                                    \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return fail(GRRMHD_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));      \
+  } while (0)
+
+#define LAUNCHCHK()                                                                     \
+  do {                                                                                  \
+    hipError_t e_ = hipGetLastError();                                                  \
+    if (e_ != hipSuccess) return fail(GRRMHD_EHIP, std::string("launch: ") + hipGetErrorString(e_)); \
+  } while (0)
+
+static inline unsigned nblocks(long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+extern "C" const char* grrmhd_last_error(void) { return g_err.c_str(); }
+
+extern "C" void grrmhd_default_params(grrmhd_params* p) {
+  memset(p, 0, sizeof(*p));
+  p->n[0] = p->n[1] = p->n[2] = 1;
+  p->ng = 2;
+  p->metric = GRRMHD_MINKOWSKI;
+  for (int d = 0; d < 3; d++) {
+    p->xlo[d] = 0.0;
+    p->xhi[d] = 1.0;
+    p->bc_lo[d] = p->bc_hi[d] = GRRMHD_BC_PERIODIC;
+  }
+  p->gam = 5.0 / 3.0;
+  p->arad = 1.0;
+  p->gamma_max = 100.0;
+  p->courant = 0.5;
+  p->flux = GRRMHD_FLUX_LLF;
+  p->tol_pmhd = 1e-12;
+  p->tol_urad = 1e-9;
+  p->tol_accept = 1e-9;
+  p->tol_fail = 1e-7;
+  p->max_iter = 20;
+  p->roundoff = 1;
+  p->rho_floor = 1e-20;
+  p->u_floor = 1e-22;
+  p->bsq_rho_max = 200.0;
+  p->bsq_u_max = 1e5;
+  p->u_rho_max = 1e10;
+  p->erad_floor = 1e-150;
+}
+
+static int validate(const grrmhd_params* p, bool need_grid) {
+  if (!p) return fail(GRRMHD_EINVAL, "params is NULL");
+  if (!(p->gam > 1.0) || !(p->arad >= 0.0) || !(p->gamma_max > 1.0) || !(p->courant > 0.0))
+    return fail(GRRMHD_EINVAL, "gam > 1, arad >= 0, gamma_max > 1, courant > 0 required");
+  if (p->max_iter < 1 || p->max_iter > 200) return fail(GRRMHD_EINVAL, "max_iter out of [1, 200]");
+  if (p->flux != GRRMHD_FLUX_LLF && p->flux != GRRMHD_FLUX_HLL) return fail(GRRMHD_EINVAL, "bad flux");
+  if (p->metric != GRRMHD_MINKOWSKI && p->metric != GRRMHD_KERR_SCHILD)
+    return fail(GRRMHD_EINVAL, "bad metric");
+  if (!need_grid) return 0;
+  if (p->ng != 2) return fail(GRRMHD_EINVAL, "ghost width must be 2 (MC reconstruction)");
+  for (int d = 0; d < 3; d++) {
+    if (p->n[d] < 1 || p->n[d] > (1 << 20)) return fail(GRRMHD_EINVAL, "n out of range");
+    if (p->n[d] > 1 && p->n[d] < p->ng) return fail(GRRMHD_EINVAL, "active dimension shorter than ng");
+    if (!(p->xhi[d] > p->xlo[d])) return fail(GRRMHD_EINVAL, "xhi must exceed xlo");
+    for (int s = 0; s < 2; s++) {
+      const int bc = s ? p->bc_hi[d] : p->bc_lo[d];
+      if (bc < GRRMHD_BC_OUTFLOW || bc > GRRMHD_BC_POLAR) return fail(GRRMHD_EINVAL, "bad boundary");
+      if (bc == GRRMHD_BC_POLAR && d != 1) return fail(GRRMHD_EINVAL, "polar boundary only on x2");
+    }
+  }
+  if (p->n[1] > 1 && p->n[2] > 1 && (p->bc_lo[1] == GRRMHD_BC_POLAR || p->bc_hi[1] == GRRMHD_BC_POLAR) &&
+      (p->n[2] % 2 != 0 || p->bc_lo[2] != GRRMHD_BC_PERIODIC))
+    return fail(GRRMHD_EINVAL, "polar boundary needs an even, periodic x3");
+  if (p->metric == GRRMHD_KERR_SCHILD && !(p->a >= 0.0 && p->a < 1.0))
+    return fail(GRRMHD_EINVAL, "spin must be in [0, 1)");
+  return 0;
+}
+
+static void fill_ctx(const grrmhd_params* p, Ctx& C) {
+  memset(&C, 0, sizeof(C));
+  for (int d = 0; d < 3; d++) {
+    C.n[d] = p->n[d];
+    C.ng[d] = p->n[d] > 1 ? p->ng : 0;
+    C.N[d] = C.n[d] + 2 * C.ng[d];
+    C.dx[d] = (p->xhi[d] - p->xlo[d]) / p->n[d];
+    C.xlo[d] = p->xlo[d];
+    C.bc_lo[d] = p->bc_lo[d];
+    C.bc_hi[d] = p->bc_hi[d];
+  }
+  C.st[0] = 1;
+  C.st[1] = C.N[0];
+  C.st[2] = (long)C.N[0] * C.N[1];
+  C.Ntot = C.st[2] * C.N[2];
+  C.npos = C.N[0] * C.N[1];
+  C.metric = p->metric;
+  C.gam = p->gam;
+  C.arad = p->arad;
+  C.gamma_max = p->gamma_max;
+  const double G = p->gamma_max * p->gamma_max;
+  C.ymax = 16.0 * G * (G - 1.0) / ((4.0 * G - 1.0) * (4.0 * G - 1.0));
+  C.courant = p->courant;
+  C.flux = p->flux;
+  C.tol_pmhd = p->tol_pmhd;
+  C.tol_urad = p->tol_urad;
+  C.tol_accept = p->tol_accept;
+  C.tol_fail = p->tol_fail;
+  C.max_iter = p->max_iter;
+  C.roundoff = p->roundoff;
+  C.rho_floor = p->rho_floor;
+  C.u_floor = p->u_floor;
+  C.bsq_rho_max = p->bsq_rho_max;
+  C.bsq_u_max = p->bsq_u_max;
+  C.u_rho_max = p->u_rho_max;
+  C.erad_floor = p->erad_floor;
+}
+
+extern "C" int grrmhd_init_grid(const grrmhd_params* p, int device, void* hip_stream,
+                                grrmhd_grid** out) {
+  if (!out) return fail(GRRMHD_EINVAL, "out is NULL");
+  *out = nullptr;
+  int rc = validate(p, true);
+  if (rc) return rc;
+  int ndev = 0;
+  HIPCHK(hipGetDeviceCount(&ndev));
+  if (device < 0 || device >= ndev) return fail(GRRMHD_EINVAL, "device ordinal out of range");
+  HIPCHK(hipSetDevice(device));
+  grrmhd_grid* g = new grrmhd_grid;
+  g->p = *p;
+  g->device = device;
+  g->stream = (hipStream_t)hip_stream;
+  fill_ctx(p, g->C);
+  const size_t tab = (size_t)g->C.npos;
+  const size_t nd = tab * (GE_NCENTER + 2 * GE_NFACE);
+  hipError_t e = hipMalloc(&g->geo, nd * sizeof(double) + 64);
+  if (e != hipSuccess) {
+    delete g;
+    return fail(GRRMHD_ENOMEM, std::string("geometry allocation: ") + hipGetErrorString(e));
+  }
+  g->dtslot = (unsigned long long*)(g->geo + nd);
+  g->C.geo_c = g->geo;
+  g->C.geo_f1 = g->geo + tab * GE_NCENTER;
+  g->C.geo_f2 = g->geo + tab * (GE_NCENTER + GE_NFACE);
+  hipLaunchKernelGGL(k_geometry, dim3(nblocks(g->C.npos, 256)), dim3(256), 0, g->stream, g->C,
+                     p->a, p->R0, g->geo, (double*)g->C.geo_f1, (double*)g->C.geo_f2);
+  e = hipGetLastError();
+  if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
+  if (e != hipSuccess) {
+    (void)hipFree(g->geo);
+    delete g;
+    return fail(GRRMHD_EHIP, std::string("geometry kernel: ") + hipGetErrorString(e));
+  }
+  *out = g;
+  return 0;
+}
+
+extern "C" int grrmhd_free_grid(grrmhd_grid* g) {
+  if (!g) return 0;
+  HIPCHK(hipSetDevice(g->device));
+  HIPCHK(hipStreamSynchronize(g->stream));
+  HIPCHK(hipFree(g->geo));
+  delete g;
+  return 0;
+}
+
+extern "C" int grrmhd_set_stream(grrmhd_grid* g, void* s) {
+  if (!g) return fail(GRRMHD_EINVAL, "grid is NULL");
+  g->stream = (hipStream_t)s;
+  return 0;
+}
+
+extern "C" long grrmhd_ncell_alloc(const grrmhd_grid* g) { return g ? g->C.Ntot : -1; }
+
+// workspace layout (doubles unless noted), each part 256-byte aligned
+struct WsLayout {
+  size_t F, emf, vch, Uexp, Pa, Ua, err, st, it, total;
+};
+
+static WsLayout ws_layout(const Ctx& C) {
+  WsLayout w;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += (bytes + 255) & ~(size_t)255;
+    return o;
+  };
+  const size_t N = (size_t)C.Ntot;
+  w.F = take(sizeof(double) * 36 * N);
+  w.emf = take(sizeof(double) * 3 * N);
+  w.vch = take(sizeof(double) * 3 * N);
+  w.Uexp = take(sizeof(double) * 13 * N);
+  w.Pa = take(sizeof(double) * 12 * N);
+  w.Ua = take(sizeof(double) * 12 * N);
+  w.err = take(sizeof(double) * N);
+  w.st = take(sizeof(int) * N);
+  w.it = take(sizeof(int) * N);
+  w.total = off;
+  return w;
+}
+
+extern "C" size_t grrmhd_workspace_bytes(const grrmhd_grid* g) {
+  return g ? ws_layout(g->C).total : 0;
+}
+
+// ---------------------------------------------------------------------------
+// launch helpers
+// ---------------------------------------------------------------------------
+static int launch_bc(grrmhd_grid* g, double* P) {
+  const Ctx& C = g->C;
+  for (int d = 0; d < 3; d++) {
+    if (C.ng[d] == 0) continue;
+    const long n = 2L * C.ng[d] * C.N[(d + 1) % 3] * C.N[(d + 2) % 3];
+    hipLaunchKernelGGL(k_bc, dim3(nblocks(n, 256)), dim3(256), 0, g->stream, C, d, P);
+    LAUNCHCHK();
+  }
+  return 0;
+}
+
+static FaceRange face_range(const Ctx& C, int d) {
+  FaceRange R;
+  R.total = 1;
+  for (int e = 0; e < 3; e++) {
+    if (e == d) { R.lo[e] = C.ng[e]; R.cnt[e] = C.n[e] + 1; }
+    else if (C.n[e] > 1) { R.lo[e] = C.ng[e] - 1; R.cnt[e] = C.n[e] + 2; }
+    else { R.lo[e] = 0; R.cnt[e] = 1; }
+    R.total *= R.cnt[e];
+  }
+  return R;
+}
+
+static FaceRange edge_range(const Ctx& C, int a) {
+  FaceRange R;
+  R.total = 1;
+  for (int e = 0; e < 3; e++) {
+    if (e == a) { R.lo[e] = C.ng[e]; R.cnt[e] = C.n[e]; }
+    else { R.lo[e] = C.ng[e]; R.cnt[e] = C.n[e] + 1; }
+    R.total *= R.cnt[e];
+  }
+  return R;
+}
+
+static int launch_fluxes(grrmhd_grid* g, const double* P, const double* ca, const double* ce,
+                         double* F, double* emf, double* vch) {
+  const Ctx& C = g->C;
+  const size_t N = (size_t)C.Ntot;
+  for (int d = 0; d < 3; d++) {
+    if (C.n[d] == 1) continue;
+    FaceRange R = face_range(C, d);
+    double* Fd = F + (size_t)d * 12 * N;
+    double* vd = vch + (size_t)d * N;
+    const dim3 gr(nblocks(R.total, 128)), bl(128);
+    if (d == 0) hipLaunchKernelGGL(k_flux<1>, gr, bl, 0, g->stream, C, R, P, ca, ce, Fd, vd);
+    if (d == 1) hipLaunchKernelGGL(k_flux<2>, gr, bl, 0, g->stream, C, R, P, ca, ce, Fd, vd);
+    if (d == 2) hipLaunchKernelGGL(k_flux<3>, gr, bl, 0, g->stream, C, R, P, ca, ce, Fd, vd);
+    LAUNCHCHK();
+  }
+  for (int a = 0; a < 3; a++) {
+    const int b = (a + 1) % 3, c = (a + 2) % 3;
+    if (C.n[b] == 1 || C.n[c] == 1) continue;
+    FaceRange R = edge_range(C, a);
+    hipLaunchKernelGGL(k_emf, dim3(nblocks(R.total, 256)), dim3(256), 0, g->stream, C, a, R, F, emf);
+    LAUNCHCHK();
+  }
+  return 0;
+}
+
+static long n_interior(const Ctx& C) { return (long)C.n[0] * C.n[1] * C.n[2]; }
+
+static int launch_timestep(grrmhd_grid* g, const double* vch, double* dt_dev) {
+  const Ctx& C = g->C;
+  hipLaunchKernelGGL(k_dt_init, dim3(1), dim3(1), 0, g->stream, g->dtslot);
+  LAUNCHCHK();
+  hipLaunchKernelGGL(k_dt_min, dim3(nblocks(n_interior(C), 256)), dim3(256), 0, g->stream, C, vch,
+                     g->dtslot);
+  LAUNCHCHK();
+  hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(1), 0, g->stream, g->dtslot, C.courant, dt_dev);
+  LAUNCHCHK();
+  return 0;
+}
+
+static int launch_update(grrmhd_grid* g, double a, double b, double c, const double* dt_dev,
+                         const double* P, const double* Un, const double* Up, const double* F,
+                         const double* emf, double* Ue) {
+  hipLaunchKernelGGL(k_update, dim3(nblocks(n_interior(g->C), 256)), dim3(256), 0, g->stream,
+                     g->C, a, b, c, dt_dev, P, Un, Up, F, emf, Ue);
+  LAUNCHCHK();
+  return 0;
+}
+
+static int launch_implicit(grrmhd_grid* g, const double* Ue, const double* Pg, double scale,
+                           const double* dt_dev, const double* ca, const double* ce, double* P,
+                           double* U, int* it, int* st, double* err) {
+  hipLaunchKernelGGL(k_implicit, dim3(nblocks(n_interior(g->C), 64)), dim3(64), 0, g->stream,
+                     g->C, Ue, Pg, scale, dt_dev, ca, ce, P, U, it, st, err);
+  LAUNCHCHK();
+  return 0;
+}
+
+static int launch_fixup(grrmhd_grid* g, double* P, double* U, int* st, double* scr, int* st_acc,
+                        const int* it_stage, int* it_acc, int accumulate) {
+  const long n = n_interior(g->C);
+  hipLaunchKernelGGL(k_fixup_avg, dim3(nblocks(n, 256)), dim3(256), 0, g->stream, g->C, P, st, scr);
+  LAUNCHCHK();
+  hipLaunchKernelGGL(k_fixup_apply, dim3(nblocks(n, 256)), dim3(256), 0, g->stream, g->C, P, U, st,
+                     scr, st_acc, it_stage, it_acc, accumulate);
+  LAUNCHCHK();
+  return 0;
+}
+
+#define NEEDG()                                               \
+  do {                                                        \
+    if (!g) return fail(GRRMHD_EINVAL, "grid is NULL");       \
+    HIPCHK(hipSetDevice(g->device));                          \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// entry points
+// ---------------------------------------------------------------------------
+extern "C" int grrmhd_prim_to_cons(grrmhd_grid* g, const double* P, double* U) {
+  NEEDG();
+  if (!P || !U) return fail(GRRMHD_EINVAL, "NULL array");
+  hipLaunchKernelGGL(k_p2u, dim3(nblocks(g->C.Ntot, 256)), dim3(256), 0, g->stream, g->C, P, U);
+  LAUNCHCHK();
+  return 0;
+}
+
+extern "C" int grrmhd_apply_bc(grrmhd_grid* g, double* P) {
+  NEEDG();
+  if (!P) return fail(GRRMHD_EINVAL, "NULL array");
+  return launch_bc(g, P);
+}
+
+extern "C" int grrmhd_fluxes(grrmhd_grid* g, const double* P, const double* chi_abs,
+                             const double* chi_es, double* F, double* emf, double* vchar) {
+  NEEDG();
+  if (!P || !chi_abs || !chi_es || !F || !emf || !vchar) return fail(GRRMHD_EINVAL, "NULL array");
+  const size_t N = (size_t)g->C.Ntot;
+  HIPCHK(hipMemsetAsync(F, 0, sizeof(double) * 36 * N, g->stream));
+  HIPCHK(hipMemsetAsync(emf, 0, sizeof(double) * 3 * N, g->stream));
+  HIPCHK(hipMemsetAsync(vchar, 0, sizeof(double) * 3 * N, g->stream));
+  return launch_fluxes(g, P, chi_abs, chi_es, F, emf, vchar);
+}
+
+extern "C" int grrmhd_timestep(grrmhd_grid* g, const double* vchar, double* dt_dev) {
+  NEEDG();
+  if (!vchar || !dt_dev) return fail(GRRMHD_EINVAL, "NULL array");
+  return launch_timestep(g, vchar, dt_dev);
+}
+
+extern "C" int grrmhd_explicit_update(grrmhd_grid* g, double a, double b, double c,
+                                      const double* dt_dev, const double* P, const double* Un,
+                                      const double* Uprev, const double* F, const double* emf,
+                                      double* Uexp) {
+  NEEDG();
+  if (!dt_dev || !P || !Un || !F || !emf || !Uexp || (b != 0.0 && !Uprev))
+    return fail(GRRMHD_EINVAL, "NULL array");
+  return launch_update(g, a, b, c, dt_dev, P, Un, Uprev, F, emf, Uexp);
+}
+
+extern "C" int grrmhd_con2prim(grrmhd_grid* g, const double* U, const double* Pguess, double* P,
+                               int* status) {
+  NEEDG();
+  if (!U || !Pguess || !P) return fail(GRRMHD_EINVAL, "NULL array");
+  hipLaunchKernelGGL(k_con2prim, dim3(nblocks(n_interior(g->C), 128)), dim3(128), 0, g->stream,
+                     g->C, U, Pguess, P, status);
+  LAUNCHCHK();
+  return 0;
+}
+
+extern "C" int grrmhd_implicit_grid(grrmhd_grid* g, const double* Uexp, const double* Pguess,
+                                    double dt_scale, const double* dt_dev, const double* chi_abs,
+                                    const double* chi_es, double* P, double* U, int* iters,
+                                    int* status, double* err) {
+  NEEDG();
+  if (!Uexp || !Pguess || !dt_dev || !chi_abs || !chi_es || !P || !U)
+    return fail(GRRMHD_EINVAL, "NULL array");
+  if (U == Uexp) return fail(GRRMHD_EINVAL, "U may not alias Uexp");
+  return launch_implicit(g, Uexp, Pguess, dt_scale, dt_dev, chi_abs, chi_es, P, U, iters, status, err);
+}
+
+extern "C" int grrmhd_fixup(grrmhd_grid* g, double* P, double* U, int* status, double* scratch) {
+  NEEDG();
+  if (!P || !U || !status || !scratch) return fail(GRRMHD_EINVAL, "NULL array");
+  return launch_fixup(g, P, U, status, scratch, nullptr, nullptr, nullptr, 0);
+}
+
+extern "C" int grrmhd_step(grrmhd_grid* g, double* P, double* U, const double* chi_abs,
+                           const double* chi_es, double* dt_dev, int dt_fixed, int* status,
+                           int* iters, void* workspace, size_t ws_bytes) {
+  NEEDG();
+  if (!P || !U || !chi_abs || !chi_es || !dt_dev || !workspace)
+    return fail(GRRMHD_EINVAL, "NULL array");
+  const Ctx& C = g->C;
+  const WsLayout w = ws_layout(C);
+  if (ws_bytes < w.total) return fail(GRRMHD_EINVAL, "workspace too small");
+  if (((uintptr_t)workspace) & 255) return fail(GRRMHD_EINVAL, "workspace must be 256-byte aligned");
+  char* base = (char*)workspace;
+  double* F = (double*)(base + w.F);
+  double* emf = (double*)(base + w.emf);
+  double* vch = (double*)(base + w.vch);
+  double* Ue = (double*)(base + w.Uexp);
+  double* Pa = (double*)(base + w.Pa);
+  double* Ua = (double*)(base + w.Ua);
+  double* err = (double*)(base + w.err);
+  int* st = (int*)(base + w.st);
+  int* it = (int*)(base + w.it);
+  const size_t N = (size_t)C.Ntot;
+  (void)N;
+  // Shu-Osher RK3: U(k) = a U^n + b U(k-1) + c dt (X + M(U(k)))
+  const double A[3] = {1.0, 0.75, 1.0 / 3.0}, B[3] = {0.0, 0.25, 2.0 / 3.0},
+               Cc[3] = {1.0, 0.25, 2.0 / 3.0};
+  int rc;
+  for (int s = 0; s < 3; s++) {
+    double* Pin = (s == 0) ? P : Pa;
+    const double* Uprev = (s == 0) ? U : Ua;
+    double* Pout = (s == 2) ? P : Pa;
+    double* Uout = (s == 2) ? U : Ua;
+    if ((rc = launch_bc(g, Pin))) return rc;
+    if ((rc = launch_fluxes(g, Pin, chi_abs, chi_es, F, emf, vch))) return rc;
+    if (s == 0 && !dt_fixed && (rc = launch_timestep(g, vch, dt_dev))) return rc;
+    if ((rc = launch_update(g, A[s], B[s], Cc[s], dt_dev, Pin, U, Uprev, F, emf, Ue))) return rc;
+    if ((rc = launch_implicit(g, Ue, Pin, Cc[s], dt_dev, chi_abs, chi_es, Pout, Uout, it, st, err)))
+      return rc;
+    if ((rc = launch_fixup(g, Pout, Uout, st, Ue, status, it, iters, s > 0))) return rc;
+  }
+  return 0;
+}
+
+extern "C" int grrmhd_implicit_source(const grrmhd_params* p, long n, const double* U_expl,
+                                      const double* P_guess, const double* dt_cell,
+                                      const double* chi_abs, const double* chi_es, double* P_out,
+                                      double* U_out, int* iters, int* status, double* err,
+                                      void* hip_stream) {
+  int rc = validate(p, false);
+  if (rc) return rc;
+  if (n < 0) return fail(GRRMHD_EINVAL, "n < 0");
+  if (n == 0) return 0;
+  if (!U_expl || !P_guess || !dt_cell || !chi_abs || !chi_es || !P_out || !U_out)
+    return fail(GRRMHD_EINVAL, "NULL array");
+  if (p->metric != GRRMHD_MINKOWSKI) return fail(GRRMHD_EINVAL, "batched cells use the Minkowski metric");
+  Ctx C;
+  fill_ctx(p, C);
+  hipLaunchKernelGGL(k_implicit_batch, dim3(nblocks(n, 64)), dim3(64), 0, (hipStream_t)hip_stream,
+                     C, n, U_expl, P_guess, dt_cell, chi_abs, chi_es, P_out, U_out, iters, status, err);
+  LAUNCHCHK();
+  return 0;
+}

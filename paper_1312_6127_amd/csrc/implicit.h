@@ -1,0 +1,514 @@
+// Implicit radiation 4-force solve for one cell on the device (Sec. 4.7-4.11).
+//
+// Unknowns are iterated with an undamped Newton method ("normal" Newton of
+// Sec. 4.10).  PMHD iterates the gas primitives (u_g, u~^i) and gets its 4x4
+// Jacobian exactly from a Dual<4> evaluation of the residual.  URAD iterates
+// R^t_nu, inverts T^t_nu = T(i) - Delta R to gas primitives inside every
+// residual, and uses a one-sided finite-difference Jacobian (Sec. 4.9).
+// Pre-step checks, post-step checks, stopping rules, guesses, method order
+// and acceptance follow Sec. 4.10-4.11.
+#pragma once
+#include <float.h>
+
+#include "invert.h"
+
+enum { M_PMHD = 0, M_URAD = 1 };
+
+struct Cell {
+  Metric m;
+  double rhout, B[3];
+  double Tgi[4], Ri[4];   // explicit gas (T^t_t + rho u^t, T^t_i) and radiation R^t_nu
+  double dt, chi_abs, chi_es;
+};
+
+struct Eval {
+  double x[4];
+  double P[12];
+  double Tg[4], Rr[4], G[4], Eg[4], Er[4];
+  double J[4][4];         // d(iterated residual)/dx (PMHD only)
+  double eT, eIg, eIr;
+  int radflags, ok;
+};
+
+DEV double snorm3(const Metric& m, const double V[4]) {
+  double s = 0.0;
+#pragma unroll
+  for (int i = 0; i < 3; i++)
+#pragma unroll
+    for (int j = 0; j < 3; j++) s += gamup(m, i, j) * V[1 + i] * V[1 + j];
+  return ::sqrt(fmax(s, 0.0));
+}
+
+// Normalised errors (Sec. 4.8): gas residual over gas-scale terms and
+// dt|G|, radiation residual over radiation-scale terms and dt|G|; spatial
+// parts merged in the normal observer's orthonormal basis plus the energy
+// scale; e_T = 1/4 sum over equations of the larger of the two.
+DEV void norm_errors(const Cell& c, Eval& e) {
+  double Gdt[4];
+#pragma unroll
+  for (int k = 0; k < 4; k++) Gdt[k] = c.dt * e.G[k];
+  const double g0 = ::fabs(Gdt[0]), gs = snorm3(c.m, Gdt);
+  double ntg = ::fabs(e.Tg[0]) + ::fabs(c.Tgi[0]) + g0;
+  double ntr = ::fabs(e.Rr[0]) + ::fabs(c.Ri[0]) + g0;
+  if (!(ntg > 0.0)) ntg = 1e-300;
+  if (!(ntr > 0.0)) ntr = 1e-300;
+  const double nsg = snorm3(c.m, e.Tg) + snorm3(c.m, c.Tgi) + gs + ntg;
+  const double nsr = snorm3(c.m, e.Rr) + snorm3(c.m, c.Ri) + gs + ntr;
+  double eg[4], er[4];
+  eg[0] = ::fabs(e.Eg[0]) / ntg;
+  er[0] = ::fabs(e.Er[0]) / ntr;
+#pragma unroll
+  for (int i = 0; i < 3; i++) {
+    const double w = ::sqrt(gamup(c.m, i, i));
+    eg[1 + i] = ::fabs(e.Eg[1 + i]) * w / nsg;
+    er[1 + i] = ::fabs(e.Er[1 + i]) * w / nsr;
+  }
+  if (e.radflags & 1) eg[0] = er[0] = 0.0;
+  double t = 0.0, ig = 0.0, ir = 0.0;
+#pragma unroll
+  for (int k = 0; k < 4; k++) {
+    t += fmax(eg[k], er[k]);
+    ig += eg[k];
+    ir += er[k];
+  }
+  e.eT = 0.25 * t;
+  e.eIg = 0.25 * ig;
+  e.eIr = 0.25 * ir;
+  if (!isfinite(e.eT)) {
+    e.eT = INFINITY;
+    e.ok = 0;
+  }
+}
+
+struct Phys {
+  double gam, arad, gamma_max, ymax;
+};
+
+// PMHD residual with exact derivatives (Sec. 4.8, PMHD steps in order):
+// rho0 = (rho u^t)/u^t; T^t_nu from the gas; Delta R = -Delta T; TYPE2
+// radiation inversion; R recomputed; G; residuals.
+DEV void eval_pmhd(const Cell& c, const Phys& ph, const double x[4], Eval& e) {
+  typedef Dual<4> D4;
+  D4 ug = D4::var(x[0], 0);
+  D4 ut[3] = {D4::var(x[1], 1), D4::var(x[2], 2), D4::var(x[3], 3)};
+  D4 B[3] = {D4(c.B[0]), D4(c.B[1]), D4(c.B[2])};
+  Gas<D4> s;
+  Vel<D4> v;
+  make_vel(c.m, ut, v);
+  const D4 rho = c.rhout / v.ucon[0];
+  make_gas(c.m, ph.gam, rho, ug, ut, B, s);
+  D4 row[8];
+  gas_row(s, B, 0, row);
+  D4 R[4];
+#pragma unroll
+  for (int k = 0; k < 4; k++) R[k] = c.Ri[k] - (row[1 + k] - c.Tgi[k]);
+  D4 Eb, utr[3];
+  e.radflags = rad_invert(c.m, ph.gamma_max, ph.ymax, 1, R, Eb, utr);
+  Vel<D4> r;
+  make_vel(c.m, utr, r);
+  D4 Rr[4];
+  rad_row(r, Eb, 0, Rr);
+  const D4 Tg = s.pg / rho;
+  const D4 T2 = Tg * Tg;
+  const D4 kabs = c.chi_abs * rho, kes = c.chi_es * rho;
+  const D4 lam = kabs * ph.arad * (T2 * T2);
+  D4 G[4];
+  four_force(s.v, r, Eb, kabs, kes, lam, G);
+#pragma unroll
+  for (int k = 0; k < 4; k++) {
+    const D4 Egk = (row[1 + k] - c.Tgi[k]) - c.dt * G[k];
+    e.x[k] = x[k];
+    e.Tg[k] = row[1 + k].v;
+    e.Rr[k] = Rr[k].v;
+    e.G[k] = G[k].v;
+    e.Eg[k] = Egk.v;
+    e.Er[k] = (Rr[k].v - c.Ri[k]) + c.dt * G[k].v;
+#pragma unroll
+    for (int j = 0; j < 4; j++) e.J[k][j] = Egk.d[j];
+  }
+  e.P[0] = rho.v;
+  e.P[1] = x[0];
+#pragma unroll
+  for (int i = 0; i < 3; i++) {
+    e.P[2 + i] = x[1 + i];
+    e.P[5 + i] = c.B[i];
+    e.P[9 + i] = utr[i].v;
+  }
+  e.P[8] = Eb.v;
+  e.ok = 1;
+  norm_errors(c, e);
+}
+
+// URAD residual (Sec. 4.8, URAD steps): gas from inverting T(i) - Delta R,
+// radiation from TYPE2 inversion of x, both recomputed for consistency.
+// Pgas (rho, u_g, u~^i) is the starting guess of the MHD iteration.
+DEV void eval_urad(const Cell& c, const Phys& ph, const double x[4], const double Pgas[5],
+                   Eval& e) {
+  e.ok = 1;
+#pragma unroll
+  for (int k = 0; k < 4; k++) e.x[k] = x[k];
+  double Tt[3] = {c.Tgi[1] - (x[1] - c.Ri[1]), c.Tgi[2] - (x[2] - c.Ri[2]),
+                  c.Tgi[3] - (x[3] - c.Ri[3])};
+  const double Eg = c.Tgi[0] - (x[0] - c.Ri[0]);
+  double rho = Pgas[0], ug = Pgas[1], ut[3] = {Pgas[2], Pgas[3], Pgas[4]};
+  if (mhd_invert(c.m, ph.gam, c.rhout, Eg, Tt, c.B, rho, ug, ut)) {
+    e.ok = 0;
+    e.eT = INFINITY;
+    return;
+  }
+  double Eb, utr[3];
+  e.radflags = rad_invert(c.m, ph.gamma_max, ph.ymax, 1, x, Eb, utr);
+  Gas<double> s;
+  make_gas(c.m, ph.gam, rho, ug, ut, c.B, s);
+  double row[8];
+  gas_row(s, c.B, 0, row);
+  Vel<double> r;
+  make_vel(c.m, utr, r);
+  double Rr[4];
+  rad_row(r, Eb, 0, Rr);
+  const double Tgas = s.pg / rho;
+  const double kabs = c.chi_abs * rho, kes = c.chi_es * rho;
+  const double lam = kabs * ph.arad * (Tgas * Tgas) * (Tgas * Tgas);
+  double G[4];
+  four_force(s.v, r, Eb, kabs, kes, lam, G);
+#pragma unroll
+  for (int k = 0; k < 4; k++) {
+    e.Tg[k] = row[1 + k];
+    e.Rr[k] = Rr[k];
+    e.G[k] = G[k];
+    e.Eg[k] = (row[1 + k] - c.Tgi[k]) - c.dt * G[k];
+    e.Er[k] = (Rr[k] - c.Ri[k]) + c.dt * G[k];
+  }
+  e.P[0] = rho;
+  e.P[1] = ug;
+#pragma unroll
+  for (int i = 0; i < 3; i++) {
+    e.P[2 + i] = ut[i];
+    e.P[5 + i] = c.B[i];
+    e.P[9 + i] = utr[i];
+  }
+  e.P[8] = Eb;
+  norm_errors(c, e);
+}
+
+// 4x4 solve with partial pivoting; 0 on success
+DEV int solve4(double A[4][4], double b[4], double xo[4]) {
+#pragma unroll
+  for (int k = 0; k < 4; k++) {
+    int p = k;
+    double best = ::fabs(A[k][k]);
+#pragma unroll
+    for (int i = k + 1; i < 4; i++)
+      if (::fabs(A[i][k]) > best) { best = ::fabs(A[i][k]); p = i; }
+    if (!(best > 0.0) || !isfinite(best)) return 1;
+    if (p != k) {
+#pragma unroll
+      for (int j = 0; j < 4; j++) { const double t = A[k][j]; A[k][j] = A[p][j]; A[p][j] = t; }
+      const double t = b[k]; b[k] = b[p]; b[p] = t;
+    }
+    const double inv = 1.0 / A[k][k];
+#pragma unroll
+    for (int i = k + 1; i < 4; i++) {
+      const double f = A[i][k] * inv;
+#pragma unroll
+      for (int j = k; j < 4; j++) A[i][j] -= f * A[k][j];
+      b[i] -= f * b[k];
+    }
+  }
+#pragma unroll
+  for (int i = 3; i >= 0; i--) {
+    double s = b[i];
+#pragma unroll
+    for (int j = i + 1; j < 4; j++) s -= A[i][j] * xo[j];
+    xo[i] = s / A[i][i];
+  }
+#pragma unroll
+  for (int i = 0; i < 4; i++)
+    if (!isfinite(xo[i])) return 1;
+  return 0;
+}
+
+DEV double rad_energy_lab(const Metric& m, const double R[4]) {
+  return -R[0] + m.alpha * m.alpha * (m.up(0, 1) * R[1] + m.up(0, 2) * R[2] + m.up(0, 3) * R[3]);
+}
+
+struct Best {
+  double x[4], P[12], Tg[4], Rr[4], eT;
+  int radflags, ok;
+};
+
+DEV void keep(Best& b, const Eval& e) {
+#pragma unroll
+  for (int k = 0; k < 4; k++) { b.x[k] = e.x[k]; b.Tg[k] = e.Tg[k]; b.Rr[k] = e.Rr[k]; }
+#pragma unroll
+  for (int q = 0; q < 12; q++) b.P[q] = e.P[q];
+  b.eT = e.eT;
+  b.radflags = e.radflags;
+  b.ok = e.ok;
+}
+
+struct Opts {
+  double tol_pmhd, tol_urad;
+  int max_iter, roundoff;
+};
+
+// One "normal" Newton attempt (D = 1) with one method.
+DEV void newton(const Cell& c, const Phys& ph, const Opts& o, int method, const double x0[4],
+                const double Pg0[5], Best& best, int& iters) {
+  const double tol = (method == M_PMHD) ? o.tol_pmhd : o.tol_urad;
+  double x[4] = {x0[0], x0[1], x0[2], x0[3]};
+  Eval ev;
+  if (method == M_PMHD) eval_pmhd(c, ph, x, ev);
+  else eval_urad(c, ph, x, Pg0, ev);
+  keep(best, ev);
+  if (!ev.ok) return;
+  double h[5];           // last five e_T, h[4] newest
+#pragma unroll
+  for (int k = 0; k < 4; k++) h[k] = INFINITY;
+  h[4] = ev.eT;
+  int nrise = 0, extra = 0, conv = 0, nfail = 0;
+  for (int it = 0; it < o.max_iter; it++) {
+    if (ev.eT < tol) conv = 1;
+    if (conv) {
+      if (!o.roundoff || extra >= 3) break;
+      extra++;
+    }
+    if (!conv && it >= 5 && ev.eT > 0.5 * (h[0] + h[1] + h[2]) * (1.0 / 3.0)) break;
+    double J[4][4], r[4];
+    if (method == M_PMHD) {
+#pragma unroll
+      for (int i = 0; i < 4; i++) {
+        r[i] = ev.Eg[i];
+#pragma unroll
+        for (int j = 0; j < 4; j++) J[i][j] = ev.J[i][j];
+      }
+    } else {
+      const double delta = (ev.eIr < 1e-9) ? 1e-10 : 1e-8;
+      int jfail = 0;
+      double Pn[5] = {ev.P[0], ev.P[1], ev.P[2], ev.P[3], ev.P[4]};
+      for (int j = 0; j < 4 && !jfail; j++) {
+        const double N = (j == 0) ? ::fabs(x[0]) : ::fabs(x[j]) + ::fabs(x[0]) / ::sqrt(gamup(c.m, j - 1, j - 1));
+        double hh = delta * N;
+        int got = 0;
+        for (int tries = 0; tries < 12 && !got; tries++) {
+          double xp[4] = {x[0], x[1], x[2], x[3]};
+          xp[j] += hh;
+          Eval ep;
+          eval_urad(c, ph, xp, Pn, ep);
+          if (ep.ok) {
+            const double ih = 1.0 / hh;
+#pragma unroll
+            for (int i = 0; i < 4; i++) J[i][j] = (ep.Er[i] - ev.Er[i]) * ih;
+            got = 1;
+          } else {
+            hh = (tries % 2 == 0) ? -hh : -10.0 * hh;
+            if (::fabs(hh) > 0.3 * N) break;
+          }
+        }
+        if (!got) jfail = 1;
+      }
+      if (jfail) break;
+#pragma unroll
+      for (int i = 0; i < 4; i++) r[i] = ev.Er[i];
+    }
+    double dx[4];
+    if (solve4(J, r, dx)) break;
+    double xn[4];
+#pragma unroll
+    for (int i = 0; i < 4; i++) xn[i] = x[i] - dx[i];
+    Eval en;
+    if (method == M_PMHD) {
+      if (xn[0] < 0.0) xn[0] = 0.5 * ::fabs(xn[0]);            // one-sided bisection of u_g
+      eval_pmhd(c, ph, xn, en);
+    } else {
+      const double Erl = rad_energy_lab(c.m, xn);
+      if (Erl <= 0.0) {                                       // same for the radiation energy
+        const double a2 = c.m.alpha * c.m.alpha;
+        xn[0] = -0.5 * ::fabs(Erl) + a2 * (c.m.up(0, 1) * xn[1] + c.m.up(0, 2) * xn[2] + c.m.up(0, 3) * xn[3]);
+      }
+      double Pn[5] = {ev.P[0], ev.P[1], ev.P[2], ev.P[3], ev.P[4]};
+      eval_urad(c, ph, xn, Pn, en);
+      int back = 0;
+      while (!en.ok && back < 20) {                           // back up half-way
+        nfail++;
+#pragma unroll
+        for (int i = 0; i < 4; i++) xn[i] = 0.5 * (x[i] + xn[i]);
+        eval_urad(c, ph, xn, Pn, en);
+        back++;
+      }
+      if (!en.ok || nfail > 3) {
+        iters++;
+        break;
+      }
+    }
+    iters++;
+    bool small = true;
+#pragma unroll
+    for (int i = 0; i < 4; i++)
+      if (::fabs(xn[i] - x[i]) > 10.0 * DBL_EPSILON * ::fabs(x[i])) small = false;
+#pragma unroll
+    for (int i = 0; i < 4; i++) x[i] = xn[i];
+    const double prev = h[4];
+    ev = en;
+#pragma unroll
+    for (int k = 0; k < 4; k++) h[k] = h[k + 1];
+    h[4] = ev.eT;
+    if (ev.eT < best.eT) keep(best, ev);
+    if (it >= 5 && ev.eT > prev) {
+      nrise++;
+      if (nrise >= 5) break;
+    }
+    if (small) break;
+  }
+}
+
+struct CellOut {
+  double P[12], U[12];
+  int status, iters;
+  double err;
+};
+
+// Full cascade for one cell (Sec. 4.10-4.11).  Ui: explicit conserved state
+// without sqrt(-g) factors removed (densitised, as stored); Pg: previous
+// primitives (the guess).
+DEV void implicit_cell(const Metric& m, const Phys& ph, const Opts& o, double tol_accept,
+                       double tol_fail, const double Ui[12], const double Pg[12], double dt,
+                       double chi_abs, double chi_es, CellOut& out) {
+  Cell c;
+  c.m = m;
+  const double igd = 1.0 / m.gdet;
+  c.rhout = Ui[0] * igd;
+#pragma unroll
+  for (int i = 0; i < 3; i++) c.B[i] = Ui[5 + i] * igd;
+#pragma unroll
+  for (int k = 0; k < 4; k++) {
+    c.Tgi[k] = Ui[1 + k] * igd;
+    c.Ri[k] = Ui[8 + k] * igd;
+  }
+  c.dt = dt;
+  c.chi_abs = chi_abs;
+  c.chi_es = chi_es;
+  int status = 0, iters = 0;
+
+  // extreme radiation sub-dominance: R^t_t against the gas energy, or the
+  // gas-frame radiation energy of the guess against u_g, below 10 eps
+  double Ehat;
+  {
+    Vel<double> u, r;
+    make_vel(m, Pg + 2, u);
+    make_vel(m, Pg + 9, r);
+    double w = 0.0;
+#pragma unroll
+    for (int a = 0; a < 4; a++) w += r.ucon[a] * u.ucov[a];
+    Ehat = (4.0 / 3.0) * Pg[8] * w * w - Pg[8] * (1.0 / 3.0);
+  }
+  const double tenEps = 10.0 * DBL_EPSILON;
+  const bool extreme = (::fabs(c.Ri[0]) <= tenEps * (::fabs(c.Tgi[0]) + ::fabs(c.Ri[0]))) ||
+                       (::fabs(Ehat) <= tenEps * (::fabs(Pg[1]) + ::fabs(Ehat)));
+  if (extreme) status |= GRRMHD_ST_EXTREME;
+
+  // PMHD guess: prior primitives, or the MHD inversion of U(i) when the
+  // temporal optical depth dt kappa_tot(P_n) < 2/3
+  double Pthin[5] = {Pg[0], Pg[1], Pg[2], Pg[3], Pg[4]};
+  if (dt * (chi_abs + chi_es) * Pg[0] < 2.0 / 3.0) {
+    double rho = Pg[0], ug = Pg[1], ut[3] = {Pg[2], Pg[3], Pg[4]};
+    if (mhd_invert(m, ph.gam, c.rhout, c.Tgi[0], c.Tgi + 1, c.B, rho, ug, ut) == 0) {
+      Pthin[0] = rho; Pthin[1] = ug; Pthin[2] = ut[0]; Pthin[3] = ut[1]; Pthin[4] = ut[2];
+    } else {
+      status |= GRRMHD_ST_C2P_FAIL;
+    }
+  }
+
+  Best best;
+  best.eT = INFINITY;
+  best.ok = 0;
+  int bm = -1;
+  for (int k = 0; k < 2; k++) {
+    const int method = (k == 0) == extreme ? M_URAD : M_PMHD;
+    double x0[4], P0[5];
+    const bool prev = (bm >= 0 && best.eT < 1e-4);
+    if (method == M_PMHD) {
+      const double* src = prev ? best.P : Pthin;
+      x0[0] = src[1]; x0[1] = src[2]; x0[2] = src[3]; x0[3] = src[4];
+#pragma unroll
+      for (int q = 0; q < 5; q++) P0[q] = src[q];
+    } else if (prev) {
+#pragma unroll
+      for (int q = 0; q < 4; q++) x0[q] = best.Rr[q];
+#pragma unroll
+      for (int q = 0; q < 5; q++) P0[q] = best.P[q];
+    } else {
+      Vel<double> r;
+      make_vel(m, Pg + 9, r);
+      rad_row(r, Pg[8], 0, x0);
+#pragma unroll
+      for (int q = 0; q < 5; q++) P0[q] = Pg[q];
+    }
+    Best b;
+    b.eT = INFINITY;
+    b.ok = 0;
+    newton(c, ph, o, method, x0, P0, b, iters);
+    if (b.ok && b.eT < best.eT) {
+      best = b;
+      bm = method;
+    }
+    // accepted without a further method (Sec. 4.10); in round-off mode keep
+    // going until one method meets the PMHD tolerance
+    if (best.eT < (o.roundoff ? o.tol_pmhd : tol_accept)) break;
+  }
+
+#pragma unroll
+  for (int q = 0; q < 12; q++) {
+    out.P[q] = Pg[q];
+    out.U[q] = Ui[q];
+  }
+  out.iters = iters;
+  if (bm < 0) {
+    out.status = status | GRRMHD_ST_FAIL;
+    out.err = INFINITY;
+    return;
+  }
+  status |= (bm == M_PMHD) ? GRRMHD_ST_PMHD : GRRMHD_ST_URAD;
+  if (best.eT > tol_fail) status |= GRRMHD_ST_FAIL;
+  else if (best.eT > tol_accept) status |= GRRMHD_ST_NOT_ACCEPT;
+  if (best.radflags & 1) status |= GRRMHD_ST_TYPE2_NEG;
+#pragma unroll
+  for (int q = 0; q < 12; q++) out.P[q] = best.P[q];
+  double Ug[4], Ur[4];
+#pragma unroll
+  for (int k = 0; k < 4; k++) {
+    if (bm == M_PMHD) {
+      Ug[k] = best.Tg[k];
+      Ur[k] = c.Ri[k] - (best.Tg[k] - c.Tgi[k]);
+    } else {
+      Ur[k] = best.x[k];
+      Ug[k] = c.Tgi[k] - (best.x[k] - c.Ri[k]);
+    }
+  }
+  bool radchg = best.radflags != 0;
+  if (bm == M_PMHD && (best.radflags & 1)) {
+    double Eb, utr[3];
+    rad_invert(m, ph.gamma_max, ph.ymax, 0, Ur, Eb, utr);
+    out.P[8] = Eb;
+    out.P[9] = utr[0]; out.P[10] = utr[1]; out.P[11] = utr[2];
+    status |= GRRMHD_ST_BASIC;
+    radchg = true;
+  }
+  if (radchg) {
+    Vel<double> r;
+    make_vel(m, out.P + 9, r);
+    rad_row(r, out.P[8], 0, Ur);
+  }
+  const double gd = m.gdet;
+  out.U[0] = Ui[0];
+#pragma unroll
+  for (int k = 0; k < 4; k++) {
+    out.U[1 + k] = gd * Ug[k];
+    out.U[8 + k] = gd * Ur[k];
+  }
+#pragma unroll
+  for (int i = 0; i < 3; i++) out.U[5 + i] = Ui[5 + i];
+  if (!(out.P[1] > 0.0)) status |= GRRMHD_ST_FAIL;
+  out.status = status;
+  out.err = best.eT;
+}

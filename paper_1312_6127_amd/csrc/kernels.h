@@ -1,0 +1,650 @@
+// HIP kernels of one GRRMHD Runge-Kutta sub-step (Sec. 4.2 steps 1-13).
+// All state arrays are field-major SoA over the allocated grid; consecutive
+// threads take consecutive i (x1) so every field access is coalesced.
+#pragma once
+#include "implicit.h"
+
+#define LB(n) __launch_bounds__(n)
+
+DEV long cell_index(const Ctx& C, int i, int j, int k) { return i + C.st[1] * j + C.st[2] * k; }
+
+// ---------------------------------------------------------------------------
+// geometry (Sec. 2): metric and its x1/x2 derivatives via Dual<2>
+// ---------------------------------------------------------------------------
+template <class T>
+DEV void ks_metric_lower(double a, double R0, const T& x1, const T& x2, T g[10]) {
+  const T er = exp(x1);
+  const T r = R0 + er;
+  const T th = M_PI * x2;
+  const T s = sin(th), c = cos(th);
+  const T s2 = s * s;
+  const T Sig = r * r + (a * a) * (c * c);
+  const T z = 2.0 * r / Sig;
+  // KS components in (t, r, theta, phi) times the map Jacobian (1, er, pi, 2 pi)
+  g[sym(0, 0)] = z - 1.0;
+  g[sym(0, 1)] = z * er;
+  g[sym(0, 2)] = T(0.0);
+  g[sym(0, 3)] = -(a * 2.0 * M_PI) * z * s2;
+  g[sym(1, 1)] = (1.0 + z) * er * er;
+  g[sym(1, 2)] = T(0.0);
+  g[sym(1, 3)] = -(a * 2.0 * M_PI) * (1.0 + z) * s2 * er;
+  g[sym(2, 2)] = (M_PI * M_PI) * Sig;
+  g[sym(2, 3)] = T(0.0);
+  g[sym(3, 3)] = (4.0 * M_PI * M_PI) * s2 * (Sig + (a * a) * (1.0 + z) * s2);
+}
+
+__global__ void LB(256) k_geometry(Ctx C, double a, double R0, double* gc, double* gf1,
+                                   double* gf2) {
+  const int pos = blockIdx.x * blockDim.x + threadIdx.x;
+  if (pos >= C.npos) return;
+  const int i = pos % C.N[0], j = pos / C.N[0];
+  for (int loc = 0; loc < 3; loc++) {
+    double* tab = loc == 0 ? gc : (loc == 1 ? gf1 : gf2);
+    const double x1 = C.xlo[0] + (i - C.ng[0] + (loc == 1 ? 0.0 : 0.5)) * C.dx[0];
+    const double x2 = C.xlo[1] + (j - C.ng[1] + (loc == 2 ? 0.0 : 0.5)) * C.dx[1];
+    double gl[10], gu[10], d1[10], d2[10], gdet, alpha;
+    if (C.metric == GRRMHD_MINKOWSKI) {
+      for (int q = 0; q < 10; q++) gl[q] = gu[q] = d1[q] = d2[q] = 0.0;
+      gl[0] = gu[0] = -1.0;
+      gl[4] = gu[4] = gl[7] = gu[7] = gl[9] = gu[9] = 1.0;
+      gdet = alpha = 1.0;
+    } else {
+      Dual<2> g[10];
+      ks_metric_lower(a, R0, Dual<2>::var(x1, 0), Dual<2>::var(x2, 1), g);
+      for (int q = 0; q < 10; q++) {
+        gl[q] = g[q].v;
+        d1[q] = g[q].d[0];
+        d2[q] = g[q].d[1];
+      }
+      const double er = ::exp(x1), r = R0 + er, th = M_PI * x2;
+      const double s = ::sin(th), c = ::cos(th);
+      const double Sig = r * r + a * a * c * c, Del = r * r - 2.0 * r + a * a;
+      const double z = 2.0 * r / Sig;
+      const double J[4] = {1.0, er, M_PI, 2.0 * M_PI};
+      for (int q = 0; q < 10; q++) gu[q] = 0.0;
+      gu[sym(0, 0)] = -(1.0 + z);
+      gu[sym(0, 1)] = z / J[1];
+      gu[sym(1, 1)] = Del / Sig / (J[1] * J[1]);
+      gu[sym(1, 3)] = a / Sig / (J[1] * J[3]);
+      gu[sym(2, 2)] = 1.0 / Sig / (J[2] * J[2]);
+      // g^{phi phi} diverges on the axis (only face tables touch it, and
+      // nothing there reads it)
+      gu[sym(3, 3)] = (s != 0.0) ? 1.0 / (Sig * s * s) / (J[3] * J[3]) : 0.0;
+      gdet = Sig * ::fabs(s) * J[1] * J[2] * J[3];
+      alpha = 1.0 / ::sqrt(1.0 + z);
+    }
+    for (int q = 0; q < 10; q++) {
+      tab[(GE_GCOV + q) * C.npos + pos] = gl[q];
+      tab[(GE_GCON + q) * C.npos + pos] = gu[q];
+    }
+    tab[GE_GDET * C.npos + pos] = gdet;
+    tab[GE_ALPHA * C.npos + pos] = alpha;
+    if (loc == 0)
+      for (int q = 0; q < 10; q++) {
+        tab[(GE_DG1 + q) * C.npos + pos] = d1[q];
+        tab[(GE_DG2 + q) * C.npos + pos] = d2[q];
+      }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// step 1: ghost cells, one dimension per launch
+// ---------------------------------------------------------------------------
+__global__ void LB(256) k_bc(Ctx C, int d, double* P) {
+  const int d1 = (d + 1) % 3, d2 = (d + 2) % 3;
+  const int ng = C.ng[d], n = C.n[d];
+  const long per_side = (long)ng * C.N[d1] * C.N[d2];
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 2 * per_side) return;
+  const int side = t >= per_side;
+  long r = side ? t - per_side : t;
+  const int m = r % ng;
+  r /= ng;
+  const int a = r % C.N[d1];
+  const int b = r / C.N[d1];
+  const int bc = side ? C.bc_hi[d] : C.bc_lo[d];
+  int cd[3], sd[3];
+  cd[d] = side ? ng + n + m : ng - 1 - m;
+  if (bc == GRRMHD_BC_OUTFLOW) sd[d] = side ? ng + n - 1 : ng;
+  else if (bc == GRRMHD_BC_PERIODIC) sd[d] = side ? ng + m : ng + n - 1 - m;
+  else sd[d] = side ? ng + n - 1 - m : ng + m;
+  cd[d1] = sd[d1] = a;
+  cd[d2] = sd[d2] = b;
+  if (bc == GRRMHD_BC_POLAR && d == 1 && C.n[2] > 1) {
+    // across the axis: phi + pi; x3 ghosts are filled by the later x3 pass
+    const int g3 = C.ng[2], n3 = C.n[2];
+    if (sd[2] < g3 || sd[2] >= g3 + n3) return;
+    sd[2] = g3 + (sd[2] - g3 + n3 / 2) % n3;
+  }
+  const long dst = cell_index(C, cd[0], cd[1], cd[2]);
+  const long src = cell_index(C, sd[0], sd[1], sd[2]);
+  const bool flip = (bc == GRRMHD_BC_REFLECT || bc == GRRMHD_BC_POLAR);
+#pragma unroll
+  for (int q = 0; q < 12; q++) {
+    double v = P[q * C.Ntot + src];
+    if (flip && (q == 2 + d || q == 5 + d || q == 9 + d)) v = -v;
+    P[q * C.Ntot + dst] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// steps 2-3 helper and P -> U kernel
+// ---------------------------------------------------------------------------
+DEV void prim_to_cons_cell(const Metric& m, double gam, const double* P, double* U) {
+  Gas<double> s;
+  make_gas(m, gam, P[0], P[1], P + 2, P + 5, s);
+  double row[8];
+  gas_row(s, P + 5, 0, row);
+  Vel<double> r;
+  make_vel(m, P + 9, r);
+  double rr[4];
+  rad_row(r, P[8], 0, rr);
+#pragma unroll
+  for (int q = 0; q < 8; q++) U[q] = m.gdet * row[q];
+#pragma unroll
+  for (int q = 0; q < 4; q++) U[8 + q] = m.gdet * rr[q];
+}
+
+__global__ void LB(256) k_p2u(Ctx C, const double* __restrict__ P, double* __restrict__ U) {
+  const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= C.Ntot) return;
+  const int pos = c % C.npos;
+  Metric m;
+  load_metric(C.geo_c, C.npos, pos, m);
+  double p[12], u[12];
+#pragma unroll
+  for (int q = 0; q < 12; q++) p[q] = P[q * C.Ntot + c];
+  prim_to_cons_cell(m, C.gam, p, u);
+#pragma unroll
+  for (int q = 0; q < 12; q++) U[q * C.Ntot + c] = u[q];
+}
+
+// ---------------------------------------------------------------------------
+// steps 4-7: reconstruction, face physics, wave speeds, HLL / LAXF
+// ---------------------------------------------------------------------------
+DEV double mc_slope(double dl, double dr) {
+  if (dl * dr <= 0.0) return 0.0;
+  const double dc = 0.5 * (dl + dr);
+  return ::copysign(fmin(::fabs(dc), 2.0 * fmin(::fabs(dl), ::fabs(dr))), dc);
+}
+
+struct FaceState {
+  double U[12], F[12];
+  double gm, gp, rm, rp;   // gas and radiation characteristic speeds
+};
+
+DEV void face_state(const Ctx& C, const Metric& m, int d, const double* P, double chi_tot,
+                    FaceState& fs) {
+  Gas<double> s;
+  make_gas(m, C.gam, P[0], P[1], P + 2, P + 5, s);
+  double row[8];
+  gas_row(s, P + 5, 0, row);
+#pragma unroll
+  for (int q = 0; q < 8; q++) fs.U[q] = m.gdet * row[q];
+  gas_row(s, P + 5, d, row);
+#pragma unroll
+  for (int q = 0; q < 8; q++) fs.F[q] = m.gdet * row[q];
+  Vel<double> r;
+  make_vel(m, P + 9, r);
+  double rr[4];
+  rad_row(r, P[8], 0, rr);
+#pragma unroll
+  for (int q = 0; q < 4; q++) fs.U[8 + q] = m.gdet * rr[q];
+  rad_row(r, P[8], d, rr);
+#pragma unroll
+  for (int q = 0; q < 4; q++) fs.F[8 + q] = m.gdet * rr[q];
+  // gas: fast magnetosonic speed c_ms^2 = v_A^2 + c_s^2 (1 - v_A^2)
+  const double w = s.rho + s.ug + s.pg;
+  const double cs2 = C.gam * s.pg / w;
+  const double va2 = s.bsq / (w + s.bsq);
+  char_speeds(m, s.v.ucon, va2 + cs2 * (1.0 - va2), d, fs.gm, fs.gp);
+  // radiation: 1/sqrt(3) in the radiation frame, limited to 4/(3 tau) in the gas frame
+  char_speeds(m, r.ucon, 1.0 / 3.0, d, fs.rm, fs.rp);
+  const double tau = chi_tot * P[0] * ::sqrt(m.lo(d, d)) * C.dx[d - 1];
+  if (tau > 0.0) {
+    const double cl = 4.0 / (3.0 * tau);
+    if (cl < 1.0) {
+      double lm, lp;
+      char_speeds(m, s.v.ucon, cl * cl, d, lm, lp);
+      fs.rp = fmin(fs.rp, lp);
+      fs.rm = fmax(fs.rm, lm);
+    }
+  }
+}
+
+struct FaceRange {
+  int lo[3], cnt[3];
+  long total;
+};
+
+template <int D>
+__global__ void LB(128) k_flux(Ctx C, FaceRange R, const double* __restrict__ P,
+                               const double* __restrict__ chi_abs,
+                               const double* __restrict__ chi_es, double* __restrict__ F,
+                               double* __restrict__ vchar) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= R.total) return;
+  const int i = R.lo[0] + t % R.cnt[0];
+  const long t2 = t / R.cnt[0];
+  const int j = R.lo[1] + t2 % R.cnt[1];
+  const int k = R.lo[2] + t2 / R.cnt[1];
+  const long c = cell_index(C, i, j, k);
+  const long st = C.st[D - 1];
+  double PL[12], PR[12];
+#pragma unroll
+  for (int q = 0; q < 12; q++) {
+    const double* p = P + q * C.Ntot;
+    const double a = p[c - 2 * st], b = p[c - st], e = p[c], f = p[c + st];
+    PL[q] = b + 0.5 * mc_slope(b - a, e - b);
+    PR[q] = e - 0.5 * mc_slope(e - b, f - e);
+  }
+  Metric m;
+  const double* tab = (D == 1) ? C.geo_f1 : ((D == 2) ? C.geo_f2 : C.geo_c);
+  load_metric(tab, C.npos, i + C.N[0] * j, m);
+  FaceState L, Rs;
+  face_state(C, m, D, PL, chi_abs[c - st] + chi_es[c - st], L);
+  face_state(C, m, D, PR, chi_abs[c] + chi_es[c], Rs);
+  // eq. hll: v_min = -min(0, v-_L, v-_R), v_max = max(0, v+_L, v+_R)
+  const double gmin = -fmin(0.0, fmin(L.gm, Rs.gm)), gmax = fmax(0.0, fmax(L.gp, Rs.gp));
+  const double rmin = -fmin(0.0, fmin(L.rm, Rs.rm)), rmax = fmax(0.0, fmax(L.rp, Rs.rp));
+#pragma unroll
+  for (int q = 0; q < 12; q++) {
+    const double vmin = q < 8 ? gmin : rmin, vmax = q < 8 ? gmax : rmax;
+    double f;
+    if (C.flux == GRRMHD_FLUX_HLL) {
+      const double den = vmin + vmax;
+      f = (den > 0.0) ? (vmin * Rs.F[q] + vmax * L.F[q] - vmin * vmax * (Rs.U[q] - L.U[q])) / den
+                      : 0.5 * (L.F[q] + Rs.F[q]);
+    } else {
+      f = 0.5 * (Rs.F[q] + L.F[q] - fmax(vmin, vmax) * (Rs.U[q] - L.U[q]));
+    }
+    if (q == 4 + D) f = 0.0;   // normal field component has no induction flux
+    F[q * C.Ntot + c] = f;
+  }
+  vchar[c] = fmax(fmax(gmin, gmax), fmax(rmin, rmax));
+}
+
+// ---------------------------------------------------------------------------
+// step 9 (flux-CT): corner EMF along a = average of the four adjacent face
+// induction fluxes, emf_a = F_c[B_b] = -F_b[B_c] for cyclic (a, b, c)
+// ---------------------------------------------------------------------------
+__global__ void LB(256) k_emf(Ctx C, int a, FaceRange R, const double* __restrict__ F,
+                              double* __restrict__ emf) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= R.total) return;
+  const int i = R.lo[0] + t % R.cnt[0];
+  const long t2 = t / R.cnt[0];
+  const int j = R.lo[1] + t2 % R.cnt[1];
+  const int k = R.lo[2] + t2 / R.cnt[1];
+  const long c = cell_index(C, i, j, k);
+  const int b = (a + 1) % 3, cd = (a + 2) % 3;
+  const double* Fb = F + (long)b * 12 * C.Ntot + (long)(5 + cd) * C.Ntot;   // F_b[B_c]
+  const double* Fc = F + (long)cd * 12 * C.Ntot + (long)(5 + b) * C.Ntot;   // F_c[B_b]
+  double e = 0.25 * ((Fc[c] + Fc[c - C.st[b]]) - (Fb[c] + Fb[c - C.st[cd]]));
+  if (C.metric == GRRMHD_KERR_SCHILD && (b == 1 || cd == 1)) {
+    // edges on the polar axis carry no EMF
+    const bool lo = j == C.ng[1] && (C.bc_lo[1] == GRRMHD_BC_REFLECT || C.bc_lo[1] == GRRMHD_BC_POLAR);
+    const bool hi = j == C.ng[1] + C.n[1] && (C.bc_hi[1] == GRRMHD_BC_REFLECT || C.bc_hi[1] == GRRMHD_BC_POLAR);
+    if (lo || hi) e = 0.0;
+  }
+  emf[(long)a * C.Ntot + c] = e;
+}
+
+// ---------------------------------------------------------------------------
+// step 10: explicit stage combination with flux divergence and geometry
+// source.  The source uses sqrt(-g) T^k_l Gamma^l_{nu k} =
+// (1/2) sqrt(-g) T^{k m} d_nu g_{k m}; both metrics are independent of t and
+// x3, so only nu = 1, 2 contribute.
+// ---------------------------------------------------------------------------
+DEV double contract_sym(const double* dg, const double u[4], const double v[4]) {
+  double s = 0.0;
+#pragma unroll
+  for (int a = 0; a < 4; a++)
+#pragma unroll
+    for (int b = 0; b < 4; b++) s += u[a] * v[b] * dg[sym(a, b)];
+  return s;
+}
+
+__global__ void LB(256) k_update(Ctx C, double ca, double cb, double cc, const double* dt_dev,
+                                 const double* __restrict__ P, const double* __restrict__ Un,
+                                 const double* __restrict__ Uprev, const double* __restrict__ F,
+                                 const double* __restrict__ emf, double* __restrict__ Uexp) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long nint = (long)C.n[0] * C.n[1] * C.n[2];
+  if (t >= nint) return;
+  const int i = C.ng[0] + t % C.n[0];
+  const long t2 = t / C.n[0];
+  const int j = C.ng[1] + t2 % C.n[1];
+  const int k = C.ng[2] + t2 / C.n[1];
+  const long c = cell_index(C, i, j, k);
+  const double dt = *dt_dev;
+  double S[12];
+#pragma unroll
+  for (int q = 0; q < 12; q++) S[q] = 0.0;
+  if (C.metric != GRRMHD_MINKOWSKI) {
+    const int pos = i + C.N[0] * j;
+    Metric m;
+    load_metric(C.geo_c, C.npos, pos, m);
+    double p[12];
+#pragma unroll
+    for (int q = 0; q < 12; q++) p[q] = P[q * C.Ntot + c];
+    Gas<double> s;
+    make_gas(m, C.gam, p[0], p[1], p + 2, p + 5, s);
+    Vel<double> r;
+    make_vel(m, p + 9, r);
+    const double enth = s.rho + s.ug + s.pg + s.bsq, ptot = s.pg + 0.5 * s.bsq;
+    for (int nu = 1; nu <= 2; nu++) {
+      double dg[10];
+      const int base = (nu == 1) ? GE_DG1 : GE_DG2;
+#pragma unroll
+      for (int q = 0; q < 10; q++) dg[q] = C.geo_c[(base + q) * C.npos + pos];
+      double trace = 0.0;   // g^{km} d_nu g_{km}
+#pragma unroll
+      for (int a = 0; a < 4; a++)
+#pragma unroll
+        for (int b = 0; b < 4; b++) trace += m.up(a, b) * dg[sym(a, b)];
+      const double sg = enth * contract_sym(dg, s.v.ucon, s.v.ucon) + ptot * trace -
+                        contract_sym(dg, s.bcon, s.bcon);
+      const double sr = (4.0 / 3.0) * p[8] * contract_sym(dg, r.ucon, r.ucon) + (1.0 / 3.0) * p[8] * trace;
+      S[1 + nu] = 0.5 * m.gdet * sg;
+      S[8 + nu] = 0.5 * m.gdet * sr;
+    }
+  }
+  double div[12];
+#pragma unroll
+  for (int q = 0; q < 12; q++) div[q] = 0.0;
+  for (int d = 0; d < 3; d++) {
+    if (C.n[d] == 1) continue;
+    const double idx = 1.0 / C.dx[d];
+    const double* Fd = F + (long)d * 12 * C.Ntot;
+    const long sd = C.st[d];
+#pragma unroll
+    for (int q = 0; q < 12; q++) {
+      if (q >= 5 && q <= 7) continue;
+      div[q] += (Fd[q * C.Ntot + c + sd] - Fd[q * C.Ntot + c]) * idx;
+    }
+    for (int b = 0; b < 3; b++) {
+      if (b == d) continue;
+      double fm, fp;
+      if (C.n[b] > 1) {
+        // face flux = mean of the two corner EMFs adjacent along b
+        const int aa = 3 - b - d;
+        const double sgn = ((aa + 1) % 3 == b) ? 1.0 : -1.0;
+        const double* E = emf + (long)aa * C.Ntot;
+        const long sb = C.st[b];
+        fm = 0.5 * sgn * (E[c] + E[c + sb]);
+        fp = 0.5 * sgn * (E[c + sd] + E[c + sd + sb]);
+      } else {
+        fm = Fd[(5 + b) * C.Ntot + c];
+        fp = Fd[(5 + b) * C.Ntot + c + sd];
+      }
+      div[5 + b] += (fp - fm) * idx;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 12; q++) {
+    double u = ca * Un[q * C.Ntot + c];
+    if (cb != 0.0) u += cb * Uprev[q * C.Ntot + c];
+    Uexp[q * C.Ntot + c] = u + cc * dt * (S[q] - div[q]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Courant time step: per-cell harmonic combination, block min, one atomic
+// per block on the ordered bit pattern of a positive double
+// ---------------------------------------------------------------------------
+__global__ void k_dt_init(unsigned long long* slot) { *slot = 0x7FF0000000000000ull; }
+
+__global__ void LB(256) k_dt_min(Ctx C, const double* __restrict__ vchar,
+                                 unsigned long long* slot) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long nint = (long)C.n[0] * C.n[1] * C.n[2];
+  double dtc = INFINITY;
+  if (t < nint) {
+    const int i = C.ng[0] + t % C.n[0];
+    const long t2 = t / C.n[0];
+    const int j = C.ng[1] + t2 % C.n[1];
+    const int k = C.ng[2] + t2 / C.n[1];
+    const long c = cell_index(C, i, j, k);
+    double inv = 0.0;
+    for (int d = 0; d < 3; d++) {
+      if (C.n[d] == 1) continue;
+      const double* v = vchar + (long)d * C.Ntot;
+      inv += fmax(v[c], v[c + C.st[d]]) / C.dx[d];
+    }
+    dtc = 1.0 / inv;
+  }
+  // wavefront reduction then LDS across the block's wavefronts
+  for (int off = 32; off > 0; off >>= 1) dtc = fmin(dtc, __shfl_xor(dtc, off, 64));
+  __shared__ double wmin[4];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) wmin[wid] = dtc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double b = wmin[0];
+    for (int w = 1; w < (int)(blockDim.x >> 6); w++) b = fmin(b, wmin[w]);
+    atomicMin(slot, (unsigned long long)__double_as_longlong(b));
+  }
+}
+
+__global__ void k_dt_final(const unsigned long long* slot, double courant, double* dt_out) {
+  *dt_out = courant * __longlong_as_double((long long)*slot);
+}
+
+// ---------------------------------------------------------------------------
+// steps 11-12: implicit solve per interior cell; and the stand-alone
+// con2prim of an explicit state
+// ---------------------------------------------------------------------------
+DEV Phys make_phys(const Ctx& C) {
+  Phys ph;
+  ph.gam = C.gam;
+  ph.arad = C.arad;
+  ph.gamma_max = C.gamma_max;
+  ph.ymax = C.ymax;
+  return ph;
+}
+DEV Opts make_opts(const Ctx& C) {
+  Opts o;
+  o.tol_pmhd = C.tol_pmhd;
+  o.tol_urad = C.tol_urad;
+  o.max_iter = C.max_iter;
+  o.roundoff = C.roundoff;
+  return o;
+}
+
+__global__ void LB(64) k_implicit(Ctx C, const double* __restrict__ Uexp,
+                                  const double* Pguess, double dt_scale,
+                                  const double* __restrict__ dt_dev,
+                                  const double* __restrict__ chi_abs,
+                                  const double* __restrict__ chi_es, double* P,
+                                  double* __restrict__ U, int* __restrict__ iters,
+                                  int* __restrict__ status, double* __restrict__ err) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long nint = (long)C.n[0] * C.n[1] * C.n[2];
+  if (t >= nint) return;
+  const int i = C.ng[0] + t % C.n[0];
+  const long t2 = t / C.n[0];
+  const int j = C.ng[1] + t2 % C.n[1];
+  const int k = C.ng[2] + t2 / C.n[1];
+  const long c = cell_index(C, i, j, k);
+  Metric m;
+  load_metric(C.geo_c, C.npos, i + C.N[0] * j, m);
+  double Ui[12], Pg[12];
+#pragma unroll
+  for (int q = 0; q < 12; q++) {
+    Ui[q] = Uexp[q * C.Ntot + c];
+    Pg[q] = Pguess[q * C.Ntot + c];
+  }
+  CellOut o;
+  implicit_cell(m, make_phys(C), make_opts(C), C.tol_accept, C.tol_fail, Ui, Pg,
+                dt_scale * (*dt_dev), chi_abs[c], chi_es[c], o);
+#pragma unroll
+  for (int q = 0; q < 12; q++) {
+    P[q * C.Ntot + c] = o.P[q];
+    U[q * C.Ntot + c] = o.U[q];
+  }
+  if (iters) iters[c] = o.iters;
+  if (status) status[c] = o.status;
+  if (err) err[c] = o.err;
+}
+
+__global__ void LB(64) k_implicit_batch(Ctx C, long n, const double* __restrict__ Ui_,
+                                        const double* __restrict__ Pg_,
+                                        const double* __restrict__ dtc,
+                                        const double* __restrict__ chi_abs,
+                                        const double* __restrict__ chi_es,
+                                        double* __restrict__ Po, double* __restrict__ Uo,
+                                        int* __restrict__ iters, int* __restrict__ status,
+                                        double* __restrict__ err) {
+  const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  Metric m;
+  flat_metric(m);
+  double Ui[12], Pg[12];
+#pragma unroll
+  for (int q = 0; q < 12; q++) {
+    Ui[q] = Ui_[q * n + c];
+    Pg[q] = Pg_[q * n + c];
+  }
+  CellOut o;
+  implicit_cell(m, make_phys(C), make_opts(C), C.tol_accept, C.tol_fail, Ui, Pg, dtc[c],
+                chi_abs[c], chi_es[c], o);
+#pragma unroll
+  for (int q = 0; q < 12; q++) {
+    Po[q * n + c] = o.P[q];
+    Uo[q * n + c] = o.U[q];
+  }
+  if (iters) iters[c] = o.iters;
+  if (status) status[c] = o.status;
+  if (err) err[c] = o.err;
+}
+
+__global__ void LB(128) k_con2prim(Ctx C, const double* __restrict__ U, const double* Pguess,
+                                   double* P, int* __restrict__ status) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long nint = (long)C.n[0] * C.n[1] * C.n[2];
+  if (t >= nint) return;
+  const int i = C.ng[0] + t % C.n[0];
+  const long t2 = t / C.n[0];
+  const int j = C.ng[1] + t2 % C.n[1];
+  const int k = C.ng[2] + t2 / C.n[1];
+  const long c = cell_index(C, i, j, k);
+  Metric m;
+  load_metric(C.geo_c, C.npos, i + C.N[0] * j, m);
+  const double igd = 1.0 / m.gdet;
+  double u[12], p[12];
+#pragma unroll
+  for (int q = 0; q < 12; q++) {
+    u[q] = U[q * C.Ntot + c] * igd;
+    p[q] = Pguess[q * C.Ntot + c];
+  }
+  double rho = p[0], ug = p[1], ut[3] = {p[2], p[3], p[4]};
+  int st = 0;
+  if (mhd_invert(m, C.gam, u[0], u[1], u + 2, u + 5, rho, ug, ut) == 0) {
+    p[0] = rho; p[1] = ug; p[2] = ut[0]; p[3] = ut[1]; p[4] = ut[2];
+  } else {
+    st |= GRRMHD_ST_C2P_FAIL;
+  }
+#pragma unroll
+  for (int q = 0; q < 3; q++) p[5 + q] = u[5 + q];
+  double Eb, utr[3];
+  rad_invert(m, C.gamma_max, C.ymax, 0, u + 8, Eb, utr);
+  p[8] = Eb; p[9] = utr[0]; p[10] = utr[1]; p[11] = utr[2];
+#pragma unroll
+  for (int q = 0; q < 12; q++) P[q * C.Ntot + c] = p[q];
+  if (status) status[c] = st;
+}
+
+// ---------------------------------------------------------------------------
+// step 13 and floors.  Pass 1 averages failed cells' face neighbours into
+// scratch; pass 2 applies averages and floors and recomputes U where P changed.
+// ---------------------------------------------------------------------------
+__global__ void LB(256) k_fixup_avg(Ctx C, const double* __restrict__ P,
+                                    const int* __restrict__ status, double* __restrict__ scr) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long nint = (long)C.n[0] * C.n[1] * C.n[2];
+  if (t >= nint) return;
+  int idx[3];
+  idx[0] = C.ng[0] + t % C.n[0];
+  const long t2 = t / C.n[0];
+  idx[1] = C.ng[1] + t2 % C.n[1];
+  idx[2] = C.ng[2] + t2 / C.n[1];
+  const long c = cell_index(C, idx[0], idx[1], idx[2]);
+  if (!(status[c] & GRRMHD_ST_FAIL)) return;
+  for (int pass = 0; pass < 2; pass++) {
+    double acc[12];
+#pragma unroll
+    for (int q = 0; q < 12; q++) acc[q] = 0.0;
+    int cnt = 0;
+    for (int d = 0; d < 3; d++) {
+      if (C.n[d] == 1) continue;
+      for (int s = -1; s <= 1; s += 2) {
+        const int nid = idx[d] + s;
+        if (nid < C.ng[d] || nid >= C.ng[d] + C.n[d]) continue;
+        const long nb = c + s * C.st[d];
+        if (pass == 0 && (status[nb] & GRRMHD_ST_FAIL)) continue;
+#pragma unroll
+        for (int q = 0; q < 12; q++) acc[q] += P[q * C.Ntot + nb];
+        cnt++;
+      }
+    }
+    if (cnt > 0) {
+      const double w = 1.0 / cnt;
+#pragma unroll
+      for (int q = 0; q < 12; q++) scr[q * C.Ntot + c] = acc[q] * w;
+      scr[12 * C.Ntot + c] = pass + 1.0;
+      return;
+    }
+  }
+  scr[12 * C.Ntot + c] = 0.0;
+}
+
+__global__ void LB(256) k_fixup_apply(Ctx C, double* __restrict__ P, double* __restrict__ U,
+                                      int* __restrict__ status, const double* __restrict__ scr,
+                                      int* __restrict__ st_acc, const int* __restrict__ it_stage,
+                                      int* __restrict__ it_acc, int accumulate) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long nint = (long)C.n[0] * C.n[1] * C.n[2];
+  if (t >= nint) return;
+  const int i = C.ng[0] + t % C.n[0];
+  const long t2 = t / C.n[0];
+  const int j = C.ng[1] + t2 % C.n[1];
+  const int k = C.ng[2] + t2 / C.n[1];
+  const long c = cell_index(C, i, j, k);
+  int st = status[c];
+  double p[12];
+  bool changed = false;
+  if ((st & GRRMHD_ST_FAIL) && scr[12 * C.Ntot + c] > 0.0) {
+#pragma unroll
+    for (int q = 0; q < 12; q++) p[q] = scr[q * C.Ntot + c];
+    if (scr[12 * C.Ntot + c] > 1.5) st |= GRRMHD_ST_NO_GOOD_NB;
+    changed = true;
+  } else {
+#pragma unroll
+    for (int q = 0; q < 12; q++) p[q] = P[q * C.Ntot + c];
+  }
+  Metric m;
+  load_metric(C.geo_c, C.npos, i + C.N[0] * j, m);
+  Gas<double> s;
+  make_gas(m, C.gam, p[0], p[1], p + 2, p + 5, s);
+  const double rmin = fmax(C.rho_floor, s.bsq / C.bsq_rho_max);
+  const double umin = fmax(C.u_floor, s.bsq / C.bsq_u_max);
+  bool fl = false;
+  if (p[0] < rmin) { p[0] = rmin; fl = true; }
+  if (p[1] < umin) { p[1] = umin; fl = true; }
+  if (p[1] > C.u_rho_max * p[0]) { p[1] = C.u_rho_max * p[0]; fl = true; }
+  if (!(p[8] >= C.erad_floor)) { p[8] = C.erad_floor; fl = true; }
+  if (fl) st |= GRRMHD_ST_FLOOR;
+  if (fl || changed) {
+    double u[12];
+    prim_to_cons_cell(m, C.gam, p, u);
+#pragma unroll
+    for (int q = 0; q < 12; q++) {
+      P[q * C.Ntot + c] = p[q];
+      U[q * C.Ntot + c] = u[q];
+    }
+  }
+  status[c] = st;
+  if (st_acc) st_acc[c] = accumulate ? (st_acc[c] | st) : st;
+  if (it_acc && it_stage) it_acc[c] = accumulate ? it_acc[c] + it_stage[c] : it_stage[c];
+}

@@ -1,0 +1,227 @@
+"""Thin ctypes binding of ``libgrrmhd.so`` (include/grrmhd.h).
+
+Argument marshalling only: every step runs in the library's HIP kernels.
+PyTorch supplies device memory (tensors) and the current HIP stream.  The
+binding raises if the library is missing; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(HERE, "libgrrmhd.so")
+
+ST_PMHD, ST_URAD, ST_TYPE2_NEG, ST_BASIC, ST_C2P_FAIL, ST_FLOOR, ST_NOT_ACCEPT, ST_FAIL, \
+    ST_NO_GOOD_NB, ST_EXTREME = (1 << i for i in range(10))
+
+_BC = {"outflow": 0, "periodic": 1, "reflect": 2, "polar": 3}
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("n", C.c_int * 3), ("ng", C.c_int), ("metric", C.c_int),
+        ("a", C.c_double), ("R0", C.c_double),
+        ("xlo", C.c_double * 3), ("xhi", C.c_double * 3),
+        ("bc_lo", C.c_int * 3), ("bc_hi", C.c_int * 3),
+        ("gam", C.c_double), ("arad", C.c_double), ("gamma_max", C.c_double),
+        ("courant", C.c_double), ("flux", C.c_int),
+        ("tol_pmhd", C.c_double), ("tol_urad", C.c_double),
+        ("tol_accept", C.c_double), ("tol_fail", C.c_double),
+        ("max_iter", C.c_int), ("roundoff", C.c_int),
+        ("rho_floor", C.c_double), ("u_floor", C.c_double), ("bsq_rho_max", C.c_double),
+        ("bsq_u_max", C.c_double), ("u_rho_max", C.c_double), ("erad_floor", C.c_double),
+    ]
+
+
+def params(d: dict) -> Params:
+    p = Params()
+    p.n[:] = list(d["n"])
+    p.ng = d["ng"]
+    p.metric = 1 if d["metric"] in ("ks", "kerr-schild") else 0
+    p.a, p.R0 = d["a"], d["R0"]
+    p.xlo[:] = list(d["xlo"])
+    p.xhi[:] = list(d["xhi"])
+    p.bc_lo[:] = [_BC[b] for b in d["bc_lo"]]
+    p.bc_hi[:] = [_BC[b] for b in d["bc_hi"]]
+    for k in ("gam", "arad", "gamma_max", "courant", "tol_pmhd", "tol_urad", "tol_accept",
+              "tol_fail", "rho_floor", "u_floor", "bsq_rho_max", "bsq_u_max", "u_rho_max",
+              "erad_floor"):
+        setattr(p, k, float(d[k]))
+    p.flux = 1 if d["flux"] == "hll" else 0
+    p.max_iter = int(d["max_iter"])
+    p.roundoff = int(d["roundoff"])
+    return p
+
+
+_lib = None
+_VP = C.c_void_p
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIBPATH):
+            raise RuntimeError(f"{LIBPATH} is missing: build it with __graft_entry__.build()")
+        L = C.CDLL(LIBPATH)
+        PP = C.POINTER(Params)
+        sigs = {
+            "grrmhd_default_params": (None, [PP]),
+            "grrmhd_last_error": (C.c_char_p, []),
+            "grrmhd_init_grid": (C.c_int, [PP, C.c_int, _VP, C.POINTER(_VP)]),
+            "grrmhd_free_grid": (C.c_int, [_VP]),
+            "grrmhd_set_stream": (C.c_int, [_VP, _VP]),
+            "grrmhd_ncell_alloc": (C.c_long, [_VP]),
+            "grrmhd_workspace_bytes": (C.c_size_t, [_VP]),
+            "grrmhd_prim_to_cons": (C.c_int, [_VP, _VP, _VP]),
+            "grrmhd_apply_bc": (C.c_int, [_VP, _VP]),
+            "grrmhd_fluxes": (C.c_int, [_VP] + [_VP] * 6),
+            "grrmhd_timestep": (C.c_int, [_VP, _VP, _VP]),
+            "grrmhd_explicit_update": (C.c_int, [_VP, C.c_double, C.c_double, C.c_double] + [_VP] * 7),
+            "grrmhd_con2prim": (C.c_int, [_VP] + [_VP] * 4),
+            "grrmhd_implicit_grid": (C.c_int, [_VP, _VP, _VP, C.c_double] + [_VP] * 8),
+            "grrmhd_fixup": (C.c_int, [_VP] * 5),
+            "grrmhd_step": (C.c_int, [_VP, _VP, _VP, _VP, _VP, _VP, C.c_int, _VP, _VP, _VP,
+                                      C.c_size_t]),
+            "grrmhd_implicit_source": (C.c_int, [PP, C.c_long] + [_VP] * 11),
+        }
+        for name, (res, args) in sigs.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise RuntimeError(f"grrmhd error {rc}: {lib().grrmhd_last_error().decode()}")
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    assert t.is_cuda and t.is_contiguous(), "device tensors, contiguous"
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Grid:
+    """A grid with its device geometry; arrays are [12, N] float64 tensors."""
+
+    def __init__(self, pd: dict, device: int = 0):
+        self.pd = dict(pd)
+        self._p = params(pd)
+        h = C.c_void_p()
+        _check(lib().grrmhd_init_grid(C.byref(self._p), device, _stream(), C.byref(h)))
+        self.h = h
+        self.N = lib().grrmhd_ncell_alloc(h)
+        self.ws_bytes = lib().grrmhd_workspace_bytes(h)
+        self._ws = None
+
+    def close(self):
+        if self.h:
+            _check(lib().grrmhd_free_grid(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _sync_stream(self):
+        _check(lib().grrmhd_set_stream(self.h, _stream()))
+
+    def workspace(self):
+        if self._ws is None:
+            self._ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device="cuda")
+        off = (-self._ws.data_ptr()) % 256
+        return self._ws[off:off + self.ws_bytes]
+
+    def prim_to_cons(self, P, U=None):
+        self._sync_stream()
+        U = torch.empty_like(P) if U is None else U
+        _check(lib().grrmhd_prim_to_cons(self.h, _ptr(P), _ptr(U)))
+        return U
+
+    def apply_bc(self, P):
+        self._sync_stream()
+        _check(lib().grrmhd_apply_bc(self.h, _ptr(P)))
+        return P
+
+    def fluxes(self, P, chi_abs, chi_es):
+        self._sync_stream()
+        F = torch.empty((3, 12, self.N), dtype=torch.float64, device=P.device)
+        emf = torch.empty((3, self.N), dtype=torch.float64, device=P.device)
+        vch = torch.empty((3, self.N), dtype=torch.float64, device=P.device)
+        _check(lib().grrmhd_fluxes(self.h, _ptr(P), _ptr(chi_abs), _ptr(chi_es), _ptr(F),
+                                   _ptr(emf), _ptr(vch)))
+        return F, emf, vch
+
+    def timestep(self, vchar, dt=None):
+        self._sync_stream()
+        dt = torch.zeros(1, dtype=torch.float64, device=vchar.device) if dt is None else dt
+        _check(lib().grrmhd_timestep(self.h, _ptr(vchar), _ptr(dt)))
+        return dt
+
+    def explicit_update(self, a, b, c, dt, P, Un, Uprev, F, emf, Uexp=None):
+        self._sync_stream()
+        Uexp = Un.clone() if Uexp is None else Uexp
+        _check(lib().grrmhd_explicit_update(self.h, a, b, c, _ptr(dt), _ptr(P), _ptr(Un),
+                                            _ptr(Uprev), _ptr(F), _ptr(emf), _ptr(Uexp)))
+        return Uexp
+
+    def con2prim(self, U, Pguess):
+        self._sync_stream()
+        P = Pguess.clone()
+        st = torch.zeros(self.N, dtype=torch.int32, device=U.device)
+        _check(lib().grrmhd_con2prim(self.h, _ptr(U), _ptr(Pguess), _ptr(P), _ptr(st)))
+        return P, st
+
+    def implicit(self, Uexp, Pguess, dt_scale, dt, chi_abs, chi_es):
+        self._sync_stream()
+        P = Pguess.clone()
+        U = Uexp.clone()
+        it = torch.zeros(self.N, dtype=torch.int32, device=U.device)
+        st = torch.zeros(self.N, dtype=torch.int32, device=U.device)
+        err = torch.zeros(self.N, dtype=torch.float64, device=U.device)
+        _check(lib().grrmhd_implicit_grid(self.h, _ptr(Uexp), _ptr(Pguess), dt_scale, _ptr(dt),
+                                          _ptr(chi_abs), _ptr(chi_es), _ptr(P), _ptr(U), _ptr(it),
+                                          _ptr(st), _ptr(err)))
+        return P, U, it, st, err
+
+    def fixup(self, P, U, status):
+        self._sync_stream()
+        scratch = torch.zeros((13, self.N), dtype=torch.float64, device=P.device)
+        _check(lib().grrmhd_fixup(self.h, _ptr(P), _ptr(U), _ptr(status), _ptr(scratch)))
+        return P, U, status
+
+    def step(self, P, U, chi_abs, chi_es, dt, dt_fixed=False, status=None, iters=None):
+        """One RK3-IMEX step in place on P, U; dt is a 1-element device tensor."""
+        self._sync_stream()
+        ws = self.workspace()
+        _check(lib().grrmhd_step(self.h, _ptr(P), _ptr(U), _ptr(chi_abs), _ptr(chi_es), _ptr(dt),
+                                 1 if dt_fixed else 0, _ptr(status), _ptr(iters), _ptr(ws),
+                                 self.ws_bytes))
+        return P, U
+
+
+def implicit_source(pd: dict, U_expl, P_guess, dt_cell, chi_abs, chi_es):
+    """Batched implicit 4-force solve of independent flat-space cells."""
+    n = U_expl.shape[1]
+    P = P_guess.clone()
+    U = U_expl.clone()
+    it = torch.zeros(n, dtype=torch.int32, device=U.device)
+    st = torch.zeros(n, dtype=torch.int32, device=U.device)
+    err = torch.zeros(n, dtype=torch.float64, device=U.device)
+    p = params(pd)
+    _check(lib().grrmhd_implicit_source(C.byref(p), n, _ptr(U_expl), _ptr(P_guess), _ptr(dt_cell),
+                                        _ptr(chi_abs), _ptr(chi_es), _ptr(P), _ptr(U), _ptr(it),
+                                        _ptr(st), _ptr(err), _stream()))
+    return P, U, it, st, err
