@@ -88,7 +88,9 @@ typedef struct {
   double tol_fail;      /* above this: no solution (1e-7)                     */
   int max_iter;         /* Newton steps per method (20)                       */
   int roundoff;         /* 1: after meeting the tolerance keep stepping (at
-                           most 3 steps) until the step is at round-off      */
+                           most 3 steps) until the step is at round-off, and
+                           try the next method unless the best error is
+                           within 10 tol_pmhd (instead of tol_accept)        */
   double rho_floor, u_floor, bsq_rho_max, bsq_u_max, u_rho_max, erad_floor;
 } grrmhd_params;
 
@@ -139,7 +141,8 @@ int grrmhd_timestep(grrmhd_grid *g, const double *vchar, double *dt_dev);
 
 /* Sub-step 10: U_exp = a U^n + b U_prev + c dt (-div F + S_M(P)) at interior
  * cells, with flux-CT face fluxes for B rebuilt from the corner EMFs and the
- * geometric source S_M = sqrt(-g) T^k_l Gamma^l_{nu k} (Sec. 4 list of S_M).
+ * geometric source S_M = sqrt(-g) T^k_l Gamma^l_{nu k} (Sec. 4 list of S_M),
+ * evaluated as (1/2) sqrt(-g) T^{k m} d_nu g_{k m}.
  * dt_dev is a device scalar.  Uprev is not read when b == 0. */
 int grrmhd_explicit_update(grrmhd_grid *g, double a, double b, double c, const double *dt_dev,
                            const double *P, const double *Un, const double *Uprev,
@@ -166,7 +169,7 @@ int grrmhd_implicit_grid(grrmhd_grid *g, const double *Uexp, const double *Pgues
  * GRRMHD_ST_FAIL take the average primitives of their face neighbours with
  * a good solution (of all face neighbours if none is good); then floors on
  * rho0, u_g (b^2/rho0, b^2/u_g, u_g/rho0 limits) and Ebar; U is recomputed
- * where P changed.  `scratch` is device memory of at least 12 N doubles. */
+ * where P changed.  `scratch` is device memory of at least 13 N doubles. */
 int grrmhd_fixup(grrmhd_grid *g, double *P, double *U, int *status, double *scratch);
 
 /* One full RK3-IMEX time step (Sec. 4.1: third-order Shu-Osher stages with
@@ -182,13 +185,18 @@ int grrmhd_step(grrmhd_grid *g, double *P, double *U, const double *chi_abs,
                 void *workspace, size_t ws_bytes);
 
 /* Implicit 4-force solve for n independent cells in flat space (Minkowski
- * metric, no grid).  Arrays [12][n] (U_expl, P_guess, P_out, U_out) and [n]
+ * metric, no grid), eq. source3/source4 with the PMHD-then-URAD cascade of
+ * Sec. 4.10.  Arrays [12][n] (U_expl, P_guess, P_out, U_out) and [n]
  * (dt_cell, chi_abs, chi_es, iters, status, err; the last three nullable),
- * device memory.  Same algorithm as grrmhd_implicit_grid. */
+ * device memory; n < 2^31.  workspace: device buffer of at least
+ * grrmhd_implicit_source_workspace_bytes(n) bytes (work list of cells that
+ * need the full cascade).  Same algorithm as grrmhd_implicit_grid. */
+size_t grrmhd_implicit_source_workspace_bytes(long n);
 int grrmhd_implicit_source(const grrmhd_params *p, long n, const double *U_expl,
                            const double *P_guess, const double *dt_cell, const double *chi_abs,
                            const double *chi_es, double *P_out, double *U_out, int *iters,
-                           int *status, double *err, void *hip_stream);
+                           int *status, double *err, void *workspace, size_t ws_bytes,
+                           void *hip_stream);
 
 #ifdef __cplusplus
 }

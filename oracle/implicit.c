@@ -404,8 +404,9 @@ void orc_implicit_cell(const orc_params *p, const orc_geom *g, const double *Ui,
       best_method = method;
     }
     /* acceptable: no further method (Sec. 4.10); when iterating to round-off
-     * the next method is tried until one meets the PMHD tolerance */
-    if (best.eT < (p->roundoff ? p->tol_pmhd : p->tol_accept)) break;
+     * the next method is tried unless one came within 10x the PMHD
+     * tolerance (a method stalled at its own precision floor is kept) */
+    if (best.eT < (p->roundoff ? 10.0 * p->tol_pmhd : p->tol_accept)) break;
   }
 
   memcpy(Pout, Pguess, sizeof(double) * 12);

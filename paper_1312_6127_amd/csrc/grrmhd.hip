@@ -5,6 +5,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <string>
 
 #include "kernels.h"
@@ -16,6 +17,8 @@ struct grrmhd_grid {
   hipStream_t stream;
   double* geo;          // one allocation: centre table, x1-face table, x2-face table
   unsigned long long* dtslot;
+  int* counter;         // work-list length of the implicit cascade
+  int* list;            // work list: interior indices needing the full cascade
 };
 
 static thread_local std::string g_err;
@@ -154,12 +157,15 @@ extern "C" int grrmhd_init_grid(const grrmhd_params* p, int device, void* hip_st
   fill_ctx(p, g->C);
   const size_t tab = (size_t)g->C.npos;
   const size_t nd = tab * (GE_NCENTER + 2 * GE_NFACE);
-  hipError_t e = hipMalloc(&g->geo, nd * sizeof(double) + 64);
+  const size_t nint = (size_t)g->C.n[0] * g->C.n[1] * g->C.n[2];
+  hipError_t e = hipMalloc(&g->geo, nd * sizeof(double) + 256 + nint * sizeof(int));
   if (e != hipSuccess) {
     delete g;
     return fail(GRRMHD_ENOMEM, std::string("geometry allocation: ") + hipGetErrorString(e));
   }
   g->dtslot = (unsigned long long*)(g->geo + nd);
+  g->counter = (int*)(g->geo + nd + 16);
+  g->list = (int*)(g->geo + nd + 32);
   g->C.geo_c = g->geo;
   g->C.geo_f1 = g->geo + tab * GE_NCENTER;
   g->C.geo_f2 = g->geo + tab * (GE_NCENTER + GE_NFACE);
@@ -309,11 +315,21 @@ static int launch_update(grrmhd_grid* g, double a, double b, double c, const dou
   return 0;
 }
 
+// fallback grid: enough waves to spread a long list, grid-stride beyond
+static unsigned list_blocks(long n) { return (unsigned)std::min<long>(nblocks(n, 64), 8192); }
+
 static int launch_implicit(grrmhd_grid* g, const double* Ue, const double* Pg, double scale,
                            const double* dt_dev, const double* ca, const double* ce, double* P,
                            double* U, int* it, int* st, double* err) {
-  hipLaunchKernelGGL(k_implicit, dim3(nblocks(n_interior(g->C), 64)), dim3(64), 0, g->stream,
-                     g->C, Ue, Pg, scale, dt_dev, ca, ce, P, U, it, st, err);
+  const long n = n_interior(g->C);
+  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, g->stream, g->counter);
+  LAUNCHCHK();
+  hipLaunchKernelGGL(k_implicit, dim3(nblocks(n, 64)), dim3(64), 0, g->stream, g->C, Ue, Pg,
+                     scale, dt_dev, ca, ce, P, U, it, st, err, g->counter, g->list);
+  LAUNCHCHK();
+  hipLaunchKernelGGL(k_implicit_list, dim3(list_blocks(n)), dim3(64), 0, g->stream, g->C, Ue, Pg,
+                     scale, dt_dev, ca, ce, P, U, it, st, err, (const int*)g->counter,
+                     (const int*)g->list);
   LAUNCHCHK();
   return 0;
 }
@@ -448,22 +464,37 @@ extern "C" int grrmhd_step(grrmhd_grid* g, double* P, double* U, const double* c
   return 0;
 }
 
+extern "C" size_t grrmhd_implicit_source_workspace_bytes(long n) {
+  return n > 0 ? 256 + sizeof(int) * (size_t)n : 0;
+}
+
 extern "C" int grrmhd_implicit_source(const grrmhd_params* p, long n, const double* U_expl,
                                       const double* P_guess, const double* dt_cell,
                                       const double* chi_abs, const double* chi_es, double* P_out,
                                       double* U_out, int* iters, int* status, double* err,
-                                      void* hip_stream) {
+                                      void* workspace, size_t ws_bytes, void* hip_stream) {
   int rc = validate(p, false);
   if (rc) return rc;
-  if (n < 0) return fail(GRRMHD_EINVAL, "n < 0");
+  if (n < 0 || n > (1L << 31) - 1) return fail(GRRMHD_EINVAL, "n out of range");
   if (n == 0) return 0;
-  if (!U_expl || !P_guess || !dt_cell || !chi_abs || !chi_es || !P_out || !U_out)
+  if (!U_expl || !P_guess || !dt_cell || !chi_abs || !chi_es || !P_out || !U_out || !workspace)
     return fail(GRRMHD_EINVAL, "NULL array");
+  if (ws_bytes < grrmhd_implicit_source_workspace_bytes(n))
+    return fail(GRRMHD_EINVAL, "workspace too small");
   if (p->metric != GRRMHD_MINKOWSKI) return fail(GRRMHD_EINVAL, "batched cells use the Minkowski metric");
   Ctx C;
   fill_ctx(p, C);
-  hipLaunchKernelGGL(k_implicit_batch, dim3(nblocks(n, 64)), dim3(64), 0, (hipStream_t)hip_stream,
-                     C, n, U_expl, P_guess, dt_cell, chi_abs, chi_es, P_out, U_out, iters, status, err);
+  hipStream_t s = (hipStream_t)hip_stream;
+  int* counter = (int*)workspace;
+  int* list = (int*)((char*)workspace + 256);
+  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, counter);
+  LAUNCHCHK();
+  hipLaunchKernelGGL(k_implicit_batch, dim3(nblocks(n, 64)), dim3(64), 0, s, C, n, U_expl, P_guess,
+                     dt_cell, chi_abs, chi_es, P_out, U_out, iters, status, err, counter, list);
+  LAUNCHCHK();
+  hipLaunchKernelGGL(k_implicit_batch_list, dim3(list_blocks(n)), dim3(64), 0, s, C, n, U_expl,
+                     P_guess, dt_cell, chi_abs, chi_es, P_out, U_out, iters, status, err,
+                     (const int*)counter, (const int*)list);
   LAUNCHCHK();
   return 0;
 }

@@ -1,16 +1,26 @@
 // Implicit radiation 4-force solve for one cell on the device (Sec. 4.7-4.11).
 //
 // Unknowns are iterated with an undamped Newton method ("normal" Newton of
-// Sec. 4.10).  PMHD iterates the gas primitives (u_g, u~^i) and gets its 4x4
-// Jacobian exactly from a Dual<4> evaluation of the residual.  URAD iterates
+// Sec. 4.10).  PMHD iterates the gas primitives (u_g, u~^i); its 4x4
+// Jacobian is exact, built from dual-number evaluations of the residual in
+// passes of NJ directions (fewer live registers per pass).  URAD iterates
 // R^t_nu, inverts T^t_nu = T(i) - Delta R to gas primitives inside every
-// residual, and uses a one-sided finite-difference Jacobian (Sec. 4.9).
+// residual and uses a one-sided finite-difference Jacobian (Sec. 4.9).
 // Pre-step checks, post-step checks, stopping rules, guesses, method order
 // and acceptance follow Sec. 4.10-4.11.
+//
+// The work is split for the GPU: a lean kernel runs the common case (PMHD
+// first, accepted) and appends every other cell to a work list; a second
+// kernel runs the full cascade on the list.  Both run the same first PMHD
+// attempt from the same guess, so results equal those of one cascade.
 #pragma once
 #include <float.h>
 
 #include "invert.h"
+
+#ifndef GRRMHD_NJ
+#define GRRMHD_NJ 4   // Jacobian directions per dual-number pass (4: one pass)
+#endif
 
 enum { M_PMHD = 0, M_URAD = 1 };
 
@@ -24,10 +34,18 @@ struct Cell {
 struct Eval {
   double x[4];
   double P[12];
-  double Tg[4], Rr[4], G[4], Eg[4], Er[4];
-  double J[4][4];         // d(iterated residual)/dx (PMHD only)
+  double Eg[4], Er[4];
   double eT, eIg, eIr;
   int radflags, ok;
+};
+
+struct Phys {
+  double gam, arad, gamma_max, ymax;
+};
+
+struct Opts {
+  double tol_pmhd, tol_urad, tol_accept, tol_fail;
+  int max_iter, roundoff;
 };
 
 DEV double snorm3(const Metric& m, const double V[4]) {
@@ -43,17 +61,18 @@ DEV double snorm3(const Metric& m, const double V[4]) {
 // dt|G|, radiation residual over radiation-scale terms and dt|G|; spatial
 // parts merged in the normal observer's orthonormal basis plus the energy
 // scale; e_T = 1/4 sum over equations of the larger of the two.
-DEV void norm_errors(const Cell& c, Eval& e) {
+DEV void norm_errors(const Cell& c, const double Tg[4], const double Rr[4], const double G[4],
+                     Eval& e) {
   double Gdt[4];
 #pragma unroll
-  for (int k = 0; k < 4; k++) Gdt[k] = c.dt * e.G[k];
+  for (int k = 0; k < 4; k++) Gdt[k] = c.dt * G[k];
   const double g0 = ::fabs(Gdt[0]), gs = snorm3(c.m, Gdt);
-  double ntg = ::fabs(e.Tg[0]) + ::fabs(c.Tgi[0]) + g0;
-  double ntr = ::fabs(e.Rr[0]) + ::fabs(c.Ri[0]) + g0;
+  double ntg = ::fabs(Tg[0]) + ::fabs(c.Tgi[0]) + g0;
+  double ntr = ::fabs(Rr[0]) + ::fabs(c.Ri[0]) + g0;
   if (!(ntg > 0.0)) ntg = 1e-300;
   if (!(ntr > 0.0)) ntr = 1e-300;
-  const double nsg = snorm3(c.m, e.Tg) + snorm3(c.m, c.Tgi) + gs + ntg;
-  const double nsr = snorm3(c.m, e.Rr) + snorm3(c.m, c.Ri) + gs + ntr;
+  const double nsg = snorm3(c.m, Tg) + snorm3(c.m, c.Tgi) + gs + ntg;
+  const double nsr = snorm3(c.m, Rr) + snorm3(c.m, c.Ri) + gs + ntr;
   double eg[4], er[4];
   eg[0] = ::fabs(e.Eg[0]) / ntg;
   er[0] = ::fabs(e.Er[0]) / ntr;
@@ -80,63 +99,95 @@ DEV void norm_errors(const Cell& c, Eval& e) {
   }
 }
 
-struct Phys {
-  double gam, arad, gamma_max, ymax;
-};
-
-// PMHD residual with exact derivatives (Sec. 4.8, PMHD steps in order):
-// rho0 = (rho u^t)/u^t; T^t_nu from the gas; Delta R = -Delta T; TYPE2
-// radiation inversion; R recomputed; G; residuals.
-DEV void eval_pmhd(const Cell& c, const Phys& ph, const double x[4], Eval& e) {
-  typedef Dual<4> D4;
-  D4 ug = D4::var(x[0], 0);
-  D4 ut[3] = {D4::var(x[1], 1), D4::var(x[2], 2), D4::var(x[3], 3)};
-  D4 B[3] = {D4(c.B[0]), D4(c.B[1]), D4(c.B[2])};
-  Gas<D4> s;
-  Vel<D4> v;
-  make_vel(c.m, ut, v);
-  const D4 rho = c.rhout / v.ucon[0];
-  make_gas(c.m, ph.gam, rho, ug, ut, B, s);
-  D4 row[8];
+// PMHD residual (Sec. 4.8, PMHD steps in order): rho0 = (rho u^t)/u^t;
+// T^t_nu from the gas; Delta R = -Delta T; TYPE2 radiation inversion; R
+// recomputed; G; residuals.  One pass seeds Jacobian columns k0..k0+N-1.
+template <int N>
+DEV void pmhd_pass(const Cell& c, const Phys& ph, const double x[4], int k0, Eval& e,
+                   double J[4][4]) {
+  typedef Dual<N> D;
+  D ug(x[0]), ut[3] = {D(x[1]), D(x[2]), D(x[3])};
+#pragma unroll
+  for (int j = 0; j < N; j++) {
+    const int k = k0 + j;
+    if (k == 0) ug.d[j] = 1.0;
+    if (k == 1) ut[0].d[j] = 1.0;
+    if (k == 2) ut[1].d[j] = 1.0;
+    if (k == 3) ut[2].d[j] = 1.0;
+  }
+  D B[3] = {D(c.B[0]), D(c.B[1]), D(c.B[2])};
+  Gas<D> s;
+  {
+    Vel<D> v;
+    make_vel(c.m, ut, v);
+    const D rho = c.rhout / v.ucon[0];
+    make_gas(c.m, ph.gam, rho, ug, ut, B, s);
+  }
+  D row[8];
   gas_row(s, B, 0, row);
-  D4 R[4];
+  D R[4];
 #pragma unroll
   for (int k = 0; k < 4; k++) R[k] = c.Ri[k] - (row[1 + k] - c.Tgi[k]);
-  D4 Eb, utr[3];
+  D Eb, utr[3];
   e.radflags = rad_invert(c.m, ph.gamma_max, ph.ymax, 1, R, Eb, utr);
-  Vel<D4> r;
+  Vel<D> r;
   make_vel(c.m, utr, r);
-  D4 Rr[4];
-  rad_row(r, Eb, 0, Rr);
-  const D4 Tg = s.pg / rho;
-  const D4 T2 = Tg * Tg;
-  const D4 kabs = c.chi_abs * rho, kes = c.chi_es * rho;
-  const D4 lam = kabs * ph.arad * (T2 * T2);
-  D4 G[4];
+  const D Tgas = s.pg / s.rho;
+  const D T2 = Tgas * Tgas;
+  const D kabs = c.chi_abs * s.rho, kes = c.chi_es * s.rho;
+  const D lam = kabs * ph.arad * (T2 * T2);
+  D G[4];
   four_force(s.v, r, Eb, kabs, kes, lam, G);
+  double Tg[4], Rr[4], Gv[4];
+  D Rrow[4];
+  rad_row(r, Eb, 0, Rrow);
 #pragma unroll
   for (int k = 0; k < 4; k++) {
-    const D4 Egk = (row[1 + k] - c.Tgi[k]) - c.dt * G[k];
-    e.x[k] = x[k];
-    e.Tg[k] = row[1 + k].v;
-    e.Rr[k] = Rr[k].v;
-    e.G[k] = G[k].v;
+    const D Egk = (row[1 + k] - c.Tgi[k]) - c.dt * G[k];
+    Tg[k] = row[1 + k].v;
+    Rr[k] = Rrow[k].v;
+    Gv[k] = G[k].v;
     e.Eg[k] = Egk.v;
-    e.Er[k] = (Rr[k].v - c.Ri[k]) + c.dt * G[k].v;
+    e.Er[k] = (Rr[k] - c.Ri[k]) + c.dt * Gv[k];
 #pragma unroll
-    for (int j = 0; j < 4; j++) e.J[k][j] = Egk.d[j];
+    for (int j = 0; j < N; j++) J[k][k0 + j] = Egk.d[j];
   }
-  e.P[0] = rho.v;
-  e.P[1] = x[0];
+  if (k0 == 0) {
 #pragma unroll
-  for (int i = 0; i < 3; i++) {
-    e.P[2 + i] = x[1 + i];
-    e.P[5 + i] = c.B[i];
-    e.P[9 + i] = utr[i].v;
+    for (int k = 0; k < 4; k++) e.x[k] = x[k];
+    e.P[0] = s.rho.v;
+    e.P[1] = x[0];
+#pragma unroll
+    for (int i = 0; i < 3; i++) {
+      e.P[2 + i] = x[1 + i];
+      e.P[5 + i] = c.B[i];
+      e.P[9 + i] = utr[i].v;
+    }
+    e.P[8] = Eb.v;
+    e.ok = 1;
+    norm_errors(c, Tg, Rr, Gv, e);
   }
-  e.P[8] = Eb.v;
-  e.ok = 1;
-  norm_errors(c, e);
+}
+
+DEV void eval_pmhd(const Cell& c, const Phys& ph, const double x[4], Eval& e, double J[4][4]) {
+#pragma unroll
+  for (int k0 = 0; k0 < 4; k0 += GRRMHD_NJ) pmhd_pass<GRRMHD_NJ>(c, ph, x, k0, e, J);
+}
+
+// gas (T^t_t + rho u^t, T^t_i) of primitives P, without sqrt(-g)
+DEV void gas_cons4(const Metric& m, double gam, const double* P, double Tg[4]) {
+  Gas<double> s;
+  make_gas(m, gam, P[0], P[1], P + 2, P + 5, s);
+  double row[8];
+  gas_row(s, P + 5, 0, row);
+#pragma unroll
+  for (int k = 0; k < 4; k++) Tg[k] = row[1 + k];
+}
+
+DEV void rad_cons4(const Metric& m, const double* P, double Rr[4]) {
+  Vel<double> r;
+  make_vel(m, P + 9, r);
+  rad_row(r, P[8], 0, Rr);
 }
 
 // URAD residual (Sec. 4.8, URAD steps): gas from inverting T(i) - Delta R,
@@ -164,7 +215,7 @@ DEV void eval_urad(const Cell& c, const Phys& ph, const double x[4], const doubl
   gas_row(s, c.B, 0, row);
   Vel<double> r;
   make_vel(c.m, utr, r);
-  double Rr[4];
+  double Rr[4], Tg[4];
   rad_row(r, Eb, 0, Rr);
   const double Tgas = s.pg / rho;
   const double kabs = c.chi_abs * rho, kes = c.chi_es * rho;
@@ -173,9 +224,7 @@ DEV void eval_urad(const Cell& c, const Phys& ph, const double x[4], const doubl
   four_force(s.v, r, Eb, kabs, kes, lam, G);
 #pragma unroll
   for (int k = 0; k < 4; k++) {
-    e.Tg[k] = row[1 + k];
-    e.Rr[k] = Rr[k];
-    e.G[k] = G[k];
+    Tg[k] = row[1 + k];
     e.Eg[k] = (row[1 + k] - c.Tgi[k]) - c.dt * G[k];
     e.Er[k] = (Rr[k] - c.Ri[k]) + c.dt * G[k];
   }
@@ -188,7 +237,7 @@ DEV void eval_urad(const Cell& c, const Phys& ph, const double x[4], const doubl
     e.P[9 + i] = utr[i];
   }
   e.P[8] = Eb;
-  norm_errors(c, e);
+  norm_errors(c, Tg, Rr, G, e);
 }
 
 // 4x4 solve with partial pivoting; 0 on success
@@ -233,13 +282,13 @@ DEV double rad_energy_lab(const Metric& m, const double R[4]) {
 }
 
 struct Best {
-  double x[4], P[12], Tg[4], Rr[4], eT;
+  double x[4], P[12], eT;
   int radflags, ok;
 };
 
 DEV void keep(Best& b, const Eval& e) {
 #pragma unroll
-  for (int k = 0; k < 4; k++) { b.x[k] = e.x[k]; b.Tg[k] = e.Tg[k]; b.Rr[k] = e.Rr[k]; }
+  for (int k = 0; k < 4; k++) b.x[k] = e.x[k];
 #pragma unroll
   for (int q = 0; q < 12; q++) b.P[q] = e.P[q];
   b.eT = e.eT;
@@ -247,18 +296,18 @@ DEV void keep(Best& b, const Eval& e) {
   b.ok = e.ok;
 }
 
-struct Opts {
-  double tol_pmhd, tol_urad;
-  int max_iter, roundoff;
-};
-
-// One "normal" Newton attempt (D = 1) with one method.
-DEV void newton(const Cell& c, const Phys& ph, const Opts& o, int method, const double x0[4],
+// One "normal" Newton attempt (D = 1) with one method.  A single Eval
+// record is live: the new iterate is evaluated into it once the step is
+// taken (PMHD needs only x; URAD keeps the five gas values that seed its
+// inner inversion).
+template <int METHOD>
+DEV void newton(const Cell& c, const Phys& ph, const Opts& o, const double x0[4],
                 const double Pg0[5], Best& best, int& iters) {
-  const double tol = (method == M_PMHD) ? o.tol_pmhd : o.tol_urad;
+  const double tol = (METHOD == M_PMHD) ? o.tol_pmhd : o.tol_urad;
   double x[4] = {x0[0], x0[1], x0[2], x0[3]};
   Eval ev;
-  if (method == M_PMHD) eval_pmhd(c, ph, x, ev);
+  double J[4][4];
+  if (METHOD == M_PMHD) eval_pmhd(c, ph, x, ev, J);
   else eval_urad(c, ph, x, Pg0, ev);
   keep(best, ev);
   if (!ev.ok) return;
@@ -274,18 +323,13 @@ DEV void newton(const Cell& c, const Phys& ph, const Opts& o, int method, const 
       extra++;
     }
     if (!conv && it >= 5 && ev.eT > 0.5 * (h[0] + h[1] + h[2]) * (1.0 / 3.0)) break;
-    double J[4][4], r[4];
-    if (method == M_PMHD) {
+    double r[4];
+    double Pn[5];
 #pragma unroll
-      for (int i = 0; i < 4; i++) {
-        r[i] = ev.Eg[i];
-#pragma unroll
-        for (int j = 0; j < 4; j++) J[i][j] = ev.J[i][j];
-      }
-    } else {
+    for (int q = 0; q < 5; q++) Pn[q] = ev.P[q];
+    if (METHOD == M_URAD) {
       const double delta = (ev.eIr < 1e-9) ? 1e-10 : 1e-8;
       int jfail = 0;
-      double Pn[5] = {ev.P[0], ev.P[1], ev.P[2], ev.P[3], ev.P[4]};
       for (int j = 0; j < 4 && !jfail; j++) {
         const double N = (j == 0) ? ::fabs(x[0]) : ::fabs(x[j]) + ::fabs(x[0]) / ::sqrt(gamup(c.m, j - 1, j - 1));
         double hh = delta * N;
@@ -310,33 +354,34 @@ DEV void newton(const Cell& c, const Phys& ph, const Opts& o, int method, const 
       if (jfail) break;
 #pragma unroll
       for (int i = 0; i < 4; i++) r[i] = ev.Er[i];
+    } else {
+#pragma unroll
+      for (int i = 0; i < 4; i++) r[i] = ev.Eg[i];
     }
     double dx[4];
     if (solve4(J, r, dx)) break;
     double xn[4];
 #pragma unroll
     for (int i = 0; i < 4; i++) xn[i] = x[i] - dx[i];
-    Eval en;
-    if (method == M_PMHD) {
+    if (METHOD == M_PMHD) {
       if (xn[0] < 0.0) xn[0] = 0.5 * ::fabs(xn[0]);            // one-sided bisection of u_g
-      eval_pmhd(c, ph, xn, en);
+      eval_pmhd(c, ph, xn, ev, J);
     } else {
       const double Erl = rad_energy_lab(c.m, xn);
       if (Erl <= 0.0) {                                       // same for the radiation energy
         const double a2 = c.m.alpha * c.m.alpha;
         xn[0] = -0.5 * ::fabs(Erl) + a2 * (c.m.up(0, 1) * xn[1] + c.m.up(0, 2) * xn[2] + c.m.up(0, 3) * xn[3]);
       }
-      double Pn[5] = {ev.P[0], ev.P[1], ev.P[2], ev.P[3], ev.P[4]};
-      eval_urad(c, ph, xn, Pn, en);
+      eval_urad(c, ph, xn, Pn, ev);
       int back = 0;
-      while (!en.ok && back < 20) {                           // back up half-way
+      while (!ev.ok && back < 20) {                           // back up half-way
         nfail++;
 #pragma unroll
         for (int i = 0; i < 4; i++) xn[i] = 0.5 * (x[i] + xn[i]);
-        eval_urad(c, ph, xn, Pn, en);
+        eval_urad(c, ph, xn, Pn, ev);
         back++;
       }
-      if (!en.ok || nfail > 3) {
+      if (!ev.ok || nfail > 3) {
         iters++;
         break;
       }
@@ -349,7 +394,6 @@ DEV void newton(const Cell& c, const Phys& ph, const Opts& o, int method, const 
 #pragma unroll
     for (int i = 0; i < 4; i++) x[i] = xn[i];
     const double prev = h[4];
-    ev = en;
 #pragma unroll
     for (int k = 0; k < 4; k++) h[k] = h[k + 1];
     h[4] = ev.eT;
@@ -368,13 +412,15 @@ struct CellOut {
   double err;
 };
 
-// Full cascade for one cell (Sec. 4.10-4.11).  Ui: explicit conserved state
-// without sqrt(-g) factors removed (densitised, as stored); Pg: previous
-// primitives (the guess).
-DEV void implicit_cell(const Metric& m, const Phys& ph, const Opts& o, double tol_accept,
-                       double tol_fail, const double Ui[12], const double Pg[12], double dt,
-                       double chi_abs, double chi_es, CellOut& out) {
-  Cell c;
+// Cell set-up shared by both kernels: explicit state, regime and guess.
+struct Prep {
+  double Pthin[5];
+  int status;
+  bool extreme;
+};
+
+DEV void prepare(const Metric& m, const Phys& ph, const double Ui[12], const double Pg[12], double dt,
+                 double chi_abs, double chi_es, Cell& c, Prep& pr) {
   c.m = m;
   const double igd = 1.0 / m.gdet;
   c.rhout = Ui[0] * igd;
@@ -388,8 +434,7 @@ DEV void implicit_cell(const Metric& m, const Phys& ph, const Opts& o, double to
   c.dt = dt;
   c.chi_abs = chi_abs;
   c.chi_es = chi_es;
-  int status = 0, iters = 0;
-
+  pr.status = 0;
   // extreme radiation sub-dominance: R^t_t against the gas energy, or the
   // gas-frame radiation energy of the guess against u_g, below 10 eps
   double Ehat;
@@ -403,90 +448,52 @@ DEV void implicit_cell(const Metric& m, const Phys& ph, const Opts& o, double to
     Ehat = (4.0 / 3.0) * Pg[8] * w * w - Pg[8] * (1.0 / 3.0);
   }
   const double tenEps = 10.0 * DBL_EPSILON;
-  const bool extreme = (::fabs(c.Ri[0]) <= tenEps * (::fabs(c.Tgi[0]) + ::fabs(c.Ri[0]))) ||
-                       (::fabs(Ehat) <= tenEps * (::fabs(Pg[1]) + ::fabs(Ehat)));
-  if (extreme) status |= GRRMHD_ST_EXTREME;
-
+  pr.extreme = (::fabs(c.Ri[0]) <= tenEps * (::fabs(c.Tgi[0]) + ::fabs(c.Ri[0]))) ||
+               (::fabs(Ehat) <= tenEps * (::fabs(Pg[1]) + ::fabs(Ehat)));
+  if (pr.extreme) pr.status |= GRRMHD_ST_EXTREME;
   // PMHD guess: prior primitives, or the MHD inversion of U(i) when the
   // temporal optical depth dt kappa_tot(P_n) < 2/3
-  double Pthin[5] = {Pg[0], Pg[1], Pg[2], Pg[3], Pg[4]};
+#pragma unroll
+  for (int q = 0; q < 5; q++) pr.Pthin[q] = Pg[q];
   if (dt * (chi_abs + chi_es) * Pg[0] < 2.0 / 3.0) {
     double rho = Pg[0], ug = Pg[1], ut[3] = {Pg[2], Pg[3], Pg[4]};
     if (mhd_invert(m, ph.gam, c.rhout, c.Tgi[0], c.Tgi + 1, c.B, rho, ug, ut) == 0) {
-      Pthin[0] = rho; Pthin[1] = ug; Pthin[2] = ut[0]; Pthin[3] = ut[1]; Pthin[4] = ut[2];
+      pr.Pthin[0] = rho; pr.Pthin[1] = ug; pr.Pthin[2] = ut[0]; pr.Pthin[3] = ut[1]; pr.Pthin[4] = ut[2];
     } else {
-      status |= GRRMHD_ST_C2P_FAIL;
+      pr.status |= GRRMHD_ST_C2P_FAIL;
     }
   }
+}
 
-  Best best;
-  best.eT = INFINITY;
-  best.ok = 0;
-  int bm = -1;
-  for (int k = 0; k < 2; k++) {
-    const int method = (k == 0) == extreme ? M_URAD : M_PMHD;
-    double x0[4], P0[5];
-    const bool prev = (bm >= 0 && best.eT < 1e-4);
-    if (method == M_PMHD) {
-      const double* src = prev ? best.P : Pthin;
-      x0[0] = src[1]; x0[1] = src[2]; x0[2] = src[3]; x0[3] = src[4];
-#pragma unroll
-      for (int q = 0; q < 5; q++) P0[q] = src[q];
-    } else if (prev) {
-#pragma unroll
-      for (int q = 0; q < 4; q++) x0[q] = best.Rr[q];
-#pragma unroll
-      for (int q = 0; q < 5; q++) P0[q] = best.P[q];
-    } else {
-      Vel<double> r;
-      make_vel(m, Pg + 9, r);
-      rad_row(r, Pg[8], 0, x0);
-#pragma unroll
-      for (int q = 0; q < 5; q++) P0[q] = Pg[q];
-    }
-    Best b;
-    b.eT = INFINITY;
-    b.ok = 0;
-    newton(c, ph, o, method, x0, P0, b, iters);
-    if (b.ok && b.eT < best.eT) {
-      best = b;
-      bm = method;
-    }
-    // accepted without a further method (Sec. 4.10); in round-off mode keep
-    // going until one method meets the PMHD tolerance
-    if (best.eT < (o.roundoff ? o.tol_pmhd : tol_accept)) break;
-  }
+// Acceptance without trying a further method (Sec. 4.10: e_T < tol_accept);
+// when iterating to round-off, within 10x the PMHD tolerance.
+DEV double accept_threshold(const Opts& o) { return o.roundoff ? 10.0 * o.tol_pmhd : o.tol_accept; }
 
-#pragma unroll
-  for (int q = 0; q < 12; q++) {
-    out.P[q] = Pg[q];
-    out.U[q] = Ui[q];
-  }
+// Conserved output and status from the best solution (Sec. 4.10-4.11).
+DEV void finalize(const Cell& c, const Phys& ph, const Opts& o, const Best& best, int method,
+                  int status, int iters, const double Ui[12], CellOut& out) {
+  const Metric& m = c.m;
   out.iters = iters;
-  if (bm < 0) {
-    out.status = status | GRRMHD_ST_FAIL;
-    out.err = INFINITY;
-    return;
-  }
-  status |= (bm == M_PMHD) ? GRRMHD_ST_PMHD : GRRMHD_ST_URAD;
-  if (best.eT > tol_fail) status |= GRRMHD_ST_FAIL;
-  else if (best.eT > tol_accept) status |= GRRMHD_ST_NOT_ACCEPT;
+  status |= (method == M_PMHD) ? GRRMHD_ST_PMHD : GRRMHD_ST_URAD;
+  if (best.eT > o.tol_fail) status |= GRRMHD_ST_FAIL;
+  else if (best.eT > o.tol_accept) status |= GRRMHD_ST_NOT_ACCEPT;
   if (best.radflags & 1) status |= GRRMHD_ST_TYPE2_NEG;
 #pragma unroll
   for (int q = 0; q < 12; q++) out.P[q] = best.P[q];
   double Ug[4], Ur[4];
+  if (method == M_PMHD) {
+    gas_cons4(m, ph.gam, best.P, Ug);
 #pragma unroll
-  for (int k = 0; k < 4; k++) {
-    if (bm == M_PMHD) {
-      Ug[k] = best.Tg[k];
-      Ur[k] = c.Ri[k] - (best.Tg[k] - c.Tgi[k]);
-    } else {
+    for (int k = 0; k < 4; k++) Ur[k] = c.Ri[k] - (Ug[k] - c.Tgi[k]);
+  } else {
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
       Ur[k] = best.x[k];
       Ug[k] = c.Tgi[k] - (best.x[k] - c.Ri[k]);
     }
   }
   bool radchg = best.radflags != 0;
-  if (bm == M_PMHD && (best.radflags & 1)) {
+  if (method == M_PMHD && (best.radflags & 1)) {
     double Eb, utr[3];
     rad_invert(m, ph.gamma_max, ph.ymax, 0, Ur, Eb, utr);
     out.P[8] = Eb;
@@ -494,11 +501,7 @@ DEV void implicit_cell(const Metric& m, const Phys& ph, const Opts& o, double to
     status |= GRRMHD_ST_BASIC;
     radchg = true;
   }
-  if (radchg) {
-    Vel<double> r;
-    make_vel(m, out.P + 9, r);
-    rad_row(r, out.P[8], 0, Ur);
-  }
+  if (radchg) rad_cons4(m, out.P, Ur);
   const double gd = m.gdet;
   out.U[0] = Ui[0];
 #pragma unroll
@@ -511,4 +514,84 @@ DEV void implicit_cell(const Metric& m, const Phys& ph, const Opts& o, double to
   if (!(out.P[1] > 0.0)) status |= GRRMHD_ST_FAIL;
   out.status = status;
   out.err = best.eT;
+}
+
+DEV void failed_out(const double Ui[12], const double Pg[12], int status, int iters, CellOut& out) {
+#pragma unroll
+  for (int q = 0; q < 12; q++) {
+    out.P[q] = Pg[q];
+    out.U[q] = Ui[q];
+  }
+  out.iters = iters;
+  out.status = status | GRRMHD_ST_FAIL;
+  out.err = INFINITY;
+}
+
+// Common case: not extreme, first PMHD attempt accepted.  Returns false when
+// the cell needs the full cascade.
+DEV bool implicit_fast(const Metric& m, const Phys& ph, const Opts& o, const double Ui[12],
+                       const double Pg[12], double dt, double chi_abs, double chi_es,
+                       CellOut& out) {
+  Cell c;
+  Prep pr;
+  prepare(m, ph, Ui, Pg, dt, chi_abs, chi_es, c, pr);
+  if (pr.extreme) return false;
+  const double x0[4] = {pr.Pthin[1], pr.Pthin[2], pr.Pthin[3], pr.Pthin[4]};
+  Best b;
+  b.eT = INFINITY;
+  b.ok = 0;
+  int iters = 0;
+  newton<M_PMHD>(c, ph, o, x0, pr.Pthin, b, iters);
+  if (!(b.ok && b.eT < accept_threshold(o))) return false;
+  finalize(c, ph, o, b, M_PMHD, pr.status, iters, Ui, out);
+  return true;
+}
+
+// Full cascade for one cell (Sec. 4.10-4.11).
+DEV void implicit_cell(const Metric& m, const Phys& ph, const Opts& o, const double Ui[12],
+                       const double Pg[12], double dt, double chi_abs, double chi_es,
+                       CellOut& out) {
+  Cell c;
+  Prep pr;
+  prepare(m, ph, Ui, Pg, dt, chi_abs, chi_es, c, pr);
+  Best best;
+  best.eT = INFINITY;
+  best.ok = 0;
+  int bm = -1, iters = 0;
+  for (int k = 0; k < 2; k++) {
+    const int method = (k == 0) == pr.extreme ? M_URAD : M_PMHD;
+    double x0[4], P0[5];
+    const bool prev = (bm >= 0 && best.eT < 1e-4);
+    Best b;
+    b.eT = INFINITY;
+    b.ok = 0;
+    if (method == M_PMHD) {
+      const double* src = prev ? best.P : pr.Pthin;
+      x0[0] = src[1]; x0[1] = src[2]; x0[2] = src[3]; x0[3] = src[4];
+#pragma unroll
+      for (int q = 0; q < 5; q++) P0[q] = src[q];
+      newton<M_PMHD>(c, ph, o, x0, P0, b, iters);
+    } else {
+      if (prev) {
+        rad_cons4(m, best.P, x0);
+#pragma unroll
+        for (int q = 0; q < 5; q++) P0[q] = best.P[q];
+      } else {
+        rad_cons4(m, Pg, x0);
+#pragma unroll
+        for (int q = 0; q < 5; q++) P0[q] = Pg[q];
+      }
+      newton<M_URAD>(c, ph, o, x0, P0, b, iters);
+    }
+    if (b.ok && b.eT < best.eT) {
+      best = b;
+      bm = method;
+    }
+    if (best.eT < accept_threshold(o)) break;
+  }
+  if (bm < 0) {
+    failed_out(Ui, Pg, pr.status, iters, out);
+    return;
+  }
+  finalize(c, ph, o, best, bm, pr.status, iters, Ui, out);
 }

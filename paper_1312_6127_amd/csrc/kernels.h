@@ -5,6 +5,10 @@
 #include "implicit.h"
 
 #define LB(n) __launch_bounds__(n)
+#ifndef GRRMHD_IMP_WAVES
+#define GRRMHD_IMP_WAVES 1   // minimum waves per SIMD asked of the implicit kernels
+#endif
+#define LBI __launch_bounds__(64, GRRMHD_IMP_WAVES)
 
 DEV long cell_index(const Ctx& C, int i, int j, int k) { return i + C.st[1] * j + C.st[2] * k; }
 
@@ -447,76 +451,163 @@ DEV Opts make_opts(const Ctx& C) {
   Opts o;
   o.tol_pmhd = C.tol_pmhd;
   o.tol_urad = C.tol_urad;
+  o.tol_accept = C.tol_accept;
+  o.tol_fail = C.tol_fail;
   o.max_iter = C.max_iter;
   o.roundoff = C.roundoff;
   return o;
 }
 
-__global__ void LB(64) k_implicit(Ctx C, const double* __restrict__ Uexp,
-                                  const double* Pguess, double dt_scale,
-                                  const double* __restrict__ dt_dev,
-                                  const double* __restrict__ chi_abs,
-                                  const double* __restrict__ chi_es, double* P,
-                                  double* __restrict__ U, int* __restrict__ iters,
-                                  int* __restrict__ status, double* __restrict__ err) {
-  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  const long nint = (long)C.n[0] * C.n[1] * C.n[2];
-  if (t >= nint) return;
-  const int i = C.ng[0] + t % C.n[0];
-  const long t2 = t / C.n[0];
-  const int j = C.ng[1] + t2 % C.n[1];
-  const int k = C.ng[2] + t2 / C.n[1];
-  const long c = cell_index(C, i, j, k);
-  Metric m;
-  load_metric(C.geo_c, C.npos, i + C.N[0] * j, m);
-  double Ui[12], Pg[12];
+// Append flagged lanes of a wavefront to a work list: one atomic per
+// wavefront, slots ordered by lane (ballot + popcount prefix).
+DEV void wave_append(bool need, int item, int* counter, int* list) {
+  const unsigned long long mask = __ballot(need);
+  if (mask == 0ull) return;
+  const int lane = threadIdx.x & 63;
+  const int leader = __ffsll((long long)mask) - 1;
+  int base = 0;
+  if (lane == leader) base = atomicAdd(counter, __popcll(mask));
+  base = __shfl(base, leader, 64);
+  if (need) list[base + __popcll(mask & ((1ull << lane) - 1ull))] = item;
+}
+
+__global__ void k_zero_int(int* p) { *p = 0; }
+
+DEV void store_out(const CellOut& o, long c, long Nst, double* P, double* U, int* iters,
+                   int* status, double* err) {
 #pragma unroll
   for (int q = 0; q < 12; q++) {
-    Ui[q] = Uexp[q * C.Ntot + c];
-    Pg[q] = Pguess[q * C.Ntot + c];
-  }
-  CellOut o;
-  implicit_cell(m, make_phys(C), make_opts(C), C.tol_accept, C.tol_fail, Ui, Pg,
-                dt_scale * (*dt_dev), chi_abs[c], chi_es[c], o);
-#pragma unroll
-  for (int q = 0; q < 12; q++) {
-    P[q * C.Ntot + c] = o.P[q];
-    U[q * C.Ntot + c] = o.U[q];
+    P[q * Nst + c] = o.P[q];
+    U[q * Nst + c] = o.U[q];
   }
   if (iters) iters[c] = o.iters;
   if (status) status[c] = o.status;
   if (err) err[c] = o.err;
 }
 
-__global__ void LB(64) k_implicit_batch(Ctx C, long n, const double* __restrict__ Ui_,
+// Common path of the implicit solve at interior cells; cells that need the
+// full cascade go to the work list (index into the interior enumeration).
+__global__ void LBI k_implicit(Ctx C, const double* __restrict__ Uexp, const double* Pguess,
+                                  double dt_scale, const double* __restrict__ dt_dev,
+                                  const double* __restrict__ chi_abs,
+                                  const double* __restrict__ chi_es, double* P,
+                                  double* __restrict__ U, int* __restrict__ iters,
+                                  int* __restrict__ status, double* __restrict__ err,
+                                  int* counter, int* list) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long nint = (long)C.n[0] * C.n[1] * C.n[2];
+  bool need = false;
+  if (t < nint) {
+    const int i = C.ng[0] + t % C.n[0];
+    const long t2 = t / C.n[0];
+    const int j = C.ng[1] + t2 % C.n[1];
+    const int k = C.ng[2] + t2 / C.n[1];
+    const long c = cell_index(C, i, j, k);
+    Metric m;
+    load_metric(C.geo_c, C.npos, i + C.N[0] * j, m);
+    double Ui[12], Pg[12];
+#pragma unroll
+    for (int q = 0; q < 12; q++) {
+      Ui[q] = Uexp[q * C.Ntot + c];
+      Pg[q] = Pguess[q * C.Ntot + c];
+    }
+    CellOut o;
+    if (implicit_fast(m, make_phys(C), make_opts(C), Ui, Pg, dt_scale * (*dt_dev), chi_abs[c],
+                      chi_es[c], o))
+      store_out(o, c, C.Ntot, P, U, iters, status, err);
+    else
+      need = true;
+  }
+  wave_append(need, (int)t, counter, list);
+}
+
+// Full cascade over the work list; grid-stride over a count kept on the device.
+__global__ void LB(64) k_implicit_list(Ctx C, const double* __restrict__ Uexp,
+                                       const double* Pguess, double dt_scale,
+                                       const double* __restrict__ dt_dev,
+                                       const double* __restrict__ chi_abs,
+                                       const double* __restrict__ chi_es, double* P,
+                                       double* __restrict__ U, int* __restrict__ iters,
+                                       int* __restrict__ status, double* __restrict__ err,
+                                       const int* counter, const int* list) {
+  const int n = *counter;
+  for (long w = (long)blockIdx.x * blockDim.x + threadIdx.x; w < n;
+       w += (long)gridDim.x * blockDim.x) {
+    const long t = list[w];
+    const int i = C.ng[0] + t % C.n[0];
+    const long t2 = t / C.n[0];
+    const int j = C.ng[1] + t2 % C.n[1];
+    const int k = C.ng[2] + t2 / C.n[1];
+    const long c = cell_index(C, i, j, k);
+    Metric m;
+    load_metric(C.geo_c, C.npos, i + C.N[0] * j, m);
+    double Ui[12], Pg[12];
+#pragma unroll
+    for (int q = 0; q < 12; q++) {
+      Ui[q] = Uexp[q * C.Ntot + c];
+      Pg[q] = Pguess[q * C.Ntot + c];
+    }
+    CellOut o;
+    implicit_cell(m, make_phys(C), make_opts(C), Ui, Pg, dt_scale * (*dt_dev), chi_abs[c],
+                  chi_es[c], o);
+    store_out(o, c, C.Ntot, P, U, iters, status, err);
+  }
+}
+
+// Independent flat-space cells: same two-kernel structure.
+__global__ void LBI k_implicit_batch(Ctx C, long n, const double* __restrict__ Ui_,
                                         const double* __restrict__ Pg_,
                                         const double* __restrict__ dtc,
                                         const double* __restrict__ chi_abs,
                                         const double* __restrict__ chi_es,
                                         double* __restrict__ Po, double* __restrict__ Uo,
                                         int* __restrict__ iters, int* __restrict__ status,
-                                        double* __restrict__ err) {
+                                        double* __restrict__ err, int* counter, int* list) {
   const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= n) return;
-  Metric m;
-  flat_metric(m);
-  double Ui[12], Pg[12];
+  bool need = false;
+  if (c < n) {
+    Metric m;
+    flat_metric(m);
+    double Ui[12], Pg[12];
 #pragma unroll
-  for (int q = 0; q < 12; q++) {
-    Ui[q] = Ui_[q * n + c];
-    Pg[q] = Pg_[q * n + c];
+    for (int q = 0; q < 12; q++) {
+      Ui[q] = Ui_[q * n + c];
+      Pg[q] = Pg_[q * n + c];
+    }
+    CellOut o;
+    if (implicit_fast(m, make_phys(C), make_opts(C), Ui, Pg, dtc[c], chi_abs[c], chi_es[c], o))
+      store_out(o, c, n, Po, Uo, iters, status, err);
+    else
+      need = true;
   }
-  CellOut o;
-  implicit_cell(m, make_phys(C), make_opts(C), C.tol_accept, C.tol_fail, Ui, Pg, dtc[c],
-                chi_abs[c], chi_es[c], o);
+  wave_append(need, (int)c, counter, list);
+}
+
+__global__ void LB(64) k_implicit_batch_list(Ctx C, long n, const double* __restrict__ Ui_,
+                                             const double* __restrict__ Pg_,
+                                             const double* __restrict__ dtc,
+                                             const double* __restrict__ chi_abs,
+                                             const double* __restrict__ chi_es,
+                                             double* __restrict__ Po, double* __restrict__ Uo,
+                                             int* __restrict__ iters, int* __restrict__ status,
+                                             double* __restrict__ err, const int* counter,
+                                             const int* list) {
+  const int cnt = *counter;
+  for (long w = (long)blockIdx.x * blockDim.x + threadIdx.x; w < cnt;
+       w += (long)gridDim.x * blockDim.x) {
+    const long c = list[w];
+    Metric m;
+    flat_metric(m);
+    double Ui[12], Pg[12];
 #pragma unroll
-  for (int q = 0; q < 12; q++) {
-    Po[q * n + c] = o.P[q];
-    Uo[q * n + c] = o.U[q];
+    for (int q = 0; q < 12; q++) {
+      Ui[q] = Ui_[q * n + c];
+      Pg[q] = Pg_[q * n + c];
+    }
+    CellOut o;
+    implicit_cell(m, make_phys(C), make_opts(C), Ui, Pg, dtc[c], chi_abs[c], chi_es[c], o);
+    store_out(o, c, n, Po, Uo, iters, status, err);
   }
-  if (iters) iters[c] = o.iters;
-  if (status) status[c] = o.status;
-  if (err) err[c] = o.err;
 }
 
 __global__ void LB(128) k_con2prim(Ctx C, const double* __restrict__ U, const double* Pguess,

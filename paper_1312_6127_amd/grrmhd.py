@@ -85,7 +85,8 @@ def lib():
             "grrmhd_fixup": (C.c_int, [_VP] * 5),
             "grrmhd_step": (C.c_int, [_VP, _VP, _VP, _VP, _VP, _VP, C.c_int, _VP, _VP, _VP,
                                       C.c_size_t]),
-            "grrmhd_implicit_source": (C.c_int, [PP, C.c_long] + [_VP] * 11),
+            "grrmhd_implicit_source_workspace_bytes": (C.c_size_t, [C.c_long]),
+            "grrmhd_implicit_source": (C.c_int, [PP, C.c_long] + [_VP] * 11 + [C.c_size_t, _VP]),
         }
         for name, (res, args) in sigs.items():
             f = getattr(L, name)
@@ -221,7 +222,9 @@ def implicit_source(pd: dict, U_expl, P_guess, dt_cell, chi_abs, chi_es):
     st = torch.zeros(n, dtype=torch.int32, device=U.device)
     err = torch.zeros(n, dtype=torch.float64, device=U.device)
     p = params(pd)
+    wsb = lib().grrmhd_implicit_source_workspace_bytes(n)
+    ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device=U.device)
     _check(lib().grrmhd_implicit_source(C.byref(p), n, _ptr(U_expl), _ptr(P_guess), _ptr(dt_cell),
                                         _ptr(chi_abs), _ptr(chi_es), _ptr(P), _ptr(U), _ptr(it),
-                                        _ptr(st), _ptr(err), _stream()))
+                                        _ptr(st), _ptr(err), _ptr(ws), wsb, _stream()))
     return P, U, it, st, err

@@ -62,7 +62,7 @@ def test_invalid_parameters_are_rejected_before_any_device_work(L):
         assert rc == -1, kw
         assert L.grrmhd_last_error()
     p = G.params(I.default_params(metric="ks"))
-    assert L.grrmhd_implicit_source(C.byref(p), 10, *([None] * 11)) == -1
+    assert L.grrmhd_implicit_source(C.byref(p), 10, *([None] * 11), 0, None) == -1
     p = G.params(I.default_params())
-    assert L.grrmhd_implicit_source(C.byref(p), 0, *([None] * 11)) == 0
+    assert L.grrmhd_implicit_source(C.byref(p), 0, *([None] * 11), 0, None) == 0
     assert L.grrmhd_step(None, *([None] * 5), 0, None, None, None, 0) == -1
