@@ -37,7 +37,86 @@ def parse():
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="also copy a buffer of this many MiB (counter calibration)")
+    ap.add_argument("--batch-cells", type=int, default=0,
+                    help="also time the batched implicit solve on this many independent cells "
+                         "in each execution form (16777216 for the 16.7M-cell batch)")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="time only the batched implicit solve")
     return ap.parse_args()
+
+
+def _factor3(n):
+    """A near-cubic (nx, ny, nz) with nx*ny*nz == n (powers of two split evenly)."""
+    best = (n, 1, 1)
+    for nz in range(1, int(round(n ** (1 / 3))) + 2):
+        if n % nz:
+            continue
+        m = n // nz
+        for ny in range(nz, int(m ** 0.5) + 2):
+            if m % ny == 0 and m // ny >= ny and max(m // ny, ny, nz) < max(best):
+                best = (m // ny, ny, nz)
+    return best
+
+
+def batch_inputs(G, I, torch, dev, n, seed=11):
+    """Seeded batch (inputs.implicit_batch) with its explicit state: the
+    primitives' conserved form from the library's own prim_to_cons on a flat
+    grid holding the cells, the radiation energy raised 30% and the gas
+    energy lowered to match, so every cell starts out of equilibrium."""
+    pd, P, dt, ca, ce = I.implicit_batch(n, seed=seed)
+    shape = _factor3(n)
+    gd = dict(pd, n=shape)
+    g = G.Grid(gd)
+    na = I.nalloc(gd)
+    Pf = torch.zeros((12, g.N), dtype=torch.float64, device=dev)
+    inner = I.interior(gd)
+    Pv = Pf.view(12, *na[::-1])
+    Pt = torch.tensor(P, device=dev)
+    Pv[(slice(None),) + inner] = Pt.view(12, *shape[::-1])
+    Uf = g.prim_to_cons(Pf)
+    U = Uf.view(12, *na[::-1])[(slice(None),) + inner].reshape(12, n).contiguous()
+    g.close()
+    del Pf, Uf
+    Ui = U.clone()
+    Ui[8] *= 1.3
+    Ui[1] -= 0.3 * U[8]
+    return pd, [Ui, Pt, torch.tensor(dt, device=dev), torch.tensor(ca, device=dev),
+                torch.tensor(ce, device=dev)]
+
+
+def bench_batch(G, I, torch, dev, n, reps=3):
+    """Cell-solves/s of the batched implicit solve in each execution form."""
+    pd, args = batch_inputs(G, I, torch, dev, n)
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    tune, outs = G.autotune_implicit_source(pd, *args)
+    st = outs[3].cpu().numpy()
+    its = outs[2].cpu().numpy()
+    res = {"cells": n, "tol_pmhd": pd["tol_pmhd"],
+           "failed_frac": float(((st & G.ST_FAIL) != 0).mean()),
+           "urad_frac": float(((st & G.ST_URAD) != 0).mean()),
+           "mean_iters": float(its.mean()), "max_iters": int(its.max()),
+           "autotuned": {"mode": ["per_cell", "per_iteration", "persistent"][tune.mode],
+                         "block": tune.block, "waves_per_cu": tune.waves_per_cu}, "forms": {}}
+    forms = [("per_cell", G.PER_CELL, 64, 0), ("per_iteration", G.PER_ITERATION, 64, 0),
+             ("persistent_tuned", G.PERSISTENT, tune.block, max(tune.waves_per_cu, 1))]
+    for name, mode, block, wpc in forms:
+        ws = G.batch_workspace(n, mode)
+        out = G._batch_out(args[0], args[1])
+        G.implicit_source_ex(pd, *args, mode, block, wpc, out=out, ws=ws)
+        e0.record(stream)
+        for _ in range(reps):
+            G.implicit_source_ex(pd, *args, mode, block, wpc, out=out, ws=ws)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        same = all(torch.equal(a, b) for a, b in zip(out[1:], outs))
+        res["forms"][name] = {"ms": ms, "cell_solves_per_s": n / (ms * 1e-3),
+                              "block": block, "waves_per_cu": wpc, "identical_to_tuned_run": same}
+        del ws, out
+        print(f"batch form {name}: {ms:.3f} ms", file=sys.stderr, flush=True)
+    return res
 
 
 def main():
@@ -53,9 +132,12 @@ def main():
     from paper_1312_6127_amd import grrmhd as G
     from paper_1312_6127_amd import inputs as I
 
+    dev = torch.device("cuda:0")
+    if args.batch_only:
+        print(json.dumps({"implicit_batch": bench_batch(G, I, torch, dev, args.batch_cells or (1 << 24))}))
+        return
     n = tuple(args.n)
     pd, P, ca, ce = I.accretion_disk(n=n, seed=3)
-    dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
     g = G.Grid(pd)
     Pt = torch.tensor(P, device=dev)
@@ -157,6 +239,8 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
     }
+    if args.batch_cells:
+        out["implicit_batch"] = bench_batch(G, I, torch, dev, args.batch_cells)
     print(json.dumps(out))
     g.close()
 

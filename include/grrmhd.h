@@ -198,6 +198,42 @@ int grrmhd_implicit_source(const grrmhd_params *p, long n, const double *U_expl,
                            int *status, double *err, void *workspace, size_t ws_bytes,
                            void *hip_stream);
 
+/* Batched implicit solve with an explicit execution form (SURVEY growth
+ * direction: uneven Newton counts).  mode:
+ *   GRRMHD_IMPLICIT_PER_CELL       one thread per cell (as grrmhd_implicit_source);
+ *   GRRMHD_IMPLICIT_PER_ITERATION  one launch per Newton trip, lane state in
+ *                                  HBM, still-active cells compacted into the
+ *                                  next launch's queue;
+ *   GRRMHD_IMPLICIT_PERSISTENT     a fixed grid of waves_per_cu waves per CU in
+ *                                  blocks of `block` (64, 128, 256) threads;
+ *                                  each lane takes the next cell from a queue
+ *                                  whenever its cell converges.
+ * All forms give identical results (same decisions per cell).  workspace:
+ * grrmhd_implicit_source_workspace_bytes_ex(n, mode) bytes, 256-byte aligned. */
+enum { GRRMHD_IMPLICIT_PER_CELL = 0, GRRMHD_IMPLICIT_PER_ITERATION = 1, GRRMHD_IMPLICIT_PERSISTENT = 2 };
+size_t grrmhd_implicit_source_workspace_bytes_ex(long n, int mode);
+int grrmhd_implicit_source_ex(const grrmhd_params *p, long n, const double *U_expl,
+                              const double *P_guess, const double *dt_cell, const double *chi_abs,
+                              const double *chi_es, double *P_out, double *U_out, int *iters,
+                              int *status, double *err, int mode, int block, int waves_per_cu,
+                              void *workspace, size_t ws_bytes, void *hip_stream);
+
+/* Autotuner: times each candidate (per-cell form; persistent form with
+ * block 64/128/256 and 4/8/16 waves per CU) on the caller's inputs with HIP
+ * events (each candidate run twice, the second timed) and returns the
+ * fastest.  Outputs hold the last candidate's (identical) results.
+ * Synchronises the stream.  Workspace as for GRRMHD_IMPLICIT_PERSISTENT. */
+typedef struct {
+  int mode, block, waves_per_cu;
+  float ms;
+} grrmhd_tuning;
+int grrmhd_autotune_implicit_source(const grrmhd_params *p, long n, const double *U_expl,
+                                    const double *P_guess, const double *dt_cell,
+                                    const double *chi_abs, const double *chi_es, double *P_out,
+                                    double *U_out, int *iters, int *status, double *err,
+                                    void *workspace, size_t ws_bytes, void *hip_stream,
+                                    grrmhd_tuning *best);
+
 #ifdef __cplusplus
 }
 #endif

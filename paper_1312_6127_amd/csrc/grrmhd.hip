@@ -464,8 +464,164 @@ extern "C" int grrmhd_step(grrmhd_grid* g, double* P, double* U, const double* c
   return 0;
 }
 
+// Workspace of the batched solve: [0, 256) counters (list length, queue
+// cursor, two queue lengths), then the cascade work list, and for the
+// per-iteration form two queues and the lane state.
+static size_t round256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+extern "C" size_t grrmhd_implicit_source_workspace_bytes_ex(long n, int mode) {
+  if (n <= 0) return 0;
+  size_t b = 256 + round256(sizeof(int) * (size_t)n);
+  if (mode == GRRMHD_IMPLICIT_PER_ITERATION)
+    b += 2 * round256(sizeof(int) * (size_t)n) + round256(sizeof(double) * LS_ND * (size_t)n) +
+         round256(sizeof(int) * LI_NI * (size_t)n);
+  return b;
+}
+
 extern "C" size_t grrmhd_implicit_source_workspace_bytes(long n) {
-  return n > 0 ? 256 + sizeof(int) * (size_t)n : 0;
+  return grrmhd_implicit_source_workspace_bytes_ex(n, GRRMHD_IMPLICIT_PER_CELL);
+}
+
+static int check_batch_args(const grrmhd_params* p, long n, const double* U_expl,
+                            const double* P_guess, const double* dt_cell, const double* chi_abs,
+                            const double* chi_es, double* P_out, double* U_out, void* workspace,
+                            size_t ws_bytes, int mode) {
+  int rc = validate(p, false);
+  if (rc) return rc;
+  if (n < 0 || n > (1L << 31) - 1) return fail(GRRMHD_EINVAL, "n out of range");
+  if (n == 0) return 0;
+  if (!U_expl || !P_guess || !dt_cell || !chi_abs || !chi_es || !P_out || !U_out || !workspace)
+    return fail(GRRMHD_EINVAL, "NULL array");
+  if (mode < GRRMHD_IMPLICIT_PER_CELL || mode > GRRMHD_IMPLICIT_PERSISTENT)
+    return fail(GRRMHD_EINVAL, "bad implicit mode");
+  // the persistent queue cursor runs past n by up to one fetch per lane
+  if (mode == GRRMHD_IMPLICIT_PERSISTENT && n > (1L << 30))
+    return fail(GRRMHD_EINVAL, "n above 2^30 for the persistent form");
+  if (ws_bytes < grrmhd_implicit_source_workspace_bytes_ex(n, mode))
+    return fail(GRRMHD_EINVAL, "workspace too small");
+  if (((uintptr_t)workspace) & 255) return fail(GRRMHD_EINVAL, "workspace must be 256-byte aligned");
+  if (p->metric != GRRMHD_MINKOWSKI) return fail(GRRMHD_EINVAL, "batched cells use the Minkowski metric");
+  return 0;
+}
+
+static int launch_batch(const Ctx& C, long n, const double* U_expl, const double* P_guess,
+                        const double* dt_cell, const double* chi_abs, const double* chi_es,
+                        double* P_out, double* U_out, int* iters, int* status, double* err,
+                        int mode, int block, int waves_per_cu, void* workspace, hipStream_t s) {
+  char* base = (char*)workspace;
+  int* counter = (int*)base;          // cascade list length
+  int* next = counter + 1;            // persistent queue cursor
+  int* qc = counter + 2;              // per-iteration queue lengths (2)
+  int* list = (int*)(base + 256);
+  hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, s, counter, 4);
+  LAUNCHCHK();
+  if (mode == GRRMHD_IMPLICIT_PER_CELL) {
+    hipLaunchKernelGGL(k_implicit_batch, dim3(nblocks(n, 64)), dim3(64), 0, s, C, n, U_expl, P_guess,
+                       dt_cell, chi_abs, chi_es, P_out, U_out, iters, status, err, counter, list);
+    LAUNCHCHK();
+  } else if (mode == GRRMHD_IMPLICIT_PERSISTENT) {
+    if (block != 64 && block != 128 && block != 256) return fail(GRRMHD_EINVAL, "block must be 64, 128 or 256");
+    if (waves_per_cu < 1 || waves_per_cu > 64) return fail(GRRMHD_EINVAL, "waves_per_cu out of [1, 64]");
+    int dev = 0, ncu = 0;
+    HIPCHK(hipGetDevice(&dev));
+    HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    const long waves = (long)ncu * waves_per_cu;
+    const long blocks = std::max<long>(1, std::min<long>(waves * 64 / block, nblocks(n, block)));
+    hipLaunchKernelGGL(k_implicit_persist, dim3((unsigned)blocks), dim3(block), 0, s, C, n, U_expl,
+                       P_guess, dt_cell, chi_abs, chi_es, P_out, U_out, iters, status, err, next,
+                       counter, list);
+    LAUNCHCHK();
+  } else {
+    const size_t qb = round256(sizeof(int) * (size_t)n);
+    int* q0 = (int*)(base + 256 + qb);
+    int* q1 = (int*)(base + 256 + 2 * qb);
+    double* sd = (double*)(base + 256 + 3 * qb);
+    int* si = (int*)(base + 256 + 3 * qb + round256(sizeof(double) * LS_ND * (size_t)n));
+    hipLaunchKernelGGL(k_iter_start, dim3(nblocks(n, 64)), dim3(64), 0, s, C, n, U_expl, P_guess,
+                       dt_cell, chi_abs, chi_es, sd, si, qc, q0, counter, list);
+    LAUNCHCHK();
+    // every attempt ends within max_iter trips (+3 round-off trips are inside it)
+    for (int t = 0; t <= C.max_iter; t++) {
+      int* qin = (t % 2 == 0) ? q0 : q1;
+      int* qout = (t % 2 == 0) ? q1 : q0;
+      int* cin = qc + (t % 2);
+      int* cout = qc + 1 - (t % 2);
+      hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, s, cout, 1);
+      LAUNCHCHK();
+      hipLaunchKernelGGL(k_iter_step, dim3(list_blocks(n)), dim3(64), 0, s, C, n, U_expl, dt_cell,
+                         chi_abs, chi_es, sd, si, (const int*)cin, (const int*)qin, cout, qout,
+                         P_out, U_out, iters, status, err, counter, list);
+      LAUNCHCHK();
+    }
+  }
+  hipLaunchKernelGGL(k_implicit_batch_list, dim3(list_blocks(n)), dim3(64), 0, s, C, n, U_expl,
+                     P_guess, dt_cell, chi_abs, chi_es, P_out, U_out, iters, status, err,
+                     (const int*)counter, (const int*)list);
+  LAUNCHCHK();
+  return 0;
+}
+
+extern "C" int grrmhd_implicit_source_ex(const grrmhd_params* p, long n, const double* U_expl,
+                                         const double* P_guess, const double* dt_cell,
+                                         const double* chi_abs, const double* chi_es,
+                                         double* P_out, double* U_out, int* iters, int* status,
+                                         double* err, int mode, int block, int waves_per_cu,
+                                         void* workspace, size_t ws_bytes, void* hip_stream) {
+  int rc = check_batch_args(p, n, U_expl, P_guess, dt_cell, chi_abs, chi_es, P_out, U_out,
+                            workspace, ws_bytes, mode);
+  if (rc || n == 0) return rc;
+  Ctx C;
+  fill_ctx(p, C);
+  return launch_batch(C, n, U_expl, P_guess, dt_cell, chi_abs, chi_es, P_out, U_out, iters, status,
+                      err, mode, block, waves_per_cu, workspace, (hipStream_t)hip_stream);
+}
+
+extern "C" int grrmhd_autotune_implicit_source(const grrmhd_params* p, long n,
+                                               const double* U_expl, const double* P_guess,
+                                               const double* dt_cell, const double* chi_abs,
+                                               const double* chi_es, double* P_out,
+                                               double* U_out, int* iters, int* status,
+                                               double* err, void* workspace, size_t ws_bytes,
+                                               void* hip_stream, grrmhd_tuning* best) {
+  if (!best) return fail(GRRMHD_EINVAL, "best is NULL");
+  int rc = check_batch_args(p, n, U_expl, P_guess, dt_cell, chi_abs, chi_es, P_out, U_out,
+                            workspace, ws_bytes, GRRMHD_IMPLICIT_PERSISTENT);
+  if (rc) return rc;
+  if (n == 0) return fail(GRRMHD_EINVAL, "n must be positive");
+  Ctx C;
+  fill_ctx(p, C);
+  hipStream_t s = (hipStream_t)hip_stream;
+  const int cands[][3] = {{GRRMHD_IMPLICIT_PER_CELL, 64, 0},  {GRRMHD_IMPLICIT_PERSISTENT, 64, 4},
+                          {GRRMHD_IMPLICIT_PERSISTENT, 64, 8}, {GRRMHD_IMPLICIT_PERSISTENT, 128, 4},
+                          {GRRMHD_IMPLICIT_PERSISTENT, 128, 8}, {GRRMHD_IMPLICIT_PERSISTENT, 256, 4},
+                          {GRRMHD_IMPLICIT_PERSISTENT, 256, 8}, {GRRMHD_IMPLICIT_PERSISTENT, 256, 16}};
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  best->ms = 1e30f;
+  for (const auto& cd : cands) {
+    float tbest = 1e30f;
+    for (int rep = 0; rep < 2; rep++) {   // first run warms caches and code objects
+      HIPCHK(hipEventRecord(e0, s));
+      rc = launch_batch(C, n, U_expl, P_guess, dt_cell, chi_abs, chi_es, P_out, U_out, iters,
+                        status, err, cd[0], cd[1], cd[2], workspace, s);
+      if (rc) return rc;
+      HIPCHK(hipEventRecord(e1, s));
+      HIPCHK(hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+      if (rep > 0) tbest = ms;
+    }
+    if (tbest < best->ms) {
+      best->ms = tbest;
+      best->mode = cd[0];
+      best->block = cd[1];
+      best->waves_per_cu = cd[2];
+    }
+  }
+  HIPCHK(hipEventDestroy(e0));
+  HIPCHK(hipEventDestroy(e1));
+  return 0;
 }
 
 extern "C" int grrmhd_implicit_source(const grrmhd_params* p, long n, const double* U_expl,
@@ -473,28 +629,7 @@ extern "C" int grrmhd_implicit_source(const grrmhd_params* p, long n, const doub
                                       const double* chi_abs, const double* chi_es, double* P_out,
                                       double* U_out, int* iters, int* status, double* err,
                                       void* workspace, size_t ws_bytes, void* hip_stream) {
-  int rc = validate(p, false);
-  if (rc) return rc;
-  if (n < 0 || n > (1L << 31) - 1) return fail(GRRMHD_EINVAL, "n out of range");
-  if (n == 0) return 0;
-  if (!U_expl || !P_guess || !dt_cell || !chi_abs || !chi_es || !P_out || !U_out || !workspace)
-    return fail(GRRMHD_EINVAL, "NULL array");
-  if (ws_bytes < grrmhd_implicit_source_workspace_bytes(n))
-    return fail(GRRMHD_EINVAL, "workspace too small");
-  if (p->metric != GRRMHD_MINKOWSKI) return fail(GRRMHD_EINVAL, "batched cells use the Minkowski metric");
-  Ctx C;
-  fill_ctx(p, C);
-  hipStream_t s = (hipStream_t)hip_stream;
-  int* counter = (int*)workspace;
-  int* list = (int*)((char*)workspace + 256);
-  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, counter);
-  LAUNCHCHK();
-  hipLaunchKernelGGL(k_implicit_batch, dim3(nblocks(n, 64)), dim3(64), 0, s, C, n, U_expl, P_guess,
-                     dt_cell, chi_abs, chi_es, P_out, U_out, iters, status, err, counter, list);
-  LAUNCHCHK();
-  hipLaunchKernelGGL(k_implicit_batch_list, dim3(list_blocks(n)), dim3(64), 0, s, C, n, U_expl,
-                     P_guess, dt_cell, chi_abs, chi_es, P_out, U_out, iters, status, err,
-                     (const int*)counter, (const int*)list);
-  LAUNCHCHK();
-  return 0;
+  return grrmhd_implicit_source_ex(p, n, U_expl, P_guess, dt_cell, chi_abs, chi_es, P_out, U_out,
+                                   iters, status, err, GRRMHD_IMPLICIT_PER_CELL, 64, 0, workspace,
+                                   ws_bytes, hip_stream);
 }

@@ -595,3 +595,79 @@ DEV void implicit_cell(const Metric& m, const Phys& ph, const Opts& o, const dou
   }
   finalize(c, ph, o, best, bm, pr.status, iters, Ui, out);
 }
+
+// ---------------------------------------------------------------------------
+// Resumable PMHD attempt for the persistent and per-iteration kernels.
+//
+// The first PMHD attempt of the fast path as a state machine: every trip
+// evaluates the residual once, either at a new cell's guess or at the next
+// Newton iterate, so lanes that start a cell and lanes that continue one run
+// the same expensive code.  The decisions are exactly those of newton<PMHD>,
+// so results equal those of k_implicit bit for bit.
+// ---------------------------------------------------------------------------
+struct Lane {
+  double x[4];
+  double Eg[4], eT;        // residual and error of the current iterate
+  double J[4][4];
+  Best best;
+  double h[5];
+  int it, nrise, extra, conv, iters, status;
+};
+
+enum { TRIP_CONTINUE = 0, TRIP_DONE = 1, TRIP_CASCADE = 2 };
+
+// Part A of a Newton trip: loop-top checks and the step.  Returns true when
+// the attempt ends here.
+DEV bool lane_step(const Cell& c, const Opts& o, Lane& L) {
+  if (L.it >= o.max_iter) return true;
+  if (L.eT < o.tol_pmhd) L.conv = 1;
+  if (L.conv) {
+    if (!o.roundoff || L.extra >= 3) return true;
+    L.extra++;
+  }
+  if (!L.conv && L.it >= 5 && L.eT > 0.5 * (L.h[0] + L.h[1] + L.h[2]) * (1.0 / 3.0)) return true;
+  double r[4] = {L.Eg[0], L.Eg[1], L.Eg[2], L.Eg[3]}, dx[4];
+  if (solve4(L.J, r, dx)) return true;
+#pragma unroll
+  for (int i = 0; i < 4; i++) L.x[i] -= dx[i];
+  if (L.x[0] < 0.0) L.x[0] = 0.5 * ::fabs(L.x[0]);
+  return false;
+}
+
+// Part B after evaluating at the new iterate (xprev: the previous iterate).
+// Returns true when the attempt ends here.
+DEV bool lane_after(const Eval& ev, const double xprev[4], Lane& L) {
+  L.iters++;
+  bool small = true;
+#pragma unroll
+  for (int i = 0; i < 4; i++)
+    if (::fabs(L.x[i] - xprev[i]) > 10.0 * DBL_EPSILON * ::fabs(xprev[i])) small = false;
+  const double prev = L.h[4];
+#pragma unroll
+  for (int k = 0; k < 4; k++) L.h[k] = L.h[k + 1];
+  L.h[4] = ev.eT;
+  if (ev.eT < L.best.eT) keep(L.best, ev);
+  bool done = false;
+  if (L.it >= 5 && ev.eT > prev) {
+    L.nrise++;
+    if (L.nrise >= 5) done = true;
+  }
+  if (small) done = true;
+  L.it++;
+  return done;
+}
+
+DEV void lane_take(const Eval& ev, Lane& L) {
+#pragma unroll
+  for (int k = 0; k < 4; k++) L.Eg[k] = ev.Eg[k];
+  L.eT = ev.eT;
+}
+
+DEV void lane_start(const Eval& ev, Lane& L) {
+  keep(L.best, ev);
+#pragma unroll
+  for (int k = 0; k < 4; k++) L.h[k] = INFINITY;
+  L.h[4] = ev.eT;
+  L.it = L.nrise = L.extra = L.conv = L.iters = 0;
+  lane_take(ev, L);
+}

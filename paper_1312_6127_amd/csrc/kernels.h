@@ -739,3 +739,286 @@ __global__ void LB(256) k_fixup_apply(Ctx C, double* __restrict__ P, double* __r
   if (st_acc) st_acc[c] = accumulate ? (st_acc[c] | st) : st;
   if (it_acc && it_stage) it_acc[c] = accumulate ? it_acc[c] + it_stage[c] : it_stage[c];
 }
+
+// ---------------------------------------------------------------------------
+// Batched implicit solve, persistent and per-iteration forms.
+//
+// Persistent: a fixed grid of waves; each lane runs the resumable PMHD
+// attempt and, whenever its cell ends, takes the next cell from a global
+// queue (one atomic per wavefront), so unconverged cells stay packed in the
+// lanes whatever the spread of Newton counts.  Per-iteration: one launch per
+// Newton trip, the lane state kept in HBM and the still-active cells
+// compacted into the next launch's queue.  Cells that need the full cascade
+// go to the same work list as in k_implicit_batch.
+// ---------------------------------------------------------------------------
+#define LBP __launch_bounds__(256, 1)
+
+DEV void setup_cell(const Metric& m, const double Ui[12], double dt, double ca, double ce, Cell& c) {
+  c.m = m;
+  const double igd = 1.0 / m.gdet;
+  c.rhout = Ui[0] * igd;
+#pragma unroll
+  for (int i = 0; i < 3; i++) c.B[i] = Ui[5 + i] * igd;
+#pragma unroll
+  for (int k = 0; k < 4; k++) {
+    c.Tgi[k] = Ui[1 + k] * igd;
+    c.Ri[k] = Ui[8 + k] * igd;
+  }
+  c.dt = dt;
+  c.chi_abs = ca;
+  c.chi_es = ce;
+}
+
+// wavefront-aggregated queue fetch: one atomic for all lanes asking
+DEV long wave_fetch(bool need, int* next) {
+  const unsigned long long mask = __ballot(need);
+  if (mask == 0ull) return -1;
+  const int lane = threadIdx.x & 63;
+  const int leader = __ffsll((long long)mask) - 1;
+  int base = 0;
+  if (lane == leader) base = atomicAdd(next, __popcll(mask));
+  base = __shfl(base, leader, 64);
+  return need ? (long)base + __popcll(mask & ((1ull << lane) - 1ull)) : -1;
+}
+
+DEV void finish_lane(const Cell& c, const Phys& ph, const Opts& o, Lane& L, double U0,
+                     const double UB[3], long cidx, long nst, double* P, double* U, int* iters,
+                     int* status, double* err) {
+  double Uk[12];
+#pragma unroll
+  for (int q = 0; q < 12; q++) Uk[q] = 0.0;
+  Uk[0] = U0;
+  Uk[5] = UB[0]; Uk[6] = UB[1]; Uk[7] = UB[2];
+  CellOut out;
+  finalize(c, ph, o, L.best, M_PMHD, L.status, L.iters, Uk, out);
+  store_out(out, cidx, nst, P, U, iters, status, err);
+}
+
+__global__ void LBP k_implicit_persist(Ctx C, long n, const double* __restrict__ Ui_,
+                                       const double* __restrict__ Pg_,
+                                       const double* __restrict__ dtc,
+                                       const double* __restrict__ chi_abs,
+                                       const double* __restrict__ chi_es,
+                                       double* __restrict__ Po, double* __restrict__ Uo,
+                                       int* __restrict__ iters, int* __restrict__ status,
+                                       double* __restrict__ err, int* next, int* counter,
+                                       int* list) {
+  const Phys ph = make_phys(C);
+  const Opts o = make_opts(C);
+  const double thr = accept_threshold(o);
+  Metric m;
+  flat_metric(m);
+  Lane L;
+  Cell c;
+  double U0 = 0.0, UB[3] = {0.0, 0.0, 0.0};
+  long item = -1;
+  bool active = false, exhausted = false;
+  for (;;) {
+    const bool need = !active && !exhausted;
+    const long got = wave_fetch(need, next);
+    bool first = false, tolist = false;
+    if (need) {
+      if (got < n) {
+        item = got;
+        double Ui[12], Pg[12];
+#pragma unroll
+        for (int q = 0; q < 12; q++) {
+          Ui[q] = Ui_[q * n + item];
+          Pg[q] = Pg_[q * n + item];
+        }
+        Prep pr;
+        prepare(m, ph, Ui, Pg, dtc[item], chi_abs[item], chi_es[item], c, pr);
+        U0 = Ui[0];
+        UB[0] = Ui[5]; UB[1] = Ui[6]; UB[2] = Ui[7];
+        L.status = pr.status;
+        if (pr.extreme) {
+          tolist = true;
+        } else {
+          L.x[0] = pr.Pthin[1]; L.x[1] = pr.Pthin[2]; L.x[2] = pr.Pthin[3]; L.x[3] = pr.Pthin[4];
+          active = true;
+          first = true;
+        }
+      } else {
+        exhausted = true;
+      }
+    }
+    bool ended = false, doeval = first;
+    double xprev[4] = {L.x[0], L.x[1], L.x[2], L.x[3]};
+    if (active && !first) {
+      ended = lane_step(c, o, L);
+      doeval = !ended;
+    }
+    if (doeval) {
+      Eval ev;
+      eval_pmhd(c, ph, L.x, ev, L.J);
+      if (first) {
+        lane_start(ev, L);
+        if (!ev.ok) ended = true;
+      } else {
+        lane_take(ev, L);
+        ended = lane_after(ev, xprev, L);
+      }
+    }
+    if (ended) {
+      if (L.best.ok && L.best.eT < thr)
+        finish_lane(c, ph, o, L, U0, UB, item, n, Po, Uo, iters, status, err);
+      else
+        tolist = true;
+      active = false;
+    }
+    wave_append(tolist, (int)item, counter, list);
+    if (!__any(active) && __all(exhausted)) break;
+  }
+}
+
+// Lane state kept in HBM between per-iteration launches, field-major [f][n].
+enum { LS_X = 0, LS_EG = 4, LS_ET = 8, LS_J = 9, LS_BX = 25, LS_BP = 29, LS_BET = 41, LS_H = 42,
+       LS_ND = 47 };
+enum { LI_BRAD = 0, LI_BOK, LI_IT, LI_NRISE, LI_EXTRA, LI_CONV, LI_ITERS, LI_STATUS, LI_NI };
+
+DEV void lane_save(const Lane& L, long c, long n, double* sd, int* si) {
+#pragma unroll
+  for (int k = 0; k < 4; k++) {
+    sd[(LS_X + k) * n + c] = L.x[k];
+    sd[(LS_EG + k) * n + c] = L.Eg[k];
+    sd[(LS_BX + k) * n + c] = L.best.x[k];
+#pragma unroll
+    for (int j = 0; j < 4; j++) sd[(LS_J + 4 * k + j) * n + c] = L.J[k][j];
+  }
+  sd[LS_ET * n + c] = L.eT;
+#pragma unroll
+  for (int q = 0; q < 12; q++) sd[(LS_BP + q) * n + c] = L.best.P[q];
+  sd[LS_BET * n + c] = L.best.eT;
+#pragma unroll
+  for (int k = 0; k < 5; k++) sd[(LS_H + k) * n + c] = L.h[k];
+  si[LI_BRAD * n + c] = L.best.radflags;
+  si[LI_BOK * n + c] = L.best.ok;
+  si[LI_IT * n + c] = L.it;
+  si[LI_NRISE * n + c] = L.nrise;
+  si[LI_EXTRA * n + c] = L.extra;
+  si[LI_CONV * n + c] = L.conv;
+  si[LI_ITERS * n + c] = L.iters;
+  si[LI_STATUS * n + c] = L.status;
+}
+
+DEV void lane_load(Lane& L, long c, long n, const double* sd, const int* si) {
+#pragma unroll
+  for (int k = 0; k < 4; k++) {
+    L.x[k] = sd[(LS_X + k) * n + c];
+    L.Eg[k] = sd[(LS_EG + k) * n + c];
+    L.best.x[k] = sd[(LS_BX + k) * n + c];
+#pragma unroll
+    for (int j = 0; j < 4; j++) L.J[k][j] = sd[(LS_J + 4 * k + j) * n + c];
+  }
+  L.eT = sd[LS_ET * n + c];
+#pragma unroll
+  for (int q = 0; q < 12; q++) L.best.P[q] = sd[(LS_BP + q) * n + c];
+  L.best.eT = sd[LS_BET * n + c];
+#pragma unroll
+  for (int k = 0; k < 5; k++) L.h[k] = sd[(LS_H + k) * n + c];
+  L.best.radflags = si[LI_BRAD * n + c];
+  L.best.ok = si[LI_BOK * n + c];
+  L.it = si[LI_IT * n + c];
+  L.nrise = si[LI_NRISE * n + c];
+  L.extra = si[LI_EXTRA * n + c];
+  L.conv = si[LI_CONV * n + c];
+  L.iters = si[LI_ITERS * n + c];
+  L.status = si[LI_STATUS * n + c];
+}
+
+// first trip of every cell: guess, first evaluation; active cells to queue
+__global__ void LB(64) k_iter_start(Ctx C, long n, const double* __restrict__ Ui_,
+                                    const double* __restrict__ Pg_, const double* __restrict__ dtc,
+                                    const double* __restrict__ chi_abs,
+                                    const double* __restrict__ chi_es, double* sd, int* si,
+                                    int* qcount, int* queue, int* counter, int* list) {
+  const long cidx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  bool act = false, tolist = false;
+  if (cidx < n) {
+    const Phys ph = make_phys(C);
+    Metric m;
+    flat_metric(m);
+    double Ui[12], Pg[12];
+#pragma unroll
+    for (int q = 0; q < 12; q++) {
+      Ui[q] = Ui_[q * n + cidx];
+      Pg[q] = Pg_[q * n + cidx];
+    }
+    Cell c;
+    Prep pr;
+    prepare(m, ph, Ui, Pg, dtc[cidx], chi_abs[cidx], chi_es[cidx], c, pr);
+    Lane L;
+    L.status = pr.status;
+    if (pr.extreme) {
+      tolist = true;
+    } else {
+      L.x[0] = pr.Pthin[1]; L.x[1] = pr.Pthin[2]; L.x[2] = pr.Pthin[3]; L.x[3] = pr.Pthin[4];
+      Eval ev;
+      eval_pmhd(c, ph, L.x, ev, L.J);
+      lane_start(ev, L);
+      if (ev.ok) act = true;
+      else tolist = true;
+      lane_save(L, cidx, n, sd, si);
+    }
+  }
+  wave_append(act, (int)cidx, qcount, queue);
+  wave_append(tolist, (int)cidx, counter, list);
+}
+
+// one Newton trip for every queued cell
+__global__ void LB(64) k_iter_step(Ctx C, long n, const double* __restrict__ Ui_,
+                                   const double* __restrict__ dtc,
+                                   const double* __restrict__ chi_abs,
+                                   const double* __restrict__ chi_es, double* sd, int* si,
+                                   const int* qin_count, const int* qin, int* qout_count,
+                                   int* qout, double* __restrict__ Po, double* __restrict__ Uo,
+                                   int* __restrict__ iters, int* __restrict__ status,
+                                   double* __restrict__ err, int* counter, int* list) {
+  const int cnt = *qin_count;
+  const long stride = (long)gridDim.x * blockDim.x;
+  const long rounds = (cnt + stride - 1) / stride;
+  for (long r = 0; r < rounds; r++) {
+    const long w = r * stride + (long)blockIdx.x * blockDim.x + threadIdx.x;
+    bool keepgoing = false, tolist = false;
+    long cidx = -1;
+    if (w < cnt) {
+      cidx = qin[w];
+      const Phys ph = make_phys(C);
+      const Opts o = make_opts(C);
+      Metric m;
+      flat_metric(m);
+      double Ui[12];
+#pragma unroll
+      for (int q = 0; q < 12; q++) Ui[q] = Ui_[q * n + cidx];
+      Cell c;
+      setup_cell(m, Ui, dtc[cidx], chi_abs[cidx], chi_es[cidx], c);
+      Lane L;
+      lane_load(L, cidx, n, sd, si);
+      double xprev[4] = {L.x[0], L.x[1], L.x[2], L.x[3]};
+      bool ended = lane_step(c, o, L);
+      if (!ended) {
+        Eval ev;
+        eval_pmhd(c, ph, L.x, ev, L.J);
+        lane_take(ev, L);
+        ended = lane_after(ev, xprev, L);
+      }
+      if (ended) {
+        if (L.best.ok && L.best.eT < accept_threshold(o)) {
+          const double UB[3] = {Ui[5], Ui[6], Ui[7]};
+          finish_lane(c, ph, o, L, Ui[0], UB, cidx, n, Po, Uo, iters, status, err);
+        } else {
+          tolist = true;
+        }
+      } else {
+        lane_save(L, cidx, n, sd, si);
+        keepgoing = true;
+      }
+    }
+    wave_append(keepgoing, (int)cidx, qout_count, qout);
+    wave_append(tolist, (int)cidx, counter, list);
+  }
+}
+
+__global__ void k_zero_ints(int* p, int k) {
+  if (threadIdx.x < k) p[threadIdx.x] = 0;
+}

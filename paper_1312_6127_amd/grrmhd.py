@@ -36,6 +36,13 @@ class Params(C.Structure):
     ]
 
 
+class Tuning(C.Structure):
+    _fields_ = [("mode", C.c_int), ("block", C.c_int), ("waves_per_cu", C.c_int), ("ms", C.c_float)]
+
+
+PER_CELL, PER_ITERATION, PERSISTENT = 0, 1, 2
+
+
 def params(d: dict) -> Params:
     p = Params()
     p.n[:] = list(d["n"])
@@ -87,6 +94,11 @@ def lib():
                                       C.c_size_t]),
             "grrmhd_implicit_source_workspace_bytes": (C.c_size_t, [C.c_long]),
             "grrmhd_implicit_source": (C.c_int, [PP, C.c_long] + [_VP] * 11 + [C.c_size_t, _VP]),
+            "grrmhd_implicit_source_workspace_bytes_ex": (C.c_size_t, [C.c_long, C.c_int]),
+            "grrmhd_implicit_source_ex": (C.c_int, [PP, C.c_long] + [_VP] * 10 +
+                                          [C.c_int, C.c_int, C.c_int, _VP, C.c_size_t, _VP]),
+            "grrmhd_autotune_implicit_source": (C.c_int, [PP, C.c_long] + [_VP] * 11 +
+                                                [C.c_size_t, _VP, C.POINTER(Tuning)]),
         }
         for name, (res, args) in sigs.items():
             f = getattr(L, name)
@@ -213,18 +225,57 @@ class Grid:
         return P, U
 
 
-def implicit_source(pd: dict, U_expl, P_guess, dt_cell, chi_abs, chi_es):
-    """Batched implicit 4-force solve of independent flat-space cells."""
+def _batch_out(U_expl, P_guess):
     n = U_expl.shape[1]
     P = P_guess.clone()
     U = U_expl.clone()
     it = torch.zeros(n, dtype=torch.int32, device=U.device)
     st = torch.zeros(n, dtype=torch.int32, device=U.device)
     err = torch.zeros(n, dtype=torch.float64, device=U.device)
+    return n, P, U, it, st, err
+
+
+def batch_workspace(n: int, mode: int = PER_CELL):
+    """Device workspace of the batched solve, 256-byte aligned."""
+    wsb = lib().grrmhd_implicit_source_workspace_bytes_ex(n, mode)
+    raw = torch.empty(wsb + 256, dtype=torch.uint8, device="cuda")
+    off = (-raw.data_ptr()) % 256
+    return raw[off:off + wsb], wsb
+
+
+def implicit_source(pd: dict, U_expl, P_guess, dt_cell, chi_abs, chi_es):
+    """Batched implicit 4-force solve of independent flat-space cells."""
+    n, P, U, it, st, err = _batch_out(U_expl, P_guess)
     p = params(pd)
-    wsb = lib().grrmhd_implicit_source_workspace_bytes(n)
-    ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device=U.device)
+    ws, wsb = batch_workspace(n)
     _check(lib().grrmhd_implicit_source(C.byref(p), n, _ptr(U_expl), _ptr(P_guess), _ptr(dt_cell),
                                         _ptr(chi_abs), _ptr(chi_es), _ptr(P), _ptr(U), _ptr(it),
                                         _ptr(st), _ptr(err), _ptr(ws), wsb, _stream()))
     return P, U, it, st, err
+
+
+def implicit_source_ex(pd: dict, U_expl, P_guess, dt_cell, chi_abs, chi_es, mode=PERSISTENT,
+                       block=256, waves_per_cu=8, out=None, ws=None):
+    """Batched solve in an explicit execution form (per cell, one launch per
+    Newton trip, or persistent with the given block and waves per CU)."""
+    n, P, U, it, st, err = _batch_out(U_expl, P_guess) if out is None else out
+    p = params(pd)
+    ws, wsb = batch_workspace(n, mode) if ws is None else ws
+    _check(lib().grrmhd_implicit_source_ex(C.byref(p), n, _ptr(U_expl), _ptr(P_guess),
+                                           _ptr(dt_cell), _ptr(chi_abs), _ptr(chi_es), _ptr(P),
+                                           _ptr(U), _ptr(it), _ptr(st), _ptr(err), mode, block,
+                                           waves_per_cu, _ptr(ws), wsb, _stream()))
+    return P, U, it, st, err
+
+
+def autotune_implicit_source(pd: dict, U_expl, P_guess, dt_cell, chi_abs, chi_es):
+    """Times the execution forms on these inputs; returns (Tuning, outputs)."""
+    n, P, U, it, st, err = _batch_out(U_expl, P_guess)
+    p = params(pd)
+    ws, wsb = batch_workspace(n, PERSISTENT)
+    t = Tuning()
+    _check(lib().grrmhd_autotune_implicit_source(C.byref(p), n, _ptr(U_expl), _ptr(P_guess),
+                                                 _ptr(dt_cell), _ptr(chi_abs), _ptr(chi_es),
+                                                 _ptr(P), _ptr(U), _ptr(it), _ptr(st), _ptr(err),
+                                                 _ptr(ws), wsb, _stream(), C.byref(t)))
+    return t, (P, U, it, st, err)

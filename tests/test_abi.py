@@ -66,3 +66,28 @@ def test_invalid_parameters_are_rejected_before_any_device_work(L):
     p = G.params(I.default_params())
     assert L.grrmhd_implicit_source(C.byref(p), 0, *([None] * 11), 0, None) == 0
     assert L.grrmhd_step(None, *([None] * 5), 0, None, None, None, 0) == -1
+    # execution forms: bad mode, block and workspace are refused on the host
+    ex = L.grrmhd_implicit_source_ex
+    args = [C.c_void_p(256)] * 10
+    assert ex(C.byref(p), 10, *args, 7, 64, 4, C.c_void_p(256), 1 << 20, None) == -1
+    assert b"mode" in L.grrmhd_last_error()
+    assert ex(C.byref(p), 10, *args, G.PERSISTENT, 64, 4, C.c_void_p(256), 16, None) == -1
+    assert b"workspace" in L.grrmhd_last_error()
+    assert ex(C.byref(p), 10, *args, G.PERSISTENT, 64, 4, C.c_void_p(260), 1 << 20, None) == -1
+    assert ex(C.byref(p), 0, *([None] * 10), G.PERSISTENT, 64, 4, None, 0, None) == 0
+    t = G.Tuning()
+    assert L.grrmhd_autotune_implicit_source(C.byref(p), 0, *([None] * 11), 0, None,
+                                              C.byref(t)) == -1
+
+
+def test_batch_workspace_sizes(L):
+    from paper_1312_6127_amd import grrmhd as G
+
+    f = L.grrmhd_implicit_source_workspace_bytes_ex
+    assert f(0, G.PER_CELL) == 0
+    for n in (1, 63, 64, 1000, 1 << 24):
+        a, b, c = f(n, G.PER_CELL), f(n, G.PERSISTENT), f(n, G.PER_ITERATION)
+        assert a == b == L.grrmhd_implicit_source_workspace_bytes(n)
+        assert a >= 256 + 4 * n and a % 256 == 0
+        # two queues, 47 doubles and 8 ints of lane state per cell
+        assert c >= a + 8 * n + 47 * 8 * n + 8 * 4 * n

@@ -218,12 +218,18 @@ def test_implicit_batch(G, orc):
     # per cell, conserved quantities against the cell's own energy scale
     scale = np.abs(Ur[1]) + np.abs(Ur[8]) + np.abs(Ur[2:5]).sum(0) + np.abs(Ur[9:12]).sum(0)
     d = np.abs(Ug - Ur)[1:12, good].max(axis=0) / scale[good]
-    assert d.max() < 5e-11, d.max()
-    # primitives per cell: Ebar in radiation-sub-dominant cells with
-    # dt kappa up to 1e6 is conditioned by the exchange, hence the looser bound
-    for q, tol in ((0, 1e-10), (1, 1e-10), (8, 1e-9)):
-        rel = np.abs(Pg[q, good] - Pr[q, good]) / np.abs(Pr[q, good])
-        assert np.quantile(rel, 0.99) < tol, (q, np.quantile(rel, 0.99))
+    assert d.max() < 1e-12, d.max()
+    # primitives per cell.  Where the two sides accept different methods
+    # (both within tolerance) the fluid-frame energies agree against the
+    # cell's total fluid-frame energy u_g + Ebar (the exchange conserves it),
+    # not against Ebar alone, which is ill-conditioned in radiation-sub-
+    # dominant cells; the radiation frame velocity is covered by R^t_i above.
+    eng = np.abs(Pr[1, good]) + np.abs(Pr[8, good])
+    assert (np.abs(Pg[0, good] - Pr[0, good]) / Pr[0, good]).max() < 1e-12
+    for q in (1, 8):
+        assert (np.abs(Pg[q, good] - Pr[q, good]) / eng).max() < 1e-10, q
+    gsc = 1.0 + np.abs(Pr[2:5, good]).sum(0)
+    assert (np.abs(Pg[2:5, good] - Pr[2:5, good]).max(0) / gsc).max() < 1e-12
 
 
 def test_full_size_disk_step(G, orc):
@@ -243,3 +249,57 @@ def test_full_size_disk_step(G, orc):
     say("  full-size field errors P", eP, "U", eU)
     assert eP.max() < 1e-11 and eU.max() < 1e-11
     g.close()
+
+
+def _batch_cons(orc, pd, P):
+    """Explicit state of a batch: the primitives' conserved form with the
+    radiation energy raised 30% and the gas energy lowered to match."""
+    g0 = orc.geom(pd, 0.0, 0.0)
+    U = np.stack([orc.p2u(pd, g0, P[:, c]) for c in range(P.shape[1])], axis=1)
+    Ui = U.copy()
+    Ui[8] *= 1.3
+    Ui[1] -= 0.3 * U[8]
+    return Ui
+
+
+FORMS = {"per_iteration": (1, 64, 0), "persistent64": (2, 64, 8), "persistent256": (2, 256, 16)}
+
+
+@pytest.mark.parametrize("form", sorted(FORMS))
+def test_implicit_batch_forms_identical(G, orc, form):
+    """The per-iteration and persistent forms take the same decisions per
+    cell as the per-cell form: identical bits in every output."""
+    say("case batch forms", form)
+    n = 5003
+    pd, P, dt, ca, ce = I.implicit_batch(n, seed=6)
+    args = [dev(_batch_cons(orc, pd, P)), dev(P), dev(dt), dev(ca), dev(ce)]
+    ref = [host(x) for x in G.implicit_source(pd, *args)]
+    mode, block, wpc = FORMS[form]
+    got = [host(x) for x in G.implicit_source_ex(pd, *args, mode, block, wpc)]
+    for a, b in zip(got, ref):
+        assert np.array_equal(a.view(np.uint8), b.view(np.uint8))
+
+
+def test_implicit_batch_autotune_and_reuse(G, orc):
+    """The autotuner returns one of its candidates with outputs equal to the
+    per-cell form's; the chosen form then reproduces the per-cell results on
+    a smaller batch with the same workspace."""
+    say("case batch autotune")
+    n = 20000
+    pd, P, dt, ca, ce = I.implicit_batch(n, seed=8)
+    Ui = _batch_cons(orc, pd, P)
+    args = [dev(Ui), dev(P), dev(dt), dev(ca), dev(ce)]
+    t, outs = G.autotune_implicit_source(pd, *args)
+    say("  tuned", t.mode, t.block, t.waves_per_cu, t.ms)
+    assert t.mode in (G.PER_CELL, G.PERSISTENT) and t.ms > 0
+    ref = [host(x) for x in G.implicit_source(pd, *args)]
+    for a, b in zip([host(x) for x in outs], ref):
+        assert np.array_equal(a.view(np.uint8), b.view(np.uint8))
+    ws = G.batch_workspace(n, t.mode)
+    m = n // 3
+    args = [dev(Ui[:, :m]), dev(P[:, :m]), dev(dt[:m]), dev(ca[:m]), dev(ce[:m])]
+    got = [host(x) for x in G.implicit_source_ex(pd, *args, t.mode, t.block, max(t.waves_per_cu, 1),
+                                                  ws=ws)]
+    ref2 = [host(x) for x in G.implicit_source(pd, *args)]
+    for a, b in zip(got, ref2):
+        assert np.array_equal(a.view(np.uint8), b.view(np.uint8))
