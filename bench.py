@@ -20,11 +20,23 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# FP64 instructions per PMHD/URAD Newton iteration and per cell of the
-# implicit kernel, from a rocprofv3 counter run (see the profiles folder);
-# used to turn the live launch time into achieved FP64 throughput.
-FP64_PEAK_TFLOPS = 78.6
-HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6      # MI355X FP64 vector peak
+HBM_PEAK_GBS = 8000.0        # MI355X HBM3E peak
+# Algorithmic state bytes of one zone-cycle of the FP64 step: stage 1 reads
+# P^n, U^n and writes U^(1), P^(1); stages 2 and 3 also read U^n (12 doubles
+# each array): (4 + 5 + 5) x 96 B.
+STEP_BYTES_PER_ZONE = 1344
+
+# Counter figures of the implicit kernel on this workload, from rocprofv3
+# --pmc runs of this script (profiles/k_implicit_disk128x64x32_counters.md):
+# FP64 flops per lane slot of a Newton trip (64 x (ADD + MUL + TRANS +
+# 2 FMA) wave instructions over the lane slots), and HBM bytes per launch
+# (FETCH_SIZE x 2 + WRITE_SIZE x 1, the scales from a copy of known size).
+# They hold for the kernel sources whose digest is KERNEL_DIGEST; otherwise
+# traffic is reported as null and the flop figure as stale.
+FLOPS_PER_TRIP = 3009.0
+HBM_BYTES_PER_LAUNCH = 121.7e6
+KERNEL_DIGEST = "310e16509b82f1b2"
 
 
 def parse():
@@ -43,6 +55,18 @@ def parse():
     ap.add_argument("--batch-only", action="store_true",
                     help="time only the batched implicit solve")
     return ap.parse_args()
+
+
+def kernel_digest():
+    """sha256 over the HIP sources of the implicit kernel."""
+    import hashlib
+
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_1312_6127_amd", "csrc")
+    for f in ("dual.h", "common.h", "physics.h", "invert.h", "implicit.h", "kernels.h"):
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def _factor3(n):
@@ -85,22 +109,26 @@ def batch_inputs(G, I, torch, dev, n, seed=11):
 
 
 def bench_batch(G, I, torch, dev, n, reps=3):
-    """Cell-solves/s of the batched implicit solve in each execution form."""
+    """Cell-solves/s of the batched implicit solve in each execution form,
+    with the active-lane fraction of the first PMHD attempts."""
     pd, args = batch_inputs(G, I, torch, dev, n)
     stream = torch.cuda.current_stream()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
-    tune, outs = G.autotune_implicit_source(pd, *args)
+    tune, allt, outs = G.autotune_implicit_source(pd, *args)
     st = outs[3].cpu().numpy()
     its = outs[2].cpu().numpy()
     res = {"cells": n, "tol_pmhd": pd["tol_pmhd"],
            "failed_frac": float(((st & G.ST_FAIL) != 0).mean()),
            "urad_frac": float(((st & G.ST_URAD) != 0).mean()),
            "mean_iters": float(its.mean()), "max_iters": int(its.max()),
-           "autotuned": {"mode": ["per_cell", "per_iteration", "persistent"][tune.mode],
-                         "block": tune.block, "waves_per_cu": tune.waves_per_cu}, "forms": {}}
-    forms = [("per_cell", G.PER_CELL, 64, 0), ("per_iteration", G.PER_ITERATION, 64, 0),
-             ("persistent_tuned", G.PERSISTENT, tune.block, max(tune.waves_per_cu, 1))]
+           "autotune": [{"form": G.FORM_NAMES[a.mode], "block": a.block,
+                         "waves_per_cu": a.waves_per_cu, "ms": a.ms} for a in allt],
+           "autotuned": {"form": G.FORM_NAMES[tune.mode], "block": tune.block,
+                         "waves_per_cu": tune.waves_per_cu}, "forms": {}}
+    pers = min((a for a in allt if a.mode == G.PERSISTENT), key=lambda a: a.ms)
+    forms = [("per_cell", G.PER_CELL, 64, 1), ("per_iteration", G.PER_ITERATION, 64, 1),
+             ("persistent", G.PERSISTENT, pers.block, pers.waves_per_cu)]
     for name, mode, block, wpc in forms:
         ws = G.batch_workspace(n, mode)
         out = G._batch_out(args[0], args[1])
@@ -111,9 +139,13 @@ def bench_batch(G, I, torch, dev, n, reps=3):
         e1.record(stream)
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / reps
+        trips, slots, ncas = G.batch_stats(ws)
         same = all(torch.equal(a, b) for a, b in zip(out[1:], outs))
-        res["forms"][name] = {"ms": ms, "cell_solves_per_s": n / (ms * 1e-3),
-                              "block": block, "waves_per_cu": wpc, "identical_to_tuned_run": same}
+        res["forms"][name] = {"ms": ms, "cell_solves_per_s": n / (ms * 1e-3), "block": block,
+                              "waves_per_cu": wpc if mode == G.PERSISTENT else None,
+                              "first_attempt_trips": trips, "lane_slots": slots,
+                              "active_lane_frac": trips / max(slots, 1), "cascade_cells": ncas,
+                              "identical_results": same}
         del ws, out
         print(f"batch form {name}: {ms:.3f} ms", file=sys.stderr, flush=True)
     return res
@@ -159,11 +191,13 @@ def main():
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
+    g.time_implicit(True)
     e0.record(stream)
     for _ in range(args.steps):
         g.step(Pt, Ut, cat, cet, dt, status=st, iters=it)
     e1.record(stream)
     torch.cuda.synchronize()
+    g.time_implicit(False)
     ms = e0.elapsed_time(e1)
     ms_step = ms / args.steps
     zones = n[0] * n[1] * n[2]
@@ -174,34 +208,27 @@ def main():
     itv = it.cpu().numpy().reshape(na[::-1])[interior]
     nfail = int(((stv & G.ST_FAIL) != 0).sum())
 
-    # dominant kernel: the implicit solve of stage 1 on the current state,
-    # launched alone through the C ABI and timed with events on its stream
-    Pb = g.apply_bc(Pt.clone())
-    F, emf, vch = g.fluxes(Pb, cat, cet)
-    dts = g.timestep(vch)
-    Ue = g.explicit_update(1.0, 0.0, 1.0, dts, Pb, Ut, Ut, F, emf)
-    reps = 5
-    k0 = torch.cuda.Event(enable_timing=True)
-    k1 = torch.cuda.Event(enable_timing=True)
-    g.implicit(Ue, Pb, 1.0, dts, cat, cet)
-    torch.cuda.synchronize()
-    k0.record(stream)
-    for _ in range(reps):
-        res = g.implicit(Ue, Pb, 1.0, dts, cat, cet)
-    k1.record(stream)
-    torch.cuda.synchronize()
-    imp_ms = k0.elapsed_time(k1) / reps
-    imp_iters = res[2].cpu().numpy().reshape(na[::-1])[interior]
-    # per-launch algorithmic FP64 flops: Newton iterations of the launch times
-    # the flops one iteration costs (see DESIGN: per-iteration count)
-    flops_per_iter = float(os.environ.get("GRRMHD_FLOPS_PER_ITER", "0")) or None
+    # dominant kernel: the implicit kernel of each stage, timed with HIP events
+    # on its stream inside the timed region
+    imp_total_ms, imp_launches = g.implicit_time()
+    trips, slots, _ = g.implicit_stats()
+    imp_ms = imp_total_ms / max(imp_launches, 1)
+    fresh = KERNEL_DIGEST is not None and KERNEL_DIGEST == kernel_digest()
     roof = {"kernel": "k_implicit", "bound": "alu", "unit": "TFLOP/s", "peak": FP64_PEAK_TFLOPS,
-            "avg_launch_ms": imp_ms, "newton_iters_per_launch": int(imp_iters.sum()),
+            "avg_launch_ms": imp_ms, "launches": imp_launches,
+            "newton_trips_per_launch": trips / max(imp_launches, 1),
+            "lane_slots_per_launch": slots / max(imp_launches, 1),
+            "active_lane_frac": trips / max(slots, 1),
+            "flops_per_trip": FLOPS_PER_TRIP, "counters_current": fresh,
             "achieved": None, "frac": None, "traffic": None}
-    if flops_per_iter:
-        ach = flops_per_iter * imp_iters.sum() / (imp_ms * 1e-3) / 1e12
+    if FLOPS_PER_TRIP:
+        ach = FLOPS_PER_TRIP * trips / (imp_total_ms * 1e-3) / 1e12
         roof["achieved"] = ach
         roof["frac"] = ach / FP64_PEAK_TFLOPS
+        roof["issued_frac"] = FLOPS_PER_TRIP * slots / (imp_total_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS
+    if fresh and HBM_BYTES_PER_LAUNCH:
+        roof["traffic"] = HBM_BYTES_PER_LAUNCH
+        roof["traffic_GBs"] = HBM_BYTES_PER_LAUNCH / (imp_ms * 1e-3) / 1e9
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -236,6 +263,9 @@ def main():
                                "FP64 RK3-IMEX step, LAXF, MC, flux-CT, implicit G^mu",
                    "grid": list(n), "precision": "fp64", "parity_vs_oracle": "1e-11 per field (tests)"},
         "implicit": {"mean_newton_iters_per_cell_step": float(itv.mean()), "failed_cells": nfail},
+        "step_hbm": {"algorithmic_bytes_per_zone_cycle": STEP_BYTES_PER_ZONE,
+                     "achieved_GBs": value * STEP_BYTES_PER_ZONE / 1e9,
+                     "frac": value * STEP_BYTES_PER_ZONE / 1e9 / HBM_PEAK_GBS},
         "roofline": roof,
         "cpu_baseline": cpu,
     }

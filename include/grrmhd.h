@@ -189,8 +189,9 @@ int grrmhd_step(grrmhd_grid *g, double *P, double *U, const double *chi_abs,
  * Sec. 4.10.  Arrays [12][n] (U_expl, P_guess, P_out, U_out) and [n]
  * (dt_cell, chi_abs, chi_es, iters, status, err; the last three nullable),
  * device memory; n < 2^31.  workspace: device buffer of at least
- * grrmhd_implicit_source_workspace_bytes(n) bytes (work list of cells that
- * need the full cascade).  Same algorithm as grrmhd_implicit_grid. */
+ * grrmhd_implicit_source_workspace_bytes(n) bytes, 256-byte aligned (work
+ * list of the cells that need the full cascade, with the result of their
+ * first attempt; lane statistics).  Same algorithm as grrmhd_implicit_grid. */
 size_t grrmhd_implicit_source_workspace_bytes(long n);
 int grrmhd_implicit_source(const grrmhd_params *p, long n, const double *U_expl,
                            const double *P_guess, const double *dt_cell, const double *chi_abs,
@@ -198,8 +199,9 @@ int grrmhd_implicit_source(const grrmhd_params *p, long n, const double *U_expl,
                            int *status, double *err, void *workspace, size_t ws_bytes,
                            void *hip_stream);
 
-/* Batched implicit solve with an explicit execution form (SURVEY growth
- * direction: uneven Newton counts).  mode:
+/* Batched implicit solve with an explicit execution form, for batches whose
+ * Newton counts are very uneven between cells (optically thin against thick
+ * cells, Sec. 4.10).  mode:
  *   GRRMHD_IMPLICIT_PER_CELL       one thread per cell (as grrmhd_implicit_source);
  *   GRRMHD_IMPLICIT_PER_ITERATION  one launch per Newton trip, lane state in
  *                                  HBM, still-active cells compacted into the
@@ -209,7 +211,9 @@ int grrmhd_implicit_source(const grrmhd_params *p, long n, const double *U_expl,
  *                                  each lane takes the next cell from a queue
  *                                  whenever its cell converges.
  * All forms give identical results (same decisions per cell).  workspace:
- * grrmhd_implicit_source_workspace_bytes_ex(n, mode) bytes, 256-byte aligned. */
+ * grrmhd_implicit_source_workspace_bytes_ex(n, mode) bytes, 256-byte aligned;
+ * EINVAL for a bad mode, block or waves_per_cu, a small or misaligned
+ * workspace, or n > 2^30 in the persistent form. */
 enum { GRRMHD_IMPLICIT_PER_CELL = 0, GRRMHD_IMPLICIT_PER_ITERATION = 1, GRRMHD_IMPLICIT_PERSISTENT = 2 };
 size_t grrmhd_implicit_source_workspace_bytes_ex(long n, int mode);
 int grrmhd_implicit_source_ex(const grrmhd_params *p, long n, const double *U_expl,
@@ -218,11 +222,14 @@ int grrmhd_implicit_source_ex(const grrmhd_params *p, long n, const double *U_ex
                               int *status, double *err, int mode, int block, int waves_per_cu,
                               void *workspace, size_t ws_bytes, void *hip_stream);
 
-/* Autotuner: times each candidate (per-cell form; persistent form with
- * block 64/128/256 and 4/8/16 waves per CU) on the caller's inputs with HIP
- * events (each candidate run twice, the second timed) and returns the
- * fastest.  Outputs hold the last candidate's (identical) results.
- * Synchronises the stream.  Workspace as for GRRMHD_IMPLICIT_PERSISTENT. */
+/* Autotuner: times each of GRRMHD_TUNE_CANDIDATES candidates (per-cell
+ * form; one launch per Newton trip; persistent form with block 64/128/256
+ * and 4/8/16 waves per CU) on the caller's inputs with HIP events (each
+ * candidate run twice, the second timed) and returns the fastest in *best;
+ * `all` (nullable) receives up to n_all candidates with their times, in the
+ * order tried.  Outputs hold the last candidate's (identical) results.
+ * Synchronises the stream.  Workspace as for GRRMHD_IMPLICIT_PER_ITERATION. */
+#define GRRMHD_TUNE_CANDIDATES 9
 typedef struct {
   int mode, block, waves_per_cu;
   float ms;
@@ -232,7 +239,28 @@ int grrmhd_autotune_implicit_source(const grrmhd_params *p, long n, const double
                                     const double *chi_abs, const double *chi_es, double *P_out,
                                     double *U_out, int *iters, int *status, double *err,
                                     void *workspace, size_t ws_bytes, void *hip_stream,
-                                    grrmhd_tuning *best);
+                                    grrmhd_tuning *best, grrmhd_tuning *all, int n_all);
+
+/* Lane statistics of implicit solves: out[0] residual evaluations of the
+ * first PMHD attempts (Newton trips over all cells), out[1] lane slots the
+ * wavefronts spent on them (64 per wavefront trip), out[2] cells the last
+ * launch sent to the rest of the cascade.  out[0]/out[1] is the active-lane
+ * fraction.  A grid's out[0..1] accumulate over its implicit launches since
+ * its creation or the last grrmhd_time_implicit(g, 1); a batch's cover the
+ * last solve that used the workspace.  Synchronises the stream (the grid's,
+ * or hip_stream). */
+int grrmhd_implicit_stats(grrmhd_grid *g, unsigned long long out[3]);
+int grrmhd_implicit_source_stats(const void *workspace, unsigned long long out[3],
+                                 void *hip_stream);
+
+/* HIP-event timing of the grid's implicit kernel (the first-attempt kernel
+ * of every implicit launch, grrmhd_step's three included).  on != 0 clears
+ * the record and the grid's lane statistics, then brackets the next
+ * launches (up to 256) with events on the grid's stream; on == 0 stops.
+ * grrmhd_implicit_time synchronises the stream and returns the summed
+ * duration and the number of timed launches. */
+int grrmhd_time_implicit(grrmhd_grid *g, int on);
+int grrmhd_implicit_time(grrmhd_grid *g, double *total_ms, int *launches);
 
 #ifdef __cplusplus
 }

@@ -15,11 +15,31 @@ struct grrmhd_grid {
   Ctx C;
   int device;
   hipStream_t stream;
-  double* geo;          // one allocation: centre table, x1-face table, x2-face table
+  double* geo;          // one allocation: centre table, x1-face table, x2-face table,
+                        // then the dt slot, the implicit bookkeeping and work list
   unsigned long long* dtslot;
-  int* counter;         // work-list length of the implicit cascade
-  int* list;            // work list: interior indices needing the full cascade
+  Work W;               // implicit cascade list (interior indices), records, stats
+  // optional HIP-event timing of the implicit kernel's launches
+  static const int TCAP = 256;
+  int timing = 0, nt = 0;
+  hipEvent_t* ev = nullptr;   // 2 * TCAP events, created on first use
 };
+
+static size_t round256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Cascade list of up to cap cells with the first attempts' records, laid out
+// from `base` (256-byte aligned); returns the bytes used.
+static size_t cascade_bytes(size_t cap) {
+  return round256(sizeof(int) * cap) + round256(sizeof(double) * 13 * cap) +
+         round256(sizeof(int) * 3 * cap);
+}
+
+static void cascade_layout(char* base, size_t cap, Work& W) {
+  W.list = (int*)base;
+  W.rec.d = (double*)(base + round256(sizeof(int) * cap));
+  W.rec.i = (int*)(base + round256(sizeof(int) * cap) + round256(sizeof(double) * 13 * cap));
+  W.rec.cap = (long)cap;
+}
 
 static thread_local std::string g_err;
 
@@ -158,19 +178,23 @@ extern "C" int grrmhd_init_grid(const grrmhd_params* p, int device, void* hip_st
   const size_t tab = (size_t)g->C.npos;
   const size_t nd = tab * (GE_NCENTER + 2 * GE_NFACE);
   const size_t nint = (size_t)g->C.n[0] * g->C.n[1] * g->C.n[2];
-  hipError_t e = hipMalloc(&g->geo, nd * sizeof(double) + 256 + nint * sizeof(int));
+  // [nd doubles][256 B: dt slot @0, list length @128, stats @192][cascade]
+  hipError_t e = hipMalloc(&g->geo, nd * sizeof(double) + 256 + cascade_bytes(nint));
   if (e != hipSuccess) {
     delete g;
     return fail(GRRMHD_ENOMEM, std::string("geometry allocation: ") + hipGetErrorString(e));
   }
-  g->dtslot = (unsigned long long*)(g->geo + nd);
-  g->counter = (int*)(g->geo + nd + 16);
-  g->list = (int*)(g->geo + nd + 32);
+  char* tail = (char*)(g->geo + nd);
+  g->dtslot = (unsigned long long*)tail;
+  g->W.counter = (int*)(tail + 128);
+  g->W.stats = (unsigned long long*)(tail + 192);
+  cascade_layout(tail + 256, nint, g->W);
   g->C.geo_c = g->geo;
   g->C.geo_f1 = g->geo + tab * GE_NCENTER;
   g->C.geo_f2 = g->geo + tab * (GE_NCENTER + GE_NFACE);
   hipLaunchKernelGGL(k_geometry, dim3(nblocks(g->C.npos, 256)), dim3(256), 0, g->stream, g->C,
                      p->a, p->R0, g->geo, (double*)g->C.geo_f1, (double*)g->C.geo_f2);
+  hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, g->stream, (int*)g->W.stats, 4);
   e = hipGetLastError();
   if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
   if (e != hipSuccess) {
@@ -186,6 +210,10 @@ extern "C" int grrmhd_free_grid(grrmhd_grid* g) {
   if (!g) return 0;
   HIPCHK(hipSetDevice(g->device));
   HIPCHK(hipStreamSynchronize(g->stream));
+  if (g->ev) {
+    for (int i = 0; i < 2 * grrmhd_grid::TCAP; i++) (void)hipEventDestroy(g->ev[i]);
+    delete[] g->ev;
+  }
   HIPCHK(hipFree(g->geo));
   delete g;
   return 0;
@@ -322,14 +350,20 @@ static int launch_implicit(grrmhd_grid* g, const double* Ue, const double* Pg, d
                            const double* dt_dev, const double* ca, const double* ce, double* P,
                            double* U, int* it, int* st, double* err) {
   const long n = n_interior(g->C);
-  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, g->stream, g->counter);
+  // list length (the lane statistics accumulate over launches)
+  hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, g->stream, g->W.counter, 1);
   LAUNCHCHK();
+  const bool timed = g->timing && g->nt < grrmhd_grid::TCAP;
+  if (timed) HIPCHK(hipEventRecord(g->ev[2 * g->nt], g->stream));
   hipLaunchKernelGGL(k_implicit, dim3(nblocks(n, 64)), dim3(64), 0, g->stream, g->C, Ue, Pg,
-                     scale, dt_dev, ca, ce, P, U, it, st, err, g->counter, g->list);
+                     scale, dt_dev, ca, ce, P, U, it, st, err, g->W);
   LAUNCHCHK();
+  if (timed) {
+    HIPCHK(hipEventRecord(g->ev[2 * g->nt + 1], g->stream));
+    g->nt++;
+  }
   hipLaunchKernelGGL(k_implicit_list, dim3(list_blocks(n)), dim3(64), 0, g->stream, g->C, Ue, Pg,
-                     scale, dt_dev, ca, ce, P, U, it, st, err, (const int*)g->counter,
-                     (const int*)g->list);
+                     scale, dt_dev, ca, ce, P, U, it, st, err, g->W);
   LAUNCHCHK();
   return 0;
 }
@@ -464,14 +498,12 @@ extern "C" int grrmhd_step(grrmhd_grid* g, double* P, double* U, const double* c
   return 0;
 }
 
-// Workspace of the batched solve: [0, 256) counters (list length, queue
-// cursor, two queue lengths), then the cascade work list, and for the
-// per-iteration form two queues and the lane state.
-static size_t round256(size_t b) { return (b + 255) & ~(size_t)255; }
-
+// Workspace of the batched solve: [0, 256) counters (list length @0, queue
+// cursor @4, two queue lengths @8, stats @64), then the cascade list and
+// records, and for the per-iteration form two queues and the lane state.
 extern "C" size_t grrmhd_implicit_source_workspace_bytes_ex(long n, int mode) {
   if (n <= 0) return 0;
-  size_t b = 256 + round256(sizeof(int) * (size_t)n);
+  size_t b = 256 + cascade_bytes((size_t)n);
   if (mode == GRRMHD_IMPLICIT_PER_ITERATION)
     b += 2 * round256(sizeof(int) * (size_t)n) + round256(sizeof(double) * LS_ND * (size_t)n) +
          round256(sizeof(int) * LI_NI * (size_t)n);
@@ -509,36 +541,40 @@ static int launch_batch(const Ctx& C, long n, const double* U_expl, const double
                         double* P_out, double* U_out, int* iters, int* status, double* err,
                         int mode, int block, int waves_per_cu, void* workspace, hipStream_t s) {
   char* base = (char*)workspace;
-  int* counter = (int*)base;          // cascade list length
-  int* next = counter + 1;            // persistent queue cursor
-  int* qc = counter + 2;              // per-iteration queue lengths (2)
-  int* list = (int*)(base + 256);
-  hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, s, counter, 4);
+  Work W;
+  W.counter = (int*)base;
+  int* next = W.counter + 1;          // persistent queue cursor
+  int* qc = W.counter + 2;            // per-iteration queue lengths (2)
+  W.stats = (unsigned long long*)(base + 64);
+  cascade_layout(base + 256, (size_t)n, W);
+  char* extra = base + 256 + cascade_bytes((size_t)n);
+  if (mode == GRRMHD_IMPLICIT_PERSISTENT) {
+    if (block != 64 && block != 128 && block != 256) return fail(GRRMHD_EINVAL, "block must be 64, 128 or 256");
+    if (waves_per_cu < 1 || waves_per_cu > 64) return fail(GRRMHD_EINVAL, "waves_per_cu out of [1, 64]");
+  }
+  hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, s, W.counter, 20);
   LAUNCHCHK();
   if (mode == GRRMHD_IMPLICIT_PER_CELL) {
     hipLaunchKernelGGL(k_implicit_batch, dim3(nblocks(n, 64)), dim3(64), 0, s, C, n, U_expl, P_guess,
-                       dt_cell, chi_abs, chi_es, P_out, U_out, iters, status, err, counter, list);
+                       dt_cell, chi_abs, chi_es, P_out, U_out, iters, status, err, W);
     LAUNCHCHK();
   } else if (mode == GRRMHD_IMPLICIT_PERSISTENT) {
-    if (block != 64 && block != 128 && block != 256) return fail(GRRMHD_EINVAL, "block must be 64, 128 or 256");
-    if (waves_per_cu < 1 || waves_per_cu > 64) return fail(GRRMHD_EINVAL, "waves_per_cu out of [1, 64]");
     int dev = 0, ncu = 0;
     HIPCHK(hipGetDevice(&dev));
     HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
     const long waves = (long)ncu * waves_per_cu;
     const long blocks = std::max<long>(1, std::min<long>(waves * 64 / block, nblocks(n, block)));
     hipLaunchKernelGGL(k_implicit_persist, dim3((unsigned)blocks), dim3(block), 0, s, C, n, U_expl,
-                       P_guess, dt_cell, chi_abs, chi_es, P_out, U_out, iters, status, err, next,
-                       counter, list);
+                       P_guess, dt_cell, chi_abs, chi_es, P_out, U_out, iters, status, err, next, W);
     LAUNCHCHK();
   } else {
     const size_t qb = round256(sizeof(int) * (size_t)n);
-    int* q0 = (int*)(base + 256 + qb);
-    int* q1 = (int*)(base + 256 + 2 * qb);
-    double* sd = (double*)(base + 256 + 3 * qb);
-    int* si = (int*)(base + 256 + 3 * qb + round256(sizeof(double) * LS_ND * (size_t)n));
+    int* q0 = (int*)extra;
+    int* q1 = (int*)(extra + qb);
+    double* sd = (double*)(extra + 2 * qb);
+    int* si = (int*)(extra + 2 * qb + round256(sizeof(double) * LS_ND * (size_t)n));
     hipLaunchKernelGGL(k_iter_start, dim3(nblocks(n, 64)), dim3(64), 0, s, C, n, U_expl, P_guess,
-                       dt_cell, chi_abs, chi_es, sd, si, qc, q0, counter, list);
+                       dt_cell, chi_abs, chi_es, sd, si, qc, q0, W);
     LAUNCHCHK();
     // every attempt ends within max_iter trips (+3 round-off trips are inside it)
     for (int t = 0; t <= C.max_iter; t++) {
@@ -550,15 +586,74 @@ static int launch_batch(const Ctx& C, long n, const double* U_expl, const double
       LAUNCHCHK();
       hipLaunchKernelGGL(k_iter_step, dim3(list_blocks(n)), dim3(64), 0, s, C, n, U_expl, dt_cell,
                          chi_abs, chi_es, sd, si, (const int*)cin, (const int*)qin, cout, qout,
-                         P_out, U_out, iters, status, err, counter, list);
+                         P_out, U_out, iters, status, err, W);
       LAUNCHCHK();
     }
   }
   hipLaunchKernelGGL(k_implicit_batch_list, dim3(list_blocks(n)), dim3(64), 0, s, C, n, U_expl,
-                     P_guess, dt_cell, chi_abs, chi_es, P_out, U_out, iters, status, err,
-                     (const int*)counter, (const int*)list);
+                     P_guess, dt_cell, chi_abs, chi_es, P_out, U_out, iters, status, err, W);
   LAUNCHCHK();
   return 0;
+}
+
+// stats[0..1] at `src` and the list length at `cnt` into out[0..2]
+static int read_stats(const unsigned long long* src, const int* cnt, unsigned long long out[3],
+                      hipStream_t s) {
+  unsigned long long st[2];
+  int c = 0;
+  HIPCHK(hipMemcpyAsync(st, src, sizeof(st), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(&c, cnt, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  out[0] = st[0];
+  out[1] = st[1];
+  out[2] = (unsigned long long)c;
+  return 0;
+}
+
+extern "C" int grrmhd_time_implicit(grrmhd_grid* g, int on) {
+  if (!g) return fail(GRRMHD_EINVAL, "grid is NULL");
+  HIPCHK(hipSetDevice(g->device));
+  if (on && !g->ev) {
+    g->ev = new hipEvent_t[2 * grrmhd_grid::TCAP];
+    for (int i = 0; i < 2 * grrmhd_grid::TCAP; i++) HIPCHK(hipEventCreate(&g->ev[i]));
+  }
+  if (on) {
+    g->nt = 0;
+    hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, g->stream, (int*)g->W.stats, 4);
+    LAUNCHCHK();
+  }
+  g->timing = on ? 1 : 0;
+  return 0;
+}
+
+extern "C" int grrmhd_implicit_time(grrmhd_grid* g, double* total_ms, int* launches) {
+  if (!g || !total_ms || !launches) return fail(GRRMHD_EINVAL, "NULL argument");
+  HIPCHK(hipSetDevice(g->device));
+  HIPCHK(hipStreamSynchronize(g->stream));
+  double t = 0.0;
+  for (int i = 0; i < g->nt; i++) {
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, g->ev[2 * i], g->ev[2 * i + 1]));
+    t += ms;
+  }
+  *total_ms = t;
+  *launches = g->nt;
+  return 0;
+}
+
+extern "C" int grrmhd_implicit_stats(grrmhd_grid* g, unsigned long long out[3]) {
+  if (!g || !out) return fail(GRRMHD_EINVAL, "NULL argument");
+  HIPCHK(hipSetDevice(g->device));
+  return read_stats(g->W.stats, g->W.counter, out, g->stream);
+}
+
+extern "C" int grrmhd_implicit_source_stats(const void* workspace, unsigned long long out[3],
+                                            void* hip_stream) {
+  if (!workspace || !out) return fail(GRRMHD_EINVAL, "NULL argument");
+  if (((uintptr_t)workspace) & 255) return fail(GRRMHD_EINVAL, "workspace must be 256-byte aligned");
+  const char* base = (const char*)workspace;
+  return read_stats((const unsigned long long*)(base + 64), (const int*)base, out,
+                    (hipStream_t)hip_stream);
 }
 
 extern "C" int grrmhd_implicit_source_ex(const grrmhd_params* p, long n, const double* U_expl,
@@ -582,23 +677,28 @@ extern "C" int grrmhd_autotune_implicit_source(const grrmhd_params* p, long n,
                                                const double* chi_es, double* P_out,
                                                double* U_out, int* iters, int* status,
                                                double* err, void* workspace, size_t ws_bytes,
-                                               void* hip_stream, grrmhd_tuning* best) {
+                                               void* hip_stream, grrmhd_tuning* best,
+                                               grrmhd_tuning* all, int n_all) {
   if (!best) return fail(GRRMHD_EINVAL, "best is NULL");
   int rc = check_batch_args(p, n, U_expl, P_guess, dt_cell, chi_abs, chi_es, P_out, U_out,
-                            workspace, ws_bytes, GRRMHD_IMPLICIT_PERSISTENT);
+                            workspace, ws_bytes, GRRMHD_IMPLICIT_PER_ITERATION);
   if (rc) return rc;
   if (n == 0) return fail(GRRMHD_EINVAL, "n must be positive");
+  if (n > (1L << 30)) return fail(GRRMHD_EINVAL, "n above 2^30 for the persistent form");
   Ctx C;
   fill_ctx(p, C);
   hipStream_t s = (hipStream_t)hip_stream;
-  const int cands[][3] = {{GRRMHD_IMPLICIT_PER_CELL, 64, 0},  {GRRMHD_IMPLICIT_PERSISTENT, 64, 4},
-                          {GRRMHD_IMPLICIT_PERSISTENT, 64, 8}, {GRRMHD_IMPLICIT_PERSISTENT, 128, 4},
-                          {GRRMHD_IMPLICIT_PERSISTENT, 128, 8}, {GRRMHD_IMPLICIT_PERSISTENT, 256, 4},
-                          {GRRMHD_IMPLICIT_PERSISTENT, 256, 8}, {GRRMHD_IMPLICIT_PERSISTENT, 256, 16}};
+  const int cands[GRRMHD_TUNE_CANDIDATES][3] = {
+      {GRRMHD_IMPLICIT_PER_CELL, 64, 0},    {GRRMHD_IMPLICIT_PER_ITERATION, 64, 0},
+      {GRRMHD_IMPLICIT_PERSISTENT, 64, 4},  {GRRMHD_IMPLICIT_PERSISTENT, 64, 8},
+      {GRRMHD_IMPLICIT_PERSISTENT, 128, 4}, {GRRMHD_IMPLICIT_PERSISTENT, 128, 8},
+      {GRRMHD_IMPLICIT_PERSISTENT, 256, 4}, {GRRMHD_IMPLICIT_PERSISTENT, 256, 8},
+      {GRRMHD_IMPLICIT_PERSISTENT, 256, 16}};
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
   best->ms = 1e30f;
+  int k = 0;
   for (const auto& cd : cands) {
     float tbest = 1e30f;
     for (int rep = 0; rep < 2; rep++) {   // first run warms caches and code objects
@@ -612,6 +712,13 @@ extern "C" int grrmhd_autotune_implicit_source(const grrmhd_params* p, long n,
       HIPCHK(hipEventElapsedTime(&ms, e0, e1));
       if (rep > 0) tbest = ms;
     }
+    if (all && k < n_all) {
+      all[k].mode = cd[0];
+      all[k].block = cd[1];
+      all[k].waves_per_cu = cd[2];
+      all[k].ms = tbest;
+    }
+    k++;
     if (tbest < best->ms) {
       best->ms = tbest;
       best->mode = cd[0];

@@ -527,38 +527,82 @@ DEV void failed_out(const double Ui[12], const double Pg[12], int status, int it
   out.err = INFINITY;
 }
 
+// Result of a cell's first PMHD attempt, kept per cascade-list slot so that
+// the cascade resumes where the first attempt ended: field-major [f][cap],
+// d = P[12], e_T; i = radiation flags, ok, iterations.
+struct RecBuf {
+  double* d;
+  int* i;
+  long cap;
+};
+
+DEV void rec_store(const RecBuf& R, long slot, const Best& b, int iters) {
+#pragma unroll
+  for (int q = 0; q < 12; q++) R.d[q * R.cap + slot] = b.P[q];
+  R.d[12 * R.cap + slot] = b.eT;
+  R.i[slot] = b.radflags;
+  R.i[R.cap + slot] = b.ok;
+  R.i[2 * R.cap + slot] = iters;
+}
+
+DEV void rec_load(const RecBuf& R, long slot, Best& b, int& iters) {
+#pragma unroll
+  for (int k = 0; k < 4; k++) b.x[k] = 0.0;
+#pragma unroll
+  for (int q = 0; q < 12; q++) b.P[q] = R.d[q * R.cap + slot];
+  b.eT = R.d[12 * R.cap + slot];
+  b.radflags = R.i[slot];
+  b.ok = R.i[R.cap + slot];
+  iters = R.i[2 * R.cap + slot];
+}
+
 // Common case: not extreme, first PMHD attempt accepted.  Returns false when
-// the cell needs the full cascade.
+// the cell needs the full cascade; b and iters then hold the first attempt
+// (none when the cell is extreme), trips the residual evaluations it took.
 DEV bool implicit_fast(const Metric& m, const Phys& ph, const Opts& o, const double Ui[12],
                        const double Pg[12], double dt, double chi_abs, double chi_es,
-                       CellOut& out) {
+                       CellOut& out, Best& b, int& iters, bool& extreme, int& trips) {
   Cell c;
   Prep pr;
   prepare(m, ph, Ui, Pg, dt, chi_abs, chi_es, c, pr);
-  if (pr.extreme) return false;
-  const double x0[4] = {pr.Pthin[1], pr.Pthin[2], pr.Pthin[3], pr.Pthin[4]};
-  Best b;
   b.eT = INFINITY;
   b.ok = 0;
-  int iters = 0;
+  iters = 0;
+  trips = 0;
+  extreme = pr.extreme;
+  if (pr.extreme) return false;
+  const double x0[4] = {pr.Pthin[1], pr.Pthin[2], pr.Pthin[3], pr.Pthin[4]};
   newton<M_PMHD>(c, ph, o, x0, pr.Pthin, b, iters);
+  trips = iters + 1;
   if (!(b.ok && b.eT < accept_threshold(o))) return false;
   finalize(c, ph, o, b, M_PMHD, pr.status, iters, Ui, out);
   return true;
 }
 
-// Full cascade for one cell (Sec. 4.10-4.11).
+// Full cascade for one cell (Sec. 4.10-4.11).  With R, a non-extreme cell
+// resumes after its first PMHD attempt, stored at list slot `slot` by the
+// kernel that ran it (that attempt was not accepted, else the cell would not
+// be in the cascade).
 DEV void implicit_cell(const Metric& m, const Phys& ph, const Opts& o, const double Ui[12],
                        const double Pg[12], double dt, double chi_abs, double chi_es,
-                       CellOut& out) {
+                       CellOut& out, const RecBuf* R = nullptr, long slot = 0) {
   Cell c;
   Prep pr;
   prepare(m, ph, Ui, Pg, dt, chi_abs, chi_es, c, pr);
   Best best;
   best.eT = INFINITY;
   best.ok = 0;
-  int bm = -1, iters = 0;
-  for (int k = 0; k < 2; k++) {
+  int bm = -1, iters = 0, k0 = 0;
+  if (R && !pr.extreme) {
+    Best b;
+    rec_load(*R, slot, b, iters);
+    if (b.ok && b.eT < best.eT) {
+      best = b;
+      bm = M_PMHD;
+    }
+    k0 = 1;
+  }
+  for (int k = k0; k < 2; k++) {
     const int method = (k == 0) == pr.extreme ? M_URAD : M_PMHD;
     double x0[4], P0[5];
     const bool prev = (bm >= 0 && best.eT < 1e-4);

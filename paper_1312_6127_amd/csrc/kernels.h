@@ -459,19 +459,51 @@ DEV Opts make_opts(const Ctx& C) {
 }
 
 // Append flagged lanes of a wavefront to a work list: one atomic per
-// wavefront, slots ordered by lane (ballot + popcount prefix).
-DEV void wave_append(bool need, int item, int* counter, int* list) {
+// wavefront, slots ordered by lane (ballot + popcount prefix).  Returns the
+// lane's slot, or -1.
+DEV long wave_append(bool need, int item, int* counter, int* list) {
   const unsigned long long mask = __ballot(need);
-  if (mask == 0ull) return;
+  if (mask == 0ull) return -1;
   const int lane = threadIdx.x & 63;
   const int leader = __ffsll((long long)mask) - 1;
   int base = 0;
   if (lane == leader) base = atomicAdd(counter, __popcll(mask));
   base = __shfl(base, leader, 64);
-  if (need) list[base + __popcll(mask & ((1ull << lane) - 1ull))] = item;
+  if (!need) return -1;
+  const long slot = (long)base + __popcll(mask & ((1ull << lane) - 1ull));
+  list[slot] = item;
+  return slot;
 }
 
-__global__ void k_zero_int(int* p) { *p = 0; }
+// Bookkeeping of one implicit launch: the cascade work list with the first
+// attempts' records, and lane statistics: stats[0] residual evaluations of
+// first PMHD attempts (Newton trips), stats[1] lane slots the wavefronts
+// spent on them (64 per wavefront trip), so stats[0]/stats[1] is the active
+// lane fraction.
+struct Work {
+  int* counter;
+  int* list;
+  unsigned long long* stats;
+  RecBuf rec;
+};
+
+// per-wavefront totals of lanes that each ran `trips` trips in lockstep
+DEV void wave_stats(int trips, unsigned long long* stats) {
+  int s = trips, mx = trips;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    s += __shfl_xor(s, off, 64);
+    mx = ::max(mx, __shfl_xor(mx, off, 64));
+  }
+  if ((threadIdx.x & 63) == 0 && s > 0) {
+    atomicAdd(&stats[0], (unsigned long long)s);
+    atomicAdd(&stats[1], 64ull * (unsigned long long)mx);
+  }
+}
+
+__global__ void k_zero_ints(int* p, int k) {
+  for (int i = threadIdx.x; i < k; i += blockDim.x) p[i] = 0;
+}
 
 DEV void store_out(const CellOut& o, long c, long Nst, double* P, double* U, int* iters,
                    int* status, double* err) {
@@ -485,6 +517,13 @@ DEV void store_out(const CellOut& o, long c, long Nst, double* P, double* U, int
   if (err) err[c] = o.err;
 }
 
+// A cell the fast path did not accept: to the work list, with its first
+// attempt (extreme cells have none).
+DEV void to_cascade(bool need, bool extreme, int item, const Best& b, int iters, const Work& W) {
+  const long slot = wave_append(need, item, W.counter, W.list);
+  if (slot >= 0 && !extreme) rec_store(W.rec, slot, b, iters);
+}
+
 // Common path of the implicit solve at interior cells; cells that need the
 // full cascade go to the work list (index into the interior enumeration).
 __global__ void LBI k_implicit(Ctx C, const double* __restrict__ Uexp, const double* Pguess,
@@ -492,11 +531,12 @@ __global__ void LBI k_implicit(Ctx C, const double* __restrict__ Uexp, const dou
                                   const double* __restrict__ chi_abs,
                                   const double* __restrict__ chi_es, double* P,
                                   double* __restrict__ U, int* __restrict__ iters,
-                                  int* __restrict__ status, double* __restrict__ err,
-                                  int* counter, int* list) {
+                                  int* __restrict__ status, double* __restrict__ err, Work W) {
   const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
   const long nint = (long)C.n[0] * C.n[1] * C.n[2];
-  bool need = false;
+  bool need = false, extreme = false;
+  Best b;
+  int it = 0, trips = 0;
   if (t < nint) {
     const int i = C.ng[0] + t % C.n[0];
     const long t2 = t / C.n[0];
@@ -513,15 +553,17 @@ __global__ void LBI k_implicit(Ctx C, const double* __restrict__ Uexp, const dou
     }
     CellOut o;
     if (implicit_fast(m, make_phys(C), make_opts(C), Ui, Pg, dt_scale * (*dt_dev), chi_abs[c],
-                      chi_es[c], o))
+                      chi_es[c], o, b, it, extreme, trips))
       store_out(o, c, C.Ntot, P, U, iters, status, err);
     else
       need = true;
   }
-  wave_append(need, (int)t, counter, list);
+  wave_stats(trips, W.stats);
+  to_cascade(need, extreme, (int)t, b, it, W);
 }
 
-// Full cascade over the work list; grid-stride over a count kept on the device.
+// Rest of the cascade over the work list; grid-stride over a count kept on
+// the device.
 __global__ void LB(64) k_implicit_list(Ctx C, const double* __restrict__ Uexp,
                                        const double* Pguess, double dt_scale,
                                        const double* __restrict__ dt_dev,
@@ -529,11 +571,11 @@ __global__ void LB(64) k_implicit_list(Ctx C, const double* __restrict__ Uexp,
                                        const double* __restrict__ chi_es, double* P,
                                        double* __restrict__ U, int* __restrict__ iters,
                                        int* __restrict__ status, double* __restrict__ err,
-                                       const int* counter, const int* list) {
-  const int n = *counter;
+                                       Work W) {
+  const int n = *W.counter;
   for (long w = (long)blockIdx.x * blockDim.x + threadIdx.x; w < n;
        w += (long)gridDim.x * blockDim.x) {
-    const long t = list[w];
+    const long t = W.list[w];
     const int i = C.ng[0] + t % C.n[0];
     const long t2 = t / C.n[0];
     const int j = C.ng[1] + t2 % C.n[1];
@@ -549,7 +591,7 @@ __global__ void LB(64) k_implicit_list(Ctx C, const double* __restrict__ Uexp,
     }
     CellOut o;
     implicit_cell(m, make_phys(C), make_opts(C), Ui, Pg, dt_scale * (*dt_dev), chi_abs[c],
-                  chi_es[c], o);
+                  chi_es[c], o, &W.rec, w);
     store_out(o, c, C.Ntot, P, U, iters, status, err);
   }
 }
@@ -562,9 +604,11 @@ __global__ void LBI k_implicit_batch(Ctx C, long n, const double* __restrict__ U
                                         const double* __restrict__ chi_es,
                                         double* __restrict__ Po, double* __restrict__ Uo,
                                         int* __restrict__ iters, int* __restrict__ status,
-                                        double* __restrict__ err, int* counter, int* list) {
+                                        double* __restrict__ err, Work W) {
   const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  bool need = false;
+  bool need = false, extreme = false;
+  Best b;
+  int it = 0, trips = 0;
   if (c < n) {
     Metric m;
     flat_metric(m);
@@ -575,12 +619,14 @@ __global__ void LBI k_implicit_batch(Ctx C, long n, const double* __restrict__ U
       Pg[q] = Pg_[q * n + c];
     }
     CellOut o;
-    if (implicit_fast(m, make_phys(C), make_opts(C), Ui, Pg, dtc[c], chi_abs[c], chi_es[c], o))
+    if (implicit_fast(m, make_phys(C), make_opts(C), Ui, Pg, dtc[c], chi_abs[c], chi_es[c], o, b,
+                      it, extreme, trips))
       store_out(o, c, n, Po, Uo, iters, status, err);
     else
       need = true;
   }
-  wave_append(need, (int)c, counter, list);
+  wave_stats(trips, W.stats);
+  to_cascade(need, extreme, (int)c, b, it, W);
 }
 
 __global__ void LB(64) k_implicit_batch_list(Ctx C, long n, const double* __restrict__ Ui_,
@@ -590,12 +636,11 @@ __global__ void LB(64) k_implicit_batch_list(Ctx C, long n, const double* __rest
                                              const double* __restrict__ chi_es,
                                              double* __restrict__ Po, double* __restrict__ Uo,
                                              int* __restrict__ iters, int* __restrict__ status,
-                                             double* __restrict__ err, const int* counter,
-                                             const int* list) {
-  const int cnt = *counter;
+                                             double* __restrict__ err, Work W) {
+  const int cnt = *W.counter;
   for (long w = (long)blockIdx.x * blockDim.x + threadIdx.x; w < cnt;
        w += (long)gridDim.x * blockDim.x) {
-    const long c = list[w];
+    const long c = W.list[w];
     Metric m;
     flat_metric(m);
     double Ui[12], Pg[12];
@@ -605,7 +650,8 @@ __global__ void LB(64) k_implicit_batch_list(Ctx C, long n, const double* __rest
       Pg[q] = Pg_[q * n + c];
     }
     CellOut o;
-    implicit_cell(m, make_phys(C), make_opts(C), Ui, Pg, dtc[c], chi_abs[c], chi_es[c], o);
+    implicit_cell(m, make_phys(C), make_opts(C), Ui, Pg, dtc[c], chi_abs[c], chi_es[c], o, &W.rec,
+                  w);
     store_out(o, c, n, Po, Uo, iters, status, err);
   }
 }
@@ -801,8 +847,7 @@ __global__ void LBP k_implicit_persist(Ctx C, long n, const double* __restrict__
                                        const double* __restrict__ chi_es,
                                        double* __restrict__ Po, double* __restrict__ Uo,
                                        int* __restrict__ iters, int* __restrict__ status,
-                                       double* __restrict__ err, int* next, int* counter,
-                                       int* list) {
+                                       double* __restrict__ err, int* next, Work W) {
   const Phys ph = make_phys(C);
   const Opts o = make_opts(C);
   const double thr = accept_threshold(o);
@@ -813,6 +858,7 @@ __global__ void LBP k_implicit_persist(Ctx C, long n, const double* __restrict__
   double U0 = 0.0, UB[3] = {0.0, 0.0, 0.0};
   long item = -1;
   bool active = false, exhausted = false;
+  unsigned long long useful = 0, slots = 0;
   for (;;) {
     const bool need = !active && !exhausted;
     const long got = wave_fetch(need, next);
@@ -859,6 +905,10 @@ __global__ void LBP k_implicit_persist(Ctx C, long n, const double* __restrict__
         ended = lane_after(ev, xprev, L);
       }
     }
+    const unsigned long long ev_mask = __ballot(doeval);
+    useful += __popcll(ev_mask);
+    slots += ev_mask ? 64ull : 0ull;
+    bool extreme = tolist;
     if (ended) {
       if (L.best.ok && L.best.eT < thr)
         finish_lane(c, ph, o, L, U0, UB, item, n, Po, Uo, iters, status, err);
@@ -866,8 +916,12 @@ __global__ void LBP k_implicit_persist(Ctx C, long n, const double* __restrict__
         tolist = true;
       active = false;
     }
-    wave_append(tolist, (int)item, counter, list);
+    to_cascade(tolist, extreme, (int)item, L.best, L.iters, W);
     if (!__any(active) && __all(exhausted)) break;
+  }
+  if ((threadIdx.x & 63) == 0 && useful) {
+    atomicAdd(&W.stats[0], useful);
+    atomicAdd(&W.stats[1], slots);
   }
 }
 
@@ -931,9 +985,11 @@ __global__ void LB(64) k_iter_start(Ctx C, long n, const double* __restrict__ Ui
                                     const double* __restrict__ Pg_, const double* __restrict__ dtc,
                                     const double* __restrict__ chi_abs,
                                     const double* __restrict__ chi_es, double* sd, int* si,
-                                    int* qcount, int* queue, int* counter, int* list) {
+                                    int* qcount, int* queue, Work W) {
   const long cidx = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  bool act = false, tolist = false;
+  bool act = false, tolist = false, extreme = false;
+  int trips = 0;
+  Lane L;
   if (cidx < n) {
     const Phys ph = make_phys(C);
     Metric m;
@@ -947,22 +1003,24 @@ __global__ void LB(64) k_iter_start(Ctx C, long n, const double* __restrict__ Ui
     Cell c;
     Prep pr;
     prepare(m, ph, Ui, Pg, dtc[cidx], chi_abs[cidx], chi_es[cidx], c, pr);
-    Lane L;
     L.status = pr.status;
     if (pr.extreme) {
       tolist = true;
+      extreme = true;
     } else {
       L.x[0] = pr.Pthin[1]; L.x[1] = pr.Pthin[2]; L.x[2] = pr.Pthin[3]; L.x[3] = pr.Pthin[4];
       Eval ev;
       eval_pmhd(c, ph, L.x, ev, L.J);
       lane_start(ev, L);
+      trips = 1;
       if (ev.ok) act = true;
       else tolist = true;
       lane_save(L, cidx, n, sd, si);
     }
   }
+  wave_stats(trips, W.stats);
   wave_append(act, (int)cidx, qcount, queue);
-  wave_append(tolist, (int)cidx, counter, list);
+  to_cascade(tolist, extreme, (int)cidx, L.best, L.iters, W);
 }
 
 // one Newton trip for every queued cell
@@ -973,7 +1031,7 @@ __global__ void LB(64) k_iter_step(Ctx C, long n, const double* __restrict__ Ui_
                                    const int* qin_count, const int* qin, int* qout_count,
                                    int* qout, double* __restrict__ Po, double* __restrict__ Uo,
                                    int* __restrict__ iters, int* __restrict__ status,
-                                   double* __restrict__ err, int* counter, int* list) {
+                                   double* __restrict__ err, Work W) {
   const int cnt = *qin_count;
   const long stride = (long)gridDim.x * blockDim.x;
   const long rounds = (cnt + stride - 1) / stride;
@@ -981,6 +1039,8 @@ __global__ void LB(64) k_iter_step(Ctx C, long n, const double* __restrict__ Ui_
     const long w = r * stride + (long)blockIdx.x * blockDim.x + threadIdx.x;
     bool keepgoing = false, tolist = false;
     long cidx = -1;
+    int trips = 0;
+    Lane L;
     if (w < cnt) {
       cidx = qin[w];
       const Phys ph = make_phys(C);
@@ -992,11 +1052,11 @@ __global__ void LB(64) k_iter_step(Ctx C, long n, const double* __restrict__ Ui_
       for (int q = 0; q < 12; q++) Ui[q] = Ui_[q * n + cidx];
       Cell c;
       setup_cell(m, Ui, dtc[cidx], chi_abs[cidx], chi_es[cidx], c);
-      Lane L;
       lane_load(L, cidx, n, sd, si);
       double xprev[4] = {L.x[0], L.x[1], L.x[2], L.x[3]};
       bool ended = lane_step(c, o, L);
       if (!ended) {
+        trips = 1;
         Eval ev;
         eval_pmhd(c, ph, L.x, ev, L.J);
         lane_take(ev, L);
@@ -1014,11 +1074,8 @@ __global__ void LB(64) k_iter_step(Ctx C, long n, const double* __restrict__ Ui_
         keepgoing = true;
       }
     }
+    wave_stats(trips, W.stats);
     wave_append(keepgoing, (int)cidx, qout_count, qout);
-    wave_append(tolist, (int)cidx, counter, list);
+    to_cascade(tolist, false, (int)cidx, L.best, L.iters, W);
   }
-}
-
-__global__ void k_zero_ints(int* p, int k) {
-  if (threadIdx.x < k) p[threadIdx.x] = 0;
 }

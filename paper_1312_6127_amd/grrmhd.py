@@ -41,6 +41,8 @@ class Tuning(C.Structure):
 
 
 PER_CELL, PER_ITERATION, PERSISTENT = 0, 1, 2
+TUNE_CANDIDATES = 9
+FORM_NAMES = {PER_CELL: "per_cell", PER_ITERATION: "per_iteration", PERSISTENT: "persistent"}
 
 
 def params(d: dict) -> Params:
@@ -98,7 +100,12 @@ def lib():
             "grrmhd_implicit_source_ex": (C.c_int, [PP, C.c_long] + [_VP] * 10 +
                                           [C.c_int, C.c_int, C.c_int, _VP, C.c_size_t, _VP]),
             "grrmhd_autotune_implicit_source": (C.c_int, [PP, C.c_long] + [_VP] * 11 +
-                                                [C.c_size_t, _VP, C.POINTER(Tuning)]),
+                                                [C.c_size_t, _VP, C.POINTER(Tuning),
+                                                 C.POINTER(Tuning), C.c_int]),
+            "grrmhd_implicit_stats": (C.c_int, [_VP, C.POINTER(C.c_ulonglong)]),
+            "grrmhd_time_implicit": (C.c_int, [_VP, C.c_int]),
+            "grrmhd_implicit_time": (C.c_int, [_VP, C.POINTER(C.c_double), C.POINTER(C.c_int)]),
+            "grrmhd_implicit_source_stats": (C.c_int, [_VP, C.POINTER(C.c_ulonglong), _VP]),
         }
         for name, (res, args) in sigs.items():
             f = getattr(L, name)
@@ -209,6 +216,25 @@ class Grid:
                                           _ptr(st), _ptr(err)))
         return P, U, it, st, err
 
+    def implicit_stats(self):
+        """(Newton trips of first attempts, lane slots, cascade cells) of the
+        last implicit launch on this grid."""
+        out = (C.c_ulonglong * 3)()
+        _check(lib().grrmhd_implicit_stats(self.h, out))
+        return tuple(int(v) for v in out)
+
+    def time_implicit(self, on: bool):
+        """Start (clearing the record) or stop HIP-event timing of the
+        implicit kernel's launches on this grid's stream."""
+        self._sync_stream()
+        _check(lib().grrmhd_time_implicit(self.h, 1 if on else 0))
+
+    def implicit_time(self):
+        """(summed milliseconds, launches) of the timed implicit kernels."""
+        ms, cnt = C.c_double(), C.c_int()
+        _check(lib().grrmhd_implicit_time(self.h, C.byref(ms), C.byref(cnt)))
+        return ms.value, cnt.value
+
     def fixup(self, P, U, status):
         self._sync_stream()
         scratch = torch.zeros((13, self.N), dtype=torch.float64, device=P.device)
@@ -269,13 +295,24 @@ def implicit_source_ex(pd: dict, U_expl, P_guess, dt_cell, chi_abs, chi_es, mode
 
 
 def autotune_implicit_source(pd: dict, U_expl, P_guess, dt_cell, chi_abs, chi_es):
-    """Times the execution forms on these inputs; returns (Tuning, outputs)."""
+    """Times the execution forms on these inputs; returns (best Tuning, list
+    of every candidate's Tuning, outputs)."""
     n, P, U, it, st, err = _batch_out(U_expl, P_guess)
     p = params(pd)
-    ws, wsb = batch_workspace(n, PERSISTENT)
+    ws, wsb = batch_workspace(n, PER_ITERATION)
     t = Tuning()
+    allt = (Tuning * TUNE_CANDIDATES)()
     _check(lib().grrmhd_autotune_implicit_source(C.byref(p), n, _ptr(U_expl), _ptr(P_guess),
                                                  _ptr(dt_cell), _ptr(chi_abs), _ptr(chi_es),
                                                  _ptr(P), _ptr(U), _ptr(it), _ptr(st), _ptr(err),
-                                                 _ptr(ws), wsb, _stream(), C.byref(t)))
-    return t, (P, U, it, st, err)
+                                                 _ptr(ws), wsb, _stream(), C.byref(t), allt,
+                                                 TUNE_CANDIDATES))
+    return t, list(allt), (P, U, it, st, err)
+
+
+def batch_stats(ws):
+    """(Newton trips of first attempts, lane slots, cascade cells) of the
+    last batched solve that used workspace ws (a (tensor, bytes) pair)."""
+    out = (C.c_ulonglong * 3)()
+    _check(lib().grrmhd_implicit_source_stats(_ptr(ws[0]), out, _stream()))
+    return tuple(int(v) for v in out)

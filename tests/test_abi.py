@@ -77,7 +77,10 @@ def test_invalid_parameters_are_rejected_before_any_device_work(L):
     assert ex(C.byref(p), 0, *([None] * 10), G.PERSISTENT, 64, 4, None, 0, None) == 0
     t = G.Tuning()
     assert L.grrmhd_autotune_implicit_source(C.byref(p), 0, *([None] * 11), 0, None,
-                                              C.byref(t)) == -1
+                                              C.byref(t), None, 0) == -1
+    out = (C.c_ulonglong * 3)()
+    assert L.grrmhd_implicit_stats(None, out) == -1
+    assert L.grrmhd_implicit_source_stats(C.c_void_p(260), out, None) == -1
 
 
 def test_batch_workspace_sizes(L):
@@ -88,6 +91,7 @@ def test_batch_workspace_sizes(L):
     for n in (1, 63, 64, 1000, 1 << 24):
         a, b, c = f(n, G.PER_CELL), f(n, G.PERSISTENT), f(n, G.PER_ITERATION)
         assert a == b == L.grrmhd_implicit_source_workspace_bytes(n)
-        assert a >= 256 + 4 * n and a % 256 == 0
+        # list, first-attempt record (13 doubles, 3 ints) per cell
+        assert a >= 256 + 4 * n + 13 * 8 * n + 3 * 4 * n and a % 256 == 0
         # two queues, 47 doubles and 8 ints of lane state per cell
         assert c >= a + 8 * n + 47 * 8 * n + 8 * 4 * n

@@ -273,11 +273,23 @@ def test_implicit_batch_forms_identical(G, orc, form):
     n = 5003
     pd, P, dt, ca, ce = I.implicit_batch(n, seed=6)
     args = [dev(_batch_cons(orc, pd, P)), dev(P), dev(dt), dev(ca), dev(ce)]
-    ref = [host(x) for x in G.implicit_source(pd, *args)]
+    ws0 = G.batch_workspace(n, G.PER_CELL)
+    ref = [host(x) for x in G.implicit_source_ex(pd, *args, G.PER_CELL, 64, 1, ws=ws0)]
+    s0 = G.batch_stats(ws0)
     mode, block, wpc = FORMS[form]
-    got = [host(x) for x in G.implicit_source_ex(pd, *args, mode, block, wpc)]
+    ws = G.batch_workspace(n, mode)
+    got = [host(x) for x in G.implicit_source_ex(pd, *args, mode, block, wpc, ws=ws)]
     for a, b in zip(got, ref):
         assert np.array_equal(a.view(np.uint8), b.view(np.uint8))
+    # same Newton trips and cascade cells; lane slots cover the trips
+    s1 = G.batch_stats(ws)
+    say("  stats per-cell", s0, form, s1)
+    assert s1[0] == s0[0] and s1[2] == s0[2]
+    assert s0[0] <= s0[1] and s1[0] <= s1[1]
+    # every non-extreme cell takes between 1 and max_iter + 1 trips
+    st = ref[3]
+    nonext = int(((st & G.ST_EXTREME) == 0).sum())
+    assert nonext <= s0[0] <= (pd["max_iter"] + 1) * nonext
 
 
 def test_implicit_batch_autotune_and_reuse(G, orc):
@@ -289,9 +301,10 @@ def test_implicit_batch_autotune_and_reuse(G, orc):
     pd, P, dt, ca, ce = I.implicit_batch(n, seed=8)
     Ui = _batch_cons(orc, pd, P)
     args = [dev(Ui), dev(P), dev(dt), dev(ca), dev(ce)]
-    t, outs = G.autotune_implicit_source(pd, *args)
+    t, allt, outs = G.autotune_implicit_source(pd, *args)
     say("  tuned", t.mode, t.block, t.waves_per_cu, t.ms)
-    assert t.mode in (G.PER_CELL, G.PERSISTENT) and t.ms > 0
+    assert t.ms > 0 and min(a.ms for a in allt) == t.ms
+    assert (t.mode, t.block, t.waves_per_cu) in [(a.mode, a.block, a.waves_per_cu) for a in allt]
     ref = [host(x) for x in G.implicit_source(pd, *args)]
     for a, b in zip([host(x) for x in outs], ref):
         assert np.array_equal(a.view(np.uint8), b.view(np.uint8))
