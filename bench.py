@@ -6,10 +6,15 @@ LAXF fluxes, MC reconstruction, flux-CT, implicit 4-force per cell; inputs
 are synthetic and seeded (paper_1312_6127_amd.inputs.accretion_disk).
 
 Prints one JSON line.  value = interior cells x steps / wall time of the K
-timed steps (HIP events on the step's stream, inputs resident in HBM).
-roofline: the dominant kernel (the per-cell implicit solve), its average
-launch time measured with HIP events on its stream.  cpu_baseline: the FP64
-oracle stepping the same workload on the host cores (bounded sample).
+timed FP64 steps (HIP events on the step's stream, inputs resident in HBM).
+mixed_precision: the same run with FP32 reconstruction, face states,
+Riemann fluxes and EMFs, and the per-field error of both precisions against
+the FP64 oracle after the oracle's steps.  roofline: the dominant kernel
+(the implicit kernel's first PMHD attempt), its average launch time from HIP
+events on its stream inside the timed region.  cpu_baseline: the FP64 oracle
+stepping the same workload on the host cores (bounded sample).
+implicit_batch (--batch-cells): the batched implicit solve in each
+execution form.
 """
 import argparse
 import json
@@ -46,7 +51,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, nargs=3, default=[128, 64, 32])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--cpu-steps", type=int, default=20,
+                    help="oracle steps (the CPU baseline sample and the error reference)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="also copy a buffer of this many MiB (counter calibration)")
     ap.add_argument("--batch-cells", type=int, default=0,
@@ -151,6 +157,71 @@ def bench_batch(G, I, torch, dev, n, reps=3):
     return res
 
 
+GROUPS = [(0,), (1,), (2, 3, 4), (5, 6, 7), (8,), (9, 10, 11)]
+FIELDS = ["rho", "u_g", "u1", "u2", "u3", "B1", "B2", "B3", "Ebar", "ur1", "ur2", "ur3"]
+
+
+def field_errors(a, b):
+    """Per-field max|a - b| over interior cells, relative to max|b| over the
+    field (over the three components for vectors)."""
+    import numpy as np
+
+    out = {}
+    for grp in GROUPS:
+        s = max(np.abs(b[q]).max() for q in grp)
+        for q in grp:
+            d = np.abs(a[q] - b[q]).max()
+            out[FIELDS[q]] = float(d / s) if s > 0 else float(d)
+    return out
+
+
+def time_steps(G, torch, dev, pd, P, ca, ce, steps, warmup, kernel_timing):
+    """Warm up, then time `steps` RK3-IMEX steps with HIP events on the
+    step's stream (inputs resident in HBM)."""
+    stream = torch.cuda.current_stream()
+    g = G.Grid(pd)
+    Pt = torch.tensor(P, device=dev)
+    Ut = g.prim_to_cons(Pt)
+    cat = torch.tensor(ca, device=dev)
+    cet = torch.tensor(ce, device=dev)
+    dt = torch.zeros(1, dtype=torch.float64, device=dev)
+    st = torch.zeros(g.N, dtype=torch.int32, device=dev)
+    it = torch.zeros(g.N, dtype=torch.int32, device=dev)
+    for _ in range(warmup):
+        g.step(Pt, Ut, cat, cet, dt, status=st, iters=it)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    if kernel_timing:
+        g.time_implicit(True)
+    e0.record(stream)
+    for _ in range(steps):
+        g.step(Pt, Ut, cat, cet, dt, status=st, iters=it)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    res = {"ms": e0.elapsed_time(e1), "st": st.cpu().numpy(), "it": it.cpu().numpy()}
+    if kernel_timing:
+        g.time_implicit(False)
+        res["imp_total_ms"], res["imp_launches"] = g.implicit_time()
+        res["trips"], res["slots"], _ = g.implicit_stats()
+    g.close()
+    return res
+
+
+def gpu_run(G, torch, dev, pd, P, ca, ce, steps):
+    """Interior P, U after `steps` steps from the initial state (untimed)."""
+    g = G.Grid(pd)
+    Pt = torch.tensor(P, device=dev)
+    Ut = g.prim_to_cons(Pt)
+    cat, cet = torch.tensor(ca, device=dev), torch.tensor(ce, device=dev)
+    dt = torch.zeros(1, dtype=torch.float64, device=dev)
+    for _ in range(steps):
+        g.step(Pt, Ut, cat, cet, dt)
+    out = Pt.cpu().numpy(), Ut.cpu().numpy()
+    g.close()
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -168,50 +239,33 @@ def main():
     if args.batch_only:
         print(json.dumps({"implicit_batch": bench_batch(G, I, torch, dev, args.batch_cells or (1 << 24))}))
         return
-    n = tuple(args.n)
-    pd, P, ca, ce = I.accretion_disk(n=n, seed=3)
-    stream = torch.cuda.current_stream()
-    g = G.Grid(pd)
-    Pt = torch.tensor(P, device=dev)
-    Ut = g.prim_to_cons(Pt)
-    cat = torch.tensor(ca, device=dev)
-    cet = torch.tensor(ce, device=dev)
-    dt = torch.zeros(1, dtype=torch.float64, device=dev)
-    st = torch.zeros(g.N, dtype=torch.int32, device=dev)
-    it = torch.zeros(g.N, dtype=torch.int32, device=dev)
-    P0, U0 = Pt.clone(), Ut.clone()
     if args.copy_probe_mb:
         src = torch.ones(args.copy_probe_mb * (1 << 20) // 8, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    for _ in range(args.warmup):
-        g.step(Pt, Ut, cat, cet, dt, status=st, iters=it)
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    g.time_implicit(True)
-    e0.record(stream)
-    for _ in range(args.steps):
-        g.step(Pt, Ut, cat, cet, dt, status=st, iters=it)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    g.time_implicit(False)
-    ms = e0.elapsed_time(e1)
-    ms_step = ms / args.steps
+    n = tuple(args.n)
     zones = n[0] * n[1] * n[2]
-    value = zones * args.steps / (ms * 1e-3)
+    pd, P, ca, ce = I.accretion_disk(n=n, seed=3)
     interior = I.interior(pd)
     na = I.nalloc(pd)
-    stv = st.cpu().numpy().reshape(na[::-1])[interior]
-    itv = it.cpu().numpy().reshape(na[::-1])[interior]
+
+    r64 = time_steps(G, torch, dev, pd, P, ca, ce, args.steps, args.warmup, kernel_timing=True)
+    print(f"fp64 steps: {r64['ms'] / args.steps:.3f} ms/step", file=sys.stderr, flush=True)
+    ms_step = r64["ms"] / args.steps
+    value = zones * args.steps / (r64["ms"] * 1e-3)
+    stv = r64["st"].reshape(na[::-1])[interior]
+    itv = r64["it"].reshape(na[::-1])[interior]
     nfail = int(((stv & G.ST_FAIL) != 0).sum())
+    pdm = dict(pd, precision="mixed")
+    rmx = time_steps(G, torch, dev, pdm, P, ca, ce, args.steps, args.warmup, kernel_timing=False)
+    print(f"mixed steps: {rmx['ms'] / args.steps:.3f} ms/step", file=sys.stderr, flush=True)
 
     # dominant kernel: the implicit kernel of each stage, timed with HIP events
     # on its stream inside the timed region
-    imp_total_ms, imp_launches = g.implicit_time()
-    trips, slots, _ = g.implicit_stats()
+    trips, slots = r64["trips"], r64["slots"]
+    imp_total_ms, imp_launches = r64["imp_total_ms"], r64["imp_launches"]
     imp_ms = imp_total_ms / max(imp_launches, 1)
     fresh = KERNEL_DIGEST is not None and KERNEL_DIGEST == kernel_digest()
     roof = {"kernel": "k_implicit", "bound": "alu", "unit": "TFLOP/s", "peak": FP64_PEAK_TFLOPS,
@@ -230,13 +284,17 @@ def main():
         roof["traffic"] = HBM_BYTES_PER_LAUNCH
         roof["traffic_GBs"] = HBM_BYTES_PER_LAUNCH / (imp_ms * 1e-3) / 1e9
 
+    mixed = {"value": zones * args.steps / (rmx["ms"] * 1e-3), "ms_per_step": rmx["ms"] / args.steps,
+             "speedup_vs_fp64": r64["ms"] / rmx["ms"], "r_fp64": pdm["r_fp64"]}
     cpu = None
     if not args.no_cpu_baseline:
+        # the oracle steps the same workload from the same initial state; its
+        # result is also the reference of both GPU precisions' error
         import oracle
 
         oracle.build()
-        Ph = P0.cpu().numpy()
-        Uh = U0.cpu().numpy()
+        Uh = oracle.prim_to_cons(pd, P)
+        Ph = P
         t0 = time.perf_counter()
         for _ in range(args.cpu_steps):
             Ph, Uh, dth, sth, ith, nb = oracle.step(pd, Ph, Uh, ca, ce)
@@ -244,7 +302,18 @@ def main():
         cpu = {"value": zones * args.cpu_steps / tc, "unit": "zone-cycles/s",
                "cores": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)),
                "kind": "oracle",
-               "sample": f"{args.cpu_steps} full steps of the same {n[0]}x{n[1]}x{n[2]} workload"}
+               "sample": f"{args.cpu_steps} full steps of the same {n[0]}x{n[1]}x{n[2]} workload "
+                         "from its initial state"}
+        ref = [x.reshape((12,) + na[::-1])[(slice(None),) + interior].reshape(12, -1) for x in (Ph, Uh)]
+        errs = {}
+        for name, pdx in (("fp64", pd), ("mixed", pdm)):
+            Pg, Ug = gpu_run(G, torch, dev, pdx, P, ca, ce, args.cpu_steps)
+            got = [x.reshape((12,) + na[::-1])[(slice(None),) + interior].reshape(12, -1) for x in (Pg, Ug)]
+            errs[name] = {"P": field_errors(got[0], ref[0]), "U": field_errors(got[1], ref[1])}
+            errs[name]["max"] = max(max(errs[name]["P"].values()), max(errs[name]["U"].values()))
+        mixed["err_vs_oracle"] = errs["mixed"]
+        mixed["fp64_err_vs_oracle_max"] = errs["fp64"]["max"]
+        mixed["err_steps"] = args.cpu_steps
 
     out = {
         "metric": "zone-cycles/s per GRRMHD step (FP32-mixed vs FP64) at stated rel. error; % HBM peak",
@@ -266,13 +335,13 @@ def main():
         "step_hbm": {"algorithmic_bytes_per_zone_cycle": STEP_BYTES_PER_ZONE,
                      "achieved_GBs": value * STEP_BYTES_PER_ZONE / 1e9,
                      "frac": value * STEP_BYTES_PER_ZONE / 1e9 / HBM_PEAK_GBS},
+        "mixed_precision": mixed,
         "roofline": roof,
         "cpu_baseline": cpu,
     }
     if args.batch_cells:
         out["implicit_batch"] = bench_batch(G, I, torch, dev, args.batch_cells)
     print(json.dumps(out))
-    g.close()
 
 
 if __name__ == "__main__":

@@ -49,6 +49,7 @@ extern "C" {
 enum { GRRMHD_MINKOWSKI = 0, GRRMHD_KERR_SCHILD = 1 };
 enum { GRRMHD_BC_OUTFLOW = 0, GRRMHD_BC_PERIODIC = 1, GRRMHD_BC_REFLECT = 2, GRRMHD_BC_POLAR = 3 };
 enum { GRRMHD_FLUX_LLF = 0, GRRMHD_FLUX_HLL = 1 };
+enum { GRRMHD_FP64 = 0, GRRMHD_MIXED = 1 };
 enum { GRRMHD_EINVAL = -1, GRRMHD_EHIP = -2, GRRMHD_ENOMEM = -3 };
 
 /* per-cell status bits written by the implicit solve and the fix-ups */
@@ -82,6 +83,13 @@ typedef struct {
   double gamma_max;     /* cap on the radiation frame's Lorentz factor        */
   double courant;
   int flux;             /* GRRMHD_FLUX_LLF or GRRMHD_FLUX_HLL                 */
+  int precision;        /* GRRMHD_FP64, or GRRMHD_MIXED: reconstruction, face
+                           states, Riemann fluxes and corner EMFs in FP32
+                           arithmetic (state, update, inversions and the
+                           implicit solve stay FP64)                          */
+  double r_fp64;        /* MIXED on Kerr-Schild: faces and edges next to cells
+                           with r < r_fp64 keep FP64 (default 2, which covers
+                           the horizon and the ergosphere)                    */
   double tol_pmhd;      /* stop tolerance of PMHD iterations (1e-12)          */
   double tol_urad;      /* stop tolerance of URAD iterations (1e-9)           */
   double tol_accept;    /* accepted without trying the next method (1e-9)     */

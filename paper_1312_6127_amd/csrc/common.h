@@ -39,6 +39,7 @@ struct Ctx {
   int bc_lo[3], bc_hi[3];
   double gam, arad, gamma_max, ymax, courant;
   int flux;
+  int mixed_i;         // FP32-mixed: cells with x1 index >= mixed_i take the FP32 face path
   double tol_pmhd, tol_urad, tol_accept, tol_fail;
   int max_iter, roundoff;
   double rho_floor, u_floor, bsq_rho_max, bsq_u_max, u_rho_max, erad_floor;
@@ -47,20 +48,34 @@ struct Ctx {
   const double* geo_f2;  // [GE_NFACE][npos] at x2 faces
 };
 
-// Metric at one point, loaded from a table.
-struct Metric {
-  double gcov[10], gcon[10], gdet, alpha;
-  DEV double lo(int a, int b) const { return gcov[sym(a, b)]; }
-  DEV double up(int a, int b) const { return gcon[sym(a, b)]; }
+// Real type of the literals and metric coefficients that go with a scalar
+// T: float on the FP32 face path, double otherwise (double and Dual<N>).
+template <class T>
+struct RealOf {
+  using type = double;
+};
+template <>
+struct RealOf<float> {
+  using type = float;
 };
 
-DEV void load_metric(const double* tab, int npos, int pos, Metric& m) {
+// Metric at one point, loaded from a table (rounded to R on the FP32 path).
+template <class R>
+struct MetricT {
+  R gcov[10], gcon[10], gdet, alpha;
+  DEV R lo(int a, int b) const { return gcov[sym(a, b)]; }
+  DEV R up(int a, int b) const { return gcon[sym(a, b)]; }
+};
+using Metric = MetricT<double>;
+
+template <class R>
+DEV void load_metric(const double* tab, int npos, int pos, MetricT<R>& m) {
 #pragma unroll
-  for (int q = 0; q < 10; q++) m.gcov[q] = tab[(GE_GCOV + q) * npos + pos];
+  for (int q = 0; q < 10; q++) m.gcov[q] = (R)tab[(GE_GCOV + q) * npos + pos];
 #pragma unroll
-  for (int q = 0; q < 10; q++) m.gcon[q] = tab[(GE_GCON + q) * npos + pos];
-  m.gdet = tab[GE_GDET * npos + pos];
-  m.alpha = tab[GE_ALPHA * npos + pos];
+  for (int q = 0; q < 10; q++) m.gcon[q] = (R)tab[(GE_GCON + q) * npos + pos];
+  m.gdet = (R)tab[GE_GDET * npos + pos];
+  m.alpha = (R)tab[GE_ALPHA * npos + pos];
 }
 
 DEV void flat_metric(Metric& m) {

@@ -80,6 +80,8 @@ extern "C" void grrmhd_default_params(grrmhd_params* p) {
   p->gamma_max = 100.0;
   p->courant = 0.5;
   p->flux = GRRMHD_FLUX_LLF;
+  p->precision = GRRMHD_FP64;
+  p->r_fp64 = 2.0;
   p->tol_pmhd = 1e-12;
   p->tol_urad = 1e-9;
   p->tol_accept = 1e-9;
@@ -100,6 +102,8 @@ static int validate(const grrmhd_params* p, bool need_grid) {
     return fail(GRRMHD_EINVAL, "gam > 1, arad >= 0, gamma_max > 1, courant > 0 required");
   if (p->max_iter < 1 || p->max_iter > 200) return fail(GRRMHD_EINVAL, "max_iter out of [1, 200]");
   if (p->flux != GRRMHD_FLUX_LLF && p->flux != GRRMHD_FLUX_HLL) return fail(GRRMHD_EINVAL, "bad flux");
+  if (p->precision != GRRMHD_FP64 && p->precision != GRRMHD_MIXED)
+    return fail(GRRMHD_EINVAL, "bad precision");
   if (p->metric != GRRMHD_MINKOWSKI && p->metric != GRRMHD_KERR_SCHILD)
     return fail(GRRMHD_EINVAL, "bad metric");
   if (!need_grid) return 0;
@@ -146,6 +150,15 @@ static void fill_ctx(const grrmhd_params* p, Ctx& C) {
   C.ymax = 16.0 * G * (G - 1.0) / ((4.0 * G - 1.0) * (4.0 * G - 1.0));
   C.courant = p->courant;
   C.flux = p->flux;
+  // FP32 face path from the first x1 index i whose cell i-1 has r >= r_fp64
+  C.mixed_i = 1 << 30;
+  if (p->precision == GRRMHD_MIXED) {
+    C.mixed_i = 0;
+    if (p->metric == GRRMHD_KERR_SCHILD)
+      while (C.mixed_i < C.N[0] &&
+             p->R0 + exp(C.xlo[0] + (C.mixed_i - 1 - C.ng[0] + 0.5) * C.dx[0]) < p->r_fp64)
+        C.mixed_i++;
+  }
   C.tol_pmhd = p->tol_pmhd;
   C.tol_urad = p->tol_urad;
   C.tol_accept = p->tol_accept;
@@ -295,6 +308,34 @@ static FaceRange edge_range(const Ctx& C, int a) {
   return R;
 }
 
+// Split a range at x1 index i0: [lo, i0) and [i0, hi) (either may be empty).
+static void split_x1(const FaceRange& R, int i0, FaceRange& a, FaceRange& b) {
+  a = b = R;
+  const int cut = std::min(std::max(i0, R.lo[0]), R.lo[0] + R.cnt[0]);
+  a.cnt[0] = cut - R.lo[0];
+  b.lo[0] = cut;
+  b.cnt[0] = R.lo[0] + R.cnt[0] - cut;
+  a.total = (long)a.cnt[0] * a.cnt[1] * a.cnt[2];
+  b.total = (long)b.cnt[0] * b.cnt[1] * b.cnt[2];
+}
+
+template <int D, class T>
+static void flux_launch(grrmhd_grid* g, const FaceRange& R, const double* P, const double* ca,
+                        const double* ce, double* Fd, double* vd) {
+  if (R.total <= 0) return;
+  hipLaunchKernelGGL((k_flux<D, T>), dim3(nblocks(R.total, 128)), dim3(128), 0, g->stream, g->C,
+                     R, P, ca, ce, Fd, vd);
+}
+
+template <int D>
+static void flux_dir(grrmhd_grid* g, const FaceRange& R, const double* P, const double* ca,
+                     const double* ce, double* Fd, double* vd) {
+  FaceRange r64, r32;
+  split_x1(R, g->C.mixed_i, r64, r32);
+  flux_launch<D, double>(g, r64, P, ca, ce, Fd, vd);
+  flux_launch<D, float>(g, r32, P, ca, ce, Fd, vd);
+}
+
 static int launch_fluxes(grrmhd_grid* g, const double* P, const double* ca, const double* ce,
                          double* F, double* emf, double* vch) {
   const Ctx& C = g->C;
@@ -304,17 +345,22 @@ static int launch_fluxes(grrmhd_grid* g, const double* P, const double* ca, cons
     FaceRange R = face_range(C, d);
     double* Fd = F + (size_t)d * 12 * N;
     double* vd = vch + (size_t)d * N;
-    const dim3 gr(nblocks(R.total, 128)), bl(128);
-    if (d == 0) hipLaunchKernelGGL(k_flux<1>, gr, bl, 0, g->stream, C, R, P, ca, ce, Fd, vd);
-    if (d == 1) hipLaunchKernelGGL(k_flux<2>, gr, bl, 0, g->stream, C, R, P, ca, ce, Fd, vd);
-    if (d == 2) hipLaunchKernelGGL(k_flux<3>, gr, bl, 0, g->stream, C, R, P, ca, ce, Fd, vd);
+    if (d == 0) flux_dir<1>(g, R, P, ca, ce, Fd, vd);
+    if (d == 1) flux_dir<2>(g, R, P, ca, ce, Fd, vd);
+    if (d == 2) flux_dir<3>(g, R, P, ca, ce, Fd, vd);
     LAUNCHCHK();
   }
   for (int a = 0; a < 3; a++) {
     const int b = (a + 1) % 3, c = (a + 2) % 3;
     if (C.n[b] == 1 || C.n[c] == 1) continue;
-    FaceRange R = edge_range(C, a);
-    hipLaunchKernelGGL(k_emf, dim3(nblocks(R.total, 256)), dim3(256), 0, g->stream, C, a, R, F, emf);
+    FaceRange r64, r32;
+    split_x1(edge_range(C, a), C.mixed_i, r64, r32);
+    if (r64.total > 0)
+      hipLaunchKernelGGL(k_emf<double>, dim3(nblocks(r64.total, 256)), dim3(256), 0, g->stream, C,
+                         a, r64, F, emf);
+    if (r32.total > 0)
+      hipLaunchKernelGGL(k_emf<float>, dim3(nblocks(r32.total, 256)), dim3(256), 0, g->stream, C,
+                         a, r32, F, emf);
     LAUNCHCHK();
   }
   return 0;

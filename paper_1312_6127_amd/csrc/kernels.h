@@ -166,31 +166,35 @@ __global__ void LB(256) k_p2u(Ctx C, const double* __restrict__ P, double* __res
 // ---------------------------------------------------------------------------
 // steps 4-7: reconstruction, face physics, wave speeds, HLL / LAXF
 // ---------------------------------------------------------------------------
-DEV double mc_slope(double dl, double dr) {
-  if (dl * dr <= 0.0) return 0.0;
-  const double dc = 0.5 * (dl + dr);
-  return ::copysign(fmin(::fabs(dc), 2.0 * fmin(::fabs(dl), ::fabs(dr))), dc);
+template <class T>
+DEV T mc_slope(T dl, T dr) {
+  if (dl * dr <= T(0.0)) return T(0.0);
+  const T dc = T(0.5) * (dl + dr);
+  return copysign(fmin(fabs(dc), T(2.0) * fmin(fabs(dl), fabs(dr))), dc);
 }
 
+template <class T>
 struct FaceState {
-  double U[12], F[12];
-  double gm, gp, rm, rp;   // gas and radiation characteristic speeds
+  T U[12], F[12];
+  T gm, gp, rm, rp;   // gas and radiation characteristic speeds
 };
 
-DEV void face_state(const Ctx& C, const Metric& m, int d, const double* P, double chi_tot,
-                    FaceState& fs) {
-  Gas<double> s;
+// T = double, or float on the FP32 face path (metric rounded to float too)
+template <class T>
+DEV void face_state(const Ctx& C, const MetricT<T>& m, int d, const T* P, T chi_tot,
+                    FaceState<T>& fs) {
+  Gas<T> s;
   make_gas(m, C.gam, P[0], P[1], P + 2, P + 5, s);
-  double row[8];
+  T row[8];
   gas_row(s, P + 5, 0, row);
 #pragma unroll
   for (int q = 0; q < 8; q++) fs.U[q] = m.gdet * row[q];
   gas_row(s, P + 5, d, row);
 #pragma unroll
   for (int q = 0; q < 8; q++) fs.F[q] = m.gdet * row[q];
-  Vel<double> r;
+  Vel<T> r;
   make_vel(m, P + 9, r);
-  double rr[4];
+  T rr[4];
   rad_row(r, P[8], 0, rr);
 #pragma unroll
   for (int q = 0; q < 4; q++) fs.U[8 + q] = m.gdet * rr[q];
@@ -198,17 +202,17 @@ DEV void face_state(const Ctx& C, const Metric& m, int d, const double* P, doubl
 #pragma unroll
   for (int q = 0; q < 4; q++) fs.F[8 + q] = m.gdet * rr[q];
   // gas: fast magnetosonic speed c_ms^2 = v_A^2 + c_s^2 (1 - v_A^2)
-  const double w = s.rho + s.ug + s.pg;
-  const double cs2 = C.gam * s.pg / w;
-  const double va2 = s.bsq / (w + s.bsq);
-  char_speeds(m, s.v.ucon, va2 + cs2 * (1.0 - va2), d, fs.gm, fs.gp);
+  const T w = s.rho + s.ug + s.pg;
+  const T cs2 = T(C.gam) * s.pg / w;
+  const T va2 = s.bsq / (w + s.bsq);
+  char_speeds(m, s.v.ucon, va2 + cs2 * (T(1.0) - va2), d, fs.gm, fs.gp);
   // radiation: 1/sqrt(3) in the radiation frame, limited to 4/(3 tau) in the gas frame
-  char_speeds(m, r.ucon, 1.0 / 3.0, d, fs.rm, fs.rp);
-  const double tau = chi_tot * P[0] * ::sqrt(m.lo(d, d)) * C.dx[d - 1];
-  if (tau > 0.0) {
-    const double cl = 4.0 / (3.0 * tau);
-    if (cl < 1.0) {
-      double lm, lp;
+  char_speeds(m, r.ucon, T(1.0 / 3.0), d, fs.rm, fs.rp);
+  const T tau = chi_tot * P[0] * sqrt(m.lo(d, d)) * T(C.dx[d - 1]);
+  if (tau > T(0.0)) {
+    const T cl = T(4.0) / (T(3.0) * tau);
+    if (cl < T(1.0)) {
+      T lm, lp;
       char_speeds(m, s.v.ucon, cl * cl, d, lm, lp);
       fs.rp = fmin(fs.rp, lp);
       fs.rm = fmax(fs.rm, lm);
@@ -221,7 +225,10 @@ struct FaceRange {
   long total;
 };
 
-template <int D>
+// Faces normal to D in range R: reconstruction, face states, HLL / LAXF, in
+// arithmetic T (double; float for the FP32-mixed path); fluxes and speeds are
+// stored as double.
+template <int D, class T>
 __global__ void LB(128) k_flux(Ctx C, FaceRange R, const double* __restrict__ P,
                                const double* __restrict__ chi_abs,
                                const double* __restrict__ chi_es, double* __restrict__ F,
@@ -234,44 +241,46 @@ __global__ void LB(128) k_flux(Ctx C, FaceRange R, const double* __restrict__ P,
   const int k = R.lo[2] + t2 / R.cnt[1];
   const long c = cell_index(C, i, j, k);
   const long st = C.st[D - 1];
-  double PL[12], PR[12];
+  T PL[12], PR[12];
 #pragma unroll
   for (int q = 0; q < 12; q++) {
     const double* p = P + q * C.Ntot;
-    const double a = p[c - 2 * st], b = p[c - st], e = p[c], f = p[c + st];
-    PL[q] = b + 0.5 * mc_slope(b - a, e - b);
-    PR[q] = e - 0.5 * mc_slope(e - b, f - e);
+    const T a = (T)p[c - 2 * st], b = (T)p[c - st], e = (T)p[c], f = (T)p[c + st];
+    PL[q] = b + T(0.5) * mc_slope(b - a, e - b);
+    PR[q] = e - T(0.5) * mc_slope(e - b, f - e);
   }
-  Metric m;
+  MetricT<T> m;
   const double* tab = (D == 1) ? C.geo_f1 : ((D == 2) ? C.geo_f2 : C.geo_c);
   load_metric(tab, C.npos, i + C.N[0] * j, m);
-  FaceState L, Rs;
-  face_state(C, m, D, PL, chi_abs[c - st] + chi_es[c - st], L);
-  face_state(C, m, D, PR, chi_abs[c] + chi_es[c], Rs);
+  FaceState<T> L, Rs;
+  face_state(C, m, D, PL, (T)(chi_abs[c - st] + chi_es[c - st]), L);
+  face_state(C, m, D, PR, (T)(chi_abs[c] + chi_es[c]), Rs);
   // eq. hll: v_min = -min(0, v-_L, v-_R), v_max = max(0, v+_L, v+_R)
-  const double gmin = -fmin(0.0, fmin(L.gm, Rs.gm)), gmax = fmax(0.0, fmax(L.gp, Rs.gp));
-  const double rmin = -fmin(0.0, fmin(L.rm, Rs.rm)), rmax = fmax(0.0, fmax(L.rp, Rs.rp));
+  const T zero = T(0.0);
+  const T gmin = -fmin(zero, fmin(L.gm, Rs.gm)), gmax = fmax(zero, fmax(L.gp, Rs.gp));
+  const T rmin = -fmin(zero, fmin(L.rm, Rs.rm)), rmax = fmax(zero, fmax(L.rp, Rs.rp));
 #pragma unroll
   for (int q = 0; q < 12; q++) {
-    const double vmin = q < 8 ? gmin : rmin, vmax = q < 8 ? gmax : rmax;
-    double f;
+    const T vmin = q < 8 ? gmin : rmin, vmax = q < 8 ? gmax : rmax;
+    T f;
     if (C.flux == GRRMHD_FLUX_HLL) {
-      const double den = vmin + vmax;
-      f = (den > 0.0) ? (vmin * Rs.F[q] + vmax * L.F[q] - vmin * vmax * (Rs.U[q] - L.U[q])) / den
-                      : 0.5 * (L.F[q] + Rs.F[q]);
+      const T den = vmin + vmax;
+      f = (den > zero) ? (vmin * Rs.F[q] + vmax * L.F[q] - vmin * vmax * (Rs.U[q] - L.U[q])) / den
+                       : T(0.5) * (L.F[q] + Rs.F[q]);
     } else {
-      f = 0.5 * (Rs.F[q] + L.F[q] - fmax(vmin, vmax) * (Rs.U[q] - L.U[q]));
+      f = T(0.5) * (Rs.F[q] + L.F[q] - fmax(vmin, vmax) * (Rs.U[q] - L.U[q]));
     }
-    if (q == 4 + D) f = 0.0;   // normal field component has no induction flux
-    F[q * C.Ntot + c] = f;
+    if (q == 4 + D) f = zero;   // normal field component has no induction flux
+    F[q * C.Ntot + c] = (double)f;
   }
-  vchar[c] = fmax(fmax(gmin, gmax), fmax(rmin, rmax));
+  vchar[c] = (double)fmax(fmax(gmin, gmax), fmax(rmin, rmax));
 }
 
 // ---------------------------------------------------------------------------
 // step 9 (flux-CT): corner EMF along a = average of the four adjacent face
 // induction fluxes, emf_a = F_c[B_b] = -F_b[B_c] for cyclic (a, b, c)
 // ---------------------------------------------------------------------------
+template <class T>
 __global__ void LB(256) k_emf(Ctx C, int a, FaceRange R, const double* __restrict__ F,
                               double* __restrict__ emf) {
   const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -284,14 +293,14 @@ __global__ void LB(256) k_emf(Ctx C, int a, FaceRange R, const double* __restric
   const int b = (a + 1) % 3, cd = (a + 2) % 3;
   const double* Fb = F + (long)b * 12 * C.Ntot + (long)(5 + cd) * C.Ntot;   // F_b[B_c]
   const double* Fc = F + (long)cd * 12 * C.Ntot + (long)(5 + b) * C.Ntot;   // F_c[B_b]
-  double e = 0.25 * ((Fc[c] + Fc[c - C.st[b]]) - (Fb[c] + Fb[c - C.st[cd]]));
+  T e = T(0.25) * (((T)Fc[c] + (T)Fc[c - C.st[b]]) - ((T)Fb[c] + (T)Fb[c - C.st[cd]]));
   if (C.metric == GRRMHD_KERR_SCHILD && (b == 1 || cd == 1)) {
     // edges on the polar axis carry no EMF
     const bool lo = j == C.ng[1] && (C.bc_lo[1] == GRRMHD_BC_REFLECT || C.bc_lo[1] == GRRMHD_BC_POLAR);
     const bool hi = j == C.ng[1] + C.n[1] && (C.bc_hi[1] == GRRMHD_BC_REFLECT || C.bc_hi[1] == GRRMHD_BC_POLAR);
-    if (lo || hi) e = 0.0;
+    if (lo || hi) e = T(0.0);
   }
-  emf[(long)a * C.Ntot + c] = e;
+  emf[(long)a * C.Ntot + c] = (double)e;
 }
 
 // ---------------------------------------------------------------------------

@@ -1,6 +1,7 @@
 // Pointwise GRRMHD + M1 physics on the device.  Templated on the scalar so
-// the same code yields values (double) or values with exact derivatives
-// (Dual<N>).  Only the tensor rows a caller needs are formed.
+// the same code yields values (double, or float on the FP32 face path) or
+// values with exact derivatives (Dual<N>).  Only the tensor rows a caller
+// needs are formed.
 #pragma once
 #include "common.h"
 
@@ -16,16 +17,17 @@ struct Vel {
 };
 
 template <class T>
-DEV void make_vel(const Metric& m, const T ut[3], Vel<T>& v) {
-  T q = T(0.0);
+DEV void make_vel(const MetricT<typename RealOf<T>::type>& m, const T ut[3], Vel<T>& v) {
+  using R = typename RealOf<T>::type;
+  T q = T(R(0.0));
 #pragma unroll
   for (int i = 0; i < 3; i++) {
     q = q + m.lo(i + 1, i + 1) * ut[i] * ut[i];
 #pragma unroll
-    for (int j = i + 1; j < 3; j++) q = q + 2.0 * m.lo(i + 1, j + 1) * ut[i] * ut[j];
+    for (int j = i + 1; j < 3; j++) q = q + R(2.0) * m.lo(i + 1, j + 1) * ut[i] * ut[j];
   }
   v.usq = q;
-  v.gamma = sqrt(1.0 + q);
+  v.gamma = sqrt(R(1.0) + q);
   const T ga = v.gamma * m.alpha;
   v.ucon[0] = v.gamma / m.alpha;
 #pragma unroll
@@ -49,15 +51,16 @@ struct Gas {
 };
 
 template <class T>
-DEV void make_gas(const Metric& m, double gam, const T& rho, const T& ug, const T ut[3],
-                  const T B[3], Gas<T>& s) {
+DEV void make_gas(const MetricT<typename RealOf<T>::type>& m, double gam, const T& rho,
+                  const T& ug, const T ut[3], const T B[3], Gas<T>& s) {
+  using R = typename RealOf<T>::type;
   make_vel(m, ut, s.v);
   s.rho = rho;
   s.ug = ug;
-  s.pg = (gam - 1.0) * ug;
+  s.pg = R(gam - 1.0) * ug;
   T bt = B[0] * s.v.ucov[1] + B[1] * s.v.ucov[2] + B[2] * s.v.ucov[3];
   s.bcon[0] = bt;
-  const T iut = 1.0 / s.v.ucon[0];
+  const T iut = R(1.0) / s.v.ucon[0];
 #pragma unroll
   for (int i = 0; i < 3; i++) s.bcon[i + 1] = (B[i] + bt * s.v.ucon[i + 1]) * iut;
 #pragma unroll
@@ -71,7 +74,7 @@ DEV void make_gas(const Metric& m, double gam, const T& rho, const T& ug, const 
           s.bcon[3] * s.bcov[3];
   // u_t = g_ti u~^i - alpha gamma  =>  1 + u_t = (1 - alpha) - alpha u~^2/(1 + gamma) + g_ti u~^i
   T gtu = m.lo(0, 1) * ut[0] + m.lo(0, 2) * ut[1] + m.lo(0, 3) * ut[2];
-  s.opu = (1.0 - m.alpha) - m.alpha * s.v.usq / (1.0 + s.v.gamma) + gtu;
+  s.opu = (R(1.0) - m.alpha) - m.alpha * s.v.usq / (R(1.0) + s.v.gamma) + gtu;
 }
 
 // Row mu of the gas conserved/flux vector (Sec. 4 lists of U_q and F_q):
@@ -79,8 +82,9 @@ DEV void make_gas(const Metric& m, double gam, const T& rho, const T& ug, const 
 // out[5..7] = B^i (mu = 0) or b^i u^mu - b^mu u^i, all without sqrt(-g).
 template <class T>
 DEV void gas_row(const Gas<T>& s, const T B[3], int mu, T out[8]) {
+  using R = typename RealOf<T>::type;
   const T um = s.v.ucon[mu];
-  const T ptot = s.pg + 0.5 * s.bsq;
+  const T ptot = s.pg + R(0.5) * s.bsq;
   const T enth = s.rho + s.ug + s.pg + s.bsq;
   out[0] = s.rho * um;
   out[1] = s.rho * um * s.opu + (s.ug + s.pg + s.bsq) * um * s.v.ucov[0] - s.bcon[mu] * s.bcov[0];
@@ -98,11 +102,12 @@ DEV void gas_row(const Gas<T>& s, const T B[3], int mu, T out[8]) {
 // M1 radiation (eq. Rlab): R^mu_nu = (4/3) Ebar u^mu u_nu + (1/3) Ebar delta
 template <class T>
 DEV void rad_row(const Vel<T>& r, const T& E, int mu, T out[4]) {
-  const T f = (4.0 / 3.0) * E * r.ucon[mu];
+  using R = typename RealOf<T>::type;
+  const T f = R(4.0 / 3.0) * E * r.ucon[mu];
 #pragma unroll
   for (int nu = 0; nu < 4; nu++) {
     out[nu] = f * r.ucov[nu];
-    if (nu == mu) out[nu] = out[nu] + E * (1.0 / 3.0);
+    if (nu == mu) out[nu] = out[nu] + E * R(1.0 / 3.0);
   }
 }
 
@@ -131,19 +136,19 @@ DEV void four_force(const Vel<T>& u, const Vel<T>& r, const T& E, const T& kabs,
 // frame of 4-velocity u: the two roots of
 // [(1-c2)(u^t)^2 - c2 g^tt] v^2 - 2[(1-c2) u^t u^d - c2 g^td] v + [(1-c2)(u^d)^2 - c2 g^dd] = 0
 // (the dispersion relation (k.u)^2 = c2 (k.k + (k.u)^2) with k = d(x^d - v t)).
-DEV void char_speeds(const Metric& m, const double u[4], double c2, int dir, double& vm,
-                     double& vp) {
-  const double A = (1.0 - c2) * u[0] * u[0] - c2 * m.up(0, 0);
-  const double B = (1.0 - c2) * u[0] * u[dir] - c2 * m.up(0, dir);
+template <class R>
+DEV void char_speeds(const MetricT<R>& m, const R u[4], R c2, int dir, R& vm, R& vp) {
+  const R A = (R(1.0) - c2) * u[0] * u[0] - c2 * m.up(0, 0);
+  const R B = (R(1.0) - c2) * u[0] * u[dir] - c2 * m.up(0, dir);
   // discriminant B^2 - A C = c2 [(1 - c2) h + c2 k]: the (1 - c2)^2 (u^t u^d)^2
   // parts cancel exactly, so a tiny c2 (optically thick limiter) loses nothing
-  const double h = u[0] * u[0] * m.up(dir, dir) - 2.0 * u[0] * u[dir] * m.up(0, dir) +
-                   u[dir] * u[dir] * m.up(0, 0);
-  const double k = m.up(0, dir) * m.up(0, dir) - m.up(0, 0) * m.up(dir, dir);
-  const double disc = fmax(c2 * ((1.0 - c2) * h + c2 * k), 0.0);
-  const double sq = ::sqrt(disc);
-  const double ia = 1.0 / A;
-  const double v1 = (B + sq) * ia, v2 = (B - sq) * ia;
+  const R h = u[0] * u[0] * m.up(dir, dir) - R(2.0) * u[0] * u[dir] * m.up(0, dir) +
+              u[dir] * u[dir] * m.up(0, 0);
+  const R k = m.up(0, dir) * m.up(0, dir) - m.up(0, 0) * m.up(dir, dir);
+  const R disc = fmax(c2 * ((R(1.0) - c2) * h + c2 * k), R(0.0));
+  const R sq = sqrt(disc);
+  const R ia = R(1.0) / A;
+  const R v1 = (B + sq) * ia, v2 = (B - sq) * ia;
   vp = fmax(v1, v2);
   vm = fmin(v1, v2);
 }

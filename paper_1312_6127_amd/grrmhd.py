@@ -27,7 +27,7 @@ class Params(C.Structure):
         ("xlo", C.c_double * 3), ("xhi", C.c_double * 3),
         ("bc_lo", C.c_int * 3), ("bc_hi", C.c_int * 3),
         ("gam", C.c_double), ("arad", C.c_double), ("gamma_max", C.c_double),
-        ("courant", C.c_double), ("flux", C.c_int),
+        ("courant", C.c_double), ("flux", C.c_int), ("precision", C.c_int), ("r_fp64", C.c_double),
         ("tol_pmhd", C.c_double), ("tol_urad", C.c_double),
         ("tol_accept", C.c_double), ("tol_fail", C.c_double),
         ("max_iter", C.c_int), ("roundoff", C.c_int),
@@ -60,6 +60,8 @@ def params(d: dict) -> Params:
               "erad_floor"):
         setattr(p, k, float(d[k]))
     p.flux = 1 if d["flux"] == "hll" else 0
+    p.precision = 1 if d.get("precision", "fp64") == "mixed" else 0
+    p.r_fp64 = float(d.get("r_fp64", 2.0))
     p.max_iter = int(d["max_iter"])
     p.roundoff = int(d["roundoff"])
     return p

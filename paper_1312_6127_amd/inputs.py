@@ -52,6 +52,7 @@ def default_params(**kw) -> dict:
         xlo=(0.0, 0.0, 0.0), xhi=(1.0, 1.0, 1.0),
         bc_lo=("periodic",) * 3, bc_hi=("periodic",) * 3,
         gam=5.0 / 3.0, arad=1.0, gamma_max=100.0, courant=0.5, flux="llf",
+        precision="fp64", r_fp64=2.0,
         tol_pmhd=1e-12, tol_urad=1e-9, tol_accept=1e-9, tol_fail=1e-7,
         max_iter=20, roundoff=1,
         rho_floor=1e-20, u_floor=1e-22, bsq_rho_max=200.0, bsq_u_max=1e5,
