@@ -41,7 +41,7 @@ STEP_BYTES_PER_ZONE = 1344
 # traffic is reported as null and the flop figure as stale.
 FLOPS_PER_TRIP = 3009.0
 HBM_BYTES_PER_LAUNCH = 121.7e6
-KERNEL_DIGEST = "310e16509b82f1b2"
+KERNEL_DIGEST = "001d5d9ecd750de2"
 
 
 def parse():
