@@ -192,6 +192,48 @@ int grrmhd_step(grrmhd_grid *g, double *P, double *U, const double *chi_abs,
                 const double *chi_es, double *dt_dev, int dt_fixed, int *status, int *iters,
                 void *workspace, size_t ws_bytes);
 
+/* Adjoint of one full step (grrmhd_step with dt_fixed): gP_n = dL/dP^n for
+ * L = sum over interior cells and fields of gU_next * U^{n+1}(P^n), with
+ * U^n = U(P^n) and dt (*dt_dev) held fixed.  The forward step is recomputed
+ * with per-stage checkpoints; the implicit solve is differentiated by the
+ * implicit-function theorem on the PMHD residual at the converged state
+ * (Sec. 4.8; one transposed 4x4 solve per cell), the fluxes, EMFs, source
+ * and ghost fill by their local Jacobians (dual numbers) and transposes.
+ * Fix-ups are taken as the identity (a failed cell passes its conserved
+ * cotangent through).  P_n [12][N] (interior read; not modified), gU_next
+ * [12][N] (interior read), gP_n [12][N] out (ghosts zero); P_next, U_next
+ * (nullable) receive the forward result.  workspace: device buffer of
+ * grrmhd_adjoint_workspace_bytes() bytes, 256-byte aligned.  Errors: EINVAL,
+ * EHIP. */
+size_t grrmhd_adjoint_workspace_bytes(const grrmhd_grid *g);
+int grrmhd_step_adjoint(grrmhd_grid *g, const double *P_n, const double *chi_abs,
+                        const double *chi_es, const double *dt_dev, const double *gU_next,
+                        double *gP_n, double *P_next, double *U_next, void *workspace,
+                        size_t ws_bytes);
+
+/* Pieces of the adjoint sweep (each the transpose of the Jacobian of a
+ * forward entry point; ghosts of inputs are ignored where the forward
+ * ignores them):
+ *  grrmhd_implicit_vjp   of grrmhd_implicit_grid at its result (P_out,
+ *                        status): gUexp = (dP/dUexp)^T gP_out +
+ *                        (dU/dUexp)^T gU_out at interior cells (zero at
+ *                        ghosts);
+ *  grrmhd_explicit_vjp   of grrmhd_fluxes followed by grrmhd_explicit_update
+ *                        with stage coefficient c on dt, with respect to the
+ *                        ghost-filled P: gP at every allocated cell;
+ *                        workspace grrmhd_explicit_vjp_workspace_bytes();
+ *  grrmhd_bc_vjp         of grrmhd_apply_bc, in place (ghost entries folded
+ *                        into their source cells and cleared). */
+int grrmhd_implicit_vjp(grrmhd_grid *g, const double *Uexp, const double *P_out,
+                        const int *status, double dt_scale, const double *dt_dev,
+                        const double *chi_abs, const double *chi_es, const double *gP_out,
+                        const double *gU_out, double *gUexp);
+size_t grrmhd_explicit_vjp_workspace_bytes(const grrmhd_grid *g);
+int grrmhd_explicit_vjp(grrmhd_grid *g, double c, const double *dt_dev, const double *P,
+                        const double *chi_abs, const double *chi_es, const double *gUexp,
+                        double *gP, void *workspace, size_t ws_bytes);
+int grrmhd_bc_vjp(grrmhd_grid *g, double *gP);
+
 /* Implicit 4-force solve for n independent cells in flat space (Minkowski
  * metric, no grid), eq. source3/source4 with the PMHD-then-URAD cascade of
  * Sec. 4.10.  Arrays [12][n] (U_expl, P_guess, P_out, U_out) and [n]

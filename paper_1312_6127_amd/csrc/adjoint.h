@@ -1,0 +1,675 @@
+// Adjoint of one RK3-IMEX step: the vector-Jacobian product dL/dP^n of
+// L = sum(gU . U^{n+1}(P^n)) with dt held fixed and U^n = U(P^n).
+//
+// The forward step is recomputed with every stage's inputs and outputs kept
+// (checkpoints); the reverse sweep then runs, per stage, from last to first:
+//   implicit solve   implicit-function theorem on the PMHD residual at the
+//                    converged state: J_x^T mu = (dOut/dx)^T lambda, then
+//                    lambda_Ue = (dOut/dUe)^T lambda - (dE/dUe)^T mu
+//                    (one transposed 4x4 solve per cell, no unrolled Newton);
+//   stage update     U(k) = a U^n + b U(k-1) + c dt (S(P) - div F): linear
+//                    parts exact, the geometric source S by its local
+//                    Jacobian;
+//   fluxes           corner EMFs (linear), then per face the Jacobian of the
+//                    Riemann flux with respect to its four stencil cells
+//                    (MC reconstruction, face states, HLL / LAXF);
+//   ghost cells      the transpose of the boundary copies (ghost cotangents
+//                    folded into their source cells, dimensions in reverse).
+// Local Jacobians come from Dual<4> passes of the same templated physics as
+// the forward kernels, so each piecewise choice (limiter branch, wave-speed
+// extremum, radiation limiter) is differentiated on the branch the forward
+// step took.  A failed cell's fix-up (the mean of its neighbours) is
+// differentiated as such; floors are taken as the identity.
+#pragma once
+#include "kernels.h"
+
+typedef Dual<4> D4;
+
+// Seed the four inputs k0..k0+3 of an input vector of n doubles.
+template <int NI>
+DEV void seed4(const double v[NI], int k0, D4 out[NI]) {
+#pragma unroll
+  for (int q = 0; q < NI; q++) {
+    out[q] = D4(v[q]);
+#pragma unroll
+    for (int j = 0; j < 4; j++)
+      if (q == k0 + j) out[q].d[j] = 1.0;
+  }
+}
+
+DEV void interior_cell(const Ctx& C, long t, int& i, int& j, int& k) {
+  i = C.ng[0] + t % C.n[0];
+  const long t2 = t / C.n[0];
+  j = C.ng[1] + t2 % C.n[1];
+  k = C.ng[2] + t2 / C.n[1];
+}
+
+// ---------------------------------------------------------------------------
+// U^n = U(P^n): lamP += (dU/dP)^T lamU at interior cells
+// ---------------------------------------------------------------------------
+DEV void adj_p2u_at(Ctx C, const double* __restrict__ P,
+                                  const double* __restrict__ lamU, double* __restrict__ lamP, long t) {
+  if (t >= (long)C.n[0] * C.n[1] * C.n[2]) return;
+  int i, j, k;
+  interior_cell(C, t, i, j, k);
+  const long c = cell_index(C, i, j, k);
+  Metric m;
+  load_metric(C.geo_c, C.npos, i + C.N[0] * j, m);
+  double p[12], lu[12];
+#pragma unroll
+  for (int q = 0; q < 12; q++) {
+    p[q] = P[q * C.Ntot + c];
+    lu[q] = lamU[q * C.Ntot + c];
+  }
+  for (int pass = 0; pass < 3; pass++) {
+    D4 pd[12], ud[12];
+    seed4<12>(p, 4 * pass, pd);
+    prim_to_cons_cell(m, C.gam, pd, ud);
+#pragma unroll
+    for (int jj = 0; jj < 4; jj++) {
+      double s = 0.0;
+#pragma unroll
+      for (int q = 0; q < 12; q++) s += lu[q] * ud[q].d[jj];
+      lamP[(4 * pass + jj) * C.Ntot + c] += s;
+    }
+  }
+}
+
+__global__ void LB(128) k_adj_p2u(Ctx C, const double* __restrict__ P,
+                                  const double* __restrict__ lamU, double* __restrict__ lamP) {
+  adj_p2u_at(C, P, lamU, lamP, (long)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// Implicit solve.  The PMHD map at (x, theta): x = (u_g, u~^i), theta = the
+// explicit conserved state U(i) (with sqrt(-g)); E the residual, P and U the
+// outputs exactly as the forward step finalises a PMHD solution.
+// ---------------------------------------------------------------------------
+template <class T>
+DEV void pmhd_map(const Metric& m, const Phys& ph, double dtc, double chi_abs, double chi_es,
+                  const T x[4], const T th[12], T E[4], T P[12], T U[12]) {
+  const double igd = 1.0 / m.gdet;
+  const T rhout = th[0] * igd;
+  T B[3], Tgi[4], Ri[4];
+#pragma unroll
+  for (int i = 0; i < 3; i++) B[i] = th[5 + i] * igd;
+#pragma unroll
+  for (int k = 0; k < 4; k++) {
+    Tgi[k] = th[1 + k] * igd;
+    Ri[k] = th[8 + k] * igd;
+  }
+  Gas<T> s;
+  {
+    Vel<T> v;
+    make_vel(m, x + 1, v);
+    const T rho = rhout / v.ucon[0];
+    make_gas(m, ph.gam, rho, x[0], x + 1, B, s);
+  }
+  T row[8];
+  gas_row(s, B, 0, row);
+  T R[4];
+#pragma unroll
+  for (int k = 0; k < 4; k++) R[k] = Ri[k] - (row[1 + k] - Tgi[k]);
+  T Eb, utr[3];
+  const int flags = rad_invert(m, ph.gamma_max, ph.ymax, 1, R, Eb, utr);
+  Vel<T> r;
+  make_vel(m, utr, r);
+  const T Tgas = s.pg / s.rho;
+  const T T2 = Tgas * Tgas;
+  const T kabs = chi_abs * s.rho, kes = chi_es * s.rho;
+  const T lam = kabs * ph.arad * (T2 * T2);
+  T G[4];
+  four_force(s.v, r, Eb, kabs, kes, lam, G);
+#pragma unroll
+  for (int k = 0; k < 4; k++) E[k] = (row[1 + k] - Tgi[k]) - dtc * G[k];
+  P[0] = s.rho;
+  P[1] = x[0];
+#pragma unroll
+  for (int i = 0; i < 3; i++) {
+    P[2 + i] = x[1 + i];
+    P[5 + i] = B[i];
+    P[9 + i] = utr[i];
+  }
+  P[8] = Eb;
+  T Ur[4];
+#pragma unroll
+  for (int k = 0; k < 4; k++) Ur[k] = R[k];
+  if (flags & 1) {   // E_rad <= 0 met: BASIC re-inversion of the radiation
+    T Eb2, ut2[3];
+    rad_invert(m, ph.gamma_max, ph.ymax, 0, R, Eb2, ut2);
+    P[8] = Eb2;
+#pragma unroll
+    for (int i = 0; i < 3; i++) P[9 + i] = ut2[i];
+  }
+  if (flags) {       // a limiter acted: radiation recomputed from its primitives
+    Vel<T> r2;
+    make_vel(m, P + 9, r2);
+    rad_row(r2, P[8], 0, Ur);
+  }
+  U[0] = th[0];
+#pragma unroll
+  for (int k = 0; k < 4; k++) {
+    U[1 + k] = m.gdet * row[1 + k];
+    U[8 + k] = m.gdet * Ur[k];
+  }
+#pragma unroll
+  for (int i = 0; i < 3; i++) U[5 + i] = th[5 + i];
+}
+
+DEV void adj_implicit_at(Ctx C, double scale, const double* __restrict__ dt_dev,
+                                      const double* __restrict__ Ue, const double* __restrict__ Pk,
+                                      const int* __restrict__ status,
+                                      const double* __restrict__ chi_abs,
+                                      const double* __restrict__ chi_es,
+                                      const double* __restrict__ lamP,
+                                      const double* __restrict__ lamU, double* __restrict__ lamUe, long t) {
+  if (t >= (long)C.n[0] * C.n[1] * C.n[2]) return;
+  int i, j, k;
+  interior_cell(C, t, i, j, k);
+  const long c = cell_index(C, i, j, k);
+  double lp[12], lu[12], th[12], x[4];
+#pragma unroll
+  for (int q = 0; q < 12; q++) {
+    lp[q] = lamP[q * C.Ntot + c];
+    lu[q] = lamU[q * C.Ntot + c];
+    th[q] = Ue[q * C.Ntot + c];
+  }
+  bool ok = !(status[c] & GRRMHD_ST_FAIL);
+  double mu[4];
+  Metric m;
+  load_metric(C.geo_c, C.npos, i + C.N[0] * j, m);
+  Phys ph;
+  ph.gam = C.gam;
+  ph.arad = C.arad;
+  ph.gamma_max = C.gamma_max;
+  ph.ymax = C.ymax;
+  const double dtc = scale * (*dt_dev);
+  const double ca = chi_abs[c], ce = chi_es[c];
+  if (ok) {
+#pragma unroll
+    for (int q = 0; q < 4; q++) x[q] = Pk[(1 + q) * C.Ntot + c];
+    D4 xd[4], thd[12], E[4], Po[12], Uo[12];
+    seed4<4>(x, 0, xd);
+#pragma unroll
+    for (int q = 0; q < 12; q++) thd[q] = D4(th[q]);
+    pmhd_map(m, ph, dtc, ca, ce, xd, thd, E, Po, Uo);
+    double JT[4][4], gx[4];
+#pragma unroll
+    for (int jj = 0; jj < 4; jj++) {
+      double s = 0.0;
+#pragma unroll
+      for (int q = 0; q < 12; q++) s += lp[q] * Po[q].d[jj] + lu[q] * Uo[q].d[jj];
+      gx[jj] = s;
+#pragma unroll
+      for (int kk = 0; kk < 4; kk++) JT[jj][kk] = E[kk].d[jj];
+    }
+    ok = solve4(JT, gx, mu) == 0;
+  }
+  if (!ok) {   // failed cell (or singular Jacobian): U passes through unchanged
+#pragma unroll
+    for (int q = 0; q < 12; q++) lamUe[q * C.Ntot + c] = lu[q];
+    return;
+  }
+  for (int pass = 0; pass < 3; pass++) {
+    D4 xd[4], thd[12], E[4], Po[12], Uo[12];
+#pragma unroll
+    for (int q = 0; q < 4; q++) xd[q] = D4(x[q]);
+    seed4<12>(th, 4 * pass, thd);
+    pmhd_map(m, ph, dtc, ca, ce, xd, thd, E, Po, Uo);
+#pragma unroll
+    for (int jj = 0; jj < 4; jj++) {
+      double s = 0.0;
+#pragma unroll
+      for (int q = 0; q < 12; q++) s += lp[q] * Po[q].d[jj] + lu[q] * Uo[q].d[jj];
+#pragma unroll
+      for (int kk = 0; kk < 4; kk++) s -= mu[kk] * E[kk].d[jj];
+      lamUe[(4 * pass + jj) * C.Ntot + c] = s;
+    }
+  }
+}
+
+__global__ void LB(64) k_adj_implicit(Ctx C, double scale, const double* __restrict__ dt_dev,
+                                      const double* __restrict__ Ue, const double* __restrict__ Pk,
+                                      const int* __restrict__ status,
+                                      const double* __restrict__ chi_abs,
+                                      const double* __restrict__ chi_es,
+                                      const double* __restrict__ lamP,
+                                      const double* __restrict__ lamU, double* __restrict__ lamUe) {
+  adj_implicit_at(C, scale, dt_dev, Ue, Pk, status, chi_abs, chi_es, lamP, lamU, lamUe, (long)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// Fix-up of failed cells: P_f = mean of the face neighbours' P (the good ones;
+// all of them when none is good), U_f = U(P_f).  Transpose: Lam_f =
+// lamP_f + (dU/dP)^T lamU_f, spread back over the neighbours that were
+// averaged; the failed cell's own solve receives nothing.  Floors are taken
+// as the identity.
+// ---------------------------------------------------------------------------
+DEV bool failed_at(const int* st, long c) { return (st[c] & GRRMHD_ST_FAIL) != 0; }
+
+DEV bool interior_idx(const Ctx& C, const int idx[3]) {
+  for (int d = 0; d < 3; d++)
+    if (idx[d] < C.ng[d] || idx[d] >= C.ng[d] + C.n[d]) return false;
+  return true;
+}
+
+// neighbours the fix-up averaged for failed cell f: *good (pass 0) or all
+DEV int fixup_count(const Ctx& C, const int* st, const int idx[3], bool& good_pass) {
+  int good = 0, all = 0;
+  const long c = cell_index(C, idx[0], idx[1], idx[2]);
+  for (int d = 0; d < 3; d++) {
+    if (C.n[d] == 1) continue;
+    for (int s = -1; s <= 1; s += 2) {
+      const int nid = idx[d] + s;
+      if (nid < C.ng[d] || nid >= C.ng[d] + C.n[d]) continue;
+      all++;
+      if (!failed_at(st, c + s * C.st[d])) good++;
+    }
+  }
+  good_pass = good > 0;
+  return good_pass ? good : all;
+}
+
+DEV void adj_fixup_own_at(Ctx C, const double* __restrict__ P, const int* __restrict__ st,
+                          const double* __restrict__ lamP, const double* __restrict__ lamU,
+                          double* __restrict__ Lam, long t) {
+  if (t >= (long)C.n[0] * C.n[1] * C.n[2]) return;
+  int i, j, k;
+  interior_cell(C, t, i, j, k);
+  const long c = cell_index(C, i, j, k);
+  if (!failed_at(st, c)) return;
+  Metric m;
+  load_metric(C.geo_c, C.npos, i + C.N[0] * j, m);
+  double p[12], lu[12];
+#pragma unroll
+  for (int q = 0; q < 12; q++) {
+    p[q] = P[q * C.Ntot + c];
+    lu[q] = lamU[q * C.Ntot + c];
+  }
+  for (int pass = 0; pass < 3; pass++) {
+    D4 pd[12], ud[12];
+    seed4<12>(p, 4 * pass, pd);
+    prim_to_cons_cell(m, C.gam, pd, ud);
+#pragma unroll
+    for (int jj = 0; jj < 4; jj++) {
+      double s = 0.0;
+#pragma unroll
+      for (int q = 0; q < 12; q++) s += lu[q] * ud[q].d[jj];
+      Lam[(4 * pass + jj) * C.Ntot + c] = lamP[(4 * pass + jj) * C.Ntot + c] + s;
+    }
+  }
+}
+
+__global__ void LB(128) k_adj_fixup_own(Ctx C, const double* __restrict__ P,
+                                        const int* __restrict__ st, const double* __restrict__ lamP,
+                                        const double* __restrict__ lamU, double* __restrict__ Lam) {
+  adj_fixup_own_at(C, P, st, lamP, lamU, Lam, (long)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+DEV void adj_fixup_at(Ctx C, const int* __restrict__ st, const double* __restrict__ Lam,
+                      const double* __restrict__ lamP, const double* __restrict__ lamU,
+                      double* __restrict__ lamPpre, double* __restrict__ lamUpre, long t) {
+  if (t >= (long)C.n[0] * C.n[1] * C.n[2]) return;
+  int idx[3];
+  interior_cell(C, t, idx[0], idx[1], idx[2]);
+  const long c = cell_index(C, idx[0], idx[1], idx[2]);
+  const bool fc = failed_at(st, c);
+  double acc[12];
+#pragma unroll
+  for (int q = 0; q < 12; q++) acc[q] = fc ? 0.0 : lamP[q * C.Ntot + c];
+  for (int d = 0; d < 3; d++) {
+    if (C.n[d] == 1) continue;
+    for (int s = -1; s <= 1; s += 2) {
+      int nb[3] = {idx[0], idx[1], idx[2]};
+      nb[d] += s;
+      if (!interior_idx(C, nb)) continue;
+      const long f = c + s * C.st[d];
+      if (!failed_at(st, f)) continue;
+      bool good_pass;
+      const int cnt = fixup_count(C, st, nb, good_pass);
+      if (cnt == 0 || (good_pass && fc)) continue;
+      const double w = 1.0 / cnt;
+#pragma unroll
+      for (int q = 0; q < 12; q++) acc[q] += w * Lam[q * C.Ntot + f];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 12; q++) {
+    lamPpre[q * C.Ntot + c] = acc[q];
+    lamUpre[q * C.Ntot + c] = fc ? 0.0 : lamU[q * C.Ntot + c];
+  }
+}
+
+__global__ void LB(256) k_adj_fixup(Ctx C, const int* __restrict__ st, const double* __restrict__ Lam,
+                                    const double* __restrict__ lamP, const double* __restrict__ lamU,
+                                    double* __restrict__ lamPpre, double* __restrict__ lamUpre) {
+  adj_fixup_at(C, st, Lam, lamP, lamU, lamPpre, lamUpre, (long)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// Linear parts of the stage combination: lamUn += a lamUe, lamUprev = b lamUe
+// ---------------------------------------------------------------------------
+DEV void adj_stage_at(Ctx C, double a, double b, const double* __restrict__ lamUe,
+                                    double* __restrict__ lamUn, double* __restrict__ lamUprev, long t) {
+  if (t >= (long)C.n[0] * C.n[1] * C.n[2]) return;
+  int i, j, k;
+  interior_cell(C, t, i, j, k);
+  const long c = cell_index(C, i, j, k);
+#pragma unroll
+  for (int q = 0; q < 12; q++) {
+    const double l = lamUe[q * C.Ntot + c];
+    lamUn[q * C.Ntot + c] += a * l;
+    lamUprev[q * C.Ntot + c] = b * l;
+  }
+}
+
+__global__ void LB(256) k_adj_stage(Ctx C, double a, double b, const double* __restrict__ lamUe,
+                                    double* __restrict__ lamUn, double* __restrict__ lamUprev) {
+  adj_stage_at(C, a, b, lamUe, lamUn, lamUprev, (long)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// Corner EMFs: cotangent of E_a at the edges of edge range R, gathered from
+// the stage cotangent lamUe (zero outside the interior) through the face
+// induction fluxes the update builds from the EMFs.
+// ---------------------------------------------------------------------------
+DEV void adj_emf_at(Ctx C, int a, FaceRange R, double scale,
+                                  const double* __restrict__ dt_dev,
+                                  const double* __restrict__ lamUe, double* __restrict__ lamE, long t) {
+  if (t >= R.total) return;
+  const int i = R.lo[0] + t % R.cnt[0];
+  const long t2 = t / R.cnt[0];
+  const int j = R.lo[1] + t2 % R.cnt[1];
+  const int k = R.lo[2] + t2 / R.cnt[1];
+  const long e = cell_index(C, i, j, k);
+  const int b = (a + 1) % 3, cd = (a + 2) % 3;
+  double acc = 0.0;
+  bool zero = false;
+  if (C.metric == GRRMHD_KERR_SCHILD && (b == 1 || cd == 1)) {
+    const bool lo = j == C.ng[1] && (C.bc_lo[1] == GRRMHD_BC_REFLECT || C.bc_lo[1] == GRRMHD_BC_POLAR);
+    const bool hi = j == C.ng[1] + C.n[1] && (C.bc_hi[1] == GRRMHD_BC_REFLECT || C.bc_hi[1] == GRRMHD_BC_POLAR);
+    zero = lo || hi;
+  }
+  if (!zero) {
+    const double cdt = scale * (*dt_dev);
+    for (int pair = 0; pair < 2; pair++) {
+      const int d = pair ? cd : b;        // flux direction
+      const int bb = pair ? b : cd;       // field component
+      const double sgn = ((a + 1) % 3 == bb) ? 1.0 : -1.0;
+      const double coef = -cdt / C.dx[d] * 0.5 * sgn;
+      const double* L = lamUe + (5 + bb) * C.Ntot;
+      const long sd = C.st[d], sb = C.st[bb];
+      acc += coef * ((L[e - sd] + L[e - sd - sb]) - (L[e] + L[e - sb]));
+    }
+  }
+  lamE[(long)a * C.Ntot + e] = acc;
+}
+
+__global__ void LB(256) k_adj_emf(Ctx C, int a, FaceRange R, double scale,
+                                  const double* __restrict__ dt_dev,
+                                  const double* __restrict__ lamUe, double* __restrict__ lamE) {
+  adj_emf_at(C, a, R, scale, dt_dev, lamUe, lamE, (long)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// Faces normal to D: the cotangent of the face flux, then its Jacobian with
+// respect to the four stencil cells c-2s, c-s, c, c+s (s the stride along
+// D); the 48 products go to G[(slot*12 + q)][face].
+// ---------------------------------------------------------------------------
+template <int D>
+DEV void adj_flux_at(Ctx C, FaceRange R, double scale,
+                                                 const double* __restrict__ dt_dev,
+                                                 const double* __restrict__ P,
+                                                 const double* __restrict__ chi_abs,
+                                                 const double* __restrict__ chi_es,
+                                                 const double* __restrict__ lamUe,
+                                                 const double* __restrict__ lamE,
+                                                 double* __restrict__ G, long t) {
+  if (t >= R.total) return;
+  const int i = R.lo[0] + t % R.cnt[0];
+  const long t2 = t / R.cnt[0];
+  const int j = R.lo[1] + t2 % R.cnt[1];
+  const int k = R.lo[2] + t2 / R.cnt[1];
+  const long f = cell_index(C, i, j, k);
+  const int d = D - 1;
+  const long st = C.st[d];
+  const double cdt = scale * (*dt_dev);
+  const double idx = 1.0 / C.dx[d];
+  double lF[12];
+#pragma unroll
+  for (int q = 0; q < 12; q++) {
+    const double direct = cdt * idx * (lamUe[q * C.Ntot + f] - lamUe[q * C.Ntot + f - st]);
+    if (q >= 5 && q <= 7) {
+      const int e = q - 5;
+      if (e == d) {
+        lF[q] = 0.0;                       // normal field: no induction flux
+      } else if (C.n[e] > 1) {             // through the corner EMF E_a, a the third axis
+        const int a = 3 - d - e;
+        const double sgn = (d == (a + 2) % 3) ? 0.25 : -0.25;
+        const double* L = lamE + (long)a * C.Ntot;
+        lF[q] = sgn * (L[f] + L[f + C.st[e]]);
+      } else {
+        lF[q] = direct;
+      }
+    } else {
+      lF[q] = direct;
+    }
+  }
+  double sten[4][12];
+#pragma unroll
+  for (int q = 0; q < 12; q++) {
+    const double* p = P + q * C.Ntot;
+    sten[0][q] = p[f - 2 * st];
+    sten[1][q] = p[f - st];
+    sten[2][q] = p[f];
+    sten[3][q] = p[f + st];
+  }
+  double PLR[24];
+#pragma unroll
+  for (int q = 0; q < 12; q++) {
+    const double a = sten[0][q], b = sten[1][q], e = sten[2][q], ff = sten[3][q];
+    PLR[q] = b + 0.5 * mc_slope(b - a, e - b);
+    PLR[12 + q] = e - 0.5 * mc_slope(e - b, ff - e);
+  }
+  Metric m;
+  const double* tab = (D == 1) ? C.geo_f1 : ((D == 2) ? C.geo_f2 : C.geo_c);
+  load_metric(tab, C.npos, i + C.N[0] * j, m);
+  const D4 chiL(chi_abs[f - st] + chi_es[f - st]), chiR(chi_abs[f] + chi_es[f]);
+  double lPLR[24];
+  for (int pass = 0; pass < 6; pass++) {
+    D4 in[24];
+    seed4<24>(PLR, 4 * pass, in);
+    FaceState<D4> L, Rs;
+    face_state(C, m, D, in, chiL, L);
+    face_state(C, m, D, in + 12, chiR, Rs);
+    const D4 zero(0.0);
+    const D4 gmin = -fmin(zero, fmin(L.gm, Rs.gm)), gmax = fmax(zero, fmax(L.gp, Rs.gp));
+    const D4 rmin = -fmin(zero, fmin(L.rm, Rs.rm)), rmax = fmax(zero, fmax(L.rp, Rs.rp));
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int q = 0; q < 12; q++) {
+      if (q == 4 + D) continue;
+      const D4 vmin = q < 8 ? gmin : rmin, vmax = q < 8 ? gmax : rmax;
+      D4 fl;
+      if (C.flux == GRRMHD_FLUX_HLL) {
+        const D4 den = vmin + vmax;
+        fl = (den.v > 0.0) ? (vmin * Rs.F[q] + vmax * L.F[q] - vmin * vmax * (Rs.U[q] - L.U[q])) / den
+                           : 0.5 * (L.F[q] + Rs.F[q]);
+      } else {
+        fl = 0.5 * (Rs.F[q] + L.F[q] - fmax(vmin, vmax) * (Rs.U[q] - L.U[q]));
+      }
+#pragma unroll
+      for (int jj = 0; jj < 4; jj++) acc[jj] += lF[q] * fl.d[jj];
+    }
+#pragma unroll
+    for (int jj = 0; jj < 4; jj++) lPLR[4 * pass + jj] = acc[jj];
+  }
+  // MC reconstruction, per primitive, with respect to the four stencil cells
+#pragma unroll
+  for (int q = 0; q < 12; q++) {
+    const double v[4] = {sten[0][q], sten[1][q], sten[2][q], sten[3][q]};
+    D4 s[4];
+    seed4<4>(v, 0, s);
+    const D4 PL = s[1] + 0.5 * mc_slope(s[1] - s[0], s[2] - s[1]);
+    const D4 PR = s[2] - 0.5 * mc_slope(s[2] - s[1], s[3] - s[2]);
+#pragma unroll
+    for (int slot = 0; slot < 4; slot++)
+      G[(slot * 12 + q) * C.Ntot + f] = lPLR[q] * PL.d[slot] + lPLR[12 + q] * PR.d[slot];
+  }
+}
+
+template <int D>
+__global__ void __launch_bounds__(64) k_adj_flux(Ctx C, FaceRange R, double scale,
+                                                 const double* __restrict__ dt_dev,
+                                                 const double* __restrict__ P,
+                                                 const double* __restrict__ chi_abs,
+                                                 const double* __restrict__ chi_es,
+                                                 const double* __restrict__ lamUe,
+                                                 const double* __restrict__ lamE,
+                                                 double* __restrict__ G) {
+  adj_flux_at<D>(C, R, scale, dt_dev, P, chi_abs, chi_es, lamUe, lamE, G, (long)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// Per allocated cell: gather the stencil products of the faces that read it
+// and, at interior cells, add the geometric source's Jacobian; the result is
+// the cotangent of the stage's ghost-filled input primitives.
+// ---------------------------------------------------------------------------
+struct FaceRanges {
+  FaceRange r[3];
+};
+
+DEV void adj_gather_at(Ctx C, FaceRanges FR, double scale,
+                                     const double* __restrict__ dt_dev,
+                                     const double* __restrict__ P,
+                                     const double* __restrict__ lamUe,
+                                     const double* __restrict__ G1, const double* __restrict__ G2,
+                                     const double* __restrict__ G3, double* __restrict__ lamPb, long c) {
+  if (c >= C.Ntot) return;
+  int idx[3];
+  idx[0] = c % C.N[0];
+  idx[1] = (c / C.N[0]) % C.N[1];
+  idx[2] = c / ((long)C.N[0] * C.N[1]);
+  double acc[12];
+#pragma unroll
+  for (int q = 0; q < 12; q++) acc[q] = 0.0;
+  for (int d = 0; d < 3; d++) {
+    if (C.n[d] == 1) continue;
+    const double* G = (d == 0) ? G1 : ((d == 1) ? G2 : G3);
+    const FaceRange& R = FR.r[d];
+    bool trans = true;
+    for (int e = 0; e < 3; e++)
+      if (e != d && (idx[e] < R.lo[e] || idx[e] >= R.lo[e] + R.cnt[e])) trans = false;
+    if (!trans) continue;
+    for (int slot = 0; slot < 4; slot++) {
+      const int fd = idx[d] + 2 - slot;   // face whose slot-th stencil cell is c
+      if (fd < R.lo[d] || fd >= R.lo[d] + R.cnt[d]) continue;
+      const long f = c + (long)(2 - slot) * C.st[d];
+#pragma unroll
+      for (int q = 0; q < 12; q++) acc[q] += G[(slot * 12 + q) * C.Ntot + f];
+    }
+  }
+  const bool interior = idx[0] >= C.ng[0] && idx[0] < C.ng[0] + C.n[0] && idx[1] >= C.ng[1] &&
+                        idx[1] < C.ng[1] + C.n[1] && idx[2] >= C.ng[2] && idx[2] < C.ng[2] + C.n[2];
+  if (interior && C.metric != GRRMHD_MINKOWSKI) {
+    const int pos = idx[0] + C.N[0] * idx[1];
+    Metric m;
+    load_metric(C.geo_c, C.npos, pos, m);
+    double p[12], lu[12], dg[2][10];
+#pragma unroll
+    for (int q = 0; q < 12; q++) {
+      p[q] = P[q * C.Ntot + c];
+      lu[q] = lamUe[q * C.Ntot + c];
+    }
+    load_dg(C, pos, dg);
+    const double cdt = scale * (*dt_dev);
+    for (int pass = 0; pass < 3; pass++) {
+      D4 pd[12], S[12];
+      seed4<12>(p, 4 * pass, pd);
+      geom_source(m, dg, C.gam, pd, S);
+#pragma unroll
+      for (int jj = 0; jj < 4; jj++) {
+        double s = 0.0;
+#pragma unroll
+        for (int q = 0; q < 12; q++) s += lu[q] * S[q].d[jj];
+        acc[4 * pass + jj] += cdt * s;
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 12; q++) lamPb[q * C.Ntot + c] = acc[q];
+}
+
+__global__ void LB(128) k_adj_gather(Ctx C, FaceRanges FR, double scale,
+                                     const double* __restrict__ dt_dev,
+                                     const double* __restrict__ P,
+                                     const double* __restrict__ lamUe,
+                                     const double* __restrict__ G1, const double* __restrict__ G2,
+                                     const double* __restrict__ G3, double* __restrict__ lamPb) {
+  adj_gather_at(C, FR, scale, dt_dev, P, lamUe, G1, G2, G3, lamPb, (long)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// Transpose of the ghost fill along d: each ghost's cotangent is added to its
+// source cell (sign-flipped where the fill flips), then cleared.  One thread
+// per line along d handles both ends, so no two threads touch one cell.
+// ---------------------------------------------------------------------------
+DEV void adj_bc_at(Ctx C, int d, double* lam, long t) {
+  const int d1 = (d + 1) % 3, d2 = (d + 2) % 3;
+  const int ng = C.ng[d], n = C.n[d];
+  if (t >= (long)C.N[d1] * C.N[d2]) return;
+  const int a = t % C.N[d1];
+  const int b = t / C.N[d1];
+  for (int side = 0; side < 2; side++) {
+    const int bc = side ? C.bc_hi[d] : C.bc_lo[d];
+    for (int m = 0; m < ng; m++) {
+      int cd[3], sd[3];
+      cd[d] = side ? ng + n + m : ng - 1 - m;
+      if (bc == GRRMHD_BC_OUTFLOW) sd[d] = side ? ng + n - 1 : ng;
+      else if (bc == GRRMHD_BC_PERIODIC) sd[d] = side ? ng + m : ng + n - 1 - m;
+      else sd[d] = side ? ng + n - 1 - m : ng + m;
+      cd[d1] = sd[d1] = a;
+      cd[d2] = sd[d2] = b;
+      if (bc == GRRMHD_BC_POLAR && d == 1 && C.n[2] > 1) {
+        const int g3 = C.ng[2], n3 = C.n[2];
+        if (sd[2] < g3 || sd[2] >= g3 + n3) continue;   // filled by the x3 pass
+        sd[2] = g3 + (sd[2] - g3 + n3 / 2) % n3;
+      }
+      const long dst = cell_index(C, cd[0], cd[1], cd[2]);
+      const long src = cell_index(C, sd[0], sd[1], sd[2]);
+      const bool flip = (bc == GRRMHD_BC_REFLECT || bc == GRRMHD_BC_POLAR);
+#pragma unroll
+      for (int q = 0; q < 12; q++) {
+        double v = lam[q * C.Ntot + dst];
+        if (flip && (q == 2 + d || q == 5 + d || q == 9 + d)) v = -v;
+        lam[q * C.Ntot + src] += v;
+        lam[q * C.Ntot + dst] = 0.0;
+      }
+    }
+  }
+}
+
+__global__ void LB(256) k_adj_bc(Ctx C, int d, double* lam) {
+  adj_bc_at(C, d, lam, (long)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+__global__ void LB(256) k_fill_d(double* p, long n, double v) {
+  for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x)
+    p[t] = v;
+}
+
+// interior entries of src into dst, every other entry of dst cleared
+DEV void copy_interior_at(Ctx C, const double* __restrict__ src, double* __restrict__ dst, long c) {
+  if (c >= C.Ntot) return;
+  const int i = c % C.N[0];
+  const int j = (c / C.N[0]) % C.N[1];
+  const int k = c / ((long)C.N[0] * C.N[1]);
+  const bool in = i >= C.ng[0] && i < C.ng[0] + C.n[0] && j >= C.ng[1] && j < C.ng[1] + C.n[1] &&
+                  k >= C.ng[2] && k < C.ng[2] + C.n[2];
+#pragma unroll
+  for (int q = 0; q < 12; q++) dst[q * C.Ntot + c] = in ? src[q * C.Ntot + c] : 0.0;
+}
+
+__global__ void LB(256) k_copy_interior(Ctx C, const double* __restrict__ src, double* __restrict__ dst) {
+  copy_interior_at(C, src, dst, (long)blockIdx.x * blockDim.x + threadIdx.x);
+}

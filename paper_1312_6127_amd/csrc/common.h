@@ -8,7 +8,9 @@
 #include "../../include/grrmhd.h"
 #include "dual.h"
 
+#ifndef DEV
 #define DEV __device__ __forceinline__
+#endif
 
 // Geometry tables: 2-D (x1, x2) arrays broadcast over x3, because both
 // metrics are independent of x3 (phi).  Field-major [field][j][i].

@@ -1,9 +1,10 @@
 // Forward-mode dual numbers carrying N directional derivatives.
 //
 // Used on the device for exact Jacobians: the metric derivatives of the
-// geometry kernel (N = 2: d/dx1, d/dx2) and the 4x4 Jacobian of the PMHD
-// implicit residual (N = 4: d/du_g, d/du~^i).  Every operator propagates
-// the chain rule; sqrt/exp/sin/cos use their analytic derivatives.
+// geometry kernel (N = 2: d/dx1, d/dx2), the 4x4 Jacobian of the PMHD
+// implicit residual (N = 4: d/du_g, d/du~^i), and the local Jacobians of the
+// adjoint step.  Every operator propagates the chain rule; sqrt/exp/sin/cos
+// use their analytic derivatives.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -121,6 +122,32 @@ GR_HD Dual<N> cos(const Dual<N>& a) {
   return r;
 }
 
+// Piecewise functions take the derivative of the branch the value selects
+// (ties: the first argument), as the adjoint of a step differentiates the
+// branch the forward step took.
+template <int N>
+GR_HD Dual<N> fabs(const Dual<N>& a) {
+  return (a.v < 0.0) ? -a : a;
+}
+template <int N>
+GR_HD Dual<N> fmax(const Dual<N>& a, const Dual<N>& b) {
+  return (a.v >= b.v || b.v != b.v) ? a : b;
+}
+template <int N>
+GR_HD Dual<N> fmin(const Dual<N>& a, const Dual<N>& b) {
+  return (a.v <= b.v || b.v != b.v) ? a : b;
+}
+// |a| with the sign of b
+template <int N>
+GR_HD Dual<N> copysign(const Dual<N>& a, const Dual<N>& b) {
+  return (__builtin_signbit(a.v) != __builtin_signbit(b.v)) ? -a : a;
+}
+template <int N> GR_HD bool operator<(const Dual<N>& a, const Dual<N>& b) { return a.v < b.v; }
+template <int N> GR_HD bool operator>(const Dual<N>& a, const Dual<N>& b) { return a.v > b.v; }
+template <int N> GR_HD bool operator<=(const Dual<N>& a, const Dual<N>& b) { return a.v <= b.v; }
+template <int N> GR_HD bool operator>=(const Dual<N>& a, const Dual<N>& b) { return a.v >= b.v; }
+
 // value accessor usable for both double and Dual
 GR_HD double val(double x) { return x; }
+GR_HD float val(float x) { return x; }
 template <int N> GR_HD double val(const Dual<N>& x) { return x.v; }

@@ -8,7 +8,7 @@
 #include <algorithm>
 #include <string>
 
-#include "kernels.h"
+#include "adjoint.h"
 
 struct grrmhd_grid {
   grrmhd_params p;
@@ -541,6 +541,264 @@ extern "C" int grrmhd_step(grrmhd_grid* g, double* P, double* U, const double* c
       return rc;
     if ((rc = launch_fixup(g, Pout, Uout, st, Ue, status, it, iters, s > 0))) return rc;
   }
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// adjoint of one step
+// ---------------------------------------------------------------------------
+struct AdjLayout {
+  size_t F, emf, vch, scr, err, it, Un, Pb, Ue, Pk, Uk, stk, lamP, lamU, lamUe, lamUn, lamPb, lamE,
+      G, Lam, lamPpre, lamUpre, total;
+};
+
+static AdjLayout adj_layout(const Ctx& C) {
+  AdjLayout w;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += (bytes + 255) & ~(size_t)255;
+    return o;
+  };
+  const size_t N = (size_t)C.Ntot, D8 = sizeof(double);
+  w.F = take(D8 * 36 * N);
+  w.emf = take(D8 * 3 * N);
+  w.vch = take(D8 * 3 * N);
+  w.scr = take(D8 * 13 * N);
+  w.err = take(D8 * N);
+  w.it = take(sizeof(int) * N);
+  w.Un = take(D8 * 12 * N);
+  w.Pb = take(D8 * 36 * N);     // per stage: ghost-filled input primitives
+  w.Ue = take(D8 * 36 * N);     // per stage: explicit state U(i)
+  w.Pk = take(D8 * 36 * N);     // per stage: output primitives
+  w.Uk = take(D8 * 36 * N);     // per stage: output conserved
+  w.stk = take(sizeof(int) * 3 * N);
+  w.lamP = take(D8 * 12 * N);
+  w.lamU = take(D8 * 12 * N);
+  w.lamUe = take(D8 * 12 * N);
+  w.lamUn = take(D8 * 12 * N);
+  w.lamPb = take(D8 * 12 * N);
+  w.lamE = take(D8 * 3 * N);
+  w.G = take(D8 * 3 * 48 * N);  // per direction: face products with the 4 stencil cells
+  w.Lam = take(D8 * 12 * N);
+  w.lamPpre = take(D8 * 12 * N);
+  w.lamUpre = take(D8 * 12 * N);
+  w.total = off;
+  return w;
+}
+
+extern "C" size_t grrmhd_adjoint_workspace_bytes(const grrmhd_grid* g) {
+  return g ? adj_layout(g->C).total : 0;
+}
+
+static int fill_d(grrmhd_grid* g, double* p, size_t n, double v) {
+  hipLaunchKernelGGL(k_fill_d, dim3((unsigned)std::min<size_t>((n + 255) / 256, 65536)), dim3(256), 0,
+                     g->stream, p, (long)n, v);
+  LAUNCHCHK();
+  return 0;
+}
+
+// lamUe (all cells; zero outside the interior) from the cotangents of the
+// implicit solve's outputs
+static int adj_implicit(grrmhd_grid* g, double scale, const double* dt_dev, const double* Ue,
+                        const double* Pk, const int* st, const double* ca, const double* ce,
+                        const double* lamP, const double* lamU, double* lamUe) {
+  const Ctx& C = g->C;
+  int rc;
+  if ((rc = fill_d(g, lamUe, 12 * (size_t)C.Ntot, 0.0))) return rc;
+  hipLaunchKernelGGL(k_adj_implicit, dim3(nblocks(n_interior(C), 64)), dim3(64), 0, g->stream, C,
+                     scale, dt_dev, Ue, Pk, st, ca, ce, lamP, lamU, lamUe);
+  LAUNCHCHK();
+  return 0;
+}
+
+// lamPb (every allocated cell) = (d Ue / d Pb)^T lamUe through the fluxes,
+// EMFs and geometric source of a stage with coefficient `scale` on dt
+static int adj_explicit(grrmhd_grid* g, double scale, const double* dt_dev, const double* Pb,
+                        const double* ca, const double* ce, const double* lamUe, double* lamE,
+                        double* G, double* lamPb) {
+  const Ctx& C = g->C;
+  const size_t N = (size_t)C.Ntot;
+  hipStream_t s = g->stream;
+  int rc;
+  if ((rc = fill_d(g, lamE, 3 * N, 0.0))) return rc;
+  for (int a = 0; a < 3; a++) {
+    if (C.n[(a + 1) % 3] == 1 || C.n[(a + 2) % 3] == 1) continue;
+    const FaceRange R = edge_range(C, a);
+    hipLaunchKernelGGL(k_adj_emf, dim3(nblocks(R.total, 256)), dim3(256), 0, s, C, a, R, scale,
+                       dt_dev, lamUe, lamE);
+    LAUNCHCHK();
+  }
+  FaceRanges FR;
+  for (int d = 0; d < 3; d++) FR.r[d] = face_range(C, d);
+  for (int d = 0; d < 3; d++) {
+    if (C.n[d] == 1) continue;
+    const FaceRange& R = FR.r[d];
+    double* Gd = G + (size_t)d * 48 * N;
+    const dim3 gr(nblocks(R.total, 64)), bl(64);
+    if (d == 0)
+      hipLaunchKernelGGL(k_adj_flux<1>, gr, bl, 0, s, C, R, scale, dt_dev, Pb, ca, ce, lamUe,
+                         (const double*)lamE, Gd);
+    if (d == 1)
+      hipLaunchKernelGGL(k_adj_flux<2>, gr, bl, 0, s, C, R, scale, dt_dev, Pb, ca, ce, lamUe,
+                         (const double*)lamE, Gd);
+    if (d == 2)
+      hipLaunchKernelGGL(k_adj_flux<3>, gr, bl, 0, s, C, R, scale, dt_dev, Pb, ca, ce, lamUe,
+                         (const double*)lamE, Gd);
+    LAUNCHCHK();
+  }
+  hipLaunchKernelGGL(k_adj_gather, dim3(nblocks(C.Ntot, 128)), dim3(128), 0, s, C, FR, scale, dt_dev,
+                     Pb, lamUe, (const double*)G, (const double*)(G + 48 * N),
+                     (const double*)(G + 96 * N), lamPb);
+  LAUNCHCHK();
+  return 0;
+}
+
+// transpose of the ghost fill, in place
+static int adj_bc(grrmhd_grid* g, double* lam) {
+  const Ctx& C = g->C;
+  for (int d = 2; d >= 0; d--) {
+    if (C.ng[d] == 0) continue;
+    const long lines = (long)C.N[(d + 1) % 3] * C.N[(d + 2) % 3];
+    hipLaunchKernelGGL(k_adj_bc, dim3(nblocks(lines, 256)), dim3(256), 0, g->stream, C, d, lam);
+    LAUNCHCHK();
+  }
+  return 0;
+}
+
+// Pieces of the adjoint, for callers composing their own sweeps (and for
+// checking each piece against finite differences of its forward part).
+extern "C" int grrmhd_implicit_vjp(grrmhd_grid* g, const double* Uexp, const double* P_out,
+                                   const int* status, double dt_scale, const double* dt_dev,
+                                   const double* chi_abs, const double* chi_es,
+                                   const double* gP_out, const double* gU_out, double* gUexp) {
+  NEEDG();
+  if (!Uexp || !P_out || !status || !dt_dev || !chi_abs || !chi_es || !gP_out || !gU_out || !gUexp)
+    return fail(GRRMHD_EINVAL, "NULL array");
+  return adj_implicit(g, dt_scale, dt_dev, Uexp, P_out, status, chi_abs, chi_es, gP_out, gU_out,
+                      gUexp);
+}
+
+extern "C" size_t grrmhd_explicit_vjp_workspace_bytes(const grrmhd_grid* g) {
+  return g ? sizeof(double) * (size_t)g->C.Ntot * (3 + 144) + 512 : 0;
+}
+
+extern "C" int grrmhd_explicit_vjp(grrmhd_grid* g, double c, const double* dt_dev,
+                                   const double* P, const double* chi_abs, const double* chi_es,
+                                   const double* gUexp, double* gP, void* workspace,
+                                   size_t ws_bytes) {
+  NEEDG();
+  if (!dt_dev || !P || !chi_abs || !chi_es || !gUexp || !gP || !workspace)
+    return fail(GRRMHD_EINVAL, "NULL array");
+  if (ws_bytes < grrmhd_explicit_vjp_workspace_bytes(g)) return fail(GRRMHD_EINVAL, "workspace too small");
+  if (((uintptr_t)workspace) & 255) return fail(GRRMHD_EINVAL, "workspace must be 256-byte aligned");
+  const size_t N = (size_t)g->C.Ntot;
+  double* lamE = (double*)workspace;
+  double* G = (double*)((char*)workspace + (((3 * N * sizeof(double)) + 255) & ~(size_t)255));
+  return adj_explicit(g, c, dt_dev, P, chi_abs, chi_es, gUexp, lamE, G, gP);
+}
+
+extern "C" int grrmhd_bc_vjp(grrmhd_grid* g, double* gP) {
+  NEEDG();
+  if (!gP) return fail(GRRMHD_EINVAL, "NULL array");
+  return adj_bc(g, gP);
+}
+
+extern "C" int grrmhd_step_adjoint(grrmhd_grid* g, const double* P_n, const double* chi_abs,
+                                   const double* chi_es, const double* dt_dev,
+                                   const double* gU_next, double* gP_n, double* P_next,
+                                   double* U_next, void* workspace, size_t ws_bytes) {
+  NEEDG();
+  if (!P_n || !chi_abs || !chi_es || !dt_dev || !gU_next || !gP_n || !workspace)
+    return fail(GRRMHD_EINVAL, "NULL array");
+  const Ctx& C = g->C;
+  const AdjLayout w = adj_layout(C);
+  if (ws_bytes < w.total) return fail(GRRMHD_EINVAL, "workspace too small");
+  if (((uintptr_t)workspace) & 255) return fail(GRRMHD_EINVAL, "workspace must be 256-byte aligned");
+  char* base = (char*)workspace;
+  const size_t N = (size_t)C.Ntot, N12 = 12 * N, B12 = sizeof(double) * N12;
+  double* F = (double*)(base + w.F);
+  double* emf = (double*)(base + w.emf);
+  double* vch = (double*)(base + w.vch);
+  double* scr = (double*)(base + w.scr);
+  double* err = (double*)(base + w.err);
+  int* it = (int*)(base + w.it);
+  double* Un = (double*)(base + w.Un);
+  double* Pb = (double*)(base + w.Pb);
+  double* Ue = (double*)(base + w.Ue);
+  double* Pk = (double*)(base + w.Pk);
+  double* Uk = (double*)(base + w.Uk);
+  int* stk = (int*)(base + w.stk);
+  double* lamP = (double*)(base + w.lamP);
+  double* lamU = (double*)(base + w.lamU);
+  double* lamUe = (double*)(base + w.lamUe);
+  double* lamUn = (double*)(base + w.lamUn);
+  double* lamPb = (double*)(base + w.lamPb);
+  double* lamE = (double*)(base + w.lamE);
+  double* G = (double*)(base + w.G);
+  double* Lam = (double*)(base + w.Lam);
+  double* lamPpre = (double*)(base + w.lamPpre);
+  double* lamUpre = (double*)(base + w.lamUpre);
+  hipStream_t s = g->stream;
+  const double A[3] = {1.0, 0.75, 1.0 / 3.0}, B[3] = {0.0, 0.25, 2.0 / 3.0},
+               Cc[3] = {1.0, 0.25, 2.0 / 3.0};
+  const long nint = n_interior(C);
+  int rc;
+  // forward step with checkpoints (the same launches as grrmhd_step, dt fixed)
+  HIPCHK(hipMemcpyAsync(Pb, P_n, B12, hipMemcpyDeviceToDevice, s));
+  hipLaunchKernelGGL(k_p2u, dim3(nblocks(C.Ntot, 256)), dim3(256), 0, s, C, Pb, Un);
+  LAUNCHCHK();
+  for (int k = 0; k < 3; k++) {
+    double* Pin = Pb + k * N12;
+    double* Uek = Ue + k * N12;
+    double* Pout = Pk + k * N12;
+    double* Uout = Uk + k * N12;
+    int* st = stk + k * N;
+    if (k > 0) HIPCHK(hipMemcpyAsync(Pin, Pk + (k - 1) * N12, B12, hipMemcpyDeviceToDevice, s));
+    if ((rc = launch_bc(g, Pin))) return rc;
+    if ((rc = launch_fluxes(g, Pin, chi_abs, chi_es, F, emf, vch))) return rc;
+    if ((rc = launch_update(g, A[k], B[k], Cc[k], dt_dev, Pin, Un, k == 0 ? Un : Uk + (k - 1) * N12,
+                            F, emf, Uek)))
+      return rc;
+    HIPCHK(hipMemcpyAsync(Pout, Pin, B12, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(Uout, Uek, B12, hipMemcpyDeviceToDevice, s));
+    if ((rc = launch_implicit(g, Uek, Pin, Cc[k], dt_dev, chi_abs, chi_es, Pout, Uout, it, st, err)))
+      return rc;
+    if ((rc = launch_fixup(g, Pout, Uout, st, scr, nullptr, it, nullptr, 0))) return rc;
+  }
+  if (P_next) HIPCHK(hipMemcpyAsync(P_next, Pk + 2 * N12, B12, hipMemcpyDeviceToDevice, s));
+  if (U_next) HIPCHK(hipMemcpyAsync(U_next, Uk + 2 * N12, B12, hipMemcpyDeviceToDevice, s));
+  // reverse sweep
+  const unsigned gi = nblocks(nint, 256), ga = nblocks(C.Ntot, 256);
+  hipLaunchKernelGGL(k_copy_interior, dim3(ga), dim3(256), 0, s, C, gU_next, lamU);
+  LAUNCHCHK();
+  if ((rc = fill_d(g, lamP, N12, 0.0)) || (rc = fill_d(g, lamUn, N12, 0.0))) return rc;
+  for (int k = 2; k >= 0; k--) {
+    const double* Pin = Pb + k * N12;
+    // fix-up of failed cells, then the implicit solve
+    hipLaunchKernelGGL(k_adj_fixup_own, dim3(nblocks(nint, 128)), dim3(128), 0, s, C,
+                       (const double*)(Pk + k * N12), (const int*)(stk + k * N), (const double*)lamP,
+                       (const double*)lamU, Lam);
+    LAUNCHCHK();
+    hipLaunchKernelGGL(k_adj_fixup, dim3(gi), dim3(256), 0, s, C, (const int*)(stk + k * N),
+                       (const double*)Lam, (const double*)lamP, (const double*)lamU, lamPpre, lamUpre);
+    LAUNCHCHK();
+    if ((rc = adj_implicit(g, Cc[k], dt_dev, Ue + k * N12, Pk + k * N12, stk + k * N, chi_abs,
+                           chi_es, lamPpre, lamUpre, lamUe)))
+      return rc;
+    hipLaunchKernelGGL(k_adj_stage, dim3(gi), dim3(256), 0, s, C, A[k], B[k], (const double*)lamUe,
+                       lamUn, lamU);
+    LAUNCHCHK();
+    if ((rc = adj_explicit(g, Cc[k], dt_dev, Pin, chi_abs, chi_es, lamUe, lamE, G, lamPb))) return rc;
+    if ((rc = adj_bc(g, lamPb))) return rc;
+    hipLaunchKernelGGL(k_copy_interior, dim3(ga), dim3(256), 0, s, C, (const double*)lamPb, lamP);
+    LAUNCHCHK();
+  }
+  hipLaunchKernelGGL(k_adj_p2u, dim3(nblocks(nint, 128)), dim3(128), 0, s, C, (const double*)Pb,
+                     (const double*)lamUn, lamP);
+  LAUNCHCHK();
+  hipLaunchKernelGGL(k_copy_interior, dim3(ga), dim3(256), 0, s, C, (const double*)lamP, gP_n);
+  LAUNCHCHK();
   return 0;
 }
 

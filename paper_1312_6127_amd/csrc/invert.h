@@ -6,6 +6,8 @@
 //   RAD (Sec. 4.6): analytic y -> gamma_rad^2 -> p_rad -> v~_rad with the
 //   BASIC or TYPE2 limiter; templated so derivatives flow through it.
 #pragma once
+#include <type_traits>
+
 #include "physics.h"
 
 // spatial inverse metric of the normal observer: g^{ij} - g^{ti} g^{tj}/g^{tt}
@@ -55,7 +57,14 @@ DEV int rad_invert(const Metric& m, double gamma_max, double ymax, int type2, co
   }
   if (yv <= 0.0) {                            // gamma_rad = 1
     Ebar = Erad;
-    ut[0] = ut[1] = ut[2] = T(0.0);
+    if constexpr (std::is_same<T, double>::value) {
+      ut[0] = ut[1] = ut[2] = 0.0;
+    } else {
+      // zero flux: u~ = 3 U~ / (4 E_rad) to first order, so derivatives
+      // with respect to the flux survive
+#pragma unroll
+      for (int i = 0; i < 3; i++) ut[i] = Ut[i] * (0.75 / val(Erad));
+    }
     return flags;
   }
   // eq. ysol, gammarvsy, prsol, tvrsol

@@ -37,9 +37,7 @@ DEV void ks_metric_lower(double a, double R0, const T& x1, const T& x2, T g[10])
   g[sym(3, 3)] = (4.0 * M_PI * M_PI) * s2 * (Sig + (a * a) * (1.0 + z) * s2);
 }
 
-__global__ void LB(256) k_geometry(Ctx C, double a, double R0, double* gc, double* gf1,
-                                   double* gf2) {
-  const int pos = blockIdx.x * blockDim.x + threadIdx.x;
+DEV void geometry_at(Ctx C, double a, double R0, double* gc, double* gf1, double* gf2, int pos) {
   if (pos >= C.npos) return;
   const int i = pos % C.N[0], j = pos / C.N[0];
   for (int loc = 0; loc < 3; loc++) {
@@ -91,14 +89,18 @@ __global__ void LB(256) k_geometry(Ctx C, double a, double R0, double* gc, doubl
   }
 }
 
+__global__ void LB(256) k_geometry(Ctx C, double a, double R0, double* gc, double* gf1,
+                                   double* gf2) {
+  geometry_at(C, a, R0, gc, gf1, gf2, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
 // ---------------------------------------------------------------------------
 // step 1: ghost cells, one dimension per launch
 // ---------------------------------------------------------------------------
-__global__ void LB(256) k_bc(Ctx C, int d, double* P) {
+DEV void bc_at(Ctx C, int d, double* P, long t) {
   const int d1 = (d + 1) % 3, d2 = (d + 2) % 3;
   const int ng = C.ng[d], n = C.n[d];
   const long per_side = (long)ng * C.N[d1] * C.N[d2];
-  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= 2 * per_side) return;
   const int side = t >= per_side;
   long r = side ? t - per_side : t;
@@ -131,17 +133,22 @@ __global__ void LB(256) k_bc(Ctx C, int d, double* P) {
   }
 }
 
+__global__ void LB(256) k_bc(Ctx C, int d, double* P) {
+  bc_at(C, d, P, (long)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
 // ---------------------------------------------------------------------------
 // steps 2-3 helper and P -> U kernel
 // ---------------------------------------------------------------------------
-DEV void prim_to_cons_cell(const Metric& m, double gam, const double* P, double* U) {
-  Gas<double> s;
+template <class T>
+DEV void prim_to_cons_cell(const Metric& m, double gam, const T* P, T* U) {
+  Gas<T> s;
   make_gas(m, gam, P[0], P[1], P + 2, P + 5, s);
-  double row[8];
+  T row[8];
   gas_row(s, P + 5, 0, row);
-  Vel<double> r;
+  Vel<T> r;
   make_vel(m, P + 9, r);
-  double rr[4];
+  T rr[4];
   rad_row(r, P[8], 0, rr);
 #pragma unroll
   for (int q = 0; q < 8; q++) U[q] = m.gdet * row[q];
@@ -149,8 +156,7 @@ DEV void prim_to_cons_cell(const Metric& m, double gam, const double* P, double*
   for (int q = 0; q < 4; q++) U[8 + q] = m.gdet * rr[q];
 }
 
-__global__ void LB(256) k_p2u(Ctx C, const double* __restrict__ P, double* __restrict__ U) {
-  const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+DEV void p2u_at(Ctx C, const double* __restrict__ P, double* __restrict__ U, long c) {
   if (c >= C.Ntot) return;
   const int pos = c % C.npos;
   Metric m;
@@ -163,14 +169,19 @@ __global__ void LB(256) k_p2u(Ctx C, const double* __restrict__ P, double* __res
   for (int q = 0; q < 12; q++) U[q * C.Ntot + c] = u[q];
 }
 
+__global__ void LB(256) k_p2u(Ctx C, const double* __restrict__ P, double* __restrict__ U) {
+  p2u_at(C, P, U, (long)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
 // ---------------------------------------------------------------------------
 // steps 4-7: reconstruction, face physics, wave speeds, HLL / LAXF
 // ---------------------------------------------------------------------------
 template <class T>
 DEV T mc_slope(T dl, T dr) {
-  if (dl * dr <= T(0.0)) return T(0.0);
-  const T dc = T(0.5) * (dl + dr);
-  return copysign(fmin(fabs(dc), T(2.0) * fmin(fabs(dl), fabs(dr))), dc);
+  using R = typename RealOf<T>::type;
+  if (val(dl) * val(dr) <= R(0.0)) return T(R(0.0));
+  const T dc = R(0.5) * (dl + dr);
+  return copysign(fmin(fabs(dc), R(2.0) * fmin(fabs(dl), fabs(dr))), dc);
 }
 
 template <class T>
@@ -179,10 +190,12 @@ struct FaceState {
   T gm, gp, rm, rp;   // gas and radiation characteristic speeds
 };
 
-// T = double, or float on the FP32 face path (metric rounded to float too)
+// T = double, float on the FP32 face path (metric rounded to float too), or
+// Dual<N> for the adjoint
 template <class T>
-DEV void face_state(const Ctx& C, const MetricT<T>& m, int d, const T* P, T chi_tot,
-                    FaceState<T>& fs) {
+DEV void face_state(const Ctx& C, const MetricT<typename RealOf<T>::type>& m, int d, const T* P,
+                    T chi_tot, FaceState<T>& fs) {
+  using R = typename RealOf<T>::type;
   Gas<T> s;
   make_gas(m, C.gam, P[0], P[1], P + 2, P + 5, s);
   T row[8];
@@ -203,15 +216,15 @@ DEV void face_state(const Ctx& C, const MetricT<T>& m, int d, const T* P, T chi_
   for (int q = 0; q < 4; q++) fs.F[8 + q] = m.gdet * rr[q];
   // gas: fast magnetosonic speed c_ms^2 = v_A^2 + c_s^2 (1 - v_A^2)
   const T w = s.rho + s.ug + s.pg;
-  const T cs2 = T(C.gam) * s.pg / w;
+  const T cs2 = R(C.gam) * s.pg / w;
   const T va2 = s.bsq / (w + s.bsq);
-  char_speeds(m, s.v.ucon, va2 + cs2 * (T(1.0) - va2), d, fs.gm, fs.gp);
+  char_speeds(m, s.v.ucon, va2 + cs2 * (R(1.0) - va2), d, fs.gm, fs.gp);
   // radiation: 1/sqrt(3) in the radiation frame, limited to 4/(3 tau) in the gas frame
-  char_speeds(m, r.ucon, T(1.0 / 3.0), d, fs.rm, fs.rp);
-  const T tau = chi_tot * P[0] * sqrt(m.lo(d, d)) * T(C.dx[d - 1]);
-  if (tau > T(0.0)) {
-    const T cl = T(4.0) / (T(3.0) * tau);
-    if (cl < T(1.0)) {
+  char_speeds(m, r.ucon, T(R(1.0 / 3.0)), d, fs.rm, fs.rp);
+  const T tau = chi_tot * P[0] * sqrt(m.lo(d, d)) * R(C.dx[d - 1]);
+  if (val(tau) > R(0.0)) {
+    const T cl = R(4.0) / (R(3.0) * tau);
+    if (val(cl) < R(1.0)) {
       T lm, lp;
       char_speeds(m, s.v.ucon, cl * cl, d, lm, lp);
       fs.rp = fmin(fs.rp, lp);
@@ -229,11 +242,10 @@ struct FaceRange {
 // arithmetic T (double; float for the FP32-mixed path); fluxes and speeds are
 // stored as double.
 template <int D, class T>
-__global__ void LB(128) k_flux(Ctx C, FaceRange R, const double* __restrict__ P,
+DEV void flux_at(Ctx C, FaceRange R, const double* __restrict__ P,
                                const double* __restrict__ chi_abs,
                                const double* __restrict__ chi_es, double* __restrict__ F,
-                               double* __restrict__ vchar) {
-  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+                               double* __restrict__ vchar, long t) {
   if (t >= R.total) return;
   const int i = R.lo[0] + t % R.cnt[0];
   const long t2 = t / R.cnt[0];
@@ -276,14 +288,21 @@ __global__ void LB(128) k_flux(Ctx C, FaceRange R, const double* __restrict__ P,
   vchar[c] = (double)fmax(fmax(gmin, gmax), fmax(rmin, rmax));
 }
 
+template <int D, class T>
+__global__ void LB(128) k_flux(Ctx C, FaceRange R, const double* __restrict__ P,
+                               const double* __restrict__ chi_abs,
+                               const double* __restrict__ chi_es, double* __restrict__ F,
+                               double* __restrict__ vchar) {
+  flux_at<D, T>(C, R, P, chi_abs, chi_es, F, vchar, (long)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
 // ---------------------------------------------------------------------------
 // step 9 (flux-CT): corner EMF along a = average of the four adjacent face
 // induction fluxes, emf_a = F_c[B_b] = -F_b[B_c] for cyclic (a, b, c)
 // ---------------------------------------------------------------------------
 template <class T>
-__global__ void LB(256) k_emf(Ctx C, int a, FaceRange R, const double* __restrict__ F,
-                              double* __restrict__ emf) {
-  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+DEV void emf_at(Ctx C, int a, FaceRange R, const double* __restrict__ F,
+                              double* __restrict__ emf, long t) {
   if (t >= R.total) return;
   const int i = R.lo[0] + t % R.cnt[0];
   const long t2 = t / R.cnt[0];
@@ -303,26 +322,66 @@ __global__ void LB(256) k_emf(Ctx C, int a, FaceRange R, const double* __restric
   emf[(long)a * C.Ntot + c] = (double)e;
 }
 
+template <class T>
+__global__ void LB(256) k_emf(Ctx C, int a, FaceRange R, const double* __restrict__ F,
+                              double* __restrict__ emf) {
+  emf_at<T>(C, a, R, F, emf, (long)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
 // ---------------------------------------------------------------------------
 // step 10: explicit stage combination with flux divergence and geometry
 // source.  The source uses sqrt(-g) T^k_l Gamma^l_{nu k} =
 // (1/2) sqrt(-g) T^{k m} d_nu g_{k m}; both metrics are independent of t and
 // x3, so only nu = 1, 2 contribute.
 // ---------------------------------------------------------------------------
-DEV double contract_sym(const double* dg, const double u[4], const double v[4]) {
-  double s = 0.0;
+template <class T>
+DEV T contract_sym(const double* dg, const T u[4], const T v[4]) {
+  T s = T(0.0);
 #pragma unroll
   for (int a = 0; a < 4; a++)
 #pragma unroll
-    for (int b = 0; b < 4; b++) s += u[a] * v[b] * dg[sym(a, b)];
+    for (int b = 0; b < 4; b++) s = s + u[a] * v[b] * dg[sym(a, b)];
   return s;
 }
 
-__global__ void LB(256) k_update(Ctx C, double ca, double cb, double cc, const double* dt_dev,
+// Geometric source of the cell with primitives p: S[q] = 0 except the
+// x1, x2 momentum slots of gas and radiation (dg: d g_{km}/dx1, d/dx2).
+template <class T>
+DEV void geom_source(const Metric& m, const double dg[2][10], double gam, const T p[12], T S[12]) {
+#pragma unroll
+  for (int q = 0; q < 12; q++) S[q] = T(0.0);
+  Gas<T> s;
+  make_gas(m, gam, p[0], p[1], p + 2, p + 5, s);
+  Vel<T> r;
+  make_vel(m, p + 9, r);
+  const T enth = s.rho + s.ug + s.pg + s.bsq, ptot = s.pg + 0.5 * s.bsq;
+  for (int nu = 1; nu <= 2; nu++) {
+    const double* g = dg[nu - 1];
+    double trace = 0.0;   // g^{km} d_nu g_{km}
+#pragma unroll
+    for (int a = 0; a < 4; a++)
+#pragma unroll
+      for (int b = 0; b < 4; b++) trace += m.up(a, b) * g[sym(a, b)];
+    const T sg = enth * contract_sym(g, s.v.ucon, s.v.ucon) + ptot * trace -
+                 contract_sym(g, s.bcon, s.bcon);
+    const T sr = (4.0 / 3.0) * p[8] * contract_sym(g, r.ucon, r.ucon) + (1.0 / 3.0) * p[8] * trace;
+    S[1 + nu] = 0.5 * m.gdet * sg;
+    S[8 + nu] = 0.5 * m.gdet * sr;
+  }
+}
+
+DEV void load_dg(const Ctx& C, int pos, double dg[2][10]) {
+#pragma unroll
+  for (int q = 0; q < 10; q++) {
+    dg[0][q] = C.geo_c[(GE_DG1 + q) * C.npos + pos];
+    dg[1][q] = C.geo_c[(GE_DG2 + q) * C.npos + pos];
+  }
+}
+
+DEV void update_at(Ctx C, double ca, double cb, double cc, const double* dt_dev,
                                  const double* __restrict__ P, const double* __restrict__ Un,
                                  const double* __restrict__ Uprev, const double* __restrict__ F,
-                                 const double* __restrict__ emf, double* __restrict__ Uexp) {
-  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+                                 const double* __restrict__ emf, double* __restrict__ Uexp, long t) {
   const long nint = (long)C.n[0] * C.n[1] * C.n[2];
   if (t >= nint) return;
   const int i = C.ng[0] + t % C.n[0];
@@ -338,30 +397,11 @@ __global__ void LB(256) k_update(Ctx C, double ca, double cb, double cc, const d
     const int pos = i + C.N[0] * j;
     Metric m;
     load_metric(C.geo_c, C.npos, pos, m);
-    double p[12];
+    double p[12], dg[2][10];
 #pragma unroll
     for (int q = 0; q < 12; q++) p[q] = P[q * C.Ntot + c];
-    Gas<double> s;
-    make_gas(m, C.gam, p[0], p[1], p + 2, p + 5, s);
-    Vel<double> r;
-    make_vel(m, p + 9, r);
-    const double enth = s.rho + s.ug + s.pg + s.bsq, ptot = s.pg + 0.5 * s.bsq;
-    for (int nu = 1; nu <= 2; nu++) {
-      double dg[10];
-      const int base = (nu == 1) ? GE_DG1 : GE_DG2;
-#pragma unroll
-      for (int q = 0; q < 10; q++) dg[q] = C.geo_c[(base + q) * C.npos + pos];
-      double trace = 0.0;   // g^{km} d_nu g_{km}
-#pragma unroll
-      for (int a = 0; a < 4; a++)
-#pragma unroll
-        for (int b = 0; b < 4; b++) trace += m.up(a, b) * dg[sym(a, b)];
-      const double sg = enth * contract_sym(dg, s.v.ucon, s.v.ucon) + ptot * trace -
-                        contract_sym(dg, s.bcon, s.bcon);
-      const double sr = (4.0 / 3.0) * p[8] * contract_sym(dg, r.ucon, r.ucon) + (1.0 / 3.0) * p[8] * trace;
-      S[1 + nu] = 0.5 * m.gdet * sg;
-      S[8 + nu] = 0.5 * m.gdet * sr;
-    }
+    load_dg(C, pos, dg);
+    geom_source(m, dg, C.gam, p, S);
   }
   double div[12];
 #pragma unroll
@@ -400,6 +440,13 @@ __global__ void LB(256) k_update(Ctx C, double ca, double cb, double cc, const d
     if (cb != 0.0) u += cb * Uprev[q * C.Ntot + c];
     Uexp[q * C.Ntot + c] = u + cc * dt * (S[q] - div[q]);
   }
+}
+
+__global__ void LB(256) k_update(Ctx C, double ca, double cb, double cc, const double* dt_dev,
+                                 const double* __restrict__ P, const double* __restrict__ Un,
+                                 const double* __restrict__ Uprev, const double* __restrict__ F,
+                                 const double* __restrict__ emf, double* __restrict__ Uexp) {
+  update_at(C, ca, cb, cc, dt_dev, P, Un, Uprev, F, emf, Uexp, (long)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -705,9 +752,8 @@ __global__ void LB(128) k_con2prim(Ctx C, const double* __restrict__ U, const do
 // step 13 and floors.  Pass 1 averages failed cells' face neighbours into
 // scratch; pass 2 applies averages and floors and recomputes U where P changed.
 // ---------------------------------------------------------------------------
-__global__ void LB(256) k_fixup_avg(Ctx C, const double* __restrict__ P,
-                                    const int* __restrict__ status, double* __restrict__ scr) {
-  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+DEV void fixup_avg_at(Ctx C, const double* __restrict__ P,
+                                    const int* __restrict__ status, double* __restrict__ scr, long t) {
   const long nint = (long)C.n[0] * C.n[1] * C.n[2];
   if (t >= nint) return;
   int idx[3];
@@ -745,11 +791,15 @@ __global__ void LB(256) k_fixup_avg(Ctx C, const double* __restrict__ P,
   scr[12 * C.Ntot + c] = 0.0;
 }
 
-__global__ void LB(256) k_fixup_apply(Ctx C, double* __restrict__ P, double* __restrict__ U,
+__global__ void LB(256) k_fixup_avg(Ctx C, const double* __restrict__ P,
+                                    const int* __restrict__ status, double* __restrict__ scr) {
+  fixup_avg_at(C, P, status, scr, (long)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+DEV void fixup_apply_at(Ctx C, double* __restrict__ P, double* __restrict__ U,
                                       int* __restrict__ status, const double* __restrict__ scr,
                                       int* __restrict__ st_acc, const int* __restrict__ it_stage,
-                                      int* __restrict__ it_acc, int accumulate) {
-  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+                                      int* __restrict__ it_acc, int accumulate, long t) {
   const long nint = (long)C.n[0] * C.n[1] * C.n[2];
   if (t >= nint) return;
   const int i = C.ng[0] + t % C.n[0];
@@ -793,6 +843,13 @@ __global__ void LB(256) k_fixup_apply(Ctx C, double* __restrict__ P, double* __r
   status[c] = st;
   if (st_acc) st_acc[c] = accumulate ? (st_acc[c] | st) : st;
   if (it_acc && it_stage) it_acc[c] = accumulate ? it_acc[c] + it_stage[c] : it_stage[c];
+}
+
+__global__ void LB(256) k_fixup_apply(Ctx C, double* __restrict__ P, double* __restrict__ U,
+                                      int* __restrict__ status, const double* __restrict__ scr,
+                                      int* __restrict__ st_acc, const int* __restrict__ it_stage,
+                                      int* __restrict__ it_acc, int accumulate) {
+  fixup_apply_at(C, P, U, status, scr, st_acc, it_stage, it_acc, accumulate, (long)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------

@@ -136,19 +136,21 @@ DEV void four_force(const Vel<T>& u, const Vel<T>& r, const T& E, const T& kabs,
 // frame of 4-velocity u: the two roots of
 // [(1-c2)(u^t)^2 - c2 g^tt] v^2 - 2[(1-c2) u^t u^d - c2 g^td] v + [(1-c2)(u^d)^2 - c2 g^dd] = 0
 // (the dispersion relation (k.u)^2 = c2 (k.k + (k.u)^2) with k = d(x^d - v t)).
-template <class R>
-DEV void char_speeds(const MetricT<R>& m, const R u[4], R c2, int dir, R& vm, R& vp) {
-  const R A = (R(1.0) - c2) * u[0] * u[0] - c2 * m.up(0, 0);
-  const R B = (R(1.0) - c2) * u[0] * u[dir] - c2 * m.up(0, dir);
+template <class T>
+DEV void char_speeds(const MetricT<typename RealOf<T>::type>& m, const T u[4], T c2, int dir,
+                     T& vm, T& vp) {
+  using R = typename RealOf<T>::type;
+  const T A = (R(1.0) - c2) * u[0] * u[0] - c2 * m.up(0, 0);
+  const T B = (R(1.0) - c2) * u[0] * u[dir] - c2 * m.up(0, dir);
   // discriminant B^2 - A C = c2 [(1 - c2) h + c2 k]: the (1 - c2)^2 (u^t u^d)^2
   // parts cancel exactly, so a tiny c2 (optically thick limiter) loses nothing
-  const R h = u[0] * u[0] * m.up(dir, dir) - R(2.0) * u[0] * u[dir] * m.up(0, dir) +
+  const T h = u[0] * u[0] * m.up(dir, dir) - R(2.0) * u[0] * u[dir] * m.up(0, dir) +
               u[dir] * u[dir] * m.up(0, 0);
   const R k = m.up(0, dir) * m.up(0, dir) - m.up(0, 0) * m.up(dir, dir);
-  const R disc = fmax(c2 * ((R(1.0) - c2) * h + c2 * k), R(0.0));
-  const R sq = sqrt(disc);
-  const R ia = R(1.0) / A;
-  const R v1 = (B + sq) * ia, v2 = (B - sq) * ia;
+  const T disc = fmax(c2 * ((R(1.0) - c2) * h + c2 * k), T(R(0.0)));
+  const T sq = sqrt(disc);
+  const T ia = R(1.0) / A;
+  const T v1 = (B + sq) * ia, v2 = (B - sq) * ia;
   vp = fmax(v1, v2);
   vm = fmin(v1, v2);
 }

@@ -96,6 +96,12 @@ def lib():
             "grrmhd_fixup": (C.c_int, [_VP] * 5),
             "grrmhd_step": (C.c_int, [_VP, _VP, _VP, _VP, _VP, _VP, C.c_int, _VP, _VP, _VP,
                                       C.c_size_t]),
+            "grrmhd_adjoint_workspace_bytes": (C.c_size_t, [_VP]),
+            "grrmhd_step_adjoint": (C.c_int, [_VP] * 10 + [C.c_size_t]),
+            "grrmhd_implicit_vjp": (C.c_int, [_VP, _VP, _VP, _VP, C.c_double] + [_VP] * 6),
+            "grrmhd_explicit_vjp_workspace_bytes": (C.c_size_t, [_VP]),
+            "grrmhd_explicit_vjp": (C.c_int, [_VP, C.c_double] + [_VP] * 7 + [C.c_size_t]),
+            "grrmhd_bc_vjp": (C.c_int, [_VP, _VP]),
             "grrmhd_implicit_source_workspace_bytes": (C.c_size_t, [C.c_long]),
             "grrmhd_implicit_source": (C.c_int, [PP, C.c_long] + [_VP] * 11 + [C.c_size_t, _VP]),
             "grrmhd_implicit_source_workspace_bytes_ex": (C.c_size_t, [C.c_long, C.c_int]),
@@ -225,6 +231,51 @@ class Grid:
         _check(lib().grrmhd_implicit_stats(self.h, out))
         return tuple(int(v) for v in out)
 
+    def adjoint_workspace(self):
+        if getattr(self, "_aws", None) is None:
+            nb = lib().grrmhd_adjoint_workspace_bytes(self.h)
+            raw = torch.empty(nb + 256, dtype=torch.uint8, device="cuda")
+            off = (-raw.data_ptr()) % 256
+            self._aws = (raw[off:off + nb], nb)
+        return self._aws
+
+    def step_adjoint(self, P, chi_abs, chi_es, dt, gU, want_next=False):
+        """dL/dP^n for L = sum(gU * U^{n+1}(P^n)), dt (1-element device
+        tensor) held fixed and U^n = U(P^n).  Returns gP, or (gP, P^{n+1},
+        U^{n+1}) with want_next."""
+        self._sync_stream()
+        ws, nb = self.adjoint_workspace()
+        gP = torch.empty_like(P)
+        Pn = torch.empty_like(P) if want_next else None
+        Un = torch.empty_like(P) if want_next else None
+        _check(lib().grrmhd_step_adjoint(self.h, _ptr(P), _ptr(chi_abs), _ptr(chi_es), _ptr(dt),
+                                         _ptr(gU), _ptr(gP), _ptr(Pn), _ptr(Un), _ptr(ws), nb))
+        return (gP, Pn, Un) if want_next else gP
+
+    def implicit_vjp(self, Uexp, P_out, status, dt_scale, dt, chi_abs, chi_es, gP, gU):
+        self._sync_stream()
+        gUe = torch.empty_like(Uexp)
+        _check(lib().grrmhd_implicit_vjp(self.h, _ptr(Uexp), _ptr(P_out), _ptr(status), dt_scale,
+                                         _ptr(dt), _ptr(chi_abs), _ptr(chi_es), _ptr(gP), _ptr(gU),
+                                         _ptr(gUe)))
+        return gUe
+
+    def explicit_vjp(self, c, dt, P, chi_abs, chi_es, gUe):
+        self._sync_stream()
+        nb = lib().grrmhd_explicit_vjp_workspace_bytes(self.h)
+        raw = torch.empty(nb + 256, dtype=torch.uint8, device=P.device)
+        off = (-raw.data_ptr()) % 256
+        ws = raw[off:off + nb]
+        gP = torch.empty_like(P)
+        _check(lib().grrmhd_explicit_vjp(self.h, c, _ptr(dt), _ptr(P), _ptr(chi_abs), _ptr(chi_es),
+                                         _ptr(gUe), _ptr(gP), _ptr(ws), nb))
+        return gP
+
+    def bc_vjp(self, gP):
+        self._sync_stream()
+        _check(lib().grrmhd_bc_vjp(self.h, _ptr(gP)))
+        return gP
+
     def time_implicit(self, on: bool):
         """Start (clearing the record) or stop HIP-event timing of the
         implicit kernel's launches on this grid's stream."""
@@ -318,3 +369,27 @@ def batch_stats(ws):
     out = (C.c_ulonglong * 3)()
     _check(lib().grrmhd_implicit_source_stats(_ptr(ws[0]), out, _stream()))
     return tuple(int(v) for v in out)
+
+
+class GRRMHDStep(torch.autograd.Function):
+    """U^{n+1} = step(P^n) with dt fixed, differentiable in P^n through the
+    library's hand-written adjoint (grrmhd_step_adjoint).
+
+    GRRMHDStep.apply(grid, P, chi_abs, chi_es, dt) -> U_next; the backward
+    returns dL/dP at interior cells (ghost entries zero)."""
+
+    @staticmethod
+    def forward(ctx, grid, P, chi_abs, chi_es, dt):
+        Pc = P.detach().contiguous()
+        Pw = Pc.clone()
+        Uw = grid.prim_to_cons(Pw)
+        grid.step(Pw, Uw, chi_abs, chi_es, dt, dt_fixed=True)
+        ctx.grid = grid
+        ctx.save_for_backward(Pc, chi_abs, chi_es, dt)
+        return Uw
+
+    @staticmethod
+    def backward(ctx, gU):
+        Pc, chi_abs, chi_es, dt = ctx.saved_tensors
+        gP = ctx.grid.step_adjoint(Pc, chi_abs, chi_es, dt, gU.contiguous())
+        return None, gP, None, None, None

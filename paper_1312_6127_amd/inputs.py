@@ -292,3 +292,21 @@ def random_states(n: int, seed: int, gmax: float = 50.0, bsq_rho_max: float = 1e
     grad = 10.0 ** (math.log10(20.0) * u[9])
     P[F1:F3 + 1] = np.sqrt(grad * grad - 1.0) * direction(u[10], u[11])
     return P
+
+
+def jitter(P, seed: int, rel: float = 1e-3):
+    """A copy of P with seeded relative noise on every primitive, absolute
+    noise of rel x max|B| on the field and rel on the radiation velocity:
+    removes the exact ties (equal neighbours, zero field or flux) at which
+    the limiters and wave-speed extrema are not differentiable, for
+    finite-difference checks of derivatives."""
+    c = np.arange(P.shape[1], dtype=np.int64)
+    z = np.stack([np.sqrt(-2.0 * np.log(uniform(seed, c, 2 * q) + 1e-300)) *
+                  np.cos(2.0 * math.pi * uniform(seed, c, 2 * q + 1)) for q in range(12)])
+    out = P * (1.0 + rel * z)
+    sc = np.abs(P[B1:B3 + 1]).max() + rel
+    zb = np.stack([np.sqrt(-2.0 * np.log(uniform(seed + 1, c, 2 * q) + 1e-300)) *
+                   np.cos(2.0 * math.pi * uniform(seed + 1, c, 2 * q + 1)) for q in range(6)])
+    out[B1:B3 + 1] += rel * sc * zb[:3]
+    out[F1:F3 + 1] += rel * zb[3:]
+    return out

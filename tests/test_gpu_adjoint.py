@@ -1,0 +1,270 @@
+"""Adjoint of the step (HIP, through the C ABI) against central finite
+differences of the GPU step and of the FP64 oracle's step.
+
+Finite differences: h = 1e-6 x max(|P|, 1e-3 max|P_q|) per component, the
+per-element differences U(P + h) - U(P - h) weighted and summed (not the
+difference of two sums, which would cancel).  Inputs are jittered (seeded
+relative noise 1e-3) so that no limiter or wave-speed extremum sits exactly
+on a tie, where the step is not differentiable.  The figure of merit over a
+sample of components is ||g_adj - g_fd|| / ||g_fd|| (the sample's 2-norm).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1312_6127_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def G():
+    from paper_1312_6127_amd import grrmhd
+
+    grrmhd.lib()
+    assert torch.cuda.is_available()
+    return grrmhd
+
+
+def dev(x):
+    return torch.tensor(np.ascontiguousarray(x), device="cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def interior_idx(pd):
+    m = np.zeros(I.nalloc(pd)[::-1], dtype=bool)
+    m[I.interior(pd)] = True
+    return np.flatnonzero(m.reshape(-1))
+
+
+def box():
+    from test_oracle_pins import _periodic_box
+
+    pd, P, ca, ce = _periodic_box((8, 6, 4), seed=7)
+    return pd, I.jitter(P, 11), ca, ce
+
+
+def disk_small():
+    pd, P, ca, ce = I.accretion_disk(n=(12, 8, 4), seed=3)
+    return pd, I.jitter(P, 11), ca, ce
+
+
+def disk_c5():
+    pd, P, ca, ce = I.accretion_disk(n=(96, 48, 24), seed=3)
+    return pd, I.jitter(P, 11), ca, ce
+
+
+def step_dt(G, g, P, cat, cet):
+    """dt of a first step from P (then held fixed)."""
+    dt = torch.zeros(1, dtype=torch.float64, device="cuda")
+    Pw = dev(P)
+    Uw = g.prim_to_cons(Pw)
+    st = torch.zeros(g.N, dtype=torch.int32, device="cuda")
+    g.step(Pw, Uw, cat, cet, dt, status=st)
+    return dt, int(((host(st) & G.ST_FAIL) != 0).sum())
+
+
+def fd_rows(comps, P, scale, U_of, w):
+    rows = []
+    for q, c in comps:
+        h = 1e-6 * max(abs(P[q, c]), 1e-3 * scale[q], 1e-12)
+        Pp, Pm = P.copy(), P.copy()
+        Pp[q, c] += h
+        Pm[q, c] -= h
+        rows.append(float(((U_of(Pp) - U_of(Pm)) * w).sum() / (2 * h)))
+    return np.array(rows)
+
+
+def norm_err(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def test_bc_vjp_is_the_transpose(G):
+    say("case bc transpose")
+    for pd, P, ca, ce in (box(), disk_small()):
+        g = G.Grid(pd)
+        r = np.random.default_rng(1)
+        x, y = r.standard_normal(P.shape), r.standard_normal(P.shape)
+        Bx = host(g.apply_bc(dev(x)))
+        BTy = host(g.bc_vjp(dev(y)))
+        assert abs((Bx * y).sum() - (x * BTy).sum()) < 1e-12 * np.abs(Bx * y).sum()
+        g.close()
+
+
+def test_implicit_vjp_against_fd(G, orc):
+    """Implicit-function-theorem VJP of the per-cell solve against central
+    differences of the solve itself (cell-local)."""
+    say("case implicit vjp")
+    pd, P, ca, ce = box()
+    g = G.Grid(pd)
+    cat, cet = dev(ca), dev(ce)
+    Pb = orc.bc(pd, P)
+    F, emf, vch = orc.fluxes(pd, Pb, ca, ce)
+    dtv = orc.timestep(pd, vch)
+    dt = dev(np.array([dtv]))
+    U = orc.prim_to_cons(pd, Pb)
+    Ue = orc.explicit_update(pd, 1.0, 0.0, 1.0, dtv, Pb, U, U, F, emf)
+    Pk, Uk, it, st, err = g.implicit(dev(Ue), dev(Pb), 1.0, dt, cat, cet)
+    idx = interior_idx(pd)
+    r = np.random.default_rng(2)
+    lp, lu = np.zeros_like(P), np.zeros_like(P)
+    lp[:, idx] = r.standard_normal((12, idx.size))
+    lu[:, idx] = r.standard_normal((12, idx.size))
+    gUe = host(g.implicit_vjp(dev(Ue), Pk, st, 1.0, dt, cat, cet, dev(lp), dev(lu)))
+    assert np.all(gUe[:, np.setdiff1d(np.arange(P.shape[1]), idx)] == 0.0)
+    scale = np.abs(Ue[:, idx]).max(axis=1)
+    adj, fd = [], []
+    for _ in range(40):
+        q, c = int(r.integers(12)), int(idx[r.integers(idx.size)])
+        h = 1e-6 * max(abs(Ue[q, c]), 1e-3 * scale[q])
+        outs = []
+        for s in (1, -1):
+            Up = Ue.copy()
+            Up[q, c] += s * h
+            a, b, *_ = g.implicit(dev(Up), dev(Pb), 1.0, dt, cat, cet)
+            outs.append((host(a)[:, c], host(b)[:, c]))
+        fd.append(((outs[0][0] - outs[1][0]) * lp[:, c]).sum() / (2 * h) +
+                  ((outs[0][1] - outs[1][1]) * lu[:, c]).sum() / (2 * h))
+        adj.append(gUe[q, c])
+    adj, fd = np.array(adj), np.array(fd)
+    e = norm_err(adj, fd)
+    say("  implicit vjp norm error", e)
+    assert e < 1e-7
+    g.close()
+
+
+def test_explicit_vjp_against_fd(G):
+    """Fluxes + EMFs + update, with respect to the ghost-filled primitives."""
+    say("case explicit vjp")
+    pd, P, ca, ce = box()
+    g = G.Grid(pd)
+    cat, cet = dev(ca), dev(ce)
+    Pb = host(g.apply_bc(dev(P)))
+    dt = dev(np.array([0.01]))
+    Ut = g.prim_to_cons(dev(Pb))
+    idx = interior_idx(pd)
+    r = np.random.default_rng(3)
+    lue = np.zeros_like(P)
+    lue[:, idx] = r.standard_normal((12, idx.size))
+    gP = host(g.explicit_vjp(0.25, dt, dev(Pb), cat, cet, dev(lue)))
+
+    def Ue_of(Pp):
+        Pt = dev(Pp)
+        F, emf, vch = g.fluxes(Pt, cat, cet)
+        return host(g.explicit_update(0.75, 0.25, 0.25, dt, Pt, Ut, Ut, F, emf))
+
+    scale = np.abs(Pb).max(axis=1)
+    comps = [(int(r.integers(12)), int(r.integers(P.shape[1]))) for _ in range(60)]
+    fd = fd_rows(comps, Pb, scale, Ue_of, lue)
+    adj = np.array([gP[q, c] for q, c in comps])
+    e = norm_err(adj, fd)
+    say("  explicit vjp norm error", e)
+    assert e < 1e-7
+    g.close()
+
+
+def _step_check(G, orc, pd, P, ca, ce, ncomp, n_oracle, tol):
+    g = G.Grid(pd)
+    cat, cet = dev(ca), dev(ce)
+    dt, nfail = step_dt(G, g, P, cat, cet)
+    idx = interior_idx(pd)
+    r = np.random.default_rng(5)
+    w = np.zeros_like(P)
+    w[:, idx] = r.standard_normal((12, idx.size))
+    gP, Pn, Un = g.step_adjoint(dev(P), cat, cet, dt, dev(w), want_next=True)
+    gP = host(gP)
+    # the forward result the adjoint reports is the step itself
+    Pw = dev(P)
+    Uw = g.prim_to_cons(Pw)
+    g.step(Pw, Uw, cat, cet, dt, dt_fixed=True)
+    assert np.array_equal(host(Un)[:, idx], host(Uw)[:, idx])
+    assert np.all(gP[:, np.setdiff1d(np.arange(P.shape[1]), idx)] == 0.0)
+
+    def U_gpu(Pp):
+        Pw = dev(Pp)
+        Uw = g.prim_to_cons(Pw)
+        g.step(Pw, Uw, cat, cet, dt, dt_fixed=True)
+        return host(Uw)[:, idx]
+
+    scale = np.abs(P[:, idx]).max(axis=1)
+    comps = [(int(r.integers(12)), int(idx[r.integers(idx.size)])) for _ in range(ncomp)]
+    adj = np.array([gP[q, c] for q, c in comps])
+    fdg = fd_rows(comps, P, scale, U_gpu, w[:, idx])
+    eg = norm_err(adj, fdg)
+    rel = np.abs(adj - fdg) / np.abs(fdg)
+    say(f"  failed cells {nfail}; vs GPU FD: norm {eg:.3e} median {np.median(rel):.3e}")
+    assert eg < tol and np.median(rel) < tol
+    if n_oracle:
+        dtv = host(dt)[0]
+
+        def U_orc(Pp):
+            Up = orc.prim_to_cons(pd, Pp)
+            P1, U1, *_ = orc.step(pd, Pp, Up, ca, ce, dt=dtv, dt_fixed=True)
+            return U1[:, idx]
+
+        fdo = fd_rows(comps[:n_oracle], P, scale, U_orc, w[:, idx])
+        eo = norm_err(adj[:n_oracle], fdo)
+        say(f"  vs oracle FD ({n_oracle} components): norm {eo:.3e}")
+        assert eo < tol
+    g.close()
+
+
+def test_step_adjoint_box(G, orc):
+    say("case step adjoint, periodic Minkowski box")
+    _step_check(G, orc, *box(), ncomp=64, n_oracle=64, tol=1e-6)
+
+
+def test_step_adjoint_kerr_schild_96x48x24(G, orc):
+    """The 96x48x24 Kerr-Schild step (a = 0.9375): 64 random components
+    against GPU finite differences, 16 of them against the oracle's."""
+    say("case step adjoint, Kerr-Schild 96x48x24")
+    _step_check(G, orc, *disk_c5(), ncomp=64, n_oracle=16, tol=1e-6)
+
+
+def test_autograd_function(G):
+    """GRRMHDStep: forward equals grid.step with dt fixed; backward's
+    gradient gives the directional derivative along a random direction."""
+    say("case autograd")
+    pd, P, ca, ce = box()
+    g = G.Grid(pd)
+    cat, cet = dev(ca), dev(ce)
+    dt, _ = step_dt(G, g, P, cat, cet)
+    idx = interior_idx(pd)
+    r = np.random.default_rng(7)
+    w = np.zeros_like(P)
+    w[:, idx] = r.standard_normal((12, idx.size))
+    Pt = dev(P).requires_grad_(True)
+    U1 = G.GRRMHDStep.apply(g, Pt, cat, cet, dt)
+    L = (U1 * dev(w)).sum()
+    L.backward()
+    gP = host(Pt.grad)
+    ref = host(g.step_adjoint(dev(P), cat, cet, dt, dev(w)))
+    assert np.array_equal(gP, ref)
+    # a direction on the 12 primitives of two cells (a direction on many
+    # cells crosses limiter kinks somewhere for any usable h)
+    v = np.zeros_like(P)
+    cells = idx[r.choice(idx.size, 2, replace=False)]
+    v[:, cells] = r.standard_normal((12, cells.size)) * np.abs(P[:, idx]).max(axis=1)[:, None]
+    h = 1e-6
+
+    def L_of(Pp):
+        with torch.no_grad():
+            return G.GRRMHDStep.apply(g, dev(Pp), cat, cet, dt)
+
+    dd = float(((host(L_of(P + h * v)) - host(L_of(P - h * v))) * w).sum() / (2 * h))
+    ad = float((gP * v).sum())
+    say("  directional derivative fd", dd, "adjoint", ad)
+    assert abs(dd - ad) < 1e-5 * abs(dd)
+    g.close()
