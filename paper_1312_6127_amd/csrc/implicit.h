@@ -16,6 +16,8 @@
 #pragma once
 #include <float.h>
 
+#include <type_traits>
+
 #include "invert.h"
 
 #ifndef GRRMHD_NJ
@@ -101,19 +103,22 @@ DEV void norm_errors(const Cell& c, const double Tg[4], const double Rr[4], cons
 
 // PMHD residual (Sec. 4.8, PMHD steps in order): rho0 = (rho u^t)/u^t;
 // T^t_nu from the gas; Delta R = -Delta T; TYPE2 radiation inversion; R
-// recomputed; G; residuals.  One pass seeds Jacobian columns k0..k0+N-1.
-template <int N>
+// recomputed; G; residuals.  With D = Dual<N> one pass seeds Jacobian
+// columns k0..k0+N-1; with D = double it evaluates the residual alone.
+template <class D>
 DEV void pmhd_pass(const Cell& c, const Phys& ph, const double x[4], int k0, Eval& e,
                    double J[4][4]) {
-  typedef Dual<N> D;
   D ug(x[0]), ut[3] = {D(x[1]), D(x[2]), D(x[3])};
+  if constexpr (!std::is_same<D, double>::value) {
+    constexpr int N = sizeof(D::d) / sizeof(double);
 #pragma unroll
-  for (int j = 0; j < N; j++) {
-    const int k = k0 + j;
-    if (k == 0) ug.d[j] = 1.0;
-    if (k == 1) ut[0].d[j] = 1.0;
-    if (k == 2) ut[1].d[j] = 1.0;
-    if (k == 3) ut[2].d[j] = 1.0;
+    for (int j = 0; j < N; j++) {
+      const int k = k0 + j;
+      if (k == 0) ug.d[j] = 1.0;
+      if (k == 1) ut[0].d[j] = 1.0;
+      if (k == 2) ut[1].d[j] = 1.0;
+      if (k == 3) ut[2].d[j] = 1.0;
+    }
   }
   D B[3] = {D(c.B[0]), D(c.B[1]), D(c.B[2])};
   Gas<D> s;
@@ -144,26 +149,29 @@ DEV void pmhd_pass(const Cell& c, const Phys& ph, const double x[4], int k0, Eva
 #pragma unroll
   for (int k = 0; k < 4; k++) {
     const D Egk = (row[1 + k] - c.Tgi[k]) - c.dt * G[k];
-    Tg[k] = row[1 + k].v;
-    Rr[k] = Rrow[k].v;
-    Gv[k] = G[k].v;
-    e.Eg[k] = Egk.v;
+    Tg[k] = val(row[1 + k]);
+    Rr[k] = val(Rrow[k]);
+    Gv[k] = val(G[k]);
+    e.Eg[k] = val(Egk);
     e.Er[k] = (Rr[k] - c.Ri[k]) + c.dt * Gv[k];
+    if constexpr (!std::is_same<D, double>::value) {
+      constexpr int N = sizeof(D::d) / sizeof(double);
 #pragma unroll
-    for (int j = 0; j < N; j++) J[k][k0 + j] = Egk.d[j];
+      for (int j = 0; j < N; j++) J[k][k0 + j] = Egk.d[j];
+    }
   }
   if (k0 == 0) {
 #pragma unroll
     for (int k = 0; k < 4; k++) e.x[k] = x[k];
-    e.P[0] = s.rho.v;
+    e.P[0] = val(s.rho);
     e.P[1] = x[0];
 #pragma unroll
     for (int i = 0; i < 3; i++) {
       e.P[2 + i] = x[1 + i];
       e.P[5 + i] = c.B[i];
-      e.P[9 + i] = utr[i].v;
+      e.P[9 + i] = val(utr[i]);
     }
-    e.P[8] = Eb.v;
+    e.P[8] = val(Eb);
     e.ok = 1;
     norm_errors(c, Tg, Rr, Gv, e);
   }
@@ -171,7 +179,13 @@ DEV void pmhd_pass(const Cell& c, const Phys& ph, const double x[4], int k0, Eva
 
 DEV void eval_pmhd(const Cell& c, const Phys& ph, const double x[4], Eval& e, double J[4][4]) {
 #pragma unroll
-  for (int k0 = 0; k0 < 4; k0 += GRRMHD_NJ) pmhd_pass<GRRMHD_NJ>(c, ph, x, k0, e, J);
+  for (int k0 = 0; k0 < 4; k0 += GRRMHD_NJ) pmhd_pass<Dual<GRRMHD_NJ>>(c, ph, x, k0, e, J);
+}
+
+// Residual alone: a Newton step close to the root reuses the factorised
+// Jacobian of the previous evaluation (chord step).
+DEV void eval_pmhd_value(const Cell& c, const Phys& ph, const double x[4], Eval& e) {
+  pmhd_pass<double>(c, ph, x, 0, e, nullptr);
 }
 
 // gas (T^t_t + rho u^t, T^t_i) of primitives P, without sqrt(-g)
@@ -277,6 +291,65 @@ DEV int solve4(double A[4][4], double b[4], double xo[4]) {
   return 0;
 }
 
+// The same elimination split in two: LU with partial pivoting in place
+// (multipliers stored below the diagonal in the row positions of their own
+// step), then the solve; lu4 + lu_solve4 give solve4's result bit for bit,
+// and the factors can be reused for further right-hand sides.
+DEV int lu4(double A[4][4], int piv[4]) {
+#pragma unroll
+  for (int k = 0; k < 4; k++) {
+    int p = k;
+    double best = ::fabs(A[k][k]);
+#pragma unroll
+    for (int i = k + 1; i < 4; i++)
+      if (::fabs(A[i][k]) > best) { best = ::fabs(A[i][k]); p = i; }
+    if (!(best > 0.0) || !isfinite(best)) return 1;
+    piv[k] = p;
+    if (p != k) {
+#pragma unroll
+      for (int j = k; j < 4; j++) { const double t = A[k][j]; A[k][j] = A[p][j]; A[p][j] = t; }
+    }
+    const double inv = 1.0 / A[k][k];
+#pragma unroll
+    for (int i = k + 1; i < 4; i++) {
+      const double f = A[i][k] * inv;
+#pragma unroll
+      for (int j = k + 1; j < 4; j++) A[i][j] -= f * A[k][j];
+      A[i][k] = f;
+    }
+  }
+  return 0;
+}
+
+DEV int lu_solve4(const double A[4][4], const int piv[4], double b[4], double xo[4]) {
+#pragma unroll
+  for (int k = 0; k < 4; k++) {
+    if (piv[k] != k) {
+#pragma unroll
+      for (int p = k + 1; p < 4; p++)
+        if (p == piv[k]) { const double t = b[k]; b[k] = b[p]; b[p] = t; }
+    }
+#pragma unroll
+    for (int i = k + 1; i < 4; i++) b[i] -= A[i][k] * b[k];
+  }
+#pragma unroll
+  for (int i = 3; i >= 0; i--) {
+    double s = b[i];
+#pragma unroll
+    for (int j = i + 1; j < 4; j++) s -= A[i][j] * xo[j];
+    xo[i] = s / A[i][i];
+  }
+#pragma unroll
+  for (int i = 0; i < 4; i++)
+    if (!isfinite(xo[i])) return 1;
+  return 0;
+}
+
+// Below this error the PMHD Newton step keeps the factorised Jacobian of the
+// last full evaluation and evaluates the residual alone (chord step): near
+// the root the Jacobian changes by O(e_T) between iterates.
+#define GRRMHD_CHORD_TOL 1e-6
+
 DEV double rad_energy_lab(const Metric& m, const double R[4]) {
   return -R[0] + m.alpha * m.alpha * (m.up(0, 1) * R[1] + m.up(0, 2) * R[2] + m.up(0, 3) * R[3]);
 }
@@ -307,6 +380,8 @@ DEV void newton(const Cell& c, const Phys& ph, const Opts& o, const double x0[4]
   double x[4] = {x0[0], x0[1], x0[2], x0[3]};
   Eval ev;
   double J[4][4];
+  int piv[4] = {0, 1, 2, 3};
+  bool fresh = true;   // PMHD: J holds a new Jacobian, not yet factorised
   if (METHOD == M_PMHD) eval_pmhd(c, ph, x, ev, J);
   else eval_urad(c, ph, x, Pg0, ev);
   keep(best, ev);
@@ -359,13 +434,26 @@ DEV void newton(const Cell& c, const Phys& ph, const Opts& o, const double x0[4]
       for (int i = 0; i < 4; i++) r[i] = ev.Eg[i];
     }
     double dx[4];
-    if (solve4(J, r, dx)) break;
+    if (METHOD == M_PMHD) {
+      if (fresh) {
+        if (lu4(J, piv)) break;
+        fresh = false;
+      }
+      if (lu_solve4(J, piv, r, dx)) break;
+    } else {
+      if (solve4(J, r, dx)) break;
+    }
     double xn[4];
 #pragma unroll
     for (int i = 0; i < 4; i++) xn[i] = x[i] - dx[i];
     if (METHOD == M_PMHD) {
       if (xn[0] < 0.0) xn[0] = 0.5 * ::fabs(xn[0]);            // one-sided bisection of u_g
-      eval_pmhd(c, ph, xn, ev, J);
+      if (ev.eT < GRRMHD_CHORD_TOL) {
+        eval_pmhd_value(c, ph, xn, ev);
+      } else {
+        eval_pmhd(c, ph, xn, ev, J);
+        fresh = true;
+      }
     } else {
       const double Erl = rad_energy_lab(c.m, xn);
       if (Erl <= 0.0) {                                       // same for the radiation energy
@@ -652,10 +740,11 @@ DEV void implicit_cell(const Metric& m, const Phys& ph, const Opts& o, const dou
 struct Lane {
   double x[4];
   double Eg[4], eT;        // residual and error of the current iterate
-  double J[4][4];
+  double J[4][4];          // Jacobian, or its LU factors once factorised
   Best best;
   double h[5];
   int it, nrise, extra, conv, iters, status;
+  int piv[4], fresh, chord;  // pivots; J not yet factorised; next evaluation is a chord step
 };
 
 enum { TRIP_CONTINUE = 0, TRIP_DONE = 1, TRIP_CASCADE = 2 };
@@ -671,11 +760,27 @@ DEV bool lane_step(const Cell& c, const Opts& o, Lane& L) {
   }
   if (!L.conv && L.it >= 5 && L.eT > 0.5 * (L.h[0] + L.h[1] + L.h[2]) * (1.0 / 3.0)) return true;
   double r[4] = {L.Eg[0], L.Eg[1], L.Eg[2], L.Eg[3]}, dx[4];
-  if (solve4(L.J, r, dx)) return true;
+  if (L.fresh) {
+    if (lu4(L.J, L.piv)) return true;
+    L.fresh = 0;
+  }
+  if (lu_solve4(L.J, L.piv, r, dx)) return true;
 #pragma unroll
   for (int i = 0; i < 4; i++) L.x[i] -= dx[i];
   if (L.x[0] < 0.0) L.x[0] = 0.5 * ::fabs(L.x[0]);
+  L.chord = L.eT < GRRMHD_CHORD_TOL;
   return false;
+}
+
+// The evaluation at the lane's new iterate: residual alone on a chord step,
+// else residual and Jacobian.
+DEV void lane_eval(const Cell& c, const Phys& ph, Lane& L, Eval& ev) {
+  if (L.chord) {
+    eval_pmhd_value(c, ph, L.x, ev);
+  } else {
+    eval_pmhd(c, ph, L.x, ev, L.J);
+    L.fresh = 1;
+  }
 }
 
 // Part B after evaluating at the new iterate (xprev: the previous iterate).
@@ -708,6 +813,10 @@ DEV void lane_take(const Eval& ev, Lane& L) {
 }
 
 DEV void lane_start(const Eval& ev, Lane& L) {
+  L.fresh = 1;
+  L.chord = 0;
+#pragma unroll
+  for (int k = 0; k < 4; k++) L.piv[k] = k;
   keep(L.best, ev);
 #pragma unroll
   for (int k = 0; k < 4; k++) L.h[k] = INFINITY;

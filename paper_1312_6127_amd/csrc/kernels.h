@@ -962,11 +962,12 @@ __global__ void LBP k_implicit_persist(Ctx C, long n, const double* __restrict__
     }
     if (doeval) {
       Eval ev;
-      eval_pmhd(c, ph, L.x, ev, L.J);
       if (first) {
+        eval_pmhd(c, ph, L.x, ev, L.J);
         lane_start(ev, L);
         if (!ev.ok) ended = true;
       } else {
+        lane_eval(c, ph, L, ev);
         lane_take(ev, L);
         ended = lane_after(ev, xprev, L);
       }
@@ -994,7 +995,8 @@ __global__ void LBP k_implicit_persist(Ctx C, long n, const double* __restrict__
 // Lane state kept in HBM between per-iteration launches, field-major [f][n].
 enum { LS_X = 0, LS_EG = 4, LS_ET = 8, LS_J = 9, LS_BX = 25, LS_BP = 29, LS_BET = 41, LS_H = 42,
        LS_ND = 47 };
-enum { LI_BRAD = 0, LI_BOK, LI_IT, LI_NRISE, LI_EXTRA, LI_CONV, LI_ITERS, LI_STATUS, LI_NI };
+enum { LI_BRAD = 0, LI_BOK, LI_IT, LI_NRISE, LI_EXTRA, LI_CONV, LI_ITERS, LI_STATUS, LI_PIV,
+       LI_FRESH = LI_PIV + 4, LI_NI };
 
 DEV void lane_save(const Lane& L, long c, long n, double* sd, int* si) {
 #pragma unroll
@@ -1019,6 +1021,9 @@ DEV void lane_save(const Lane& L, long c, long n, double* sd, int* si) {
   si[LI_CONV * n + c] = L.conv;
   si[LI_ITERS * n + c] = L.iters;
   si[LI_STATUS * n + c] = L.status;
+#pragma unroll
+  for (int k = 0; k < 4; k++) si[(LI_PIV + k) * n + c] = L.piv[k];
+  si[LI_FRESH * n + c] = L.fresh;
 }
 
 DEV void lane_load(Lane& L, long c, long n, const double* sd, const int* si) {
@@ -1044,6 +1049,10 @@ DEV void lane_load(Lane& L, long c, long n, const double* sd, const int* si) {
   L.conv = si[LI_CONV * n + c];
   L.iters = si[LI_ITERS * n + c];
   L.status = si[LI_STATUS * n + c];
+#pragma unroll
+  for (int k = 0; k < 4; k++) L.piv[k] = si[(LI_PIV + k) * n + c];
+  L.fresh = si[LI_FRESH * n + c];
+  L.chord = 0;
 }
 
 // first trip of every cell: guess, first evaluation; active cells to queue
@@ -1124,7 +1133,7 @@ __global__ void LB(64) k_iter_step(Ctx C, long n, const double* __restrict__ Ui_
       if (!ended) {
         trips = 1;
         Eval ev;
-        eval_pmhd(c, ph, L.x, ev, L.J);
+        lane_eval(c, ph, L, ev);
         lane_take(ev, L);
         ended = lane_after(ev, xprev, L);
       }
