@@ -276,12 +276,8 @@ extern "C" size_t grrmhd_workspace_bytes(const grrmhd_grid* g) {
 // ---------------------------------------------------------------------------
 static int launch_bc(grrmhd_grid* g, double* P) {
   const Ctx& C = g->C;
-  for (int d = 0; d < 3; d++) {
-    if (C.ng[d] == 0) continue;
-    const long n = 2L * C.ng[d] * C.N[(d + 1) % 3] * C.N[(d + 2) % 3];
-    hipLaunchKernelGGL(k_bc, dim3(nblocks(n, 256)), dim3(256), 0, g->stream, C, d, P);
-    LAUNCHCHK();
-  }
+  hipLaunchKernelGGL(k_bc_all, dim3(nblocks(C.Ntot, 256)), dim3(256), 0, g->stream, C, P);
+  LAUNCHCHK();
   return 0;
 }
 
@@ -350,17 +346,19 @@ static int launch_fluxes(grrmhd_grid* g, const double* P, const double* ca, cons
     if (d == 2) flux_dir<3>(g, R, P, ca, ce, Fd, vd);
     LAUNCHCHK();
   }
-  for (int a = 0; a < 3; a++) {
-    const int b = (a + 1) % 3, c = (a + 2) % 3;
-    if (C.n[b] == 1 || C.n[c] == 1) continue;
-    FaceRange r64, r32;
-    split_x1(edge_range(C, a), C.mixed_i, r64, r32);
-    if (r64.total > 0)
-      hipLaunchKernelGGL(k_emf<double>, dim3(nblocks(r64.total, 256)), dim3(256), 0, g->stream, C,
-                         a, r64, F, emf);
-    if (r32.total > 0)
-      hipLaunchKernelGGL(k_emf<float>, dim3(nblocks(r32.total, 256)), dim3(256), 0, g->stream, C,
-                         a, r32, F, emf);
+  // corner EMFs: union of the edge ranges (n + 1 positions along active axes)
+  bool any = false;
+  for (int a = 0; a < 3; a++) any = any || (C.n[(a + 1) % 3] > 1 && C.n[(a + 2) % 3] > 1);
+  if (any) {
+    FaceRange R;
+    R.total = 1;
+    for (int e = 0; e < 3; e++) {
+      R.lo[e] = C.ng[e];
+      R.cnt[e] = C.n[e] > 1 ? C.n[e] + 1 : 1;
+      R.total *= R.cnt[e];
+    }
+    hipLaunchKernelGGL(k_emf_all, dim3(nblocks(R.total, 256)), dim3(256), 0, g->stream, C, R, F,
+                       emf);
     LAUNCHCHK();
   }
   return 0;

@@ -5,6 +5,9 @@
 #include "implicit.h"
 
 #define LB(n) __launch_bounds__(n)
+#ifndef GRRMHD_FLUX_LB
+#define GRRMHD_FLUX_LB __launch_bounds__(128)
+#endif
 #ifndef GRRMHD_IMP_WAVES
 #define GRRMHD_IMP_WAVES 1   // minimum waves per SIMD asked of the implicit kernels
 #endif
@@ -95,46 +98,49 @@ __global__ void LB(256) k_geometry(Ctx C, double a, double R0, double* gc, doubl
 }
 
 // ---------------------------------------------------------------------------
-// step 1: ghost cells, one dimension per launch
+// step 1: ghost cells
 // ---------------------------------------------------------------------------
-DEV void bc_at(Ctx C, int d, double* P, long t) {
-  const int d1 = (d + 1) % 3, d2 = (d + 2) % 3;
-  const int ng = C.ng[d], n = C.n[d];
-  const long per_side = (long)ng * C.N[d1] * C.N[d2];
-  if (t >= 2 * per_side) return;
-  const int side = t >= per_side;
-  long r = side ? t - per_side : t;
-  const int m = r % ng;
-  r /= ng;
-  const int a = r % C.N[d1];
-  const int b = r / C.N[d1];
-  const int bc = side ? C.bc_hi[d] : C.bc_lo[d];
-  int cd[3], sd[3];
-  cd[d] = side ? ng + n + m : ng - 1 - m;
-  if (bc == GRRMHD_BC_OUTFLOW) sd[d] = side ? ng + n - 1 : ng;
-  else if (bc == GRRMHD_BC_PERIODIC) sd[d] = side ? ng + m : ng + n - 1 - m;
-  else sd[d] = side ? ng + n - 1 - m : ng + m;
-  cd[d1] = sd[d1] = a;
-  cd[d2] = sd[d2] = b;
-  if (bc == GRRMHD_BC_POLAR && d == 1 && C.n[2] > 1) {
-    // across the axis: phi + pi; x3 ghosts are filled by the later x3 pass
-    const int g3 = C.ng[2], n3 = C.n[2];
-    if (sd[2] < g3 || sd[2] >= g3 + n3) return;
-    sd[2] = g3 + (sd[2] - g3 + n3 / 2) % n3;
+// All ghost cells in one pass: the fill dimension by dimension (x1, then x2,
+// then x3, each pass copying whole planes including earlier ghosts) composed
+// into one source cell and sign per ghost cell.  Applying the maps from the
+// last dimension back to the first gives the cell whose interior value the
+// three passes carry into the ghost.
+DEV void bc_all_at(Ctx C, double* P, long c) {
+  if (c >= C.Ntot) return;
+  int idx[3];
+  idx[0] = c % C.N[0];
+  idx[1] = (c / C.N[0]) % C.N[1];
+  idx[2] = c / ((long)C.N[0] * C.N[1]);
+  int sd[3] = {idx[0], idx[1], idx[2]};
+  int flip = 0;
+  bool ghost = false;
+  for (int d = 2; d >= 0; d--) {
+    const int ng = C.ng[d], n = C.n[d];
+    if (ng == 0 || (sd[d] >= ng && sd[d] < ng + n)) continue;
+    ghost = true;
+    const int side = sd[d] >= ng + n;
+    const int m = side ? sd[d] - ng - n : ng - 1 - sd[d];
+    const int bc = side ? C.bc_hi[d] : C.bc_lo[d];
+    if (bc == GRRMHD_BC_OUTFLOW) sd[d] = side ? ng + n - 1 : ng;
+    else if (bc == GRRMHD_BC_PERIODIC) sd[d] = side ? ng + m : ng + n - 1 - m;
+    else sd[d] = side ? ng + n - 1 - m : ng + m;
+    if (bc == GRRMHD_BC_REFLECT || bc == GRRMHD_BC_POLAR) flip ^= 1 << d;
+    if (bc == GRRMHD_BC_POLAR && d == 1 && C.n[2] > 1)   // across the axis: phi + pi
+      sd[2] = C.ng[2] + (sd[2] - C.ng[2] + C.n[2] / 2) % C.n[2];
   }
-  const long dst = cell_index(C, cd[0], cd[1], cd[2]);
+  if (!ghost) return;
   const long src = cell_index(C, sd[0], sd[1], sd[2]);
-  const bool flip = (bc == GRRMHD_BC_REFLECT || bc == GRRMHD_BC_POLAR);
 #pragma unroll
   for (int q = 0; q < 12; q++) {
     double v = P[q * C.Ntot + src];
-    if (flip && (q == 2 + d || q == 5 + d || q == 9 + d)) v = -v;
-    P[q * C.Ntot + dst] = v;
+    const int dq = (q >= 2 && q <= 4) ? q - 2 : ((q >= 5 && q <= 7) ? q - 5 : ((q >= 9) ? q - 9 : -1));
+    if (dq >= 0 && (flip >> dq & 1)) v = -v;
+    P[q * C.Ntot + c] = v;
   }
 }
 
-__global__ void LB(256) k_bc(Ctx C, int d, double* P) {
-  bc_at(C, d, P, (long)blockIdx.x * blockDim.x + threadIdx.x);
+__global__ void LB(256) k_bc_all(Ctx C, double* P) {
+  bc_all_at(C, P, (long)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -289,7 +295,7 @@ DEV void flux_at(Ctx C, FaceRange R, const double* __restrict__ P,
 }
 
 template <int D, class T>
-__global__ void LB(128) k_flux(Ctx C, FaceRange R, const double* __restrict__ P,
+__global__ void GRRMHD_FLUX_LB k_flux(Ctx C, FaceRange R, const double* __restrict__ P,
                                const double* __restrict__ chi_abs,
                                const double* __restrict__ chi_es, double* __restrict__ F,
                                double* __restrict__ vchar) {
@@ -301,13 +307,8 @@ __global__ void LB(128) k_flux(Ctx C, FaceRange R, const double* __restrict__ P,
 // induction fluxes, emf_a = F_c[B_b] = -F_b[B_c] for cyclic (a, b, c)
 // ---------------------------------------------------------------------------
 template <class T>
-DEV void emf_at(Ctx C, int a, FaceRange R, const double* __restrict__ F,
-                              double* __restrict__ emf, long t) {
-  if (t >= R.total) return;
-  const int i = R.lo[0] + t % R.cnt[0];
-  const long t2 = t / R.cnt[0];
-  const int j = R.lo[1] + t2 % R.cnt[1];
-  const int k = R.lo[2] + t2 / R.cnt[1];
+DEV void emf_edge(const Ctx& C, int a, int i, int j, int k, const double* __restrict__ F,
+                  double* __restrict__ emf) {
   const long c = cell_index(C, i, j, k);
   const int b = (a + 1) % 3, cd = (a + 2) % 3;
   const double* Fb = F + (long)b * 12 * C.Ntot + (long)(5 + cd) * C.Ntot;   // F_b[B_c]
@@ -322,10 +323,28 @@ DEV void emf_at(Ctx C, int a, FaceRange R, const double* __restrict__ F,
   emf[(long)a * C.Ntot + c] = (double)e;
 }
 
-template <class T>
-__global__ void LB(256) k_emf(Ctx C, int a, FaceRange R, const double* __restrict__ F,
-                              double* __restrict__ emf) {
-  emf_at<T>(C, a, R, F, emf, (long)blockIdx.x * blockDim.x + threadIdx.x);
+// Every corner EMF in one pass: position (i, j, k) in the union of the edge
+// ranges, each orientation a whose other two axes are active and whose range
+// holds the position; FP32 arithmetic from x1 index mixed_i on.
+DEV void emf_all_at(Ctx C, FaceRange R, const double* __restrict__ F, double* __restrict__ emf,
+                    long t) {
+  if (t >= R.total) return;
+  const int i = R.lo[0] + t % R.cnt[0];
+  const long t2 = t / R.cnt[0];
+  const int j = R.lo[1] + t2 % R.cnt[1];
+  const int k = R.lo[2] + t2 / R.cnt[1];
+  const int idx[3] = {i, j, k};
+  for (int a = 0; a < 3; a++) {
+    if (C.n[(a + 1) % 3] == 1 || C.n[(a + 2) % 3] == 1) continue;
+    if (idx[a] >= C.ng[a] + C.n[a]) continue;
+    if (i < C.mixed_i) emf_edge<double>(C, a, i, j, k, F, emf);
+    else emf_edge<float>(C, a, i, j, k, F, emf);
+  }
+}
+
+__global__ void LB(256) k_emf_all(Ctx C, FaceRange R, const double* __restrict__ F,
+                                  double* __restrict__ emf) {
+  emf_all_at(C, R, F, emf, (long)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
