@@ -315,35 +315,34 @@ static void split_x1(const FaceRange& R, int i0, FaceRange& a, FaceRange& b) {
   b.total = (long)b.cnt[0] * b.cnt[1] * b.cnt[2];
 }
 
-template <int D, class T>
-static void flux_launch(grrmhd_grid* g, const FaceRange& R, const double* P, const double* ca,
-                        const double* ce, double* Fd, double* vd) {
-  if (R.total <= 0) return;
-  hipLaunchKernelGGL((k_flux<D, T>), dim3(nblocks(R.total, 128)), dim3(128), 0, g->stream, g->C,
-                     R, P, ca, ce, Fd, vd);
-}
-
-template <int D>
-static void flux_dir(grrmhd_grid* g, const FaceRange& R, const double* P, const double* ca,
-                     const double* ce, double* Fd, double* vd) {
-  FaceRange r64, r32;
-  split_x1(R, g->C.mixed_i, r64, r32);
-  flux_launch<D, double>(g, r64, P, ca, ce, Fd, vd);
-  flux_launch<D, float>(g, r32, P, ca, ce, Fd, vd);
-}
-
 static int launch_fluxes(grrmhd_grid* g, const double* P, const double* ca, const double* ce,
                          double* F, double* emf, double* vch) {
   const Ctx& C = g->C;
-  const size_t N = (size_t)C.Ntot;
+  // faces of every direction, FP64 part and FP32 part (split at mixed_i)
+  FluxSegs S64, S32;
+  S64.n = S32.n = 0;
+  S64.total = S32.total = 0;
   for (int d = 0; d < 3; d++) {
     if (C.n[d] == 1) continue;
-    FaceRange R = face_range(C, d);
-    double* Fd = F + (size_t)d * 12 * N;
-    double* vd = vch + (size_t)d * N;
-    if (d == 0) flux_dir<1>(g, R, P, ca, ce, Fd, vd);
-    if (d == 1) flux_dir<2>(g, R, P, ca, ce, Fd, vd);
-    if (d == 2) flux_dir<3>(g, R, P, ca, ce, Fd, vd);
+    FaceRange r64, r32;
+    split_x1(face_range(C, d), C.mixed_i, r64, r32);
+    if (r64.total > 0) {
+      S64.R[S64.n] = r64; S64.D[S64.n] = d + 1; S64.start[S64.n] = S64.total;
+      S64.total += r64.total; S64.n++;
+    }
+    if (r32.total > 0) {
+      S32.R[S32.n] = r32; S32.D[S32.n] = d + 1; S32.start[S32.n] = S32.total;
+      S32.total += r32.total; S32.n++;
+    }
+  }
+  if (S64.total > 0) {
+    hipLaunchKernelGGL(k_flux_all<double>, dim3(nblocks(S64.total, 128)), dim3(128), 0, g->stream,
+                       C, S64, P, ca, ce, F, vch);
+    LAUNCHCHK();
+  }
+  if (S32.total > 0) {
+    hipLaunchKernelGGL(k_flux_all<float>, dim3(nblocks(S32.total, 128)), dim3(128), 0, g->stream,
+                       C, S32, P, ca, ce, F, vch);
     LAUNCHCHK();
   }
   // corner EMFs: union of the edge ranges (n + 1 positions along active axes)

@@ -348,7 +348,9 @@ DEV int lu_solve4(const double A[4][4], const int piv[4], double b[4], double xo
 // Below this error the PMHD Newton step keeps the factorised Jacobian of the
 // last full evaluation and evaluates the residual alone (chord step): near
 // the root the Jacobian changes by O(e_T) between iterates.
+#ifndef GRRMHD_CHORD_TOL
 #define GRRMHD_CHORD_TOL 1e-6
+#endif
 
 DEV double rad_energy_lab(const Metric& m, const double R[4]) {
   return -R[0] + m.alpha * m.alpha * (m.up(0, 1) * R[1] + m.up(0, 2) * R[2] + m.up(0, 3) * R[3]);

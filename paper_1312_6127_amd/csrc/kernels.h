@@ -294,12 +294,41 @@ DEV void flux_at(Ctx C, FaceRange R, const double* __restrict__ P,
   vchar[c] = (double)fmax(fmax(gmin, gmax), fmax(rmin, rmax));
 }
 
-template <int D, class T>
-__global__ void GRRMHD_FLUX_LB k_flux(Ctx C, FaceRange R, const double* __restrict__ P,
-                               const double* __restrict__ chi_abs,
-                               const double* __restrict__ chi_es, double* __restrict__ F,
-                               double* __restrict__ vchar) {
-  flux_at<D, T>(C, R, P, chi_abs, chi_es, F, vchar, (long)blockIdx.x * blockDim.x + threadIdx.x);
+
+// The faces of all directions in one launch: up to three segments (one per
+// direction) laid end to end over the thread index; consecutive threads stay
+// within one direction except at the two segment boundaries.
+struct FluxSegs {
+  FaceRange R[3];
+  long start[3];
+  int D[3];
+  int n;
+  long total;
+};
+
+template <class T>
+DEV void flux_all_at(Ctx C, const FluxSegs& S, const double* __restrict__ P,
+                     const double* __restrict__ chi_abs, const double* __restrict__ chi_es,
+                     double* __restrict__ F, double* __restrict__ vchar, long t) {
+  if (t >= S.total) return;
+  int k = 0;
+  if (S.n > 1 && t >= S.start[1]) k = 1;
+  if (S.n > 2 && t >= S.start[2]) k = 2;
+  const long u = t - S.start[k];
+  const int D = S.D[k];
+  double* Fd = F + (long)(D - 1) * 12 * C.Ntot;
+  double* vd = vchar + (long)(D - 1) * C.Ntot;
+  if (D == 1) flux_at<1, T>(C, S.R[k], P, chi_abs, chi_es, Fd, vd, u);
+  else if (D == 2) flux_at<2, T>(C, S.R[k], P, chi_abs, chi_es, Fd, vd, u);
+  else flux_at<3, T>(C, S.R[k], P, chi_abs, chi_es, Fd, vd, u);
+}
+
+template <class T>
+__global__ void GRRMHD_FLUX_LB k_flux_all(Ctx C, FluxSegs S, const double* __restrict__ P,
+                                          const double* __restrict__ chi_abs,
+                                          const double* __restrict__ chi_es,
+                                          double* __restrict__ F, double* __restrict__ vchar) {
+  flux_all_at<T>(C, S, P, chi_abs, chi_es, F, vchar, (long)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
