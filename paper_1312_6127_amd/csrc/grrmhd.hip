@@ -25,6 +25,10 @@ struct grrmhd_grid {
   hipEvent_t* ev = nullptr;   // 2 * TCAP events, created on first use
 };
 
+#ifndef GRRMHD_IMPLICIT_TILE_I
+#define GRRMHD_IMPLICIT_TILE_I 16  // x1 extent of a wavefront's tile in the implicit kernel
+#endif
+
 static size_t round256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 // Cascade list of up to cap cells with the first attempts' records, laid out
@@ -398,7 +402,10 @@ static int launch_implicit(grrmhd_grid* g, const double* Ue, const double* Pg, d
   LAUNCHCHK();
   const bool timed = g->timing && g->nt < grrmhd_grid::TCAP;
   if (timed) HIPCHK(hipEventRecord(g->ev[2 * g->nt], g->stream));
-  hipLaunchKernelGGL(k_implicit, dim3(nblocks(n, 64)), dim3(64), 0, g->stream, g->C, Ue, Pg,
+  // wavefront tiles of 16 x 4 cells in (x1, x2); 64 x 1 on one-dimensional grids
+  const int ti = (g->C.n[1] > 1) ? GRRMHD_IMPLICIT_TILE_I : 64, tj = 64 / ti;
+  const long tiles = (long)((g->C.n[0] + ti - 1) / ti) * ((g->C.n[1] + tj - 1) / tj) * g->C.n[2];
+  hipLaunchKernelGGL(k_implicit, dim3((unsigned)tiles), dim3(64), 0, g->stream, g->C, ti, Ue, Pg,
                      scale, dt_dev, ca, ce, P, U, it, st, err, g->W);
   LAUNCHCHK();
   if (timed) {

@@ -349,7 +349,7 @@ DEV int lu_solve4(const double A[4][4], const int piv[4], double b[4], double xo
 // last full evaluation and evaluates the residual alone (chord step): near
 // the root the Jacobian changes by O(e_T) between iterates.
 #ifndef GRRMHD_CHORD_TOL
-#define GRRMHD_CHORD_TOL 1e-6
+#define GRRMHD_CHORD_TOL 1e-4
 #endif
 
 DEV double rad_energy_lab(const Metric& m, const double R[4]) {

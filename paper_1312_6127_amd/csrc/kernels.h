@@ -630,22 +630,38 @@ DEV void to_cascade(bool need, bool extreme, int item, const Best& b, int iters,
 
 // Common path of the implicit solve at interior cells; cells that need the
 // full cascade go to the work list (index into the interior enumeration).
-__global__ void LBI k_implicit(Ctx C, const double* __restrict__ Uexp, const double* Pguess,
+// Cells of one wavefront: a tile of ti x (64 / ti) cells in (x1, x2) at one
+// x3, so that its lanes share radius and latitude (and with them the Newton
+// count) more than a run of 64 cells along x1 does, while each group of ti
+// lanes still reads contiguous memory.
+DEV bool tile_cell(const Ctx& C, int ti, long wave, int lane, int& i, int& j, int& k) {
+  const int tj = 64 / ti;
+  const int nti = (C.n[0] + ti - 1) / ti, ntj = (C.n[1] + tj - 1) / tj;
+  const int a = wave % nti;
+  const long w2 = wave / nti;
+  const int b = w2 % ntj;
+  k = w2 / ntj;
+  const int ii = a * ti + lane % ti, jj = b * tj + lane / ti;
+  if (ii >= C.n[0] || jj >= C.n[1] || k >= C.n[2]) return false;
+  i = C.ng[0] + ii;
+  j = C.ng[1] + jj;
+  k += C.ng[2];
+  return true;
+}
+
+__global__ void LBI k_implicit(Ctx C, int ti, const double* __restrict__ Uexp, const double* Pguess,
                                   double dt_scale, const double* __restrict__ dt_dev,
                                   const double* __restrict__ chi_abs,
                                   const double* __restrict__ chi_es, double* P,
                                   double* __restrict__ U, int* __restrict__ iters,
                                   int* __restrict__ status, double* __restrict__ err, Work W) {
-  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  const long nint = (long)C.n[0] * C.n[1] * C.n[2];
   bool need = false, extreme = false;
   Best b;
   int it = 0, trips = 0;
-  if (t < nint) {
-    const int i = C.ng[0] + t % C.n[0];
-    const long t2 = t / C.n[0];
-    const int j = C.ng[1] + t2 % C.n[1];
-    const int k = C.ng[2] + t2 / C.n[1];
+  int i = 0, j = 0, k = 0;
+  long t = 0;   // the cell's index in the interior enumeration (x1 fastest)
+  if (tile_cell(C, ti, blockIdx.x, threadIdx.x, i, j, k)) {
+    t = (i - C.ng[0]) + (long)C.n[0] * ((j - C.ng[1]) + (long)C.n[1] * (k - C.ng[2]));
     const long c = cell_index(C, i, j, k);
     Metric m;
     load_metric(C.geo_c, C.npos, i + C.N[0] * j, m);
