@@ -8,6 +8,18 @@
 #ifndef GRRMHD_FLUX_LB
 #define GRRMHD_FLUX_LB __launch_bounds__(128)
 #endif
+
+// Workgroups are dealt to the 8 XCDs round-robin (workgroup b to XCD b mod 8)
+// and each XCD has its own L2.  This maps b to a work index so that each XCD
+// works through one contiguous eighth of the work: neighbouring tiles, which
+// share cache lines and stencil rows, then meet in the same L2.  A bijection
+// on [0, G): the last G mod 8 workgroups keep their own index.
+DEV long xcd_block(long b, long G) {
+  const long full = (G / 8) * 8;
+  if (b >= full) return b;
+  return (b % 8) * (G / 8) + b / 8;
+}
+
 #ifndef GRRMHD_IMP_WAVES
 #define GRRMHD_IMP_WAVES 1   // minimum waves per SIMD asked of the implicit kernels
 #endif
@@ -328,7 +340,8 @@ __global__ void GRRMHD_FLUX_LB k_flux_all(Ctx C, FluxSegs S, const double* __res
                                           const double* __restrict__ chi_abs,
                                           const double* __restrict__ chi_es,
                                           double* __restrict__ F, double* __restrict__ vchar) {
-  flux_all_at<T>(C, S, P, chi_abs, chi_es, F, vchar, (long)blockIdx.x * blockDim.x + threadIdx.x);
+  flux_all_at<T>(C, S, P, chi_abs, chi_es, F, vchar,
+                 xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -660,7 +673,7 @@ __global__ void LBI k_implicit(Ctx C, int ti, const double* __restrict__ Uexp, c
   int it = 0, trips = 0;
   int i = 0, j = 0, k = 0;
   long t = 0;   // the cell's index in the interior enumeration (x1 fastest)
-  if (tile_cell(C, ti, blockIdx.x, threadIdx.x, i, j, k)) {
+  if (tile_cell(C, ti, xcd_block(blockIdx.x, gridDim.x), threadIdx.x, i, j, k)) {
     t = (i - C.ng[0]) + (long)C.n[0] * ((j - C.ng[1]) + (long)C.n[1] * (k - C.ng[2]));
     const long c = cell_index(C, i, j, k);
     Metric m;
