@@ -39,9 +39,9 @@ STEP_BYTES_PER_ZONE = 1344
 # (FETCH_SIZE x 2 + WRITE_SIZE x 1, the scales from a copy of known size).
 # They hold for the kernel sources whose digest is KERNEL_DIGEST; otherwise
 # traffic is reported as null and the flop figure as stale.
-FLOPS_PER_TRIP = 3009.0
-HBM_BYTES_PER_LAUNCH = 121.7e6
-KERNEL_DIGEST = "001d5d9ecd750de2"
+FLOPS_PER_TRIP = 1722.0
+HBM_BYTES_PER_LAUNCH = 158.8e6
+KERNEL_DIGEST = "516af7dafd0ee6ca"
 
 
 def parse():
