@@ -17,8 +17,13 @@ struct grrmhd_grid {
   hipStream_t stream;
   double* geo;          // one allocation: centre table, x1-face table, x2-face table,
                         // then the dt slot, the implicit bookkeeping and work list
-  unsigned long long* dtslot;
-  Work W;               // implicit cascade list (interior indices), records, stats
+  unsigned long long* dtslot;    // Courant reduction of the stand-alone timestep call
+  unsigned long long* dtstep[2]; // the step's reductions, alternating (each resets the other)
+  int dtp = 0;
+  int* cnt[2];          // cascade list lengths, alternating (each launch zeroes the other)
+  int cp = 0;
+  Work W;               // implicit cascade list (interior indices), records, stats;
+                        // W.counter is the list length of the last launch
   // optional HIP-event timing of the implicit kernel's launches
   static const int TCAP = 256;
   int timing = 0, nt = 0;
@@ -177,6 +182,13 @@ static void fill_ctx(const grrmhd_params* p, Ctx& C) {
   C.erad_floor = p->erad_floor;
 }
 
+// Bookkeeping after the geometry tables: the stand-alone timestep's dt slot
+// at 0, the cascade list lengths at 128 and 160, the lane statistics at 192,
+// the step's two sets of Courant slots, then the cascade list and records.
+static const size_t TAIL_DT0 = 256;
+static const size_t TAIL_DT1 = TAIL_DT0 + 8 * GRRMHD_DT_SLOTS * GRRMHD_DT_STRIDE;
+static const size_t TAIL_CASCADE = TAIL_DT1 + 8 * GRRMHD_DT_SLOTS * GRRMHD_DT_STRIDE;
+
 extern "C" int grrmhd_init_grid(const grrmhd_params* p, int device, void* hip_stream,
                                 grrmhd_grid** out) {
   if (!out) return fail(GRRMHD_EINVAL, "out is NULL");
@@ -196,22 +208,31 @@ extern "C" int grrmhd_init_grid(const grrmhd_params* p, int device, void* hip_st
   const size_t nd = tab * (GE_NCENTER + 2 * GE_NFACE);
   const size_t nint = (size_t)g->C.n[0] * g->C.n[1] * g->C.n[2];
   // [nd doubles][256 B: dt slot @0, list length @128, stats @192][cascade]
-  hipError_t e = hipMalloc(&g->geo, nd * sizeof(double) + 256 + cascade_bytes(nint));
+  hipError_t e = hipMalloc(&g->geo, nd * sizeof(double) + TAIL_CASCADE + cascade_bytes(nint));
   if (e != hipSuccess) {
     delete g;
     return fail(GRRMHD_ENOMEM, std::string("geometry allocation: ") + hipGetErrorString(e));
   }
   char* tail = (char*)(g->geo + nd);
   g->dtslot = (unsigned long long*)tail;
-  g->W.counter = (int*)(tail + 128);
+  g->dtstep[0] = (unsigned long long*)(tail + TAIL_DT0);
+  g->dtstep[1] = (unsigned long long*)(tail + TAIL_DT1);
+  g->cnt[0] = (int*)(tail + 128);
+  g->cnt[1] = (int*)(tail + 160);
+  g->W.counter = g->cnt[0];
+  g->W.counter_next = nullptr;
   g->W.stats = (unsigned long long*)(tail + 192);
-  cascade_layout(tail + 256, nint, g->W);
+  cascade_layout(tail + TAIL_CASCADE, nint, g->W);
   g->C.geo_c = g->geo;
   g->C.geo_f1 = g->geo + tab * GE_NCENTER;
   g->C.geo_f2 = g->geo + tab * (GE_NCENTER + GE_NFACE);
   hipLaunchKernelGGL(k_geometry, dim3(nblocks(g->C.npos, 256)), dim3(256), 0, g->stream, g->C,
                      p->a, p->R0, g->geo, (double*)g->C.geo_f1, (double*)g->C.geo_f2);
-  hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, g->stream, (int*)g->W.stats, 4);
+  // both list lengths and the lane statistics (bytes 128..223 of the tail)
+  hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, g->stream, (int*)(tail + 128), 24);
+  hipLaunchKernelGGL(k_dt_init, dim3(1), dim3(64), 0, g->stream, g->dtslot, 1, 1);
+  hipLaunchKernelGGL(k_dt_init, dim3(1), dim3(64), 0, g->stream, g->dtstep[0],
+                     2 * GRRMHD_DT_SLOTS, GRRMHD_DT_STRIDE);
   e = hipGetLastError();
   if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
   if (e != hipSuccess) {
@@ -319,8 +340,10 @@ static void split_x1(const FaceRange& R, int i0, FaceRange& a, FaceRange& b) {
   b.total = (long)b.cnt[0] * b.cnt[1] * b.cnt[2];
 }
 
+// dtmin set: the Courant reduction over interior cells runs in the EMF launch
 static int launch_fluxes(grrmhd_grid* g, const double* P, const double* ca, const double* ce,
-                         double* F, double* emf, double* vch) {
+                         double* F, double* emf, double* vch,
+                         unsigned long long* dtmin = nullptr) {
   const Ctx& C = g->C;
   // faces of every direction, FP64 part and FP32 part (split at mixed_i)
   FluxSegs S64, S32;
@@ -352,14 +375,20 @@ static int launch_fluxes(grrmhd_grid* g, const double* P, const double* ca, cons
   // corner EMFs: union of the edge ranges (n + 1 positions along active axes)
   bool any = false;
   for (int a = 0; a < 3; a++) any = any || (C.n[(a + 1) % 3] > 1 && C.n[(a + 2) % 3] > 1);
-  if (any) {
-    FaceRange R;
-    R.total = 1;
-    for (int e = 0; e < 3; e++) {
-      R.lo[e] = C.ng[e];
-      R.cnt[e] = C.n[e] > 1 ? C.n[e] + 1 : 1;
-      R.total *= R.cnt[e];
-    }
+  FaceRange R;
+  R.total = 1;
+  for (int e = 0; e < 3; e++) {
+    R.lo[e] = C.ng[e];
+    R.cnt[e] = C.n[e] > 1 ? C.n[e] + 1 : 1;
+    R.total *= R.cnt[e];
+  }
+  if (!any) R.total = 0;
+  if (dtmin) {
+    const long n = std::max<long>(R.total, (long)C.n[0] * C.n[1] * C.n[2]);
+    hipLaunchKernelGGL(k_emf_dt, dim3(nblocks(n, 256)), dim3(256), 0, g->stream, C, R, F, emf, vch,
+                       dtmin);
+    LAUNCHCHK();
+  } else if (any) {
     hipLaunchKernelGGL(k_emf_all, dim3(nblocks(R.total, 256)), dim3(256), 0, g->stream, C, R, F,
                        emf);
     LAUNCHCHK();
@@ -371,7 +400,7 @@ static long n_interior(const Ctx& C) { return (long)C.n[0] * C.n[1] * C.n[2]; }
 
 static int launch_timestep(grrmhd_grid* g, const double* vch, double* dt_dev) {
   const Ctx& C = g->C;
-  hipLaunchKernelGGL(k_dt_init, dim3(1), dim3(1), 0, g->stream, g->dtslot);
+  hipLaunchKernelGGL(k_dt_init, dim3(1), dim3(64), 0, g->stream, g->dtslot, 1, 1);
   LAUNCHCHK();
   hipLaunchKernelGGL(k_dt_min, dim3(nblocks(n_interior(C), 256)), dim3(256), 0, g->stream, C, vch,
                      g->dtslot);
@@ -381,11 +410,14 @@ static int launch_timestep(grrmhd_grid* g, const double* vch, double* dt_dev) {
   return 0;
 }
 
+// dtmin set: dt = courant x *dtmin, stored in *dt_dev; *dtnext reset to +inf
 static int launch_update(grrmhd_grid* g, double a, double b, double c, const double* dt_dev,
                          const double* P, const double* Un, const double* Up, const double* F,
-                         const double* emf, double* Ue) {
+                         const double* emf, double* Ue, const unsigned long long* dtmin = nullptr,
+                         unsigned long long* dtnext = nullptr) {
   hipLaunchKernelGGL(k_update, dim3(nblocks(n_interior(g->C), 256)), dim3(256), 0, g->stream,
-                     g->C, a, b, c, dt_dev, P, Un, Up, F, emf, Ue);
+                     g->C, a, b, c, const_cast<double*>(dt_dev), dtmin, dtnext, P, Un, Up, F, emf,
+                     Ue);
   LAUNCHCHK();
   return 0;
 }
@@ -397,24 +429,28 @@ static int launch_implicit(grrmhd_grid* g, const double* Ue, const double* Pg, d
                            const double* dt_dev, const double* ca, const double* ce, double* P,
                            double* U, int* it, int* st, double* err) {
   const long n = n_interior(g->C);
-  // list length (the lane statistics accumulate over launches)
-  hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, g->stream, g->W.counter, 1);
-  LAUNCHCHK();
+  // this launch appends to cnt[cp] (zero: set at creation or by the previous
+  // launch's cascade kernel) and its cascade kernel zeroes cnt[cp ^ 1]
+  Work W = g->W;
+  W.counter = g->cnt[g->cp];
+  W.counter_next = g->cnt[g->cp ^ 1];
   const bool timed = g->timing && g->nt < grrmhd_grid::TCAP;
   if (timed) HIPCHK(hipEventRecord(g->ev[2 * g->nt], g->stream));
   // wavefront tiles of 16 x 4 cells in (x1, x2); 64 x 1 on one-dimensional grids
   const int ti = (g->C.n[1] > 1) ? GRRMHD_IMPLICIT_TILE_I : 64, tj = 64 / ti;
   const long tiles = (long)((g->C.n[0] + ti - 1) / ti) * ((g->C.n[1] + tj - 1) / tj) * g->C.n[2];
   hipLaunchKernelGGL(k_implicit, dim3((unsigned)tiles), dim3(64), 0, g->stream, g->C, ti, Ue, Pg,
-                     scale, dt_dev, ca, ce, P, U, it, st, err, g->W);
+                     scale, dt_dev, ca, ce, P, U, it, st, err, W);
   LAUNCHCHK();
   if (timed) {
     HIPCHK(hipEventRecord(g->ev[2 * g->nt + 1], g->stream));
     g->nt++;
   }
   hipLaunchKernelGGL(k_implicit_list, dim3(list_blocks(n)), dim3(64), 0, g->stream, g->C, Ue, Pg,
-                     scale, dt_dev, ca, ce, P, U, it, st, err, g->W);
+                     scale, dt_dev, ca, ce, P, U, it, st, err, W);
   LAUNCHCHK();
+  g->W.counter = W.counter;
+  g->cp ^= 1;
   return 0;
 }
 
@@ -538,9 +574,15 @@ extern "C" int grrmhd_step(grrmhd_grid* g, double* P, double* U, const double* c
     double* Pout = (s == 2) ? P : Pa;
     double* Uout = (s == 2) ? U : Ua;
     if ((rc = launch_bc(g, Pin))) return rc;
-    if ((rc = launch_fluxes(g, Pin, chi_abs, chi_es, F, emf, vch))) return rc;
-    if (s == 0 && !dt_fixed && (rc = launch_timestep(g, vch, dt_dev))) return rc;
-    if ((rc = launch_update(g, A[s], B[s], Cc[s], dt_dev, Pin, U, Uprev, F, emf, Ue))) return rc;
+    // stage 1 without a fixed dt: the Courant reduction rides on the EMF launch
+    // and the update takes dt from it (dtstep alternates between steps)
+    const bool red = (s == 0 && !dt_fixed);
+    unsigned long long* dmin = red ? g->dtstep[g->dtp] : nullptr;
+    unsigned long long* dnext = red ? g->dtstep[g->dtp ^ 1] : nullptr;
+    if ((rc = launch_fluxes(g, Pin, chi_abs, chi_es, F, emf, vch, dmin))) return rc;
+    if ((rc = launch_update(g, A[s], B[s], Cc[s], dt_dev, Pin, U, Uprev, F, emf, Ue, dmin, dnext)))
+      return rc;
+    if (red) g->dtp ^= 1;
     if ((rc = launch_implicit(g, Ue, Pin, Cc[s], dt_dev, chi_abs, chi_es, Pout, Uout, it, st, err)))
       return rc;
     if ((rc = launch_fixup(g, Pout, Uout, st, Ue, status, it, iters, s > 0))) return rc;
@@ -851,6 +893,7 @@ static int launch_batch(const Ctx& C, long n, const double* U_expl, const double
   char* base = (char*)workspace;
   Work W;
   W.counter = (int*)base;
+  W.counter_next = nullptr;
   int* next = W.counter + 1;          // persistent queue cursor
   int* qc = W.counter + 2;            // per-iteration queue lengths (2)
   W.stats = (unsigned long long*)(base + 64);

@@ -23,6 +23,9 @@
 #ifndef GRRMHD_NJ
 #define GRRMHD_NJ 4   // Jacobian directions per dual-number pass (4: one pass)
 #endif
+#ifndef GRRMHD_URAD_EXACT
+#define GRRMHD_URAD_EXACT 1   // URAD Jacobian: 1 exact (dual numbers), 0 one-sided differences
+#endif
 
 enum { M_PMHD = 0, M_URAD = 1 };
 
@@ -254,6 +257,68 @@ DEV void eval_urad(const Cell& c, const Phys& ph, const double x[4], const doubl
   norm_errors(c, Tg, Rr, G, e);
 }
 
+// URAD residual and its exact Jacobian dE_rad/dx in one dual-number pass:
+// the same steps as eval_urad, the gas inversion differentiated by the
+// implicit-function theorem (mhd_invert_dual).  Values equal eval_urad's.
+DEV void eval_urad_jac(const Cell& c, const Phys& ph, const double x[4], const double Pgas[5],
+                       Eval& e, double J[4][4]) {
+  using D = Dual<4>;
+  e.ok = 1;
+  D xd[4];
+#pragma unroll
+  for (int k = 0; k < 4; k++) {
+    e.x[k] = x[k];
+    xd[k] = D::var(x[k], k);
+  }
+  const D Tt[3] = {c.Tgi[1] - (xd[1] - c.Ri[1]), c.Tgi[2] - (xd[2] - c.Ri[2]),
+                   c.Tgi[3] - (xd[3] - c.Ri[3])};
+  const D Eg = c.Tgi[0] - (xd[0] - c.Ri[0]);
+  D rho, ug, ut[3];
+  if (mhd_invert_dual<4>(c.m, ph.gam, c.rhout, Eg, Tt, c.B, Pgas[1], Pgas + 2, rho, ug, ut)) {
+    e.ok = 0;
+    e.eT = INFINITY;
+    return;
+  }
+  D Eb, utr[3];
+  e.radflags = rad_invert(c.m, ph.gamma_max, ph.ymax, 1, xd, Eb, utr);
+  const D B[3] = {D(c.B[0]), D(c.B[1]), D(c.B[2])};
+  Gas<D> s;
+  make_gas(c.m, ph.gam, rho, ug, ut, B, s);
+  D row[8];
+  gas_row(s, B, 0, row);
+  Vel<D> r;
+  make_vel(c.m, utr, r);
+  D Rr[4];
+  rad_row(r, Eb, 0, Rr);
+  const D Tgas = s.pg / rho;
+  const D kabs = c.chi_abs * rho, kes = c.chi_es * rho;
+  const D lam = kabs * ph.arad * (Tgas * Tgas) * (Tgas * Tgas);
+  D G[4];
+  four_force(s.v, r, Eb, kabs, kes, lam, G);
+  double Tg[4], Rv[4], Gv[4];
+#pragma unroll
+  for (int k = 0; k < 4; k++) {
+    const D Erk = (Rr[k] - c.Ri[k]) + c.dt * G[k];
+#pragma unroll
+    for (int j = 0; j < 4; j++) J[k][j] = Erk.d[j];
+    Tg[k] = row[1 + k].v;
+    Rv[k] = Rr[k].v;
+    Gv[k] = G[k].v;
+    e.Eg[k] = (Tg[k] - c.Tgi[k]) - c.dt * Gv[k];
+    e.Er[k] = Erk.v;
+  }
+  e.P[0] = rho.v;
+  e.P[1] = ug.v;
+#pragma unroll
+  for (int i = 0; i < 3; i++) {
+    e.P[2 + i] = ut[i].v;
+    e.P[5 + i] = c.B[i];
+    e.P[9 + i] = utr[i].v;
+  }
+  e.P[8] = Eb.v;
+  norm_errors(c, Tg, Rv, Gv, e);
+}
+
 // 4x4 solve with partial pivoting; 0 on success
 DEV int solve4(double A[4][4], double b[4], double xo[4]) {
 #pragma unroll
@@ -384,7 +449,9 @@ DEV void newton(const Cell& c, const Phys& ph, const Opts& o, const double x0[4]
   double J[4][4];
   int piv[4] = {0, 1, 2, 3};
   bool fresh = true;   // PMHD: J holds a new Jacobian, not yet factorised
+  bool jok = true;      // URAD (exact): J holds the Jacobian at x
   if (METHOD == M_PMHD) eval_pmhd(c, ph, x, ev, J);
+  else if (GRRMHD_URAD_EXACT) eval_urad_jac(c, ph, x, Pg0, ev, J);
   else eval_urad(c, ph, x, Pg0, ev);
   keep(best, ev);
   if (!ev.ok) return;
@@ -404,7 +471,16 @@ DEV void newton(const Cell& c, const Phys& ph, const Opts& o, const double x0[4]
     double Pn[5];
 #pragma unroll
     for (int q = 0; q < 5; q++) Pn[q] = ev.P[q];
-    if (METHOD == M_URAD) {
+    if (METHOD == M_URAD && GRRMHD_URAD_EXACT) {
+      if (!jok) {                       // after a back-off: the Jacobian at x
+        Eval ej;
+        eval_urad_jac(c, ph, x, Pn, ej, J);
+        if (!ej.ok) break;
+        jok = true;
+      }
+#pragma unroll
+      for (int i = 0; i < 4; i++) r[i] = ev.Er[i];
+    } else if (METHOD == M_URAD) {
       const double delta = (ev.eIr < 1e-9) ? 1e-10 : 1e-8;
       int jfail = 0;
       for (int j = 0; j < 4 && !jfail; j++) {
@@ -462,7 +538,12 @@ DEV void newton(const Cell& c, const Phys& ph, const Opts& o, const double x0[4]
         const double a2 = c.m.alpha * c.m.alpha;
         xn[0] = -0.5 * ::fabs(Erl) + a2 * (c.m.up(0, 1) * xn[1] + c.m.up(0, 2) * xn[2] + c.m.up(0, 3) * xn[3]);
       }
-      eval_urad(c, ph, xn, Pn, ev);
+      if (GRRMHD_URAD_EXACT) {
+        eval_urad_jac(c, ph, xn, Pn, ev, J);
+        jok = ev.ok;
+      } else {
+        eval_urad(c, ph, xn, Pn, ev);
+      }
       int back = 0;
       while (!ev.ok && back < 20) {                           // back up half-way
         nfail++;

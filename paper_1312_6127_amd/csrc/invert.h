@@ -81,14 +81,21 @@ DEV int rad_invert(const Metric& m, double gamma_max, double ymax, int type2, co
 // ---------------------------------------------------------------------------
 // MHD inversion
 // ---------------------------------------------------------------------------
-struct MhdC {
-  double D, Ep, Qt2, Bsq, S, gam;
-  double Qt[3], Bz[3];
+// Constants of eq. EMHD; those that depend on the conserved energy and
+// momentum have the scalar type C (double, or dual numbers carrying their
+// derivatives with respect to upstream unknowns).
+template <class C>
+struct MhdCT {
+  double D, Bsq, gam;
+  C Ep, Qt2, S;
+  C Qt[3];
+  double Bz[3];
 };
+using MhdC = MhdCT<double>;
 
 // residual of eq. EMHD in W' and chi = u + p; templated for the derivative
-template <class T>
-DEV T mhd_f(const MhdC& c, const T& Wp, T& chi, T& gamma) {
+template <class T, class C>
+DEV T mhd_f(const MhdCT<C>& c, const T& Wp, T& chi, T& gamma) {
   const T W = Wp + c.D;
   const T a = c.Bsq + W;
   const T W2 = W * W;
@@ -151,18 +158,17 @@ DEV int mhd_bisect(const MhdC& c, double& Wp_out) {
   return 0;
 }
 
-// Gas primitives from rho u^t, E_gas = T^t_t + rho u^t, T^t_i, B^i (all
-// without sqrt(-g)).  Pg supplies the starting W'.  Writes rho, u_g, u~^i.
-// Returns 0 on success, 1 without a physical (u_g > 0) root.
-DEV int mhd_invert(const Metric& m, double gam, double rhout, double Eg, const double Tt[3],
-                   const double B[3], double& rho_g, double& ug_g, double ut_g[3]) {
+// Constants of eq. EMHD from rho u^t, E_gas = T^t_t + rho u^t, T^t_i, B^i
+// (all without sqrt(-g)), eq. PRIM1 and the normal-observer projections.
+template <class C>
+DEV void mhd_consts(const Metric& m, double gam, double rhout, const C& Eg, const C Tt[3],
+                    const double B[3], MhdCT<C>& c) {
   const double al = m.alpha;
-  MhdC c;
   c.gam = gam;
   c.D = al * rhout;                                                       // eq. PRIM1
   c.Ep = -Eg + rhout * (1.0 - al) + al * al * (m.up(0, 1) * Tt[0] + m.up(0, 2) * Tt[1] + m.up(0, 3) * Tt[2]);
-  c.Qt2 = 0.0;
-  c.S = 0.0;
+  c.Qt2 = C(0.0);
+  c.S = C(0.0);
   c.Bsq = 0.0;
 #pragma unroll
   for (int i = 0; i < 3; i++) {
@@ -171,15 +177,18 @@ DEV int mhd_invert(const Metric& m, double gam, double rhout, double Eg, const d
   }
 #pragma unroll
   for (int i = 0; i < 3; i++) {
-    c.Qt2 += c.Qt[i] * al * Tt[i];
-    c.S += al * Tt[i] * c.Bz[i];
+    c.Qt2 = c.Qt2 + c.Qt[i] * al * Tt[i];
+    c.S = c.S + al * Tt[i] * c.Bz[i];
 #pragma unroll
     for (int j = 0; j < 3; j++) c.Bsq += m.lo(i + 1, j + 1) * c.Bz[i] * c.Bz[j];
   }
-  if (!(c.D > 0.0) || !(c.Ep > 0.0) || !isfinite(c.Ep) || !isfinite(c.Qt2)) return 1;
+}
 
-  // starting point from the guess primitives: W' = D u~^2/(1+gamma) + chi gamma^2
-  double Wp;
+// The root W' of eq. EMHD: Newton from the guess primitives (W' = D u~^2/(1+gamma)
+// + chi gamma^2), bracketed bisection when Newton leaves the admissible
+// region or stalls.  0 on success (with chi > 0 at the root), 1 otherwise.
+DEV int mhd_solve(const Metric& m, const MhdC& c, double ug_g, const double ut_g[3], double& Wp) {
+  if (!(c.D > 0.0) || !(c.Ep > 0.0) || !isfinite(c.Ep) || !isfinite(c.Qt2)) return 1;
   {
     double q = 0.0;
 #pragma unroll
@@ -187,7 +196,7 @@ DEV int mhd_invert(const Metric& m, double gam, double rhout, double Eg, const d
 #pragma unroll
       for (int j = 0; j < 3; j++) q += m.lo(i + 1, j + 1) * ut_g[i] * ut_g[j];
     const double g = ::sqrt(1.0 + q);
-    Wp = c.D * q / (1.0 + g) + gam * ug_g * (1.0 + q);
+    Wp = c.D * q / (1.0 + g) + c.gam * ug_g * (1.0 + q);
   }
   bool ok = isfinite(Wp) && Wp > 0.0;
   int conv = 0;
@@ -208,20 +217,75 @@ DEV int mhd_invert(const Metric& m, double gam, double rhout, double Eg, const d
       if (it == 59) ok = false;
     }
   }
-  double chi, gm;
   if (ok) {
+    double chi, gm;
     mhd_f<double>(c, Wp, chi, gm);
     if (!(chi > 0.0)) ok = false;
   }
-  if (!ok) {
-    if (mhd_bisect(c, Wp)) return 1;
-    mhd_f<double>(c, Wp, chi, gm);
-  }
-  const double W = Wp + c.D;
-  const double iw = 1.0 / (W + c.Bsq);
+  if (!ok && mhd_bisect(c, Wp)) return 1;
+  return 0;
+}
+
+// Primitives rho, u_g, u~^i at W' (eq. tveq, rho = D/gamma, u_g = chi/gam)
+template <class T, class C>
+DEV void mhd_prims(const MhdCT<C>& c, const T& Wp, T& rho, T& ug, T ut[3]) {
+  T chi, gm;
+  mhd_f<T>(c, Wp, chi, gm);
+  const T W = Wp + c.D;
+  const T iw = 1.0 / (W + c.Bsq);
 #pragma unroll
-  for (int i = 0; i < 3; i++) ut_g[i] = gm * (c.Qt[i] + c.S * c.Bz[i] / W) * iw;   // eq. tveq
-  rho_g = c.D / gm;
-  ug_g = chi / gam;
+  for (int i = 0; i < 3; i++) ut[i] = gm * (c.Qt[i] + c.S * c.Bz[i] / W) * iw;   // eq. tveq
+  rho = c.D / gm;
+  ug = chi / c.gam;
+}
+
+// Gas primitives from rho u^t, E_gas = T^t_t + rho u^t, T^t_i, B^i (all
+// without sqrt(-g)).  The guess supplies the starting W'.  Writes rho, u_g,
+// u~^i.  Returns 0 on success, 1 without a physical (u_g > 0) root.
+DEV int mhd_invert(const Metric& m, double gam, double rhout, double Eg, const double Tt[3],
+                   const double B[3], double& rho_g, double& ug_g, double ut_g[3]) {
+  MhdC c;
+  mhd_consts(m, gam, rhout, Eg, Tt, B, c);
+  double Wp;
+  if (mhd_solve(m, c, ug_g, ut_g, Wp)) return 1;
+  mhd_prims(c, Wp, rho_g, ug_g, ut_g);
   return (ug_g > 0.0) ? 0 : 1;
+}
+
+// The same inversion as a function of upstream unknowns carried by dual
+// numbers: the root W' in double precision, then its derivative from the
+// implicit-function theorem on eq. EMHD, dW' = -(df/dc . dc) / (df/dW'),
+// and the primitives' derivatives through eq. tveq.
+template <int N>
+DEV int mhd_invert_dual(const Metric& m, double gam, double rhout, const Dual<N>& Eg,
+                        const Dual<N> Tt[3], const double B[3], double ug_g, const double ut_g[3],
+                        Dual<N>& rho, Dual<N>& ug, Dual<N> ut[3]) {
+  using D = Dual<N>;
+  MhdCT<D> cd;
+  mhd_consts(m, gam, rhout, Eg, Tt, B, cd);
+  MhdC cv;
+  cv.D = cd.D;
+  cv.Bsq = cd.Bsq;
+  cv.gam = cd.gam;
+  cv.Ep = cd.Ep.v;
+  cv.Qt2 = cd.Qt2.v;
+  cv.S = cd.S.v;
+#pragma unroll
+  for (int i = 0; i < 3; i++) {
+    cv.Qt[i] = cd.Qt[i].v;
+    cv.Bz[i] = cd.Bz[i];
+  }
+  double Wp;
+  if (mhd_solve(m, cv, ug_g, ut_g, Wp)) return 1;
+  D chi, gm;
+  const D f = mhd_f<D>(cd, D(Wp), chi, gm);            // df/dc . dc at fixed W'
+  Dual<1> chi1, gm1;
+  const Dual<1> fw = mhd_f<Dual<1>>(cv, Dual<1>::var(Wp, 0), chi1, gm1);
+  if (!(fw.d[0] != 0.0) || !isfinite(fw.d[0])) return 1;
+  const double ifw = 1.0 / fw.d[0];
+  D Wd(Wp);
+#pragma unroll
+  for (int j = 0; j < N; j++) Wd.d[j] = -f.d[j] * ifw;
+  mhd_prims(cd, Wd, rho, ug, ut);
+  return (ug.v > 0.0) ? 0 : 1;
 }

@@ -389,6 +389,7 @@ __global__ void LB(256) k_emf_all(Ctx C, FaceRange R, const double* __restrict__
   emf_all_at(C, R, F, emf, (long)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
+
 // ---------------------------------------------------------------------------
 // step 10: explicit stage combination with flux divergence and geometry
 // source.  The source uses sqrt(-g) T^k_l Gamma^l_{nu k} =
@@ -439,10 +440,27 @@ DEV void load_dg(const Ctx& C, int pos, double dg[2][10]) {
   }
 }
 
-DEV void update_at(Ctx C, double ca, double cb, double cc, const double* dt_dev,
-                                 const double* __restrict__ P, const double* __restrict__ Un,
-                                 const double* __restrict__ Uprev, const double* __restrict__ F,
-                                 const double* __restrict__ emf, double* __restrict__ Uexp, long t) {
+// The step's Courant reduction spreads its atomics over GRRMHD_DT_SLOTS
+// slots, one 128-byte line apart (block b uses slot b mod GRRMHD_DT_SLOTS,
+// i.e. one per XCD), so the blocks of different XCDs do not queue on one line.
+#define GRRMHD_DT_SLOTS 8
+#define GRRMHD_DT_STRIDE 16
+
+DEV double dt_slots_min(const unsigned long long* s) {
+  unsigned long long b = s[0];
+#pragma unroll
+  for (int i = 1; i < GRRMHD_DT_SLOTS; i++) b = ::min(b, s[i * GRRMHD_DT_STRIDE]);
+  return __longlong_as_double((long long)b);
+}
+
+// dt: *dt_dev, or, when dtmin is set, courant x the minimum over the Courant
+// reduction's slots, which thread 0 also stores in *dt_dev while it resets
+// dtnext (the slots of the following step's reduction) to +inf.
+DEV void update_at(Ctx C, double ca, double cb, double cc, double* dt_dev,
+                   const unsigned long long* dtmin, unsigned long long* dtnext,
+                   const double* __restrict__ P, const double* __restrict__ Un,
+                   const double* __restrict__ Uprev, const double* __restrict__ F,
+                   const double* __restrict__ emf, double* __restrict__ Uexp, long t) {
   const long nint = (long)C.n[0] * C.n[1] * C.n[2];
   if (t >= nint) return;
   const int i = C.ng[0] + t % C.n[0];
@@ -450,7 +468,17 @@ DEV void update_at(Ctx C, double ca, double cb, double cc, const double* dt_dev,
   const int j = C.ng[1] + t2 % C.n[1];
   const int k = C.ng[2] + t2 / C.n[1];
   const long c = cell_index(C, i, j, k);
-  const double dt = *dt_dev;
+  double dt;
+  if (dtmin) {
+    dt = C.courant * dt_slots_min(dtmin);
+    if (t == 0) {
+      *dt_dev = dt;
+#pragma unroll
+      for (int i = 0; i < GRRMHD_DT_SLOTS; i++) dtnext[i * GRRMHD_DT_STRIDE] = 0x7FF0000000000000ull;
+    }
+  } else {
+    dt = *dt_dev;
+  }
   double S[12];
 #pragma unroll
   for (int q = 0; q < 12; q++) S[q] = 0.0;
@@ -503,49 +531,69 @@ DEV void update_at(Ctx C, double ca, double cb, double cc, const double* dt_dev,
   }
 }
 
-__global__ void LB(256) k_update(Ctx C, double ca, double cb, double cc, const double* dt_dev,
+__global__ void LB(256) k_update(Ctx C, double ca, double cb, double cc, double* dt_dev,
+                                 const unsigned long long* dtmin, unsigned long long* dtnext,
                                  const double* __restrict__ P, const double* __restrict__ Un,
                                  const double* __restrict__ Uprev, const double* __restrict__ F,
                                  const double* __restrict__ emf, double* __restrict__ Uexp) {
-  update_at(C, ca, cb, cc, dt_dev, P, Un, Uprev, F, emf, Uexp, (long)blockIdx.x * blockDim.x + threadIdx.x);
+  update_at(C, ca, cb, cc, dt_dev, dtmin, dtnext, P, Un, Uprev, F, emf, Uexp,
+            (long)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
 // Courant time step: per-cell harmonic combination, block min, one atomic
 // per block on the ordered bit pattern of a positive double
 // ---------------------------------------------------------------------------
-__global__ void k_dt_init(unsigned long long* slot) { *slot = 0x7FF0000000000000ull; }
+__global__ void k_dt_init(unsigned long long* slot, int n, int stride) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) slot[(long)i * stride] = 0x7FF0000000000000ull;
+}
 
-__global__ void LB(256) k_dt_min(Ctx C, const double* __restrict__ vchar,
-                                 unsigned long long* slot) {
-  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+// 1 / sum_d (larger face speed along d / dx_d) of interior cell t; +inf past the end
+DEV double cell_dt(const Ctx& C, const double* __restrict__ vchar, long t) {
   const long nint = (long)C.n[0] * C.n[1] * C.n[2];
-  double dtc = INFINITY;
-  if (t < nint) {
-    const int i = C.ng[0] + t % C.n[0];
-    const long t2 = t / C.n[0];
-    const int j = C.ng[1] + t2 % C.n[1];
-    const int k = C.ng[2] + t2 / C.n[1];
-    const long c = cell_index(C, i, j, k);
-    double inv = 0.0;
-    for (int d = 0; d < 3; d++) {
-      if (C.n[d] == 1) continue;
-      const double* v = vchar + (long)d * C.Ntot;
-      inv += fmax(v[c], v[c + C.st[d]]) / C.dx[d];
-    }
-    dtc = 1.0 / inv;
+  if (t >= nint) return INFINITY;
+  const int i = C.ng[0] + t % C.n[0];
+  const long t2 = t / C.n[0];
+  const int j = C.ng[1] + t2 % C.n[1];
+  const int k = C.ng[2] + t2 / C.n[1];
+  const long c = cell_index(C, i, j, k);
+  double inv = 0.0;
+  for (int d = 0; d < 3; d++) {
+    if (C.n[d] == 1) continue;
+    const double* v = vchar + (long)d * C.Ntot;
+    inv += fmax(v[c], v[c + C.st[d]]) / C.dx[d];
   }
-  // wavefront reduction then LDS across the block's wavefronts
-  for (int off = 32; off > 0; off >>= 1) dtc = fmin(dtc, __shfl_xor(dtc, off, 64));
+  return 1.0 / inv;
+}
+
+// minimum over a block of up to 256 threads (every thread calls it), then
+// one atomicMin per block on the ordered bits of a positive double
+DEV void block_min_atomic(double v, unsigned long long* slot) {
+  for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));
   __shared__ double wmin[4];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  if (lane == 0) wmin[wid] = dtc;
+  if (lane == 0) wmin[wid] = v;
   __syncthreads();
   if (threadIdx.x == 0) {
     double b = wmin[0];
     for (int w = 1; w < (int)(blockDim.x >> 6); w++) b = fmin(b, wmin[w]);
     atomicMin(slot, (unsigned long long)__double_as_longlong(b));
   }
+}
+
+__global__ void LB(256) k_dt_min(Ctx C, const double* __restrict__ vchar,
+                                 unsigned long long* slot) {
+  block_min_atomic(cell_dt(C, vchar, (long)blockIdx.x * blockDim.x + threadIdx.x), slot);
+}
+
+// The same, and the Courant reduction over interior cells into dtmin (the
+// grid covers both ranges; R.total = 0 when there are no EMFs)
+__global__ void LB(256) k_emf_dt(Ctx C, FaceRange R, const double* __restrict__ F,
+                                 double* __restrict__ emf, const double* __restrict__ vchar,
+                                 unsigned long long* dtmin) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  emf_all_at(C, R, F, emf, t);
+  block_min_atomic(cell_dt(C, vchar, t), dtmin + (blockIdx.x % GRRMHD_DT_SLOTS) * GRRMHD_DT_STRIDE);
 }
 
 __global__ void k_dt_final(const unsigned long long* slot, double courant, double* dt_out) {
@@ -599,6 +647,7 @@ DEV long wave_append(bool need, int item, int* counter, int* list) {
 // lane fraction.
 struct Work {
   int* counter;
+  int* counter_next;   // if set: zeroed by the cascade kernel for the next launch
   int* list;
   unsigned long long* stats;
   RecBuf rec;
@@ -706,6 +755,7 @@ __global__ void LB(64) k_implicit_list(Ctx C, const double* __restrict__ Uexp,
                                        int* __restrict__ status, double* __restrict__ err,
                                        Work W) {
   const int n = *W.counter;
+  if (W.counter_next && blockIdx.x == 0 && threadIdx.x == 0) *W.counter_next = 0;
   for (long w = (long)blockIdx.x * blockDim.x + threadIdx.x; w < n;
        w += (long)gridDim.x * blockDim.x) {
     const long t = W.list[w];
