@@ -146,11 +146,14 @@ def bench_batch(G, I, torch, dev, n, reps=3):
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / reps
         trips, slots, ncas = G.batch_stats(ws)
+        ctrips, cslots = G.batch_cascade_stats(ws)
         same = all(torch.equal(a, b) for a, b in zip(out[1:], outs))
         res["forms"][name] = {"ms": ms, "cell_solves_per_s": n / (ms * 1e-3), "block": block,
                               "waves_per_cu": wpc if mode == G.PERSISTENT else None,
                               "first_attempt_trips": trips, "lane_slots": slots,
                               "active_lane_frac": trips / max(slots, 1), "cascade_cells": ncas,
+                              "cascade_trips": ctrips, "cascade_lane_slots": cslots,
+                              "cascade_active_lane_frac": ctrips / max(cslots, 1),
                               "identical_results": same}
         del ws, out
         print(f"batch form {name}: {ms:.3f} ms", file=sys.stderr, flush=True)

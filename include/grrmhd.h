@@ -241,7 +241,10 @@ int grrmhd_bc_vjp(grrmhd_grid *g, double *gP);
  * device memory; n < 2^31.  workspace: device buffer of at least
  * grrmhd_implicit_source_workspace_bytes(n) bytes, 256-byte aligned (work
  * list of the cells that need the full cascade, with the result of their
- * first attempt; lane statistics).  Same algorithm as grrmhd_implicit_grid. */
+ * first attempt; list of deferred extreme cells; lane statistics).  Same
+ * algorithm as grrmhd_implicit_grid.  The cascade's URAD attempts run in a
+ * compacting persistent grid (lanes take the next listed cell as soon as
+ * theirs ends); extreme cells (URAD first) run one thread each afterwards. */
 size_t grrmhd_implicit_source_workspace_bytes(long n);
 int grrmhd_implicit_source(const grrmhd_params *p, long n, const double *U_expl,
                            const double *P_guess, const double *dt_cell, const double *chi_abs,
@@ -302,6 +305,14 @@ int grrmhd_autotune_implicit_source(const grrmhd_params *p, long n, const double
 int grrmhd_implicit_stats(grrmhd_grid *g, unsigned long long out[3]);
 int grrmhd_implicit_source_stats(const void *workspace, unsigned long long out[3],
                                  void *hip_stream);
+
+/* Lane statistics of a batch's cascade (the URAD attempts of the cells the
+ * first attempt did not accept, run by a compacting persistent grid): out[0]
+ * residual evaluations, out[1] lane slots (64 per wavefront trip) of the last
+ * solve that used the workspace.  Synchronises hip_stream.  EINVAL for a NULL
+ * or misaligned workspace. */
+int grrmhd_implicit_source_cascade_stats(const void *workspace, unsigned long long out[2],
+                                         void *hip_stream);
 
 /* HIP-event timing of the grid's implicit kernel (the first-attempt kernel
  * of every implicit launch, grrmhd_step's three included).  on != 0 clears

@@ -853,7 +853,7 @@ extern "C" int grrmhd_step_adjoint(grrmhd_grid* g, const double* P_n, const doub
 // records, and for the per-iteration form two queues and the lane state.
 extern "C" size_t grrmhd_implicit_source_workspace_bytes_ex(long n, int mode) {
   if (n <= 0) return 0;
-  size_t b = 256 + cascade_bytes((size_t)n);
+  size_t b = 256 + cascade_bytes((size_t)n) + round256(sizeof(int) * (size_t)n);
   if (mode == GRRMHD_IMPLICIT_PER_ITERATION)
     b += 2 * round256(sizeof(int) * (size_t)n) + round256(sizeof(double) * LS_ND * (size_t)n) +
          round256(sizeof(int) * LI_NI * (size_t)n);
@@ -896,23 +896,29 @@ static int launch_batch(const Ctx& C, long n, const double* U_expl, const double
   W.counter_next = nullptr;
   int* next = W.counter + 1;          // persistent queue cursor
   int* qc = W.counter + 2;            // per-iteration queue lengths (2)
+  int* cursor = W.counter + 4;        // cascade queue cursor
   W.stats = (unsigned long long*)(base + 64);
   cascade_layout(base + 256, (size_t)n, W);
-  char* extra = base + 256 + cascade_bytes((size_t)n);
+  // deferred (extreme) cells of the cascade
+  Work D = W;
+  D.counter = W.counter + 5;
+  D.list = (int*)(base + 256 + cascade_bytes((size_t)n));
+  char* extra = (char*)D.list + round256(sizeof(int) * (size_t)n);
   if (mode == GRRMHD_IMPLICIT_PERSISTENT) {
     if (block != 64 && block != 128 && block != 256) return fail(GRRMHD_EINVAL, "block must be 64, 128 or 256");
     if (waves_per_cu < 1 || waves_per_cu > 64) return fail(GRRMHD_EINVAL, "waves_per_cu out of [1, 64]");
   }
-  hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, s, W.counter, 20);
+  // counters, cursors and the four statistics (bytes 0..95)
+  hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, s, W.counter, 24);
   LAUNCHCHK();
+  int dev = 0, ncu = 0;
+  HIPCHK(hipGetDevice(&dev));
+  HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
   if (mode == GRRMHD_IMPLICIT_PER_CELL) {
     hipLaunchKernelGGL(k_implicit_batch, dim3(nblocks(n, 64)), dim3(64), 0, s, C, n, U_expl, P_guess,
                        dt_cell, chi_abs, chi_es, P_out, U_out, iters, status, err, W);
     LAUNCHCHK();
   } else if (mode == GRRMHD_IMPLICIT_PERSISTENT) {
-    int dev = 0, ncu = 0;
-    HIPCHK(hipGetDevice(&dev));
-    HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
     const long waves = (long)ncu * waves_per_cu;
     const long blocks = std::max<long>(1, std::min<long>(waves * 64 / block, nblocks(n, block)));
     hipLaunchKernelGGL(k_implicit_persist, dim3((unsigned)blocks), dim3(block), 0, s, C, n, U_expl,
@@ -941,8 +947,15 @@ static int launch_batch(const Ctx& C, long n, const double* U_expl, const double
       LAUNCHCHK();
     }
   }
+  // the rest of the cascade: URAD attempts in a compacting persistent grid
+  // (one wavefront per SIMD: the kernel holds ~470 registers per lane), then
+  // the deferred extreme cells one thread each
+  const long cwaves = std::max<long>(1, std::min<long>(4L * ncu, nblocks(n, 64)));
+  hipLaunchKernelGGL(k_cascade_urad, dim3((unsigned)cwaves), dim3(64), 0, s, C, n, U_expl, P_guess,
+                     dt_cell, chi_abs, chi_es, P_out, U_out, iters, status, err, W, cursor, D);
+  LAUNCHCHK();
   hipLaunchKernelGGL(k_implicit_batch_list, dim3(list_blocks(n)), dim3(64), 0, s, C, n, U_expl,
-                     P_guess, dt_cell, chi_abs, chi_es, P_out, U_out, iters, status, err, W);
+                     P_guess, dt_cell, chi_abs, chi_es, P_out, U_out, iters, status, err, D);
   LAUNCHCHK();
   return 0;
 }
@@ -1005,6 +1018,16 @@ extern "C" int grrmhd_implicit_source_stats(const void* workspace, unsigned long
   const char* base = (const char*)workspace;
   return read_stats((const unsigned long long*)(base + 64), (const int*)base, out,
                     (hipStream_t)hip_stream);
+}
+
+extern "C" int grrmhd_implicit_source_cascade_stats(const void* workspace,
+                                                    unsigned long long out[2], void* hip_stream) {
+  if (!workspace || !out) return fail(GRRMHD_EINVAL, "NULL argument");
+  if (((uintptr_t)workspace) & 255) return fail(GRRMHD_EINVAL, "workspace must be 256-byte aligned");
+  HIPCHK(hipMemcpyAsync(out, (const char*)workspace + 80, 2 * sizeof(unsigned long long),
+                        hipMemcpyDeviceToHost, (hipStream_t)hip_stream));
+  HIPCHK(hipStreamSynchronize((hipStream_t)hip_stream));
+  return 0;
 }
 
 extern "C" int grrmhd_implicit_source_ex(const grrmhd_params* p, long n, const double* U_expl,

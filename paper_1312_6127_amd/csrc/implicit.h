@@ -329,10 +329,13 @@ DEV int solve4(double A[4][4], double b[4], double xo[4]) {
     for (int i = k + 1; i < 4; i++)
       if (::fabs(A[i][k]) > best) { best = ::fabs(A[i][k]); p = i; }
     if (!(best > 0.0) || !isfinite(best)) return 1;
-    if (p != k) {
 #pragma unroll
-      for (int j = 0; j < 4; j++) { const double t = A[k][j]; A[k][j] = A[p][j]; A[p][j] = t; }
-      const double t = b[k]; b[k] = b[p]; b[p] = t;
+    for (int i = k + 1; i < 4; i++) {   // row swap with static indices only
+      if (i == p) {
+#pragma unroll
+        for (int j = 0; j < 4; j++) { const double t = A[k][j]; A[k][j] = A[i][j]; A[i][j] = t; }
+        const double t = b[k]; b[k] = b[i]; b[i] = t;
+      }
     }
     const double inv = 1.0 / A[k][k];
 #pragma unroll
@@ -370,9 +373,13 @@ DEV int lu4(double A[4][4], int piv[4]) {
       if (::fabs(A[i][k]) > best) { best = ::fabs(A[i][k]); p = i; }
     if (!(best > 0.0) || !isfinite(best)) return 1;
     piv[k] = p;
-    if (p != k) {
+    // row swap with static indices only (a register-resident matrix)
 #pragma unroll
-      for (int j = k; j < 4; j++) { const double t = A[k][j]; A[k][j] = A[p][j]; A[p][j] = t; }
+    for (int i = k + 1; i < 4; i++) {
+      if (i == p) {
+#pragma unroll
+        for (int j = k; j < 4; j++) { const double t = A[k][j]; A[k][j] = A[i][j]; A[i][j] = t; }
+      }
     }
     const double inv = 1.0 / A[k][k];
 #pragma unroll
@@ -547,9 +554,15 @@ DEV void newton(const Cell& c, const Phys& ph, const Opts& o, const double x0[4]
       int back = 0;
       while (!ev.ok && back < 20) {                           // back up half-way
         nfail++;
+        if (GRRMHD_URAD_EXACT && nfail > 3) break;            // ends below either way
 #pragma unroll
         for (int i = 0; i < 4; i++) xn[i] = 0.5 * (x[i] + xn[i]);
-        eval_urad(c, ph, xn, Pn, ev);
+        if (GRRMHD_URAD_EXACT) {
+          eval_urad_jac(c, ph, xn, Pn, ev, J);
+          jok = ev.ok;
+        } else {
+          eval_urad(c, ph, xn, Pn, ev);
+        }
         back++;
       }
       if (!ev.ok || nfail > 3) {
@@ -906,4 +919,109 @@ DEV void lane_start(const Eval& ev, Lane& L) {
   L.h[4] = ev.eT;
   L.it = L.nrise = L.extra = L.conv = L.iters = 0;
   lane_take(ev, L);
+}
+
+// ---------------------------------------------------------------------------
+// The URAD attempt (exact Jacobians) as a lane state machine with one
+// residual evaluation per trip, so that lanes of a wavefront can hold cells
+// at different stages: START evaluates the guess, STEP takes the Newton step
+// from x and evaluates the new point, BACK evaluates half-way back towards x
+// after a failed evaluation.  The evaluation points, guesses and decisions
+// are those of newton<M_URAD>.
+// ---------------------------------------------------------------------------
+enum { UM_START = 0, UM_STEP = 1, UM_BACK = 2 };
+
+struct UradLane {
+  double x[4], p[4];     // iterate; point of this trip's evaluation
+  double Er[4], eT;      // residual and error at x
+  double J[4][4];        // Jacobian at x (the solve overwrites it)
+  double Pn[5];          // gas primitives at x: guess of the inner MHD inversion
+  double h[5];
+  Best best;
+  int it, nrise, extra, conv, nfail, iters, mode;
+};
+
+// Before the evaluation: STEP's loop-top checks and step (true: the attempt
+// ends here), BACK's half-way point.
+DEV bool urad_before(const Cell& c, const Opts& o, UradLane& L) {
+  if (L.mode == UM_BACK) {
+#pragma unroll
+    for (int i = 0; i < 4; i++) L.p[i] = 0.5 * (L.x[i] + L.p[i]);
+    return false;
+  }
+  if (L.mode != UM_STEP) return false;
+  if (L.it >= o.max_iter) return true;
+  if (L.eT < o.tol_urad) L.conv = 1;
+  if (L.conv) {
+    if (!o.roundoff || L.extra >= 3) return true;
+    L.extra++;
+  }
+  if (!L.conv && L.it >= 5 && L.eT > 0.5 * (L.h[0] + L.h[1] + L.h[2]) * (1.0 / 3.0)) return true;
+  double r[4] = {L.Er[0], L.Er[1], L.Er[2], L.Er[3]}, dx[4];
+  if (solve4(L.J, r, dx)) return true;
+#pragma unroll
+  for (int i = 0; i < 4; i++) L.p[i] = L.x[i] - dx[i];
+  const double Erl = rad_energy_lab(c.m, L.p);
+  if (Erl <= 0.0) {
+    const double a2 = c.m.alpha * c.m.alpha;
+    L.p[0] = -0.5 * ::fabs(Erl) + a2 * (c.m.up(0, 1) * L.p[1] + c.m.up(0, 2) * L.p[2] + c.m.up(0, 3) * L.p[3]);
+  }
+  return false;
+}
+
+DEV void urad_take(const Eval& ev, const double Jn[4][4], UradLane& L) {
+#pragma unroll
+  for (int i = 0; i < 4; i++) {
+    L.x[i] = L.p[i];
+    L.Er[i] = ev.Er[i];
+#pragma unroll
+    for (int j = 0; j < 4; j++) L.J[i][j] = Jn[i][j];
+  }
+#pragma unroll
+  for (int q = 0; q < 5; q++) L.Pn[q] = ev.P[q];
+  L.eT = ev.eT;
+}
+
+// After the evaluation at L.p (true: the attempt ends here).
+DEV bool urad_after(const Eval& ev, const double Jn[4][4], UradLane& L) {
+  if (L.mode == UM_START) {
+    keep(L.best, ev);
+    if (!ev.ok) return true;
+    urad_take(ev, Jn, L);
+#pragma unroll
+    for (int k = 0; k < 4; k++) L.h[k] = INFINITY;
+    L.h[4] = ev.eT;
+    L.it = L.nrise = L.extra = L.conv = L.nfail = 0;
+    L.mode = UM_STEP;
+    return false;
+  }
+  if (!ev.ok) {
+    L.nfail++;
+    if (L.nfail > 3) {
+      L.iters++;
+      return true;
+    }
+    L.mode = UM_BACK;
+    return false;
+  }
+  L.iters++;
+  bool small = true;
+#pragma unroll
+  for (int i = 0; i < 4; i++)
+    if (::fabs(L.p[i] - L.x[i]) > 10.0 * DBL_EPSILON * ::fabs(L.x[i])) small = false;
+  urad_take(ev, Jn, L);
+  const double prev = L.h[4];
+#pragma unroll
+  for (int k = 0; k < 4; k++) L.h[k] = L.h[k + 1];
+  L.h[4] = ev.eT;
+  if (ev.eT < L.best.eT) keep(L.best, ev);
+  bool done = false;
+  if (L.it >= 5 && ev.eT > prev) {
+    L.nrise++;
+    if (L.nrise >= 5) done = true;
+  }
+  if (small) done = true;
+  L.it++;
+  L.mode = UM_STEP;
+  return done;
 }

@@ -640,6 +640,18 @@ DEV long wave_append(bool need, int item, int* counter, int* list) {
   return slot;
 }
 
+// wavefront-aggregated queue fetch: one atomic for all lanes asking
+DEV long wave_fetch(bool need, int* next) {
+  const unsigned long long mask = __ballot(need);
+  if (mask == 0ull) return -1;
+  const int lane = threadIdx.x & 63;
+  const int leader = __ffsll((long long)mask) - 1;
+  int base = 0;
+  if (lane == leader) base = atomicAdd(next, __popcll(mask));
+  base = __shfl(base, leader, 64);
+  return need ? (long)base + __popcll(mask & ((1ull << lane) - 1ull)) : -1;
+}
+
 // Bookkeeping of one implicit launch: the cascade work list with the first
 // attempts' records, and lane statistics: stats[0] residual evaluations of
 // first PMHD attempts (Newton trips), stats[1] lane slots the wavefronts
@@ -839,6 +851,114 @@ __global__ void LB(64) k_implicit_batch_list(Ctx C, long n, const double* __rest
   }
 }
 
+// The cascade of a batch, compacting: a fixed grid of wavefronts whose lanes
+// take list entries from a cursor (one atomic per wavefront) and run the URAD
+// attempt as a lane state machine, one residual evaluation per trip, taking
+// the next entry as soon as their cell ends.  Extreme cells (URAD first, then
+// PMHD from scratch) go to the deferred list D for the per-cell cascade.
+// Results equal those of implicit_cell resuming from the same record.
+__global__ void LB(64) k_cascade_urad(Ctx C, long n, const double* __restrict__ Ui_,
+                                      const double* __restrict__ Pg_,
+                                      const double* __restrict__ dtc,
+                                      const double* __restrict__ chi_abs,
+                                      const double* __restrict__ chi_es,
+                                      double* __restrict__ Po, double* __restrict__ Uo,
+                                      int* __restrict__ iters, int* __restrict__ status,
+                                      double* __restrict__ err, Work W, int* cursor, Work D) {
+  const Phys ph = make_phys(C);
+  const Opts o = make_opts(C);
+  Metric m;
+  flat_metric(m);
+  const int cnt = *W.counter;
+  UradLane L;
+  Cell c;
+  long item = 0, slot = 0;
+  int pst = 0;
+  bool active = false, exhausted = false;
+  unsigned long long useful = 0, slots = 0;
+  for (;;) {
+    const bool need = !active && !exhausted;
+    const long got = wave_fetch(need, cursor);
+    bool defer = false;
+    if (need) {
+      if (got < cnt) {
+        slot = got;
+        item = W.list[slot];
+        double Ui[12], Pg[12];
+#pragma unroll
+        for (int q = 0; q < 12; q++) {
+          Ui[q] = Ui_[q * n + item];
+          Pg[q] = Pg_[q * n + item];
+        }
+        Prep pr;
+        prepare(m, ph, Ui, Pg, dtc[item], chi_abs[item], chi_es[item], c, pr);
+        pst = pr.status;
+        if (pr.extreme) {
+          defer = true;
+        } else {
+          // URAD from the first attempt's solution when it got below 1e-4, else from the guess
+          Best b0;
+          int it0;
+          rec_load(W.rec, slot, b0, it0);
+          const bool prev = b0.ok && b0.eT < 1e-4;
+          const double* src = prev ? b0.P : Pg;
+          rad_cons4(m, src, L.p);
+#pragma unroll
+          for (int q = 0; q < 5; q++) L.Pn[q] = src[q];
+          L.iters = it0;
+          L.mode = UM_START;
+          active = true;
+        }
+      } else {
+        exhausted = true;
+      }
+    }
+    wave_append(defer, (int)item, D.counter, D.list);
+    bool ended = false, doeval = false;
+    if (active) {
+      ended = urad_before(c, o, L);
+      doeval = !ended;
+    }
+    if (doeval) {
+      Eval ev;
+      double Jn[4][4];
+      eval_urad_jac(c, ph, L.p, L.Pn, ev, Jn);
+      ended = urad_after(ev, Jn, L);
+    }
+    const unsigned long long ev_mask = __ballot(doeval);
+    useful += __popcll(ev_mask);
+    slots += ev_mask ? 64ull : 0ull;
+    if (ended) {
+      Best best;
+      int it0;
+      rec_load(W.rec, slot, best, it0);
+      int bm = -1;
+      if (best.ok) bm = M_PMHD;
+      else best.eT = INFINITY;
+      if (L.best.ok && L.best.eT < best.eT) {
+        best = L.best;
+        bm = M_URAD;
+      }
+      double Ui[12], Pg[12];
+#pragma unroll
+      for (int q = 0; q < 12; q++) {
+        Ui[q] = Ui_[q * n + item];
+        Pg[q] = Pg_[q * n + item];
+      }
+      CellOut out;
+      if (bm < 0) failed_out(Ui, Pg, pst, L.iters, out);
+      else finalize(c, ph, o, best, bm, pst, L.iters, Ui, out);
+      store_out(out, item, n, Po, Uo, iters, status, err);
+      active = false;
+    }
+    if (!__any(active) && __all(exhausted)) break;
+  }
+  if ((threadIdx.x & 63) == 0 && useful) {
+    atomicAdd(&W.stats[2], useful);
+    atomicAdd(&W.stats[3], slots);
+  }
+}
+
 __global__ void LB(128) k_con2prim(Ctx C, const double* __restrict__ U, const double* Pguess,
                                    double* P, int* __restrict__ status) {
   const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1008,17 +1128,6 @@ DEV void setup_cell(const Metric& m, const double Ui[12], double dt, double ca, 
   c.chi_es = ce;
 }
 
-// wavefront-aggregated queue fetch: one atomic for all lanes asking
-DEV long wave_fetch(bool need, int* next) {
-  const unsigned long long mask = __ballot(need);
-  if (mask == 0ull) return -1;
-  const int lane = threadIdx.x & 63;
-  const int leader = __ffsll((long long)mask) - 1;
-  int base = 0;
-  if (lane == leader) base = atomicAdd(next, __popcll(mask));
-  base = __shfl(base, leader, 64);
-  return need ? (long)base + __popcll(mask & ((1ull << lane) - 1ull)) : -1;
-}
 
 DEV void finish_lane(const Cell& c, const Phys& ph, const Opts& o, Lane& L, double U0,
                      const double UB[3], long cidx, long nst, double* P, double* U, int* iters,
@@ -1088,13 +1197,15 @@ __global__ void LBP k_implicit_persist(Ctx C, long n, const double* __restrict__
       doeval = !ended;
     }
     if (doeval) {
+      // one evaluation call site for new and continuing lanes (a new lane's
+      // first evaluation is a full one), so a wave never runs two of them
       Eval ev;
+      if (first) L.chord = 0;
+      lane_eval(c, ph, L, ev);
       if (first) {
-        eval_pmhd(c, ph, L.x, ev, L.J);
         lane_start(ev, L);
         if (!ev.ok) ended = true;
       } else {
-        lane_eval(c, ph, L, ev);
         lane_take(ev, L);
         ended = lane_after(ev, xprev, L);
       }

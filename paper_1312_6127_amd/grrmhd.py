@@ -114,6 +114,7 @@ def lib():
             "grrmhd_time_implicit": (C.c_int, [_VP, C.c_int]),
             "grrmhd_implicit_time": (C.c_int, [_VP, C.POINTER(C.c_double), C.POINTER(C.c_int)]),
             "grrmhd_implicit_source_stats": (C.c_int, [_VP, C.POINTER(C.c_ulonglong), _VP]),
+            "grrmhd_implicit_source_cascade_stats": (C.c_int, [_VP, C.POINTER(C.c_ulonglong), _VP]),
         }
         for name, (res, args) in sigs.items():
             f = getattr(L, name)
@@ -368,6 +369,14 @@ def batch_stats(ws):
     last batched solve that used workspace ws (a (tensor, bytes) pair)."""
     out = (C.c_ulonglong * 3)()
     _check(lib().grrmhd_implicit_source_stats(_ptr(ws[0]), out, _stream()))
+    return tuple(int(v) for v in out)
+
+
+def batch_cascade_stats(ws):
+    """(residual evaluations, lane slots) of the compacted cascade of the last
+    batched solve that used workspace ws."""
+    out = (C.c_ulonglong * 2)()
+    _check(lib().grrmhd_implicit_source_cascade_stats(_ptr(ws[0]), out, _stream()))
     return tuple(int(v) for v in out)
 
 

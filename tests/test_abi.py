@@ -81,6 +81,8 @@ def test_invalid_parameters_are_rejected_before_any_device_work(L):
     out = (C.c_ulonglong * 3)()
     assert L.grrmhd_implicit_stats(None, out) == -1
     assert L.grrmhd_implicit_source_stats(C.c_void_p(260), out, None) == -1
+    assert L.grrmhd_implicit_source_cascade_stats(C.c_void_p(260), out, None) == -1
+    assert L.grrmhd_implicit_source_cascade_stats(None, out, None) == -1
 
 
 def test_batch_workspace_sizes(L):
@@ -91,7 +93,7 @@ def test_batch_workspace_sizes(L):
     for n in (1, 63, 64, 1000, 1 << 24):
         a, b, c = f(n, G.PER_CELL), f(n, G.PERSISTENT), f(n, G.PER_ITERATION)
         assert a == b == L.grrmhd_implicit_source_workspace_bytes(n)
-        # list, first-attempt record (13 doubles, 3 ints) per cell
-        assert a >= 256 + 4 * n + 13 * 8 * n + 3 * 4 * n and a % 256 == 0
+        # list, first-attempt record (13 doubles, 3 ints), deferred list per cell
+        assert a >= 256 + 4 * n + 13 * 8 * n + 3 * 4 * n + 4 * n and a % 256 == 0
         # two queues, 47 doubles and 8 ints of lane state per cell
         assert c >= a + 8 * n + 47 * 8 * n + 8 * 4 * n

@@ -285,6 +285,11 @@ def test_implicit_batch_forms_identical(G, orc, form):
     s1 = G.batch_stats(ws)
     say("  stats per-cell", s0, form, s1)
     assert s1[0] == s0[0] and s1[2] == s0[2]
+    # the compacted cascade: the same residual evaluations whatever the
+    # order lanes took the cells in
+    c0, c1 = G.batch_cascade_stats(ws0), G.batch_cascade_stats(ws)
+    say("  cascade evaluations, lane slots", c0, c1)
+    assert c0[0] == c1[0] and 0 < c0[0] <= c0[1] and c1[0] <= c1[1]
     assert s0[0] <= s0[1] and s1[0] <= s1[1]
     # every non-extreme cell takes between 1 and max_iter + 1 trips
     st = ref[3]
