@@ -20,6 +20,7 @@ ST_PMHD, ST_URAD, ST_TYPE2_NEG, ST_BASIC, ST_C2P_FAIL, ST_FLOOR, ST_NOT_ACCEPT, 
     ST_NO_GOOD_NB, ST_EXTREME = (1 << i for i in range(10))
 
 _BC = {"outflow": 0, "periodic": 1, "reflect": 2, "polar": 3}
+_SCHEME = {"rk3": 0, "imex2": 1, "imex2b": 2, "imex3": 3}
 
 
 def build(force: bool = False) -> str:
@@ -46,6 +47,7 @@ class Params(C.Structure):
         ("max_iter", C.c_int), ("roundoff", C.c_int),
         ("rho_floor", C.c_double), ("u_floor", C.c_double), ("bsq_rho_max", C.c_double),
         ("bsq_u_max", C.c_double), ("u_rho_max", C.c_double), ("erad_floor", C.c_double),
+        ("scheme", C.c_int),
     ]
 
 
@@ -76,6 +78,7 @@ def params(d: dict) -> Params:
     p.flux = 1 if d["flux"] == "hll" else 0
     p.max_iter = int(d["max_iter"])
     p.roundoff = int(d["roundoff"])
+    p.scheme = _SCHEME[d.get("scheme", "rk3")]
     return p
 
 

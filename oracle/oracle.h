@@ -26,6 +26,9 @@
 enum { ORC_MINKOWSKI = 0, ORC_KERR_SCHILD = 1 };
 enum { ORC_BC_OUTFLOW = 0, ORC_BC_PERIODIC = 1, ORC_BC_REFLECT = 2, ORC_BC_POLAR = 3 };
 enum { ORC_FLUX_LLF = 0, ORC_FLUX_HLL = 1 };
+/* time integrators (Sec. 4.1): RK3 with equal explicit and implicit
+ * coefficients, and the IMEX2, IMEX2B and IMEX3 schemes */
+enum { ORC_RK3 = 0, ORC_IMEX2 = 1, ORC_IMEX2B = 2, ORC_IMEX3 = 3 };
 
 /* per-cell status bits of the implicit solve and fix-ups */
 enum {
@@ -58,6 +61,7 @@ typedef struct {
   int max_iter;           /* Newton steps per method                          */
   int roundoff;           /* keep iterating past tolerance to round-off       */
   double rho_floor, u_floor, bsq_rho_max, bsq_u_max, u_rho_max, erad_floor;
+  int scheme;             /* ORC_RK3, ORC_IMEX2, ORC_IMEX2B, ORC_IMEX3         */
 } orc_params;
 
 /* ---- geometry (Sec. 2; metric of the Kerr-Schild form) ---- */
@@ -119,7 +123,12 @@ void orc_implicit_grid(const orc_params *p, const double *Uexp, const double *Pg
                        const double *chi_abs, const double *chi_es, double *Pout, double *Uout,
                        int *iters, int *status);
 void orc_fixup(const orc_params *p, double *P, double *U, int *status);
-/* full RK3-IMEX step; dt in/out (computed unless dt_fixed) */
+/* radiation 4-force source of primitives P at interior cells: M[1+nu] =
+ * sqrt(-g) G_nu, M[8+nu] = -sqrt(-g) G_nu, other slots 0 (arrays [12][N]) */
+void orc_source_m(const orc_params *p, const double *P, const double *chi_abs,
+                  const double *chi_es, double *M);
+/* one full step of the scheme p->scheme; dt in/out (computed from P^n
+ * unless dt_fixed) */
 int orc_step(const orc_params *p, double *P, double *U, const double *chi_abs, const double *chi_es,
              double *dt, int dt_fixed, int *status, int *iters);
 

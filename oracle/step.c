@@ -417,48 +417,184 @@ void orc_fixup(const orc_params *p, double *P, double *U, int *status) {
   free(P0);
 }
 
-/* one full RK3-IMEX step (Sec. 4.1 RK3 with equal explicit and implicit
- * coefficients; stage k is implicit in its own new value) */
+/* ---- radiation 4-force source of a stage (the M^i of the IMEX schemes) ---- */
+void orc_source_m(const orc_params *p, const double *P, const double *chi_abs,
+                  const double *chi_es, double *M) {
+  const long N = orc_ncell_alloc(p);
+#pragma omp parallel for collapse(2)
+  for (int k = orc_ng(p, 2); k < orc_ng(p, 2) + p->n[2]; k++)
+    for (int j = orc_ng(p, 1); j < orc_ng(p, 1) + p->n[1]; j++)
+      for (int i = orc_ng(p, 0); i < orc_ng(p, 0) + p->n[0]; i++) {
+        const long c = IDX(p, i, j, k);
+        double x1, x2;
+        orc_cell_x(p, i, j, &x1, &x2);
+        orc_geom g;
+        orc_geom_point(p, x1, x2, &g);
+        double Pc[12], G[4];
+        for (int q = 0; q < 12; q++) Pc[q] = P[q * N + c];
+        orc_four_force(p, &g, Pc, chi_abs[c] * Pc[0], chi_es[c] * Pc[0], G);
+        for (int q = 0; q < 12; q++) M[q * N + c] = 0.0;
+        for (int nu = 0; nu < 4; nu++) {
+          M[(1 + nu) * N + c] = g.gdet * G[nu];     /* gas gains G_nu  */
+          M[(8 + nu) * N + c] = -g.gdet * G[nu];    /* radiation loses */
+        }
+      }
+}
+
+/* ---- the time integrators as stage tables (Sec. 4.1) ----
+ * Stage i:  U^i = a U^n + b U^j + c dt F^{i-1} + dt sum_k m_k M^k  + g dt M(U^i)
+ * F^{i-1}: flux divergence and geometric source of the previous stage's
+ * primitives (of P^n at the first stage); M^k: the 4-force source of stage
+ * k's primitives.  A stage with g = 0 is the final explicit combination;
+ * its primitives come from the MHD and radiation inversions. */
+typedef struct {
+  double a, b;
+  int j;          /* stage of the U^j term, -1 for none */
+  double c;
+  double m[4];
+  double g;
+} orc_stage;
+
+typedef struct {
+  int ns;
+  orc_stage s[5];
+} orc_scheme;
+
+static orc_scheme scheme_table(int which) {
+  orc_scheme S;
+  memset(&S, 0, sizeof(S));
+  for (int i = 0; i < 5; i++) S.s[i].j = -1;
+  if (which == ORC_IMEX2) {
+    /* eq. IMEX2, gamma = 1 - 1/sqrt(2) */
+    const double ga = 1.0 - 1.0 / sqrt(2.0);
+    S.ns = 3;
+    S.s[0].a = 1.0; S.s[0].g = ga;
+    S.s[1].a = (3.0 * ga - 1.0) / ga; S.s[1].b = (1.0 - 2.0 * ga) / ga; S.s[1].j = 0;
+    S.s[1].c = 1.0; S.s[1].g = ga;
+    S.s[2].a = 0.5; S.s[2].b = 0.5; S.s[2].j = 1; S.s[2].c = 0.5;
+    S.s[2].m[0] = ga; S.s[2].m[1] = 0.5 * (1.0 - ga);
+  } else if (which == ORC_IMEX2B) {
+    /* eq. IMEX2B */
+    S.ns = 4;
+    S.s[0].a = 1.0; S.s[0].g = 0.25;
+    S.s[1].a = 1.0; S.s[1].c = 0.5; S.s[1].g = 0.25;
+    S.s[2].b = 1.0; S.s[2].j = 1; S.s[2].c = 0.5; S.s[2].m[0] = 1.0 / 3.0;
+    S.s[2].m[1] = 1.0 / 12.0; S.s[2].g = 1.0 / 3.0;
+    S.s[3].a = 1.0 / 3.0; S.s[3].b = 2.0 / 3.0; S.s[3].j = 2; S.s[3].c = 1.0 / 3.0;
+    S.s[3].m[0] = S.s[3].m[1] = S.s[3].m[2] = 1.0 / 9.0;
+  } else if (which == ORC_IMEX3) {
+    /* eq. IMEX3 with the printed alpha, beta, eta */
+    const double al = 0.24169426078821, be = 0.06042356519705, et = 0.12915286960590;
+    S.ns = 5;
+    S.s[0].a = 1.0; S.s[0].g = al;
+    S.s[1].a = 2.0; S.s[1].b = -1.0; S.s[1].j = 0; S.s[1].g = al;
+    S.s[2].a = 1.0; S.s[2].c = 1.0; S.s[2].m[1] = 1.0 - al; S.s[2].g = al;
+    S.s[3].a = 0.75; S.s[3].b = 0.25; S.s[3].j = 2; S.s[3].c = 0.25;
+    S.s[3].m[0] = be; S.s[3].m[1] = (-1.0 + al + 4.0 * et) / 4.0;
+    S.s[3].m[2] = (2.0 - 5.0 * al - 4.0 * (be + et)) / 4.0; S.s[3].g = al;
+    S.s[4].a = 1.0 / 3.0; S.s[4].b = 2.0 / 3.0; S.s[4].j = 3; S.s[4].c = 2.0 / 3.0;
+    S.s[4].m[0] = -2.0 * be / 3.0; S.s[4].m[1] = (1.0 - 4.0 * et) / 6.0;
+    S.s[4].m[2] = (-1.0 + 4.0 * al + 4.0 * (be + et)) / 6.0; S.s[4].m[3] = 4.0 * (1.0 - al) / 6.0;
+  } else {
+    /* RK3 (Shu-Osher) with the same coefficients for the implicit part */
+    S.ns = 3;
+    S.s[0].a = 1.0; S.s[0].c = 1.0; S.s[0].g = 1.0;
+    S.s[1].a = 0.75; S.s[1].b = 0.25; S.s[1].j = 0; S.s[1].c = 0.25; S.s[1].g = 0.25;
+    S.s[2].a = 1.0 / 3.0; S.s[2].b = 2.0 / 3.0; S.s[2].j = 1; S.s[2].c = 2.0 / 3.0;
+    S.s[2].g = 2.0 / 3.0;
+  }
+  return S;
+}
+
+/* one full step of the scheme p->scheme (Sec. 4.1); each implicit stage is
+ * implicit in its own new value with dt_k = g dt */
 int orc_step(const orc_params *p, double *P, double *U, const double *chi_abs, const double *chi_es,
              double *dt, int dt_fixed, int *status, int *iters) {
+  const orc_scheme S = scheme_table(p->scheme);
   const long N = orc_ncell_alloc(p);
+  const size_t B12 = sizeof(double) * 12 * N;
   double *F = malloc(sizeof(double) * 3 * 12 * N);
   double *emf = malloc(sizeof(double) * 3 * N);
   double *vch = malloc(sizeof(double) * 3 * N);
-  double *Uexp = malloc(sizeof(double) * 12 * N);
-  double *Un = malloc(sizeof(double) * 12 * N);
-  double *Pk = malloc(sizeof(double) * 12 * N);
-  double *Uk = malloc(sizeof(double) * 12 * N);
+  double *Uexp = malloc(B12);
+  double *Un = malloc(B12);
+  double *Pk = malloc(B12);
+  double *Ust[5], *Mst[5];
+  int need_m[5] = {0};
+  for (int i = 0; i < S.ns; i++)
+    for (int k = 0; k < 4; k++)
+      if (S.s[i].m[k] != 0.0) need_m[k] = 1;
+  for (int i = 0; i < S.ns; i++) {
+    Ust[i] = malloc(B12);
+    memcpy(Ust[i], U, B12);   /* ghost cells keep U^n */
+    Mst[i] = need_m[i] ? calloc(12 * N, sizeof(double)) : NULL;
+  }
   int *st = calloc(N, sizeof(int));
   int *stacc = calloc(N, sizeof(int));
   int *it = calloc(N, sizeof(int));
-  memcpy(Un, U, sizeof(double) * 12 * N);
-  memcpy(Pk, P, sizeof(double) * 12 * N);
-  memcpy(Uk, U, sizeof(double) * 12 * N);
-  memcpy(Uexp, U, sizeof(double) * 12 * N);
-  const double A[3] = {1.0, 0.75, 1.0 / 3.0}, B[3] = {0.0, 0.25, 2.0 / 3.0},
-               C[3] = {1.0, 0.25, 2.0 / 3.0};
+  memcpy(Un, U, B12);
+  memcpy(Pk, P, B12);
+  memcpy(Uexp, U, B12);
   int nbad = 0;
   if (iters) memset(iters, 0, sizeof(int) * N);
-  for (int s = 0; s < 3; s++) {
+  int fresh = 0;   /* F holds the fluxes of Pk */
+  if (!dt_fixed) {
+    /* Courant dt from the wave speeds of P^n (Sec. 4.4) */
     orc_bc(p, Pk);
     orc_fluxes(p, Pk, chi_abs, chi_es, F, emf, vch);
-    if (s == 0 && !dt_fixed) *dt = orc_timestep(p, vch);
-    orc_explicit_update(p, A[s], B[s], C[s], *dt, Pk, Un, Uk, F, emf, Uexp);
-    orc_implicit_grid(p, Uexp, Pk, C[s] * (*dt), chi_abs, chi_es, Pk, Uk, it, st);
-    orc_fixup(p, Pk, Uk, st);
+    *dt = orc_timestep(p, vch);
+    fresh = 1;
+  }
+  for (int i = 0; i < S.ns; i++) {
+    const orc_stage *s = &S.s[i];
+    const double *Uj = (s->j >= 0) ? Ust[s->j] : Un;
+    if (s->c != 0.0) {
+      if (!fresh) {
+        orc_bc(p, Pk);
+        orc_fluxes(p, Pk, chi_abs, chi_es, F, emf, vch);
+      }
+      orc_explicit_update(p, s->a, s->b, s->c, *dt, Pk, Un, Uj, F, emf, Uexp);
+    } else {
+      for (long q = 0; q < 12 * N; q++) Uexp[q] = s->a * Un[q] + (s->b != 0.0 ? s->b * Uj[q] : 0.0);
+    }
+    for (int k = 0; k < i && k < 4; k++) {
+      if (s->m[k] == 0.0) continue;
+      for (long q = 0; q < 12 * N; q++) Uexp[q] += *dt * s->m[k] * Mst[k][q];
+    }
+    if (s->g > 0.0) {
+      orc_implicit_grid(p, Uexp, Pk, s->g * (*dt), chi_abs, chi_es, Pk, Ust[i], it, st);
+    } else {
+      /* final explicit combination: inversions; a failed MHD inversion is a
+       * failed cell (neighbour average) */
+      double *Pg = malloc(B12);
+      memcpy(Pg, Pk, B12);
+      orc_con2prim(p, Uexp, Pg, Pk, st);
+      free(Pg);
+      memcpy(Ust[i], Uexp, B12);
+      for (long c = 0; c < N; c++) {
+        if (st[c] & ORC_ST_C2P_FAIL) st[c] |= ORC_ST_FAIL;
+        it[c] = 0;
+      }
+    }
+    orc_fixup(p, Pk, Ust[i], st);
+    fresh = 0;
+    if (i < 4 && need_m[i]) orc_source_m(p, Pk, chi_abs, chi_es, Mst[i]);
     for (long c = 0; c < N; c++) {
       stacc[c] |= st[c];
       if (iters) iters[c] += it[c];
     }
   }
   if (status) memcpy(status, stacc, sizeof(int) * N);
-  /* write back interior (ghost cells of P keep the last stage's fill) */
-  memcpy(P, Pk, sizeof(double) * 12 * N);
-  memcpy(U, Uk, sizeof(double) * 12 * N);
+  /* write back (ghost cells of P keep the last fill) */
+  memcpy(P, Pk, B12);
+  memcpy(U, Ust[S.ns - 1], B12);
   for (long c = 0; c < N; c++)
     if (stacc[c] & ORC_ST_FAIL) nbad++;
-  free(F); free(emf); free(vch); free(Uexp); free(Un); free(Pk); free(Uk); free(st); free(stacc);
+  for (int i = 0; i < S.ns; i++) {
+    free(Ust[i]);
+    free(Mst[i]);
+  }
+  free(F); free(emf); free(vch); free(Uexp); free(Un); free(Pk); free(st); free(stacc);
   free(it);
   return nbad;
 }
