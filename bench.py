@@ -9,7 +9,9 @@ Prints one JSON line.  value = interior cells x steps / wall time of the K
 timed FP64 steps (HIP events on the step's stream, inputs resident in HBM).
 mixed_precision: the same run with FP32 reconstruction, face states,
 Riemann fluxes and EMFs, and the per-field error of both precisions against
-the FP64 oracle after the oracle's steps.  roofline: the dominant kernel
+the FP64 oracle after the oracle's steps.  imex3: the same workload stepped
+with the IMEX3 scheme (eq. IMEX3; four implicit stages), its time per step
+and its error against the oracle's IMEX3 steps.  roofline: the dominant kernel
 (the implicit kernel's first PMHD attempt), its average launch time from HIP
 events on its stream inside the timed region.  cpu_baseline: the FP64 oracle
 stepping the same workload on the host cores (bounded sample).
@@ -51,6 +53,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, nargs=3, default=[128, 64, 32])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--imex-err-steps", type=int, default=3,
+                    help="IMEX3 steps compared with the oracle's")
     ap.add_argument("--cpu-steps", type=int, default=20,
                     help="oracle steps (the CPU baseline sample and the error reference)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
@@ -264,6 +268,11 @@ def main():
     pdm = dict(pd, precision="mixed")
     rmx = time_steps(G, torch, dev, pdm, P, ca, ce, args.steps, args.warmup, kernel_timing=False)
     print(f"mixed steps: {rmx['ms'] / args.steps:.3f} ms/step", file=sys.stderr, flush=True)
+    pdi = dict(pd, scheme="imex3")
+    rim = time_steps(G, torch, dev, pdi, P, ca, ce, args.steps, args.warmup, kernel_timing=False)
+    print(f"imex3 steps: {rim['ms'] / args.steps:.3f} ms/step", file=sys.stderr, flush=True)
+    imex = {"value": zones * args.steps / (rim["ms"] * 1e-3), "ms_per_step": rim["ms"] / args.steps,
+            "time_vs_rk3": rim["ms"] / r64["ms"]}
 
     # dominant kernel: the implicit kernel of each stage, timed with HIP events
     # on its stream inside the timed region
@@ -317,6 +326,16 @@ def main():
         mixed["err_vs_oracle"] = errs["mixed"]
         mixed["fp64_err_vs_oracle_max"] = errs["fp64"]["max"]
         mixed["err_steps"] = args.cpu_steps
+        # IMEX3 against the oracle's IMEX3 (a few steps: the oracle is slow)
+        Ph, Uh = P, oracle.prim_to_cons(pdi, P)
+        for _ in range(args.imex_err_steps):
+            Ph, Uh, dth, sth, ith, nb = oracle.step(pdi, Ph, Uh, ca, ce)
+        ref = [x.reshape((12,) + na[::-1])[(slice(None),) + interior].reshape(12, -1) for x in (Ph, Uh)]
+        Pg, Ug = gpu_run(G, torch, dev, pdi, P, ca, ce, args.imex_err_steps)
+        got = [x.reshape((12,) + na[::-1])[(slice(None),) + interior].reshape(12, -1) for x in (Pg, Ug)]
+        e = [field_errors(got[0], ref[0]), field_errors(got[1], ref[1])]
+        imex["err_vs_oracle_max"] = max(max(e[0].values()), max(e[1].values()))
+        imex["err_steps"] = args.imex_err_steps
 
     out = {
         "metric": "zone-cycles/s per GRRMHD step (FP32-mixed vs FP64) at stated rel. error; % HBM peak",
@@ -339,6 +358,7 @@ def main():
                      "achieved_GBs": value * STEP_BYTES_PER_ZONE / 1e9,
                      "frac": value * STEP_BYTES_PER_ZONE / 1e9 / HBM_PEAK_GBS},
         "mixed_precision": mixed,
+        "imex3": imex,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

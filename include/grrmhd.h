@@ -50,6 +50,7 @@ enum { GRRMHD_MINKOWSKI = 0, GRRMHD_KERR_SCHILD = 1 };
 enum { GRRMHD_BC_OUTFLOW = 0, GRRMHD_BC_PERIODIC = 1, GRRMHD_BC_REFLECT = 2, GRRMHD_BC_POLAR = 3 };
 enum { GRRMHD_FLUX_LLF = 0, GRRMHD_FLUX_HLL = 1 };
 enum { GRRMHD_FP64 = 0, GRRMHD_MIXED = 1 };
+enum { GRRMHD_RK3 = 0, GRRMHD_IMEX2 = 1, GRRMHD_IMEX2B = 2, GRRMHD_IMEX3 = 3 };
 enum { GRRMHD_EINVAL = -1, GRRMHD_EHIP = -2, GRRMHD_ENOMEM = -3 };
 
 /* per-cell status bits written by the implicit solve and the fix-ups */
@@ -100,6 +101,11 @@ typedef struct {
                            try the next method unless the best error is
                            within 10 tol_pmhd (instead of tol_accept)        */
   double rho_floor, u_floor, bsq_rho_max, bsq_u_max, u_rho_max, erad_floor;
+  int scheme;           /* time integrator of grrmhd_step (Sec. 4.1):
+                           GRRMHD_RK3 (default; RK3 with the same stages and
+                           coefficients for the implicit part), or the IMEX
+                           schemes GRRMHD_IMEX2, GRRMHD_IMEX2B, GRRMHD_IMEX3
+                           (eq. IMEX2, IMEX2B, IMEX3)                        */
 } grrmhd_params;
 
 typedef struct grrmhd_grid grrmhd_grid;
@@ -180,14 +186,24 @@ int grrmhd_implicit_grid(grrmhd_grid *g, const double *Uexp, const double *Pgues
  * where P changed.  `scratch` is device memory of at least 13 N doubles. */
 int grrmhd_fixup(grrmhd_grid *g, double *P, double *U, int *status, double *scratch);
 
-/* One full RK3-IMEX time step (Sec. 4.1: third-order Shu-Osher stages with
- * identical explicit and implicit coefficients; stage k implicit in its own
- * value with dt_k = c_k dt).  P, U [12][N] in/out: U^n must hold the
- * conserved state of P^n at interior cells; on return both hold the new
- * state at interior cells (ghosts of P are stale).  dt_dev: device scalar,
- * read when dt_fixed != 0, otherwise computed at stage 1 and written.
- * status/iters [N] (nullable): OR of status bits / sum of Newton steps over
- * the three stages.  workspace: device buffer of grrmhd_workspace_bytes(). */
+/* One full time step of the grid's scheme (Sec. 4.1).  GRRMHD_RK3:
+ * third-order Shu-Osher stages with identical explicit and implicit
+ * coefficients, stage k implicit in its own value with dt_k = c_k dt.
+ * GRRMHD_IMEX2/IMEX2B/IMEX3 (eq. IMEX2, IMEX2B, IMEX3): each implicit stage
+ * i solves U^i = [explicit bracket] + g_i dt M(U^i); the brackets combine
+ * U^n, one earlier stage, the flux divergence and geometric source of the
+ * previous stage and the stored 4-force sources M^k of earlier stages
+ * (M^k = (U^k - bracket)/(g_k dt) from stage k's implicit solve, before its
+ * fix-ups, zero where it failed); the final
+ * combination is explicit and followed by the MHD and radiation (BASIC)
+ * inversions, a cell whose MHD inversion fails being a failed cell.  P, U
+ * [12][N] in/out: U^n must hold the conserved state of P^n at interior
+ * cells; on return both hold the new state at interior cells (ghosts of P
+ * are stale).  dt_dev: device scalar, read when dt_fixed != 0, otherwise
+ * computed from the wave speeds of P^n and written.  status/iters [N]
+ * (nullable): OR of status bits / sum of Newton steps over the stages.
+ * workspace: device buffer of grrmhd_workspace_bytes() (which depends on
+ * the scheme). */
 int grrmhd_step(grrmhd_grid *g, double *P, double *U, const double *chi_abs,
                 const double *chi_es, double *dt_dev, int dt_fixed, int *status, int *iters,
                 void *workspace, size_t ws_bytes);
@@ -199,8 +215,9 @@ int grrmhd_step(grrmhd_grid *g, double *P, double *U, const double *chi_abs,
  * implicit-function theorem on the PMHD residual at the converged state
  * (Sec. 4.8; one transposed 4x4 solve per cell), the fluxes, EMFs, source
  * and ghost fill by their local Jacobians (dual numbers) and transposes.
- * Fix-ups are taken as the identity (a failed cell passes its conserved
- * cotangent through).  P_n [12][N] (interior read; not modified), gU_next
+ * Floors are taken as the identity; a failed cell's neighbour average is
+ * differentiated (its own failed solve receives nothing).  RK3 grids only
+ * (EINVAL for another scheme).  P_n [12][N] (interior read; not modified), gU_next
  * [12][N] (interior read), gP_n [12][N] out (ghosts zero); P_next, U_next
  * (nullable) receive the forward result.  workspace: device buffer of
  * grrmhd_adjoint_workspace_bytes() bytes, 256-byte aligned.  Errors: EINVAL,

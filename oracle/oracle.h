@@ -123,10 +123,6 @@ void orc_implicit_grid(const orc_params *p, const double *Uexp, const double *Pg
                        const double *chi_abs, const double *chi_es, double *Pout, double *Uout,
                        int *iters, int *status);
 void orc_fixup(const orc_params *p, double *P, double *U, int *status);
-/* radiation 4-force source of primitives P at interior cells: M[1+nu] =
- * sqrt(-g) G_nu, M[8+nu] = -sqrt(-g) G_nu, other slots 0 (arrays [12][N]) */
-void orc_source_m(const orc_params *p, const double *P, const double *chi_abs,
-                  const double *chi_es, double *M);
 /* one full step of the scheme p->scheme; dt in/out (computed from P^n
  * unless dt_fixed) */
 int orc_step(const orc_params *p, double *P, double *U, const double *chi_abs, const double *chi_es,

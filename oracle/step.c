@@ -417,36 +417,14 @@ void orc_fixup(const orc_params *p, double *P, double *U, int *status) {
   free(P0);
 }
 
-/* ---- radiation 4-force source of a stage (the M^i of the IMEX schemes) ---- */
-void orc_source_m(const orc_params *p, const double *P, const double *chi_abs,
-                  const double *chi_es, double *M) {
-  const long N = orc_ncell_alloc(p);
-#pragma omp parallel for collapse(2)
-  for (int k = orc_ng(p, 2); k < orc_ng(p, 2) + p->n[2]; k++)
-    for (int j = orc_ng(p, 1); j < orc_ng(p, 1) + p->n[1]; j++)
-      for (int i = orc_ng(p, 0); i < orc_ng(p, 0) + p->n[0]; i++) {
-        const long c = IDX(p, i, j, k);
-        double x1, x2;
-        orc_cell_x(p, i, j, &x1, &x2);
-        orc_geom g;
-        orc_geom_point(p, x1, x2, &g);
-        double Pc[12], G[4];
-        for (int q = 0; q < 12; q++) Pc[q] = P[q * N + c];
-        orc_four_force(p, &g, Pc, chi_abs[c] * Pc[0], chi_es[c] * Pc[0], G);
-        for (int q = 0; q < 12; q++) M[q * N + c] = 0.0;
-        for (int nu = 0; nu < 4; nu++) {
-          M[(1 + nu) * N + c] = g.gdet * G[nu];     /* gas gains G_nu  */
-          M[(8 + nu) * N + c] = -g.gdet * G[nu];    /* radiation loses */
-        }
-      }
-}
-
 /* ---- the time integrators as stage tables (Sec. 4.1) ----
  * Stage i:  U^i = a U^n + b U^j + c dt F^{i-1} + dt sum_k m_k M^k  + g dt M(U^i)
  * F^{i-1}: flux divergence and geometric source of the previous stage's
  * primitives (of P^n at the first stage); M^k: the 4-force source of stage
- * k's primitives.  A stage with g = 0 is the final explicit combination;
- * its primitives come from the MHD and radiation inversions. */
+ * k as its implicit solve found it, (U^k - [bracket])/(g_k dt) in the gas
+ * and radiation energy-momentum slots (zero elsewhere, and where the solve
+ * failed).  A stage with g = 0 is the final explicit combination; its
+ * primitives come from the MHD and radiation inversions. */
 typedef struct {
   double a, b;
   int j;          /* stage of the U^j term, -1 for none */
@@ -563,6 +541,15 @@ int orc_step(const orc_params *p, double *P, double *U, const double *chi_abs, c
     }
     if (s->g > 0.0) {
       orc_implicit_grid(p, Uexp, Pk, s->g * (*dt), chi_abs, chi_es, Pk, Ust[i], it, st);
+      if (i < 4 && need_m[i]) {
+        const double gdt = s->g * (*dt);
+        for (long c = 0; c < N; c++)
+          for (int q = 0; q < 12; q++) {
+            const int slot = (q >= 1 && q <= 4) || q >= 8;
+            Mst[i][q * N + c] = (slot && !(st[c] & ORC_ST_FAIL))
+                                    ? (Ust[i][q * N + c] - Uexp[q * N + c]) / gdt : 0.0;
+          }
+      }
     } else {
       /* final explicit combination: inversions; a failed MHD inversion is a
        * failed cell (neighbour average) */
@@ -578,7 +565,6 @@ int orc_step(const orc_params *p, double *P, double *U, const double *chi_abs, c
     }
     orc_fixup(p, Pk, Ust[i], st);
     fresh = 0;
-    if (i < 4 && need_m[i]) orc_source_m(p, Pk, chi_abs, chi_es, Mst[i]);
     for (long c = 0; c < N; c++) {
       stacc[c] |= st[c];
       if (iters) iters[c] += it[c];

@@ -90,6 +90,7 @@ extern "C" void grrmhd_default_params(grrmhd_params* p) {
   p->courant = 0.5;
   p->flux = GRRMHD_FLUX_LLF;
   p->precision = GRRMHD_FP64;
+  p->scheme = GRRMHD_RK3;
   p->r_fp64 = 2.0;
   p->tol_pmhd = 1e-12;
   p->tol_urad = 1e-9;
@@ -115,6 +116,7 @@ static int validate(const grrmhd_params* p, bool need_grid) {
     return fail(GRRMHD_EINVAL, "bad precision");
   if (p->metric != GRRMHD_MINKOWSKI && p->metric != GRRMHD_KERR_SCHILD)
     return fail(GRRMHD_EINVAL, "bad metric");
+  if (p->scheme < GRRMHD_RK3 || p->scheme > GRRMHD_IMEX3) return fail(GRRMHD_EINVAL, "bad scheme");
   if (!need_grid) return 0;
   if (p->ng != 2) return fail(GRRMHD_EINVAL, "ghost width must be 2 (MC reconstruction)");
   for (int d = 0; d < 3; d++) {
@@ -266,11 +268,80 @@ extern "C" int grrmhd_set_stream(grrmhd_grid* g, void* s) {
 extern "C" long grrmhd_ncell_alloc(const grrmhd_grid* g) { return g ? g->C.Ntot : -1; }
 
 // workspace layout (doubles unless noted), each part 256-byte aligned
-struct WsLayout {
-  size_t F, emf, vch, Uexp, Pa, Ua, err, st, it, total;
+// ---------------------------------------------------------------------------
+// Time integrators (Sec. 4.1) as stage tables.  Stage i:
+//   U^i = a U^n + b U^j + c dt F^{i-1} + dt sum_k m_k M^k + g dt M(U^i),
+// F^{i-1} the flux divergence and geometric source of the previous stage's
+// primitives (of P^n at stage 0), M^k the 4-force source of stage k as its
+// implicit solve found it.  g = 0 marks the final explicit combination (then
+// inversions).
+// ---------------------------------------------------------------------------
+struct Stage {
+  double a, b;
+  int j;            // stage of the U^j term (-1: none)
+  double c;
+  double m[4];
+  double g;
 };
 
-static WsLayout ws_layout(const Ctx& C) {
+struct Scheme {
+  int ns;
+  Stage s[5];
+  bool keep_m[4];   // M^k read by a later stage
+};
+
+static Scheme make_scheme(int which) {
+  Scheme S;
+  memset(&S, 0, sizeof(S));
+  auto st = [&](double a, double b, int j, double c, double g, double m0 = 0.0, double m1 = 0.0,
+                double m2 = 0.0, double m3 = 0.0) {
+    Stage& x = S.s[S.ns++];
+    x.a = a; x.b = b; x.j = j; x.c = c; x.g = g;
+    x.m[0] = m0; x.m[1] = m1; x.m[2] = m2; x.m[3] = m3;
+  };
+  switch (which) {
+    case GRRMHD_IMEX2: {            // eq. IMEX2
+      const double gm = 1.0 - 1.0 / sqrt(2.0);
+      st(1.0, 0.0, -1, 0.0, gm);
+      st((3.0 * gm - 1.0) / gm, (1.0 - 2.0 * gm) / gm, 0, 1.0, gm);
+      st(0.5, 0.5, 1, 0.5, 0.0, gm, 0.5 * (1.0 - gm));
+      break;
+    }
+    case GRRMHD_IMEX2B:             // eq. IMEX2B
+      st(1.0, 0.0, -1, 0.0, 0.25);
+      st(1.0, 0.0, -1, 0.5, 0.25);
+      st(0.0, 1.0, 1, 0.5, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 12.0);
+      st(1.0 / 3.0, 2.0 / 3.0, 2, 1.0 / 3.0, 0.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0);
+      break;
+    case GRRMHD_IMEX3: {            // eq. IMEX3 with the printed alpha, beta, eta
+      const double al = 0.24169426078821, be = 0.06042356519705, et = 0.12915286960590;
+      st(1.0, 0.0, -1, 0.0, al);
+      st(2.0, -1.0, 0, 0.0, al);
+      st(1.0, 0.0, -1, 1.0, al, 0.0, 1.0 - al);
+      st(0.75, 0.25, 2, 0.25, al, be, (-1.0 + al + 4.0 * et) / 4.0,
+         (2.0 - 5.0 * al - 4.0 * (be + et)) / 4.0);
+      st(1.0 / 3.0, 2.0 / 3.0, 3, 2.0 / 3.0, 0.0, -2.0 * be / 3.0, (1.0 - 4.0 * et) / 6.0,
+         (-1.0 + 4.0 * al + 4.0 * (be + et)) / 6.0, 4.0 * (1.0 - al) / 6.0);
+      break;
+    }
+    default:                        // RK3, implicit part with the same coefficients
+      st(1.0, 0.0, -1, 1.0, 1.0);
+      st(0.75, 0.25, 0, 0.25, 0.25);
+      st(1.0 / 3.0, 2.0 / 3.0, 1, 2.0 / 3.0, 2.0 / 3.0);
+      break;
+  }
+  for (int i = 0; i < S.ns; i++)
+    for (int k = 0; k < 4; k++)
+      if (S.s[i].m[k] != 0.0) S.keep_m[k] = true;
+  return S;
+}
+
+struct WsLayout {
+  size_t F, emf, vch, Uexp, Pa, Ua, err, st, it, Us, M, total;
+};
+
+// IMEX schemes add the stage U's (all but the last) and the kept M^k
+static WsLayout ws_layout(const Ctx& C, int scheme = GRRMHD_RK3) {
   WsLayout w;
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -288,12 +359,18 @@ static WsLayout ws_layout(const Ctx& C) {
   w.err = take(sizeof(double) * N);
   w.st = take(sizeof(int) * N);
   w.it = take(sizeof(int) * N);
+  w.Us = w.M = off;
+  if (scheme != GRRMHD_RK3) {
+    const Scheme S = make_scheme(scheme);
+    w.Us = take(round256(sizeof(double) * 12 * N) * (S.ns - 1));
+    w.M = take(round256(sizeof(double) * 8 * N) * 4);
+  }
   w.total = off;
   return w;
 }
 
 extern "C" size_t grrmhd_workspace_bytes(const grrmhd_grid* g) {
-  return g ? ws_layout(g->C).total : 0;
+  return g ? ws_layout(g->C, g->p.scheme).total : 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -414,10 +491,13 @@ static int launch_timestep(grrmhd_grid* g, const double* vch, double* dt_dev) {
 static int launch_update(grrmhd_grid* g, double a, double b, double c, const double* dt_dev,
                          const double* P, const double* Un, const double* Up, const double* F,
                          const double* emf, double* Ue, const unsigned long long* dtmin = nullptr,
-                         unsigned long long* dtnext = nullptr) {
+                         unsigned long long* dtnext = nullptr, const MTerms* mt = nullptr) {
+  MTerms MT;
+  memset(&MT, 0, sizeof(MT));
+  if (mt) MT = *mt;
   hipLaunchKernelGGL(k_update, dim3(nblocks(n_interior(g->C), 256)), dim3(256), 0, g->stream,
                      g->C, a, b, c, const_cast<double*>(dt_dev), dtmin, dtnext, P, Un, Up, F, emf,
-                     Ue);
+                     MT, Ue);
   LAUNCHCHK();
   return 0;
 }
@@ -520,7 +600,7 @@ extern "C" int grrmhd_con2prim(grrmhd_grid* g, const double* U, const double* Pg
   NEEDG();
   if (!U || !Pguess || !P) return fail(GRRMHD_EINVAL, "NULL array");
   hipLaunchKernelGGL(k_con2prim, dim3(nblocks(n_interior(g->C), 128)), dim3(128), 0, g->stream,
-                     g->C, U, Pguess, P, status);
+                     g->C, U, Pguess, P, status, 0);
   LAUNCHCHK();
   return 0;
 }
@@ -542,6 +622,83 @@ extern "C" int grrmhd_fixup(grrmhd_grid* g, double* P, double* U, int* status, d
   return launch_fixup(g, P, U, status, scratch, nullptr, nullptr, nullptr, 0);
 }
 
+// One step of an IMEX scheme (stage table above).  The latest primitives
+// live in P (stage input of stage 0) or Pa; stage U's in the workspace; the
+// last stage writes P and U.
+static int imex_step(grrmhd_grid* g, double* P, double* U, const double* chi_abs,
+                     const double* chi_es, double* dt_dev, int dt_fixed, int* status, int* iters,
+                     char* base, const WsLayout& w) {
+  const Ctx& C = g->C;
+  const Scheme S = make_scheme(g->p.scheme);
+  const size_t N = (size_t)C.Ntot;
+  double* F = (double*)(base + w.F);
+  double* emf = (double*)(base + w.emf);
+  double* vch = (double*)(base + w.vch);
+  double* Ue = (double*)(base + w.Uexp);
+  double* Pa = (double*)(base + w.Pa);
+  double* err = (double*)(base + w.err);
+  int* st = (int*)(base + w.st);
+  int* it = (int*)(base + w.it);
+  double* Us[4];
+  double* Mk[4];
+  for (int k = 0; k < 4; k++) {
+    Us[k] = (double*)(base + w.Us + k * round256(sizeof(double) * 12 * N));
+    Mk[k] = (double*)(base + w.M + k * round256(sizeof(double) * 8 * N));
+  }
+  const long nint = n_interior(C);
+  double* Pcur = P;
+  int rc;
+  for (int i = 0; i < S.ns; i++) {
+    const Stage& x = S.s[i];
+    const bool last = (i == S.ns - 1);
+    // dt from the wave speeds of P^n: the Courant reduction rides on the
+    // first flux launch (made for it even when stage 0 has no explicit flux)
+    const bool red = (i == 0 && !dt_fixed);
+    unsigned long long* dmin = red ? g->dtstep[g->dtp] : nullptr;
+    unsigned long long* dnext = red ? g->dtstep[g->dtp ^ 1] : nullptr;
+    if (x.c != 0.0 || red) {
+      if ((rc = launch_bc(g, Pcur))) return rc;
+      if ((rc = launch_fluxes(g, Pcur, chi_abs, chi_es, F, emf, vch, dmin))) return rc;
+    }
+    MTerms MT;
+    memset(&MT, 0, sizeof(MT));
+    for (int k = 0; k < i && k < 4; k++) {
+      if (x.m[k] == 0.0) continue;
+      MT.M[MT.n] = Mk[k];
+      MT.m[MT.n] = x.m[k];
+      MT.n++;
+    }
+    const double* Uj = (x.j >= 0) ? Us[x.j] : U;
+    if ((rc = launch_update(g, x.a, x.b, x.c, dt_dev, Pcur, U, Uj, F, emf, Ue, dmin, dnext, &MT)))
+      return rc;
+    if (red) g->dtp ^= 1;
+    double* Pout = last ? P : Pa;
+    double* Uout = last ? U : Us[i];
+    if (x.g > 0.0) {
+      if ((rc = launch_implicit(g, Ue, Pcur, x.g, dt_dev, chi_abs, chi_es, Pout, Uout, it, st, err)))
+        return rc;
+      if (i < 4 && S.keep_m[i]) {   // the stage's source, before the fix-ups
+        hipLaunchKernelGGL(k_stage_m, dim3(nblocks(nint, 256)), dim3(256), 0, g->stream, C, Ue,
+                           Uout, st, x.g, dt_dev, Mk[i]);
+        LAUNCHCHK();
+      }
+      if ((rc = launch_fixup(g, Pout, Uout, st, Ue, status, it, iters, i > 0))) return rc;
+    } else {
+      // final explicit combination: MHD and radiation inversions; a failed
+      // MHD inversion makes a failed cell (neighbour average in the fix-up)
+      hipLaunchKernelGGL(k_con2prim, dim3(nblocks(nint, 128)), dim3(128), 0, g->stream, C, Ue,
+                         Pcur, Pout, st, (int)GRRMHD_ST_FAIL);
+      LAUNCHCHK();
+      hipLaunchKernelGGL(k_copy_interior12, dim3(nblocks(nint, 256)), dim3(256), 0, g->stream, C,
+                         Ue, Uout);
+      LAUNCHCHK();
+      if ((rc = launch_fixup(g, Pout, Uout, st, Ue, status, nullptr, iters, i > 0))) return rc;
+    }
+    Pcur = Pout;
+  }
+  return 0;
+}
+
 extern "C" int grrmhd_step(grrmhd_grid* g, double* P, double* U, const double* chi_abs,
                            const double* chi_es, double* dt_dev, int dt_fixed, int* status,
                            int* iters, void* workspace, size_t ws_bytes) {
@@ -549,10 +706,12 @@ extern "C" int grrmhd_step(grrmhd_grid* g, double* P, double* U, const double* c
   if (!P || !U || !chi_abs || !chi_es || !dt_dev || !workspace)
     return fail(GRRMHD_EINVAL, "NULL array");
   const Ctx& C = g->C;
-  const WsLayout w = ws_layout(C);
+  const WsLayout w = ws_layout(C, g->p.scheme);
   if (ws_bytes < w.total) return fail(GRRMHD_EINVAL, "workspace too small");
   if (((uintptr_t)workspace) & 255) return fail(GRRMHD_EINVAL, "workspace must be 256-byte aligned");
   char* base = (char*)workspace;
+  if (g->p.scheme != GRRMHD_RK3)
+    return imex_step(g, P, U, chi_abs, chi_es, dt_dev, dt_fixed, status, iters, base, w);
   double* F = (double*)(base + w.F);
   double* emf = (double*)(base + w.emf);
   double* vch = (double*)(base + w.vch);
@@ -757,6 +916,7 @@ extern "C" int grrmhd_step_adjoint(grrmhd_grid* g, const double* P_n, const doub
   NEEDG();
   if (!P_n || !chi_abs || !chi_es || !dt_dev || !gU_next || !gP_n || !workspace)
     return fail(GRRMHD_EINVAL, "NULL array");
+  if (g->p.scheme != GRRMHD_RK3) return fail(GRRMHD_EINVAL, "the adjoint covers the RK3 scheme");
   const Ctx& C = g->C;
   const AdjLayout w = adj_layout(C);
   if (ws_bytes < w.total) return fail(GRRMHD_EINVAL, "workspace too small");

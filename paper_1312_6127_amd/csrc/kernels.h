@@ -453,14 +453,24 @@ DEV double dt_slots_min(const unsigned long long* s) {
   return __longlong_as_double((long long)b);
 }
 
+// Stored 4-force sources of earlier stages added to an explicit bracket:
+// dt sum_k m[k] M_k, each M_k an [8][Ntot] array (slots 1-4 and 8-11 of U).
+struct MTerms {
+  const double* M[4];
+  double m[4];
+  int n;
+};
+
 // dt: *dt_dev, or, when dtmin is set, courant x the minimum over the Courant
 // reduction's slots, which thread 0 also stores in *dt_dev while it resets
 // dtnext (the slots of the following step's reduction) to +inf.
+// cc = 0: no flux or geometric term (F, emf and P are not read).
 DEV void update_at(Ctx C, double ca, double cb, double cc, double* dt_dev,
                    const unsigned long long* dtmin, unsigned long long* dtnext,
                    const double* __restrict__ P, const double* __restrict__ Un,
                    const double* __restrict__ Uprev, const double* __restrict__ F,
-                   const double* __restrict__ emf, double* __restrict__ Uexp, long t) {
+                   const double* __restrict__ emf, const MTerms& MT, double* __restrict__ Uexp,
+                   long t) {
   const long nint = (long)C.n[0] * C.n[1] * C.n[2];
   if (t >= nint) return;
   const int i = C.ng[0] + t % C.n[0];
@@ -482,7 +492,10 @@ DEV void update_at(Ctx C, double ca, double cb, double cc, double* dt_dev,
   double S[12];
 #pragma unroll
   for (int q = 0; q < 12; q++) S[q] = 0.0;
-  if (C.metric != GRRMHD_MINKOWSKI) {
+  double div[12];
+#pragma unroll
+  for (int q = 0; q < 12; q++) div[q] = 0.0;
+  if (cc != 0.0 && C.metric != GRRMHD_MINKOWSKI) {
     const int pos = i + C.N[0] * j;
     Metric m;
     load_metric(C.geo_c, C.npos, pos, m);
@@ -492,10 +505,7 @@ DEV void update_at(Ctx C, double ca, double cb, double cc, double* dt_dev,
     load_dg(C, pos, dg);
     geom_source(m, dg, C.gam, p, S);
   }
-  double div[12];
-#pragma unroll
-  for (int q = 0; q < 12; q++) div[q] = 0.0;
-  for (int d = 0; d < 3; d++) {
+  for (int d = 0; d < 3 && cc != 0.0; d++) {
     if (C.n[d] == 1) continue;
     const double idx = 1.0 / C.dx[d];
     const double* Fd = F + (long)d * 12 * C.Ntot;
@@ -527,7 +537,14 @@ DEV void update_at(Ctx C, double ca, double cb, double cc, double* dt_dev,
   for (int q = 0; q < 12; q++) {
     double u = ca * Un[q * C.Ntot + c];
     if (cb != 0.0) u += cb * Uprev[q * C.Ntot + c];
-    Uexp[q * C.Ntot + c] = u + cc * dt * (S[q] - div[q]);
+    if (cc != 0.0) u += cc * dt * (S[q] - div[q]);
+    if (MT.n > 0 && ((q >= 1 && q <= 4) || q >= 8)) {
+      const int r = (q <= 4) ? q - 1 : q - 4;
+      double sm = 0.0;
+      for (int k = 0; k < MT.n; k++) sm += MT.m[k] * MT.M[k][r * C.Ntot + c];
+      u += dt * sm;
+    }
+    Uexp[q * C.Ntot + c] = u;
   }
 }
 
@@ -535,8 +552,9 @@ __global__ void LB(256) k_update(Ctx C, double ca, double cb, double cc, double*
                                  const unsigned long long* dtmin, unsigned long long* dtnext,
                                  const double* __restrict__ P, const double* __restrict__ Un,
                                  const double* __restrict__ Uprev, const double* __restrict__ F,
-                                 const double* __restrict__ emf, double* __restrict__ Uexp) {
-  update_at(C, ca, cb, cc, dt_dev, dtmin, dtnext, P, Un, Uprev, F, emf, Uexp,
+                                 const double* __restrict__ emf, MTerms MT,
+                                 double* __restrict__ Uexp) {
+  update_at(C, ca, cb, cc, dt_dev, dtmin, dtnext, P, Un, Uprev, F, emf, MT, Uexp,
             (long)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
@@ -959,8 +977,9 @@ __global__ void LB(64) k_cascade_urad(Ctx C, long n, const double* __restrict__ 
   }
 }
 
+// fail_bits: extra status bits of a cell whose MHD inversion fails
 __global__ void LB(128) k_con2prim(Ctx C, const double* __restrict__ U, const double* Pguess,
-                                   double* P, int* __restrict__ status) {
+                                   double* P, int* __restrict__ status, int fail_bits) {
   const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
   const long nint = (long)C.n[0] * C.n[1] * C.n[2];
   if (t >= nint) return;
@@ -983,7 +1002,7 @@ __global__ void LB(128) k_con2prim(Ctx C, const double* __restrict__ U, const do
   if (mhd_invert(m, C.gam, u[0], u[1], u + 2, u + 5, rho, ug, ut) == 0) {
     p[0] = rho; p[1] = ug; p[2] = ut[0]; p[3] = ut[1]; p[4] = ut[2];
   } else {
-    st |= GRRMHD_ST_C2P_FAIL;
+    st |= GRRMHD_ST_C2P_FAIL | fail_bits;
   }
 #pragma unroll
   for (int q = 0; q < 3; q++) p[5 + q] = u[5 + q];
@@ -993,6 +1012,46 @@ __global__ void LB(128) k_con2prim(Ctx C, const double* __restrict__ U, const do
 #pragma unroll
   for (int q = 0; q < 12; q++) P[q * C.Ntot + c] = p[q];
   if (status) status[c] = st;
+}
+
+// the 12 fields of src at interior cells into dst (ghost cells untouched)
+__global__ void LB(256) k_copy_interior12(Ctx C, const double* __restrict__ src,
+                                          double* __restrict__ dst) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long nint = (long)C.n[0] * C.n[1] * C.n[2];
+  if (t >= nint) return;
+  const int i = C.ng[0] + t % C.n[0];
+  const long t2 = t / C.n[0];
+  const int j = C.ng[1] + t2 % C.n[1];
+  const int k = C.ng[2] + t2 / C.n[1];
+  const long c = cell_index(C, i, j, k);
+#pragma unroll
+  for (int q = 0; q < 12; q++) dst[q * C.Ntot + c] = src[q * C.Ntot + c];
+}
+
+// The 4-force source of an implicit stage as its solve found it:
+// M = (U_out - U_expl) / (g dt) in the gas and radiation energy-momentum
+// slots (rows 0-3: U slots 1-4, rows 4-7: slots 8-11; [8][Ntot]), zero where
+// the solve failed.
+__global__ void LB(256) k_stage_m(Ctx C, const double* __restrict__ Ue,
+                                  const double* __restrict__ Uo, const int* __restrict__ status,
+                                  double g, const double* __restrict__ dt_dev,
+                                  double* __restrict__ M) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long nint = (long)C.n[0] * C.n[1] * C.n[2];
+  if (t >= nint) return;
+  const int i = C.ng[0] + t % C.n[0];
+  const long t2 = t / C.n[0];
+  const int j = C.ng[1] + t2 % C.n[1];
+  const int k = C.ng[2] + t2 / C.n[1];
+  const long c = cell_index(C, i, j, k);
+  const double gdt = g * (*dt_dev);
+  const bool bad = (status[c] & GRRMHD_ST_FAIL) != 0;
+#pragma unroll
+  for (int r = 0; r < 8; r++) {
+    const int q = (r < 4) ? 1 + r : 4 + r;
+    M[r * C.Ntot + c] = bad ? 0.0 : (Uo[q * C.Ntot + c] - Ue[q * C.Ntot + c]) / gdt;
+  }
 }
 
 // ---------------------------------------------------------------------------

@@ -33,6 +33,7 @@ class Params(C.Structure):
         ("max_iter", C.c_int), ("roundoff", C.c_int),
         ("rho_floor", C.c_double), ("u_floor", C.c_double), ("bsq_rho_max", C.c_double),
         ("bsq_u_max", C.c_double), ("u_rho_max", C.c_double), ("erad_floor", C.c_double),
+        ("scheme", C.c_int),
     ]
 
 
@@ -40,6 +41,7 @@ class Tuning(C.Structure):
     _fields_ = [("mode", C.c_int), ("block", C.c_int), ("waves_per_cu", C.c_int), ("ms", C.c_float)]
 
 
+SCHEMES = {"rk3": 0, "imex2": 1, "imex2b": 2, "imex3": 3}
 PER_CELL, PER_ITERATION, PERSISTENT = 0, 1, 2
 TUNE_CANDIDATES = 9
 FORM_NAMES = {PER_CELL: "per_cell", PER_ITERATION: "per_iteration", PERSISTENT: "persistent"}
@@ -64,6 +66,7 @@ def params(d: dict) -> Params:
     p.r_fp64 = float(d.get("r_fp64", 2.0))
     p.max_iter = int(d["max_iter"])
     p.roundoff = int(d["roundoff"])
+    p.scheme = SCHEMES[d.get("scheme", "rk3")]
     return p
 
 
@@ -296,7 +299,8 @@ class Grid:
         return P, U, status
 
     def step(self, P, U, chi_abs, chi_es, dt, dt_fixed=False, status=None, iters=None):
-        """One RK3-IMEX step in place on P, U; dt is a 1-element device tensor."""
+        """One step of the grid's scheme in place on P, U; dt is a 1-element device
+        tensor."""
         self._sync_stream()
         ws = self.workspace()
         _check(lib().grrmhd_step(self.h, _ptr(P), _ptr(U), _ptr(chi_abs), _ptr(chi_es), _ptr(dt),
