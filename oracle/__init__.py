@@ -47,7 +47,7 @@ class Params(C.Structure):
         ("max_iter", C.c_int), ("roundoff", C.c_int),
         ("rho_floor", C.c_double), ("u_floor", C.c_double), ("bsq_rho_max", C.c_double),
         ("bsq_u_max", C.c_double), ("u_rho_max", C.c_double), ("erad_floor", C.c_double),
-        ("scheme", C.c_int),
+        ("scheme", C.c_int), ("recon", C.c_int),
     ]
 
 
@@ -79,6 +79,7 @@ def params(d: dict) -> Params:
     p.max_iter = int(d["max_iter"])
     p.roundoff = int(d["roundoff"])
     p.scheme = _SCHEME[d.get("scheme", "rk3")]
+    p.recon = 1 if d.get("recon", "mc") == "ppm" else 0
     return p
 
 
@@ -112,6 +113,8 @@ def lib():
             "orc_bc": (None, [PP, _D]),
             "orc_prim_to_cons": (None, [PP, _D, _D]),
             "orc_fluxes": (None, [PP, _D, _D, _D, _D, _D, _D]),
+            "orc_flattener": (None, [PP, _D, _D, _D, _D, C.c_int]),
+            "orc_ppm_cell": (None, [_D, C.c_double, _D, _D]),
             "orc_timestep": (C.c_double, [PP, _D]),
             "orc_explicit_update": (None, [PP, C.c_double, C.c_double, C.c_double, C.c_double,
                                            _D, _D, _D, _D, _D, _D]),
@@ -276,6 +279,24 @@ def fluxes(pd, P, chi_abs, chi_es):
     vch = np.zeros((3, N))
     lib().orc_fluxes(C.byref(params(pd)), _dp(P), _dp(ca), _dp(ce), _dp(F), _dp(emf), _dp(vch))
     return F, emf, vch
+
+
+def flattener(pd, P, chi_abs, chi_es, prev=None):
+    """PPM flattener [3 directions][gas, radiation][N]; with prev, the larger
+    of the new value and prev (earlier sub-steps of the same step)."""
+    P, ca, ce = _f64(P), _f64(chi_abs), _f64(chi_es)
+    fl = np.zeros((3, 2, P.shape[1])) if prev is None else _f64(prev).copy()
+    lib().orc_flattener(C.byref(params(pd)), _dp(P), _dp(ca), _dp(ce), _dp(fl),
+                        0 if prev is None else 1)
+    return fl
+
+
+def ppm_cell(a5, f):
+    """PPM left and right values of the middle of five cell values."""
+    a = _f64(a5)
+    l, r = np.zeros(1), np.zeros(1)
+    lib().orc_ppm_cell(_dp(a), float(f), _dp(l), _dp(r))
+    return float(l[0]), float(r[0])
 
 
 def timestep(pd, vch):

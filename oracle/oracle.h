@@ -29,6 +29,9 @@ enum { ORC_FLUX_LLF = 0, ORC_FLUX_HLL = 1 };
 /* time integrators (Sec. 4.1): RK3 with equal explicit and implicit
  * coefficients, and the IMEX2, IMEX2B and IMEX3 schemes */
 enum { ORC_RK3 = 0, ORC_IMEX2 = 1, ORC_IMEX2B = 2, ORC_IMEX3 = 3 };
+/* reconstruction (Sec. 4.3): MC-limited linear (ghost width 2) or PPM with
+ * MC slopes and the gas/radiation shock flattener (ghost width 4) */
+enum { ORC_RECON_MC = 0, ORC_RECON_PPM = 1 };
 
 /* per-cell status bits of the implicit solve and fix-ups */
 enum {
@@ -62,6 +65,7 @@ typedef struct {
   int roundoff;           /* keep iterating past tolerance to round-off       */
   double rho_floor, u_floor, bsq_rho_max, bsq_u_max, u_rho_max, erad_floor;
   int scheme;             /* ORC_RK3, ORC_IMEX2, ORC_IMEX2B, ORC_IMEX3         */
+  int recon;              /* ORC_RECON_MC or ORC_RECON_PPM                    */
 } orc_params;
 
 /* ---- geometry (Sec. 2; metric of the Kerr-Schild form) ---- */
@@ -115,6 +119,16 @@ void orc_prim_to_cons(const orc_params *p, const double *P, double *U);
 void orc_fluxes(const orc_params *p, const double *P, const double *chi_abs, const double *chi_es,
                 double *F /* [3][12][N] */, double *emf /* [3][N] */, double *vchar /* [3][N] */);
 double orc_timestep(const orc_params *p, const double *vchar);
+/* PPM flattener of every cell within one cell of the interior, per active
+ * direction d, gas and radiation: fl[(2 d + kind) N + c]; with keep != 0 the
+ * larger of the new value and the one in fl (earlier sub-steps of the step) */
+void orc_flattener(const orc_params *p, const double *P, const double *chi_abs,
+                   const double *chi_es, double *fl, int keep);
+/* orc_fluxes with the flattener state fl of the step (PPM; unused for MC) */
+void orc_fluxes_fl(const orc_params *p, const double *P, const double *chi_abs,
+                   const double *chi_es, const double *fl, double *F, double *emf, double *vchar);
+/* PPM left and right values of the middle cell of a5[5] with flattener f */
+void orc_ppm_cell(const double a5[5], double f, double *aL, double *aR);
 void orc_explicit_update(const orc_params *p, double a, double b, double c, double dt,
                          const double *P, const double *Un, const double *Uprev, const double *F,
                          const double *emf, double *Uexp);

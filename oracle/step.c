@@ -112,9 +112,124 @@ static double mc_slope(double l, double c, double r) {
   return dc > 0.0 ? s : -s;
 }
 
+/* ---- PPM (Colella & Woodward 1984 without contact steepening) ----
+ * interface value between the 2nd and 3rd of four cells: the average minus
+ * the difference of the two cells' MC slopes over 6 (their eq. 1.6 with
+ * monotonised slopes) */
+static double ppm_iface(double am, double a0, double a1, double a2) {
+  return 0.5 * (a0 + a1) - (mc_slope(a0, a1, a2) - mc_slope(am, a0, a1)) / 6.0;
+}
+
+/* left and right values of the middle cell: interface values, flattened
+ * towards the cell value by f, then the monotonicity constraints (their
+ * eq. 1.10) */
+void orc_ppm_cell(const double a5[5], double f, double *aL, double *aR) {
+  const double a0 = a5[2];
+  double l = ppm_iface(a5[0], a5[1], a5[2], a5[3]);
+  double r = ppm_iface(a5[1], a5[2], a5[3], a5[4]);
+  l = f * a0 + (1.0 - f) * l;
+  r = f * a0 + (1.0 - f) * r;
+  if ((r - a0) * (a0 - l) <= 0.0) {
+    l = a0;
+    r = a0;
+  } else {
+    const double d = r - l, m6 = 6.0 * (a0 - 0.5 * (l + r));
+    if (d * m6 > d * d) l = 3.0 * a0 - 2.0 * r;
+    else if (-d * d > d * m6) r = 3.0 * a0 - 2.0 * l;
+  }
+  *aL = l;
+  *aR = r;
+}
+
+/* shock flattener (Sec. 4.3 with the FLASH form): for pressure pp and
+ * velocity v along d, f = clamp(w2 (|dp1|/|dp2| - w1), 0, 1) where the
+ * pressure jump |dp1| = |p(+1) - p(-1)| exceeds eps min(p(+1), p(-1)) and the
+ * flow converges (v(-1) > v(+1)), else 0; w1 = 0.75 (SP0), w2 = 10, eps = 0.33 */
+#define PPM_W1 0.75
+#define PPM_W2 10.0
+#define PPM_EPS 0.33
+static double flat_raw(const double *pp, const double *v, long c, long st) {
+  const double d1 = pp[c + st] - pp[c - st], d2 = pp[c + 2 * st] - pp[c - 2 * st];
+  if (!(fabs(d1) > PPM_EPS * fmin(pp[c + st], pp[c - st])) || !(v[c - st] - v[c + st] > 0.0))
+    return 0.0;
+  return fmax(0.0, fmin(1.0, PPM_W2 * (fabs(d1) / fmax(fabs(d2), 1e-300) - PPM_W1)));
+}
+
+/* the upstream maximum: f of the cell and of its neighbour on the high-
+ * pressure side */
+static double flat_tilde(const double *pp, const double *v, long c, long st) {
+  const double f0 = flat_raw(pp, v, c, st);
+  const long up = (pp[c + st] - pp[c - st] < 0.0) ? c + st : c - st;
+  return fmax(f0, flat_raw(pp, v, up, st));
+}
+
+void orc_flattener(const orc_params *p, const double *P, const double *chi_abs,
+                   const double *chi_es, double *fl, int keep) {
+  const long N = orc_ncell_alloc(p);
+  const int NA[3] = {orc_nalloc(p, 0), orc_nalloc(p, 1), orc_nalloc(p, 2)};
+  double *pg = malloc(sizeof(double) * N), *pr = malloc(sizeof(double) * N);
+  double *wt = malloc(sizeof(double) * N), *vg = malloc(sizeof(double) * N);
+  double *vr = malloc(sizeof(double) * N);
+  for (int d = 0; d < 3; d++) {
+    if (p->n[d] == 1) continue;
+    long st = 1;
+    for (int e = 0; e < d; e++) st *= NA[e];
+    const double dxd = orc_dx(p, d);
+    /* per cell: tau-blended pressures (each kind gains w times the other,
+     * w = min(1, 2 tau), tau = kappa_tot sqrt(g_dd) dx^d) and velocities */
+    for (int k = 0; k < NA[2]; k++)
+      for (int j = 0; j < NA[1]; j++)
+        for (int i = 0; i < NA[0]; i++) {
+          const long c = IDX(p, i, j, k);
+          double x1, x2;
+          orc_cell_x(p, i, j, &x1, &x2);
+          orc_geom g;
+          orc_geom_point(p, x1, x2, &g);
+          const double rho = P[0 * N + c];
+          const double tau = (chi_abs[c] + chi_es[c]) * rho * sqrt(g.gcov[d + 1][d + 1]) * dxd;
+          const double w = fmin(1.0, 2.0 * tau);
+          const double p_g = (p->gam - 1.0) * P[1 * N + c], p_r = P[8 * N + c] / 3.0;
+          pg[c] = p_g + w * p_r;
+          pr[c] = p_r + w * p_g;
+          wt[c] = w;
+          vg[c] = P[(2 + d) * N + c];
+          vr[c] = P[(9 + d) * N + c];
+        }
+    int lo[3], hi[3];
+    for (int e = 0; e < 3; e++) {
+      lo[e] = (p->n[e] > 1) ? orc_ng(p, e) - 1 : 0;
+      hi[e] = (p->n[e] > 1) ? orc_ng(p, e) + p->n[e] : 0;
+    }
+    for (int k = lo[2]; k <= hi[2]; k++)
+      for (int j = lo[1]; j <= hi[1]; j++)
+        for (int i = lo[0]; i <= hi[0]; i++) {
+          const long c = IDX(p, i, j, k);
+          const double fg = flat_tilde(pg, vg, c, st), fr = flat_tilde(pr, vr, c, st);
+          const double fm = fmax(fg, fr), w = wt[c];
+          double f2[2] = {(1.0 - w) * fg + w * fm, (1.0 - w) * fr + w * fm};
+          for (int kind = 0; kind < 2; kind++) {
+            double *dst = fl + (long)(2 * d + kind) * N + c;
+            *dst = keep ? fmax(*dst, f2[kind]) : f2[kind];
+          }
+        }
+  }
+  free(pg); free(pr); free(wt); free(vg); free(vr);
+}
+
 /* ---- steps 4-9: reconstruction, face fluxes, wave speeds, Riemann, CT ---- */
 void orc_fluxes(const orc_params *p, const double *P, const double *chi_abs, const double *chi_es,
                 double *F, double *emf, double *vchar) {
+  double *fl = NULL;
+  if (p->recon == ORC_RECON_PPM) {
+    fl = calloc(6 * orc_ncell_alloc(p), sizeof(double));
+    orc_flattener(p, P, chi_abs, chi_es, fl, 0);
+  }
+  orc_fluxes_fl(p, P, chi_abs, chi_es, fl, F, emf, vchar);
+  free(fl);
+}
+
+void orc_fluxes_fl(const orc_params *p, const double *P, const double *chi_abs,
+                   const double *chi_es, const double *fl, double *F, double *emf, double *vchar) {
   const long N = orc_ncell_alloc(p);
   memset(F, 0, sizeof(double) * 3 * 12 * N);
   memset(emf, 0, sizeof(double) * 3 * N);
@@ -140,10 +255,24 @@ void orc_fluxes(const orc_params *p, const double *P, const double *chi_abs, con
           const long c = IDX(p, i, j, k);
           const long m2 = c - 2 * st, m1 = c - st, p1 = c + st;
           double PL[12], PR[12];
-          for (int q = 0; q < 12; q++) {
-            const double a = P[q * N + m2], b = P[q * N + m1], cc = P[q * N + c], e = P[q * N + p1];
-            PL[q] = b + 0.5 * mc_slope(a, b, cc);
-            PR[q] = cc - 0.5 * mc_slope(b, cc, e);
+          if (p->recon == ORC_RECON_PPM) {
+            /* left state: right value of cell c - st; right state: left value of c */
+            for (int q = 0; q < 12; q++) {
+              const int kind = q < 8 ? 0 : 1;
+              double a5[5], l, r;
+              for (int m = 0; m < 5; m++) a5[m] = P[q * N + c + (m - 3) * st];
+              orc_ppm_cell(a5, fl[(long)(2 * d + kind) * N + m1], &l, &PL[q]);
+              for (int m = 0; m < 5; m++) a5[m] = P[q * N + c + (m - 2) * st];
+              orc_ppm_cell(a5, fl[(long)(2 * d + kind) * N + c], &PR[q], &r);
+              (void)l;
+              (void)r;
+            }
+          } else {
+            for (int q = 0; q < 12; q++) {
+              const double a = P[q * N + m2], b = P[q * N + m1], cc = P[q * N + c], e = P[q * N + p1];
+              PL[q] = b + 0.5 * mc_slope(a, b, cc);
+              PR[q] = cc - 0.5 * mc_slope(b, cc, e);
+            }
           }
           double x1, x2;
           orc_face_x(p, d + 1, i, j, &x1, &x2);
@@ -516,10 +645,19 @@ int orc_step(const orc_params *p, double *P, double *U, const double *chi_abs, c
   int nbad = 0;
   if (iters) memset(iters, 0, sizeof(int) * N);
   int fresh = 0;   /* F holds the fluxes of Pk */
+  /* PPM flattener of the step: the largest over its sub-steps so far */
+  double *fl = (p->recon == ORC_RECON_PPM) ? calloc(6 * N, sizeof(double)) : NULL;
+  int nflux = 0;
+#define STEP_FLUXES()                                              \
+  do {                                                             \
+    if (fl) orc_flattener(p, Pk, chi_abs, chi_es, fl, nflux > 0);  \
+    orc_fluxes_fl(p, Pk, chi_abs, chi_es, fl, F, emf, vch);        \
+    nflux++;                                                       \
+  } while (0)
   if (!dt_fixed) {
     /* Courant dt from the wave speeds of P^n (Sec. 4.4) */
     orc_bc(p, Pk);
-    orc_fluxes(p, Pk, chi_abs, chi_es, F, emf, vch);
+    STEP_FLUXES();
     *dt = orc_timestep(p, vch);
     fresh = 1;
   }
@@ -529,7 +667,7 @@ int orc_step(const orc_params *p, double *P, double *U, const double *chi_abs, c
     if (s->c != 0.0) {
       if (!fresh) {
         orc_bc(p, Pk);
-        orc_fluxes(p, Pk, chi_abs, chi_es, F, emf, vch);
+        STEP_FLUXES();
       }
       orc_explicit_update(p, s->a, s->b, s->c, *dt, Pk, Un, Uj, F, emf, Uexp);
     } else {
@@ -582,5 +720,7 @@ int orc_step(const orc_params *p, double *P, double *U, const double *chi_abs, c
   }
   free(F); free(emf); free(vch); free(Uexp); free(Un); free(Pk); free(st); free(stacc);
   free(it);
+  free(fl);
+#undef STEP_FLUXES
   return nbad;
 }

@@ -1,0 +1,137 @@
+"""Pins of the oracle's PPM reconstruction and shock flattener (Sec. 4.3:
+PPM with MC-limited slopes, no contact steepener, the shock flattener with
+SP0 = 0.75 applied to gas and radiation separately).
+
+- Interface values are exact for cell averages of a cubic where the MC
+  slopes are not limited (the 4th-order interpolation of Colella-Woodward).
+- After the monotonicity constraints each cell's parabola has no extremum
+  inside the cell (or is flat), for random data.
+- A full flattener (f = 1) gives the cell value on both sides; f = 0 in a
+  smooth flow, f = 1 at a strong compressive pressure jump, 0 where the
+  same jump expands.
+- A PPM step conserves mass, energy and momentum on a periodic box.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1312_6127_amd import inputs as I
+
+from test_oracle_pins import _periodic_box
+
+
+def test_interfaces_exact_for_cubic_averages(orc):
+    # q(x) = 1 + 0.3 x + 0.05 x^2 + 0.01 x^3 on cells of width h around x_i
+    def avg(x, h):
+        Q = lambda y: y + 0.15 * y ** 2 + 0.05 / 3 * y ** 3 + 0.0025 * y ** 4
+        return (Q(x + h / 2) - Q(x - h / 2)) / h
+
+    q = lambda y: 1 + 0.3 * y + 0.05 * y ** 2 + 0.01 * y ** 3
+    h = 0.1
+    for x0 in (-0.7, 0.0, 0.45):
+        a5 = np.array([avg(x0 + m * h, h) for m in range(-2, 3)])
+        l, r = orc.ppm_cell(a5, 0.0)
+        assert abs(l - q(x0 - h / 2)) < 1e-14 and abs(r - q(x0 + h / 2)) < 1e-14, (l, r)
+
+
+def test_constrained_parabola_has_no_interior_extremum(orc):
+    rng = np.random.default_rng(3)
+    for _ in range(2000):
+        a5 = rng.standard_normal(5) * rng.choice([1e-3, 1.0, 1e3])
+        l, r = orc.ppm_cell(a5, 0.0)
+        a0 = a5[2]
+        if l == a0 and r == a0:
+            continue
+        assert (a0 - l) * (r - a0) > 0
+        # |6 (a0 - mean)| <= |aR - aL|: at equality the extremum sits on the
+        # cell edge (aL = 3 a0 - 2 aR); rounding is relative to the values
+        assert abs(6 * (a0 - 0.5 * (l + r))) <= abs(r - l) + 1e-12 * np.abs(a5[1:4]).max()
+        # no value outside the range of the cell and its two neighbours
+        lo, hi = min(a5[1:4]), max(a5[1:4])
+        assert lo - 1e-12 * abs(hi) <= min(l, r) and max(l, r) <= hi + 1e-12 * abs(hi)
+
+
+def test_full_flattening_gives_cell_values(orc):
+    rng = np.random.default_rng(4)
+    for _ in range(100):
+        a5 = rng.standard_normal(5)
+        assert orc.ppm_cell(a5, 1.0) == (a5[2], a5[2])
+
+
+def _tube_state(pd, x, p, v):
+    N = I.ncell(pd)
+    P = np.zeros((12, N))
+    P[0] = 1.0
+    P[1] = p / (pd["gam"] - 1.0)
+    P[2] = v
+    P[8] = 1e-8
+    return P
+
+
+def test_flattener_marks_compressive_shocks_only(orc):
+    pd = I.default_params(n=(64, 1, 1), ng=4, recon="ppm", xlo=(-1, 0, 0), xhi=(1, 1, 1),
+                          bc_lo=("outflow",) * 3, bc_hi=("outflow",) * 3)
+    N = I.ncell(pd)
+    x = I.cell_coords(pd)[0].reshape(-1)
+    zero = np.zeros(N)
+    ng = 4
+    # smooth pressure, converging flow: no flattening
+    P = _tube_state(pd, x, 1.0 + 0.1 * np.sin(math.pi * x), -0.1 * x)
+    f = orc.flattener(pd, P, zero, zero)
+    assert np.abs(f[0, :, ng - 1:ng + 65]).max() == 0.0
+    # a 10x pressure jump over two cells with converging flow: flattened
+    p = np.where(x < 0, 10.0, 1.0)
+    P = _tube_state(pd, x, p, -0.5 * np.sign(x))
+    f = orc.flattener(pd, P, zero, zero)
+    jump = np.argmin(np.abs(x))
+    assert f[0, 0, jump - 1:jump + 2].max() == 1.0
+    assert f[0, 0, :jump - 4].max() == 0.0 and f[0, 0, jump + 4:N - ng].max() == 0.0
+    # the same jump expanding: no flattening
+    P = _tube_state(pd, x, p, 0.5 * np.sign(x))
+    assert orc.flattener(pd, P, zero, zero)[0].max() == 0.0
+
+
+def test_flattener_blends_gas_and_radiation_with_optical_depth(orc):
+    """A jump in the radiation pressure alone flattens the radiation fields;
+    at optical depth >= 1/2 per cell the gas fields take the same value."""
+    pd = I.default_params(n=(32, 1, 1), ng=4, recon="ppm", bc_lo=("outflow",) * 3,
+                          bc_hi=("outflow",) * 3)
+    N = I.ncell(pd)
+    x = I.cell_coords(pd)[0].reshape(-1)
+    P = np.zeros((12, N))
+    P[0], P[1] = 1.0, 1.0
+    P[8] = np.where(x < 0.5, 30.0, 3.0)
+    P[9] = np.where(x < 0.5, 0.3, -0.3)
+    jump = np.argmin(np.abs(x - 0.5))
+    thin = orc.flattener(pd, P, np.zeros(N), np.zeros(N))
+    assert thin[0, 1, jump - 1:jump + 2].max() == 1.0 and thin[0, 0].max() == 0.0
+    thick = orc.flattener(pd, P, np.full(N, 100.0), np.zeros(N))
+    assert np.array_equal(thick[0, 0], thick[0, 1]) and thick[0, 0].max() == 1.0
+
+
+def test_ppm_step_conserves_on_periodic_box(orc):
+    pd, P, ca, ce = _periodic_box((24, 16, 1), seed=1)
+    pd4 = dict(pd, ng=4, recon="ppm")
+    # same interior state on the wider ghost layout
+    na2, na4 = I.nalloc(pd), I.nalloc(pd4)
+    P4 = np.zeros((12,) + tuple(na4[::-1]))
+    P4[(slice(None),) + I.interior(pd4)] = P.reshape((12,) + tuple(na2[::-1]))[(slice(None),) + I.interior(pd)]
+    P4 = P4.reshape(12, -1)
+    ca4, ce4 = np.full(P4.shape[1], ca[0]), np.full(P4.shape[1], ce[0])
+    U = orc.prim_to_cons(pd4, P4)
+    sl = I.interior(pd4)
+
+    def totals(U):
+        V = U.reshape((12,) + tuple(na4[::-1]))[(slice(None),) + sl].reshape(12, -1)
+        s = V.sum(axis=1)
+        return np.array([s[0], s[1] + s[8], s[2] + s[9], s[3] + s[10], s[4] + s[11], s[5], s[6], s[7]]), V
+
+    t0, V = totals(U)
+    P1, U1, dt, st, it, nbad = orc.step(pd4, P4, U, ca4, ce4)
+    assert nbad == 0 and dt > 0
+    t1, _ = totals(U1)
+    scale = np.array([np.abs(V[0]).sum(), np.abs(V[1]).sum() + np.abs(V[8]).sum()] +
+                     [np.abs(V[2 + i]).sum() + np.abs(V[9 + i]).sum() for i in range(3)] +
+                     [np.abs(V[5 + i]).sum() + 1e-30 for i in range(3)])
+    assert np.all(np.abs(t1 - t0) <= 2e-14 * scale), (t1 - t0) / scale
