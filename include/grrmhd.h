@@ -51,6 +51,7 @@ enum { GRRMHD_BC_OUTFLOW = 0, GRRMHD_BC_PERIODIC = 1, GRRMHD_BC_REFLECT = 2, GRR
 enum { GRRMHD_FLUX_LLF = 0, GRRMHD_FLUX_HLL = 1 };
 enum { GRRMHD_FP64 = 0, GRRMHD_MIXED = 1 };
 enum { GRRMHD_RK3 = 0, GRRMHD_IMEX2 = 1, GRRMHD_IMEX2B = 2, GRRMHD_IMEX3 = 3 };
+enum { GRRMHD_RECON_MC = 0, GRRMHD_RECON_PPM = 1 };
 enum { GRRMHD_EINVAL = -1, GRRMHD_EHIP = -2, GRRMHD_ENOMEM = -3 };
 
 /* per-cell status bits written by the implicit solve and the fix-ups */
@@ -71,7 +72,8 @@ enum {
  * fixed test parameters (Sec. 5 introduction; Sec. 4.10-4.11). */
 typedef struct {
   int n[3];             /* interior cells per dimension (1 = inactive)        */
-  int ng;               /* ghost width on active dimensions (2 for MC)        */
+  int ng;               /* ghost width on active dimensions: 2 for MC, 4 for
+                           PPM                                                */
   int metric;           /* GRRMHD_MINKOWSKI or GRRMHD_KERR_SCHILD             */
   double a;             /* black-hole spin (Kerr-Schild)                      */
   double R0;            /* radial map r = R0 + exp(x1)                        */
@@ -106,6 +108,12 @@ typedef struct {
                            coefficients for the implicit part), or the IMEX
                            schemes GRRMHD_IMEX2, GRRMHD_IMEX2B, GRRMHD_IMEX3
                            (eq. IMEX2, IMEX2B, IMEX3)                        */
+  int recon;            /* reconstruction (Sec. 4.3): GRRMHD_RECON_MC (default;
+                           MC-limited linear, ng = 2) or GRRMHD_RECON_PPM
+                           (PPM with MC slopes, no contact steepening, the
+                           gas and radiation shock flatteners blended by the
+                           optical depth, each the largest over the step's
+                           sub-steps; ng = 4).  The adjoint covers MC only. */
 } grrmhd_params;
 
 typedef struct grrmhd_grid grrmhd_grid;
@@ -136,8 +144,9 @@ int grrmhd_prim_to_cons(grrmhd_grid *g, const double *P, double *U);
  * phi + pi and negates the theta components. */
 int grrmhd_apply_bc(grrmhd_grid *g, double *P);
 
-/* Sub-steps 4-9 of Sec. 4.2 on a P whose ghosts are filled: MC-limited
- * reconstruction, face U and F, gas fast-magnetosonic and M1 radiation wave
+/* Sub-steps 4-9 of Sec. 4.2 on a P whose ghosts are filled: MC-limited or
+ * PPM reconstruction (params.recon; PPM with the flattener of this P alone),
+ * face U and F, gas fast-magnetosonic and M1 radiation wave
  * speeds (radiation limited by 4/(3 tau), eq. wavespeedlimit), HLL (eq. hll)
  * or LAXF (eq. lax) fluxes, then flux-CT corner EMFs.
  * F [3][12][N]: direction d face flux at index c = face between c - e_d and
@@ -216,8 +225,9 @@ int grrmhd_step(grrmhd_grid *g, double *P, double *U, const double *chi_abs,
  * (Sec. 4.8; one transposed 4x4 solve per cell), the fluxes, EMFs, source
  * and ghost fill by their local Jacobians (dual numbers) and transposes.
  * Floors are taken as the identity; a failed cell's neighbour average is
- * differentiated (its own failed solve receives nothing).  RK3 grids only
- * (EINVAL for another scheme).  P_n [12][N] (interior read; not modified), gU_next
+ * differentiated (its own failed solve receives nothing).  RK3 grids with
+ * MC reconstruction only (EINVAL otherwise; also for grrmhd_explicit_vjp
+ * on a PPM grid).  P_n [12][N] (interior read; not modified), gU_next
  * [12][N] (interior read), gP_n [12][N] out (ghosts zero); P_next, U_next
  * (nullable) receive the forward result.  workspace: device buffer of
  * grrmhd_adjoint_workspace_bytes() bytes, 256-byte aligned.  Errors: EINVAL,

@@ -21,6 +21,7 @@ struct grrmhd_grid {
   unsigned long long* dtstep[2]; // the step's reductions, alternating (each resets the other)
   int dtp = 0;
   int* cnt[2];          // cascade list lengths, alternating (each launch zeroes the other)
+  double* flat = nullptr;  // PPM flattener of the step [3][gas, radiation][Ntot]
   int cp = 0;
   Work W;               // implicit cascade list (interior indices), records, stats;
                         // W.counter is the list length of the last launch
@@ -91,6 +92,7 @@ extern "C" void grrmhd_default_params(grrmhd_params* p) {
   p->flux = GRRMHD_FLUX_LLF;
   p->precision = GRRMHD_FP64;
   p->scheme = GRRMHD_RK3;
+  p->recon = GRRMHD_RECON_MC;
   p->r_fp64 = 2.0;
   p->tol_pmhd = 1e-12;
   p->tol_urad = 1e-9;
@@ -117,8 +119,13 @@ static int validate(const grrmhd_params* p, bool need_grid) {
   if (p->metric != GRRMHD_MINKOWSKI && p->metric != GRRMHD_KERR_SCHILD)
     return fail(GRRMHD_EINVAL, "bad metric");
   if (p->scheme < GRRMHD_RK3 || p->scheme > GRRMHD_IMEX3) return fail(GRRMHD_EINVAL, "bad scheme");
+  if (p->recon != GRRMHD_RECON_MC && p->recon != GRRMHD_RECON_PPM)
+    return fail(GRRMHD_EINVAL, "bad reconstruction");
   if (!need_grid) return 0;
-  if (p->ng != 2) return fail(GRRMHD_EINVAL, "ghost width must be 2 (MC reconstruction)");
+  if (p->recon == GRRMHD_RECON_MC && p->ng != 2)
+    return fail(GRRMHD_EINVAL, "ghost width must be 2 for MC reconstruction");
+  if (p->recon == GRRMHD_RECON_PPM && p->ng != 4)
+    return fail(GRRMHD_EINVAL, "ghost width must be 4 for PPM reconstruction");
   for (int d = 0; d < 3; d++) {
     if (p->n[d] < 1 || p->n[d] > (1 << 20)) return fail(GRRMHD_EINVAL, "n out of range");
     if (p->n[d] > 1 && p->n[d] < p->ng) return fail(GRRMHD_EINVAL, "active dimension shorter than ng");
@@ -161,6 +168,7 @@ static void fill_ctx(const grrmhd_params* p, Ctx& C) {
   C.ymax = 16.0 * G * (G - 1.0) / ((4.0 * G - 1.0) * (4.0 * G - 1.0));
   C.courant = p->courant;
   C.flux = p->flux;
+  C.recon = p->recon;
   // FP32 face path from the first x1 index i whose cell i-1 has r >= r_fp64
   C.mixed_i = 1 << 30;
   if (p->precision == GRRMHD_MIXED) {
@@ -210,7 +218,10 @@ extern "C" int grrmhd_init_grid(const grrmhd_params* p, int device, void* hip_st
   const size_t nd = tab * (GE_NCENTER + 2 * GE_NFACE);
   const size_t nint = (size_t)g->C.n[0] * g->C.n[1] * g->C.n[2];
   // [nd doubles][256 B: dt slot @0, list length @128, stats @192][cascade]
-  hipError_t e = hipMalloc(&g->geo, nd * sizeof(double) + TAIL_CASCADE + cascade_bytes(nint));
+  const size_t flat_bytes =
+      (p->recon == GRRMHD_RECON_PPM) ? round256(sizeof(double) * 6 * (size_t)g->C.Ntot) : 0;
+  hipError_t e = hipMalloc(&g->geo, nd * sizeof(double) + TAIL_CASCADE + cascade_bytes(nint) +
+                                        flat_bytes);
   if (e != hipSuccess) {
     delete g;
     return fail(GRRMHD_ENOMEM, std::string("geometry allocation: ") + hipGetErrorString(e));
@@ -225,6 +236,7 @@ extern "C" int grrmhd_init_grid(const grrmhd_params* p, int device, void* hip_st
   g->W.counter_next = nullptr;
   g->W.stats = (unsigned long long*)(tail + 192);
   cascade_layout(tail + TAIL_CASCADE, nint, g->W);
+  if (flat_bytes) g->flat = (double*)(tail + TAIL_CASCADE + cascade_bytes(nint));
   g->C.geo_c = g->geo;
   g->C.geo_f1 = g->geo + tab * GE_NCENTER;
   g->C.geo_f2 = g->geo + tab * (GE_NCENTER + GE_NFACE);
@@ -417,11 +429,20 @@ static void split_x1(const FaceRange& R, int i0, FaceRange& a, FaceRange& b) {
   b.total = (long)b.cnt[0] * b.cnt[1] * b.cnt[2];
 }
 
-// dtmin set: the Courant reduction over interior cells runs in the EMF launch
+// dtmin set: the Courant reduction over interior cells runs in the EMF launch.
+// PPM: the flattener of P first; keep_flat: the larger of it and the step's
+// earlier sub-steps' (0 at a step's first flux evaluation).
 static int launch_fluxes(grrmhd_grid* g, const double* P, const double* ca, const double* ce,
                          double* F, double* emf, double* vch,
-                         unsigned long long* dtmin = nullptr) {
+                         unsigned long long* dtmin = nullptr, int keep_flat = 0) {
   const Ctx& C = g->C;
+  if (C.recon == GRRMHD_RECON_PPM) {
+    long nb = 1;
+    for (int e = 0; e < 3; e++) nb *= C.n[e] > 1 ? C.n[e] + 2 : 1;
+    hipLaunchKernelGGL(k_flatten, dim3(nblocks(nb, 256)), dim3(256), 0, g->stream, C, P, ca, ce,
+                       g->flat, keep_flat);
+    LAUNCHCHK();
+  }
   // faces of every direction, FP64 part and FP32 part (split at mixed_i)
   FluxSegs S64, S32;
   S64.n = S32.n = 0;
@@ -441,12 +462,12 @@ static int launch_fluxes(grrmhd_grid* g, const double* P, const double* ca, cons
   }
   if (S64.total > 0) {
     hipLaunchKernelGGL(k_flux_all<double>, dim3(nblocks(S64.total, 128)), dim3(128), 0, g->stream,
-                       C, S64, P, ca, ce, F, vch);
+                       C, S64, P, ca, ce, F, vch, (const double*)g->flat);
     LAUNCHCHK();
   }
   if (S32.total > 0) {
     hipLaunchKernelGGL(k_flux_all<float>, dim3(nblocks(S32.total, 128)), dim3(128), 0, g->stream,
-                       C, S32, P, ca, ce, F, vch);
+                       C, S32, P, ca, ce, F, vch, (const double*)g->flat);
     LAUNCHCHK();
   }
   // corner EMFs: union of the edge ranges (n + 1 positions along active axes)
@@ -647,7 +668,7 @@ static int imex_step(grrmhd_grid* g, double* P, double* U, const double* chi_abs
   }
   const long nint = n_interior(C);
   double* Pcur = P;
-  int rc;
+  int rc, nflux = 0;
   for (int i = 0; i < S.ns; i++) {
     const Stage& x = S.s[i];
     const bool last = (i == S.ns - 1);
@@ -658,7 +679,8 @@ static int imex_step(grrmhd_grid* g, double* P, double* U, const double* chi_abs
     unsigned long long* dnext = red ? g->dtstep[g->dtp ^ 1] : nullptr;
     if (x.c != 0.0 || red) {
       if ((rc = launch_bc(g, Pcur))) return rc;
-      if ((rc = launch_fluxes(g, Pcur, chi_abs, chi_es, F, emf, vch, dmin))) return rc;
+      if ((rc = launch_fluxes(g, Pcur, chi_abs, chi_es, F, emf, vch, dmin, nflux > 0))) return rc;
+      nflux++;
     }
     MTerms MT;
     memset(&MT, 0, sizeof(MT));
@@ -738,7 +760,7 @@ extern "C" int grrmhd_step(grrmhd_grid* g, double* P, double* U, const double* c
     const bool red = (s == 0 && !dt_fixed);
     unsigned long long* dmin = red ? g->dtstep[g->dtp] : nullptr;
     unsigned long long* dnext = red ? g->dtstep[g->dtp ^ 1] : nullptr;
-    if ((rc = launch_fluxes(g, Pin, chi_abs, chi_es, F, emf, vch, dmin))) return rc;
+    if ((rc = launch_fluxes(g, Pin, chi_abs, chi_es, F, emf, vch, dmin, s > 0))) return rc;
     if ((rc = launch_update(g, A[s], B[s], Cc[s], dt_dev, Pin, U, Uprev, F, emf, Ue, dmin, dnext)))
       return rc;
     if (red) g->dtp ^= 1;
@@ -895,6 +917,8 @@ extern "C" int grrmhd_explicit_vjp(grrmhd_grid* g, double c, const double* dt_de
   NEEDG();
   if (!dt_dev || !P || !chi_abs || !chi_es || !gUexp || !gP || !workspace)
     return fail(GRRMHD_EINVAL, "NULL array");
+  if (g->p.recon != GRRMHD_RECON_MC)
+    return fail(GRRMHD_EINVAL, "the flux adjoint covers MC reconstruction");
   if (ws_bytes < grrmhd_explicit_vjp_workspace_bytes(g)) return fail(GRRMHD_EINVAL, "workspace too small");
   if (((uintptr_t)workspace) & 255) return fail(GRRMHD_EINVAL, "workspace must be 256-byte aligned");
   const size_t N = (size_t)g->C.Ntot;
@@ -916,7 +940,8 @@ extern "C" int grrmhd_step_adjoint(grrmhd_grid* g, const double* P_n, const doub
   NEEDG();
   if (!P_n || !chi_abs || !chi_es || !dt_dev || !gU_next || !gP_n || !workspace)
     return fail(GRRMHD_EINVAL, "NULL array");
-  if (g->p.scheme != GRRMHD_RK3) return fail(GRRMHD_EINVAL, "the adjoint covers the RK3 scheme");
+  if (g->p.scheme != GRRMHD_RK3 || g->p.recon != GRRMHD_RECON_MC)
+    return fail(GRRMHD_EINVAL, "the adjoint covers the RK3 scheme with MC reconstruction");
   const Ctx& C = g->C;
   const AdjLayout w = adj_layout(C);
   if (ws_bytes < w.total) return fail(GRRMHD_EINVAL, "workspace too small");

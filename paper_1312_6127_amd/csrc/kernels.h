@@ -202,6 +202,37 @@ DEV T mc_slope(T dl, T dr) {
   return copysign(fmin(fabs(dc), R(2.0) * fmin(fabs(dl), fabs(dr))), dc);
 }
 
+// PPM (Colella & Woodward 1984, no contact steepening): interface value
+// between the 2nd and 3rd of four cells, the mean less the difference of
+// their MC slopes over 6
+template <class T>
+DEV T ppm_iface(T am, T a0, T a1, T a2) {
+  using R = typename RealOf<T>::type;
+  return R(0.5) * (a0 + a1) - (mc_slope(a1 - a0, a2 - a1) - mc_slope(a0 - am, a1 - a0)) / R(6.0);
+}
+
+// left and right values of the middle of five cells: interface values
+// flattened towards the cell value by f, then the monotonicity constraints
+template <class T>
+DEV void ppm_cell(const T* a, T f, T& aL, T& aR) {
+  using R = typename RealOf<T>::type;
+  const T a0 = a[2];
+  T l = ppm_iface(a[0], a[1], a[2], a[3]);
+  T r = ppm_iface(a[1], a[2], a[3], a[4]);
+  l = f * a0 + (R(1.0) - f) * l;
+  r = f * a0 + (R(1.0) - f) * r;
+  if ((r - a0) * (a0 - l) <= R(0.0)) {
+    l = a0;
+    r = a0;
+  } else {
+    const T d = r - l, m6 = R(6.0) * (a0 - R(0.5) * (l + r));
+    if (d * m6 > d * d) l = R(3.0) * a0 - R(2.0) * r;
+    else if (-(d * d) > d * m6) r = R(3.0) * a0 - R(2.0) * l;
+  }
+  aL = l;
+  aR = r;
+}
+
 template <class T>
 struct FaceState {
   T U[12], F[12];
@@ -259,11 +290,12 @@ struct FaceRange {
 // Faces normal to D in range R: reconstruction, face states, HLL / LAXF, in
 // arithmetic T (double; float for the FP32-mixed path); fluxes and speeds are
 // stored as double.
+// fl: the PPM flattener [3][gas, radiation][Ntot] (unused for MC)
 template <int D, class T>
 DEV void flux_at(Ctx C, FaceRange R, const double* __restrict__ P,
                                const double* __restrict__ chi_abs,
                                const double* __restrict__ chi_es, double* __restrict__ F,
-                               double* __restrict__ vchar, long t) {
+                               double* __restrict__ vchar, const double* __restrict__ fl, long t) {
   if (t >= R.total) return;
   const int i = R.lo[0] + t % R.cnt[0];
   const long t2 = t / R.cnt[0];
@@ -272,12 +304,29 @@ DEV void flux_at(Ctx C, FaceRange R, const double* __restrict__ P,
   const long c = cell_index(C, i, j, k);
   const long st = C.st[D - 1];
   T PL[12], PR[12];
+  if (C.recon == GRRMHD_RECON_PPM) {
+    // left state: right value of cell c - st; right state: left value of c
+    const double* fg = fl + (long)(2 * (D - 1)) * C.Ntot;
+    const double* fr = fg + C.Ntot;
+    const T fgL = (T)fg[c - st], frL = (T)fr[c - st], fgR = (T)fg[c], frR = (T)fr[c];
 #pragma unroll
-  for (int q = 0; q < 12; q++) {
-    const double* p = P + q * C.Ntot;
-    const T a = (T)p[c - 2 * st], b = (T)p[c - st], e = (T)p[c], f = (T)p[c + st];
-    PL[q] = b + T(0.5) * mc_slope(b - a, e - b);
-    PR[q] = e - T(0.5) * mc_slope(e - b, f - e);
+    for (int q = 0; q < 12; q++) {
+      const double* p = P + q * C.Ntot;
+      T a[6];
+#pragma unroll
+      for (int m = 0; m < 6; m++) a[m] = (T)p[c + (m - 3) * st];
+      T l, r;
+      ppm_cell(a, q < 8 ? fgL : frL, l, PL[q]);
+      ppm_cell(a + 1, q < 8 ? fgR : frR, PR[q], r);
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < 12; q++) {
+      const double* p = P + q * C.Ntot;
+      const T a = (T)p[c - 2 * st], b = (T)p[c - st], e = (T)p[c], f = (T)p[c + st];
+      PL[q] = b + T(0.5) * mc_slope(b - a, e - b);
+      PR[q] = e - T(0.5) * mc_slope(e - b, f - e);
+    }
   }
   MetricT<T> m;
   const double* tab = (D == 1) ? C.geo_f1 : ((D == 2) ? C.geo_f2 : C.geo_c);
@@ -321,7 +370,8 @@ struct FluxSegs {
 template <class T>
 DEV void flux_all_at(Ctx C, const FluxSegs& S, const double* __restrict__ P,
                      const double* __restrict__ chi_abs, const double* __restrict__ chi_es,
-                     double* __restrict__ F, double* __restrict__ vchar, long t) {
+                     double* __restrict__ F, double* __restrict__ vchar,
+                     const double* __restrict__ fl, long t) {
   if (t >= S.total) return;
   int k = 0;
   if (S.n > 1 && t >= S.start[1]) k = 1;
@@ -330,18 +380,99 @@ DEV void flux_all_at(Ctx C, const FluxSegs& S, const double* __restrict__ P,
   const int D = S.D[k];
   double* Fd = F + (long)(D - 1) * 12 * C.Ntot;
   double* vd = vchar + (long)(D - 1) * C.Ntot;
-  if (D == 1) flux_at<1, T>(C, S.R[k], P, chi_abs, chi_es, Fd, vd, u);
-  else if (D == 2) flux_at<2, T>(C, S.R[k], P, chi_abs, chi_es, Fd, vd, u);
-  else flux_at<3, T>(C, S.R[k], P, chi_abs, chi_es, Fd, vd, u);
+  if (D == 1) flux_at<1, T>(C, S.R[k], P, chi_abs, chi_es, Fd, vd, fl, u);
+  else if (D == 2) flux_at<2, T>(C, S.R[k], P, chi_abs, chi_es, Fd, vd, fl, u);
+  else flux_at<3, T>(C, S.R[k], P, chi_abs, chi_es, Fd, vd, fl, u);
 }
 
 template <class T>
 __global__ void GRRMHD_FLUX_LB k_flux_all(Ctx C, FluxSegs S, const double* __restrict__ P,
                                           const double* __restrict__ chi_abs,
                                           const double* __restrict__ chi_es,
-                                          double* __restrict__ F, double* __restrict__ vchar) {
-  flux_all_at<T>(C, S, P, chi_abs, chi_es, F, vchar,
+                                          double* __restrict__ F, double* __restrict__ vchar,
+                                          const double* __restrict__ fl) {
+  flux_all_at<T>(C, S, P, chi_abs, chi_es, F, vchar, fl,
                  xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// PPM shock flattener (Sec. 4.3; FLASH form with SP0 = 0.75): per cell within
+// one cell of the interior and per active direction d, for gas (pressure
+// (gam-1) u_g, velocity u~^d) and radiation (Ebar/3, u~^d_rad), each pressure
+// raised by w = min(1, 2 tau) times the other, tau = kappa_tot sqrt(g_dd) dx^d:
+//   f = clamp(10 (|dp1|/|dp2| - 0.75), 0, 1) where |dp1| = |p(+1) - p(-1)| >
+//   0.33 min(p(+1), p(-1)) and the flow converges, else 0; then the larger of
+//   f and f at the neighbour on the high-pressure side; finally each kind
+//   moves towards the larger of the two by w.  keep: the larger of this and
+//   the stored value (earlier sub-steps of the step).
+// ---------------------------------------------------------------------------
+DEV double flat_raw(const double* pp, const double* v, int m) {
+  const double d1 = pp[m + 1] - pp[m - 1], d2 = pp[m + 2] - pp[m - 2];
+  if (!(::fabs(d1) > 0.33 * ::fmin(pp[m + 1], pp[m - 1])) || !(v[m - 1] - v[m + 1] > 0.0))
+    return 0.0;
+  return ::fmax(0.0, ::fmin(1.0, 10.0 * (::fabs(d1) / ::fmax(::fabs(d2), 1e-300) - 0.75)));
+}
+
+DEV double flat_tilde(const double* pp, const double* v) {
+  const double f0 = flat_raw(pp, v, 0);
+  const int up = (pp[1] - pp[-1] < 0.0) ? 1 : -1;
+  return ::fmax(f0, flat_raw(pp, v, up));
+}
+
+DEV void flatten_at(Ctx C, const double* __restrict__ P, const double* __restrict__ chi_abs,
+                    const double* __restrict__ chi_es, double* __restrict__ fl, int keep, long t) {
+  int lo[3], cnt[3];
+#pragma unroll
+  for (int e = 0; e < 3; e++) {
+    lo[e] = C.n[e] > 1 ? C.ng[e] - 1 : 0;
+    cnt[e] = C.n[e] > 1 ? C.n[e] + 2 : 1;
+  }
+  if (t >= (long)cnt[0] * cnt[1] * cnt[2]) return;
+  const int i = lo[0] + t % cnt[0];
+  const long t2 = t / cnt[0];
+  const int j = lo[1] + t2 % cnt[1];
+  const int k = lo[2] + t2 / cnt[1];
+  const long c = cell_index(C, i, j, k);
+  for (int d = 0; d < 3; d++) {
+    if (C.n[d] == 1) continue;
+    const long st = C.st[d];
+    const int sq = sym(d + 1, d + 1);
+    double pg7[7], pr7[7], vg5[5], vr5[5], w0 = 0.0;
+#pragma unroll
+    for (int m = -3; m <= 3; m++) {
+      const long cm = c + m * st;
+      const int pos = (int)(cm % ((long)C.N[0] * C.N[1]));
+      const double gdd = C.geo_c[(GE_GCOV + sq) * C.npos + pos];
+      const double rho = P[cm];
+      const double tau = (chi_abs[cm] + chi_es[cm]) * rho * ::sqrt(gdd) * C.dx[d];
+      const double w = ::fmin(1.0, 2.0 * tau);
+      const double p_g = (C.gam - 1.0) * P[C.Ntot + cm], p_r = P[8 * C.Ntot + cm] / 3.0;
+      pg7[m + 3] = p_g + w * p_r;
+      pr7[m + 3] = p_r + w * p_g;
+      if (m == 0) w0 = w;
+      if (m >= -2 && m <= 2) {
+        vg5[m + 2] = P[(2 + d) * C.Ntot + cm];
+        vr5[m + 2] = P[(9 + d) * C.Ntot + cm];
+      }
+    }
+    // flat_raw indexes pressures at m +- 2 and velocities at m +- 1 around m
+    // in {-1, 0, 1}: centre the arrays
+    const double fg = flat_tilde(pg7 + 3, vg5 + 2), fr = flat_tilde(pr7 + 3, vr5 + 2);
+    const double fm = ::fmax(fg, fr);
+    const double f2[2] = {(1.0 - w0) * fg + w0 * fm, (1.0 - w0) * fr + w0 * fm};
+#pragma unroll
+    for (int kind = 0; kind < 2; kind++) {
+      double* dst = fl + (long)(2 * d + kind) * C.Ntot + c;
+      *dst = keep ? ::fmax(*dst, f2[kind]) : f2[kind];
+    }
+  }
+}
+
+__global__ void LB(256) k_flatten(Ctx C, const double* __restrict__ P,
+                                  const double* __restrict__ chi_abs,
+                                  const double* __restrict__ chi_es, double* __restrict__ fl,
+                                  int keep) {
+  flatten_at(C, P, chi_abs, chi_es, fl, keep, (long)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------

@@ -33,7 +33,7 @@ class Params(C.Structure):
         ("max_iter", C.c_int), ("roundoff", C.c_int),
         ("rho_floor", C.c_double), ("u_floor", C.c_double), ("bsq_rho_max", C.c_double),
         ("bsq_u_max", C.c_double), ("u_rho_max", C.c_double), ("erad_floor", C.c_double),
-        ("scheme", C.c_int),
+        ("scheme", C.c_int), ("recon", C.c_int),
     ]
 
 
@@ -67,6 +67,7 @@ def params(d: dict) -> Params:
     p.max_iter = int(d["max_iter"])
     p.roundoff = int(d["roundoff"])
     p.scheme = SCHEMES[d.get("scheme", "rk3")]
+    p.recon = 1 if d.get("recon", "mc") == "ppm" else 0
     return p
 
 

@@ -56,7 +56,7 @@ def default_params(**kw) -> dict:
         tol_pmhd=1e-12, tol_urad=1e-9, tol_accept=1e-9, tol_fail=1e-7,
         max_iter=20, roundoff=1,
         rho_floor=1e-20, u_floor=1e-22, bsq_rho_max=200.0, bsq_u_max=1e5,
-        u_rho_max=1e10, erad_floor=1e-150, scheme="rk3",
+        u_rho_max=1e10, erad_floor=1e-150, scheme="rk3", recon="mc",
     )
     p.update(kw)
     return p
@@ -96,14 +96,16 @@ def cell_coords(p: dict):
 # workloads
 # ---------------------------------------------------------------------------
 
-def shock_tube_1d(n: int = 256):
+def shock_tube_1d(n: int = 256, **kw):
     """1-D Minkowski radiative shock tube: x in [-1, 1], outflow, gamma = 5/3,
     no field, left (rho, p) = (1, 1e-2), right (0.125, 1e-3), at rest,
     Ebar = a_rad T^4 with T = p/rho, zero flux (radiation frame = gas frame),
-    a_rad = 1e-2, per-mass opacities chi_abs = 1, chi_es = 0.5, HLL, C = 0.5."""
+    a_rad = 1e-2, per-mass opacities chi_abs = 1, chi_es = 0.5, HLL, C = 0.5.
+    kw: further parameters (e.g. ng=4, recon="ppm")."""
     p = default_params(n=(n, 1, 1), xlo=(-1.0, 0.0, 0.0), xhi=(1.0, 1.0, 1.0),
                        bc_lo=("outflow",) * 3, bc_hi=("outflow",) * 3,
                        arad=1e-2, flux="hll")
+    p.update(kw)
     N = ncell(p)
     x1, _, _ = cell_coords(p)
     x1 = x1.reshape(-1)
@@ -120,9 +122,9 @@ def shock_tube_1d(n: int = 256):
     return p, P, chi_abs, chi_es
 
 
-def disk_params(n=(128, 64, 1), a=0.9375, rin=1.2, rout=40.0, flux="llf"):
+def disk_params(n=(128, 64, 1), a=0.9375, rin=1.2, rout=40.0, flux="llf", **kw):
     threed = n[2] > 1
-    return default_params(
+    p = default_params(
         n=tuple(n), metric="ks", a=a, R0=0.0,
         xlo=(math.log(rin), 0.0, 0.0), xhi=(math.log(rout), 1.0, 1.0),
         bc_lo=("outflow", "polar" if threed else "reflect", "periodic"),
@@ -130,6 +132,8 @@ def disk_params(n=(128, 64, 1), a=0.9375, rin=1.2, rout=40.0, flux="llf"):
         gam=5.0 / 3.0, arad=1.247e5, flux=flux,
         rho_floor=1e-12, u_floor=1e-14,
     )
+    p.update(kw)
+    return p
 
 
 def _ks_sqrtg(a, r, th):
@@ -139,7 +143,7 @@ def _ks_sqrtg(a, r, th):
 
 
 def accretion_disk(n=(128, 64, 1), seed=2, a=0.9375, rin=1.2, rout=40.0, flux="llf",
-                   perturb3d=None):
+                   perturb3d=None, **kw):
     """Synthetic accretion-shaped state on a log-r Kerr-Schild grid.
 
     rho0 = (r/r_in)^-1.5, p = 0.1 rho0/r, radial inflow u~^1 = -sqrt(2/r)/r
@@ -150,10 +154,11 @@ def accretion_disk(n=(128, 64, 1), seed=2, a=0.9375, rin=1.2, rout=40.0, flux="l
     radiation frame = gas frame, chi_abs from a per-cell optical depth
     log-uniform in x1 from 1e4 (inner edge) to 1e-3 (outer edge), chi_es = 0.
     With perturb3d: rho0 x (1 + 0.04 (U - 1/2)) and each u~^i += 0.02
-    sqrt(2/r) (2U - 1) in orthonormal-magnitude units."""
+    sqrt(2/r) (2U - 1) in orthonormal-magnitude units.  kw: further
+    parameters (e.g. ng=4, recon="ppm")."""
     if perturb3d is None:
         perturb3d = n[2] > 1
-    p = disk_params(n=n, a=a, rin=rin, rout=rout, flux=flux)
+    p = disk_params(n=n, a=a, rin=rin, rout=rout, flux=flux, **kw)
     na = nalloc(p)
     N = ncell(p)
     x1, x2, x3 = cell_coords(p)
