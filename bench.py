@@ -11,7 +11,9 @@ mixed_precision: the same run with FP32 reconstruction, face states,
 Riemann fluxes and EMFs, and the per-field error of both precisions against
 the FP64 oracle after the oracle's steps.  imex3: the same workload stepped
 with the IMEX3 scheme (eq. IMEX3; four implicit stages), its time per step
-and its error against the oracle's IMEX3 steps.  roofline: the dominant kernel
+and its error against the oracle's IMEX3 steps.  ppm: the same disk recipe
+with PPM reconstruction and the shock flattener (ghost width 4), its time
+per step and its error against the oracle's PPM steps.  roofline: the dominant kernel
 (the implicit kernel's first PMHD attempt), its average launch time from HIP
 events on its stream inside the timed region.  cpu_baseline: the FP64 oracle
 stepping the same workload on the host cores (bounded sample).
@@ -41,9 +43,9 @@ STEP_BYTES_PER_ZONE = 1344
 # (FETCH_SIZE x 2 + WRITE_SIZE x 1, the scales from a copy of known size).
 # They hold for the kernel sources whose digest is KERNEL_DIGEST; otherwise
 # traffic is reported as null and the flop figure as stale.
-FLOPS_PER_TRIP = 1722.0
-HBM_BYTES_PER_LAUNCH = 158.8e6
-KERNEL_DIGEST = "516af7dafd0ee6ca"
+FLOPS_PER_TRIP = 1732.0
+HBM_BYTES_PER_LAUNCH = 159.5e6
+KERNEL_DIGEST = "edea756143859c32"
 
 
 def parse():
@@ -54,7 +56,7 @@ def parse():
     ap.add_argument("--n", type=int, nargs=3, default=[128, 64, 32])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--imex-err-steps", type=int, default=3,
-                    help="IMEX3 steps compared with the oracle's")
+                    help="IMEX3 and PPM steps compared with the oracle's")
     ap.add_argument("--cpu-steps", type=int, default=20,
                     help="oracle steps (the CPU baseline sample and the error reference)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
@@ -273,6 +275,11 @@ def main():
     print(f"imex3 steps: {rim['ms'] / args.steps:.3f} ms/step", file=sys.stderr, flush=True)
     imex = {"value": zones * args.steps / (rim["ms"] * 1e-3), "ms_per_step": rim["ms"] / args.steps,
             "time_vs_rk3": rim["ms"] / r64["ms"]}
+    pdp, Pp, cap, cep = I.accretion_disk(n=n, seed=3, ng=4, recon="ppm")
+    rpp = time_steps(G, torch, dev, pdp, Pp, cap, cep, args.steps, args.warmup, kernel_timing=False)
+    print(f"ppm steps: {rpp['ms'] / args.steps:.3f} ms/step", file=sys.stderr, flush=True)
+    ppm = {"value": zones * args.steps / (rpp["ms"] * 1e-3), "ms_per_step": rpp["ms"] / args.steps,
+           "time_vs_mc": rpp["ms"] / r64["ms"]}
 
     # dominant kernel: the implicit kernel of each stage, timed with HIP events
     # on its stream inside the timed region
@@ -336,6 +343,17 @@ def main():
         e = [field_errors(got[0], ref[0]), field_errors(got[1], ref[1])]
         imex["err_vs_oracle_max"] = max(max(e[0].values()), max(e[1].values()))
         imex["err_steps"] = args.imex_err_steps
+        # PPM against the oracle's PPM (same few steps)
+        nap, intp = I.nalloc(pdp), I.interior(pdp)
+        Ph, Uh = Pp, oracle.prim_to_cons(pdp, Pp)
+        for _ in range(args.imex_err_steps):
+            Ph, Uh, dth, sth, ith, nb = oracle.step(pdp, Ph, Uh, cap, cep)
+        ref = [x.reshape((12,) + nap[::-1])[(slice(None),) + intp].reshape(12, -1) for x in (Ph, Uh)]
+        Pg, Ug = gpu_run(G, torch, dev, pdp, Pp, cap, cep, args.imex_err_steps)
+        got = [x.reshape((12,) + nap[::-1])[(slice(None),) + intp].reshape(12, -1) for x in (Pg, Ug)]
+        e = [field_errors(got[0], ref[0]), field_errors(got[1], ref[1])]
+        ppm["err_vs_oracle_max"] = max(max(e[0].values()), max(e[1].values()))
+        ppm["err_steps"] = args.imex_err_steps
 
     out = {
         "metric": "zone-cycles/s per GRRMHD step (FP32-mixed vs FP64) at stated rel. error; % HBM peak",
@@ -359,6 +377,7 @@ def main():
                      "frac": value * STEP_BYTES_PER_ZONE / 1e9 / HBM_PEAK_GBS},
         "mixed_precision": mixed,
         "imex3": imex,
+        "ppm": ppm,
         "roofline": roof,
         "cpu_baseline": cpu,
     }
