@@ -112,6 +112,32 @@ DEV double mhd_vsq(const MhdC& c, double W) {
   return (c.Qt2 * W * W + c.S * c.S * (c.Bsq + 2.0 * W)) / (a * a * W * W);
 }
 
+// Narrows a bracket [lo, hi] of the root of g(W') = f (KIND 0) or chi
+// (KIND 1), both increasing on the admissible region, by Newton steps from
+// the last point (the midpoint whenever a step would leave the bracket);
+// the bisection that follows takes it to adjacent doubles as before, in a
+// few steps instead of ~60.  KIND 1 keeps chi > 0 at hi (chi = 0 goes low).
+template <int KIND>
+DEV void mhd_narrow(const MhdC& c, double& lo, double& hi) {
+  double x = 0.5 * (lo + hi);
+  for (int it = 0; it < 40; it++) {
+    Dual<1> chi, gm;
+    const Dual<1> f = mhd_f<Dual<1>>(c, Dual<1>::var(x, 0), chi, gm);
+    const Dual<1> g = (KIND == 0) ? f : chi;
+    if (!isfinite(g.v) || !isfinite(g.d[0])) return;
+    if (KIND == 0 && g.v == 0.0) {
+      lo = hi = x;
+      return;
+    }
+    if (g.v > 0.0) hi = x;
+    else lo = x;
+    if (!(hi - lo > 8.0 * DBL_EPSILON * ::fabs(hi))) return;
+    double xn = (g.d[0] != 0.0) ? x - g.v / g.d[0] : lo;
+    if (!(xn > lo && xn < hi)) xn = 0.5 * (lo + hi);
+    x = xn;
+  }
+}
+
 // Bracketed bisection: the admissible region is v~^2 < 1 and chi > 0; on it
 // the root is bracketed by W0' (chi = 0) and gam (E' - Bsq/2).
 DEV int mhd_bisect(const MhdC& c, double& Wp_out) {
@@ -137,6 +163,7 @@ DEV int mhd_bisect(const MhdC& c, double& Wp_out) {
     nb = 2.0 * nb + 1e-300;
   }
   double na = a0;
+  mhd_narrow<1>(c, na, nb);
   for (int it = 0; it < 200; it++) {
     const double mid = 0.5 * (na + nb);
     if (mid <= na || mid >= nb) break;
@@ -145,6 +172,7 @@ DEV int mhd_bisect(const MhdC& c, double& Wp_out) {
   }
   double lo = nb;
   if (!(lo <= hi) || !(mhd_f<double>(c, lo, chi, gm) < 0.0)) return 1;
+  mhd_narrow<0>(c, lo, hi);
   for (int it = 0; it < 200; it++) {
     const double mid = 0.5 * (lo + hi);
     if (mid <= lo || mid >= hi) break;
