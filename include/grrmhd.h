@@ -228,15 +228,19 @@ int grrmhd_step(grrmhd_grid *g, double *P, double *U, const double *chi_abs,
  * differentiated (its own failed solve receives nothing).  RK3 grids with
  * MC reconstruction only (EINVAL otherwise; also for grrmhd_explicit_vjp
  * on a PPM grid).  P_n [12][N] (interior read; not modified), gU_next
- * [12][N] (interior read), gP_n [12][N] out (ghosts zero); P_next, U_next
- * (nullable) receive the forward result.  workspace: device buffer of
+ * [12][N] (interior read), gP_n [12][N] out (ghosts zero); g_chi (nullable)
+ * [2][N] out: dL/dchi_abs, dL/dchi_es at every allocated cell (the per-mass
+ * opacities enter the implicit residual through kappa = chi rho0 and the
+ * face fluxes through the radiation speed limiter of the two face cells,
+ * ghost cells included); P_next, U_next (nullable) receive the forward
+ * result.  workspace: device buffer of
  * grrmhd_adjoint_workspace_bytes() bytes, 256-byte aligned.  Errors: EINVAL,
  * EHIP. */
 size_t grrmhd_adjoint_workspace_bytes(const grrmhd_grid *g);
 int grrmhd_step_adjoint(grrmhd_grid *g, const double *P_n, const double *chi_abs,
                         const double *chi_es, const double *dt_dev, const double *gU_next,
-                        double *gP_n, double *P_next, double *U_next, void *workspace,
-                        size_t ws_bytes);
+                        double *gP_n, double *g_chi, double *P_next, double *U_next,
+                        void *workspace, size_t ws_bytes);
 
 /* Pieces of the adjoint sweep (each the transpose of the Jacobian of a
  * forward entry point; ghosts of inputs are ignored where the forward

@@ -86,7 +86,7 @@ __global__ void LB(128) k_adj_p2u(Ctx C, const double* __restrict__ P,
 // outputs exactly as the forward step finalises a PMHD solution.
 // ---------------------------------------------------------------------------
 template <class T>
-DEV void pmhd_map(const Metric& m, const Phys& ph, double dtc, double chi_abs, double chi_es,
+DEV void pmhd_map(const Metric& m, const Phys& ph, double dtc, const T& chi_abs, const T& chi_es,
                   const T x[4], const T th[12], T E[4], T P[12], T U[12]) {
   const double igd = 1.0 / m.gdet;
   const T rhout = th[0] * igd;
@@ -162,7 +162,8 @@ DEV void adj_implicit_at(Ctx C, double scale, const double* __restrict__ dt_dev,
                                       const double* __restrict__ chi_abs,
                                       const double* __restrict__ chi_es,
                                       const double* __restrict__ lamP,
-                                      const double* __restrict__ lamU, double* __restrict__ lamUe, long t) {
+                                      const double* __restrict__ lamU, double* __restrict__ lamUe,
+                                      double* __restrict__ gchi, long t) {
   if (t >= (long)C.n[0] * C.n[1] * C.n[2]) return;
   int i, j, k;
   interior_cell(C, t, i, j, k);
@@ -192,7 +193,7 @@ DEV void adj_implicit_at(Ctx C, double scale, const double* __restrict__ dt_dev,
     seed4<4>(x, 0, xd);
 #pragma unroll
     for (int q = 0; q < 12; q++) thd[q] = D4(th[q]);
-    pmhd_map(m, ph, dtc, ca, ce, xd, thd, E, Po, Uo);
+    pmhd_map(m, ph, dtc, D4(ca), D4(ce), xd, thd, E, Po, Uo);
     double JT[4][4], gx[4];
 #pragma unroll
     for (int jj = 0; jj < 4; jj++) {
@@ -215,7 +216,7 @@ DEV void adj_implicit_at(Ctx C, double scale, const double* __restrict__ dt_dev,
 #pragma unroll
     for (int q = 0; q < 4; q++) xd[q] = D4(x[q]);
     seed4<12>(th, 4 * pass, thd);
-    pmhd_map(m, ph, dtc, ca, ce, xd, thd, E, Po, Uo);
+    pmhd_map(m, ph, dtc, D4(ca), D4(ce), xd, thd, E, Po, Uo);
 #pragma unroll
     for (int jj = 0; jj < 4; jj++) {
       double s = 0.0;
@@ -226,6 +227,21 @@ DEV void adj_implicit_at(Ctx C, double scale, const double* __restrict__ dt_dev,
       lamUe[(4 * pass + jj) * C.Ntot + c] = s;
     }
   }
+  if (gchi) {   // the opacities: they enter the residual only (kappa = chi rho0)
+    D4 xd[4], thd[12], E[4], Po[12], Uo[12];
+#pragma unroll
+    for (int q = 0; q < 4; q++) xd[q] = D4(x[q]);
+#pragma unroll
+    for (int q = 0; q < 12; q++) thd[q] = D4(th[q]);
+    pmhd_map(m, ph, dtc, D4::var(ca, 0), D4::var(ce, 1), xd, thd, E, Po, Uo);
+#pragma unroll
+    for (int jj = 0; jj < 2; jj++) {
+      double s = 0.0;
+#pragma unroll
+      for (int kk = 0; kk < 4; kk++) s -= mu[kk] * E[kk].d[jj];
+      gchi[jj * C.Ntot + c] += s;
+    }
+  }
 }
 
 __global__ void LB(64) k_adj_implicit(Ctx C, double scale, const double* __restrict__ dt_dev,
@@ -234,8 +250,10 @@ __global__ void LB(64) k_adj_implicit(Ctx C, double scale, const double* __restr
                                       const double* __restrict__ chi_abs,
                                       const double* __restrict__ chi_es,
                                       const double* __restrict__ lamP,
-                                      const double* __restrict__ lamU, double* __restrict__ lamUe) {
-  adj_implicit_at(C, scale, dt_dev, Ue, Pk, status, chi_abs, chi_es, lamP, lamU, lamUe, (long)blockIdx.x * blockDim.x + threadIdx.x);
+                                      const double* __restrict__ lamU, double* __restrict__ lamUe,
+                                      double* __restrict__ gchi) {
+  adj_implicit_at(C, scale, dt_dev, Ue, Pk, status, chi_abs, chi_es, lamP, lamU, lamUe, gchi,
+                  (long)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -424,7 +442,8 @@ DEV void adj_flux_at(Ctx C, FaceRange R, double scale,
                                                  const double* __restrict__ chi_es,
                                                  const double* __restrict__ lamUe,
                                                  const double* __restrict__ lamE,
-                                                 double* __restrict__ G, long t) {
+                                                 double* __restrict__ G, double* __restrict__ Gx,
+                                                 long t) {
   if (t >= R.total) return;
   const int i = R.lo[0] + t % R.cnt[0];
   const long t2 = t / R.cnt[0];
@@ -504,6 +523,36 @@ DEV void adj_flux_at(Ctx C, FaceRange R, double scale,
 #pragma unroll
     for (int jj = 0; jj < 4; jj++) lPLR[4 * pass + jj] = acc[jj];
   }
+  if (Gx) {   // the total opacities of the two face cells (radiation speed limiter)
+    D4 in[24];
+#pragma unroll
+    for (int q = 0; q < 24; q++) in[q] = D4(PLR[q]);
+    const D4 xL = D4::var(chiL.v, 0), xR = D4::var(chiR.v, 1);
+    FaceState<D4> L, Rs;
+    face_state(C, m, D, in, xL, L);
+    face_state(C, m, D, in + 12, xR, Rs);
+    const D4 zero(0.0);
+    const D4 gmin = -fmin(zero, fmin(L.gm, Rs.gm)), gmax = fmax(zero, fmax(L.gp, Rs.gp));
+    const D4 rmin = -fmin(zero, fmin(L.rm, Rs.rm)), rmax = fmax(zero, fmax(L.rp, Rs.rp));
+    double acc[2] = {0.0, 0.0};
+#pragma unroll
+    for (int q = 0; q < 12; q++) {
+      if (q == 4 + D) continue;
+      const D4 vmin = q < 8 ? gmin : rmin, vmax = q < 8 ? gmax : rmax;
+      D4 fl;
+      if (C.flux == GRRMHD_FLUX_HLL) {
+        const D4 den = vmin + vmax;
+        fl = (den.v > 0.0) ? (vmin * Rs.F[q] + vmax * L.F[q] - vmin * vmax * (Rs.U[q] - L.U[q])) / den
+                           : 0.5 * (L.F[q] + Rs.F[q]);
+      } else {
+        fl = 0.5 * (Rs.F[q] + L.F[q] - fmax(vmin, vmax) * (Rs.U[q] - L.U[q]));
+      }
+      acc[0] += lF[q] * fl.d[0];
+      acc[1] += lF[q] * fl.d[1];
+    }
+    Gx[f] = acc[0];              // d/d chi_tot of cell f - e_d
+    Gx[C.Ntot + f] = acc[1];     // d/d chi_tot of cell f
+  }
   // MC reconstruction, per primitive, with respect to the four stencil cells
 #pragma unroll
   for (int q = 0; q < 12; q++) {
@@ -526,9 +575,11 @@ __global__ void __launch_bounds__(64) k_adj_flux(Ctx C, FaceRange R, double scal
                                                  const double* __restrict__ chi_es,
                                                  const double* __restrict__ lamUe,
                                                  const double* __restrict__ lamE,
-                                                 double* __restrict__ G) {
-  adj_flux_at<D>(C, R, scale, dt_dev, P, chi_abs, chi_es, lamUe, lamE, G, (long)blockIdx.x * blockDim.x + threadIdx.x);
+                                                 double* __restrict__ G, double* __restrict__ Gx) {
+  adj_flux_at<D>(C, R, scale, dt_dev, P, chi_abs, chi_es, lamUe, lamE, G, Gx,
+                 (long)blockIdx.x * blockDim.x + threadIdx.x);
 }
+
 
 // ---------------------------------------------------------------------------
 // Per allocated cell: gather the stencil products of the faces that read it
@@ -607,6 +658,36 @@ __global__ void LB(128) k_adj_gather(Ctx C, FaceRanges FR, double scale,
                                      const double* __restrict__ G1, const double* __restrict__ G2,
                                      const double* __restrict__ G3, double* __restrict__ lamPb) {
   adj_gather_at(C, FR, scale, dt_dev, P, lamUe, G1, G2, G3, lamPb, (long)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// Opacity cotangents through the fluxes: per allocated cell, the faces that
+// read its total opacity (as left cell of face c + e_d, right cell of face c);
+// chi_abs and chi_es receive the same amount.  Gx_d: [2][Ntot] per direction.
+__global__ void LB(256) k_adj_gather_chi(Ctx C, FaceRanges FR, const double* __restrict__ Gx1,
+                                         const double* __restrict__ Gx2,
+                                         const double* __restrict__ Gx3,
+                                         double* __restrict__ gchi) {
+  const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= C.Ntot) return;
+  int idx[3];
+  idx[0] = c % C.N[0];
+  idx[1] = (c / C.N[0]) % C.N[1];
+  idx[2] = c / ((long)C.N[0] * C.N[1]);
+  double acc = 0.0;
+  for (int d = 0; d < 3; d++) {
+    if (C.n[d] == 1) continue;
+    const double* Gx = (d == 0) ? Gx1 : ((d == 1) ? Gx2 : Gx3);
+    const FaceRange& R = FR.r[d];
+    bool trans = true;
+    for (int e = 0; e < 3; e++)
+      if (e != d && (idx[e] < R.lo[e] || idx[e] >= R.lo[e] + R.cnt[e])) trans = false;
+    if (!trans) continue;
+    const int up = idx[d] + 1;   // face c + e_d: c is its left cell
+    if (up >= R.lo[d] && up < R.lo[d] + R.cnt[d]) acc += Gx[c + C.st[d]];
+    if (idx[d] >= R.lo[d] && idx[d] < R.lo[d] + R.cnt[d]) acc += Gx[C.Ntot + c];
+  }
+  gchi[c] += acc;
+  gchi[C.Ntot + c] += acc;
 }
 
 // ---------------------------------------------------------------------------

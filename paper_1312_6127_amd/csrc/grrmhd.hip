@@ -776,7 +776,7 @@ extern "C" int grrmhd_step(grrmhd_grid* g, double* P, double* U, const double* c
 // ---------------------------------------------------------------------------
 struct AdjLayout {
   size_t F, emf, vch, scr, err, it, Un, Pb, Ue, Pk, Uk, stk, lamP, lamU, lamUe, lamUn, lamPb, lamE,
-      G, Lam, lamPpre, lamUpre, total;
+      G, Gx, Lam, lamPpre, lamUpre, total;
 };
 
 static AdjLayout adj_layout(const Ctx& C) {
@@ -807,6 +807,7 @@ static AdjLayout adj_layout(const Ctx& C) {
   w.lamPb = take(D8 * 12 * N);
   w.lamE = take(D8 * 3 * N);
   w.G = take(D8 * 3 * 48 * N);  // per direction: face products with the 4 stencil cells
+  w.Gx = take(D8 * 3 * 2 * N);  // per direction: face products with the 2 face cells' opacity
   w.Lam = take(D8 * 12 * N);
   w.lamPpre = take(D8 * 12 * N);
   w.lamUpre = take(D8 * 12 * N);
@@ -827,23 +828,27 @@ static int fill_d(grrmhd_grid* g, double* p, size_t n, double v) {
 
 // lamUe (all cells; zero outside the interior) from the cotangents of the
 // implicit solve's outputs
+// gchi (nullable, [2][N]): the opacity cotangents are added to it
 static int adj_implicit(grrmhd_grid* g, double scale, const double* dt_dev, const double* Ue,
                         const double* Pk, const int* st, const double* ca, const double* ce,
-                        const double* lamP, const double* lamU, double* lamUe) {
+                        const double* lamP, const double* lamU, double* lamUe,
+                        double* gchi = nullptr) {
   const Ctx& C = g->C;
   int rc;
   if ((rc = fill_d(g, lamUe, 12 * (size_t)C.Ntot, 0.0))) return rc;
   hipLaunchKernelGGL(k_adj_implicit, dim3(nblocks(n_interior(C), 64)), dim3(64), 0, g->stream, C,
-                     scale, dt_dev, Ue, Pk, st, ca, ce, lamP, lamU, lamUe);
+                     scale, dt_dev, Ue, Pk, st, ca, ce, lamP, lamU, lamUe, gchi);
   LAUNCHCHK();
   return 0;
 }
 
 // lamPb (every allocated cell) = (d Ue / d Pb)^T lamUe through the fluxes,
 // EMFs and geometric source of a stage with coefficient `scale` on dt
+// Gx, gchi (nullable together): opacity face products and the cotangents
+// they add to gchi [2][N]
 static int adj_explicit(grrmhd_grid* g, double scale, const double* dt_dev, const double* Pb,
                         const double* ca, const double* ce, const double* lamUe, double* lamE,
-                        double* G, double* lamPb) {
+                        double* G, double* lamPb, double* Gx = nullptr, double* gchi = nullptr) {
   const Ctx& C = g->C;
   const size_t N = (size_t)C.Ntot;
   hipStream_t s = g->stream;
@@ -865,19 +870,25 @@ static int adj_explicit(grrmhd_grid* g, double scale, const double* dt_dev, cons
     const dim3 gr(nblocks(R.total, 64)), bl(64);
     if (d == 0)
       hipLaunchKernelGGL(k_adj_flux<1>, gr, bl, 0, s, C, R, scale, dt_dev, Pb, ca, ce, lamUe,
-                         (const double*)lamE, Gd);
+                         (const double*)lamE, Gd, Gx ? Gx + (size_t)d * 2 * N : nullptr);
     if (d == 1)
       hipLaunchKernelGGL(k_adj_flux<2>, gr, bl, 0, s, C, R, scale, dt_dev, Pb, ca, ce, lamUe,
-                         (const double*)lamE, Gd);
+                         (const double*)lamE, Gd, Gx ? Gx + (size_t)d * 2 * N : nullptr);
     if (d == 2)
       hipLaunchKernelGGL(k_adj_flux<3>, gr, bl, 0, s, C, R, scale, dt_dev, Pb, ca, ce, lamUe,
-                         (const double*)lamE, Gd);
+                         (const double*)lamE, Gd, Gx ? Gx + (size_t)d * 2 * N : nullptr);
     LAUNCHCHK();
   }
   hipLaunchKernelGGL(k_adj_gather, dim3(nblocks(C.Ntot, 128)), dim3(128), 0, s, C, FR, scale, dt_dev,
                      Pb, lamUe, (const double*)G, (const double*)(G + 48 * N),
                      (const double*)(G + 96 * N), lamPb);
   LAUNCHCHK();
+  if (Gx && gchi) {
+    hipLaunchKernelGGL(k_adj_gather_chi, dim3(nblocks(C.Ntot, 256)), dim3(256), 0, s, C, FR,
+                       (const double*)Gx, (const double*)(Gx + 2 * N), (const double*)(Gx + 4 * N),
+                       gchi);
+    LAUNCHCHK();
+  }
   return 0;
 }
 
@@ -935,8 +946,9 @@ extern "C" int grrmhd_bc_vjp(grrmhd_grid* g, double* gP) {
 
 extern "C" int grrmhd_step_adjoint(grrmhd_grid* g, const double* P_n, const double* chi_abs,
                                    const double* chi_es, const double* dt_dev,
-                                   const double* gU_next, double* gP_n, double* P_next,
-                                   double* U_next, void* workspace, size_t ws_bytes) {
+                                   const double* gU_next, double* gP_n, double* g_chi,
+                                   double* P_next, double* U_next, void* workspace,
+                                   size_t ws_bytes) {
   NEEDG();
   if (!P_n || !chi_abs || !chi_es || !dt_dev || !gU_next || !gP_n || !workspace)
     return fail(GRRMHD_EINVAL, "NULL array");
@@ -967,6 +979,7 @@ extern "C" int grrmhd_step_adjoint(grrmhd_grid* g, const double* P_n, const doub
   double* lamPb = (double*)(base + w.lamPb);
   double* lamE = (double*)(base + w.lamE);
   double* G = (double*)(base + w.G);
+  double* Gx = g_chi ? (double*)(base + w.Gx) : nullptr;
   double* Lam = (double*)(base + w.Lam);
   double* lamPpre = (double*)(base + w.lamPpre);
   double* lamUpre = (double*)(base + w.lamUpre);
@@ -1004,6 +1017,7 @@ extern "C" int grrmhd_step_adjoint(grrmhd_grid* g, const double* P_n, const doub
   hipLaunchKernelGGL(k_copy_interior, dim3(ga), dim3(256), 0, s, C, gU_next, lamU);
   LAUNCHCHK();
   if ((rc = fill_d(g, lamP, N12, 0.0)) || (rc = fill_d(g, lamUn, N12, 0.0))) return rc;
+  if (g_chi && (rc = fill_d(g, g_chi, 2 * N, 0.0))) return rc;
   for (int k = 2; k >= 0; k--) {
     const double* Pin = Pb + k * N12;
     // fix-up of failed cells, then the implicit solve
@@ -1015,12 +1029,14 @@ extern "C" int grrmhd_step_adjoint(grrmhd_grid* g, const double* P_n, const doub
                        (const double*)Lam, (const double*)lamP, (const double*)lamU, lamPpre, lamUpre);
     LAUNCHCHK();
     if ((rc = adj_implicit(g, Cc[k], dt_dev, Ue + k * N12, Pk + k * N12, stk + k * N, chi_abs,
-                           chi_es, lamPpre, lamUpre, lamUe)))
+                           chi_es, lamPpre, lamUpre, lamUe, g_chi)))
       return rc;
     hipLaunchKernelGGL(k_adj_stage, dim3(gi), dim3(256), 0, s, C, A[k], B[k], (const double*)lamUe,
                        lamUn, lamU);
     LAUNCHCHK();
-    if ((rc = adj_explicit(g, Cc[k], dt_dev, Pin, chi_abs, chi_es, lamUe, lamE, G, lamPb))) return rc;
+    if ((rc = adj_explicit(g, Cc[k], dt_dev, Pin, chi_abs, chi_es, lamUe, lamE, G, lamPb, Gx,
+                           g_chi)))
+      return rc;
     if ((rc = adj_bc(g, lamPb))) return rc;
     hipLaunchKernelGGL(k_copy_interior, dim3(ga), dim3(256), 0, s, C, (const double*)lamPb, lamP);
     LAUNCHCHK();

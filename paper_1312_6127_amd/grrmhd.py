@@ -101,7 +101,7 @@ def lib():
             "grrmhd_step": (C.c_int, [_VP, _VP, _VP, _VP, _VP, _VP, C.c_int, _VP, _VP, _VP,
                                       C.c_size_t]),
             "grrmhd_adjoint_workspace_bytes": (C.c_size_t, [_VP]),
-            "grrmhd_step_adjoint": (C.c_int, [_VP] * 10 + [C.c_size_t]),
+            "grrmhd_step_adjoint": (C.c_int, [_VP] * 11 + [C.c_size_t]),
             "grrmhd_implicit_vjp": (C.c_int, [_VP, _VP, _VP, _VP, C.c_double] + [_VP] * 6),
             "grrmhd_explicit_vjp_workspace_bytes": (C.c_size_t, [_VP]),
             "grrmhd_explicit_vjp": (C.c_int, [_VP, C.c_double] + [_VP] * 7 + [C.c_size_t]),
@@ -244,18 +244,22 @@ class Grid:
             self._aws = (raw[off:off + nb], nb)
         return self._aws
 
-    def step_adjoint(self, P, chi_abs, chi_es, dt, gU, want_next=False):
+    def step_adjoint(self, P, chi_abs, chi_es, dt, gU, want_next=False, want_chi=False):
         """dL/dP^n for L = sum(gU * U^{n+1}(P^n)), dt (1-element device
-        tensor) held fixed and U^n = U(P^n).  Returns gP, or (gP, P^{n+1},
-        U^{n+1}) with want_next."""
+        tensor) held fixed and U^n = U(P^n).  Returns gP, then with want_chi
+        the [2][N] opacity gradient (d/dchi_abs, d/dchi_es), then with
+        want_next P^{n+1} and U^{n+1}."""
         self._sync_stream()
         ws, nb = self.adjoint_workspace()
         gP = torch.empty_like(P)
+        gc = torch.empty((2, self.N), dtype=P.dtype, device=P.device) if want_chi else None
         Pn = torch.empty_like(P) if want_next else None
         Un = torch.empty_like(P) if want_next else None
         _check(lib().grrmhd_step_adjoint(self.h, _ptr(P), _ptr(chi_abs), _ptr(chi_es), _ptr(dt),
-                                         _ptr(gU), _ptr(gP), _ptr(Pn), _ptr(Un), _ptr(ws), nb))
-        return (gP, Pn, Un) if want_next else gP
+                                         _ptr(gU), _ptr(gP), _ptr(gc), _ptr(Pn), _ptr(Un),
+                                         _ptr(ws), nb))
+        out = (gP,) + ((gc,) if want_chi else ()) + ((Pn, Un) if want_next else ())
+        return out if len(out) > 1 else gP
 
     def implicit_vjp(self, Uexp, P_out, status, dt_scale, dt, chi_abs, chi_es, gP, gU):
         self._sync_stream()
@@ -390,7 +394,8 @@ class GRRMHDStep(torch.autograd.Function):
     library's hand-written adjoint (grrmhd_step_adjoint).
 
     GRRMHDStep.apply(grid, P, chi_abs, chi_es, dt) -> U_next; the backward
-    returns dL/dP at interior cells (ghost entries zero)."""
+    returns dL/dP at interior cells (ghost entries zero) and, where they
+    require it, dL/dchi_abs and dL/dchi_es at every allocated cell."""
 
     @staticmethod
     def forward(ctx, grid, P, chi_abs, chi_es, dt):
@@ -405,5 +410,10 @@ class GRRMHDStep(torch.autograd.Function):
     @staticmethod
     def backward(ctx, gU):
         Pc, chi_abs, chi_es, dt = ctx.saved_tensors
-        gP = ctx.grid.step_adjoint(Pc, chi_abs, chi_es, dt, gU.contiguous())
-        return None, gP, None, None, None
+        want = ctx.needs_input_grad[2] or ctx.needs_input_grad[3]
+        if not want:
+            gP = ctx.grid.step_adjoint(Pc, chi_abs, chi_es, dt, gU.contiguous())
+            return None, gP, None, None, None
+        gP, gc = ctx.grid.step_adjoint(Pc, chi_abs, chi_es, dt, gU.contiguous(), want_chi=True)
+        return (None, gP, gc[0] if ctx.needs_input_grad[2] else None,
+                gc[1] if ctx.needs_input_grad[3] else None, None)
