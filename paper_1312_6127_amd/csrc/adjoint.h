@@ -429,6 +429,118 @@ __global__ void LB(256) k_adj_emf(Ctx C, int a, FaceRange R, double scale,
   adj_emf_at(C, a, R, scale, dt_dev, lamUe, lamE, (long)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
+// A face state reduced to what the flux cotangent needs: the sums
+// sum_q lF[q] U_q and sum_q lF[q] F_q over the gas components (q < 8, the
+// normal field left out) and over the radiation components (q >= 8), and
+// the four characteristic speeds.  The flux is linear in U and F once the
+// speeds are fixed, so these sums carry all of it.
+template <class T>
+struct FaceSums {
+  T gU, gF, rU, rF;
+  T gm, gp, rm, rp;
+};
+
+template <class T>
+DEV void face_sums(const Ctx& C, const Metric& m, int d, const T* P, T chi_tot, const double lF[12],
+                   FaceSums<T>& o) {
+  Gas<T> s;
+  make_gas(m, C.gam, P[0], P[1], P + 2, P + 5, s);
+  T row[8];
+  T acc;
+  gas_row(s, P + 5, 0, row);
+  acc = T(0.0);
+#pragma unroll
+  for (int q = 0; q < 8; q++)
+    if (q != 4 + d) acc = acc + lF[q] * row[q];
+  o.gU = m.gdet * acc;
+  gas_row(s, P + 5, d, row);
+  acc = T(0.0);
+#pragma unroll
+  for (int q = 0; q < 8; q++)
+    if (q != 4 + d) acc = acc + lF[q] * row[q];
+  o.gF = m.gdet * acc;
+  Vel<T> r;
+  make_vel(m, P + 9, r);
+  T rr[4];
+  rad_row(r, P[8], 0, rr);
+  acc = T(0.0);
+#pragma unroll
+  for (int q = 0; q < 4; q++) acc = acc + lF[8 + q] * rr[q];
+  o.rU = m.gdet * acc;
+  rad_row(r, P[8], d, rr);
+  acc = T(0.0);
+#pragma unroll
+  for (int q = 0; q < 4; q++) acc = acc + lF[8 + q] * rr[q];
+  o.rF = m.gdet * acc;
+  face_speeds(C, m, d, P, chi_tot, s, r, o.gm, o.gp, o.rm, o.rp);
+}
+
+// The contracted Riemann flux sum_q lF[q] flux_q of one face (HLL or LAXF,
+// as the forward step), its derivative carried by whichever side is a Dual,
+// the other side a constant.  Speed extrema take their operands in the
+// forward order, so a tie between the two sides takes the forward branch.
+template <int N, class TL, class TR>
+DEV void flux_contract(const Ctx& C, const FaceSums<TL>& L, const FaceSums<TR>& R, double acc[N]) {
+  typedef Dual<N> T;
+  const T gmin = -fmin(0.0, fmin(L.gm, R.gm)), gmax = fmax(0.0, fmax(L.gp, R.gp));
+  const T rmin = -fmin(0.0, fmin(L.rm, R.rm)), rmax = fmax(0.0, fmax(L.rp, R.rp));
+  T fl[2];
+#pragma unroll
+  for (int grp = 0; grp < 2; grp++) {
+    const T vmin = grp ? rmin : gmin, vmax = grp ? rmax : gmax;
+    const TL LU = grp ? L.rU : L.gU, LF = grp ? L.rF : L.gF;
+    const TR RU = grp ? R.rU : R.gU, RF = grp ? R.rF : R.gF;
+    if (C.flux == GRRMHD_FLUX_HLL) {
+      const T den = vmin + vmax;
+      fl[grp] = (den.v > 0.0) ? (vmin * RF + vmax * LF - vmin * vmax * (RU - LU)) / den
+                              : 0.5 * (LF + RF);
+    } else {
+      fl[grp] = 0.5 * (RF + LF - fmax(vmin, vmax) * (RU - LU));
+    }
+  }
+#pragma unroll
+  for (int jj = 0; jj < N; jj++) acc[jj] = fl[0].d[jj] + fl[1].d[jj];
+}
+
+// One side S (0 left, 1 right) of a face: its 12 reconstructed primitives
+// seeded four at a time with the other side's state held fixed, giving
+// lS[q] = sum_p lF[p] d(flux_p)/d(P_S[q]); with gx, also the derivative with
+// respect to side S's total opacity (radiation speed limiter).
+template <int S>
+DEV void adj_face_side(const Ctx& C, const Metric& m, int D, const double PLR[24], double chiL,
+                       double chiR, const double lF[12], double lS[12], double* gx) {
+  const double* own = PLR + 12 * S;
+  const double chi_own = S ? chiR : chiL;
+  FaceSums<double> O;
+  face_sums(C, m, D, PLR + 12 * (1 - S), S ? chiL : chiR, lF, O);
+  for (int g = 0; g < 3; g++) {
+    D4 in[12];
+    seed4<12>(own, 4 * g, in);
+    FaceSums<D4> F;
+    face_sums(C, m, D, in, D4(chi_own), lF, F);
+    double acc[4];
+    if (S == 0)
+      flux_contract<4>(C, F, O, acc);
+    else
+      flux_contract<4>(C, O, F, acc);
+#pragma unroll
+    for (int q = 0; q < 12; q++) lS[q] = (q / 4 == g) ? acc[q % 4] : lS[q];
+  }
+  if (gx) {
+    Dual<1> in[12];
+#pragma unroll
+    for (int q = 0; q < 12; q++) in[q] = Dual<1>(own[q]);
+    FaceSums<Dual<1>> F;
+    face_sums(C, m, D, in, Dual<1>::var(chi_own, 0), lF, F);
+    double acc[1];
+    if (S == 0)
+      flux_contract<1>(C, F, O, acc);
+    else
+      flux_contract<1>(C, O, F, acc);
+    *gx = acc[0];
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Faces normal to D: the cotangent of the face flux, then its Jacobian with
 // respect to the four stencil cells c-2s, c-s, c, c+s (s the stride along
@@ -474,89 +586,32 @@ DEV void adj_flux_at(Ctx C, FaceRange R, double scale,
       lF[q] = direct;
     }
   }
-  double sten[4][12];
-#pragma unroll
-  for (int q = 0; q < 12; q++) {
-    const double* p = P + q * C.Ntot;
-    sten[0][q] = p[f - 2 * st];
-    sten[1][q] = p[f - st];
-    sten[2][q] = p[f];
-    sten[3][q] = p[f + st];
-  }
   double PLR[24];
 #pragma unroll
   for (int q = 0; q < 12; q++) {
-    const double a = sten[0][q], b = sten[1][q], e = sten[2][q], ff = sten[3][q];
+    const double* p = P + q * C.Ntot;
+    const double a = p[f - 2 * st], b = p[f - st], e = p[f], ff = p[f + st];
     PLR[q] = b + 0.5 * mc_slope(b - a, e - b);
     PLR[12 + q] = e - 0.5 * mc_slope(e - b, ff - e);
   }
   Metric m;
   const double* tab = (D == 1) ? C.geo_f1 : ((D == 2) ? C.geo_f2 : C.geo_c);
   load_metric(tab, C.npos, i + C.N[0] * j, m);
-  const D4 chiL(chi_abs[f - st] + chi_es[f - st]), chiR(chi_abs[f] + chi_es[f]);
+  const double chiL = chi_abs[f - st] + chi_es[f - st], chiR = chi_abs[f] + chi_es[f];
   double lPLR[24];
-  for (int pass = 0; pass < 6; pass++) {
-    D4 in[24];
-    seed4<24>(PLR, 4 * pass, in);
-    FaceState<D4> L, Rs;
-    face_state(C, m, D, in, chiL, L);
-    face_state(C, m, D, in + 12, chiR, Rs);
-    const D4 zero(0.0);
-    const D4 gmin = -fmin(zero, fmin(L.gm, Rs.gm)), gmax = fmax(zero, fmax(L.gp, Rs.gp));
-    const D4 rmin = -fmin(zero, fmin(L.rm, Rs.rm)), rmax = fmax(zero, fmax(L.rp, Rs.rp));
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int q = 0; q < 12; q++) {
-      if (q == 4 + D) continue;
-      const D4 vmin = q < 8 ? gmin : rmin, vmax = q < 8 ? gmax : rmax;
-      D4 fl;
-      if (C.flux == GRRMHD_FLUX_HLL) {
-        const D4 den = vmin + vmax;
-        fl = (den.v > 0.0) ? (vmin * Rs.F[q] + vmax * L.F[q] - vmin * vmax * (Rs.U[q] - L.U[q])) / den
-                           : 0.5 * (L.F[q] + Rs.F[q]);
-      } else {
-        fl = 0.5 * (Rs.F[q] + L.F[q] - fmax(vmin, vmax) * (Rs.U[q] - L.U[q]));
-      }
-#pragma unroll
-      for (int jj = 0; jj < 4; jj++) acc[jj] += lF[q] * fl.d[jj];
-    }
-#pragma unroll
-    for (int jj = 0; jj < 4; jj++) lPLR[4 * pass + jj] = acc[jj];
-  }
-  if (Gx) {   // the total opacities of the two face cells (radiation speed limiter)
-    D4 in[24];
-#pragma unroll
-    for (int q = 0; q < 24; q++) in[q] = D4(PLR[q]);
-    const D4 xL = D4::var(chiL.v, 0), xR = D4::var(chiR.v, 1);
-    FaceState<D4> L, Rs;
-    face_state(C, m, D, in, xL, L);
-    face_state(C, m, D, in + 12, xR, Rs);
-    const D4 zero(0.0);
-    const D4 gmin = -fmin(zero, fmin(L.gm, Rs.gm)), gmax = fmax(zero, fmax(L.gp, Rs.gp));
-    const D4 rmin = -fmin(zero, fmin(L.rm, Rs.rm)), rmax = fmax(zero, fmax(L.rp, Rs.rp));
-    double acc[2] = {0.0, 0.0};
-#pragma unroll
-    for (int q = 0; q < 12; q++) {
-      if (q == 4 + D) continue;
-      const D4 vmin = q < 8 ? gmin : rmin, vmax = q < 8 ? gmax : rmax;
-      D4 fl;
-      if (C.flux == GRRMHD_FLUX_HLL) {
-        const D4 den = vmin + vmax;
-        fl = (den.v > 0.0) ? (vmin * Rs.F[q] + vmax * L.F[q] - vmin * vmax * (Rs.U[q] - L.U[q])) / den
-                           : 0.5 * (L.F[q] + Rs.F[q]);
-      } else {
-        fl = 0.5 * (Rs.F[q] + L.F[q] - fmax(vmin, vmax) * (Rs.U[q] - L.U[q]));
-      }
-      acc[0] += lF[q] * fl.d[0];
-      acc[1] += lF[q] * fl.d[1];
-    }
-    Gx[f] = acc[0];              // d/d chi_tot of cell f - e_d
-    Gx[C.Ntot + f] = acc[1];     // d/d chi_tot of cell f
+  double gxL = 0.0, gxR = 0.0;
+  adj_face_side<0>(C, m, D, PLR, chiL, chiR, lF, lPLR, Gx ? &gxL : nullptr);
+  adj_face_side<1>(C, m, D, PLR, chiL, chiR, lF, lPLR + 12, Gx ? &gxR : nullptr);
+  if (Gx) {
+    Gx[f] = gxL;                 // d/d chi_tot of cell f - e_d
+    Gx[C.Ntot + f] = gxR;        // d/d chi_tot of cell f
   }
   // MC reconstruction, per primitive, with respect to the four stencil cells
+  // (the stencil is read again rather than held through the face passes)
 #pragma unroll
   for (int q = 0; q < 12; q++) {
-    const double v[4] = {sten[0][q], sten[1][q], sten[2][q], sten[3][q]};
+    const double* p = P + q * C.Ntot;
+    const double v[4] = {p[f - 2 * st], p[f - st], p[f], p[f + st]};
     D4 s[4];
     seed4<4>(v, 0, s);
     const D4 PL = s[1] + 0.5 * mc_slope(s[1] - s[0], s[2] - s[1]);

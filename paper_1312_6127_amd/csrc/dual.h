@@ -137,6 +137,23 @@ template <int N>
 GR_HD Dual<N> fmin(const Dual<N>& a, const Dual<N>& b) {
   return (a.v <= b.v || b.v != b.v) ? a : b;
 }
+// One operand constant: the same selection, the constant's derivative zero.
+template <int N>
+GR_HD Dual<N> fmax(const Dual<N>& a, double b) {
+  return (a.v >= b || b != b) ? a : Dual<N>(b);
+}
+template <int N>
+GR_HD Dual<N> fmax(double a, const Dual<N>& b) {
+  return (a >= b.v || b.v != b.v) ? Dual<N>(a) : b;
+}
+template <int N>
+GR_HD Dual<N> fmin(const Dual<N>& a, double b) {
+  return (a.v <= b || b != b) ? a : Dual<N>(b);
+}
+template <int N>
+GR_HD Dual<N> fmin(double a, const Dual<N>& b) {
+  return (a <= b.v || b.v != b.v) ? Dual<N>(a) : b;
+}
 // |a| with the sign of b
 template <int N>
 GR_HD Dual<N> copysign(const Dual<N>& a, const Dual<N>& b) {

@@ -239,12 +239,36 @@ struct FaceState {
   T gm, gp, rm, rp;   // gas and radiation characteristic speeds
 };
 
+// Characteristic speeds along d of one face state: gas (gm, gp) and
+// radiation (rm, rp).
+template <class T>
+DEV void face_speeds(const Ctx& C, const MetricT<typename RealOf<T>::type>& m, int d, const T* P,
+                     T chi_tot, const Gas<T>& s, const Vel<T>& r, T& gm, T& gp, T& rm, T& rp) {
+  using R = typename RealOf<T>::type;
+  // gas: fast magnetosonic speed c_ms^2 = v_A^2 + c_s^2 (1 - v_A^2)
+  const T w = s.rho + s.ug + s.pg;
+  const T cs2 = R(C.gam) * s.pg / w;
+  const T va2 = s.bsq / (w + s.bsq);
+  char_speeds(m, s.v.ucon, va2 + cs2 * (R(1.0) - va2), d, gm, gp);
+  // radiation: 1/sqrt(3) in the radiation frame, limited to 4/(3 tau) in the gas frame
+  char_speeds(m, r.ucon, T(R(1.0 / 3.0)), d, rm, rp);
+  const T tau = chi_tot * P[0] * sqrt(m.lo(d, d)) * R(C.dx[d - 1]);
+  if (val(tau) > R(0.0)) {
+    const T cl = R(4.0) / (R(3.0) * tau);
+    if (val(cl) < R(1.0)) {
+      T lm, lp;
+      char_speeds(m, s.v.ucon, cl * cl, d, lm, lp);
+      rp = fmin(rp, lp);
+      rm = fmax(rm, lm);
+    }
+  }
+}
+
 // T = double, float on the FP32 face path (metric rounded to float too), or
 // Dual<N> for the adjoint
 template <class T>
 DEV void face_state(const Ctx& C, const MetricT<typename RealOf<T>::type>& m, int d, const T* P,
                     T chi_tot, FaceState<T>& fs) {
-  using R = typename RealOf<T>::type;
   Gas<T> s;
   make_gas(m, C.gam, P[0], P[1], P + 2, P + 5, s);
   T row[8];
@@ -263,23 +287,7 @@ DEV void face_state(const Ctx& C, const MetricT<typename RealOf<T>::type>& m, in
   rad_row(r, P[8], d, rr);
 #pragma unroll
   for (int q = 0; q < 4; q++) fs.F[8 + q] = m.gdet * rr[q];
-  // gas: fast magnetosonic speed c_ms^2 = v_A^2 + c_s^2 (1 - v_A^2)
-  const T w = s.rho + s.ug + s.pg;
-  const T cs2 = R(C.gam) * s.pg / w;
-  const T va2 = s.bsq / (w + s.bsq);
-  char_speeds(m, s.v.ucon, va2 + cs2 * (R(1.0) - va2), d, fs.gm, fs.gp);
-  // radiation: 1/sqrt(3) in the radiation frame, limited to 4/(3 tau) in the gas frame
-  char_speeds(m, r.ucon, T(R(1.0 / 3.0)), d, fs.rm, fs.rp);
-  const T tau = chi_tot * P[0] * sqrt(m.lo(d, d)) * R(C.dx[d - 1]);
-  if (val(tau) > R(0.0)) {
-    const T cl = R(4.0) / (R(3.0) * tau);
-    if (val(cl) < R(1.0)) {
-      T lm, lp;
-      char_speeds(m, s.v.ucon, cl * cl, d, lm, lp);
-      fs.rp = fmin(fs.rp, lp);
-      fs.rm = fmax(fs.rm, lm);
-    }
-  }
+  face_speeds(C, m, d, P, chi_tot, s, r, fs.gm, fs.gp, fs.rm, fs.rp);
 }
 
 struct FaceRange {
