@@ -211,11 +211,25 @@ DEV void adj_implicit_at(Ctx C, double scale, const double* __restrict__ dt_dev,
     for (int q = 0; q < 12; q++) lamUe[q * C.Ntot + c] = lu[q];
     return;
   }
+  // passes over the 12 conserved inputs, four at a time; the values are kept
+  // opaque per pass (empty asm) so the compiler recomputes them rather than
+  // hoisting the whole value chain out of the loop and spilling it
+#pragma unroll 1
   for (int pass = 0; pass < 3; pass++) {
     D4 xd[4], thd[12], E[4], Po[12], Uo[12];
+    double xv[4], tv[12];
 #pragma unroll
-    for (int q = 0; q < 4; q++) xd[q] = D4(x[q]);
-    seed4<12>(th, 4 * pass, thd);
+    for (int q = 0; q < 4; q++) {
+      xv[q] = x[q];
+      asm volatile("" : "+v"(xv[q]));
+      xd[q] = D4(xv[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < 12; q++) {
+      tv[q] = th[q];
+      asm volatile("" : "+v"(tv[q]));
+    }
+    seed4<12>(tv, 4 * pass, thd);
     pmhd_map(m, ph, dtc, D4(ca), D4(ce), xd, thd, E, Po, Uo);
 #pragma unroll
     for (int jj = 0; jj < 4; jj++) {
@@ -230,9 +244,17 @@ DEV void adj_implicit_at(Ctx C, double scale, const double* __restrict__ dt_dev,
   if (gchi) {   // the opacities: they enter the residual only (kappa = chi rho0)
     D4 xd[4], thd[12], E[4], Po[12], Uo[12];
 #pragma unroll
-    for (int q = 0; q < 4; q++) xd[q] = D4(x[q]);
+    for (int q = 0; q < 4; q++) {
+      double v = x[q];
+      asm volatile("" : "+v"(v));
+      xd[q] = D4(v);
+    }
 #pragma unroll
-    for (int q = 0; q < 12; q++) thd[q] = D4(th[q]);
+    for (int q = 0; q < 12; q++) {
+      double v = th[q];
+      asm volatile("" : "+v"(v));
+      thd[q] = D4(v);
+    }
     pmhd_map(m, ph, dtc, D4::var(ca, 0), D4::var(ce, 1), xd, thd, E, Po, Uo);
 #pragma unroll
     for (int jj = 0; jj < 2; jj++) {
@@ -547,7 +569,11 @@ DEV void adj_face_side(const Ctx& C, const Metric& m, int D, const double PLR[24
   if (gx) {
     Dual<1> in[12];
 #pragma unroll
-    for (int q = 0; q < 12; q++) in[q] = Dual<1>(own[q]);
+    for (int q = 0; q < 12; q++) {
+      double v = own[q];
+      asm volatile("" : "+v"(v));
+      in[q] = Dual<1>(v);
+    }
     FaceSums<Dual<1>> F;
     face_sums(C, m, D, in, Dual<1>::var(chi_own, 0), lF, F);
     double acc[1];
