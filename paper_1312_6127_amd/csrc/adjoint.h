@@ -681,20 +681,19 @@ __global__ void __launch_bounds__(64) k_adj_flux(Ctx C, FaceRange R, double scal
 
 
 // ---------------------------------------------------------------------------
-// Per allocated cell: gather the stencil products of the faces that read it
-// and, at interior cells, add the geometric source's Jacobian; the result is
-// the cotangent of the stage's ghost-filled input primitives.
+// Per allocated cell: gather the stencil products of the faces that read it;
+// with the geometric source's Jacobian added at interior cells (a kernel of
+// its own, the next one), the result is the cotangent of the stage's
+// ghost-filled input primitives.  The gather is memory-bound and small in
+// registers, the source Jacobian the opposite, hence two kernels.
 // ---------------------------------------------------------------------------
 struct FaceRanges {
   FaceRange r[3];
 };
 
-DEV void adj_gather_at(Ctx C, FaceRanges FR, double scale,
-                                     const double* __restrict__ dt_dev,
-                                     const double* __restrict__ P,
-                                     const double* __restrict__ lamUe,
-                                     const double* __restrict__ G1, const double* __restrict__ G2,
-                                     const double* __restrict__ G3, double* __restrict__ lamPb, long c) {
+DEV void adj_gather_at(Ctx C, FaceRanges FR, const double* __restrict__ G1,
+                       const double* __restrict__ G2, const double* __restrict__ G3,
+                       double* __restrict__ lamPb, long c) {
   if (c >= C.Ntot) return;
   int idx[3];
   idx[0] = c % C.N[0];
@@ -719,44 +718,62 @@ DEV void adj_gather_at(Ctx C, FaceRanges FR, double scale,
       for (int q = 0; q < 12; q++) acc[q] += G[(slot * 12 + q) * C.Ntot + f];
     }
   }
-  const bool interior = idx[0] >= C.ng[0] && idx[0] < C.ng[0] + C.n[0] && idx[1] >= C.ng[1] &&
-                        idx[1] < C.ng[1] + C.n[1] && idx[2] >= C.ng[2] && idx[2] < C.ng[2] + C.n[2];
-  if (interior && C.metric != GRRMHD_MINKOWSKI) {
-    const int pos = idx[0] + C.N[0] * idx[1];
-    Metric m;
-    load_metric(C.geo_c, C.npos, pos, m);
-    double p[12], lu[12], dg[2][10];
-#pragma unroll
-    for (int q = 0; q < 12; q++) {
-      p[q] = P[q * C.Ntot + c];
-      lu[q] = lamUe[q * C.Ntot + c];
-    }
-    load_dg(C, pos, dg);
-    const double cdt = scale * (*dt_dev);
-    for (int pass = 0; pass < 3; pass++) {
-      D4 pd[12], S[12];
-      seed4<12>(p, 4 * pass, pd);
-      geom_source(m, dg, C.gam, pd, S);
-#pragma unroll
-      for (int jj = 0; jj < 4; jj++) {
-        double s = 0.0;
-#pragma unroll
-        for (int q = 0; q < 12; q++) s += lu[q] * S[q].d[jj];
-        acc[4 * pass + jj] += cdt * s;
-      }
-    }
-  }
 #pragma unroll
   for (int q = 0; q < 12; q++) lamPb[q * C.Ntot + c] = acc[q];
 }
 
-__global__ void LB(128) k_adj_gather(Ctx C, FaceRanges FR, double scale,
-                                     const double* __restrict__ dt_dev,
-                                     const double* __restrict__ P,
-                                     const double* __restrict__ lamUe,
-                                     const double* __restrict__ G1, const double* __restrict__ G2,
-                                     const double* __restrict__ G3, double* __restrict__ lamPb) {
-  adj_gather_at(C, FR, scale, dt_dev, P, lamUe, G1, G2, G3, lamPb, (long)blockIdx.x * blockDim.x + threadIdx.x);
+__global__ void LB(256) k_adj_gather(Ctx C, FaceRanges FR, const double* __restrict__ G1,
+                                     const double* __restrict__ G2, const double* __restrict__ G3,
+                                     double* __restrict__ lamPb) {
+  adj_gather_at(C, FR, G1, G2, G3, lamPb, (long)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// Interior cell t (curved metric): lamPb += c dt (dS/dP)^T lamUe, the
+// geometric source's Jacobian by Dual<4> passes over the 12 primitives.
+DEV void adj_geom_at(Ctx C, double scale, const double* __restrict__ dt_dev,
+                     const double* __restrict__ P, const double* __restrict__ lamUe,
+                     double* __restrict__ lamPb, long t) {
+  if (t >= (long)C.n[0] * C.n[1] * C.n[2]) return;
+  int i, j, k;
+  interior_cell(C, t, i, j, k);
+  const long c = cell_index(C, i, j, k);
+  const int pos = i + C.N[0] * j;
+  Metric m;
+  load_metric(C.geo_c, C.npos, pos, m);
+  double p[12], lu[12], dg[2][10];
+#pragma unroll
+  for (int q = 0; q < 12; q++) {
+    p[q] = P[q * C.Ntot + c];
+    lu[q] = lamUe[q * C.Ntot + c];
+  }
+  load_dg(C, pos, dg);
+  const double cdt = scale * (*dt_dev);
+  // values kept opaque per pass (empty asm), as in the face passes
+#pragma unroll 1
+  for (int pass = 0; pass < 3; pass++) {
+    D4 pd[12], S[12];
+    double pv[12];
+#pragma unroll
+    for (int q = 0; q < 12; q++) {
+      pv[q] = p[q];
+      asm volatile("" : "+v"(pv[q]));
+    }
+    seed4<12>(pv, 4 * pass, pd);
+    geom_source(m, dg, C.gam, pd, S);
+#pragma unroll
+    for (int jj = 0; jj < 4; jj++) {
+      double s = 0.0;
+#pragma unroll
+      for (int q = 0; q < 12; q++) s += lu[q] * S[q].d[jj];
+      lamPb[(4 * pass + jj) * C.Ntot + c] += cdt * s;
+    }
+  }
+}
+
+__global__ void LB(64) k_adj_geom(Ctx C, double scale, const double* __restrict__ dt_dev,
+                                  const double* __restrict__ P, const double* __restrict__ lamUe,
+                                  double* __restrict__ lamPb) {
+  adj_geom_at(C, scale, dt_dev, P, lamUe, lamPb, (long)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 // Opacity cotangents through the fluxes: per allocated cell, the faces that
@@ -792,24 +809,32 @@ __global__ void LB(256) k_adj_gather_chi(Ctx C, FaceRanges FR, const double* __r
 // ---------------------------------------------------------------------------
 // Transpose of the ghost fill along d: each ghost's cotangent is added to its
 // source cell (sign-flipped where the fill flips), then cleared.  One thread
-// per line along d handles both ends, so no two threads touch one cell.
+// per (quantity, line along d) handles both ends of its line, so every cell
+// a thread adds into or clears is its own (the polar shift maps lines one to
+// one); the lower transverse axis runs fastest for coalesced access.
 // ---------------------------------------------------------------------------
 DEV void adj_bc_at(Ctx C, int d, double* lam, long t) {
-  const int d1 = (d + 1) % 3, d2 = (d + 2) % 3;
+  const int e1 = (d == 0) ? 1 : 0, e2 = (d == 2) ? 1 : 2;
   const int ng = C.ng[d], n = C.n[d];
-  if (t >= (long)C.N[d1] * C.N[d2]) return;
-  const int a = t % C.N[d1];
-  const int b = t / C.N[d1];
+  const long lines = (long)C.N[e1] * C.N[e2];
+  if (t >= 12 * lines) return;
+  const int q = (int)(t / lines);
+  const long l = t - q * lines;
+  const int a = (int)(l % C.N[e1]);
+  const int b = (int)(l / C.N[e1]);
+  double* L = lam + (long)q * C.Ntot;
+  const bool odd = (q == 2 + d || q == 5 + d || q == 9 + d);   // components along d
   for (int side = 0; side < 2; side++) {
     const int bc = side ? C.bc_hi[d] : C.bc_lo[d];
+    const bool flip = odd && (bc == GRRMHD_BC_REFLECT || bc == GRRMHD_BC_POLAR);
     for (int m = 0; m < ng; m++) {
       int cd[3], sd[3];
       cd[d] = side ? ng + n + m : ng - 1 - m;
       if (bc == GRRMHD_BC_OUTFLOW) sd[d] = side ? ng + n - 1 : ng;
       else if (bc == GRRMHD_BC_PERIODIC) sd[d] = side ? ng + m : ng + n - 1 - m;
       else sd[d] = side ? ng + n - 1 - m : ng + m;
-      cd[d1] = sd[d1] = a;
-      cd[d2] = sd[d2] = b;
+      cd[e1] = sd[e1] = a;
+      cd[e2] = sd[e2] = b;
       if (bc == GRRMHD_BC_POLAR && d == 1 && C.n[2] > 1) {
         const int g3 = C.ng[2], n3 = C.n[2];
         if (sd[2] < g3 || sd[2] >= g3 + n3) continue;   // filled by the x3 pass
@@ -817,14 +842,9 @@ DEV void adj_bc_at(Ctx C, int d, double* lam, long t) {
       }
       const long dst = cell_index(C, cd[0], cd[1], cd[2]);
       const long src = cell_index(C, sd[0], sd[1], sd[2]);
-      const bool flip = (bc == GRRMHD_BC_REFLECT || bc == GRRMHD_BC_POLAR);
-#pragma unroll
-      for (int q = 0; q < 12; q++) {
-        double v = lam[q * C.Ntot + dst];
-        if (flip && (q == 2 + d || q == 5 + d || q == 9 + d)) v = -v;
-        lam[q * C.Ntot + src] += v;
-        lam[q * C.Ntot + dst] = 0.0;
-      }
+      const double v = L[dst];
+      L[src] += flip ? -v : v;
+      L[dst] = 0.0;
     }
   }
 }

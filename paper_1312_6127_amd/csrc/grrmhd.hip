@@ -879,10 +879,16 @@ static int adj_explicit(grrmhd_grid* g, double scale, const double* dt_dev, cons
                          (const double*)lamE, Gd, Gx ? Gx + (size_t)d * 2 * N : nullptr);
     LAUNCHCHK();
   }
-  hipLaunchKernelGGL(k_adj_gather, dim3(nblocks(C.Ntot, 128)), dim3(128), 0, s, C, FR, scale, dt_dev,
-                     Pb, lamUe, (const double*)G, (const double*)(G + 48 * N),
-                     (const double*)(G + 96 * N), lamPb);
+  hipLaunchKernelGGL(k_adj_gather, dim3(nblocks(C.Ntot, 256)), dim3(256), 0, s, C, FR,
+                     (const double*)G, (const double*)(G + 48 * N), (const double*)(G + 96 * N),
+                     lamPb);
   LAUNCHCHK();
+  if (C.metric != GRRMHD_MINKOWSKI) {
+    const long ncell = (long)C.n[0] * C.n[1] * C.n[2];
+    hipLaunchKernelGGL(k_adj_geom, dim3(nblocks(ncell, 64)), dim3(64), 0, s, C, scale, dt_dev, Pb,
+                       lamUe, lamPb);
+    LAUNCHCHK();
+  }
   if (Gx && gchi) {
     hipLaunchKernelGGL(k_adj_gather_chi, dim3(nblocks(C.Ntot, 256)), dim3(256), 0, s, C, FR,
                        (const double*)Gx, (const double*)(Gx + 2 * N), (const double*)(Gx + 4 * N),
@@ -897,8 +903,8 @@ static int adj_bc(grrmhd_grid* g, double* lam) {
   const Ctx& C = g->C;
   for (int d = 2; d >= 0; d--) {
     if (C.ng[d] == 0) continue;
-    const long lines = (long)C.N[(d + 1) % 3] * C.N[(d + 2) % 3];
-    hipLaunchKernelGGL(k_adj_bc, dim3(nblocks(lines, 256)), dim3(256), 0, g->stream, C, d, lam);
+    const long items = 12L * C.N[(d + 1) % 3] * C.N[(d + 2) % 3];   // (quantity, line)
+    hipLaunchKernelGGL(k_adj_bc, dim3(nblocks(items, 256)), dim3(256), 0, g->stream, C, d, lam);
     LAUNCHCHK();
   }
   return 0;
