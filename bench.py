@@ -17,8 +17,10 @@ per step and its error against the oracle's PPM steps.  roofline: the dominant k
 (the implicit kernel's first PMHD attempt), its average launch time from HIP
 events on its stream inside the timed region.  cpu_baseline: the FP64 oracle
 stepping the same workload on the host cores (bounded sample).
-implicit_batch (--batch-cells): the batched implicit solve in each
-execution form.
+adjoint: the adjoint of one FP64 step of the 96x48x24 Kerr-Schild disk
+(dt held fixed), its time per call next to the forward step's, and a
+directional-derivative check of it on the GPU.  implicit_batch
+(--batch-cells): the batched implicit solve in each execution form.
 """
 import argparse
 import json
@@ -45,7 +47,7 @@ STEP_BYTES_PER_ZONE = 1344
 # traffic is reported as null and the flop figure as stale.
 FLOPS_PER_TRIP = 1732.0
 HBM_BYTES_PER_LAUNCH = 159.5e6
-KERNEL_DIGEST = "edea756143859c32"
+KERNEL_DIGEST = "a2d22ab2739d85f8"
 
 
 def parse():
@@ -55,6 +57,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, nargs=3, default=[128, 64, 32])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint leg")
+    ap.add_argument("--adjoint-only", action="store_true", help="run only the adjoint leg")
     ap.add_argument("--imex-err-steps", type=int, default=3,
                     help="IMEX3 and PPM steps compared with the oracle's")
     ap.add_argument("--cpu-steps", type=int, default=20,
@@ -170,6 +174,77 @@ GROUPS = [(0,), (1,), (2, 3, 4), (5, 6, 7), (8,), (9, 10, 11)]
 FIELDS = ["rho", "u_g", "u1", "u2", "u3", "B1", "B2", "B3", "Ebar", "ur1", "ur2", "ur3"]
 
 
+def bench_adjoint(G, I, torch, dev, reps=5, warmup=2, h=1e-6):
+    """Adjoint of one FP64 RK3 step of the 96x48x24 Kerr-Schild disk, dt held
+    fixed (the forward step recomputed with its stage checkpoints, then the
+    reverse sweep): ms per call and the forward step's ms, both from HIP
+    events on the library's stream; and <gP, v> against the central
+    difference (L(P + h v) - L(P - h v)) / 2h of the GPU step, with
+    L = sum(gU . U^{n+1}), gU seeded normals on the interior cells and v
+    seeded normals on 256 of them, each component scaled by its magnitude."""
+    import numpy as np
+
+    n = (96, 48, 24)
+    pd, P, ca, ce = I.accretion_disk(n=n, seed=3)
+    P = I.jitter(P, 11)
+    g = G.Grid(pd)
+
+    def T(x):
+        return torch.tensor(np.ascontiguousarray(x), device=dev)
+
+    Pt, cat, cet = T(P), T(ca), T(ce)
+    dt = torch.zeros(1, dtype=torch.float64, device=dev)
+    Pw = Pt.clone()
+    Uw = g.prim_to_cons(Pw)
+    g.step(Pw, Uw, cat, cet, dt)
+    mask = np.zeros(I.nalloc(pd)[::-1], bool)
+    mask[I.interior(pd)] = True
+    mask = mask.reshape(-1)
+    r = np.random.default_rng(7)
+    w = np.zeros_like(P)
+    w[:, mask] = r.standard_normal((12, int(mask.sum())))
+    # direction: 256 random interior cells, each component scaled by its own
+    # magnitude (floor 1e-3 of the field's largest), so that h v is a small
+    # relative change everywhere
+    cells = r.choice(np.flatnonzero(mask), 256, replace=False)
+    big = np.abs(P[:, mask]).max(axis=1)[:, None]
+    v = np.zeros_like(P)
+    v[:, cells] = r.standard_normal((12, 256)) * np.maximum(np.abs(P[:, cells]), 1e-3 * big)
+    wt, vt = T(w), T(v)
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+
+    def timed(fn):
+        for _ in range(warmup):
+            fn()
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        e1.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    ms_adj = timed(lambda: g.step_adjoint(Pt, cat, cet, dt, wt))
+    ms_adj_chi = timed(lambda: g.step_adjoint(Pt, cat, cet, dt, wt, want_chi=True))
+    ms_fwd = timed(lambda: g.step(Pw, Uw, cat, cet, dt, dt_fixed=True))
+
+    def L(Pin):
+        Pq = Pin.clone()
+        Uq = g.prim_to_cons(Pq)
+        g.step(Pq, Uq, cat, cet, dt, dt_fixed=True)
+        return float((wt * Uq).sum())
+
+    gP = g.step_adjoint(Pt, cat, cet, dt, wt)
+    ad = float((gP * vt).sum())
+    fd = (L(Pt + h * vt) - L(Pt - h * vt)) / (2 * h)
+    g.close()
+    return {"grid": list(n), "ms_per_adjoint": ms_adj, "ms_per_adjoint_with_opacity_grad": ms_adj_chi,
+            "ms_forward_step": ms_fwd, "time_vs_forward": ms_adj / ms_fwd,
+            "directional_check": {"adjoint": ad, "central_difference": fd, "h": h,
+                                  "rel_diff": abs(ad - fd) / abs(fd)}}
+
+
 def field_errors(a, b):
     """Per-field max|a - b| over interior cells, relative to max|b| over the
     field (over the three components for vectors)."""
@@ -248,6 +323,9 @@ def main():
     if args.batch_only:
         print(json.dumps({"implicit_batch": bench_batch(G, I, torch, dev, args.batch_cells or (1 << 24))}))
         return
+    if args.adjoint_only:
+        print(json.dumps({"adjoint": bench_adjoint(G, I, torch, dev)}))
+        return
     if args.copy_probe_mb:
         src = torch.ones(args.copy_probe_mb * (1 << 20) // 8, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)
@@ -280,6 +358,10 @@ def main():
     print(f"ppm steps: {rpp['ms'] / args.steps:.3f} ms/step", file=sys.stderr, flush=True)
     ppm = {"value": zones * args.steps / (rpp["ms"] * 1e-3), "ms_per_step": rpp["ms"] / args.steps,
            "time_vs_mc": rpp["ms"] / r64["ms"]}
+
+    adj = None if args.no_adjoint else bench_adjoint(G, I, torch, dev)
+    if adj:
+        print(f"adjoint: {adj['ms_per_adjoint']:.3f} ms/call", file=sys.stderr, flush=True)
 
     # dominant kernel: the implicit kernel of each stage, timed with HIP events
     # on its stream inside the timed region
@@ -378,6 +460,7 @@ def main():
         "mixed_precision": mixed,
         "imex3": imex,
         "ppm": ppm,
+        "adjoint": adj,
         "roofline": roof,
         "cpu_baseline": cpu,
     }
