@@ -17,7 +17,7 @@ LIB = os.path.join(HERE, "liboracle.so")
 SOURCES = ["geom.c", "phys.c", "invert.c", "implicit.c", "step.c"]
 
 ST_PMHD, ST_URAD, ST_TYPE2_NEG, ST_BASIC, ST_C2P_FAIL, ST_FLOOR, ST_NOT_ACCEPT, ST_FAIL, \
-    ST_NO_GOOD_NB, ST_EXTREME = (1 << i for i in range(10))
+    ST_NO_GOOD_NB, ST_EXTREME, ST_COLD = (1 << i for i in range(11))
 
 _BC = {"outflow": 0, "periodic": 1, "reflect": 2, "polar": 3}
 _SCHEME = {"rk3": 0, "imex2": 1, "imex2b": 2, "imex3": 3}
@@ -47,7 +47,7 @@ class Params(C.Structure):
         ("max_iter", C.c_int), ("roundoff", C.c_int),
         ("rho_floor", C.c_double), ("u_floor", C.c_double), ("bsq_rho_max", C.c_double),
         ("bsq_u_max", C.c_double), ("u_rho_max", C.c_double), ("erad_floor", C.c_double),
-        ("scheme", C.c_int), ("recon", C.c_int),
+        ("scheme", C.c_int), ("recon", C.c_int), ("cold", C.c_int),
     ]
 
 
@@ -80,6 +80,7 @@ def params(d: dict) -> Params:
     p.roundoff = int(d["roundoff"])
     p.scheme = _SCHEME[d.get("scheme", "rk3")]
     p.recon = 1 if d.get("recon", "mc") == "ppm" else 0
+    p.cold = int(d.get("cold", 1))
     return p
 
 
@@ -108,6 +109,8 @@ def lib():
             "orc_rad_invert": (C.c_int, [PP, GP, _D, C.c_int, _D]),
             "orc_implicit_cell": (None, [PP, GP, _D, _D, C.c_double, C.c_double, C.c_double,
                                          _D, _D, C.POINTER(ImplicitInfo)]),
+            "orc_implicit_cold": (None, [PP, GP, _D, _D, C.c_double, C.c_double, C.c_double,
+                                         C.c_double, _D, _D, C.POINTER(ImplicitInfo)]),
             "orc_implicit_batch": (None, [PP, C.c_long, _D, _D, _D, _D, _D, _D, _D, _I, _I]),
             "orc_ncell_alloc": (C.c_long, [PP]),
             "orc_bc": (None, [PP, _D]),
@@ -235,6 +238,19 @@ def implicit_cell(pd, g, Ui, Pguess, dt, chi_abs, chi_es):
     info = ImplicitInfo()
     lib().orc_implicit_cell(C.byref(params(pd)), C.byref(g), _dp(Ui), _dp(Pg), dt, chi_abs,
                             chi_es, _dp(Po), _dp(Uo), C.byref(info))
+    return Po, Uo, info.status, info.iters, info.err
+
+
+def implicit_cold(pd, g, Ui, Pguess, dt, chi_abs, chi_es, u_c):
+    """The cold MHD solve alone: u_g held at u_c, the gas momentum equations
+    solved for u~^i."""
+    Ui = _f64(Ui)
+    Pg = _f64(Pguess)
+    Po = np.zeros(12)
+    Uo = np.zeros(12)
+    info = ImplicitInfo()
+    lib().orc_implicit_cold(C.byref(params(pd)), C.byref(g), _dp(Ui), _dp(Pg), dt, chi_abs,
+                            chi_es, u_c, _dp(Po), _dp(Uo), C.byref(info))
     return Po, Uo, info.status, info.iters, info.err
 
 

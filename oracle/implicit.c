@@ -32,6 +32,7 @@ typedef struct {
   double Tgi[4]; /* explicit gas  (T^t_t + rho u^t, T^t_i), per sqrt(-g) */
   double Ri[4];  /* explicit radiation R^t_nu, per sqrt(-g) */
   double dt, chi_abs, chi_es;
+  int cold; /* cold MHD: energy residuals left out of the errors */
 } ictx;
 
 typedef struct {
@@ -91,7 +92,7 @@ static void errors(const ictx *c, ieval *e) {
     eg[1 + i] = fabs(e->Eg[1 + i]) * w / Nsg;
     er[1 + i] = fabs(e->Er[1 + i]) * w / Nsr;
   }
-  if (e->radflags & 1) eg[0] = er[0] = 0.0; /* TYPE2 met E_rad <= 0: energy excluded */
+  if ((e->radflags & 1) || c->cold) eg[0] = er[0] = 0.0; /* TYPE2 met E_rad <= 0, or cold: energy excluded */
   double eT = 0.0, eIg = 0.0, eIr = 0.0;
   for (int m = 0; m < 4; m++) {
     eT += (eg[m] > er[m] ? eg[m] : er[m]);
@@ -326,23 +327,176 @@ static void newton(const ictx *c, int method, const double x0[4], const double *
   }
 }
 
+/* Cold MHD attempt (Sec. 4.7: when neither the energy nor the entropy
+ * equation has a solution, energy and entropy conservation are dropped).
+ * The gas internal energy is held at x0[0] and the three gas momentum
+ * equations are solved for u~^i with the PMHD residual, the radiation
+ * following from total energy-momentum conservation as in PMHD; the energy
+ * residuals are left out of e_T (c->cold).  Centred-difference Jacobian of
+ * the 3 momentum residuals in u~^i, the stopping rules of newton(). */
+static void newton_cold(const ictx *c, const double x0[4], ieval *best, int *iters) {
+  const orc_params *p = c->p;
+  double x[4];
+  memcpy(x, x0, sizeof(x));
+  ieval ev;
+  eval_pmhd(c, x, &ev);
+  *best = ev;
+  if (!ev.ok) return;
+  double hist[MAXH];
+  int nh = 0;
+  hist[nh++] = ev.eT;
+  int nrise = 0, extra = 0, conv = 0;
+  for (int it = 0; it < p->max_iter && nh < MAXH - 1; it++) {
+    if (ev.eT < p->tol_pmhd) conv = 1;
+    if (conv) {
+      if (!p->roundoff || extra >= 3) break;
+      extra++;
+    }
+    if (!conv && it >= 5) {
+      const double avg = (hist[nh - 5] + hist[nh - 4] + hist[nh - 3]) / 3.0;
+      if (ev.eT > 0.5 * avg) break;
+    }
+    const double delta = (ev.eIg < 1e-9) ? 1e-10 : 1e-8;
+    /* 4x4 system with u_g pinned: row 0 reads dx_0 = 0 */
+    double J[4][4] = {{1.0, 0.0, 0.0, 0.0}, {0.0}, {0.0}, {0.0}};
+    for (int j = 1; j < 4; j++) {
+      const double h = delta * (1.0 + fabs(x[j]));
+      double xp[4], xm[4];
+      memcpy(xp, x, sizeof(x));
+      memcpy(xm, x, sizeof(x));
+      xp[j] += h;
+      xm[j] -= h;
+      ieval ep, em;
+      eval_pmhd(c, xp, &ep);
+      eval_pmhd(c, xm, &em);
+      for (int i = 1; i < 4; i++) J[i][j] = (ep.Eg[i] - em.Eg[i]) / (2.0 * h);
+    }
+    const double res[4] = {0.0, ev.Eg[1], ev.Eg[2], ev.Eg[3]};
+    double dx[4];
+    if (solve4(J, res, dx)) break;
+    double xn[4];
+    for (int i = 0; i < 4; i++) xn[i] = x[i] - dx[i];
+    ieval en;
+    eval_pmhd(c, xn, &en);
+    (*iters)++;
+    int small = 1;
+    for (int i = 0; i < 4; i++)
+      if (fabs(xn[i] - x[i]) > 10.0 * EPS_M * fabs(x[i])) small = 0;
+    memcpy(x, xn, sizeof(x));
+    const double prev = hist[nh - 1];
+    ev = en;
+    hist[nh++] = ev.eT;
+    if (ev.ok && ev.eT < best->eT) *best = ev;
+    if (!ev.ok) break;
+    if (it >= 5 && ev.eT > prev) {
+      nrise++;
+      if (nrise >= 5) break;
+    }
+    if (small) break;
+  }
+}
+
+static void cell_context(const orc_params *p, const orc_geom *g, const double *Ui, double dt,
+                         double chi_abs, double chi_es, ictx *c) {
+  c->p = p;
+  c->g = g;
+  orc_spatial_gcon(g, c->gij);
+  const double gd = g->gdet;
+  c->rhout = Ui[0] / gd;
+  for (int i = 0; i < 3; i++) c->B[i] = Ui[5 + i] / gd;
+  for (int m = 0; m < 4; m++) {
+    c->Tgi[m] = Ui[1 + m] / gd;
+    c->Ri[m] = Ui[8 + m] / gd;
+  }
+  c->dt = dt;
+  c->chi_abs = chi_abs;
+  c->chi_es = chi_es;
+  c->cold = 0;
+}
+
+/* Outputs and status of an accepted (or best) solution of one method
+ * (Sec. 4.10-4.11): the iterated side's conserved quantities from the
+ * solution, the other side's from total conservation, the BASIC re-inversion
+ * where TYPE2 met E_rad <= 0, radiation recomputed where a limiter acted. */
+static int emit(const ictx *c, const ieval *best, int method, int status, const double *Ui,
+                double *Pout, double *Uout) {
+  const orc_params *p = c->p;
+  const orc_geom *g = c->g;
+  const double gd = g->gdet;
+  status |= (method == M_PMHD) ? ORC_ST_PMHD : ORC_ST_URAD;
+  if (best->eT > p->tol_fail) status |= ORC_ST_FAIL;
+  else if (best->eT > p->tol_accept) status |= ORC_ST_NOT_ACCEPT;
+  if (best->radflags & 1) status |= ORC_ST_TYPE2_NEG;
+  memcpy(Pout, best->P, sizeof(double) * 12);
+  double Ucons_rad[4], Ucons_gas[4];
+  for (int m = 0; m < 4; m++) {
+    if (method == M_PMHD) {
+      Ucons_gas[m] = best->Tg[m];
+      Ucons_rad[m] = c->Ri[m] - (best->Tg[m] - c->Tgi[m]);
+    } else {
+      Ucons_rad[m] = best->x[m];
+      Ucons_gas[m] = c->Tgi[m] - (best->x[m] - c->Ri[m]);
+    }
+  }
+  int rad_changed = (best->radflags != 0);
+  if (method == M_PMHD && (best->radflags & 1)) {
+    /* the accepted solution met E_rad < 0 under TYPE2: re-invert with BASIC */
+    double U[12];
+    memset(U, 0, sizeof(U));
+    for (int m = 0; m < 4; m++) U[8 + m] = gd * Ucons_rad[m];
+    orc_rad_invert(p, g, U, 0, Pout);
+    status |= ORC_ST_BASIC;
+    rad_changed = 1;
+  }
+  if (rad_changed) rad_cons(c, Pout, Ucons_rad);
+  Uout[0] = Ui[0];
+  for (int m = 0; m < 4; m++) {
+    Uout[1 + m] = gd * Ucons_gas[m];
+    Uout[8 + m] = gd * Ucons_rad[m];
+  }
+  for (int i = 0; i < 3; i++) Uout[5 + i] = Ui[5 + i];
+  if (!(Pout[1] > 0.0)) status |= ORC_ST_FAIL;
+  return status;
+}
+
+/* Cold MHD solve with u_g held at u_c, guess u~^i from Pguess; returns 0
+ * and fills the outputs (status bit ORC_ST_COLD in place of ORC_ST_PMHD)
+ * when e_T of the momentum equations is within tol_fail, 1 otherwise. */
+static int cold_cell(const ictx *c0, const double *Ui, const double *Pguess, double u_c,
+                     int status, double *Pout, double *Uout, orc_implicit_info *info) {
+  ictx c = *c0;
+  c.cold = 1;
+  const double x0[4] = {u_c, Pguess[2], Pguess[3], Pguess[4]};
+  ieval best;
+  int iters = 0;
+  newton_cold(&c, x0, &best, &iters);
+  info->iters += iters;
+  if (!best.ok || !(best.eT <= c.p->tol_fail)) return 1;
+  const int st = emit(&c, &best, M_PMHD, status, Ui, Pout, Uout);
+  info->status = (st & ~ORC_ST_PMHD) | ORC_ST_COLD;
+  info->err = best.eT;
+  return 0;
+}
+
+void orc_implicit_cold(const orc_params *p, const orc_geom *g, const double *Ui,
+                       const double *Pguess, double dt, double chi_abs, double chi_es, double u_c,
+                       double *Pout, double *Uout, orc_implicit_info *info) {
+  ictx c;
+  cell_context(p, g, Ui, dt, chi_abs, chi_es, &c);
+  info->iters = 0;
+  if (cold_cell(&c, Ui, Pguess, u_c, 0, Pout, Uout, info)) {
+    memcpy(Pout, Pguess, sizeof(double) * 12);
+    memcpy(Uout, Ui, sizeof(double) * 12);
+    info->status = ORC_ST_FAIL;
+    info->err = INFINITY;
+  }
+}
+
 void orc_implicit_cell(const orc_params *p, const orc_geom *g, const double *Ui,
                        const double *Pguess, double dt, double chi_abs, double chi_es,
                        double *Pout, double *Uout, orc_implicit_info *info) {
   ictx c;
-  c.p = p;
-  c.g = g;
-  orc_spatial_gcon(g, c.gij);
-  const double gd = g->gdet;
-  c.rhout = Ui[0] / gd;
-  for (int i = 0; i < 3; i++) c.B[i] = Ui[5 + i] / gd;
-  for (int m = 0; m < 4; m++) {
-    c.Tgi[m] = Ui[1 + m] / gd;
-    c.Ri[m] = Ui[8 + m] / gd;
-  }
-  c.dt = dt;
-  c.chi_abs = chi_abs;
-  c.chi_es = chi_es;
+  cell_context(p, g, Ui, dt, chi_abs, chi_es, &c);
   int status = 0, iters = 0;
 
   /* extreme radiation sub-dominance (Sec. 4.10): radiation energy, or the
@@ -409,52 +563,33 @@ void orc_implicit_cell(const orc_params *p, const orc_geom *g, const double *Ui,
     if (best.eT < (p->roundoff ? 10.0 * p->tol_pmhd : p->tol_accept)) break;
   }
 
-  memcpy(Pout, Pguess, sizeof(double) * 12);
-  for (int i = 0; i < 12; i++) Uout[i] = Ui[i];
+  /* status bits of the set-up (EXTREME, C2P_FAIL) */
+  const int status0 = status;
   if (best_method < 0) {
+    memcpy(Pout, Pguess, sizeof(double) * 12);
+    for (int i = 0; i < 12; i++) Uout[i] = Ui[i];
     status |= ORC_ST_FAIL;
-    info->status = status;
-    info->iters = iters;
     info->err = INFINITY;
-    return;
+  } else {
+    status = emit(&c, &best, best_method, status, Ui, Pout, Uout);
+    info->err = best.eT;
   }
-  status |= (best_method == M_PMHD) ? ORC_ST_PMHD : ORC_ST_URAD;
-  if (best.eT > p->tol_fail) status |= ORC_ST_FAIL;
-  else if (best.eT > p->tol_accept) status |= ORC_ST_NOT_ACCEPT;
-  if (best.radflags & 1) status |= ORC_ST_TYPE2_NEG;
-
-  memcpy(Pout, best.P, sizeof(double) * 12);
-  double Ucons_rad[4], Ucons_gas[4];
-  for (int m = 0; m < 4; m++) {
-    if (best_method == M_PMHD) {
-      Ucons_gas[m] = best.Tg[m];
-      Ucons_rad[m] = c.Ri[m] - (best.Tg[m] - c.Tgi[m]);
-    } else {
-      Ucons_rad[m] = best.x[m];
-      Ucons_gas[m] = c.Tgi[m] - (best.x[m] - c.Ri[m]);
-    }
-  }
-  int rad_changed = (best.radflags != 0);
-  if (best_method == M_PMHD && (best.radflags & 1)) {
-    /* the accepted solution met E_rad < 0 under TYPE2: re-invert with BASIC */
-    double U[12];
-    memset(U, 0, sizeof(U));
-    for (int m = 0; m < 4; m++) U[8 + m] = gd * Ucons_rad[m];
-    orc_rad_invert(p, g, U, 0, Pout);
-    status |= ORC_ST_BASIC;
-    rad_changed = 1;
-  }
-  if (rad_changed) rad_cons(&c, Pout, Ucons_rad);
-  Uout[0] = Ui[0];
-  for (int m = 0; m < 4; m++) {
-    Uout[1 + m] = gd * Ucons_gas[m];
-    Uout[8 + m] = gd * Ucons_rad[m];
-  }
-  for (int i = 0; i < 3; i++) Uout[5 + i] = Ui[5 + i];
-  if (!(Pout[1] > 0.0)) status |= ORC_ST_FAIL;
   info->status = status;
   info->iters = iters;
-  info->err = best.eT;
+  /* no energy solution: the cold MHD limit (the entropy equation, tried
+   * before it in the paper's cascade, needs an evolved entropy tracer that
+   * this step does not carry) */
+  if ((status & ORC_ST_FAIL) && p->cold && p->u_floor > 0.0) {
+    double Pc[12], Uc[12];
+    orc_implicit_info ic = *info;
+    if (cold_cell(&c, Ui, Pguess, p->u_floor, status0, Pc, Uc, &ic) == 0) {
+      memcpy(Pout, Pc, sizeof(Pc));
+      memcpy(Uout, Uc, sizeof(Uc));
+      *info = ic;
+    } else {
+      info->iters = ic.iters;
+    }
+  }
 }
 
 void orc_implicit_batch(const orc_params *p, long n, const double *Ui, const double *Pg,

@@ -44,7 +44,8 @@ enum {
   ORC_ST_NOT_ACCEPT = 1 << 6,  /* best e_T above the acceptance tolerance    */
   ORC_ST_FAIL = 1 << 7,        /* no solution: primitives neighbour-averaged */
   ORC_ST_NO_GOOD_NB = 1 << 8,  /* averaging found no good neighbour          */
-  ORC_ST_EXTREME = 1 << 9      /* radiation extremely sub-dominant: URAD first */
+  ORC_ST_EXTREME = 1 << 9,     /* radiation extremely sub-dominant: URAD first */
+  ORC_ST_COLD = 1 << 10        /* solution of the cold MHD limit (u_g held)   */
 };
 
 typedef struct {
@@ -66,6 +67,7 @@ typedef struct {
   double rho_floor, u_floor, bsq_rho_max, bsq_u_max, u_rho_max, erad_floor;
   int scheme;             /* ORC_RK3, ORC_IMEX2, ORC_IMEX2B, ORC_IMEX3         */
   int recon;              /* ORC_RECON_MC or ORC_RECON_PPM                    */
+  int cold;               /* 1: cells with no energy solution try cold MHD    */
 } orc_params;
 
 /* ---- geometry (Sec. 2; metric of the Kerr-Schild form) ---- */
@@ -105,6 +107,10 @@ typedef struct {
 
 void orc_implicit_cell(const orc_params *p, const orc_geom *g, const double *Ui,
                        const double *Pguess, double dt, double chi_abs, double chi_es,
+                       double *Pout, double *Uout, orc_implicit_info *info);
+/* the cold MHD solve alone, u_g held at u_c (for tests) */
+void orc_implicit_cold(const orc_params *p, const orc_geom *g, const double *Ui,
+                       const double *Pguess, double dt, double chi_abs, double chi_es, double u_c,
                        double *Pout, double *Uout, orc_implicit_info *info);
 
 /* batch of independent Minkowski cells, arrays [12][n] */

@@ -402,12 +402,18 @@ def test_implicit_relaxation_at_rest(orc, dtk):
         ka = dtk
         Po, Uo, st, it, err = orc.implicit_cell(pd, g, U, P, 1.0, ka / rho, 0.0)
         u = _quartic_root(u0, E0, rho, ka, 1.0, pd["arad"], pd["gam"])
-        if st & orc.ST_FAIL:
+        if st & (orc.ST_FAIL | orc.ST_COLD):
             # The last two states are far from equilibrium at low density: the
             # first undamped Newton step overshoots along the T^4 emission
             # term and the stagnation check ends the normal cascade. Such a
-            # cell must be flagged, never returned as a wrong accepted answer.
+            # cell must be flagged, never returned as a wrong accepted answer:
+            # it fails, or it takes the cold MHD limit, which at rest keeps
+            # the gas at rest with u_g at the floor and conserves the total.
             assert (rho, u0, E0) in cases[3:] and dtk >= 0.3
+            if st & orc.ST_COLD:
+                assert not (st & orc.ST_FAIL)
+                assert Po[1] == pd["u_floor"] and np.abs(Po[2:5]).max() < 1e-14
+                assert abs((Uo[1] + Uo[8]) - (U[1] + U[8])) < 1e-15 * (abs(U[1]) + abs(U[8]))
             continue
         assert abs(Po[1] / u - 1) < 1e-12, (rho, u0, E0)
         assert abs(Po[8] - (E0 + u0 - u)) < 1e-12 * (E0 + u0)
@@ -459,7 +465,7 @@ def test_implicit_solution_satisfies_equations(orc):
     ok = tight = 0
     for c in range(P.shape[1]):
         Po, Uo, st, it, err = orc.implicit_cell(pd, g, Ui[:, c], P[:, c], dt[c], ca[c], ce[c])
-        if st & (orc.ST_FAIL | orc.ST_TYPE2_NEG | orc.ST_BASIC):
+        if st & (orc.ST_FAIL | orc.ST_TYPE2_NEG | orc.ST_BASIC | orc.ST_COLD):
             continue
         assert err < pd["tol_fail"]
         if not (st & orc.ST_NOT_ACCEPT):
@@ -469,6 +475,114 @@ def test_implicit_solution_satisfies_equations(orc):
         ok += 1
         tight += max(rg, rr) < 1e-12
     assert ok > 350 and tight > 0.9 * ok
+
+
+def _mink_momentum_residual(pd, P, Ui, dt, ka, ke):
+    """Gas momentum residual T^t_i - T^t_i(i) - dt G_i (i = 1..3) in flat
+    space, written independently as in _mink_residual, over the same scale."""
+    gam = pd["gam"]
+    eta = np.diag([-1.0, 1, 1, 1])
+    rho, ug = P[0], P[1]
+    u = np.concatenate([[math.sqrt(1 + P[2:5] @ P[2:5])], P[2:5]])
+    ur = np.concatenate([[math.sqrt(1 + P[9:12] @ P[9:12])], P[9:12]])
+    pg = (gam - 1) * ug
+    Tup = (rho + ug + pg) * np.outer(u, u) + pg * eta
+    Rup = P[8] * (4.0 / 3.0 * np.outer(ur, ur) + eta / 3.0)
+    ucov = eta @ u
+    Ehat = ucov @ Rup @ ucov
+    Fvec = -(Rup @ ucov) - Ehat * u
+    lam = ka * pd["arad"] * (pg / rho) ** 4
+    Gcov = eta @ ((ka * Ehat - lam) * u + (ka + ke) * Fvec)
+    Tt = Tup[0] @ eta
+    Rt = Rup[0] @ eta
+    res = Tt[1:] - Ui[2:5] - dt * Gcov[1:]
+    scale = np.abs(Tt).sum() + np.abs(Ui[1:5]).sum() + np.abs(Rt).sum() + np.abs(Ui[8:12]).sum() + dt * np.abs(Gcov).sum()
+    return np.abs(res).max() / scale
+
+
+def _batch_explicit(orc, n, seed):
+    pd, P, dt, ca, ce = I.implicit_batch(n, seed=seed)
+    g = orc.geom(pd, 0.0, 0.0)
+    U = np.stack([orc.p2u(pd, g, P[:, c]) for c in range(n)], axis=1)
+    Ui = U.copy()
+    Ui[8] *= 1.3
+    Ui[1] -= 0.3 * U[8]
+    return pd, g, P, dt, ca, ce, Ui
+
+
+def test_cold_mhd_uncoupled_closed_form(orc):
+    """No coupling (chi = 0) and no field in flat space: the cold solve keeps
+    each fluid's momentum, so u~_i = T^t_i(i) / (D + (u_c + p_c) u^t) with
+    D = rho0 u^t; with u_c at the floor that is T^t_i(i) / D to round-off."""
+    pd, g, P, dt, ca, ce, Ui = _batch_explicit(orc, 64, 7)
+    for c in range(P.shape[1]):
+        Po, Uo, st, it, err = orc.implicit_cold(pd, g, Ui[:, c], P[:, c], 1.0, 0.0, 0.0, pd["u_floor"])
+        assert st & orc.ST_COLD and not st & orc.ST_FAIL
+        assert Po[1] == pd["u_floor"]
+        ut = Ui[2:5, c] / Ui[0, c]
+        assert np.abs(Po[2:5] - ut).max() < 1e-13 * (1 + np.abs(ut).max()), (c, Po[2:5], ut)
+        # radiation untouched: the gas momentum alone balances
+        assert np.abs(Uo[9:12] - Ui[9:12, c]).max() <= 1e-15 * (np.abs(Ui[8:12, c]).sum() + np.abs(Ui[1:5, c]).sum())
+
+
+def test_cold_mhd_reproduces_energy_solutions(orc):
+    """With u_g held at the value of an accepted energy solution, the cold
+    solve returns that solution (the momentum equations and total
+    conservation are the energy solution's own): started at the solution it
+    stays there, and started from the prior primitives it gets there in all
+    but a few strongly coupled cells, where the undamped Newton stalls."""
+    pd, g, P, dt, ca, ce, Ui = _batch_explicit(orc, 800, 4)
+    pd = dict(pd, roundoff=1)   # both solves iterate to round-off
+    checked = reached = 0
+    for c in range(P.shape[1]):
+        Po, Uo, st, it, err = orc.implicit_cell(pd, g, Ui[:, c], P[:, c], dt[c], ca[c], ce[c])
+        # PMHD-accepted energy solutions at round-off (the cold limit is the
+        # PMHD form with u_g held; where PMHD itself could not converge, URAD
+        # took the cell and the gas-primitive residual is no better held cold)
+        if st & (orc.ST_FAIL | orc.ST_COLD | orc.ST_NOT_ACCEPT | orc.ST_TYPE2_NEG | orc.ST_URAD) \
+                or err > 1e-12:
+            continue
+        scale = np.abs(Uo[1:5]).sum() + np.abs(Uo[8:12]).sum()
+        for guess in (Po, P[:, c]):
+            Pc, Uc, stc, itc, errc = orc.implicit_cold(pd, g, Ui[:, c], guess, dt[c], ca[c], ce[c], Po[1])
+            if guess is not Po and stc & orc.ST_FAIL:
+                continue
+            assert stc & orc.ST_COLD and not stc & orc.ST_FAIL, c
+            assert np.abs(Uc - Uo)[1:12].max() < 1e-11 * scale, (c, np.abs(Uc - Uo).max() / scale)
+            assert np.abs(Pc[2:5] - Po[2:5]).max() < 1e-10 * (1 + np.abs(Po[2:5]).max())
+            reached += guess is not Po
+        checked += 1
+    assert checked > 60 and reached >= 0.95 * checked, (checked, reached)
+
+
+def test_cold_mhd_rescues_cells_without_energy_solution(orc):
+    """Cells whose energy equation has no solution take the cold MHD limit:
+    flagged COLD, u_g at the floor, the gas momentum equations satisfied
+    (written independently), total energy-momentum conserved exactly; with
+    the limit switched off the same cells fail."""
+    pd, g, P, dt, ca, ce, Ui = _batch_explicit(orc, 600, 11)
+    pd = dict(pd, roundoff=1)   # solves iterate to round-off
+    pd0 = dict(pd, cold=0)
+    cold = tight = 0
+    for c in range(P.shape[1]):
+        Po, Uo, st, it, err = orc.implicit_cell(pd, g, Ui[:, c], P[:, c], dt[c], ca[c], ce[c])
+        if not st & orc.ST_COLD:
+            continue
+        cold += 1
+        _, _, st0, _, _ = orc.implicit_cell(pd0, g, Ui[:, c], P[:, c], dt[c], ca[c], ce[c])
+        assert st0 & orc.ST_FAIL and not st0 & orc.ST_COLD
+        assert not st & (orc.ST_FAIL | orc.ST_PMHD | orc.ST_URAD)
+        assert Po[1] == pd["u_floor"] and err <= pd["tol_fail"]
+        # the residual written here cancels G ~ kappa (E u + F) itself, so its
+        # own rounding grows with dt kappa: checked where that stays small
+        if dt[c] * (ca[c] + ce[c]) * Po[0] < 1e3:
+            r = _mink_momentum_residual(pd, Po, Ui[:, c], dt[c], ca[c] * Po[0], ce[c] * Po[0])
+            assert r < 1e-13 + 10.0 * err, (c, r, err)
+            tight += 1
+        tot = np.abs(Ui[1:5, c]).sum() + np.abs(Ui[8:12, c]).sum()
+        assert np.abs((Uo[1:5] + Uo[8:12]) - (Ui[1:5, c] + Ui[8:12, c])).max() < 1e-15 * tot
+        assert Uo[0] == Ui[0, c]
+    assert cold > 20 and tight > 10, (cold, tight)
 
 
 # ---------------------------------------------------------------------------
