@@ -65,7 +65,9 @@ enum {
   GRRMHD_ST_NOT_ACCEPT = 1 << 6, /* best error above tol_accept, below tol_fail  */
   GRRMHD_ST_FAIL = 1 << 7,       /* no solution: neighbour-averaged primitives   */
   GRRMHD_ST_NO_GOOD_NB = 1 << 8, /* averaging found no good neighbour            */
-  GRRMHD_ST_EXTREME = 1 << 9     /* radiation extremely sub-dominant: URAD first */
+  GRRMHD_ST_EXTREME = 1 << 9,    /* radiation extremely sub-dominant: URAD first */
+  GRRMHD_ST_COLD = 1 << 10       /* no energy solution: cold MHD limit (u_g at the
+                                    floor, gas momentum equations solved)       */
 };
 
 /* Numerical parameters.  Defaults (grrmhd_default_params) are the paper's
@@ -114,6 +116,15 @@ typedef struct {
                            gas and radiation shock flatteners blended by the
                            optical depth, each the largest over the step's
                            sub-steps; ng = 4).  The adjoint covers MC only. */
+  int cold;             /* 1 (default): a cell whose implicit solve finds no
+                           energy solution takes the cold MHD limit (Sec.
+                           4.7): u_g held at u_floor, the three gas momentum
+                           equations solved for the gas velocity (PMHD
+                           residual, energy residuals left out of e_T), the
+                           radiation from total energy-momentum conservation;
+                           on success GRRMHD_ST_COLD replaces GRRMHD_ST_FAIL.
+                           0: such cells fail (and are neighbour-averaged in
+                           grrmhd_step).                                     */
 } grrmhd_params;
 
 typedef struct grrmhd_grid grrmhd_grid;
@@ -179,7 +190,8 @@ int grrmhd_con2prim(grrmhd_grid *g, const double *U, const double *Pguess, doubl
 
 /* Sub-steps 11-12: implicit radiation 4-force solve at interior cells with
  * time step dt_scale * (*dt_dev) (eq. source3/source4; PMHD then URAD,
- * Sec. 4.7-4.11).  Uexp [12][N] explicit conserved state; Pguess [12][N]
+ * Sec. 4.7-4.11; then, where neither has a solution, the cold MHD limit of
+ * Sec. 4.7 when params.cold is set).  Uexp [12][N] explicit conserved state; Pguess [12][N]
  * previous primitives (may alias P).  Out: P, U [12][N] (U may not alias
  * Uexp), iters/status/err [N] (each may be NULL): Newton steps, status
  * bits, final total normalised error e_T. */
@@ -248,7 +260,8 @@ int grrmhd_step_adjoint(grrmhd_grid *g, const double *P_n, const double *chi_abs
  *  grrmhd_implicit_vjp   of grrmhd_implicit_grid at its result (P_out,
  *                        status): gUexp = (dP/dUexp)^T gP_out +
  *                        (dU/dUexp)^T gU_out at interior cells (zero at
- *                        ghosts);
+ *                        ghosts); cold cells (GRRMHD_ST_COLD) through the
+ *                        three momentum equations with u_g fixed;
  *  grrmhd_explicit_vjp   of grrmhd_fluxes followed by grrmhd_explicit_update
  *                        with stage coefficient c on dt, with respect to the
  *                        ghost-filled P: gP at every allocated cell;
@@ -267,15 +280,17 @@ int grrmhd_bc_vjp(grrmhd_grid *g, double *gP);
 
 /* Implicit 4-force solve for n independent cells in flat space (Minkowski
  * metric, no grid), eq. source3/source4 with the PMHD-then-URAD cascade of
- * Sec. 4.10.  Arrays [12][n] (U_expl, P_guess, P_out, U_out) and [n]
- * (dt_cell, chi_abs, chi_es, iters, status, err; the last three nullable),
- * device memory; n < 2^31.  workspace: device buffer of at least
+ * Sec. 4.10, then the cold MHD limit (Sec. 4.7, params.cold) for cells left
+ * without an energy solution.  Arrays [12][n] (U_expl, P_guess, P_out, U_out)
+ * and [n] (dt_cell, chi_abs, chi_es, iters, status, err; the last three
+ * nullable), device memory; n < 2^31.  workspace: device buffer of at least
  * grrmhd_implicit_source_workspace_bytes(n) bytes, 256-byte aligned (work
  * list of the cells that need the full cascade, with the result of their
- * first attempt; list of deferred extreme cells; lane statistics).  Same
- * algorithm as grrmhd_implicit_grid.  The cascade's URAD attempts run in a
- * compacting persistent grid (lanes take the next listed cell as soon as
- * theirs ends); extreme cells (URAD first) run one thread each afterwards. */
+ * first attempt; list of deferred extreme cells; list of cells for the cold
+ * limit; lane statistics).  Same algorithm as grrmhd_implicit_grid.  The
+ * cascade's URAD attempts run in a compacting persistent grid (lanes take
+ * the next listed cell as soon as theirs ends); extreme cells (URAD first)
+ * and then cold cells run one thread each afterwards. */
 size_t grrmhd_implicit_source_workspace_bytes(long n);
 int grrmhd_implicit_source(const grrmhd_params *p, long n, const double *U_expl,
                            const double *P_guess, const double *dt_cell, const double *chi_abs,

@@ -204,6 +204,12 @@ DEV void adj_implicit_at(Ctx C, double scale, const double* __restrict__ dt_dev,
 #pragma unroll
       for (int kk = 0; kk < 4; kk++) JT[jj][kk] = E[kk].d[jj];
     }
+    if (status[c] & GRRMHD_ST_COLD) {   // cold limit: u_g held, the energy equation dropped
+      gx[0] = 0.0;
+      JT[0][0] = 1.0;
+#pragma unroll
+      for (int k = 1; k < 4; k++) JT[0][k] = JT[k][0] = 0.0;
+    }
     ok = solve4(JT, gx, mu) == 0;
   }
   if (!ok) {   // failed cell (or singular Jacobian): U passes through unchanged

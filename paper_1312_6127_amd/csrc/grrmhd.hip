@@ -93,6 +93,7 @@ extern "C" void grrmhd_default_params(grrmhd_params* p) {
   p->precision = GRRMHD_FP64;
   p->scheme = GRRMHD_RK3;
   p->recon = GRRMHD_RECON_MC;
+  p->cold = 1;
   p->r_fp64 = 2.0;
   p->tol_pmhd = 1e-12;
   p->tol_urad = 1e-9;
@@ -119,6 +120,7 @@ static int validate(const grrmhd_params* p, bool need_grid) {
   if (p->metric != GRRMHD_MINKOWSKI && p->metric != GRRMHD_KERR_SCHILD)
     return fail(GRRMHD_EINVAL, "bad metric");
   if (p->scheme < GRRMHD_RK3 || p->scheme > GRRMHD_IMEX3) return fail(GRRMHD_EINVAL, "bad scheme");
+  if (p->cold != 0 && p->cold != 1) return fail(GRRMHD_EINVAL, "cold must be 0 or 1");
   if (p->recon != GRRMHD_RECON_MC && p->recon != GRRMHD_RECON_PPM)
     return fail(GRRMHD_EINVAL, "bad reconstruction");
   if (!need_grid) return 0;
@@ -169,6 +171,7 @@ static void fill_ctx(const grrmhd_params* p, Ctx& C) {
   C.courant = p->courant;
   C.flux = p->flux;
   C.recon = p->recon;
+  C.cold = p->cold;
   // FP32 face path from the first x1 index i whose cell i-1 has r >= r_fp64
   C.mixed_i = 1 << 30;
   if (p->precision == GRRMHD_MIXED) {
@@ -1056,11 +1059,13 @@ extern "C" int grrmhd_step_adjoint(grrmhd_grid* g, const double* P_n, const doub
 }
 
 // Workspace of the batched solve: [0, 256) counters (list length @0, queue
-// cursor @4, two queue lengths @8, stats @64), then the cascade list and
-// records, and for the per-iteration form two queues and the lane state.
+// cursor @4, two queue lengths @8, cascade cursor @16, deferred and cold
+// list lengths @20 and @24, stats @64), then the cascade list and records,
+// the deferred (extreme) and cold lists, and for the per-iteration form two
+// queues and the lane state.
 extern "C" size_t grrmhd_implicit_source_workspace_bytes_ex(long n, int mode) {
   if (n <= 0) return 0;
-  size_t b = 256 + cascade_bytes((size_t)n) + round256(sizeof(int) * (size_t)n);
+  size_t b = 256 + cascade_bytes((size_t)n) + 2 * round256(sizeof(int) * (size_t)n);
   if (mode == GRRMHD_IMPLICIT_PER_ITERATION)
     b += 2 * round256(sizeof(int) * (size_t)n) + round256(sizeof(double) * LS_ND * (size_t)n) +
          round256(sizeof(int) * LI_NI * (size_t)n);
@@ -1110,7 +1115,11 @@ static int launch_batch(const Ctx& C, long n, const double* U_expl, const double
   Work D = W;
   D.counter = W.counter + 5;
   D.list = (int*)(base + 256 + cascade_bytes((size_t)n));
-  char* extra = (char*)D.list + round256(sizeof(int) * (size_t)n);
+  // cells the cascade leaves without an energy solution, for the cold limit
+  Work K = W;
+  K.counter = W.counter + 6;
+  K.list = (int*)((char*)D.list + round256(sizeof(int) * (size_t)n));
+  char* extra = (char*)K.list + round256(sizeof(int) * (size_t)n);
   if (mode == GRRMHD_IMPLICIT_PERSISTENT) {
     if (block != 64 && block != 128 && block != 256) return fail(GRRMHD_EINVAL, "block must be 64, 128 or 256");
     if (waves_per_cu < 1 || waves_per_cu > 64) return fail(GRRMHD_EINVAL, "waves_per_cu out of [1, 64]");
@@ -1159,11 +1168,17 @@ static int launch_batch(const Ctx& C, long n, const double* U_expl, const double
   // the deferred extreme cells one thread each
   const long cwaves = std::max<long>(1, std::min<long>(4L * ncu, nblocks(n, 64)));
   hipLaunchKernelGGL(k_cascade_urad, dim3((unsigned)cwaves), dim3(64), 0, s, C, n, U_expl, P_guess,
-                     dt_cell, chi_abs, chi_es, P_out, U_out, iters, status, err, W, cursor, D);
+                     dt_cell, chi_abs, chi_es, P_out, U_out, iters, status, err, W, cursor, D, K);
   LAUNCHCHK();
   hipLaunchKernelGGL(k_implicit_batch_list, dim3(list_blocks(n)), dim3(64), 0, s, C, n, U_expl,
-                     P_guess, dt_cell, chi_abs, chi_es, P_out, U_out, iters, status, err, D);
+                     P_guess, dt_cell, chi_abs, chi_es, P_out, U_out, iters, status, err, D, K);
   LAUNCHCHK();
+  // cells with no energy solution: the cold MHD limit, one thread each
+  if (C.cold && C.u_floor > 0.0) {
+    hipLaunchKernelGGL(k_cold_batch_list, dim3(list_blocks(n)), dim3(64), 0, s, C, n, U_expl,
+                       P_guess, dt_cell, chi_abs, chi_es, P_out, U_out, iters, status, err, K);
+    LAUNCHCHK();
+  }
   return 0;
 }
 

@@ -34,6 +34,7 @@ struct Cell {
   double rhout, B[3];
   double Tgi[4], Ri[4];   // explicit gas (T^t_t + rho u^t, T^t_i) and radiation R^t_nu
   double dt, chi_abs, chi_es;
+  int cold;               // cold MHD: energy residuals left out of the errors
 };
 
 struct Eval {
@@ -51,6 +52,8 @@ struct Phys {
 struct Opts {
   double tol_pmhd, tol_urad, tol_accept, tol_fail;
   int max_iter, roundoff;
+  int cold;         // try the cold MHD limit where no energy solution is found
+  double u_floor;   // u_g of the cold limit
 };
 
 DEV double snorm3(const Metric& m, const double V[4]) {
@@ -87,7 +90,7 @@ DEV void norm_errors(const Cell& c, const double Tg[4], const double Rr[4], cons
     eg[1 + i] = ::fabs(e.Eg[1 + i]) * w / nsg;
     er[1 + i] = ::fabs(e.Er[1 + i]) * w / nsr;
   }
-  if (e.radflags & 1) eg[0] = er[0] = 0.0;
+  if ((e.radflags & 1) || c.cold) eg[0] = er[0] = 0.0;
   double t = 0.0, ig = 0.0, ir = 0.0;
 #pragma unroll
   for (int k = 0; k < 4; k++) {
@@ -618,6 +621,7 @@ DEV void prepare(const Metric& m, const Phys& ph, const double Ui[12], const dou
   c.dt = dt;
   c.chi_abs = chi_abs;
   c.chi_es = chi_es;
+  c.cold = 0;
   pr.status = 0;
   // extreme radiation sub-dominance: R^t_t against the gas energy, or the
   // gas-frame radiation energy of the guess against u_g, below 10 eps
@@ -711,6 +715,96 @@ DEV void failed_out(const double Ui[12], const double Pg[12], int status, int it
   out.err = INFINITY;
 }
 
+// Cold MHD limit (Sec. 4.7: with no solution of the energy or the entropy
+// equation, both conservation laws are dropped): u_g held at x0[0], the
+// three gas momentum equations solved for u~^i with the PMHD residual and
+// its exact Jacobian, the radiation following from total conservation; the
+// energy residuals leave e_T (c.cold).  The u_g row and column of the 4x4
+// system are pinned (dx_0 = 0); the stopping rules are newton()'s.
+DEV void newton_cold(const Cell& c, const Phys& ph, const Opts& o, const double x0[4], Best& best,
+                     int& iters) {
+  double x[4] = {x0[0], x0[1], x0[2], x0[3]};
+  Eval ev;
+  double J[4][4];
+  eval_pmhd(c, ph, x, ev, J);
+  keep(best, ev);
+  if (!ev.ok) return;
+  double h[5];
+#pragma unroll
+  for (int k = 0; k < 4; k++) h[k] = INFINITY;
+  h[4] = ev.eT;
+  int nrise = 0, extra = 0, conv = 0;
+  for (int it = 0; it < o.max_iter; it++) {
+    if (ev.eT < o.tol_pmhd) conv = 1;
+    if (conv) {
+      if (!o.roundoff || extra >= 3) break;
+      extra++;
+    }
+    if (!conv && it >= 5 && ev.eT > 0.5 * (h[0] + h[1] + h[2]) * (1.0 / 3.0)) break;
+    J[0][0] = 1.0;
+#pragma unroll
+    for (int k = 1; k < 4; k++) J[0][k] = J[k][0] = 0.0;
+    double r[4] = {0.0, ev.Eg[1], ev.Eg[2], ev.Eg[3]};
+    double dx[4];
+    if (solve4(J, r, dx)) break;
+    double xn[4];
+#pragma unroll
+    for (int i = 0; i < 4; i++) xn[i] = x[i] - dx[i];
+    eval_pmhd(c, ph, xn, ev, J);
+    iters++;
+    bool small = true;
+#pragma unroll
+    for (int i = 0; i < 4; i++)
+      if (::fabs(xn[i] - x[i]) > 10.0 * DBL_EPSILON * ::fabs(x[i])) small = false;
+#pragma unroll
+    for (int i = 0; i < 4; i++) x[i] = xn[i];
+    const double prev = h[4];
+#pragma unroll
+    for (int k = 0; k < 4; k++) h[k] = h[k + 1];
+    h[4] = ev.eT;
+    if (ev.ok && ev.eT < best.eT) keep(best, ev);
+    if (!ev.ok) break;
+    if (it >= 5 && ev.eT > prev) {
+      nrise++;
+      if (nrise >= 5) break;
+    }
+    if (small) break;
+  }
+}
+
+// Cold attempt for a cell with no energy solution: u_g at the floor, u~^i
+// from the prior primitives.  On success (e_T within tol_fail) `out` holds
+// the solution with the set-up's status bits (EXTREME, C2P_FAIL) and COLD
+// (TYPE2/BASIC/NOT_ACCEPT as for PMHD); iters accumulates either way.
+DEV bool cold_cell(const Metric& m, const Phys& ph, const Opts& o, const double Ui[12],
+                   const double Pg[12], double dt, double chi_abs, double chi_es, int& iters,
+                   CellOut& out) {
+  Cell c;
+  Prep pr;
+  prepare(m, ph, Ui, Pg, dt, chi_abs, chi_es, c, pr);
+  c.cold = 1;
+  const double x0[4] = {o.u_floor, Pg[2], Pg[3], Pg[4]};
+  Best b;
+  b.eT = INFINITY;
+  b.ok = 0;
+  newton_cold(c, ph, o, x0, b, iters);
+  if (!b.ok || !(b.eT <= o.tol_fail)) return false;
+  finalize(c, ph, o, b, M_PMHD, pr.status, iters, Ui, out);
+  out.status = (out.status & ~GRRMHD_ST_PMHD) | GRRMHD_ST_COLD;
+  return true;
+}
+
+// After the energy cascade: a cell left failed takes the cold limit.
+DEV void cold_fallback(const Metric& m, const Phys& ph, const Opts& o, const double Ui[12],
+                       const double Pg[12], double dt, double chi_abs, double chi_es,
+                       CellOut& out) {
+  if (!(out.status & GRRMHD_ST_FAIL) || !o.cold || !(o.u_floor > 0.0)) return;
+  int iters = out.iters;
+  CellOut oc;
+  if (cold_cell(m, ph, o, Ui, Pg, dt, chi_abs, chi_es, iters, oc)) out = oc;
+  out.iters = iters;
+}
+
 // Result of a cell's first PMHD attempt, kept per cascade-list slot so that
 // the cascade resumes where the first attempt ended: field-major [f][cap],
 // d = P[12], e_T; i = radiation flags, ok, iterations.
@@ -769,7 +863,8 @@ DEV bool implicit_fast(const Metric& m, const Phys& ph, const Opts& o, const dou
 // be in the cascade).
 DEV void implicit_cell(const Metric& m, const Phys& ph, const Opts& o, const double Ui[12],
                        const double Pg[12], double dt, double chi_abs, double chi_es,
-                       CellOut& out, const RecBuf* R = nullptr, long slot = 0) {
+                       CellOut& out, const RecBuf* R = nullptr, long slot = 0,
+                       bool try_cold = true) {
   Cell c;
   Prep pr;
   prepare(m, ph, Ui, Pg, dt, chi_abs, chi_es, c, pr);
@@ -817,11 +912,9 @@ DEV void implicit_cell(const Metric& m, const Phys& ph, const Opts& o, const dou
     }
     if (best.eT < accept_threshold(o)) break;
   }
-  if (bm < 0) {
-    failed_out(Ui, Pg, pr.status, iters, out);
-    return;
-  }
-  finalize(c, ph, o, best, bm, pr.status, iters, Ui, out);
+  if (bm < 0) failed_out(Ui, Pg, pr.status, iters, out);
+  else finalize(c, ph, o, best, bm, pr.status, iters, Ui, out);
+  if (try_cold) cold_fallback(m, ph, o, Ui, Pg, dt, chi_abs, chi_es, out);
 }
 
 // ---------------------------------------------------------------------------

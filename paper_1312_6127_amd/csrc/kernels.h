@@ -777,6 +777,8 @@ DEV Opts make_opts(const Ctx& C) {
   o.tol_fail = C.tol_fail;
   o.max_iter = C.max_iter;
   o.roundoff = C.roundoff;
+  o.cold = C.cold;
+  o.u_floor = C.u_floor;
   return o;
 }
 
@@ -988,7 +990,7 @@ __global__ void LB(64) k_implicit_batch_list(Ctx C, long n, const double* __rest
                                              const double* __restrict__ chi_es,
                                              double* __restrict__ Po, double* __restrict__ Uo,
                                              int* __restrict__ iters, int* __restrict__ status,
-                                             double* __restrict__ err, Work W) {
+                                             double* __restrict__ err, Work W, Work K) {
   const int cnt = *W.counter;
   for (long w = (long)blockIdx.x * blockDim.x + threadIdx.x; w < cnt;
        w += (long)gridDim.x * blockDim.x) {
@@ -1003,8 +1005,41 @@ __global__ void LB(64) k_implicit_batch_list(Ctx C, long n, const double* __rest
     }
     CellOut o;
     implicit_cell(m, make_phys(C), make_opts(C), Ui, Pg, dtc[c], chi_abs[c], chi_es[c], o, &W.rec,
-                  w);
+                  w, false);
     store_out(o, c, n, Po, Uo, iters, status, err);
+    wave_append((o.status & GRRMHD_ST_FAIL) != 0, (int)c, K.counter, K.list);
+  }
+}
+
+// Cells of a batch left without an energy solution (listed in K by the
+// cascade kernels): the cold MHD limit, one thread each; the iterations of
+// the cell's energy attempts (in `iters`, when kept) are carried on.
+__global__ void LB(64) k_cold_batch_list(Ctx C, long n, const double* __restrict__ Ui_,
+                                         const double* __restrict__ Pg_,
+                                         const double* __restrict__ dtc,
+                                         const double* __restrict__ chi_abs,
+                                         const double* __restrict__ chi_es,
+                                         double* __restrict__ Po, double* __restrict__ Uo,
+                                         int* __restrict__ iters, int* __restrict__ status,
+                                         double* __restrict__ err, Work K) {
+  const int cnt = *K.counter;
+  for (long w = (long)blockIdx.x * blockDim.x + threadIdx.x; w < cnt;
+       w += (long)gridDim.x * blockDim.x) {
+    const long c = K.list[w];
+    Metric m;
+    flat_metric(m);
+    double Ui[12], Pg[12];
+#pragma unroll
+    for (int q = 0; q < 12; q++) {
+      Ui[q] = Ui_[q * n + c];
+      Pg[q] = Pg_[q * n + c];
+    }
+    int it = iters ? iters[c] : 0;
+    CellOut o;
+    if (cold_cell(m, make_phys(C), make_opts(C), Ui, Pg, dtc[c], chi_abs[c], chi_es[c], it, o))
+      store_out(o, c, n, Po, Uo, iters, status, err);
+    else if (iters)
+      iters[c] = it;
   }
 }
 
@@ -1021,7 +1056,8 @@ __global__ void LB(64) k_cascade_urad(Ctx C, long n, const double* __restrict__ 
                                       const double* __restrict__ chi_es,
                                       double* __restrict__ Po, double* __restrict__ Uo,
                                       int* __restrict__ iters, int* __restrict__ status,
-                                      double* __restrict__ err, Work W, int* cursor, Work D) {
+                                      double* __restrict__ err, Work W, int* cursor, Work D,
+                                      Work K) {
   const Phys ph = make_phys(C);
   const Opts o = make_opts(C);
   Metric m;
@@ -1085,6 +1121,7 @@ __global__ void LB(64) k_cascade_urad(Ctx C, long n, const double* __restrict__ 
     const unsigned long long ev_mask = __ballot(doeval);
     useful += __popcll(ev_mask);
     slots += ev_mask ? 64ull : 0ull;
+    bool failed = false;
     if (ended) {
       Best best;
       int it0;
@@ -1106,8 +1143,10 @@ __global__ void LB(64) k_cascade_urad(Ctx C, long n, const double* __restrict__ 
       if (bm < 0) failed_out(Ui, Pg, pst, L.iters, out);
       else finalize(c, ph, o, best, bm, pst, L.iters, Ui, out);
       store_out(out, item, n, Po, Uo, iters, status, err);
+      failed = (out.status & GRRMHD_ST_FAIL) != 0;
       active = false;
     }
+    wave_append(failed, (int)item, K.counter, K.list);   // to the cold limit
     if (!__any(active) && __all(exhausted)) break;
   }
   if ((threadIdx.x & 63) == 0 && useful) {
@@ -1324,6 +1363,7 @@ DEV void setup_cell(const Metric& m, const double Ui[12], double dt, double ca, 
   c.dt = dt;
   c.chi_abs = ca;
   c.chi_es = ce;
+  c.cold = 0;
 }
 
 

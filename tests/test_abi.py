@@ -93,7 +93,7 @@ def test_batch_workspace_sizes(L):
     for n in (1, 63, 64, 1000, 1 << 24):
         a, b, c = f(n, G.PER_CELL), f(n, G.PERSISTENT), f(n, G.PER_ITERATION)
         assert a == b == L.grrmhd_implicit_source_workspace_bytes(n)
-        # list, first-attempt record (13 doubles, 3 ints), deferred list per cell
-        assert a >= 256 + 4 * n + 13 * 8 * n + 3 * 4 * n + 4 * n and a % 256 == 0
+        # list, first-attempt record (13 doubles, 3 ints), deferred and cold lists per cell
+        assert a >= 256 + 4 * n + 13 * 8 * n + 3 * 4 * n + 2 * 4 * n and a % 256 == 0
         # two queues, 47 doubles and 8 ints of lane state per cell
         assert c >= a + 8 * n + 47 * 8 * n + 8 * 4 * n

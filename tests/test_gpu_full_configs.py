@@ -143,7 +143,8 @@ def test_batch_2e24_cells_sampled(G, orc):
     agree, good = 0, 0
     for c in cells:
         Po, Uo, st, it, err = orc.implicit_cell(pd, g0, Ui[:, c], P[:, c], dt[c], ca[c], ce[c])
-        if (st & orc.ST_FAIL) != (stg[c] & orc.ST_FAIL):
+        kind = orc.ST_FAIL | orc.ST_COLD   # energy solution, cold one, or none
+        if (st & kind) != (stg[c] & kind):
             continue
         agree += 1
         if st & orc.ST_FAIL or not errg[c] < 1e-11:
@@ -151,9 +152,13 @@ def test_batch_2e24_cells_sampled(G, orc):
         good += 1
         scale = abs(Uo[1]) + abs(Uo[8]) + np.abs(Uo[2:5]).sum() + np.abs(Uo[9:12]).sum()
         assert np.abs(Ug[1:12, c] - Uo[1:12]).max() / scale < 1e-12, c
-        assert abs(Pg[0, c] - Po[0]) / Po[0] < 1e-12, c
+        # cold cells (radiation-dominated, the gas velocity set by a momentum
+        # balance where the gas is a small part): its velocity and rho0 = D/u^t
+        # to 1e-10, the conserved state as above
+        tv = 1e-10 if st & orc.ST_COLD else 1e-12
+        assert abs(Pg[0, c] - Po[0]) / Po[0] < tv, c
         eng = abs(Po[1]) + abs(Po[8])
         assert abs(Pg[1, c] - Po[1]) / eng < 1e-10 and abs(Pg[8, c] - Po[8]) / eng < 1e-10, c
-        assert np.abs(Pg[2:5, c] - Po[2:5]).max() / (1.0 + np.abs(Po[2:5]).sum()) < 1e-12, c
-    say(f"  sampled cells: FAIL bit agrees {agree}/400, compared {good}")
+        assert np.abs(Pg[2:5, c] - Po[2:5]).max() / (1.0 + np.abs(Po[2:5]).sum()) < tv, c
+    say(f"  sampled cells: FAIL and COLD bits agree {agree}/400, compared {good}")
     assert agree >= 0.98 * 400 and good >= 0.6 * 400

@@ -210,7 +210,12 @@ def test_implicit_batch(G, orc):
     Pr, Ur, itr, str_ = orc.implicit_batch(pd, Ui, P, dt, ca, ce)
     Pg, Ug, itg, stg, errg = G.implicit_source(pd, dev(Ui), dev(P), dev(dt), dev(ca), dev(ce))
     Pg, Ug, stg, errg = host(Pg), host(Ug), host(stg), host(errg)
-    fail_agree = (stg & orc.ST_FAIL) == (str_ & orc.ST_FAIL)
+    # whether a cell has an energy solution, a cold one or none: decided the
+    # same way on both sides except near the edge of a root's existence,
+    # where the two Newton iterations (exact and difference Jacobians) can
+    # end on either side of it
+    kind = orc.ST_FAIL | orc.ST_COLD
+    fail_agree = (stg & kind) == (str_ & kind)
     assert fail_agree.mean() > 0.98
     # both sides accept a method within 10 tol_pmhd (1e-11) when iterating to round-off
     good = fail_agree & ((str_ & orc.ST_FAIL) == 0) & (errg < 1e-11)
@@ -225,11 +230,14 @@ def test_implicit_batch(G, orc):
     # not against Ebar alone, which is ill-conditioned in radiation-sub-
     # dominant cells; the radiation frame velocity is covered by R^t_i above.
     eng = np.abs(Pr[1, good]) + np.abs(Pr[8, good])
-    assert (np.abs(Pg[0, good] - Pr[0, good]) / Pr[0, good]).max() < 1e-12
+    # cold cells: the gas velocity (and rho0 = D/u^t) comes from a momentum
+    # balance in which the gas is a small part of a radiation-dominated cell
+    tv = np.where((str_[good] & orc.ST_COLD) != 0, 1e-10, 1e-12)
+    assert np.all(np.abs(Pg[0, good] - Pr[0, good]) / Pr[0, good] < tv)
     for q in (1, 8):
         assert (np.abs(Pg[q, good] - Pr[q, good]) / eng).max() < 1e-10, q
     gsc = 1.0 + np.abs(Pr[2:5, good]).sum(0)
-    assert (np.abs(Pg[2:5, good] - Pr[2:5, good]).max(0) / gsc).max() < 1e-12
+    assert np.all(np.abs(Pg[2:5, good] - Pr[2:5, good]).max(0) / gsc < tv)
 
 
 def test_full_size_disk_step(G, orc):
