@@ -136,6 +136,7 @@ def bench_batch(G, I, torch, dev, n, reps=3):
     its = outs[2].cpu().numpy()
     res = {"cells": n, "tol_pmhd": pd["tol_pmhd"],
            "failed_frac": float(((st & G.ST_FAIL) != 0).mean()),
+           "cold_frac": float(((st & G.ST_COLD) != 0).mean()),
            "urad_frac": float(((st & G.ST_URAD) != 0).mean()),
            "mean_iters": float(its.mean()), "max_iters": int(its.max()),
            "autotune": [{"form": G.FORM_NAMES[a.mode], "block": a.block,
