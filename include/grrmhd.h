@@ -202,9 +202,12 @@ int grrmhd_implicit_grid(grrmhd_grid *g, const double *Uexp, const double *Pgues
 
 /* Sub-step 13 and floors (Sec. 4.11): cells whose status has
  * GRRMHD_ST_FAIL take the average primitives of their face neighbours with
- * a good solution (of all face neighbours if none is good); then floors on
- * rho0, u_g (b^2/rho0, b^2/u_g, u_g/rho0 limits) and Ebar; U is recomputed
- * where P changed.  `scratch` is device memory of at least 13 N doubles. */
+ * a good energy solution (neither GRRMHD_ST_FAIL nor GRRMHD_ST_COLD; of all
+ * interior face neighbours if none is good, then GRRMHD_ST_NO_GOOD_NB);
+ * cells with GRRMHD_ST_COLD take the same average of u_g alone; then floors
+ * on rho0, u_g (b^2/rho0, b^2/u_g, u_g/rho0 limits) and Ebar; U is
+ * recomputed where P changed.  `scratch` is device memory of at least 13 N
+ * doubles. */
 int grrmhd_fixup(grrmhd_grid *g, double *P, double *U, int *status, double *scratch);
 
 /* One full time step of the grid's scheme (Sec. 4.1).  GRRMHD_RK3:
@@ -267,7 +270,15 @@ int grrmhd_step_adjoint(grrmhd_grid *g, const double *P_n, const double *chi_abs
  *                        ghost-filled P: gP at every allocated cell;
  *                        workspace grrmhd_explicit_vjp_workspace_bytes();
  *  grrmhd_bc_vjp         of grrmhd_apply_bc, in place (ghost entries folded
- *                        into their source cells and cleared). */
+ *                        into their source cells and cleared);
+ *  grrmhd_fixup_vjp      of grrmhd_fixup (Sec. 4.11) at its result (P,
+ *                        status): gP_pre, gU_pre [12][N] = the cotangents of
+ *                        its input P and U for output cotangents gP, gU
+ *                        (interior cells; zero at ghosts).  Failed cells'
+ *                        neighbour averages and cold cells' u_g averages are
+ *                        transposed, U = U(P) at changed cells by its local
+ *                        Jacobian, floors as the identity.  scratch: [12][N]
+ *                        doubles; no array may alias another. */
 int grrmhd_implicit_vjp(grrmhd_grid *g, const double *Uexp, const double *P_out,
                         const int *status, double dt_scale, const double *dt_dev,
                         const double *chi_abs, const double *chi_es, const double *gP_out,
@@ -277,6 +288,8 @@ int grrmhd_explicit_vjp(grrmhd_grid *g, double c, const double *dt_dev, const do
                         const double *chi_abs, const double *chi_es, const double *gUexp,
                         double *gP, void *workspace, size_t ws_bytes);
 int grrmhd_bc_vjp(grrmhd_grid *g, double *gP);
+int grrmhd_fixup_vjp(grrmhd_grid *g, const double *P, const int *status, const double *gP,
+                     const double *gU, double *gP_pre, double *gU_pre, double *scratch);
 
 /* Implicit 4-force solve for n independent cells in flat space (Minkowski
  * metric, no grid), eq. source3/source4 with the PMHD-then-URAD cascade of

@@ -459,6 +459,33 @@ static int emit(const ictx *c, const ieval *best, int method, int status, const 
   return status;
 }
 
+/* Conditions of the cold MHD attempt (Sec. 4.11, backups), on the prior
+ * primitives and the explicit gas state t^t_mu = T^t_mu + rho0 u^t delta^t_mu:
+ * u_g < 0.1 rho0 u^i u_i (the gas cold against its motion) and
+ * |t^t_t t^{tt}| < 0.1 |t^t_i t^{ti}| (its energy small against its
+ * momentum).  The paper's third condition, on R^t_t R^{tt} against
+ * R^t_i R^{ti}, cannot hold for an M1 state (|F| <= E) and is not applied. */
+static int cold_allowed(const ictx *c, const double *Pguess) {
+  const orc_geom *g = c->g;
+  double ucon[4], ucov[4];
+  orc_ucon(g, Pguess + 2, ucon);
+  for (int a = 0; a < 4; a++) {
+    ucov[a] = 0.0;
+    for (int b = 0; b < 4; b++) ucov[a] += g->gcov[a][b] * ucon[b];
+  }
+  double usp = 0.0;
+  for (int i = 1; i < 4; i++) usp += ucon[i] * ucov[i];
+  if (!(Pguess[1] < 0.1 * Pguess[0] * fabs(usp))) return 0;
+  double tup[4];
+  for (int a = 0; a < 4; a++) {
+    tup[a] = 0.0;
+    for (int b = 0; b < 4; b++) tup[a] += g->gcon[a][b] * c->Tgi[b];
+  }
+  double en = c->Tgi[0] * tup[0], mo = 0.0;
+  for (int i = 1; i < 4; i++) mo += c->Tgi[i] * tup[i];
+  return fabs(en) < 0.1 * fabs(mo);
+}
+
 /* Cold MHD solve with u_g held at u_c, guess u~^i from Pguess; returns 0
  * and fills the outputs (status bit ORC_ST_COLD in place of ORC_ST_PMHD)
  * when e_T of the momentum equations is within tol_fail, 1 otherwise. */
@@ -579,7 +606,7 @@ void orc_implicit_cell(const orc_params *p, const orc_geom *g, const double *Ui,
   /* no energy solution: the cold MHD limit (the entropy equation, tried
    * before it in the paper's cascade, needs an evolved entropy tracer that
    * this step does not carry) */
-  if ((status & ORC_ST_FAIL) && p->cold && p->u_floor > 0.0) {
+  if ((status & ORC_ST_FAIL) && p->cold && p->u_floor > 0.0 && cold_allowed(&c, Pguess)) {
     double Pc[12], Uc[12];
     orc_implicit_info ic = *info;
     if (cold_cell(&c, Ui, Pguess, p->u_floor, status0, Pc, Uc, &ic) == 0) {

@@ -492,9 +492,13 @@ void orc_fixup(const orc_params *p, double *P, double *U, int *status) {
         const long c = IDX(p, i, j, k);
         const int idx[3] = {i, j, k};
         int changed = 0;
-        if (status[c] & ORC_ST_FAIL) {
-          /* average the primitives of face neighbours with a good solution;
-           * if none is good, of all interior face neighbours */
+        /* a failed cell takes the average primitives of its face neighbours
+         * with a good energy solution (neither failed nor cold), or of all
+         * interior face neighbours if none is good (Sec. 4.11); a cold cell
+         * (Sec. 4.11, backups) takes that average for u_g alone */
+        const int fail = (status[c] & ORC_ST_FAIL) != 0;
+        const int cold = !fail && (status[c] & ORC_ST_COLD);
+        if (fail || cold) {
           for (int pass = 0; pass < 2 && !changed; pass++) {
             double acc[12] = {0};
             int cnt = 0;
@@ -504,13 +508,16 @@ void orc_fixup(const orc_params *p, double *P, double *U, int *status) {
                 const int nid = idx[d] + s;
                 if (nid < orc_ng(p, d) || nid >= orc_ng(p, d) + p->n[d]) continue;
                 const long nb = c + s * st[d];
-                if (pass == 0 && (status[nb] & ORC_ST_FAIL)) continue;
+                if (pass == 0 && (status[nb] & (ORC_ST_FAIL | ORC_ST_COLD))) continue;
                 for (int q = 0; q < 12; q++) acc[q] += P0[q * N + nb];
                 cnt++;
               }
             }
             if (cnt > 0) {
-              for (int q = 0; q < 12; q++) P[q * N + c] = acc[q] / cnt;
+              if (fail)
+                for (int q = 0; q < 12; q++) P[q * N + c] = acc[q] / cnt;
+              else
+                P[1 * N + c] = acc[1] / cnt;
               changed = 1;
               if (pass == 1) status[c] |= ORC_ST_NO_GOOD_NB;
             }

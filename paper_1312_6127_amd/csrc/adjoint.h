@@ -285,13 +285,17 @@ __global__ void LB(64) k_adj_implicit(Ctx C, double scale, const double* __restr
 }
 
 // ---------------------------------------------------------------------------
-// Fix-up of failed cells: P_f = mean of the face neighbours' P (the good ones;
-// all of them when none is good), U_f = U(P_f).  Transpose: Lam_f =
-// lamP_f + (dU/dP)^T lamU_f, spread back over the neighbours that were
-// averaged; the failed cell's own solve receives nothing.  Floors are taken
-// as the identity.
+// Fix-ups: a failed cell takes P_f = mean of its face neighbours' P (those
+// with a good energy solution, neither failed nor cold; all of them when none
+// is good), a cold cell the same mean for u_g alone; then U = U(P).
+// Transpose: Lam = lamP + (dU/dP)^T lamU at a changed cell, spread back over
+// the neighbours that were averaged (all fields from a failed cell, u_g from a
+// cold one); a failed cell's own solve receives nothing, a cold cell's keeps
+// Lam except for u_g.  A cell with no interior neighbour is left unchanged.
+// Floors are taken as the identity.
 // ---------------------------------------------------------------------------
 DEV bool failed_at(const int* st, long c) { return (st[c] & GRRMHD_ST_FAIL) != 0; }
+DEV bool bad_at(const int* st, long c) { return (st[c] & (GRRMHD_ST_FAIL | GRRMHD_ST_COLD)) != 0; }
 
 DEV bool interior_idx(const Ctx& C, const int idx[3]) {
   for (int d = 0; d < 3; d++)
@@ -299,7 +303,7 @@ DEV bool interior_idx(const Ctx& C, const int idx[3]) {
   return true;
 }
 
-// neighbours the fix-up averaged for failed cell f: *good (pass 0) or all
+// neighbours the fix-up averaged for cell idx: good ones (good_pass) or all
 DEV int fixup_count(const Ctx& C, const int* st, const int idx[3], bool& good_pass) {
   int good = 0, all = 0;
   const long c = cell_index(C, idx[0], idx[1], idx[2]);
@@ -309,23 +313,30 @@ DEV int fixup_count(const Ctx& C, const int* st, const int idx[3], bool& good_pa
       const int nid = idx[d] + s;
       if (nid < C.ng[d] || nid >= C.ng[d] + C.n[d]) continue;
       all++;
-      if (!failed_at(st, c + s * C.st[d])) good++;
+      if (!bad_at(st, c + s * C.st[d])) good++;
     }
   }
   good_pass = good > 0;
   return good_pass ? good : all;
 }
 
+// a failed or cold cell that had neighbours to average (so P and U changed)
+DEV bool fixed_at(const Ctx& C, const int* st, const int idx[3]) {
+  if (!bad_at(st, cell_index(C, idx[0], idx[1], idx[2]))) return false;
+  bool gp;
+  return fixup_count(C, st, idx, gp) > 0;
+}
+
 DEV void adj_fixup_own_at(Ctx C, const double* __restrict__ P, const int* __restrict__ st,
                           const double* __restrict__ lamP, const double* __restrict__ lamU,
                           double* __restrict__ Lam, long t) {
   if (t >= (long)C.n[0] * C.n[1] * C.n[2]) return;
-  int i, j, k;
-  interior_cell(C, t, i, j, k);
-  const long c = cell_index(C, i, j, k);
-  if (!failed_at(st, c)) return;
+  int idx[3];
+  interior_cell(C, t, idx[0], idx[1], idx[2]);
+  const long c = cell_index(C, idx[0], idx[1], idx[2]);
+  if (!fixed_at(C, st, idx)) return;
   Metric m;
-  load_metric(C.geo_c, C.npos, i + C.N[0] * j, m);
+  load_metric(C.geo_c, C.npos, idx[0] + C.N[0] * idx[1], m);
   double p[12], lu[12];
 #pragma unroll
   for (int q = 0; q < 12; q++) {
@@ -359,10 +370,13 @@ DEV void adj_fixup_at(Ctx C, const int* __restrict__ st, const double* __restric
   int idx[3];
   interior_cell(C, t, idx[0], idx[1], idx[2]);
   const long c = cell_index(C, idx[0], idx[1], idx[2]);
-  const bool fc = failed_at(st, c);
+  const bool fixed = fixed_at(C, st, idx);
+  const bool fc = fixed && failed_at(st, c);
+  const bool bc = bad_at(st, c);
   double acc[12];
 #pragma unroll
-  for (int q = 0; q < 12; q++) acc[q] = fc ? 0.0 : lamP[q * C.Ntot + c];
+  for (int q = 0; q < 12; q++)
+    acc[q] = !fixed ? lamP[q * C.Ntot + c] : ((fc || q == 1) ? 0.0 : Lam[q * C.Ntot + c]);
   for (int d = 0; d < 3; d++) {
     if (C.n[d] == 1) continue;
     for (int s = -1; s <= 1; s += 2) {
@@ -370,19 +384,23 @@ DEV void adj_fixup_at(Ctx C, const int* __restrict__ st, const double* __restric
       nb[d] += s;
       if (!interior_idx(C, nb)) continue;
       const long f = c + s * C.st[d];
-      if (!failed_at(st, f)) continue;
+      if (!bad_at(st, f)) continue;
       bool good_pass;
       const int cnt = fixup_count(C, st, nb, good_pass);
-      if (cnt == 0 || (good_pass && fc)) continue;
+      if (cnt == 0 || (good_pass && bc)) continue;
       const double w = 1.0 / cnt;
+      if (failed_at(st, f)) {
 #pragma unroll
-      for (int q = 0; q < 12; q++) acc[q] += w * Lam[q * C.Ntot + f];
+        for (int q = 0; q < 12; q++) acc[q] += w * Lam[q * C.Ntot + f];
+      } else {
+        acc[1] += w * Lam[1 * C.Ntot + f];
+      }
     }
   }
 #pragma unroll
   for (int q = 0; q < 12; q++) {
     lamPpre[q * C.Ntot + c] = acc[q];
-    lamUpre[q * C.Ntot + c] = fc ? 0.0 : lamU[q * C.Ntot + c];
+    lamUpre[q * C.Ntot + c] = fixed ? 0.0 : lamU[q * C.Ntot + c];
   }
 }
 

@@ -953,6 +953,29 @@ extern "C" int grrmhd_bc_vjp(grrmhd_grid* g, double* gP) {
   return adj_bc(g, gP);
 }
 
+extern "C" int grrmhd_fixup_vjp(grrmhd_grid* g, const double* P, const int* status,
+                                const double* gP, const double* gU, double* gP_pre,
+                                double* gU_pre, double* scratch) {
+  NEEDG();
+  if (!P || !status || !gP || !gU || !gP_pre || !gU_pre || !scratch)
+    return fail(GRRMHD_EINVAL, "NULL array");
+  if (gP_pre == gP || gP_pre == gU || gU_pre == gP || gU_pre == gU || scratch == gP ||
+      scratch == gU || scratch == gP_pre || scratch == gU_pre || gP_pre == gU_pre)
+    return fail(GRRMHD_EINVAL, "fixup_vjp arrays must not alias");
+  const Ctx& C = g->C;
+  const size_t N12 = 12 * (size_t)C.Ntot;
+  const long nint = n_interior(C);
+  int rc;
+  if ((rc = fill_d(g, gP_pre, N12, 0.0)) || (rc = fill_d(g, gU_pre, N12, 0.0))) return rc;
+  hipLaunchKernelGGL(k_adj_fixup_own, dim3(nblocks(nint, 128)), dim3(128), 0, g->stream, C, P,
+                     status, gP, gU, scratch);
+  LAUNCHCHK();
+  hipLaunchKernelGGL(k_adj_fixup, dim3(nblocks(nint, 256)), dim3(256), 0, g->stream, C, status,
+                     (const double*)scratch, gP, gU, gP_pre, gU_pre);
+  LAUNCHCHK();
+  return 0;
+}
+
 extern "C" int grrmhd_step_adjoint(grrmhd_grid* g, const double* P_n, const double* chi_abs,
                                    const double* chi_es, const double* dt_dev,
                                    const double* gU_next, double* gP_n, double* g_chi,

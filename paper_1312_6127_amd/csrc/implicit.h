@@ -772,8 +772,32 @@ DEV void newton_cold(const Cell& c, const Phys& ph, const Opts& o, const double 
   }
 }
 
-// Cold attempt for a cell with no energy solution: u_g at the floor, u~^i
-// from the prior primitives.  On success (e_T within tol_fail) `out` holds
+// Conditions of the cold attempt (Sec. 4.11, backups), on the prior
+// primitives and the explicit gas state t^t_mu (T^t_mu with rho0 u^t in the
+// energy slot): u_g < 0.1 rho0 u^i u_i and |t^t_t t^{tt}| < 0.1 |t^t_i t^{ti}|
+// (the gas cold against its motion, its energy small against its momentum).
+// The paper's condition on R^t_t R^{tt} against R^t_i R^{ti} cannot hold for
+// an M1 state (|F| <= E) and is not applied.
+DEV bool cold_allowed(const Cell& c, const double Pg[12]) {
+  Vel<double> u;
+  make_vel(c.m, Pg + 2, u);
+  const double usp = u.ucon[1] * u.ucov[1] + u.ucon[2] * u.ucov[2] + u.ucon[3] * u.ucov[3];
+  if (!(Pg[1] < 0.1 * Pg[0] * ::fabs(usp))) return false;
+  double en = 0.0, mo = 0.0;
+#pragma unroll
+  for (int a = 0; a < 4; a++) {
+    double t = 0.0;
+#pragma unroll
+    for (int b = 0; b < 4; b++) t += c.m.up(a, b) * c.Tgi[b];
+    if (a == 0) en = c.Tgi[0] * t;
+    else mo += c.Tgi[a] * t;
+  }
+  return ::fabs(en) < 0.1 * ::fabs(mo);
+}
+
+// Cold attempt for a cell with no energy solution that meets the
+// conditions above: u_g at the floor, u~^i from the prior primitives.  On
+// success (e_T within tol_fail) `out` holds
 // the solution with the set-up's status bits (EXTREME, C2P_FAIL) and COLD
 // (TYPE2/BASIC/NOT_ACCEPT as for PMHD); iters accumulates either way.
 DEV bool cold_cell(const Metric& m, const Phys& ph, const Opts& o, const double Ui[12],
@@ -782,6 +806,7 @@ DEV bool cold_cell(const Metric& m, const Phys& ph, const Opts& o, const double 
   Cell c;
   Prep pr;
   prepare(m, ph, Ui, Pg, dt, chi_abs, chi_es, c, pr);
+  if (!cold_allowed(c, Pg)) return false;
   c.cold = 1;
   const double x0[4] = {o.u_floor, Pg[2], Pg[3], Pg[4]};
   Best b;

@@ -1233,8 +1233,10 @@ __global__ void LB(256) k_stage_m(Ctx C, const double* __restrict__ Ue,
 }
 
 // ---------------------------------------------------------------------------
-// step 13 and floors.  Pass 1 averages failed cells' face neighbours into
-// scratch; pass 2 applies averages and floors and recomputes U where P changed.
+// step 13 and floors (Sec. 4.11).  Pass 1 averages the face neighbours of
+// failed and cold cells into scratch (neighbours with a good energy solution,
+// else all); pass 2 applies them (all primitives of a failed cell, u_g alone
+// of a cold one) and the floors, and recomputes U where P changed.
 // ---------------------------------------------------------------------------
 DEV void fixup_avg_at(Ctx C, const double* __restrict__ P,
                                     const int* __restrict__ status, double* __restrict__ scr, long t) {
@@ -1246,7 +1248,7 @@ DEV void fixup_avg_at(Ctx C, const double* __restrict__ P,
   idx[1] = C.ng[1] + t2 % C.n[1];
   idx[2] = C.ng[2] + t2 / C.n[1];
   const long c = cell_index(C, idx[0], idx[1], idx[2]);
-  if (!(status[c] & GRRMHD_ST_FAIL)) return;
+  if (!(status[c] & (GRRMHD_ST_FAIL | GRRMHD_ST_COLD))) return;
   for (int pass = 0; pass < 2; pass++) {
     double acc[12];
 #pragma unroll
@@ -1258,7 +1260,7 @@ DEV void fixup_avg_at(Ctx C, const double* __restrict__ P,
         const int nid = idx[d] + s;
         if (nid < C.ng[d] || nid >= C.ng[d] + C.n[d]) continue;
         const long nb = c + s * C.st[d];
-        if (pass == 0 && (status[nb] & GRRMHD_ST_FAIL)) continue;
+        if (pass == 0 && (status[nb] & (GRRMHD_ST_FAIL | GRRMHD_ST_COLD))) continue;
 #pragma unroll
         for (int q = 0; q < 12; q++) acc[q] += P[q * C.Ntot + nb];
         cnt++;
@@ -1294,9 +1296,12 @@ DEV void fixup_apply_at(Ctx C, double* __restrict__ P, double* __restrict__ U,
   int st = status[c];
   double p[12];
   bool changed = false;
-  if ((st & GRRMHD_ST_FAIL) && scr[12 * C.Ntot + c] > 0.0) {
+  const bool fail = (st & GRRMHD_ST_FAIL) != 0;
+  const bool cold = !fail && (st & GRRMHD_ST_COLD);
+  if ((fail || cold) && scr[12 * C.Ntot + c] > 0.0) {
+    // failed: the neighbours' mean primitives; cold: their mean u_g alone
 #pragma unroll
-    for (int q = 0; q < 12; q++) p[q] = scr[q * C.Ntot + c];
+    for (int q = 0; q < 12; q++) p[q] = (fail || q == 1) ? scr[q * C.Ntot + c] : P[q * C.Ntot + c];
     if (scr[12 * C.Ntot + c] > 1.5) st |= GRRMHD_ST_NO_GOOD_NB;
     changed = true;
   } else {

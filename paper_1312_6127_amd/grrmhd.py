@@ -99,6 +99,7 @@ def lib():
             "grrmhd_con2prim": (C.c_int, [_VP] + [_VP] * 4),
             "grrmhd_implicit_grid": (C.c_int, [_VP, _VP, _VP, C.c_double] + [_VP] * 8),
             "grrmhd_fixup": (C.c_int, [_VP] * 5),
+            "grrmhd_fixup_vjp": (C.c_int, [_VP] * 8),
             "grrmhd_step": (C.c_int, [_VP, _VP, _VP, _VP, _VP, _VP, C.c_int, _VP, _VP, _VP,
                                       C.c_size_t]),
             "grrmhd_adjoint_workspace_bytes": (C.c_size_t, [_VP]),
@@ -303,6 +304,17 @@ class Grid:
         scratch = torch.zeros((13, self.N), dtype=torch.float64, device=P.device)
         _check(lib().grrmhd_fixup(self.h, _ptr(P), _ptr(U), _ptr(status), _ptr(scratch)))
         return P, U, status
+
+    def fixup_vjp(self, P, status, gP, gU):
+        """Cotangents of grrmhd_fixup's input P, U for output cotangents gP, gU
+        (P, status: the fix-up's result)."""
+        self._sync_stream()
+        gPp = torch.empty_like(gP)
+        gUp = torch.empty_like(gU)
+        scratch = torch.empty((12, self.N), dtype=torch.float64, device=P.device)
+        _check(lib().grrmhd_fixup_vjp(self.h, _ptr(P), _ptr(status), _ptr(gP), _ptr(gU), _ptr(gPp),
+                                      _ptr(gUp), _ptr(scratch)))
+        return gPp, gUp
 
     def step(self, P, U, chi_abs, chi_es, dt, dt_fixed=False, status=None, iters=None):
         """One step of the grid's scheme in place on P, U; dt is a 1-element device

@@ -7,7 +7,10 @@ after the cascade), the switch that turns it off, and the implicit VJP on
 cold cells (u_g held, energy equation dropped) against central differences.
 Inputs: the batched-cell recipe with 30% of the radiation energy moved out
 of the gas, which leaves radiation-dominated cells with a negative explicit
-gas energy (no energy root when the coupling is weak)."""
+gas energy (no energy root when the coupling is weak); for the cold limit
+itself the gas flows are slowed (u~ below 0.7) so that some of those cells
+meet the attempt's conditions (gas cold against its motion, its energy
+small against its momentum)."""
 import sys
 
 import numpy as np
@@ -42,8 +45,8 @@ def host(t):
     return t.cpu().numpy()
 
 
-def batch_case(orc, n, seed):
-    pd, P, dt, ca, ce = I.implicit_batch(n, seed=seed)
+def batch_case(orc, n, seed, **kw):
+    pd, P, dt, ca, ce = I.implicit_batch(n, seed=seed, **kw)
     g0 = orc.geom(pd, 0.0, 0.0)
     U = np.stack([orc.p2u(pd, g0, P[:, c]) for c in range(n)], axis=1)
     Ui = U.copy()
@@ -63,7 +66,7 @@ def check_cold_parity(pd, Pg, Ug, stg, errg, Pr, Ur, str_, ST_COLD, ST_FAIL):
         f"failed: GPU {((stg & ST_FAIL) != 0).sum()}, oracle {((str_ & ST_FAIL) != 0).sum()}")
     assert (cg == cr).mean() > 0.98
     both = cg & cr
-    assert both.sum() > 20
+    assert both.sum() > 15
     assert np.all(Pg[1, both] == pd["u_floor"]) and np.all(Pr[1, both] == pd["u_floor"])
     good = both & (errg < 1e-11)
     assert good.sum() > 0.9 * both.sum(), (good.sum(), both.sum())
@@ -77,8 +80,8 @@ def check_cold_parity(pd, Pg, Ug, stg, errg, Pr, Ur, str_, ST_COLD, ST_FAIL):
 
 def test_cold_batch_against_oracle(G, orc):
     say("case cold batch")
-    n = 3001
-    pd, P, dt, ca, ce, Ui = batch_case(orc, n, 4)
+    n = 20000
+    pd, P, dt, ca, ce, Ui = batch_case(orc, n, 4, ugas_scale=0.14)
     Pr, Ur, itr, str_ = orc.implicit_batch(pd, Ui, P, dt, ca, ce)
     args = [dev(a) for a in (Ui, P, dt, ca, ce)]
     ref = None
@@ -110,12 +113,12 @@ def test_cold_switched_off(G, orc):
     assert fails.sum() > 20 and (fails == ((str_ & G.ST_FAIL) != 0)).mean() > 0.98
 
 
-def grid_case(orc, seed, n3=(16, 8, 4)):
+def grid_case(orc, seed, n3=(32, 16, 8)):
     """The batched-cell recipe laid out on the interior of a flat grid (ghost
     cells hold the first cell's state; the implicit solve reads interior
     cells only); dt = 1 for every cell."""
     nint = n3[0] * n3[1] * n3[2]
-    pdb, P, dt, ca, ce, Ui = batch_case(orc, nint, seed)
+    pdb, P, dt, ca, ce, Ui = batch_case(orc, nint, seed, ugas_scale=0.14)
     pd = dict(pdb, n=n3)
     na = I.nalloc(pd)
     nall = int(np.prod(na))
@@ -158,7 +161,7 @@ def test_cold_implicit_vjp_against_fd(G, orc):
     sth = host(st)
     idx = np.flatnonzero(m)
     cold = idx[(sth[idx] & G.ST_COLD) != 0]
-    assert cold.size > 20
+    assert cold.size > 15
     r = np.random.default_rng(3)
     lp, lu = np.zeros_like(P), np.zeros_like(P)
     lp[:, idx] = r.standard_normal((12, idx.size))

@@ -1,0 +1,133 @@
+"""Fix-ups (Sec. 4.11) on the GPU, through the C ABI: failed cells take the
+mean primitives of their good face neighbours (all of them if none is good),
+cold cells that mean for u_g alone, then floors and U = U(P) where P changed.
+The forward against the FP64 oracle on a Kerr-Schild grid with a seeded
+pattern of failed and cold cells, and the transpose (grrmhd_fixup_vjp)
+against central differences of the GPU fix-up itself."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1312_6127_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def G():
+    from paper_1312_6127_amd import grrmhd
+
+    grrmhd.lib()
+    assert torch.cuda.is_available()
+    return grrmhd
+
+
+def dev(x):
+    return torch.tensor(np.ascontiguousarray(x), device="cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def case(orc, seed, ffail=0.12, fcold=0.10):
+    """12x8x4 Kerr-Schild disk state (jittered), a seeded fraction of the
+    interior cells failed and another cold; no floor binds in this state."""
+    pd, P, ca, ce = I.accretion_disk(n=(12, 8, 4), seed=3)
+    P = I.jitter(P, 11)
+    U = orc.prim_to_cons(pd, P)
+    m = np.zeros(I.nalloc(pd)[::-1], dtype=bool)
+    m[I.interior(pd)] = True
+    idx = np.flatnonzero(m.reshape(-1))
+    r = np.random.default_rng(seed)
+    st = np.zeros(P.shape[1], dtype=np.int32)
+    u = r.uniform(size=idx.size)
+    st[idx[u < ffail]] = orc.ST_FAIL | orc.ST_PMHD
+    st[idx[(u >= ffail) & (u < ffail + fcold)]] = orc.ST_COLD
+    return pd, P, U, st, idx
+
+
+# sparse pattern; dense pattern where some cells have no good neighbour
+PATTERNS = [(1, 0.12, 0.10), (3, 0.45, 0.35)]
+
+
+@pytest.mark.parametrize("seed,ffail,fcold", PATTERNS)
+def test_fixup_against_oracle(G, orc, seed, ffail, fcold):
+    say("case fixup parity", seed)
+    pd, P, U, st, idx = case(orc, seed, ffail, fcold)
+    Pr, Ur, str_ = orc.fixup(pd, P, U, st)
+    assert not np.any(str_[idx] & orc.ST_FLOOR)
+    if ffail > 0.3:
+        assert np.any(str_[idx] & orc.ST_NO_GOOD_NB)
+    g = G.Grid(pd)
+    Pt, Ut, stt = dev(P), dev(U), dev(st)
+    g.fixup(Pt, Ut, stt)
+    Pg, Ug, stg = host(Pt), host(Ut), host(stt)
+    assert np.array_equal(stg[idx], str_[idx])
+    for q in range(12):
+        sc = np.abs(Pr[q, idx]).max()
+        assert np.abs(Pg[q, idx] - Pr[q, idx]).max() <= 1e-14 * sc, q
+        sc = np.abs(Ur[q, idx]).max()
+        assert np.abs(Ug[q, idx] - Ur[q, idx]).max() <= 1e-13 * sc, q
+    # the cells that neither failed nor went cold are untouched
+    ok = idx[(st[idx] & (orc.ST_FAIL | orc.ST_COLD)) == 0]
+    assert np.array_equal(Pg[:, ok], P[:, ok]) and np.array_equal(Ug[:, ok], U[:, ok])
+    g.close()
+
+
+@pytest.mark.parametrize("seed,ffail,fcold", PATTERNS)
+def test_fixup_vjp_against_fd(G, orc, seed, ffail, fcold):
+    say("case fixup vjp", seed)
+    pd, P, U, st, idx = case(orc, seed + 1, ffail, fcold)
+    g = G.Grid(pd)
+    Pt, Ut, stt = dev(P), dev(U), dev(st)
+    g.fixup(Pt, Ut, stt)
+    r = np.random.default_rng(4)
+    gP, gU = np.zeros_like(P), np.zeros_like(P)
+    gP[:, idx] = r.standard_normal((12, idx.size))
+    gU[:, idx] = r.standard_normal((12, idx.size))
+    gPp, gUp = (host(x) for x in g.fixup_vjp(Pt, stt, dev(gP), dev(gU)))
+    ghosts = np.setdiff1d(np.arange(P.shape[1]), idx)
+    assert np.all(gPp[:, ghosts] == 0.0) and np.all(gUp[:, ghosts] == 0.0)
+
+    def L(Pin, Uin):
+        Pq, Uq, sq = dev(Pin), dev(Uin), dev(st)
+        g.fixup(Pq, Uq, sq)
+        return host(Pq), host(Uq)
+
+    bad = idx[(st[idx] & (orc.ST_FAIL | orc.ST_COLD)) != 0]
+    na = I.nalloc(pd)
+    near = np.unique(np.concatenate([bad + s for s in (-1, 1, -na[0], na[0], -na[0] * na[1], na[0] * na[1])]))
+    near = np.intersect1d(near, idx)
+    scale = np.abs(P[:, idx]).max(axis=1)
+    uscale = np.abs(U[:, idx]).max(axis=1)
+    adj, fd = [], []
+    for k in range(60):
+        which = k % 2          # 0: perturb P, 1: perturb U
+        pool = near if k % 3 else idx
+        q, c = int(r.integers(12)), int(pool[r.integers(pool.size)])
+        base = P if which == 0 else U
+        # the averaging is linear and U(P) smooth, so a larger step loses
+        # nothing to truncation; 1e-7 loses digits to rounding where a field
+        # is small against the conserved energy it feeds
+        h = 1e-5 * max(abs(base[q, c]), 1e-3 * (scale if which == 0 else uscale)[q])
+        outs = []
+        for s in (1, -1):
+            Pp, Up = P.copy(), U.copy()
+            (Pp if which == 0 else Up)[q, c] += s * h
+            outs.append(L(Pp, Up))
+        fd.append((((outs[0][0] - outs[1][0]) * gP).sum() + ((outs[0][1] - outs[1][1]) * gU).sum()) / (2 * h))
+        adj.append((gPp if which == 0 else gUp)[q, c])
+    adj, fd = np.array(adj), np.array(fd)
+    e = np.linalg.norm(adj - fd) / np.linalg.norm(fd)
+    say(f"  fixup vjp: {adj.size} components, norm error {e:.3e}")
+    assert e < 1e-7
+    g.close()
