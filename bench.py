@@ -47,7 +47,7 @@ STEP_BYTES_PER_ZONE = 1344
 # traffic is reported as null and the flop figure as stale.
 FLOPS_PER_TRIP = 1732.0
 HBM_BYTES_PER_LAUNCH = 159.4e6
-KERNEL_DIGEST = "dd98b491d543d8fc"
+KERNEL_DIGEST = "3e3352d05f59fa99"
 
 
 def parse():

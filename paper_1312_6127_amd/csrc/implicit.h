@@ -606,8 +606,9 @@ struct Prep {
   bool extreme;
 };
 
-DEV void prepare(const Metric& m, const Phys& ph, const double Ui[12], const double Pg[12], double dt,
-                 double chi_abs, double chi_es, Cell& c, Prep& pr) {
+// The cell's explicit state per sqrt(-g) and its coefficients.
+DEV void cell_setup(const Metric& m, const double Ui[12], double dt, double chi_abs,
+                    double chi_es, Cell& c) {
   c.m = m;
   const double igd = 1.0 / m.gdet;
   c.rhout = Ui[0] * igd;
@@ -622,6 +623,11 @@ DEV void prepare(const Metric& m, const Phys& ph, const double Ui[12], const dou
   c.chi_abs = chi_abs;
   c.chi_es = chi_es;
   c.cold = 0;
+}
+
+DEV void prepare(const Metric& m, const Phys& ph, const double Ui[12], const double Pg[12], double dt,
+                 double chi_abs, double chi_es, Cell& c, Prep& pr) {
+  cell_setup(m, Ui, dt, chi_abs, chi_es, c);
   pr.status = 0;
   // extreme radiation sub-dominance: R^t_t against the gas energy, or the
   // gas-frame radiation energy of the guess against u_g, below 10 eps
@@ -804,9 +810,10 @@ DEV bool cold_cell(const Metric& m, const Phys& ph, const Opts& o, const double 
                    const double Pg[12], double dt, double chi_abs, double chi_es, int& iters,
                    CellOut& out) {
   Cell c;
-  Prep pr;
-  prepare(m, ph, Ui, Pg, dt, chi_abs, chi_es, c, pr);
+  cell_setup(m, Ui, dt, chi_abs, chi_es, c);
   if (!cold_allowed(c, Pg)) return false;
+  Prep pr;   // the set-up's status bits (EXTREME, C2P_FAIL) for the output
+  prepare(m, ph, Ui, Pg, dt, chi_abs, chi_es, c, pr);
   c.cold = 1;
   const double x0[4] = {o.u_floor, Pg[2], Pg[3], Pg[4]};
   Best b;

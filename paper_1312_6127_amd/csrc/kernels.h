@@ -1004,16 +1004,23 @@ __global__ void LB(64) k_implicit_batch_list(Ctx C, long n, const double* __rest
       Pg[q] = Pg_[q * n + c];
     }
     CellOut o;
-    implicit_cell(m, make_phys(C), make_opts(C), Ui, Pg, dtc[c], chi_abs[c], chi_es[c], o, &W.rec,
-                  w, false);
+    const Opts op = make_opts(C);
+    implicit_cell(m, make_phys(C), op, Ui, Pg, dtc[c], chi_abs[c], chi_es[c], o, &W.rec, w, false);
     store_out(o, c, n, Po, Uo, iters, status, err);
-    wave_append((o.status & GRRMHD_ST_FAIL) != 0, (int)c, K.counter, K.list);
+    bool cold = false;
+    if ((o.status & GRRMHD_ST_FAIL) && op.cold) {
+      Cell cl;
+      cell_setup(m, Ui, dtc[c], chi_abs[c], chi_es[c], cl);
+      cold = cold_allowed(cl, Pg);
+    }
+    wave_append(cold, (int)c, K.counter, K.list);
   }
 }
 
-// Cells of a batch left without an energy solution (listed in K by the
-// cascade kernels): the cold MHD limit, one thread each; the iterations of
-// the cell's energy attempts (in `iters`, when kept) are carried on.
+// Cells of a batch left without an energy solution that meet the cold
+// attempt's conditions (listed in K by the cascade kernels): the cold MHD
+// limit, one thread each; the iterations of the cell's energy attempts (in
+// `iters`, when kept) are carried on.
 __global__ void LB(64) k_cold_batch_list(Ctx C, long n, const double* __restrict__ Ui_,
                                          const double* __restrict__ Pg_,
                                          const double* __restrict__ dtc,
@@ -1143,7 +1150,7 @@ __global__ void LB(64) k_cascade_urad(Ctx C, long n, const double* __restrict__ 
       if (bm < 0) failed_out(Ui, Pg, pst, L.iters, out);
       else finalize(c, ph, o, best, bm, pst, L.iters, Ui, out);
       store_out(out, item, n, Po, Uo, iters, status, err);
-      failed = (out.status & GRRMHD_ST_FAIL) != 0;
+      failed = (out.status & GRRMHD_ST_FAIL) && o.cold && cold_allowed(c, Pg);
       active = false;
     }
     wave_append(failed, (int)item, K.counter, K.list);   // to the cold limit
@@ -1355,20 +1362,7 @@ __global__ void LB(256) k_fixup_apply(Ctx C, double* __restrict__ P, double* __r
 #define LBP __launch_bounds__(256, 1)
 
 DEV void setup_cell(const Metric& m, const double Ui[12], double dt, double ca, double ce, Cell& c) {
-  c.m = m;
-  const double igd = 1.0 / m.gdet;
-  c.rhout = Ui[0] * igd;
-#pragma unroll
-  for (int i = 0; i < 3; i++) c.B[i] = Ui[5 + i] * igd;
-#pragma unroll
-  for (int k = 0; k < 4; k++) {
-    c.Tgi[k] = Ui[1 + k] * igd;
-    c.Ri[k] = Ui[8 + k] * igd;
-  }
-  c.dt = dt;
-  c.chi_abs = ca;
-  c.chi_es = ce;
-  c.cold = 0;
+  cell_setup(m, Ui, dt, ca, ce, c);
 }
 
 
