@@ -235,6 +235,11 @@ def bench_adjoint(G, I, torch, dev, reps=5, warmup=2, h=1e-7):
     ms_adj = timed(lambda: g.step_adjoint(Pt, cat, cet, dt, wt))
     ms_adj_chi = timed(lambda: g.step_adjoint(Pt, cat, cet, dt, wt, want_chi=True))
     ms_fwd = timed(lambda: g.step(Pw, Uw, cat, cet, dt, dt_fixed=True))
+    # the two halves autograd uses: forward with checkpoints, then the reverse sweep alone
+    ws = g.new_adjoint_workspace()
+    ms_ckpt = timed(lambda: g.step_checkpointed(Pt, cat, cet, dt, ws))
+    ms_rev = timed(lambda: g.step_adjoint_saved(ws, cat, cet, dt, wt))
+    del ws
 
     def L(Pin):
         Pq = Pin.clone()
@@ -248,6 +253,7 @@ def bench_adjoint(G, I, torch, dev, reps=5, warmup=2, h=1e-7):
     g.close()
     return {"grid": list(n), "ms_per_adjoint": ms_adj, "ms_per_adjoint_with_opacity_grad": ms_adj_chi,
             "ms_forward_step": ms_fwd, "time_vs_forward": ms_adj / ms_fwd,
+            "ms_forward_with_checkpoints": ms_ckpt, "ms_reverse_from_checkpoints": ms_rev,
             "directional_check": {"adjoint": ad, "central_difference": fd, "h": h,
                                   "rel_diff": abs(ad - fd) / abs(fd)}}
 

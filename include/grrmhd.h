@@ -257,6 +257,22 @@ int grrmhd_step_adjoint(grrmhd_grid *g, const double *P_n, const double *chi_abs
                         double *gP_n, double *g_chi, double *P_next, double *U_next,
                         void *workspace, size_t ws_bytes);
 
+/* grrmhd_step_adjoint in two halves, for callers that run the forward step
+ * anyway (an autograd forward, then its backward): grrmhd_step_checkpointed
+ * is its forward step (P_n -> P_next, U_next, both nullable; U_next's ghost
+ * entries are U(P_n)'s), keeping the stage checkpoints in `workspace`;
+ * grrmhd_step_adjoint_saved is its reverse sweep from those checkpoints,
+ * with the same meaning of gU_next, gP_n and g_chi.  The checkpoints stay
+ * valid until `workspace` is used for anything else; the reverse sweep must
+ * be given the same grid, opacities and dt as the forward.  Workspace as for
+ * grrmhd_step_adjoint.  Errors: EINVAL, EHIP. */
+int grrmhd_step_checkpointed(grrmhd_grid *g, const double *P_n, const double *chi_abs,
+                             const double *chi_es, const double *dt_dev, double *P_next,
+                             double *U_next, void *workspace, size_t ws_bytes);
+int grrmhd_step_adjoint_saved(grrmhd_grid *g, const double *chi_abs, const double *chi_es,
+                              const double *dt_dev, const double *gU_next, double *gP_n,
+                              double *g_chi, void *workspace, size_t ws_bytes);
+
 /* Pieces of the adjoint sweep (each the transpose of the Jacobian of a
  * forward entry point; ghosts of inputs are ignored where the forward
  * ignores them):

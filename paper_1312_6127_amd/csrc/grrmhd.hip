@@ -976,6 +976,139 @@ extern "C" int grrmhd_fixup_vjp(grrmhd_grid* g, const double* P, const int* stat
   return 0;
 }
 
+// Named views of the adjoint workspace.
+struct AdjPtrs {
+  double *F, *emf, *vch, *scr, *err, *Un, *Pb, *Ue, *Pk, *Uk;
+  double *lamP, *lamU, *lamUe, *lamUn, *lamPb, *lamE, *G, *Gx, *Lam, *lamPpre, *lamUpre;
+  int *it, *stk;
+};
+
+static int adj_ptrs(grrmhd_grid* g, void* workspace, size_t ws_bytes, AdjPtrs& a) {
+  if (g->p.scheme != GRRMHD_RK3 || g->p.recon != GRRMHD_RECON_MC)
+    return fail(GRRMHD_EINVAL, "the adjoint covers the RK3 scheme with MC reconstruction");
+  const AdjLayout w = adj_layout(g->C);
+  if (ws_bytes < w.total) return fail(GRRMHD_EINVAL, "workspace too small");
+  if (((uintptr_t)workspace) & 255) return fail(GRRMHD_EINVAL, "workspace must be 256-byte aligned");
+  char* base = (char*)workspace;
+  a.F = (double*)(base + w.F);
+  a.emf = (double*)(base + w.emf);
+  a.vch = (double*)(base + w.vch);
+  a.scr = (double*)(base + w.scr);
+  a.err = (double*)(base + w.err);
+  a.it = (int*)(base + w.it);
+  a.Un = (double*)(base + w.Un);
+  a.Pb = (double*)(base + w.Pb);
+  a.Ue = (double*)(base + w.Ue);
+  a.Pk = (double*)(base + w.Pk);
+  a.Uk = (double*)(base + w.Uk);
+  a.stk = (int*)(base + w.stk);
+  a.lamP = (double*)(base + w.lamP);
+  a.lamU = (double*)(base + w.lamU);
+  a.lamUe = (double*)(base + w.lamUe);
+  a.lamUn = (double*)(base + w.lamUn);
+  a.lamPb = (double*)(base + w.lamPb);
+  a.lamE = (double*)(base + w.lamE);
+  a.G = (double*)(base + w.G);
+  a.Gx = (double*)(base + w.Gx);
+  a.Lam = (double*)(base + w.Lam);
+  a.lamPpre = (double*)(base + w.lamPpre);
+  a.lamUpre = (double*)(base + w.lamUpre);
+  return 0;
+}
+
+static const double ADJ_A[3] = {1.0, 0.75, 1.0 / 3.0}, ADJ_B[3] = {0.0, 0.25, 2.0 / 3.0},
+                    ADJ_C[3] = {1.0, 0.25, 2.0 / 3.0};
+
+// Forward step with checkpoints (the same launches as grrmhd_step, dt fixed):
+// per stage the ghost-filled input P, the explicit state, the output P, U
+// and status.  P_next/U_next (nullable) get the result; U_next's ghost
+// entries are those of U(P_n), as grrmhd_step leaves them.
+static int adj_forward(grrmhd_grid* g, const double* P_n, const double* chi_abs,
+                       const double* chi_es, const double* dt_dev, double* P_next, double* U_next,
+                       const AdjPtrs& a) {
+  const Ctx& C = g->C;
+  const size_t N = (size_t)C.Ntot, N12 = 12 * N, B12 = sizeof(double) * N12;
+  hipStream_t s = g->stream;
+  int rc;
+  HIPCHK(hipMemcpyAsync(a.Pb, P_n, B12, hipMemcpyDeviceToDevice, s));
+  hipLaunchKernelGGL(k_p2u, dim3(nblocks(C.Ntot, 256)), dim3(256), 0, s, C, a.Pb, a.Un);
+  LAUNCHCHK();
+  for (int k = 0; k < 3; k++) {
+    double* Pin = a.Pb + k * N12;
+    double* Uek = a.Ue + k * N12;
+    double* Pout = a.Pk + k * N12;
+    double* Uout = a.Uk + k * N12;
+    int* st = a.stk + k * N;
+    if (k > 0) HIPCHK(hipMemcpyAsync(Pin, a.Pk + (k - 1) * N12, B12, hipMemcpyDeviceToDevice, s));
+    if ((rc = launch_bc(g, Pin))) return rc;
+    if ((rc = launch_fluxes(g, Pin, chi_abs, chi_es, a.F, a.emf, a.vch))) return rc;
+    if ((rc = launch_update(g, ADJ_A[k], ADJ_B[k], ADJ_C[k], dt_dev, Pin, a.Un,
+                            k == 0 ? a.Un : a.Uk + (k - 1) * N12, a.F, a.emf, Uek)))
+      return rc;
+    HIPCHK(hipMemcpyAsync(Pout, Pin, B12, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(Uout, Uek, B12, hipMemcpyDeviceToDevice, s));
+    if ((rc = launch_implicit(g, Uek, Pin, ADJ_C[k], dt_dev, chi_abs, chi_es, Pout, Uout, a.it, st,
+                              a.err)))
+      return rc;
+    if ((rc = launch_fixup(g, Pout, Uout, st, a.scr, nullptr, a.it, nullptr, 0))) return rc;
+  }
+  if (P_next) HIPCHK(hipMemcpyAsync(P_next, a.Pk + 2 * N12, B12, hipMemcpyDeviceToDevice, s));
+  if (U_next) {   // interior of the last stage over U(P_n) (ghost entries kept)
+    HIPCHK(hipMemcpyAsync(U_next, a.Un, B12, hipMemcpyDeviceToDevice, s));
+    hipLaunchKernelGGL(k_copy_interior12, dim3(nblocks(n_interior(C), 256)), dim3(256), 0, s, C,
+                       (const double*)(a.Uk + 2 * N12), U_next);
+    LAUNCHCHK();
+  }
+  return 0;
+}
+
+// Reverse sweep over the checkpoints adj_forward left in the workspace.
+static int adj_reverse(grrmhd_grid* g, const double* chi_abs, const double* chi_es,
+                       const double* dt_dev, const double* gU_next, double* gP_n, double* g_chi,
+                       const AdjPtrs& a) {
+  const Ctx& C = g->C;
+  const size_t N = (size_t)C.Ntot, N12 = 12 * N;
+  hipStream_t s = g->stream;
+  const long nint = n_interior(C);
+  double* Gx = g_chi ? a.Gx : nullptr;
+  int rc;
+  const unsigned gi = nblocks(nint, 256), ga = nblocks(C.Ntot, 256);
+  hipLaunchKernelGGL(k_copy_interior, dim3(ga), dim3(256), 0, s, C, gU_next, a.lamU);
+  LAUNCHCHK();
+  if ((rc = fill_d(g, a.lamP, N12, 0.0)) || (rc = fill_d(g, a.lamUn, N12, 0.0))) return rc;
+  if (g_chi && (rc = fill_d(g, g_chi, 2 * N, 0.0))) return rc;
+  for (int k = 2; k >= 0; k--) {
+    const double* Pin = a.Pb + k * N12;
+    // fix-up of failed and cold cells, then the implicit solve
+    hipLaunchKernelGGL(k_adj_fixup_own, dim3(nblocks(nint, 128)), dim3(128), 0, s, C,
+                       (const double*)(a.Pk + k * N12), (const int*)(a.stk + k * N),
+                       (const double*)a.lamP, (const double*)a.lamU, a.Lam);
+    LAUNCHCHK();
+    hipLaunchKernelGGL(k_adj_fixup, dim3(gi), dim3(256), 0, s, C, (const int*)(a.stk + k * N),
+                       (const double*)a.Lam, (const double*)a.lamP, (const double*)a.lamU,
+                       a.lamPpre, a.lamUpre);
+    LAUNCHCHK();
+    if ((rc = adj_implicit(g, ADJ_C[k], dt_dev, a.Ue + k * N12, a.Pk + k * N12, a.stk + k * N,
+                           chi_abs, chi_es, a.lamPpre, a.lamUpre, a.lamUe, g_chi)))
+      return rc;
+    hipLaunchKernelGGL(k_adj_stage, dim3(gi), dim3(256), 0, s, C, ADJ_A[k], ADJ_B[k],
+                       (const double*)a.lamUe, a.lamUn, a.lamU);
+    LAUNCHCHK();
+    if ((rc = adj_explicit(g, ADJ_C[k], dt_dev, Pin, chi_abs, chi_es, a.lamUe, a.lamE, a.G,
+                           a.lamPb, Gx, g_chi)))
+      return rc;
+    if ((rc = adj_bc(g, a.lamPb))) return rc;
+    hipLaunchKernelGGL(k_copy_interior, dim3(ga), dim3(256), 0, s, C, (const double*)a.lamPb, a.lamP);
+    LAUNCHCHK();
+  }
+  hipLaunchKernelGGL(k_adj_p2u, dim3(nblocks(nint, 128)), dim3(128), 0, s, C, (const double*)a.Pb,
+                     (const double*)a.lamUn, a.lamP);
+  LAUNCHCHK();
+  hipLaunchKernelGGL(k_copy_interior, dim3(ga), dim3(256), 0, s, C, (const double*)a.lamP, gP_n);
+  LAUNCHCHK();
+  return 0;
+}
+
 extern "C" int grrmhd_step_adjoint(grrmhd_grid* g, const double* P_n, const double* chi_abs,
                                    const double* chi_es, const double* dt_dev,
                                    const double* gU_next, double* gP_n, double* g_chi,
@@ -984,101 +1117,36 @@ extern "C" int grrmhd_step_adjoint(grrmhd_grid* g, const double* P_n, const doub
   NEEDG();
   if (!P_n || !chi_abs || !chi_es || !dt_dev || !gU_next || !gP_n || !workspace)
     return fail(GRRMHD_EINVAL, "NULL array");
-  if (g->p.scheme != GRRMHD_RK3 || g->p.recon != GRRMHD_RECON_MC)
-    return fail(GRRMHD_EINVAL, "the adjoint covers the RK3 scheme with MC reconstruction");
-  const Ctx& C = g->C;
-  const AdjLayout w = adj_layout(C);
-  if (ws_bytes < w.total) return fail(GRRMHD_EINVAL, "workspace too small");
-  if (((uintptr_t)workspace) & 255) return fail(GRRMHD_EINVAL, "workspace must be 256-byte aligned");
-  char* base = (char*)workspace;
-  const size_t N = (size_t)C.Ntot, N12 = 12 * N, B12 = sizeof(double) * N12;
-  double* F = (double*)(base + w.F);
-  double* emf = (double*)(base + w.emf);
-  double* vch = (double*)(base + w.vch);
-  double* scr = (double*)(base + w.scr);
-  double* err = (double*)(base + w.err);
-  int* it = (int*)(base + w.it);
-  double* Un = (double*)(base + w.Un);
-  double* Pb = (double*)(base + w.Pb);
-  double* Ue = (double*)(base + w.Ue);
-  double* Pk = (double*)(base + w.Pk);
-  double* Uk = (double*)(base + w.Uk);
-  int* stk = (int*)(base + w.stk);
-  double* lamP = (double*)(base + w.lamP);
-  double* lamU = (double*)(base + w.lamU);
-  double* lamUe = (double*)(base + w.lamUe);
-  double* lamUn = (double*)(base + w.lamUn);
-  double* lamPb = (double*)(base + w.lamPb);
-  double* lamE = (double*)(base + w.lamE);
-  double* G = (double*)(base + w.G);
-  double* Gx = g_chi ? (double*)(base + w.Gx) : nullptr;
-  double* Lam = (double*)(base + w.Lam);
-  double* lamPpre = (double*)(base + w.lamPpre);
-  double* lamUpre = (double*)(base + w.lamUpre);
-  hipStream_t s = g->stream;
-  const double A[3] = {1.0, 0.75, 1.0 / 3.0}, B[3] = {0.0, 0.25, 2.0 / 3.0},
-               Cc[3] = {1.0, 0.25, 2.0 / 3.0};
-  const long nint = n_interior(C);
+  AdjPtrs a;
   int rc;
-  // forward step with checkpoints (the same launches as grrmhd_step, dt fixed)
-  HIPCHK(hipMemcpyAsync(Pb, P_n, B12, hipMemcpyDeviceToDevice, s));
-  hipLaunchKernelGGL(k_p2u, dim3(nblocks(C.Ntot, 256)), dim3(256), 0, s, C, Pb, Un);
-  LAUNCHCHK();
-  for (int k = 0; k < 3; k++) {
-    double* Pin = Pb + k * N12;
-    double* Uek = Ue + k * N12;
-    double* Pout = Pk + k * N12;
-    double* Uout = Uk + k * N12;
-    int* st = stk + k * N;
-    if (k > 0) HIPCHK(hipMemcpyAsync(Pin, Pk + (k - 1) * N12, B12, hipMemcpyDeviceToDevice, s));
-    if ((rc = launch_bc(g, Pin))) return rc;
-    if ((rc = launch_fluxes(g, Pin, chi_abs, chi_es, F, emf, vch))) return rc;
-    if ((rc = launch_update(g, A[k], B[k], Cc[k], dt_dev, Pin, Un, k == 0 ? Un : Uk + (k - 1) * N12,
-                            F, emf, Uek)))
-      return rc;
-    HIPCHK(hipMemcpyAsync(Pout, Pin, B12, hipMemcpyDeviceToDevice, s));
-    HIPCHK(hipMemcpyAsync(Uout, Uek, B12, hipMemcpyDeviceToDevice, s));
-    if ((rc = launch_implicit(g, Uek, Pin, Cc[k], dt_dev, chi_abs, chi_es, Pout, Uout, it, st, err)))
-      return rc;
-    if ((rc = launch_fixup(g, Pout, Uout, st, scr, nullptr, it, nullptr, 0))) return rc;
-  }
-  if (P_next) HIPCHK(hipMemcpyAsync(P_next, Pk + 2 * N12, B12, hipMemcpyDeviceToDevice, s));
-  if (U_next) HIPCHK(hipMemcpyAsync(U_next, Uk + 2 * N12, B12, hipMemcpyDeviceToDevice, s));
-  // reverse sweep
-  const unsigned gi = nblocks(nint, 256), ga = nblocks(C.Ntot, 256);
-  hipLaunchKernelGGL(k_copy_interior, dim3(ga), dim3(256), 0, s, C, gU_next, lamU);
-  LAUNCHCHK();
-  if ((rc = fill_d(g, lamP, N12, 0.0)) || (rc = fill_d(g, lamUn, N12, 0.0))) return rc;
-  if (g_chi && (rc = fill_d(g, g_chi, 2 * N, 0.0))) return rc;
-  for (int k = 2; k >= 0; k--) {
-    const double* Pin = Pb + k * N12;
-    // fix-up of failed cells, then the implicit solve
-    hipLaunchKernelGGL(k_adj_fixup_own, dim3(nblocks(nint, 128)), dim3(128), 0, s, C,
-                       (const double*)(Pk + k * N12), (const int*)(stk + k * N), (const double*)lamP,
-                       (const double*)lamU, Lam);
-    LAUNCHCHK();
-    hipLaunchKernelGGL(k_adj_fixup, dim3(gi), dim3(256), 0, s, C, (const int*)(stk + k * N),
-                       (const double*)Lam, (const double*)lamP, (const double*)lamU, lamPpre, lamUpre);
-    LAUNCHCHK();
-    if ((rc = adj_implicit(g, Cc[k], dt_dev, Ue + k * N12, Pk + k * N12, stk + k * N, chi_abs,
-                           chi_es, lamPpre, lamUpre, lamUe, g_chi)))
-      return rc;
-    hipLaunchKernelGGL(k_adj_stage, dim3(gi), dim3(256), 0, s, C, A[k], B[k], (const double*)lamUe,
-                       lamUn, lamU);
-    LAUNCHCHK();
-    if ((rc = adj_explicit(g, Cc[k], dt_dev, Pin, chi_abs, chi_es, lamUe, lamE, G, lamPb, Gx,
-                           g_chi)))
-      return rc;
-    if ((rc = adj_bc(g, lamPb))) return rc;
-    hipLaunchKernelGGL(k_copy_interior, dim3(ga), dim3(256), 0, s, C, (const double*)lamPb, lamP);
-    LAUNCHCHK();
-  }
-  hipLaunchKernelGGL(k_adj_p2u, dim3(nblocks(nint, 128)), dim3(128), 0, s, C, (const double*)Pb,
-                     (const double*)lamUn, lamP);
-  LAUNCHCHK();
-  hipLaunchKernelGGL(k_copy_interior, dim3(ga), dim3(256), 0, s, C, (const double*)lamP, gP_n);
-  LAUNCHCHK();
-  return 0;
+  if ((rc = adj_ptrs(g, workspace, ws_bytes, a))) return rc;
+  if ((rc = adj_forward(g, P_n, chi_abs, chi_es, dt_dev, P_next, U_next, a))) return rc;
+  return adj_reverse(g, chi_abs, chi_es, dt_dev, gU_next, gP_n, g_chi, a);
+}
+
+extern "C" int grrmhd_step_checkpointed(grrmhd_grid* g, const double* P_n, const double* chi_abs,
+                                        const double* chi_es, const double* dt_dev,
+                                        double* P_next, double* U_next, void* workspace,
+                                        size_t ws_bytes) {
+  NEEDG();
+  if (!P_n || !chi_abs || !chi_es || !dt_dev || !workspace) return fail(GRRMHD_EINVAL, "NULL array");
+  AdjPtrs a;
+  int rc;
+  if ((rc = adj_ptrs(g, workspace, ws_bytes, a))) return rc;
+  return adj_forward(g, P_n, chi_abs, chi_es, dt_dev, P_next, U_next, a);
+}
+
+extern "C" int grrmhd_step_adjoint_saved(grrmhd_grid* g, const double* chi_abs,
+                                         const double* chi_es, const double* dt_dev,
+                                         const double* gU_next, double* gP_n, double* g_chi,
+                                         void* workspace, size_t ws_bytes) {
+  NEEDG();
+  if (!chi_abs || !chi_es || !dt_dev || !gU_next || !gP_n || !workspace)
+    return fail(GRRMHD_EINVAL, "NULL array");
+  AdjPtrs a;
+  int rc;
+  if ((rc = adj_ptrs(g, workspace, ws_bytes, a))) return rc;
+  return adj_reverse(g, chi_abs, chi_es, dt_dev, gU_next, gP_n, g_chi, a);
 }
 
 // Workspace of the batched solve: [0, 256) counters (list length @0, queue

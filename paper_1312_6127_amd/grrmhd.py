@@ -104,6 +104,8 @@ def lib():
                                       C.c_size_t]),
             "grrmhd_adjoint_workspace_bytes": (C.c_size_t, [_VP]),
             "grrmhd_step_adjoint": (C.c_int, [_VP] * 11 + [C.c_size_t]),
+            "grrmhd_step_checkpointed": (C.c_int, [_VP] * 8 + [C.c_size_t]),
+            "grrmhd_step_adjoint_saved": (C.c_int, [_VP] * 8 + [C.c_size_t]),
             "grrmhd_implicit_vjp": (C.c_int, [_VP, _VP, _VP, _VP, C.c_double] + [_VP] * 6),
             "grrmhd_explicit_vjp_workspace_bytes": (C.c_size_t, [_VP]),
             "grrmhd_explicit_vjp": (C.c_int, [_VP, C.c_double] + [_VP] * 7 + [C.c_size_t]),
@@ -238,13 +240,39 @@ class Grid:
         _check(lib().grrmhd_implicit_stats(self.h, out))
         return tuple(int(v) for v in out)
 
+    def new_adjoint_workspace(self):
+        """A fresh 256-byte aligned adjoint workspace: (tensor, bytes)."""
+        nb = lib().grrmhd_adjoint_workspace_bytes(self.h)
+        raw = torch.empty(nb + 256, dtype=torch.uint8, device="cuda")
+        off = (-raw.data_ptr()) % 256
+        return raw[off:off + nb], nb
+
     def adjoint_workspace(self):
         if getattr(self, "_aws", None) is None:
-            nb = lib().grrmhd_adjoint_workspace_bytes(self.h)
-            raw = torch.empty(nb + 256, dtype=torch.uint8, device="cuda")
-            off = (-raw.data_ptr()) % 256
-            self._aws = (raw[off:off + nb], nb)
+            self._aws = self.new_adjoint_workspace()
         return self._aws
+
+    def step_checkpointed(self, P, chi_abs, chi_es, dt, ws=None):
+        """The forward half of step_adjoint (dt held fixed): returns P^{n+1},
+        U^{n+1} and the workspace holding the stage checkpoints (a fresh one
+        unless given), for step_adjoint_saved."""
+        self._sync_stream()
+        ws = self.new_adjoint_workspace() if ws is None else ws
+        Pn = torch.empty_like(P)
+        Un = torch.empty_like(P)
+        _check(lib().grrmhd_step_checkpointed(self.h, _ptr(P), _ptr(chi_abs), _ptr(chi_es), _ptr(dt),
+                                              _ptr(Pn), _ptr(Un), _ptr(ws[0]), ws[1]))
+        return Pn, Un, ws
+
+    def step_adjoint_saved(self, ws, chi_abs, chi_es, dt, gU, want_chi=False):
+        """The reverse half of step_adjoint over the checkpoints in ws (from
+        step_checkpointed with the same opacities and dt)."""
+        self._sync_stream()
+        gP = torch.empty((12, self.N), dtype=torch.float64, device=gU.device)
+        gc = torch.empty((2, self.N), dtype=torch.float64, device=gU.device) if want_chi else None
+        _check(lib().grrmhd_step_adjoint_saved(self.h, _ptr(chi_abs), _ptr(chi_es), _ptr(dt),
+                                               _ptr(gU), _ptr(gP), _ptr(gc), _ptr(ws[0]), ws[1]))
+        return (gP, gc) if want_chi else gP
 
     def step_adjoint(self, P, chi_abs, chi_es, dt, gU, want_next=False, want_chi=False):
         """dL/dP^n for L = sum(gU * U^{n+1}(P^n)), dt (1-element device
@@ -404,19 +432,27 @@ def batch_cascade_stats(ws):
 
 class GRRMHDStep(torch.autograd.Function):
     """U^{n+1} = step(P^n) with dt fixed, differentiable in P^n through the
-    library's hand-written adjoint (grrmhd_step_adjoint).
+    library's hand-written adjoint.
 
-    GRRMHDStep.apply(grid, P, chi_abs, chi_es, dt) -> U_next; the backward
-    returns dL/dP at interior cells (ghost entries zero) and, where they
-    require it, dL/dchi_abs and dL/dchi_es at every allocated cell."""
+    GRRMHDStep.apply(grid, P, chi_abs, chi_es, dt[, keep_checkpoints]) ->
+    U_next; the backward returns dL/dP at interior cells (ghost entries zero)
+    and, where they require it, dL/dchi_abs and dL/dchi_es at every allocated
+    cell.  keep_checkpoints (default True): the forward keeps the stage
+    checkpoints (one adjoint workspace per call, held until the backward),
+    and the backward runs the reverse sweep alone; False: the forward keeps
+    P only and the backward recomputes the step."""
 
     @staticmethod
-    def forward(ctx, grid, P, chi_abs, chi_es, dt):
+    def forward(ctx, grid, P, chi_abs, chi_es, dt, keep_checkpoints=True):
         Pc = P.detach().contiguous()
-        Pw = Pc.clone()
-        Uw = grid.prim_to_cons(Pw)
-        grid.step(Pw, Uw, chi_abs, chi_es, dt, dt_fixed=True)
         ctx.grid = grid
+        ctx.ws = None
+        if keep_checkpoints:
+            _, Uw, ctx.ws = grid.step_checkpointed(Pc, chi_abs, chi_es, dt)
+        else:
+            Pw = Pc.clone()
+            Uw = grid.prim_to_cons(Pw)
+            grid.step(Pw, Uw, chi_abs, chi_es, dt, dt_fixed=True)
         ctx.save_for_backward(Pc, chi_abs, chi_es, dt)
         return Uw
 
@@ -424,9 +460,14 @@ class GRRMHDStep(torch.autograd.Function):
     def backward(ctx, gU):
         Pc, chi_abs, chi_es, dt = ctx.saved_tensors
         want = ctx.needs_input_grad[2] or ctx.needs_input_grad[3]
+        gU = gU.contiguous()
+        if ctx.ws is not None:
+            out = ctx.grid.step_adjoint_saved(ctx.ws, chi_abs, chi_es, dt, gU, want_chi=want)
+            ctx.ws = None
+        else:
+            out = ctx.grid.step_adjoint(Pc, chi_abs, chi_es, dt, gU, want_chi=want)
         if not want:
-            gP = ctx.grid.step_adjoint(Pc, chi_abs, chi_es, dt, gU.contiguous())
-            return None, gP, None, None, None
-        gP, gc = ctx.grid.step_adjoint(Pc, chi_abs, chi_es, dt, gU.contiguous(), want_chi=True)
+            return None, out, None, None, None, None
+        gP, gc = out
         return (None, gP, gc[0] if ctx.needs_input_grad[2] else None,
-                gc[1] if ctx.needs_input_grad[3] else None, None)
+                gc[1] if ctx.needs_input_grad[3] else None, None, None)

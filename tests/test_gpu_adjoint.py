@@ -233,10 +233,12 @@ def test_step_adjoint_kerr_schild_96x48x24(G, orc):
     _step_check(G, orc, *disk_c5(), ncomp=64, n_oracle=16, tol=1e-6)
 
 
-def test_autograd_function(G):
+@pytest.mark.parametrize("keep", [True, False])
+def test_autograd_function(G, keep):
     """GRRMHDStep: forward equals grid.step with dt fixed; backward's
-    gradient gives the directional derivative along a random direction."""
-    say("case autograd")
+    gradient (from the kept checkpoints, or recomputed) equals the entry
+    point's and gives the directional derivative along a random direction."""
+    say("case autograd, checkpoints kept", keep)
     pd, P, ca, ce = box()
     g = G.Grid(pd)
     cat, cet = dev(ca), dev(ce)
@@ -246,7 +248,11 @@ def test_autograd_function(G):
     w = np.zeros_like(P)
     w[:, idx] = r.standard_normal((12, idx.size))
     Pt = dev(P).requires_grad_(True)
-    U1 = G.GRRMHDStep.apply(g, Pt, cat, cet, dt)
+    U1 = G.GRRMHDStep.apply(g, Pt, cat, cet, dt, keep)
+    Pw = dev(P)
+    Uw = g.prim_to_cons(Pw)
+    g.step(Pw, Uw, cat, cet, dt, dt_fixed=True)
+    assert torch.equal(U1, Uw)
     L = (U1 * dev(w)).sum()
     L.backward()
     gP = host(Pt.grad)
@@ -356,6 +362,29 @@ def test_opacity_gradient_kerr_schild_96x48x24(G, orc):
     adjoint to ~2e-5: relative steps of 1e-4, bound 1e-4."""
     say("case opacity gradient, Kerr-Schild 96x48x24")
     _chi_check(G, orc, *disk_c5(), ncomp=48, n_oracle=8, tol=1e-4, rel_h=1e-4)
+
+
+def test_checkpointed_halves_equal_step_adjoint(G):
+    """grrmhd_step_checkpointed + grrmhd_step_adjoint_saved give
+    grrmhd_step_adjoint's results bit for bit, and the checkpoints serve
+    more than one reverse sweep."""
+    say("case checkpointed halves")
+    pd, P, ca, ce = disk_small()
+    g = G.Grid(pd)
+    cat, cet = dev(ca), dev(ce)
+    dt, _ = step_dt(G, g, P, cat, cet)
+    r = np.random.default_rng(11)
+    ws = None
+    Pn, Un, ws = g.step_checkpointed(dev(P), cat, cet, dt)
+    for k in range(2):
+        w = dev(r.standard_normal(P.shape))
+        gP, gc, Pr, Ur = g.step_adjoint(dev(P), cat, cet, dt, w, want_next=True, want_chi=True)
+        gPs, gcs = g.step_adjoint_saved(ws, cat, cet, dt, w, want_chi=True)
+        assert torch.equal(gP, gPs) and torch.equal(gc, gcs)
+        assert torch.equal(Pn, Pr)
+        idx = interior_idx(pd)
+        assert np.array_equal(host(Un)[:, idx], host(Ur)[:, idx])
+    g.close()
 
 
 def test_autograd_opacity(G):
