@@ -240,9 +240,16 @@ int grrmhd_step(grrmhd_grid *g, double *P, double *U, const double *chi_abs,
  * (Sec. 4.8; one transposed 4x4 solve per cell), the fluxes, EMFs, source
  * and ghost fill by their local Jacobians (dual numbers) and transposes.
  * Floors are taken as the identity; a failed cell's neighbour average is
- * differentiated (its own failed solve receives nothing).  RK3 grids with
- * MC reconstruction only (EINVAL otherwise; also for grrmhd_explicit_vjp
- * on a PPM grid).  P_n [12][N] (interior read; not modified), gU_next
+ * differentiated (its own failed solve receives nothing).  Every scheme
+ * (RK3; eq. IMEX2, IMEX2B, IMEX3): on an IMEX grid the stored
+ * sources M^k = (U(k) - U_e(k))/(g dt) are transposed with the stages that
+ * read them, and the final explicit stage's inversion is differentiated at
+ * its result (the MHD block by the implicit-function theorem, one
+ * transposed 8x8 solve per cell; the radiation block through the limited
+ * inversion itself; where the MHD inversion failed, its guess, the stage
+ * input, takes the cotangent).  MC reconstruction only (EINVAL on a PPM
+ * grid, also for grrmhd_explicit_vjp).  The workspace size depends on the
+ * scheme.  P_n [12][N] (interior read; not modified), gU_next
  * [12][N] (interior read), gP_n [12][N] out (ghosts zero); g_chi (nullable)
  * [2][N] out: dL/dchi_abs, dL/dchi_es at every allocated cell (the per-mass
  * opacities enter the implicit residual through kappa = chi rho0 and the

@@ -883,6 +883,187 @@ __global__ void LB(256) k_fill_d(double* p, long n, double v) {
 }
 
 // interior entries of src into dst, every other entry of dst cleared
+// ---------------------------------------------------------------------------
+// Pieces of the IMEX adjoint (stage tables with stored sources M^k).
+// ---------------------------------------------------------------------------
+
+// y += alpha x, 12 fields at interior cells
+__global__ void LB(256) k_adj_axpy12(Ctx C, double alpha, const double* __restrict__ x,
+                                     double* __restrict__ y) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long)C.n[0] * C.n[1] * C.n[2]) return;
+  int i, j, k;
+  interior_cell(C, t, i, j, k);
+  const long c = cell_index(C, i, j, k);
+#pragma unroll
+  for (int q = 0; q < 12; q++) y[q * C.Ntot + c] += alpha * x[q * C.Ntot + c];
+}
+
+// the stored source's rows r = 0..7 are the U slots 1-4 and 8-11
+DEV int mslot(int r) { return (r < 4) ? 1 + r : 4 + r; }
+
+// a bracket's dt m_k M^k term: lamM += dt m lamUe (rows of the 8 slots)
+__global__ void LB(256) k_adj_mterm(Ctx C, double m, const double* __restrict__ dt_dev,
+                                    const double* __restrict__ lamUe, double* __restrict__ lamM) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long)C.n[0] * C.n[1] * C.n[2]) return;
+  int i, j, k;
+  interior_cell(C, t, i, j, k);
+  const long c = cell_index(C, i, j, k);
+  const double f = m * (*dt_dev);
+#pragma unroll
+  for (int r = 0; r < 8; r++) lamM[r * C.Ntot + c] += f * lamUe[mslot(r) * C.Ntot + c];
+}
+
+// M = (U_out - U_e)/(g dt) at cells whose solve did not fail: its transpose
+// spread into one side, tgt[slot] += scale/dt lamM (scale = 1/g for U_out,
+// -1/g for U_e)
+__global__ void LB(256) k_adj_mscatter(Ctx C, double scale, const double* __restrict__ dt_dev,
+                                       const int* __restrict__ st, const double* __restrict__ lamM,
+                                       double* __restrict__ tgt) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long)C.n[0] * C.n[1] * C.n[2]) return;
+  int i, j, k;
+  interior_cell(C, t, i, j, k);
+  const long c = cell_index(C, i, j, k);
+  if (st[c] & GRRMHD_ST_FAIL) return;
+  const double f = scale / (*dt_dev);
+#pragma unroll
+  for (int r = 0; r < 8; r++) tgt[mslot(r) * C.Ntot + c] += f * lamM[r * C.Ntot + c];
+}
+
+// x = A^-T b for a small dense A, Gaussian elimination with partial
+// pivoting on A^T; rows are swapped by selects so every index is static.
+// Returns 1 if a pivot vanishes.
+template <int N>
+DEV int solve_t(const double A[N][N], const double b[N], double x[N]) {
+  double M[N][N + 1];
+#pragma unroll
+  for (int r = 0; r < N; r++) {
+#pragma unroll
+    for (int c = 0; c < N; c++) M[r][c] = A[c][r];
+    M[r][N] = b[r];
+  }
+#pragma unroll
+  for (int k = 0; k < N; k++) {
+    double best = ::fabs(M[k][k]);
+    int piv = k;
+#pragma unroll
+    for (int r = k + 1; r < N; r++) {
+      const double v = ::fabs(M[r][k]);
+      if (v > best) { best = v; piv = r; }
+    }
+    if (!(best > 0.0) || !isfinite(best)) return 1;
+#pragma unroll
+    for (int r = k + 1; r < N; r++) {
+      const bool sw = (r == piv);
+#pragma unroll
+      for (int c = k; c <= N; c++) {
+        const double a = M[k][c], bb = M[r][c];
+        M[k][c] = sw ? bb : a;
+        M[r][c] = sw ? a : bb;
+      }
+    }
+    const double ip = 1.0 / M[k][k];
+#pragma unroll
+    for (int r = k + 1; r < N; r++) {
+      const double f = M[r][k] * ip;
+#pragma unroll
+      for (int c = k; c <= N; c++) M[r][c] -= f * M[k][c];
+    }
+  }
+#pragma unroll
+  for (int r = N - 1; r >= 0; r--) {
+    double v = M[r][N];
+#pragma unroll
+    for (int c = r + 1; c < N; c++) v -= M[r][c] * x[c];
+    x[r] = v / M[r][r];
+  }
+#pragma unroll
+  for (int r = 0; r < N; r++)
+    if (!isfinite(x[r])) return 1;
+  return 0;
+}
+
+// Transpose of the final inversion P = C2P(U_e) of an IMEX step (the MHD
+// inversion, B = U_B/sqrt(-g), the radiation inversion with the BASIC
+// limiter) at its result P: lamUe += (dP/dU_e)^T lamP.  The MHD block by the
+// implicit-function theorem (P_mhd inverts the 8x8 map U_mhd(P_mhd), so its
+// Jacobian is that map's inverse); the radiation block through the limited
+// inversion itself.  Where the MHD inversion failed the cell's P_mhd was the
+// guess: its cotangent goes to lamPg instead.
+DEV void adj_c2p_at(Ctx C, const double* __restrict__ Ue, const double* __restrict__ P,
+                    const int* __restrict__ st, const double* __restrict__ lamP,
+                    double* __restrict__ lamUe, double* __restrict__ lamPg, long t) {
+  if (t >= (long)C.n[0] * C.n[1] * C.n[2]) return;
+  int i, j, k;
+  interior_cell(C, t, i, j, k);
+  const long c = cell_index(C, i, j, k);
+  Metric m;
+  load_metric(C.geo_c, C.npos, i + C.N[0] * j, m);
+  const double igd = 1.0 / m.gdet;
+  double lp[12], lu[12];
+#pragma unroll
+  for (int q = 0; q < 12; q++) {
+    lp[q] = lamP[q * C.Ntot + c];
+    lu[q] = 0.0;
+  }
+  {
+    D4 ur[4], Eb, utr[3];
+#pragma unroll
+    for (int b = 0; b < 4; b++) ur[b] = D4::var(Ue[(8 + b) * C.Ntot + c] * igd, b);
+    rad_invert(m, C.gamma_max, C.ymax, 0, ur, Eb, utr);
+    const D4 pr[4] = {Eb, utr[0], utr[1], utr[2]};
+#pragma unroll
+    for (int b = 0; b < 4; b++) {
+      double s = 0.0;
+#pragma unroll
+      for (int a = 0; a < 4; a++) s += lp[8 + a] * pr[a].d[b];
+      lu[8 + b] = s * igd;
+    }
+  }
+  if (st[c] & GRRMHD_ST_C2P_FAIL) {
+#pragma unroll
+    for (int q = 0; q < 5; q++) lamPg[q * C.Ntot + c] += lp[q];
+#pragma unroll
+    for (int q = 5; q < 8; q++) lu[q] = lp[q] * igd;
+  } else {
+    double p[12], J[8][8];
+#pragma unroll
+    for (int q = 0; q < 12; q++) p[q] = P[q * C.Ntot + c];
+#pragma unroll 1
+    for (int pass = 0; pass < 2; pass++) {
+      D4 pd[12], ud[12];
+      seed4<12>(p, 4 * pass, pd);
+      prim_to_cons_cell(m, C.gam, pd, ud);
+#pragma unroll
+      for (int a = 0; a < 8; a++)
+#pragma unroll
+        for (int jj = 0; jj < 4; jj++) {
+          const double v = ud[a].d[jj];
+#pragma unroll
+          for (int b = 0; b < 8; b++)
+            if (b == 4 * pass + jj) J[a][b] = v;
+        }
+    }
+    double b8[8], x8[8];
+#pragma unroll
+    for (int q = 0; q < 8; q++) b8[q] = lp[q];
+    if (solve_t<8>(J, b8, x8) == 0) {
+#pragma unroll
+      for (int q = 0; q < 8; q++) lu[q] = x8[q];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 12; q++) lamUe[q * C.Ntot + c] += lu[q];
+}
+
+__global__ void LB(64) k_adj_c2p(Ctx C, const double* __restrict__ Ue, const double* __restrict__ P,
+                                 const int* __restrict__ st, const double* __restrict__ lamP,
+                                 double* __restrict__ lamUe, double* __restrict__ lamPg) {
+  adj_c2p_at(C, Ue, P, st, lamP, lamUe, lamPg, (long)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
 DEV void copy_interior_at(Ctx C, const double* __restrict__ src, double* __restrict__ dst, long c) {
   if (c >= C.Ntot) return;
   const int i = c % C.N[0];

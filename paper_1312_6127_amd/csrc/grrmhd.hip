@@ -779,10 +779,14 @@ extern "C" int grrmhd_step(grrmhd_grid* g, double* P, double* U, const double* c
 // ---------------------------------------------------------------------------
 struct AdjLayout {
   size_t F, emf, vch, scr, err, it, Un, Pb, Ue, Pk, Uk, stk, lamP, lamU, lamUe, lamUn, lamPb, lamE,
-      G, Gx, Lam, lamPpre, lamUpre, total;
+      G, Gx, Lam, lamPpre, lamUpre, M, lamUs, lamM, lamPg, Pc, total;
+  int ns;   // stages checkpointed
 };
 
-static AdjLayout adj_layout(const Ctx& C) {
+// RK3 keeps three stages; an IMEX scheme its own count, plus the stored
+// sources M^k, their cotangents, the per-stage cotangents of U(i) and the
+// final inversion's guess cotangent and result
+static AdjLayout adj_layout(const Ctx& C, int scheme) {
   AdjLayout w;
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -791,6 +795,9 @@ static AdjLayout adj_layout(const Ctx& C) {
     return o;
   };
   const size_t N = (size_t)C.Ntot, D8 = sizeof(double);
+  const bool imex = scheme != GRRMHD_RK3;
+  const size_t ns = imex ? (size_t)make_scheme(scheme).ns : 3;
+  w.ns = (int)ns;
   w.F = take(D8 * 36 * N);
   w.emf = take(D8 * 3 * N);
   w.vch = take(D8 * 3 * N);
@@ -798,11 +805,11 @@ static AdjLayout adj_layout(const Ctx& C) {
   w.err = take(D8 * N);
   w.it = take(sizeof(int) * N);
   w.Un = take(D8 * 12 * N);
-  w.Pb = take(D8 * 36 * N);     // per stage: ghost-filled input primitives
-  w.Ue = take(D8 * 36 * N);     // per stage: explicit state U(i)
-  w.Pk = take(D8 * 36 * N);     // per stage: output primitives
-  w.Uk = take(D8 * 36 * N);     // per stage: output conserved
-  w.stk = take(sizeof(int) * 3 * N);
+  w.Pb = take(D8 * 12 * ns * N);   // per stage: ghost-filled input primitives
+  w.Ue = take(D8 * 12 * ns * N);   // per stage: explicit state U(i)
+  w.Pk = take(D8 * 12 * ns * N);   // per stage: output primitives
+  w.Uk = take(D8 * 12 * ns * N);   // per stage: output conserved
+  w.stk = take(sizeof(int) * ns * N);
   w.lamP = take(D8 * 12 * N);
   w.lamU = take(D8 * 12 * N);
   w.lamUe = take(D8 * 12 * N);
@@ -814,12 +821,17 @@ static AdjLayout adj_layout(const Ctx& C) {
   w.Lam = take(D8 * 12 * N);
   w.lamPpre = take(D8 * 12 * N);
   w.lamUpre = take(D8 * 12 * N);
+  w.M = take(imex ? D8 * 4 * 8 * N : 0);
+  w.lamUs = take(imex ? D8 * 12 * ns * N : 0);
+  w.lamM = take(imex ? D8 * 4 * 8 * N : 0);
+  w.lamPg = take(imex ? D8 * 12 * N : 0);
+  w.Pc = take(imex ? D8 * 12 * N : 0);
   w.total = off;
   return w;
 }
 
 extern "C" size_t grrmhd_adjoint_workspace_bytes(const grrmhd_grid* g) {
-  return g ? adj_layout(g->C).total : 0;
+  return g ? adj_layout(g->C, g->p.scheme).total : 0;
 }
 
 static int fill_d(grrmhd_grid* g, double* p, size_t n, double v) {
@@ -980,13 +992,14 @@ extern "C" int grrmhd_fixup_vjp(grrmhd_grid* g, const double* P, const int* stat
 struct AdjPtrs {
   double *F, *emf, *vch, *scr, *err, *Un, *Pb, *Ue, *Pk, *Uk;
   double *lamP, *lamU, *lamUe, *lamUn, *lamPb, *lamE, *G, *Gx, *Lam, *lamPpre, *lamUpre;
+  double *M, *lamUs, *lamM, *lamPg, *Pc;
   int *it, *stk;
 };
 
 static int adj_ptrs(grrmhd_grid* g, void* workspace, size_t ws_bytes, AdjPtrs& a) {
-  if (g->p.scheme != GRRMHD_RK3 || g->p.recon != GRRMHD_RECON_MC)
-    return fail(GRRMHD_EINVAL, "the adjoint covers the RK3 scheme with MC reconstruction");
-  const AdjLayout w = adj_layout(g->C);
+  if (g->p.recon != GRRMHD_RECON_MC)
+    return fail(GRRMHD_EINVAL, "the adjoint covers MC reconstruction");
+  const AdjLayout w = adj_layout(g->C, g->p.scheme);
   if (ws_bytes < w.total) return fail(GRRMHD_EINVAL, "workspace too small");
   if (((uintptr_t)workspace) & 255) return fail(GRRMHD_EINVAL, "workspace must be 256-byte aligned");
   char* base = (char*)workspace;
@@ -1013,6 +1026,11 @@ static int adj_ptrs(grrmhd_grid* g, void* workspace, size_t ws_bytes, AdjPtrs& a
   a.Lam = (double*)(base + w.Lam);
   a.lamPpre = (double*)(base + w.lamPpre);
   a.lamUpre = (double*)(base + w.lamUpre);
+  a.M = (double*)(base + w.M);
+  a.lamUs = (double*)(base + w.lamUs);
+  a.lamM = (double*)(base + w.lamM);
+  a.lamPg = (double*)(base + w.lamPg);
+  a.Pc = (double*)(base + w.Pc);
   return 0;
 }
 
@@ -1109,6 +1127,195 @@ static int adj_reverse(grrmhd_grid* g, const double* chi_abs, const double* chi_
   return 0;
 }
 
+// IMEX schemes.  Forward: the launches of imex_step with dt fixed, keeping
+// per stage the input P (ghost-filled where the stage has a flux), the
+// explicit state, the output P, U and status, the stored sources M^k, and
+// the final inversion's result before its fix-up.
+static int adj_forward_imex(grrmhd_grid* g, const double* P_n, const double* chi_abs,
+                            const double* chi_es, const double* dt_dev, double* P_next,
+                            double* U_next, const AdjPtrs& a) {
+  const Ctx& C = g->C;
+  const Scheme S = make_scheme(g->p.scheme);
+  const size_t N = (size_t)C.Ntot, N12 = 12 * N, B12 = sizeof(double) * N12;
+  const long nint = n_interior(C);
+  hipStream_t s = g->stream;
+  int rc;
+  HIPCHK(hipMemcpyAsync(a.Pb, P_n, B12, hipMemcpyDeviceToDevice, s));
+  hipLaunchKernelGGL(k_p2u, dim3(nblocks(C.Ntot, 256)), dim3(256), 0, s, C, a.Pb, a.Un);
+  LAUNCHCHK();
+  for (int i = 0; i < S.ns; i++) {
+    const Stage& x = S.s[i];
+    double* Pin = a.Pb + i * N12;
+    double* Uei = a.Ue + i * N12;
+    double* Pout = a.Pk + i * N12;
+    double* Uout = a.Uk + i * N12;
+    int* st = a.stk + i * N;
+    if (i > 0) HIPCHK(hipMemcpyAsync(Pin, a.Pk + (i - 1) * N12, B12, hipMemcpyDeviceToDevice, s));
+    if (x.c != 0.0) {
+      if ((rc = launch_bc(g, Pin))) return rc;
+      if ((rc = launch_fluxes(g, Pin, chi_abs, chi_es, a.F, a.emf, a.vch))) return rc;
+    }
+    MTerms MT;
+    memset(&MT, 0, sizeof(MT));
+    for (int k = 0; k < i && k < 4; k++) {
+      if (x.m[k] == 0.0) continue;
+      MT.M[MT.n] = a.M + k * 8 * N;
+      MT.m[MT.n] = x.m[k];
+      MT.n++;
+    }
+    const double* Uj = (x.j >= 0) ? a.Uk + x.j * N12 : a.Un;
+    if ((rc = launch_update(g, x.a, x.b, x.c, dt_dev, Pin, a.Un, Uj, a.F, a.emf, Uei, nullptr,
+                            nullptr, &MT)))
+      return rc;
+    HIPCHK(hipMemcpyAsync(Pout, Pin, B12, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(Uout, Uei, B12, hipMemcpyDeviceToDevice, s));
+    if (x.g > 0.0) {
+      if ((rc = launch_implicit(g, Uei, Pin, x.g, dt_dev, chi_abs, chi_es, Pout, Uout, a.it, st,
+                                a.err)))
+        return rc;
+      if (i < 4 && S.keep_m[i]) {
+        hipLaunchKernelGGL(k_stage_m, dim3(nblocks(nint, 256)), dim3(256), 0, s, C, Uei, Uout, st,
+                           x.g, dt_dev, a.M + i * 8 * N);
+        LAUNCHCHK();
+      }
+      if ((rc = launch_fixup(g, Pout, Uout, st, a.scr, nullptr, a.it, nullptr, 0))) return rc;
+    } else {
+      hipLaunchKernelGGL(k_con2prim, dim3(nblocks(nint, 128)), dim3(128), 0, s, C, Uei,
+                         (const double*)Pin, Pout, st, (int)GRRMHD_ST_FAIL);
+      LAUNCHCHK();
+      HIPCHK(hipMemcpyAsync(a.Pc, Pout, B12, hipMemcpyDeviceToDevice, s));
+      if ((rc = launch_fixup(g, Pout, Uout, st, a.scr, nullptr, nullptr, nullptr, 0))) return rc;
+    }
+  }
+  const int l = S.ns - 1;
+  if (P_next) HIPCHK(hipMemcpyAsync(P_next, a.Pk + l * N12, B12, hipMemcpyDeviceToDevice, s));
+  if (U_next) {
+    HIPCHK(hipMemcpyAsync(U_next, a.Un, B12, hipMemcpyDeviceToDevice, s));
+    hipLaunchKernelGGL(k_copy_interior12, dim3(nblocks(nint, 256)), dim3(256), 0, s, C,
+                       (const double*)(a.Uk + l * N12), U_next);
+    LAUNCHCHK();
+  }
+  return 0;
+}
+
+// Reverse sweep of an IMEX step.  Per stage, last first: the fix-up's
+// transpose; then the implicit solve's (with the stored source's two sides,
+// M^i = (U(i) - U_e)/(g dt) taken before the fix-up) or the final
+// inversion's; then the stage bracket U_e = a U^n + b U(j) + c dt X(P_in)
+// + dt sum_k m_k M^k, which hands cotangents to U^n, U(j), the earlier M^k
+// and through the fluxes to the stage input P_in.
+static int adj_reverse_imex(grrmhd_grid* g, const double* chi_abs, const double* chi_es,
+                            const double* dt_dev, const double* gU_next, double* gP_n,
+                            double* g_chi, const AdjPtrs& a) {
+  const Ctx& C = g->C;
+  const Scheme S = make_scheme(g->p.scheme);
+  const size_t N = (size_t)C.Ntot, N12 = 12 * N;
+  hipStream_t s = g->stream;
+  const long nint = n_interior(C);
+  double* Gx = g_chi ? a.Gx : nullptr;
+  const unsigned gi = nblocks(nint, 256), ga = nblocks(C.Ntot, 256);
+  int rc;
+  if ((rc = fill_d(g, a.lamUs, (size_t)S.ns * N12, 0.0)) || (rc = fill_d(g, a.lamM, 32 * N, 0.0)) ||
+      (rc = fill_d(g, a.lamP, N12, 0.0)) || (rc = fill_d(g, a.lamUn, N12, 0.0)))
+    return rc;
+  if (g_chi && (rc = fill_d(g, g_chi, 2 * N, 0.0))) return rc;
+  hipLaunchKernelGGL(k_copy_interior, dim3(ga), dim3(256), 0, s, C, gU_next,
+                     a.lamUs + (S.ns - 1) * N12);
+  LAUNCHCHK();
+  for (int i = S.ns - 1; i >= 0; i--) {
+    const Stage& x = S.s[i];
+    const double* Pin = a.Pb + i * N12;
+    const double* Pk = a.Pk + i * N12;
+    const double* Uei = a.Ue + i * N12;
+    const int* st = a.stk + i * N;
+    const double* lamUo = a.lamUs + i * N12;
+    hipLaunchKernelGGL(k_adj_fixup_own, dim3(nblocks(nint, 128)), dim3(128), 0, s, C, Pk, st,
+                       (const double*)a.lamP, lamUo, a.Lam);
+    LAUNCHCHK();
+    hipLaunchKernelGGL(k_adj_fixup, dim3(gi), dim3(256), 0, s, C, st, (const double*)a.Lam,
+                       (const double*)a.lamP, lamUo, a.lamPpre, a.lamUpre);
+    LAUNCHCHK();
+    if (x.g > 0.0) {
+      const bool km = i < 4 && S.keep_m[i];
+      double* lamMi = a.lamM + i * 8 * N;
+      if (km) {
+        hipLaunchKernelGGL(k_adj_mscatter, dim3(gi), dim3(256), 0, s, C, 1.0 / x.g, dt_dev, st,
+                           (const double*)lamMi, a.lamUpre);
+        LAUNCHCHK();
+      }
+      if ((rc = adj_implicit(g, x.g, dt_dev, Uei, Pk, st, chi_abs, chi_es, a.lamPpre, a.lamUpre,
+                             a.lamUe, g_chi)))
+        return rc;
+      if (km) {
+        hipLaunchKernelGGL(k_adj_mscatter, dim3(gi), dim3(256), 0, s, C, -1.0 / x.g, dt_dev, st,
+                           (const double*)lamMi, a.lamUe);
+        LAUNCHCHK();
+      }
+    } else {
+      hipLaunchKernelGGL(k_copy_interior, dim3(ga), dim3(256), 0, s, C, (const double*)a.lamUpre,
+                         a.lamUe);
+      LAUNCHCHK();
+      if ((rc = fill_d(g, a.lamPg, N12, 0.0))) return rc;
+      hipLaunchKernelGGL(k_adj_c2p, dim3(nblocks(nint, 64)), dim3(64), 0, s, C, Uei,
+                         (const double*)a.Pc, st, (const double*)a.lamPpre, a.lamUe, a.lamPg);
+      LAUNCHCHK();
+    }
+    hipLaunchKernelGGL(k_adj_axpy12, dim3(gi), dim3(256), 0, s, C, x.a, (const double*)a.lamUe,
+                       a.lamUn);
+    LAUNCHCHK();
+    if (x.b != 0.0) {
+      double* lamUj = (x.j >= 0) ? a.lamUs + x.j * N12 : a.lamUn;
+      hipLaunchKernelGGL(k_adj_axpy12, dim3(gi), dim3(256), 0, s, C, x.b, (const double*)a.lamUe,
+                         lamUj);
+      LAUNCHCHK();
+    }
+    for (int k = 0; k < i && k < 4; k++) {
+      if (x.m[k] == 0.0) continue;
+      hipLaunchKernelGGL(k_adj_mterm, dim3(gi), dim3(256), 0, s, C, x.m[k], dt_dev,
+                         (const double*)a.lamUe, a.lamM + k * 8 * N);
+      LAUNCHCHK();
+    }
+    if (x.c != 0.0) {
+      if ((rc = adj_explicit(g, x.c, dt_dev, Pin, chi_abs, chi_es, a.lamUe, a.lamE, a.G, a.lamPb,
+                             Gx, g_chi)))
+        return rc;
+      if ((rc = adj_bc(g, a.lamPb))) return rc;
+      hipLaunchKernelGGL(k_copy_interior, dim3(ga), dim3(256), 0, s, C, (const double*)a.lamPb,
+                         a.lamP);
+      LAUNCHCHK();
+    } else if ((rc = fill_d(g, a.lamP, N12, 0.0))) {
+      return rc;
+    }
+    if (x.g <= 0.0) {   // a failed inversion's result was its guess, P_in
+      hipLaunchKernelGGL(k_adj_axpy12, dim3(gi), dim3(256), 0, s, C, 1.0, (const double*)a.lamPg,
+                         a.lamP);
+      LAUNCHCHK();
+    }
+  }
+  hipLaunchKernelGGL(k_adj_p2u, dim3(nblocks(nint, 128)), dim3(128), 0, s, C, (const double*)a.Pb,
+                     (const double*)a.lamUn, a.lamP);
+  LAUNCHCHK();
+  hipLaunchKernelGGL(k_copy_interior, dim3(ga), dim3(256), 0, s, C, (const double*)a.lamP, gP_n);
+  LAUNCHCHK();
+  return 0;
+}
+
+static int adj_fwd(grrmhd_grid* g, const double* P_n, const double* chi_abs,
+                   const double* chi_es, const double* dt_dev, double* P_next, double* U_next,
+                   const AdjPtrs& a) {
+  return (g->p.scheme == GRRMHD_RK3)
+             ? adj_forward(g, P_n, chi_abs, chi_es, dt_dev, P_next, U_next, a)
+             : adj_forward_imex(g, P_n, chi_abs, chi_es, dt_dev, P_next, U_next, a);
+}
+
+static int adj_rev(grrmhd_grid* g, const double* chi_abs, const double* chi_es,
+                   const double* dt_dev, const double* gU_next, double* gP_n, double* g_chi,
+                   const AdjPtrs& a) {
+  return (g->p.scheme == GRRMHD_RK3)
+             ? adj_reverse(g, chi_abs, chi_es, dt_dev, gU_next, gP_n, g_chi, a)
+             : adj_reverse_imex(g, chi_abs, chi_es, dt_dev, gU_next, gP_n, g_chi, a);
+}
+
 extern "C" int grrmhd_step_adjoint(grrmhd_grid* g, const double* P_n, const double* chi_abs,
                                    const double* chi_es, const double* dt_dev,
                                    const double* gU_next, double* gP_n, double* g_chi,
@@ -1120,8 +1327,8 @@ extern "C" int grrmhd_step_adjoint(grrmhd_grid* g, const double* P_n, const doub
   AdjPtrs a;
   int rc;
   if ((rc = adj_ptrs(g, workspace, ws_bytes, a))) return rc;
-  if ((rc = adj_forward(g, P_n, chi_abs, chi_es, dt_dev, P_next, U_next, a))) return rc;
-  return adj_reverse(g, chi_abs, chi_es, dt_dev, gU_next, gP_n, g_chi, a);
+  if ((rc = adj_fwd(g, P_n, chi_abs, chi_es, dt_dev, P_next, U_next, a))) return rc;
+  return adj_rev(g, chi_abs, chi_es, dt_dev, gU_next, gP_n, g_chi, a);
 }
 
 extern "C" int grrmhd_step_checkpointed(grrmhd_grid* g, const double* P_n, const double* chi_abs,
@@ -1133,7 +1340,7 @@ extern "C" int grrmhd_step_checkpointed(grrmhd_grid* g, const double* P_n, const
   AdjPtrs a;
   int rc;
   if ((rc = adj_ptrs(g, workspace, ws_bytes, a))) return rc;
-  return adj_forward(g, P_n, chi_abs, chi_es, dt_dev, P_next, U_next, a);
+  return adj_fwd(g, P_n, chi_abs, chi_es, dt_dev, P_next, U_next, a);
 }
 
 extern "C" int grrmhd_step_adjoint_saved(grrmhd_grid* g, const double* chi_abs,
@@ -1146,7 +1353,7 @@ extern "C" int grrmhd_step_adjoint_saved(grrmhd_grid* g, const double* chi_abs,
   AdjPtrs a;
   int rc;
   if ((rc = adj_ptrs(g, workspace, ws_bytes, a))) return rc;
-  return adj_reverse(g, chi_abs, chi_es, dt_dev, gU_next, gP_n, g_chi, a);
+  return adj_rev(g, chi_abs, chi_es, dt_dev, gU_next, gP_n, g_chi, a);
 }
 
 // Workspace of the batched solve: [0, 256) counters (list length @0, queue
