@@ -175,8 +175,9 @@ GROUPS = [(0,), (1,), (2, 3, 4), (5, 6, 7), (8,), (9, 10, 11)]
 FIELDS = ["rho", "u_g", "u1", "u2", "u3", "B1", "B2", "B3", "Ebar", "ur1", "ur2", "ur3"]
 
 
-def bench_adjoint(G, I, torch, dev, reps=5, warmup=2, h=1e-7):
-    """Adjoint of one FP64 RK3 step of the 96x48x24 Kerr-Schild disk, dt held
+def bench_adjoint(G, I, torch, dev, reps=5, warmup=2, h=1e-7, scheme="rk3"):
+    """Adjoint of one FP64 step (RK3, or the scheme named) of the 96x48x24
+    Kerr-Schild disk, dt held
     fixed (the forward step recomputed with its stage checkpoints, then the
     reverse sweep): ms per call and the forward step's ms, both from HIP
     events on the library's stream; and <gP, v> against the central
@@ -189,6 +190,7 @@ def bench_adjoint(G, I, torch, dev, reps=5, warmup=2, h=1e-7):
 
     n = (96, 48, 24)
     pd, P, ca, ce = I.accretion_disk(n=n, seed=3)
+    pd = dict(pd, scheme=scheme)
     P = I.jitter(P, 11)
     g = G.Grid(pd)
 
@@ -251,7 +253,7 @@ def bench_adjoint(G, I, torch, dev, reps=5, warmup=2, h=1e-7):
     ad = float((gP * vt).sum())
     fd = (L(Pt + h * vt) - L(Pt - h * vt)) / (2 * h)
     g.close()
-    return {"grid": list(n), "ms_per_adjoint": ms_adj, "ms_per_adjoint_with_opacity_grad": ms_adj_chi,
+    return {"grid": list(n), "scheme": scheme, "ms_per_adjoint": ms_adj, "ms_per_adjoint_with_opacity_grad": ms_adj_chi,
             "ms_forward_step": ms_fwd, "time_vs_forward": ms_adj / ms_fwd,
             "ms_forward_with_checkpoints": ms_ckpt, "ms_reverse_from_checkpoints": ms_rev,
             "directional_check": {"adjoint": ad, "central_difference": fd, "h": h,
@@ -337,7 +339,8 @@ def main():
         print(json.dumps({"implicit_batch": bench_batch(G, I, torch, dev, args.batch_cells or (1 << 24))}))
         return
     if args.adjoint_only:
-        print(json.dumps({"adjoint": bench_adjoint(G, I, torch, dev)}))
+        print(json.dumps({"adjoint": bench_adjoint(G, I, torch, dev),
+                          "adjoint_imex3": bench_adjoint(G, I, torch, dev, scheme="imex3")}))
         return
     if args.copy_probe_mb:
         src = torch.ones(args.copy_probe_mb * (1 << 20) // 8, dtype=torch.float64, device=dev)
@@ -373,8 +376,10 @@ def main():
            "time_vs_mc": rpp["ms"] / r64["ms"]}
 
     adj = None if args.no_adjoint else bench_adjoint(G, I, torch, dev)
+    adj3 = None if args.no_adjoint else bench_adjoint(G, I, torch, dev, scheme="imex3")
     if adj:
-        print(f"adjoint: {adj['ms_per_adjoint']:.3f} ms/call", file=sys.stderr, flush=True)
+        print(f"adjoint: {adj['ms_per_adjoint']:.3f} ms/call (IMEX3 {adj3['ms_per_adjoint']:.3f})",
+              file=sys.stderr, flush=True)
 
     # dominant kernel: the implicit kernel of each stage, timed with HIP events
     # on its stream inside the timed region
@@ -474,6 +479,7 @@ def main():
         "imex3": imex,
         "ppm": ppm,
         "adjoint": adj,
+        "adjoint_imex3": adj3,
         "roofline": roof,
         "cpu_baseline": cpu,
     }
