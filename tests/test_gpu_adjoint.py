@@ -260,14 +260,14 @@ def test_step_adjoint_imex(G, orc, scheme, case):
                 kinks=6, f=10.0)
 
 
-@pytest.mark.parametrize("keep", [True, False])
-def test_autograd_function(G, keep):
+@pytest.mark.parametrize("keep,scheme", [(True, "rk3"), (False, "rk3"), (True, "imex3")])
+def test_autograd_function(G, keep, scheme):
     """GRRMHDStep: forward equals grid.step with dt fixed; backward's
     gradient (from the kept checkpoints, or recomputed) equals the entry
     point's and gives the directional derivative along a random direction."""
-    say("case autograd, checkpoints kept", keep)
+    say("case autograd, checkpoints kept", keep, scheme)
     pd, P, ca, ce = box()
-    g = G.Grid(pd)
+    g = G.Grid(dict(pd, scheme=scheme))
     cat, cet = dev(ca), dev(ce)
     dt, _ = step_dt(G, g, P, cat, cet)
     idx = interior_idx(pd)
@@ -380,6 +380,17 @@ def test_opacity_gradient_box(G, orc):
     ca = ca * (1 + 0.3 * r.random(ca.size))     # per-cell opacities
     ce = ce * (1 + 0.3 * r.random(ce.size))
     _chi_check(G, orc, pd, P, ca, ce, ncomp=48, n_oracle=16, tol=1e-6)
+
+
+def test_opacity_gradient_imex3_box(G, orc):
+    """The opacity gradient through the IMEX3 stage table (five implicit
+    residuals, the stored sources and the final inversion)."""
+    say("case opacity gradient, IMEX3, periodic Minkowski box")
+    pd, P, ca, ce = box()
+    r = np.random.default_rng(4)
+    ca = ca * (1 + 0.3 * r.random(ca.size))
+    ce = ce * (1 + 0.3 * r.random(ce.size))
+    _chi_check(G, orc, dict(pd, scheme="imex3"), P, ca, ce, ncomp=48, n_oracle=16, tol=1e-6)
 
 
 def test_opacity_gradient_kerr_schild_96x48x24(G, orc):
