@@ -46,8 +46,8 @@ STEP_BYTES_PER_ZONE = 1344
 # They hold for the kernel sources whose digest is KERNEL_DIGEST; otherwise
 # traffic is reported as null and the flop figure as stale.
 FLOPS_PER_TRIP = 1732.0
-HBM_BYTES_PER_LAUNCH = 159.4e6
-KERNEL_DIGEST = "3e3352d05f59fa99"
+HBM_BYTES_PER_LAUNCH = 159.7e6
+KERNEL_DIGEST = "f7f414643f688f4b"
 
 
 def parse():

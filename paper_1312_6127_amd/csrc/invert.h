@@ -228,6 +228,7 @@ DEV int mhd_solve(const Metric& m, const MhdC& c, double ug_g, const double ut_g
   }
   bool ok = isfinite(Wp) && Wp > 0.0;
   int conv = 0;
+  double dprev = INFINITY;
   if (ok) {
     for (int it = 0; it < 60; it++) {
       Dual<1> chi, gm;
@@ -242,6 +243,11 @@ DEV int mhd_solve(const Metric& m, const MhdC& c, double ug_g, const double ut_g
       Wp = Wn;
       if (dW <= 2.0 * DBL_EPSILON * Wp) { conv++; if (conv >= 2) break; }
       else conv = 0;
+      // at the rounding floor of f: a step already below 1e-12 W' that no
+      // longer shrinks is noise of the residual, not progress (a few cells
+      // otherwise circle the root for all 60 steps and then bisect)
+      if (conv == 0 && dW <= 1e-12 * Wp && dW >= dprev) break;
+      dprev = dW;
       if (it == 59) ok = false;
     }
   }
