@@ -301,7 +301,16 @@ int grrmhd_step_adjoint_saved(grrmhd_grid *g, const double *chi_abs, const doubl
  *                        neighbour averages and cold cells' u_g averages are
  *                        transposed, U = U(P) at changed cells by its local
  *                        Jacobian, floors as the identity.  scratch: [12][N]
- *                        doubles; no array may alias another. */
+ *                        doubles; no array may alias another;
+ *  grrmhd_con2prim_vjp   of grrmhd_con2prim (Sec. 4.5, 4.6) at its result
+ *                        (P, status): gU = (dP/dU)^T gP at interior cells
+ *                        (zero at ghosts), the MHD block by the implicit-
+ *                        function theorem on U(P) (an 8x8 transposed solve),
+ *                        the radiation block through the BASIC inversion;
+ *                        where GRRMHD_ST_C2P_FAIL is set the MHD result was
+ *                        the guess, so gPguess (fields 0-4) gets gP's and
+ *                        gU's MHD block only B's; gPguess is zero elsewhere.
+ *                        gU, gPguess [12][N] out, overwritten. */
 int grrmhd_implicit_vjp(grrmhd_grid *g, const double *Uexp, const double *P_out,
                         const int *status, double dt_scale, const double *dt_dev,
                         const double *chi_abs, const double *chi_es, const double *gP_out,
@@ -313,6 +322,8 @@ int grrmhd_explicit_vjp(grrmhd_grid *g, double c, const double *dt_dev, const do
 int grrmhd_bc_vjp(grrmhd_grid *g, double *gP);
 int grrmhd_fixup_vjp(grrmhd_grid *g, const double *P, const int *status, const double *gP,
                      const double *gU, double *gP_pre, double *gU_pre, double *scratch);
+int grrmhd_con2prim_vjp(grrmhd_grid *g, const double *U, const double *P, const int *status,
+                        const double *gP, double *gU, double *gPguess);
 
 /* Implicit 4-force solve for n independent cells in flat space (Minkowski
  * metric, no grid), eq. source3/source4 with the PMHD-then-URAD cascade of

@@ -988,6 +988,22 @@ extern "C" int grrmhd_fixup_vjp(grrmhd_grid* g, const double* P, const int* stat
   return 0;
 }
 
+extern "C" int grrmhd_con2prim_vjp(grrmhd_grid* g, const double* U, const double* P,
+                                   const int* status, const double* gP, double* gU,
+                                   double* gPguess) {
+  NEEDG();
+  if (!U || !P || !status || !gP || !gU || !gPguess) return fail(GRRMHD_EINVAL, "NULL array");
+  if (gU == gPguess || gU == gP || gPguess == gP)
+    return fail(GRRMHD_EINVAL, "con2prim_vjp outputs must not alias");
+  const size_t N12 = 12 * (size_t)g->C.Ntot;
+  int rc;
+  if ((rc = fill_d(g, gU, N12, 0.0)) || (rc = fill_d(g, gPguess, N12, 0.0))) return rc;
+  hipLaunchKernelGGL(k_adj_c2p, dim3(nblocks(n_interior(g->C), 64)), dim3(64), 0, g->stream, g->C,
+                     U, P, status, gP, gU, gPguess);
+  LAUNCHCHK();
+  return 0;
+}
+
 // Named views of the adjoint workspace.
 struct AdjPtrs {
   double *F, *emf, *vch, *scr, *err, *Un, *Pb, *Ue, *Pk, *Uk;

@@ -110,6 +110,7 @@ def lib():
             "grrmhd_explicit_vjp_workspace_bytes": (C.c_size_t, [_VP]),
             "grrmhd_explicit_vjp": (C.c_int, [_VP, C.c_double] + [_VP] * 7 + [C.c_size_t]),
             "grrmhd_bc_vjp": (C.c_int, [_VP, _VP]),
+            "grrmhd_con2prim_vjp": (C.c_int, [_VP] * 7),
             "grrmhd_implicit_source_workspace_bytes": (C.c_size_t, [C.c_long]),
             "grrmhd_implicit_source": (C.c_int, [PP, C.c_long] + [_VP] * 11 + [C.c_size_t, _VP]),
             "grrmhd_implicit_source_workspace_bytes_ex": (C.c_size_t, [C.c_long, C.c_int]),
@@ -314,6 +315,16 @@ class Grid:
         self._sync_stream()
         _check(lib().grrmhd_bc_vjp(self.h, _ptr(gP)))
         return gP
+
+    def con2prim_vjp(self, U, P, status, gP):
+        """Cotangents of grrmhd_con2prim's U and guess for the cotangent gP
+        of its result (P, status: con2prim's outputs)."""
+        self._sync_stream()
+        gU = torch.empty_like(U)
+        gPg = torch.empty_like(U)
+        _check(lib().grrmhd_con2prim_vjp(self.h, _ptr(U), _ptr(P), _ptr(status), _ptr(gP), _ptr(gU),
+                                         _ptr(gPg)))
+        return gU, gPg
 
     def time_implicit(self, on: bool):
         """Start (clearing the record) or stop HIP-event timing of the

@@ -438,3 +438,65 @@ def test_autograd_opacity(G):
     gP, gc = g.step_adjoint(dev(P), dev(ca), dev(ce), dt, w, want_chi=True)
     assert torch.equal(cat.grad, gc[0]) and torch.equal(cet.grad, gc[1])
     g.close()
+
+
+def test_con2prim_vjp_against_fd(G):
+    """The final inversion's transpose (grrmhd_con2prim_vjp) against central
+    differences of grrmhd_con2prim on the 12x8x4 disk, with rho u^t made
+    negative in a few cells so that their MHD inversion fails and returns
+    its guess: there the cotangent of fields 0-4 goes to the guess and U's
+    MHD block passes only B."""
+    say("case con2prim vjp")
+    pd, P, ca, ce = disk_small()
+    g = G.Grid(pd)
+    idx = interior_idx(pd)
+    U = host(g.prim_to_cons(dev(P)))
+    r = np.random.default_rng(12)
+    bad = idx[r.choice(idx.size, 6, replace=False)]
+    U[0, bad] = -np.abs(U[0, bad])
+    Pg = I.jitter(P, 5)
+    Pt, st = g.con2prim(dev(U), dev(Pg))
+    sth = host(st)
+    assert np.all(sth[bad] & G.ST_C2P_FAIL)
+    good = np.setdiff1d(idx[(sth[idx] & G.ST_C2P_FAIL) == 0], bad)
+    assert good.size > 0.95 * idx.size
+    gP = np.zeros_like(P)
+    gP[:, idx] = r.standard_normal((12, idx.size))
+    gU, gPg = (host(x) for x in g.con2prim_vjp(dev(U), Pt, st, dev(gP)))
+    ghosts = np.setdiff1d(np.arange(P.shape[1]), idx)
+    assert np.all(gU[:, ghosts] == 0.0) and np.all(gPg[:, ghosts] == 0.0)
+    assert np.array_equal(gPg[:5, bad], gP[:5, bad]) and np.all(gU[:5, bad] == 0.0)
+    assert np.all(gPg[5:] == 0.0) and np.all(gPg[:, good] == 0.0)
+
+    def P_of(Uq):
+        Pq, _ = g.con2prim(dev(Uq), dev(Pg))
+        return host(Pq)[:, idx]
+
+    def fd(q, c, f):
+        cs = np.abs(U[1:5, c]).sum() + np.abs(U[8:12, c]).sum()
+        floor = abs(U[0, c]) if q == 0 else (np.abs(U[5:8, c]).max() if 5 <= q < 8 else cs)
+        h = f * 1e-6 * max(abs(U[q, c]), 1e-3 * floor, 1e-300)
+        Up, Um = U.copy(), U.copy()
+        Up[q, c] += h
+        Um[q, c] -= h
+        return float(((P_of(Up) - P_of(Um)) * gP[:, idx]).sum() / (2 * h))
+
+    comps = [(int(r.integers(12)), int(good[r.integers(good.size)])) for _ in range(40)]
+    comps += [(int(q), int(c)) for q, c in zip(r.integers(5, 12, 8), r.choice(bad, 8))]
+    a = np.array([gU[q, c] for q, c in comps])
+    # step 1e-5 relative, screened against a third of it (at 1e-6 the
+    # inversion's own rounding, a few ulp of W', is 1e-6 of the quotient)
+    d1 = np.array([fd(q, c, 10.0) for q, c in comps])
+    d3 = np.array([fd(q, c, 10.0 / 3) for q, c in comps])
+    d0 = np.array([fd(q, c, 1.0) for q, c in comps])
+    say(f"  norm error at steps 1e-5, 3.3e-6, 1e-6: {norm_err(a, d1):.2e} {norm_err(a, d3):.2e} "
+        f"{norm_err(a, d0):.2e}")
+    smooth = np.abs(d1 - d3) <= 1e-4 * np.abs(d1) + 1e-300
+    say(f"  {int((~smooth).sum())} of {len(comps)} components at a kink or rounding floor")
+    for k in np.flatnonzero(~smooth):
+        say(f"    q={comps[k][0]} cell={comps[k][1]} adj={a[k]:.8e} fd={d1[k]:.8e} fd/3={d3[k]:.8e}")
+    assert (~smooth).sum() <= 4
+    e = norm_err(a[smooth], d1[smooth])
+    say(f"  con2prim vjp: norm error {e:.3e}")
+    assert e < 1e-6
+    g.close()
