@@ -345,6 +345,29 @@ int grrmhd_implicit_source(const grrmhd_params *p, long n, const double *U_expl,
                            int *status, double *err, void *workspace, size_t ws_bytes,
                            void *hip_stream);
 
+/* grrmhd_implicit_source without a workspace argument and without any
+ * allocation, for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  The
+ * per-cell form's scratch memory (counters, lane statistics, cascade list
+ * with first-attempt records, deferred-cell and cold-cell lists, 128 bytes
+ * per cell) lives in a static device array sized for GRRMHD_NOALLOC_MAX_CELLS
+ * cells (32 MiB); each device the library runs on holds its own copy until
+ * the process ends.  Its address is looked up on the first call on each
+ * device (the current HIP device, which must own hip_stream); no call
+ * allocates, frees or calls an allocating library routine.  Arguments,
+ * results and errors as grrmhd_implicit_source; EINVAL for n above
+ * GRRMHD_NOALLOC_MAX_CELLS.  Every call on one device shares that device's
+ * array, which keeps the last call's contents (the counters are cleared by a
+ * kernel at the start of each call): calls stream-ordered on one device are
+ * safe, calls that overlap on one device (other streams, other host threads)
+ * race and must be serialised by the caller. */
+#define GRRMHD_NOALLOC_MAX_CELLS 262144L
+int grrmhd_implicit_source_noalloc(const grrmhd_params *p, long n, const double *U_expl,
+                                   const double *P_guess, const double *dt_cell,
+                                   const double *chi_abs, const double *chi_es, double *P_out,
+                                   double *U_out, int *iters, int *status, double *err,
+                                   void *hip_stream);
+
 /* Batched implicit solve with an explicit execution form, for batches whose
  * Newton counts are very uneven between cells (optically thin against thick
  * cells, Sec. 4.10).  mode:

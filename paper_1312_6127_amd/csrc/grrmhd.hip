@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 
 #include "adjoint.h"
@@ -35,11 +36,11 @@ struct grrmhd_grid {
 #define GRRMHD_IMPLICIT_TILE_I 16  // x1 extent of a wavefront's tile in the implicit kernel
 #endif
 
-static size_t round256(size_t b) { return (b + 255) & ~(size_t)255; }
+static constexpr size_t round256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 // Cascade list of up to cap cells with the first attempts' records, laid out
 // from `base` (256-byte aligned); returns the bytes used.
-static size_t cascade_bytes(size_t cap) {
+static constexpr size_t cascade_bytes(size_t cap) {
   return round256(sizeof(int) * cap) + round256(sizeof(double) * 13 * cap) +
          round256(sizeof(int) * 3 * cap);
 }
@@ -1377,9 +1378,15 @@ extern "C" int grrmhd_step_adjoint_saved(grrmhd_grid* g, const double* chi_abs,
 // list lengths @20 and @24, stats @64), then the cascade list and records,
 // the deferred (extreme) and cold lists, and for the per-iteration form two
 // queues and the lane state.
+// workspace of the per-cell batched form: counters and statistics, cascade
+// list with first-attempt records, deferred-cell and cold-cell lists
+static constexpr size_t batch_ws_bytes(size_t n) {
+  return 256 + cascade_bytes(n) + 2 * round256(sizeof(int) * n);
+}
+
 extern "C" size_t grrmhd_implicit_source_workspace_bytes_ex(long n, int mode) {
   if (n <= 0) return 0;
-  size_t b = 256 + cascade_bytes((size_t)n) + 2 * round256(sizeof(int) * (size_t)n);
+  size_t b = batch_ws_bytes((size_t)n);
   if (mode == GRRMHD_IMPLICIT_PER_ITERATION)
     b += 2 * round256(sizeof(int) * (size_t)n) + round256(sizeof(double) * LS_ND * (size_t)n) +
          round256(sizeof(int) * LI_NI * (size_t)n);
@@ -1649,4 +1656,61 @@ extern "C" int grrmhd_implicit_source(const grrmhd_params* p, long n, const doub
   return grrmhd_implicit_source_ex(p, n, U_expl, P_guess, dt_cell, chi_abs, chi_es, P_out, U_out,
                                    iters, status, err, GRRMHD_IMPLICIT_PER_CELL, 64, 0, workspace,
                                    ws_bytes, hip_stream);
+}
+
+// ---- the batched solve without allocation ----
+// Scratch memory of grrmhd_implicit_source_noalloc: the per-cell form's
+// workspace for GRRMHD_NOALLOC_MAX_CELLS cells (counters, lane statistics,
+// cascade list with first-attempt records, deferred and cold lists).  Each
+// device the library runs on holds its own copy until the process ends.  In
+// host code `scratch` names a host-side stand-in, never a device address:
+// kernels get the per-device address from hipGetSymbolAddress below.
+static constexpr size_t NOALLOC_BYTES = batch_ws_bytes((size_t)GRRMHD_NOALLOC_MAX_CELLS);
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+static const int NOALLOC_MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_dev[NOALLOC_MAX_DEVICES];
+
+// device address of the current device's scratch array, looked up once per
+// device (with that device current) and kept
+static int scratch_address(void** out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES)
+    return fail(GRRMHD_EINVAL, "device ordinal above the allocation-free solve's device table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* ptr = nullptr;
+    HIPCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr || (((uintptr_t)ptr) & 255))
+      return fail(GRRMHD_EHIP, "scratch array address missing or not 256-byte aligned");
+    g_scratch_dev[dev] = ptr;
+  }
+  *out = g_scratch_dev[dev];
+  return 0;
+}
+
+extern "C" int grrmhd_implicit_source_noalloc(const grrmhd_params* p, long n,
+                                              const double* U_expl, const double* P_guess,
+                                              const double* dt_cell, const double* chi_abs,
+                                              const double* chi_es, double* P_out, double* U_out,
+                                              int* iters, int* status, double* err,
+                                              void* hip_stream) {
+  if (n > GRRMHD_NOALLOC_MAX_CELLS)
+    return fail(GRRMHD_EINVAL, "n above GRRMHD_NOALLOC_MAX_CELLS for the allocation-free solve");
+  void* ws = nullptr;
+  if (n > 0) {
+    int rc = scratch_address(&ws);
+    if (rc) return rc;
+  }
+  int rc = check_batch_args(p, n, U_expl, P_guess, dt_cell, chi_abs, chi_es, P_out, U_out, ws,
+                            NOALLOC_BYTES, GRRMHD_IMPLICIT_PER_CELL);
+  if (rc || n == 0) return rc;
+  Ctx C;
+  fill_ctx(p, C);
+  // launch_batch clears the counters and statistics it uses with a kernel;
+  // the lists and records are written before they are read
+  return launch_batch(C, n, U_expl, P_guess, dt_cell, chi_abs, chi_es, P_out, U_out, iters, status,
+                      err, GRRMHD_IMPLICIT_PER_CELL, 64, 0, ws, (hipStream_t)hip_stream);
 }

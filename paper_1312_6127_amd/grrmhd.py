@@ -44,6 +44,7 @@ class Tuning(C.Structure):
 SCHEMES = {"rk3": 0, "imex2": 1, "imex2b": 2, "imex3": 3}
 PER_CELL, PER_ITERATION, PERSISTENT = 0, 1, 2
 TUNE_CANDIDATES = 9
+NOALLOC_MAX_CELLS = 262144  # GRRMHD_NOALLOC_MAX_CELLS
 FORM_NAMES = {PER_CELL: "per_cell", PER_ITERATION: "per_iteration", PERSISTENT: "persistent"}
 
 
@@ -113,6 +114,7 @@ def lib():
             "grrmhd_con2prim_vjp": (C.c_int, [_VP] * 7),
             "grrmhd_implicit_source_workspace_bytes": (C.c_size_t, [C.c_long]),
             "grrmhd_implicit_source": (C.c_int, [PP, C.c_long] + [_VP] * 11 + [C.c_size_t, _VP]),
+            "grrmhd_implicit_source_noalloc": (C.c_int, [PP, C.c_long] + [_VP] * 11),
             "grrmhd_implicit_source_workspace_bytes_ex": (C.c_size_t, [C.c_long, C.c_int]),
             "grrmhd_implicit_source_ex": (C.c_int, [PP, C.c_long] + [_VP] * 10 +
                                           [C.c_int, C.c_int, C.c_int, _VP, C.c_size_t, _VP]),
@@ -392,6 +394,18 @@ def implicit_source(pd: dict, U_expl, P_guess, dt_cell, chi_abs, chi_es):
     _check(lib().grrmhd_implicit_source(C.byref(p), n, _ptr(U_expl), _ptr(P_guess), _ptr(dt_cell),
                                         _ptr(chi_abs), _ptr(chi_es), _ptr(P), _ptr(U), _ptr(it),
                                         _ptr(st), _ptr(err), _ptr(ws), wsb, _stream()))
+    return P, U, it, st, err
+
+
+def implicit_source_noalloc(pd: dict, U_expl, P_guess, dt_cell, chi_abs, chi_es, out=None):
+    """The batched solve through the allocation-free entry point (scratch in
+    the library's static device array; at most NOALLOC_MAX_CELLS cells)."""
+    n, P, U, it, st, err = _batch_out(U_expl, P_guess) if out is None else out
+    p = params(pd)
+    _check(lib().grrmhd_implicit_source_noalloc(C.byref(p), n, _ptr(U_expl), _ptr(P_guess),
+                                                _ptr(dt_cell), _ptr(chi_abs), _ptr(chi_es),
+                                                _ptr(P), _ptr(U), _ptr(it), _ptr(st), _ptr(err),
+                                                _stream()))
     return P, U, it, st, err
 
 
