@@ -118,6 +118,7 @@ def lib():
             "orc_fluxes": (None, [PP, _D, _D, _D, _D, _D, _D]),
             "orc_flattener": (None, [PP, _D, _D, _D, _D, C.c_int]),
             "orc_ppm_cell": (None, [_D, C.c_double, _D, _D]),
+            "orc_mc_face": (None, [_D, _D, _D]),
             "orc_timestep": (C.c_double, [PP, _D]),
             "orc_explicit_update": (None, [PP, C.c_double, C.c_double, C.c_double, C.c_double,
                                            _D, _D, _D, _D, _D, _D]),
@@ -312,6 +313,15 @@ def ppm_cell(a5, f):
     a = _f64(a5)
     l, r = np.zeros(1), np.zeros(1)
     lib().orc_ppm_cell(_dp(a), float(f), _dp(l), _dp(r))
+    return float(l[0]), float(r[0])
+
+
+def mc_face(a4):
+    """MC-limited values (left state, right state) at the face between the
+    2nd and 3rd of four cell values."""
+    a = _f64(a4)
+    l, r = np.zeros(1), np.zeros(1)
+    lib().orc_mc_face(_dp(a), _dp(l), _dp(r))
     return float(l[0]), float(r[0])
 
 

@@ -133,6 +133,8 @@ void orc_flattener(const orc_params *p, const double *P, const double *chi_abs,
 /* orc_fluxes with the flattener state fl of the step (PPM; unused for MC) */
 void orc_fluxes_fl(const orc_params *p, const double *P, const double *chi_abs,
                    const double *chi_es, const double *fl, double *F, double *emf, double *vchar);
+/* MC-limited values on both sides of the face between a4[1] and a4[2] */
+void orc_mc_face(const double a4[4], double *PL, double *PR);
 /* PPM left and right values of the middle cell of a5[5] with flattener f */
 void orc_ppm_cell(const double a5[5], double f, double *aL, double *aR);
 void orc_explicit_update(const orc_params *p, double a, double b, double c, double dt,

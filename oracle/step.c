@@ -112,6 +112,14 @@ static double mc_slope(double l, double c, double r) {
   return dc > 0.0 ? s : -s;
 }
 
+/* MC-limited linear reconstruction at the face between a4[1] and a4[2]: the
+ * right value of cell a4[1] and the left value of cell a4[2] (Sec. 4.3, the
+ * MC slopes that PPM also uses) */
+void orc_mc_face(const double a4[4], double *PL, double *PR) {
+  *PL = a4[1] + 0.5 * mc_slope(a4[0], a4[1], a4[2]);
+  *PR = a4[2] - 0.5 * mc_slope(a4[1], a4[2], a4[3]);
+}
+
 /* ---- PPM (Colella & Woodward 1984 without contact steepening) ----
  * interface value between the 2nd and 3rd of four cells: the average minus
  * the difference of the two cells' MC slopes over 6 (their eq. 1.6 with
@@ -269,9 +277,8 @@ void orc_fluxes_fl(const orc_params *p, const double *P, const double *chi_abs,
             }
           } else {
             for (int q = 0; q < 12; q++) {
-              const double a = P[q * N + m2], b = P[q * N + m1], cc = P[q * N + c], e = P[q * N + p1];
-              PL[q] = b + 0.5 * mc_slope(a, b, cc);
-              PR[q] = cc - 0.5 * mc_slope(b, cc, e);
+              const double a4[4] = {P[q * N + m2], P[q * N + m1], P[q * N + c], P[q * N + p1]};
+              orc_mc_face(a4, &PL[q], &PR[q]);
             }
           }
           double x1, x2;
