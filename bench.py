@@ -70,6 +70,10 @@ def parse():
                          "in each execution form (16777216 for the 16.7M-cell batch)")
     ap.add_argument("--batch-only", action="store_true",
                     help="time only the batched implicit solve")
+    ap.add_argument("--no-fiducial", action="store_true",
+                    help="skip the 256x128x64 leg (the paper's fiducial disk shape)")
+    ap.add_argument("--cpu1-steps", type=int, default=1,
+                    help="oracle steps on one host thread (single-core baseline; 0 skips)")
     return ap.parse_args()
 
 
@@ -321,6 +325,28 @@ def gpu_run(G, torch, dev, pd, P, ca, ce, steps):
     return out
 
 
+def oracle_one_core(n, steps):
+    """Zone-cycles/s of the oracle stepping the workload on one host thread,
+    in a child process (OpenMP's thread count is fixed when it starts)."""
+    import subprocess
+
+    code = ("import sys, time; sys.path.insert(0, %r)\n"
+            "import oracle\n"
+            "from paper_1312_6127_amd import inputs as I\n"
+            "pd, P, ca, ce = I.accretion_disk(n=%r, seed=3)\n"
+            "U = oracle.prim_to_cons(pd, P)\n"
+            "t0 = time.perf_counter()\n"
+            "for _ in range(%d):\n"
+            "    P, U, *_ = oracle.step(pd, P, U, ca, ce)\n"
+            "print(time.perf_counter() - t0)\n") % (ROOT, tuple(n), steps)
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True,
+                       check=True)
+    tc = float(r.stdout.strip().splitlines()[-1])
+    return {"value": n[0] * n[1] * n[2] * steps / tc, "unit": "zone-cycles/s", "cores": 1,
+            "kind": "oracle", "sample": f"{steps} full step(s) of the same workload on one thread"}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -374,6 +400,32 @@ def main():
     print(f"ppm steps: {rpp['ms'] / args.steps:.3f} ms/step", file=sys.stderr, flush=True)
     ppm = {"value": zones * args.steps / (rpp["ms"] * 1e-3), "ms_per_step": rpp["ms"] / args.steps,
            "time_vs_mc": rpp["ms"] / r64["ms"]}
+
+    # the paper's own stopping rule for the implicit solve (roundoff = 0)
+    pdr = dict(pd, roundoff=0)
+    rpm = time_steps(G, torch, dev, pdr, P, ca, ce, args.steps, args.warmup, kernel_timing=False)
+    print(f"paper-rule steps: {rpm['ms'] / args.steps:.3f} ms/step", file=sys.stderr, flush=True)
+    itp = rpm["it"].reshape(na[::-1])[interior]
+    paper = {"value": zones * args.steps / (rpm["ms"] * 1e-3), "ms_per_step": rpm["ms"] / args.steps,
+             "time_vs_roundoff_mode": rpm["ms"] / r64["ms"],
+             "mean_newton_iters_per_cell_step": float(itp.mean()),
+             "mean_newton_iters_per_cell_step_roundoff_mode": float(itv.mean())}
+    fid = None
+    if not args.no_fiducial:
+        nf = (256, 128, 64)
+        pdf, Pf, caf, cef = I.accretion_disk(n=nf, seed=3)
+        rf = time_steps(G, torch, dev, pdf, Pf, caf, cef, max(args.steps // 2, 1), 2, kernel_timing=True)
+        nfs = max(args.steps // 2, 1)
+        vf = nf[0] * nf[1] * nf[2] * nfs / (rf["ms"] * 1e-3)
+        fid = {"grid": list(nf), "steps": nfs, "ms_per_step": rf["ms"] / nfs, "value": vf,
+               "unit": "zone-cycles/s",
+               "step_hbm_frac": vf * STEP_BYTES_PER_ZONE / 1e9 / HBM_PEAK_GBS,
+               "implicit_avg_launch_ms": rf["imp_total_ms"] / max(rf["imp_launches"], 1),
+               "implicit_active_lane_frac": rf["trips"] / max(rf["slots"], 1)}
+        if FLOPS_PER_TRIP:
+            fid["implicit_frac_fp64"] = FLOPS_PER_TRIP * rf["trips"] / (rf["imp_total_ms"] * 1e-3) / 1e12 / FP64_PEAK_TFLOPS
+        print(f"fiducial 256x128x64: {fid['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
+        del Pf, caf, cef
 
     adj = None if args.no_adjoint else bench_adjoint(G, I, torch, dev)
     adj3 = None if args.no_adjoint else bench_adjoint(G, I, torch, dev, scheme="imex3")
@@ -454,6 +506,18 @@ def main():
         e = [field_errors(got[0], ref[0]), field_errors(got[1], ref[1])]
         ppm["err_vs_oracle_max"] = max(max(e[0].values()), max(e[1].values()))
         ppm["err_steps"] = args.imex_err_steps
+        # the paper's stopping rule against the oracle's (same few steps)
+        Ph, Uh = P, oracle.prim_to_cons(pdr, P)
+        for _ in range(args.imex_err_steps):
+            Ph, Uh, dth, sth, ith, nb = oracle.step(pdr, Ph, Uh, ca, ce)
+        ref = [x.reshape((12,) + na[::-1])[(slice(None),) + interior].reshape(12, -1) for x in (Ph, Uh)]
+        Pg, Ug = gpu_run(G, torch, dev, pdr, P, ca, ce, args.imex_err_steps)
+        got = [x.reshape((12,) + na[::-1])[(slice(None),) + interior].reshape(12, -1) for x in (Pg, Ug)]
+        e = [field_errors(got[0], ref[0]), field_errors(got[1], ref[1])]
+        paper["err_vs_oracle_max"] = max(max(e[0].values()), max(e[1].values()))
+        paper["err_steps"] = args.imex_err_steps
+        if args.cpu1_steps:
+            cpu["one_core"] = oracle_one_core(n, args.cpu1_steps)
 
     out = {
         "metric": "zone-cycles/s per GRRMHD step (FP32-mixed vs FP64) at stated rel. error; % HBM peak",
@@ -470,7 +534,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"3-D Kerr-Schild a=0.9375 accretion-shaped grid {n[0]}x{n[1]}x{n[2]}, "
                                "FP64 RK3-IMEX step, LAXF, MC, flux-CT, implicit G^mu",
-                   "grid": list(n), "precision": "fp64", "parity_vs_oracle": "1e-11 per field (tests)"},
+                   "grid": list(n), "precision": "fp64", "parity_vs_oracle": "1e-12 per step per field (tests)"},
         "implicit": {"mean_newton_iters_per_cell_step": float(itv.mean()), "failed_cells": nfail},
         "step_hbm": {"algorithmic_bytes_per_zone_cycle": STEP_BYTES_PER_ZONE,
                      "achieved_GBs": value * STEP_BYTES_PER_ZONE / 1e9,
@@ -478,6 +542,8 @@ def main():
         "mixed_precision": mixed,
         "imex3": imex,
         "ppm": ppm,
+        "paper_stopping_rule": paper,
+        "fiducial_256x128x64": fid,
         "adjoint": adj,
         "adjoint_imex3": adj3,
         "roofline": roof,

@@ -71,7 +71,10 @@ enum {
 };
 
 /* Numerical parameters.  Defaults (grrmhd_default_params) are the paper's
- * fixed test parameters (Sec. 5 introduction; Sec. 4.10-4.11). */
+ * fixed test parameters (Sec. 5 introduction; Sec. 4.10-4.11) except
+ * `roundoff`, which defaults to 1 (a departure from the paper's stopping
+ * rule, for element-wise comparisons: see the field); roundoff = 0 gives the
+ * paper's rule. */
 typedef struct {
   int n[3];             /* interior cells per dimension (1 = inactive)        */
   int ng;               /* ghost width on active dimensions: 2 for MC, 4 for

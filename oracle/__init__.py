@@ -17,18 +17,21 @@ LIB = os.path.join(HERE, "liboracle.so")
 SOURCES = ["geom.c", "phys.c", "invert.c", "implicit.c", "step.c"]
 
 ST_PMHD, ST_URAD, ST_TYPE2_NEG, ST_BASIC, ST_C2P_FAIL, ST_FLOOR, ST_NOT_ACCEPT, ST_FAIL, \
-    ST_NO_GOOD_NB, ST_EXTREME, ST_COLD = (1 << i for i in range(11))
+    ST_NO_GOOD_NB, ST_EXTREME, ST_COLD, ST_PRAD, ST_ENTROPY, ST_STAGED = (1 << i for i in range(14))
 
 _BC = {"outflow": 0, "periodic": 1, "reflect": 2, "polar": 3}
 _SCHEME = {"rk3": 0, "imex2": 1, "imex2b": 2, "imex3": 3}
 
 
 def build(force: bool = False) -> str:
-    """Compile the oracle with gcc (plain C11, FP64, no FMA contraction)."""
+    """Compile the oracle with gcc (plain C11, FP64, no FMA contraction, no
+    reassociation; -O3 for x86-64-v3 so the same build runs on the AVX2 hosts
+    it is shipped to)."""
     if force or not os.path.exists(LIB) or any(
             os.path.getmtime(os.path.join(HERE, s)) > os.path.getmtime(LIB)
             for s in SOURCES + ["oracle.h", "oracle_internal.h"]):
-        cmd = ["gcc", "-O2", "-std=gnu11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+        cmd = ["gcc", "-O3", "-march=x86-64-v3", "-std=gnu11", "-fPIC", "-shared", "-fopenmp",
+               "-ffp-contract=off",
                "-o", LIB] + [os.path.join(HERE, s) for s in SOURCES] + ["-lm"]
         subprocess.run(cmd, check=True)
     return LIB
@@ -47,7 +50,7 @@ class Params(C.Structure):
         ("max_iter", C.c_int), ("roundoff", C.c_int),
         ("rho_floor", C.c_double), ("u_floor", C.c_double), ("bsq_rho_max", C.c_double),
         ("bsq_u_max", C.c_double), ("u_rho_max", C.c_double), ("erad_floor", C.c_double),
-        ("scheme", C.c_int), ("recon", C.c_int), ("cold", C.c_int),
+        ("scheme", C.c_int), ("recon", C.c_int), ("cold", C.c_int), ("cascade", C.c_int),
     ]
 
 
@@ -81,6 +84,7 @@ def params(d: dict) -> Params:
     p.scheme = _SCHEME[d.get("scheme", "rk3")]
     p.recon = 1 if d.get("recon", "mc") == "ppm" else 0
     p.cold = int(d.get("cold", 1))
+    p.cascade = int(d.get("cascade", 0))
     return p
 
 

@@ -11,9 +11,14 @@
  *
  * PMHD iterates x = (u_g, u~^i_gas); its Jacobian here is a centred finite
  * difference.  URAD iterates x = R^t_nu with an MHD inversion inside each
- * residual and a one-sided finite-difference Jacobian (Sec. 4.9).  Method
- * order, guesses, pre/post-step checks, stopping rules and the acceptance
- * cascade follow Sec. 4.10-4.11 in the order given there.
+ * residual and a one-sided finite-difference Jacobian (Sec. 4.9); PRAD
+ * iterates the radiation primitives (Ebar, u~^i_rad), the gas from the MHD
+ * inversion of T^t_nu(i) - Delta R.  With the full cascade the same methods
+ * also run in the staged form (one momentum step, energy-only steps, then
+ * the 4-D solve, damped on entering each stage) and with the entropy
+ * equation (eq. source6, weighted by T_gas) in place of the gas energy
+ * equation.  Method order, guesses, pre/post-step checks, stopping rules and
+ * the acceptance cascade follow Sec. 4.10-4.11 in the order given there.
  */
 #include <float.h>
 #include <math.h>
@@ -32,7 +37,9 @@ typedef struct {
   double Tgi[4]; /* explicit gas  (T^t_t + rho u^t, T^t_i), per sqrt(-g) */
   double Ri[4];  /* explicit radiation R^t_nu, per sqrt(-g) */
   double dt, chi_abs, chi_es;
-  int cold; /* cold MHD: energy residuals left out of the errors */
+  int cold;    /* cold MHD: energy residuals left out of the errors */
+  int entropy; /* entropy equation in place of the gas energy equation */
+  double Si;   /* explicit [S u^t]_(i) per sqrt(-g) (NAN: not available) */
 } ictx;
 
 typedef struct {
@@ -41,11 +48,19 @@ typedef struct {
   double Tg[4], Rr[4], G[4];
   double Eg[4], Er[4];
   double eT, eIg, eIr;
+  double Sut, Tgas, Gu, Es; /* entropy methods: S u^t, T_gas, G^mu u_mu, residual */
   int radflags;
   int ok;
 } ieval;
 
-enum { M_PMHD = 0, M_URAD = 1 };
+enum { M_PMHD = 0, M_URAD = 1, M_PRAD = 2 };
+
+double orc_entropy(const orc_params *p, const double *P) {
+  const double rho = P[0], pg = (p->gam - 1.0) * P[1];
+  if (!(rho > 0.0) || !(pg > 0.0)) return NAN;
+  const double n = 1.0 / (p->gam - 1.0);
+  return rho * (n * log(pg) - (n + 1.0) * log(rho)); /* rho0 ln(p^n / rho0^(n+1)) */
+}
 
 static void gas_cons(const ictx *c, const double *P, double Tg[4]) {
   orc_gas s;
@@ -92,7 +107,14 @@ static void errors(const ictx *c, ieval *e) {
     eg[1 + i] = fabs(e->Eg[1 + i]) * w / Nsg;
     er[1 + i] = fabs(e->Er[1 + i]) * w / Nsr;
   }
-  if ((e->radflags & 1) || c->cold) eg[0] = er[0] = 0.0; /* TYPE2 met E_rad <= 0, or cold: energy excluded */
+  if (c->entropy) {
+    /* the entropy equation (weighted by T_gas) replaces the energy equation
+     * on both sides; its norm carries the energy norm (Sec. 4.8) */
+    const double Ns = fabs(e->Tgas * e->Sut) + fabs(e->Tgas * c->Si) + fabs(c->dt * e->Gu) + Ntg;
+    eg[0] = er[0] = fabs(e->Es) / Ns;
+  }
+  /* TYPE2 met E_rad <= 0, or cold: the energy (entropy) equation excluded */
+  if ((e->radflags & 1) || c->cold) eg[0] = er[0] = 0.0;
   double eT = 0.0, eIg = 0.0, eIr = 0.0;
   for (int m = 0; m < 4; m++) {
     eT += (eg[m] > er[m] ? eg[m] : er[m]);
@@ -115,7 +137,20 @@ static void finish_eval(const ictx *c, ieval *e) {
     e->Eg[m] = (e->Tg[m] - c->Tgi[m]) - c->dt * e->G[m];
     e->Er[m] = (e->Rr[m] - c->Ri[m]) + c->dt * e->G[m];
   }
+  if (c->entropy) {
+    /* eq. source6 with G_S = -G^mu u_mu / T_gas (eq. GS), times T_gas:
+     * T_gas ([S u^t] - [S u^t]_(i)) + dt G^mu u_mu */
+    double ucon[4];
+    orc_ucon(c->g, e->P + 2, ucon);
+    e->Sut = orc_entropy(c->p, e->P) * ucon[0];
+    e->Tgas = (c->p->gam - 1.0) * e->P[1] / rho;
+    e->Gu = 0.0;
+    for (int m = 0; m < 4; m++) e->Gu += e->G[m] * ucon[m];
+    e->Es = e->Tgas * (e->Sut - c->Si) + c->dt * e->Gu;
+    if (!isfinite(e->Es)) e->ok = 0;
+  }
   errors(c, e);
+  if (!e->ok) e->eT = INFINITY;
 }
 
 /* PMHD residual (Sec. 4.8, PMHD steps in the listed order) */
@@ -164,6 +199,49 @@ static void eval_urad(const ictx *c, const double x[4], const double *Pgas_guess
   gas_cons(c, P, e->Tg);
   rad_cons(c, P, e->Rr);
   finish_eval(c, e);
+}
+
+/* PRAD residual (Sec. 4.8, PRAD steps): R^t_nu from the iterated radiation
+ * primitives, Delta T = -Delta R, the gas from the MHD inversion of the
+ * result (Pgas_guess starts it), T^t_nu recomputed from the gas. */
+static void eval_prad(const ictx *c, const double x[4], const double *Pgas_guess, ieval *e) {
+  memset(e, 0, sizeof(*e));
+  memcpy(e->x, x, sizeof(double) * 4);
+  e->ok = 1;
+  double *P = e->P;
+  memcpy(P, Pgas_guess, sizeof(double) * 12);
+  P[8] = x[0];
+  for (int i = 0; i < 3; i++) P[9 + i] = x[1 + i];
+  rad_cons(c, P, e->Rr);
+  double U[12];
+  const double gd = c->g->gdet;
+  U[0] = gd * c->rhout;
+  for (int m = 0; m < 4; m++) U[1 + m] = gd * (c->Tgi[m] - (e->Rr[m] - c->Ri[m]));
+  for (int i = 0; i < 3; i++) U[5 + i] = gd * c->B[i];
+  for (int m = 0; m < 4; m++) U[8 + m] = gd * e->Rr[m];
+  if (orc_mhd_invert(c->p, c->g, U, Pgas_guess, P) != 0) {
+    e->ok = 0;
+    e->eT = INFINITY;
+    return;
+  }
+  gas_cons(c, P, e->Tg);
+  e->radflags = 0;
+  finish_eval(c, e);
+}
+
+static void eval_method(const ictx *c, int method, const double x[4], const double *Pg, ieval *e) {
+  if (method == M_PMHD) eval_pmhd(c, x, e);
+  else if (method == M_URAD) eval_urad(c, x, Pg, e);
+  else eval_prad(c, x, Pg, e);
+}
+
+/* the residual a method iterates on: the gas equations for PMHD, the
+ * radiation equations for URAD and PRAD; with the entropy equation in the
+ * energy slot for the entropy-based methods (Sec. 4.9) */
+static void method_residual(const ictx *c, int method, const ieval *e, double r[4]) {
+  const double *E = (method == M_PMHD) ? e->Eg : e->Er;
+  for (int m = 0; m < 4; m++) r[m] = E[m];
+  if (c->entropy) r[0] = e->Es;
 }
 
 /* Gaussian elimination with partial pivoting: solves J dx = r. 0 on success */
@@ -253,10 +331,19 @@ static void newton(const ictx *c, int method, const double x0[4], const double *
         for (int i = 0; i < 4; i++) J[i][j] = (ep.Eg[i] - em.Eg[i]) / (2.0 * h);
       }
     } else {
-      /* offsets normalised by the iterated radiation quantities themselves */
+      /* offsets normalised by the iterated radiation quantities themselves,
+       * but never below 1e4 eps of the radiation residual's own scale
+       * (|R_t| + |R_t(i)| + dt |G_t|, Sec. 4.8): where the iterated radiation
+       * is tiny against that scale (radiation at the floor while the gas
+       * emits) a smaller offset is lost in the residual's rounding.  The
+       * energy offset raises the radiation energy (R^t_t more negative): one
+       * that lowers it can push a floor-sized energy through zero, where the
+       * TYPE2 limiter holds R fixed and the Jacobian column vanishes. */
+      const double Nres = fabs(ev.Rr[0]) + fabs(c->Ri[0]) + fabs(c->dt * ev.G[0]);
       for (int j = 0; j < 4 && !jfail; j++) {
-        const double N = (j == 0) ? fabs(x[0]) : fabs(x[j]) + fabs(x[0]) / sqrt(c->gij[j - 1][j - 1]);
-        double h = delta * N;
+        const double Nx = (j == 0) ? fabs(x[0]) : fabs(x[j]) + fabs(x[0]) / sqrt(c->gij[j - 1][j - 1]);
+        const double N = fmax(Nx, 1e4 * EPS_M * Nres / delta);
+        double h = (j == 0) ? -delta * N : delta * N;
         int got = 0;
         for (int tries = 0; tries < 12 && !got; tries++) {
           double xp[4];
@@ -412,6 +499,8 @@ static void cell_context(const orc_params *p, const orc_geom *g, const double *U
   c->chi_abs = chi_abs;
   c->chi_es = chi_es;
   c->cold = 0;
+  c->entropy = 0;
+  c->Si = NAN;
 }
 
 /* Outputs and status of an accepted (or best) solution of one method

@@ -45,7 +45,10 @@ enum {
   ORC_ST_FAIL = 1 << 7,        /* no solution: primitives neighbour-averaged */
   ORC_ST_NO_GOOD_NB = 1 << 8,  /* averaging found no good neighbour          */
   ORC_ST_EXTREME = 1 << 9,     /* radiation extremely sub-dominant: URAD first */
-  ORC_ST_COLD = 1 << 10        /* solution of the cold MHD limit (u_g held)   */
+  ORC_ST_COLD = 1 << 10,       /* solution of the cold MHD limit (u_g held)   */
+  ORC_ST_PRAD = 1 << 11,       /* solution from iterating the radiation prims */
+  ORC_ST_ENTROPY = 1 << 12,    /* entropy equation in place of the energy one */
+  ORC_ST_STAGED = 1 << 13      /* solution from the staged Newton approach    */
 };
 
 typedef struct {
@@ -68,6 +71,10 @@ typedef struct {
   int scheme;             /* ORC_RK3, ORC_IMEX2, ORC_IMEX2B, ORC_IMEX3         */
   int recon;              /* ORC_RECON_MC or ORC_RECON_PPM                    */
   int cold;               /* 1: cells with no energy solution try cold MHD    */
+  int cascade;            /* 0: PMHD, URAD (then cold); 1: the full cascade of
+                             Sec. 4.10-4.11: PMHD, URAD, PRAD, the staged
+                             approach in the extreme regime, the entropy-based
+                             methods, then cold                               */
 } orc_params;
 
 /* ---- geometry (Sec. 2; metric of the Kerr-Schild form) ---- */
@@ -108,6 +115,14 @@ typedef struct {
 void orc_implicit_cell(const orc_params *p, const orc_geom *g, const double *Ui,
                        const double *Pguess, double dt, double chi_abs, double chi_es,
                        double *Pout, double *Uout, orc_implicit_info *info);
+/* the same with the explicit entropy Si = sqrt(-g) [S u^t]_(i) of the cell
+ * (NAN: no entropy-based methods); orc_implicit_cell takes that of Pguess */
+void orc_implicit_cell_s(const orc_params *p, const orc_geom *g, const double *Ui, double Si,
+                         const double *Pguess, double dt, double chi_abs, double chi_es,
+                         double *Pout, double *Uout, orc_implicit_info *info);
+/* entropy density S = rho0 ln(p^n / rho0^(n+1)), n = 1/(gam - 1) (Sec. 2,
+ * below eq. S), of primitives P; NAN where rho0 or u_g is not positive */
+double orc_entropy(const orc_params *p, const double *P);
 /* the cold MHD solve alone, u_g held at u_c (for tests) */
 void orc_implicit_cold(const orc_params *p, const orc_geom *g, const double *Ui,
                        const double *Pguess, double dt, double chi_abs, double chi_es, double u_c,
@@ -144,6 +159,12 @@ void orc_con2prim(const orc_params *p, const double *U, const double *Pguess, do
 void orc_implicit_grid(const orc_params *p, const double *Uexp, const double *Pguess, double dt,
                        const double *chi_abs, const double *chi_es, double *Pout, double *Uout,
                        int *iters, int *status);
+/* the same with the explicit entropy Sexp [N] (sqrt(-g) [S u^t]_(i); NULL:
+ * that of Pguess) */
+void orc_implicit_grid_s(const orc_params *p, const double *Uexp, const double *Sexp,
+                         const double *Pguess, double dt, const double *chi_abs,
+                         const double *chi_es, double *Pout, double *Uout, int *iters,
+                         int *status);
 void orc_fixup(const orc_params *p, double *P, double *U, int *status);
 /* one full step of the scheme p->scheme; dt in/out (computed from P^n
  * unless dt_fixed) */

@@ -493,9 +493,14 @@ DEV void newton(const Cell& c, const Phys& ph, const Opts& o, const double x0[4]
     } else if (METHOD == M_URAD) {
       const double delta = (ev.eIr < 1e-9) ? 1e-10 : 1e-8;
       int jfail = 0;
+      // offsets relative to the iterated radiation, floored at 1e4 eps of
+      // the radiation residual's scale; the energy offset raises the energy
+      // (|R_t| + |R_t(i)| + dt |G_t|, with R_t = x_0 and dt G_t from the residual)
+      const double Nres = ::fabs(x[0]) + ::fabs(c.Ri[0]) + ::fabs(ev.Er[0] - (x[0] - c.Ri[0]));
       for (int j = 0; j < 4 && !jfail; j++) {
-        const double N = (j == 0) ? ::fabs(x[0]) : ::fabs(x[j]) + ::fabs(x[0]) / ::sqrt(gamup(c.m, j - 1, j - 1));
-        double hh = delta * N;
+        const double Nx = (j == 0) ? ::fabs(x[0]) : ::fabs(x[j]) + ::fabs(x[0]) / ::sqrt(gamup(c.m, j - 1, j - 1));
+        const double N = fmax(Nx, 1e4 * DBL_EPSILON * Nres / delta);
+        double hh = (j == 0) ? -delta * N : delta * N;
         int got = 0;
         for (int tries = 0; tries < 12 && !got; tries++) {
           double xp[4] = {x[0], x[1], x[2], x[3]};
