@@ -66,8 +66,11 @@ enum {
   GRRMHD_ST_FAIL = 1 << 7,       /* no solution: neighbour-averaged primitives   */
   GRRMHD_ST_NO_GOOD_NB = 1 << 8, /* averaging found no good neighbour            */
   GRRMHD_ST_EXTREME = 1 << 9,    /* radiation extremely sub-dominant: URAD first */
-  GRRMHD_ST_COLD = 1 << 10       /* no energy solution: cold MHD limit (u_g at the
+  GRRMHD_ST_COLD = 1 << 10,      /* no energy solution: cold MHD limit (u_g at the
                                     floor, gas momentum equations solved)       */
+  GRRMHD_ST_PRAD = 1 << 11,      /* solution from iterating radiation primitives */
+  GRRMHD_ST_ENTROPY = 1 << 12,   /* entropy equation in place of the energy one  */
+  GRRMHD_ST_STAGED = 1 << 13     /* solution of the staged Newton approach       */
 };
 
 /* Numerical parameters.  Defaults (grrmhd_default_params) are the paper's
@@ -128,6 +131,20 @@ typedef struct {
                            on success GRRMHD_ST_COLD replaces GRRMHD_ST_FAIL.
                            0: such cells fail (and are neighbour-averaged in
                            grrmhd_step).                                     */
+  int cascade;          /* implicit solve's method cascade (Sec. 4.10-4.11):
+                           0 (default): PMHD, URAD, then the cold limit;
+                           1: the paper's full cascade: PMHD, URAD and PRAD
+                           (radiation primitives iterated), their staged
+                           forms (a damped momentum step, energy-only steps,
+                           then the 4-D solve) for cells still without an
+                           acceptable solution, the same with the entropy
+                           equation in place of the gas energy equation, then
+                           the cold limit (GRRMHD_ST_PRAD, GRRMHD_ST_ENTROPY,
+                           GRRMHD_ST_STAGED mark the solutions).  The step's
+                           entropy equation needs the entropy tracer's
+                           explicit state, which grrmhd_step forms for RK3;
+                           the batched solve takes each cell's from its guess
+                           primitives.                                       */
 } grrmhd_params;
 
 typedef struct grrmhd_grid grrmhd_grid;

@@ -116,6 +116,14 @@ def lib():
             "orc_implicit_cold": (None, [PP, GP, _D, _D, C.c_double, C.c_double, C.c_double,
                                          C.c_double, _D, _D, C.POINTER(ImplicitInfo)]),
             "orc_implicit_batch": (None, [PP, C.c_long, _D, _D, _D, _D, _D, _D, _D, _I, _I]),
+            "orc_implicit_cell_s": (None, [PP, GP, _D, C.c_double, _D, C.c_double, C.c_double,
+                                           C.c_double, _D, _D, C.POINTER(ImplicitInfo)]),
+            "orc_implicit_attempt": (None, [PP, GP, _D, C.c_double, _D, C.c_double, C.c_double,
+                                            C.c_double, C.c_int, C.c_int, C.c_int, _D, _D,
+                                            C.POINTER(ImplicitInfo)]),
+            "orc_entropy": (C.c_double, [PP, _D]),
+            "orc_fluxes_s": (None, [PP, _D, _D, _D, _D, _D, _D, _D, _D]),
+            "orc_implicit_grid_s": (None, [PP, _D, _D, _D, C.c_double, _D, _D, _D, _D, _I, _I]),
             "orc_ncell_alloc": (C.c_long, [PP]),
             "orc_bc": (None, [PP, _D]),
             "orc_prim_to_cons": (None, [PP, _D, _D]),
@@ -259,6 +267,41 @@ def implicit_cold(pd, g, Ui, Pguess, dt, chi_abs, chi_es, u_c):
     return Po, Uo, info.status, info.iters, info.err
 
 
+def implicit_cell_s(pd, g, Ui, Si, Pguess, dt, chi_abs, chi_es):
+    """implicit_cell with the explicit entropy Si = sqrt(-g) [S u^t]_(i)."""
+    Ui = _f64(Ui)
+    Pg = _f64(Pguess)
+    Po = np.zeros(12)
+    Uo = np.zeros(12)
+    info = ImplicitInfo()
+    lib().orc_implicit_cell_s(C.byref(params(pd)), C.byref(g), _dp(Ui), float(Si), _dp(Pg), dt,
+                              chi_abs, chi_es, _dp(Po), _dp(Uo), C.byref(info))
+    return Po, Uo, info.status, info.iters, info.err
+
+
+METHODS = {"pmhd": 0, "urad": 1, "prad": 2}
+
+
+def implicit_attempt(pd, g, Ui, Si, Pguess, dt, chi_abs, chi_es, method, staged=False,
+                     entropy=False):
+    """One attempt of one method (pmhd, urad, prad), normal or staged, with
+    the energy or the entropy equation."""
+    Ui = _f64(Ui)
+    Pg = _f64(Pguess)
+    Po = np.zeros(12)
+    Uo = np.zeros(12)
+    info = ImplicitInfo()
+    lib().orc_implicit_attempt(C.byref(params(pd)), C.byref(g), _dp(Ui), float(Si), _dp(Pg), dt,
+                               chi_abs, chi_es, METHODS[method], int(staged), int(entropy),
+                               _dp(Po), _dp(Uo), C.byref(info))
+    return Po, Uo, info.status, info.iters, info.err
+
+
+def entropy(pd, P):
+    """S = rho0 ln(p^n / rho0^(n+1)) of one cell's primitives."""
+    return lib().orc_entropy(C.byref(params(pd)), _dp(_f64(P)))
+
+
 def implicit_batch(pd, Ui, Pg, dt, chi_abs, chi_es):
     Ui, Pg, dt, ca, ce = (_f64(a) for a in (Ui, Pg, dt, chi_abs, chi_es))
     n = Ui.shape[1]
@@ -300,6 +343,19 @@ def fluxes(pd, P, chi_abs, chi_es):
     vch = np.zeros((3, N))
     lib().orc_fluxes(C.byref(params(pd)), _dp(P), _dp(ca), _dp(ce), _dp(F), _dp(emf), _dp(vch))
     return F, emf, vch
+
+
+def fluxes_s(pd, P, chi_abs, chi_es):
+    """fluxes() plus the entropy tracer's face fluxes Fs [3][N]."""
+    P, ca, ce = _f64(P), _f64(chi_abs), _f64(chi_es)
+    N = P.shape[1]
+    F = np.zeros((3, 12, N))
+    emf = np.zeros((3, N))
+    vch = np.zeros((3, N))
+    Fs = np.zeros((3, N))
+    lib().orc_fluxes_s(C.byref(params(pd)), _dp(P), _dp(ca), _dp(ce), None, _dp(F), _dp(emf),
+                       _dp(vch), _dp(Fs))
+    return F, emf, vch, Fs
 
 
 def flattener(pd, P, chi_abs, chi_es, prev=None):

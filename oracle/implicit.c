@@ -49,6 +49,7 @@ typedef struct {
   double Eg[4], Er[4];
   double eT, eIg, eIr;
   double Sut, Tgas, Gu, Es; /* entropy methods: S u^t, T_gas, G^mu u_mu, residual */
+  double e0g, e0r;          /* normalised error of the energy (entropy) equation */
   int radflags;
   int ok;
 } ieval;
@@ -115,6 +116,8 @@ static void errors(const ictx *c, ieval *e) {
   }
   /* TYPE2 met E_rad <= 0, or cold: the energy (entropy) equation excluded */
   if ((e->radflags & 1) || c->cold) eg[0] = er[0] = 0.0;
+  e->e0g = eg[0];
+  e->e0r = er[0];
   double eT = 0.0, eIg = 0.0, eIr = 0.0;
   for (int m = 0; m < 4; m++) {
     eT += (eg[m] > er[m] ? eg[m] : er[m]);
@@ -284,6 +287,93 @@ static double rad_energy_of(const ictx *c, const double R[4]) {
   return -R[0] + al * al * s;
 }
 
+/* one-sided difference Jacobian of a radiation-side method (URAD, PRAD;
+ * Sec. 4.9) at x with residual ev: offsets of a fixed normalised size delta
+ * relative to the iterated quantities, floored at 1e4 eps of the radiation
+ * residual's own scale (|R_t| + |R_t(i)| + dt |G_t|; a smaller offset is
+ * lost in the residual's rounding where the iterated radiation is tiny
+ * against it), the energy-like offset in the direction that raises the
+ * radiation energy (lowering a floor-sized energy through zero makes the
+ * TYPE2 limiter hold R fixed and the column vanish); on an inversion failure
+ * the other side, then 10x larger, up to 0.3 of the scale.  Returns 1 when a
+ * column cannot be formed. */
+static int jacobian_rad(const ictx *c, int method, const double x[4], const ieval *ev, double delta,
+                        double J[4][4]) {
+  const double Nres = fabs(ev->Rr[0]) + fabs(c->Ri[0]) + fabs(c->dt * ev->G[0]);
+  double r0[4];
+  method_residual(c, method, ev, r0);
+  for (int j = 0; j < 4; j++) {
+    double Nx;
+    if (method == M_URAD)
+      Nx = (j == 0) ? fabs(x[0]) : fabs(x[j]) + fabs(x[0]) / sqrt(c->gij[j - 1][j - 1]);
+    else
+      Nx = (j == 0) ? fabs(x[0]) : 1.0 + fabs(x[j]);
+    const double N = fmax(Nx, 1e4 * EPS_M * Nres / delta);
+    /* URAD x_0 = R^t_t = -(energy): lower it; PRAD x_0 = Ebar: raise it */
+    double h = (j == 0) ? ((method == M_URAD) ? -delta * N : delta * N) : delta * N;
+    int got = 0;
+    for (int tries = 0; tries < 12 && !got; tries++) {
+      double xp[4];
+      memcpy(xp, x, sizeof(xp));
+      xp[j] += h;
+      ieval ep;
+      eval_method(c, method, xp, ev->P, &ep);
+      if (ep.ok) {
+        double rp[4];
+        method_residual(c, method, &ep, rp);
+        for (int i = 0; i < 4; i++) J[i][j] = (rp[i] - r0[i]) / h;
+        got = 1;
+      } else {
+        h = (tries % 2 == 0) ? -h : -10.0 * h; /* other side, then larger */
+        if (fabs(h) > 0.3 * N) break;
+      }
+    }
+    if (!got) return 1;
+  }
+  return 0;
+}
+
+/* centred difference Jacobian of PMHD (Sec. 4.9) */
+static void jacobian_pmhd(const ictx *c, const double x[4], double delta, double J[4][4]) {
+  for (int j = 0; j < 4; j++) {
+    const double h = (j == 0) ? delta * fabs(x[0]) : delta * (1.0 + fabs(x[j]));
+    double xp[4], xm[4];
+    memcpy(xp, x, sizeof(xp));
+    memcpy(xm, x, sizeof(xm));
+    xp[j] += h;
+    xm[j] -= h;
+    ieval ep, em;
+    eval_pmhd(c, xp, &ep);
+    eval_pmhd(c, xm, &em);
+    double rp[4], rm[4];
+    method_residual(c, M_PMHD, &ep, rp);
+    method_residual(c, M_PMHD, &em, rm);
+    for (int i = 0; i < 4; i++) J[i][j] = (rp[i] - rm[i]) / (2.0 * h);
+  }
+}
+
+/* post-step check (Sec. 4.10): a negative u_g (PMHD), lab radiation energy
+ * (URAD) or Ebar (PRAD) is replaced by half its magnitude; returns 1 when it
+ * acted */
+static int post_step(const ictx *c, int method, double xn[4]) {
+  if (method == M_PMHD || method == M_PRAD) {
+    if (xn[0] < 0.0) {
+      xn[0] = 0.5 * fabs(xn[0]);
+      return 1;
+    }
+    return 0;
+  }
+  const double Er = rad_energy_of(c, xn);
+  if (Er <= 0.0) {
+    const double al = c->g->alpha;
+    double s = 0.0;
+    for (int i = 0; i < 3; i++) s += c->g->gcon[0][1 + i] * xn[1 + i];
+    xn[0] = -0.5 * fabs(Er) + al * al * s;
+    return 1;
+  }
+  return 0;
+}
+
 /* one Newton attempt with one method (Sec. 4.9-4.10 "normal" Newton, D = 1) */
 static void newton(const ictx *c, int method, const double x0[4], const double *Pgas0, ieval *best,
                    int *iters) {
@@ -294,7 +384,7 @@ static void newton(const ictx *c, int method, const double x0[4], const double *
   double Pgas[12];
   memcpy(Pgas, Pgas0, sizeof(Pgas));
   ieval ev;
-  if (method == M_PMHD) eval_pmhd(c, x, &ev); else eval_urad(c, x, Pgas, &ev);
+  eval_method(c, method, x, Pgas, &ev);
   *best = ev;
   if (!ev.ok) return;
   double hist[MAXH];
@@ -316,80 +406,25 @@ static void newton(const ictx *c, int method, const double x0[4], const double *
     const double eI = (method == M_PMHD) ? ev.eIg : ev.eIr;
     const double delta = (eI < 1e-9) ? 1e-10 : 1e-8;
     double J[4][4];
-    int jfail = 0;
-    if (method == M_PMHD) {
-      for (int j = 0; j < 4; j++) {
-        const double h = (j == 0) ? delta * fabs(x[0]) : delta * (1.0 + fabs(x[j]));
-        double xp[4], xm[4];
-        memcpy(xp, x, sizeof(x));
-        memcpy(xm, x, sizeof(x));
-        xp[j] += h;
-        xm[j] -= h;
-        ieval ep, em;
-        eval_pmhd(c, xp, &ep);
-        eval_pmhd(c, xm, &em);
-        for (int i = 0; i < 4; i++) J[i][j] = (ep.Eg[i] - em.Eg[i]) / (2.0 * h);
-      }
-    } else {
-      /* offsets normalised by the iterated radiation quantities themselves,
-       * but never below 1e4 eps of the radiation residual's own scale
-       * (|R_t| + |R_t(i)| + dt |G_t|, Sec. 4.8): where the iterated radiation
-       * is tiny against that scale (radiation at the floor while the gas
-       * emits) a smaller offset is lost in the residual's rounding.  The
-       * energy offset raises the radiation energy (R^t_t more negative): one
-       * that lowers it can push a floor-sized energy through zero, where the
-       * TYPE2 limiter holds R fixed and the Jacobian column vanishes. */
-      const double Nres = fabs(ev.Rr[0]) + fabs(c->Ri[0]) + fabs(c->dt * ev.G[0]);
-      for (int j = 0; j < 4 && !jfail; j++) {
-        const double Nx = (j == 0) ? fabs(x[0]) : fabs(x[j]) + fabs(x[0]) / sqrt(c->gij[j - 1][j - 1]);
-        const double N = fmax(Nx, 1e4 * EPS_M * Nres / delta);
-        double h = (j == 0) ? -delta * N : delta * N;
-        int got = 0;
-        for (int tries = 0; tries < 12 && !got; tries++) {
-          double xp[4];
-          memcpy(xp, x, sizeof(x));
-          xp[j] += h;
-          ieval ep;
-          eval_urad(c, xp, ev.P, &ep);
-          if (ep.ok) {
-            for (int i = 0; i < 4; i++) J[i][j] = (ep.Er[i] - ev.Er[i]) / h;
-            got = 1;
-          } else {
-            h = (tries % 2 == 0) ? -h : -10.0 * h; /* other side, then larger */
-            if (fabs(h) > 0.3 * N) break;
-          }
-        }
-        if (!got) jfail = 1;
-      }
-    }
-    if (jfail) break;
-    double dx[4];
-    const double *res = (method == M_PMHD) ? ev.Eg : ev.Er;
+    if (method == M_PMHD) jacobian_pmhd(c, x, delta, J);
+    else if (jacobian_rad(c, method, x, &ev, delta, J)) break;
+    double dx[4], res[4];
+    method_residual(c, method, &ev, res);
     if (solve4(J, res, dx)) break;
     double xn[4];
     for (int i = 0; i < 4; i++) xn[i] = x[i] - dx[i];
     /* post-step checks (Sec. 4.10) */
-    if (method == M_PMHD) {
-      if (xn[0] < 0.0) xn[0] = 0.5 * fabs(xn[0]);
-    } else {
-      const double Er = rad_energy_of(c, xn);
-      if (Er <= 0.0) {
-        const double al = c->g->alpha;
-        double s = 0.0;
-        for (int i = 0; i < 3; i++) s += c->g->gcon[0][1 + i] * xn[1 + i];
-        xn[0] = -0.5 * fabs(Er) + al * al * s;
-      }
-    }
+    post_step(c, method, xn);
     ieval en;
     if (method == M_PMHD) {
       eval_pmhd(c, xn, &en);
     } else {
-      eval_urad(c, xn, ev.P, &en);
+      eval_method(c, method, xn, ev.P, &en);
       int back = 0;
       while (!en.ok && back < 20) { /* back up half-way until the inversion succeeds */
         nneg++;
         for (int i = 0; i < 4; i++) xn[i] = 0.5 * (x[i] + xn[i]);
-        eval_urad(c, xn, ev.P, &en);
+        eval_method(c, method, xn, ev.P, &en);
         back++;
       }
       if (!en.ok || nneg > 3) {
@@ -398,6 +433,131 @@ static void newton(const ictx *c, int method, const double x0[4], const double *
       }
     }
     (*iters)++;
+    int small = 1;
+    for (int i = 0; i < 4; i++)
+      if (fabs(xn[i] - x[i]) > 10.0 * EPS_M * fabs(x[i])) small = 0;
+    memcpy(x, xn, sizeof(x));
+    const double prev = hist[nh - 1];
+    ev = en;
+    hist[nh++] = ev.eT;
+    if (ev.eT < best->eT) *best = ev;
+    if (it >= 5 && ev.eT > prev) {
+      nrise++;
+      if (nrise >= 5) break;
+    }
+    if (small) break;
+  }
+}
+
+/* The staged attempt of one method (Sec. 4.10): stage 1 one momentum-only
+ * Newton step (the 3x3 momentum block, x_0 held), damped by 1/2; stage 2
+ * energy-only (entropy-only) Newton steps on x_0 with the momenta held, the
+ * first damped by 1/2, until that equation's error is below the method's
+ * tolerance, the step is at round-off or max_iter steps; stage 3 the full
+ * 4-D Newton for up to 40 steps, the first damped by 1/4, with the stopping
+ * rules of newton().  A post-step correction of u_g, the radiation energy or
+ * Ebar that recurs 2 times (4 for the entropy equation) within stage 1 or 2
+ * holds the prior value and moves on to the next stage. */
+static void newton_staged(const ictx *c, int method, const double x0[4], const double *Pgas0,
+                          ieval *best, int *iters) {
+  const orc_params *p = c->p;
+  const double tol = (method == M_PMHD) ? p->tol_pmhd : p->tol_urad;
+  const int nmod_max = c->entropy ? 4 : 2;
+  double x[4];
+  memcpy(x, x0, sizeof(x));
+  double Pgas[12];
+  memcpy(Pgas, Pgas0, sizeof(Pgas));
+  ieval ev;
+  eval_method(c, method, x, Pgas, &ev);
+  *best = ev;
+  if (!ev.ok) return;
+  for (int stage = 1; stage <= 2; stage++) {
+    const int nmax = (stage == 1) ? 1 : p->max_iter;
+    int nmod = 0;
+    for (int it = 0; it < nmax; it++) {
+      const double eI = (method == M_PMHD) ? ev.eIg : ev.eIr;
+      /* stage 2 converges the energy (entropy) equation's own error */
+      if (stage == 2 && ((method == M_PMHD) ? ev.e0g : ev.e0r) < tol) break;
+      const double delta = (eI < 1e-9) ? 1e-10 : 1e-8;
+      double J[4][4];
+      if (method == M_PMHD) jacobian_pmhd(c, x, delta, J);
+      else if (jacobian_rad(c, method, x, &ev, delta, J)) break;
+      double res[4], xn[4];
+      method_residual(c, method, &ev, res);
+      memcpy(xn, x, sizeof(xn));
+      const double D = (it == 0) ? 0.5 : 1.0;
+      if (stage == 1) {
+        double A[4][4] = {{1.0, 0.0, 0.0, 0.0}, {0.0}, {0.0}, {0.0}};
+        for (int i = 1; i < 4; i++)
+          for (int j = 1; j < 4; j++) A[i][j] = J[i][j];
+        const double r[4] = {0.0, res[1], res[2], res[3]};
+        double dx[4];
+        if (solve4(A, r, dx)) break;
+        for (int i = 1; i < 4; i++) xn[i] = x[i] - D * dx[i];
+      } else {
+        if (!(fabs(J[0][0]) > 0.0) || !isfinite(J[0][0])) break;
+        xn[0] = x[0] - D * res[0] / J[0][0];
+      }
+      if (post_step(c, method, xn)) {
+        if (++nmod >= nmod_max) break; /* hold the prior value, next stage */
+      }
+      ieval en;
+      eval_method(c, method, xn, ev.P, &en);
+      (*iters)++;
+      if (!en.ok) break;
+      int small = 1;
+      for (int i = 0; i < 4; i++)
+        if (fabs(xn[i] - x[i]) > 10.0 * EPS_M * fabs(x[i])) small = 0;
+      memcpy(x, xn, sizeof(x));
+      ev = en;
+      if (ev.eT < best->eT) *best = ev;
+      if (small) break;
+    }
+  }
+  /* stage 3: the full 4-D solve, at most 40 steps, the first damped by 1/4 */
+  double hist[MAXH];
+  int nh = 0;
+  hist[nh++] = ev.eT;
+  int nrise = 0, extra = 0, conv = 0, nneg = 0;
+  for (int it = 0; it < 40 && nh < MAXH - 1; it++) {
+    if (ev.eT < tol) conv = 1;
+    if (conv) {
+      if (!p->roundoff || extra >= 3) break;
+      extra++;
+    }
+    if (!conv && it >= 5) {
+      const double avg = (hist[nh - 5] + hist[nh - 4] + hist[nh - 3]) / 3.0;
+      if (ev.eT > 0.5 * avg) break;
+    }
+    const double eI = (method == M_PMHD) ? ev.eIg : ev.eIr;
+    const double delta = (eI < 1e-9) ? 1e-10 : 1e-8;
+    double J[4][4];
+    if (method == M_PMHD) jacobian_pmhd(c, x, delta, J);
+    else if (jacobian_rad(c, method, x, &ev, delta, J)) break;
+    double dx[4], res[4];
+    method_residual(c, method, &ev, res);
+    if (solve4(J, res, dx)) break;
+    const double D = (it == 0) ? 0.25 : 1.0;
+    double xn[4];
+    for (int i = 0; i < 4; i++) xn[i] = x[i] - D * dx[i];
+    post_step(c, method, xn);
+    ieval en;
+    eval_method(c, method, xn, ev.P, &en);
+    if (method != M_PMHD) {
+      int back = 0;
+      while (!en.ok && back < 20) {
+        nneg++;
+        for (int i = 0; i < 4; i++) xn[i] = 0.5 * (x[i] + xn[i]);
+        eval_method(c, method, xn, ev.P, &en);
+        back++;
+      }
+      if (!en.ok || nneg > 3) {
+        (*iters)++;
+        break;
+      }
+    }
+    (*iters)++;
+    if (!en.ok) break;
     int small = 1;
     for (int i = 0; i < 4; i++)
       if (fabs(xn[i] - x[i]) > 10.0 * EPS_M * fabs(x[i])) small = 0;
@@ -512,7 +672,7 @@ static int emit(const ictx *c, const ieval *best, int method, int status, const 
   const orc_params *p = c->p;
   const orc_geom *g = c->g;
   const double gd = g->gdet;
-  status |= (method == M_PMHD) ? ORC_ST_PMHD : ORC_ST_URAD;
+  status |= (method == M_PMHD) ? ORC_ST_PMHD : (method == M_URAD) ? ORC_ST_URAD : ORC_ST_PRAD;
   if (best->eT > p->tol_fail) status |= ORC_ST_FAIL;
   else if (best->eT > p->tol_accept) status |= ORC_ST_NOT_ACCEPT;
   if (best->radflags & 1) status |= ORC_ST_TYPE2_NEG;
@@ -522,6 +682,9 @@ static int emit(const ictx *c, const ieval *best, int method, int status, const 
     if (method == M_PMHD) {
       Ucons_gas[m] = best->Tg[m];
       Ucons_rad[m] = c->Ri[m] - (best->Tg[m] - c->Tgi[m]);
+    } else if (method == M_PRAD) {
+      Ucons_rad[m] = best->Rr[m];
+      Ucons_gas[m] = c->Tgi[m] - (best->Rr[m] - c->Ri[m]);
     } else {
       Ucons_rad[m] = best->x[m];
       Ucons_gas[m] = c->Tgi[m] - (best->x[m] - c->Ri[m]);
@@ -608,11 +771,168 @@ void orc_implicit_cold(const orc_params *p, const orc_geom *g, const double *Ui,
   }
 }
 
+/* one phase of the full cascade (Sec. 4.10) with the energy or, with
+ * c->entropy, the entropy equation: the normal attempts (PMHD, URAD, PRAD;
+ * URAD and PRAD first in the extreme regime) until one is acceptable, then
+ * the staged attempts of PMHD, URAD and PRAD (reading: for every cell the
+ * normal attempts leave without an acceptable solution; the printed
+ * restriction to the extreme regime is read as garbled).
+ * Each attempt starts from the previous attempts' best solution when its
+ * e_T < 1e-4, otherwise from the method's own guess: PMHD the thin-limit
+ * primitives Pthin (staged: u_g from the explicit entropy where it exists),
+ * URAD R^t_nu(P_n), PRAD the thin-limit radiation primitives Pradthin. */
+static void run_phase(const ictx *c, int extreme, const double *Pguess, const double *Pthin,
+                      const double *Pradthin, ieval *best, int *best_method, int *staged,
+                      int *iters) {
+  const orc_params *p = c->p;
+  const double acc = p->roundoff ? 10.0 * p->tol_pmhd : p->tol_accept;
+  const int normal[3] = {extreme ? M_URAD : M_PMHD, extreme ? M_PRAD : M_URAD,
+                         extreme ? M_PMHD : M_PRAD};
+  const int stages[3] = {M_PMHD, M_URAD, M_PRAD};
+  memset(best, 0, sizeof(*best));
+  best->eT = INFINITY;
+  *best_method = -1;
+  *staged = 0;
+  for (int pass = 0; pass < 2; pass++) {
+    for (int mi = 0; mi < 3; mi++) {
+      const int method = pass ? stages[mi] : normal[mi];
+      const int use_prev = (*best_method >= 0 && best->eT < 1e-4);
+      double x0[4], Pg[12];
+      if (method == M_PMHD) {
+        const double *src = use_prev ? best->P : Pthin;
+        memcpy(Pg, src, sizeof(Pg));
+        x0[0] = src[1];
+        for (int i = 0; i < 3; i++) x0[1 + i] = src[2 + i];
+        if (pass == 1 && !use_prev && isfinite(c->Si) && c->rhout > 0.0) {
+          /* u_g from the specific entropy Si/(rho0 u^t) at the prior rho0 */
+          const double sp = c->Si / c->rhout, rho = Pthin[0], n = 1.0 / (p->gam - 1.0);
+          const double pg = exp((sp + (n + 1.0) * log(rho)) / n);
+          if (isfinite(pg) && pg > 0.0) x0[0] = pg / (p->gam - 1.0);
+        }
+      } else if (method == M_URAD) {
+        if (use_prev) {
+          memcpy(x0, best->Rr, sizeof(x0));
+          memcpy(Pg, best->P, sizeof(Pg));
+        } else {
+          rad_cons(c, Pguess, x0);
+          memcpy(Pg, Pguess, sizeof(Pg));
+        }
+      } else {
+        const double *src = use_prev ? best->P : Pradthin;
+        memcpy(Pg, src, sizeof(Pg));
+        x0[0] = src[8];
+        for (int i = 0; i < 3; i++) x0[1 + i] = src[9 + i];
+      }
+      ieval bm;
+      if (pass == 0) newton(c, method, x0, Pg, &bm, iters);
+      else newton_staged(c, method, x0, Pg, &bm, iters);
+      if (bm.ok && bm.eT < best->eT) {
+        *best = bm;
+        *best_method = method;
+        *staged = pass;
+      }
+      if (best->eT < acc) return;
+    }
+  }
+}
+
+/* The full cascade (Sec. 4.10-4.11): the energy phase; when it finds no
+ * acceptable solution or one with u_g <= 0, the entropy phase (explicit
+ * entropy Si needed); the entropy solution is taken when acceptable,
+ * otherwise the smaller e_T of the two within tol_fail (u_g > 0); with
+ * neither, the cold MHD limit where its conditions hold. */
+static void cascade_full(ictx *c, int extreme, const double *Ui, const double *Pguess,
+                         const double *Pthin, int status, double *Pout, double *Uout,
+                         orc_implicit_info *info) {
+  const orc_params *p = c->p;
+  const double acc = p->roundoff ? 10.0 * p->tol_pmhd : p->tol_accept;
+  int iters = 0;
+  /* PRAD's thin-limit guess: the radiation inversion of R(i) when
+   * dt kappa_tot(P_n) < 2/3 */
+  double Pradthin[12];
+  memcpy(Pradthin, Pguess, sizeof(Pradthin));
+  if (c->dt * (c->chi_abs + c->chi_es) * Pguess[0] < 2.0 / 3.0) {
+    double U[12];
+    memset(U, 0, sizeof(U));
+    for (int m = 0; m < 4; m++) U[8 + m] = c->g->gdet * c->Ri[m];
+    double Pr[12];
+    memcpy(Pr, Pguess, sizeof(Pr));
+    orc_rad_invert(p, c->g, U, 0, Pr);
+    if (Pr[8] > 0.0 && isfinite(Pr[8])) memcpy(Pradthin + 8, Pr + 8, sizeof(double) * 4);
+  }
+  ieval bE, bS;
+  int mE, mS, sE, sS;
+  c->entropy = 0;
+  run_phase(c, extreme, Pguess, Pthin, Pradthin, &bE, &mE, &sE, &iters);
+  const int energy_ok = mE >= 0 && bE.P[1] > 0.0;
+  int use = -1; /* 0 energy, 1 entropy */
+  if (energy_ok && bE.eT < acc) {
+    use = 0;
+  } else {
+    mS = -1;
+    if (isfinite(c->Si)) {
+      c->entropy = 1;
+      run_phase(c, extreme, Pguess, Pthin, Pradthin, &bS, &mS, &sS, &iters);
+      c->entropy = 0;
+    }
+    const int entropy_ok = mS >= 0 && bS.P[1] > 0.0;
+    if (entropy_ok && bS.eT < acc) use = 1;
+    else {
+      const int eo = energy_ok && bE.eT <= p->tol_fail, so = entropy_ok && bS.eT <= p->tol_fail;
+      if (eo && so) use = (bS.eT < bE.eT) ? 1 : 0;
+      else if (eo) use = 0;
+      else if (so) use = 1;
+    }
+  }
+  const int status0 = status;
+  if (use == 0) {
+    status = emit(c, &bE, mE, status, Ui, Pout, Uout) | (sE ? ORC_ST_STAGED : 0);
+    info->err = bE.eT;
+  } else if (use == 1) {
+    status = emit(c, &bS, mS, status, Ui, Pout, Uout) | ORC_ST_ENTROPY | (sS ? ORC_ST_STAGED : 0);
+    info->err = bS.eT;
+  } else if (mE >= 0) {
+    status = emit(c, &bE, mE, status, Ui, Pout, Uout) | ORC_ST_FAIL;
+    info->err = bE.eT;
+  } else {
+    memcpy(Pout, Pguess, sizeof(double) * 12);
+    for (int i = 0; i < 12; i++) Uout[i] = Ui[i];
+    status |= ORC_ST_FAIL;
+    info->err = INFINITY;
+  }
+  info->status = status;
+  info->iters = iters;
+  if ((status & ORC_ST_FAIL) && p->cold && p->u_floor > 0.0 && cold_allowed(c, Pguess)) {
+    double Pc[12], Uc[12];
+    orc_implicit_info ic = *info;
+    if (cold_cell(c, Ui, Pguess, p->u_floor, status0, Pc, Uc, &ic) == 0) {
+      memcpy(Pout, Pc, sizeof(Pc));
+      memcpy(Uout, Uc, sizeof(Uc));
+      *info = ic;
+    } else {
+      info->iters = ic.iters;
+    }
+  }
+}
+
 void orc_implicit_cell(const orc_params *p, const orc_geom *g, const double *Ui,
                        const double *Pguess, double dt, double chi_abs, double chi_es,
                        double *Pout, double *Uout, orc_implicit_info *info) {
+  /* a cell without a grid: its explicit entropy is that of its prior
+   * primitives (no flux divergence, and the entropy has no other explicit
+   * source) */
+  double ucon[4];
+  orc_ucon(g, Pguess + 2, ucon);
+  const double Si = g->gdet * orc_entropy(p, Pguess) * ucon[0];
+  orc_implicit_cell_s(p, g, Ui, Si, Pguess, dt, chi_abs, chi_es, Pout, Uout, info);
+}
+
+void orc_implicit_cell_s(const orc_params *p, const orc_geom *g, const double *Ui, double Si,
+                         const double *Pguess, double dt, double chi_abs, double chi_es,
+                         double *Pout, double *Uout, orc_implicit_info *info) {
   ictx c;
   cell_context(p, g, Ui, dt, chi_abs, chi_es, &c);
+  c.Si = Si / g->gdet;
   int status = 0, iters = 0;
 
   /* extreme radiation sub-dominance (Sec. 4.10): radiation energy, or the
@@ -643,6 +963,10 @@ void orc_implicit_cell(const orc_params *p, const orc_geom *g, const double *Ui,
     else status |= ORC_ST_C2P_FAIL;
   }
 
+  if (p->cascade) {
+    cascade_full(&c, extreme, Ui, Pguess, Pthin, status, Pout, Uout, info);
+    return;
+  }
   const int order[2] = {extreme ? M_URAD : M_PMHD, extreme ? M_PMHD : M_URAD};
   ieval best;
   memset(&best, 0, sizeof(best));
@@ -729,4 +1053,60 @@ void orc_implicit_batch(const orc_params *p, long n, const double *Ui, const dou
     if (iters) iters[c] = info.iters;
     if (status) status[c] = info.status;
   }
+}
+
+/* One attempt of one method alone, for tests: method 0 PMHD, 1 URAD, 2 PRAD;
+ * staged != 0 the staged form; entropy != 0 the entropy equation (Si =
+ * sqrt(-g) [S u^t]_(i)); each method from its own guess as in the cascade's
+ * first attempt.  Status: the method bit, ORC_ST_FAIL above tol_fail. */
+void orc_implicit_attempt(const orc_params *p, const orc_geom *g, const double *Ui, double Si,
+                          const double *Pguess, double dt, double chi_abs, double chi_es,
+                          int method, int staged, int entropy, double *Pout, double *Uout,
+                          orc_implicit_info *info) {
+  ictx c;
+  cell_context(p, g, Ui, dt, chi_abs, chi_es, &c);
+  c.Si = Si / g->gdet;
+  c.entropy = entropy;
+  double Pthin[12], Pradthin[12];
+  memcpy(Pthin, Pguess, sizeof(Pthin));
+  memcpy(Pradthin, Pguess, sizeof(Pradthin));
+  if (dt * (chi_abs + chi_es) * Pguess[0] < 2.0 / 3.0) {
+    double Pt[12];
+    memcpy(Pt, Pguess, sizeof(Pt));
+    if (orc_mhd_invert(p, g, Ui, Pguess, Pt) == 0) memcpy(Pthin, Pt, sizeof(double) * 8);
+    double U[12];
+    memset(U, 0, sizeof(U));
+    for (int m = 0; m < 4; m++) U[8 + m] = Ui[8 + m];
+    double Pr[12];
+    memcpy(Pr, Pguess, sizeof(Pr));
+    orc_rad_invert(p, g, U, 0, Pr);
+    if (Pr[8] > 0.0 && isfinite(Pr[8])) memcpy(Pradthin + 8, Pr + 8, sizeof(double) * 4);
+  }
+  double x0[4], Pg[12];
+  if (method == M_PMHD) {
+    memcpy(Pg, Pthin, sizeof(Pg));
+    x0[0] = Pthin[1];
+    for (int i = 0; i < 3; i++) x0[1 + i] = Pthin[2 + i];
+  } else if (method == M_URAD) {
+    rad_cons(&c, Pguess, x0);
+    memcpy(Pg, Pguess, sizeof(Pg));
+  } else {
+    memcpy(Pg, Pradthin, sizeof(Pg));
+    x0[0] = Pradthin[8];
+    for (int i = 0; i < 3; i++) x0[1 + i] = Pradthin[9 + i];
+  }
+  ieval best;
+  int iters = 0;
+  if (staged) newton_staged(&c, method, x0, Pg, &best, &iters);
+  else newton(&c, method, x0, Pg, &best, &iters);
+  info->iters = iters;
+  if (!best.ok) {
+    memcpy(Pout, Pguess, sizeof(double) * 12);
+    for (int i = 0; i < 12; i++) Uout[i] = Ui[i];
+    info->status = ORC_ST_FAIL;
+    info->err = INFINITY;
+    return;
+  }
+  info->status = emit(&c, &best, method, 0, Ui, Pout, Uout) | (entropy ? ORC_ST_ENTROPY : 0);
+  info->err = best.eT;
 }

@@ -120,6 +120,12 @@ void orc_implicit_cell(const orc_params *p, const orc_geom *g, const double *Ui,
 void orc_implicit_cell_s(const orc_params *p, const orc_geom *g, const double *Ui, double Si,
                          const double *Pguess, double dt, double chi_abs, double chi_es,
                          double *Pout, double *Uout, orc_implicit_info *info);
+/* one attempt of one method alone (tests): method 0 PMHD, 1 URAD, 2 PRAD,
+ * staged form, entropy equation (Si = sqrt(-g) [S u^t]_(i)) */
+void orc_implicit_attempt(const orc_params *p, const orc_geom *g, const double *Ui, double Si,
+                          const double *Pguess, double dt, double chi_abs, double chi_es,
+                          int method, int staged, int entropy, double *Pout, double *Uout,
+                          orc_implicit_info *info);
 /* entropy density S = rho0 ln(p^n / rho0^(n+1)), n = 1/(gam - 1) (Sec. 2,
  * below eq. S), of primitives P; NAN where rho0 or u_g is not positive */
 double orc_entropy(const orc_params *p, const double *P);
@@ -145,6 +151,11 @@ double orc_timestep(const orc_params *p, const double *vchar);
  * larger of the new value and the one in fl (earlier sub-steps of the step) */
 void orc_flattener(const orc_params *p, const double *P, const double *chi_abs,
                    const double *chi_es, double *fl, int keep);
+/* orc_fluxes_fl plus, when Fs is not NULL, the face fluxes Fs [3][N] of the
+ * entropy tracer sqrt(-g) S u^t (HLL/LAXF with the gas speeds) */
+void orc_fluxes_s(const orc_params *p, const double *P, const double *chi_abs,
+                  const double *chi_es, const double *fl, double *F, double *emf, double *vchar,
+                  double *Fs);
 /* orc_fluxes with the flattener state fl of the step (PPM; unused for MC) */
 void orc_fluxes_fl(const orc_params *p, const double *P, const double *chi_abs,
                    const double *chi_es, const double *fl, double *F, double *emf, double *vchar);

@@ -238,8 +238,26 @@ void orc_fluxes(const orc_params *p, const double *P, const double *chi_abs, con
 
 void orc_fluxes_fl(const orc_params *p, const double *P, const double *chi_abs,
                    const double *chi_es, const double *fl, double *F, double *emf, double *vchar) {
+  orc_fluxes_s(p, P, chi_abs, chi_es, fl, F, emf, vchar, NULL);
+}
+
+/* sqrt(-g) S u^t and sqrt(-g) S u^dir of primitives P at geometry g (the
+ * 13th conserved quantity and its flux, Sec. 4 lists of U_q and F_q) */
+static void entropy_cons_flux(const orc_params *p, const orc_geom *g, const double *P, int dir,
+                              double *Us, double *Fs) {
+  double ucon[4];
+  orc_ucon(g, P + 2, ucon);
+  const double S = orc_entropy(p, P);
+  *Us = g->gdet * S * ucon[0];
+  if (Fs) *Fs = g->gdet * S * ucon[dir];
+}
+
+void orc_fluxes_s(const orc_params *p, const double *P, const double *chi_abs,
+                  const double *chi_es, const double *fl, double *F, double *emf, double *vchar,
+                  double *Fs) {
   const long N = orc_ncell_alloc(p);
   memset(F, 0, sizeof(double) * 3 * 12 * N);
+  if (Fs) memset(Fs, 0, sizeof(double) * 3 * N);
   memset(emf, 0, sizeof(double) * 3 * N);
   memset(vchar, 0, sizeof(double) * 3 * N);
   const int NA[3] = {orc_nalloc(p, 0), orc_nalloc(p, 1), orc_nalloc(p, 2)};
@@ -312,6 +330,21 @@ void orc_fluxes_fl(const orc_params *p, const double *P, const double *chi_abs,
           }
           Fd[(5 + d) * N + c] = 0.0; /* induction flux of the normal component vanishes */
           vchar[(long)d * N + c] = fmax(fmax(gmin, gmax), fmax(rmin, rmax));
+          if (Fs) {
+            /* the entropy tracer's flux, with the gas speeds */
+            double UsL, UsR, FsL, FsR, f;
+            entropy_cons_flux(p, &g, PL, d + 1, &UsL, &FsL);
+            entropy_cons_flux(p, &g, PR, d + 1, &UsR, &FsR);
+            if (p->flux == ORC_FLUX_HLL) {
+              if (gmin + gmax > 0.0)
+                f = (gmin * FsR + gmax * FsL - gmin * gmax * (UsR - UsL)) / (gmin + gmax);
+              else
+                f = 0.5 * (FsL + FsR);
+            } else {
+              f = 0.5 * (FsR + FsL - fmax(gmin, gmax) * (UsR - UsL));
+            }
+            Fs[(long)d * N + c] = f;
+          }
         }
   }
   /* flux-CT corner EMFs: emf_a = F_c[B_b] = -F_b[B_c], (a, b, c) cyclic */
@@ -460,6 +493,13 @@ void orc_con2prim(const orc_params *p, const double *U, const double *Pguess, do
 void orc_implicit_grid(const orc_params *p, const double *Uexp, const double *Pguess, double dt,
                        const double *chi_abs, const double *chi_es, double *Pout, double *Uout,
                        int *iters, int *status) {
+  orc_implicit_grid_s(p, Uexp, NULL, Pguess, dt, chi_abs, chi_es, Pout, Uout, iters, status);
+}
+
+void orc_implicit_grid_s(const orc_params *p, const double *Uexp, const double *Sexp,
+                         const double *Pguess, double dt, const double *chi_abs,
+                         const double *chi_es, double *Pout, double *Uout, int *iters,
+                         int *status) {
   const long N = orc_ncell_alloc(p);
 #pragma omp parallel for collapse(2) schedule(dynamic, 4)
   for (int k = orc_ng(p, 2); k < orc_ng(p, 2) + p->n[2]; k++)
@@ -476,7 +516,8 @@ void orc_implicit_grid(const orc_params *p, const double *Uexp, const double *Pg
           Pg[q] = Pguess[q * N + c];
         }
         orc_implicit_info info;
-        orc_implicit_cell(p, &g, Uc, Pg, dt, chi_abs[c], chi_es[c], Po, Uo, &info);
+        orc_implicit_cell_s(p, &g, Uc, Sexp ? Sexp[c] : NAN, Pg, dt, chi_abs[c], chi_es[c], Po, Uo,
+                            &info);
         for (int q = 0; q < 12; q++) {
           Pout[q * N + c] = Po[q];
           Uout[q * N + c] = Uo[q];
@@ -627,6 +668,46 @@ static orc_scheme scheme_table(int which) {
   return S;
 }
 
+/* sqrt(-g) S u^t of P at every allocated cell */
+static void entropy_field(const orc_params *p, const double *P, double *S) {
+  const long N = orc_ncell_alloc(p);
+  for (int k = 0; k < orc_nalloc(p, 2); k++)
+    for (int j = 0; j < orc_nalloc(p, 1); j++)
+      for (int i = 0; i < orc_nalloc(p, 0); i++) {
+        double x1, x2;
+        orc_cell_x(p, i, j, &x1, &x2);
+        orc_geom g;
+        orc_geom_point(p, x1, x2, &g);
+        const long c = IDX(p, i, j, k);
+        double Pc[12];
+        for (int q = 0; q < 12; q++) Pc[q] = P[q * N + c];
+        entropy_cons_flux(p, &g, Pc, 1, &S[c], NULL);
+      }
+}
+
+/* the entropy tracer's explicit stage value at interior cells:
+ * a Sn + b U_S(Pprev) + c dt (-div Fs); Sn = U_S(P^n) */
+static void entropy_update(const orc_params *p, double a, double b, double c, double dt,
+                           const double *Sn, const double *Pprev, const double *Fs,
+                           double *Sexp) {
+  const long N = orc_ncell_alloc(p);
+  const int NA[3] = {orc_nalloc(p, 0), orc_nalloc(p, 1), orc_nalloc(p, 2)};
+  const long st[3] = {1, NA[0], (long)NA[0] * NA[1]};
+  double *Sp = malloc(sizeof(double) * N);
+  entropy_field(p, Pprev, Sp);
+  for (long q = 0; q < N; q++) Sexp[q] = NAN;
+  for (int k = orc_ng(p, 2); k < orc_ng(p, 2) + p->n[2]; k++)
+    for (int j = orc_ng(p, 1); j < orc_ng(p, 1) + p->n[1]; j++)
+      for (int i = orc_ng(p, 0); i < orc_ng(p, 0) + p->n[0]; i++) {
+        const long cc = IDX(p, i, j, k);
+        double div = 0.0;
+        for (int d = 0; d < 3; d++)
+          if (p->n[d] > 1) div += (Fs[(long)d * N + cc + st[d]] - Fs[(long)d * N + cc]) / orc_dx(p, d);
+        Sexp[cc] = a * Sn[cc] + (b != 0.0 ? b * Sp[cc] : 0.0) - c * dt * div;
+      }
+  free(Sp);
+}
+
 /* one full step of the scheme p->scheme (Sec. 4.1); each implicit stage is
  * implicit in its own new value with dt_k = g dt */
 int orc_step(const orc_params *p, double *P, double *U, const double *chi_abs, const double *chi_es,
@@ -662,10 +743,18 @@ int orc_step(const orc_params *p, double *P, double *U, const double *chi_abs, c
   /* PPM flattener of the step: the largest over its sub-steps so far */
   double *fl = (p->recon == ORC_RECON_PPM) ? calloc(6 * N, sizeof(double)) : NULL;
   int nflux = 0;
+  /* the full cascade's entropy equation (RK3): the explicit entropy of each
+   * stage, a U_S(P^n) + b U_S(P^(k-1)) + c dt (-div F_S), the tracer taken
+   * from the primitives at every sub-step (Sec. 4.2 step 2: all U_q from P_q) */
+  const int ent = p->cascade && p->scheme == ORC_RK3;
+  double *Fs = ent ? malloc(sizeof(double) * 3 * N) : NULL;
+  double *Sn = ent ? malloc(sizeof(double) * N) : NULL;
+  double *Sexp = ent ? malloc(sizeof(double) * N) : NULL;
+  if (ent) entropy_field(p, P, Sn);
 #define STEP_FLUXES()                                              \
   do {                                                             \
     if (fl) orc_flattener(p, Pk, chi_abs, chi_es, fl, nflux > 0);  \
-    orc_fluxes_fl(p, Pk, chi_abs, chi_es, fl, F, emf, vch);        \
+    orc_fluxes_s(p, Pk, chi_abs, chi_es, fl, F, emf, vch, Fs);     \
     nflux++;                                                       \
   } while (0)
   if (!dt_fixed) {
@@ -684,6 +773,7 @@ int orc_step(const orc_params *p, double *P, double *U, const double *chi_abs, c
         STEP_FLUXES();
       }
       orc_explicit_update(p, s->a, s->b, s->c, *dt, Pk, Un, Uj, F, emf, Uexp);
+      if (ent) entropy_update(p, s->a, s->b, s->c, *dt, Sn, Pk, Fs, Sexp);
     } else {
       for (long q = 0; q < 12 * N; q++) Uexp[q] = s->a * Un[q] + (s->b != 0.0 ? s->b * Uj[q] : 0.0);
     }
@@ -692,7 +782,8 @@ int orc_step(const orc_params *p, double *P, double *U, const double *chi_abs, c
       for (long q = 0; q < 12 * N; q++) Uexp[q] += *dt * s->m[k] * Mst[k][q];
     }
     if (s->g > 0.0) {
-      orc_implicit_grid(p, Uexp, Pk, s->g * (*dt), chi_abs, chi_es, Pk, Ust[i], it, st);
+      orc_implicit_grid_s(p, Uexp, ent ? Sexp : NULL, Pk, s->g * (*dt), chi_abs, chi_es, Pk, Ust[i],
+                          it, st);
       if (i < 4 && need_m[i]) {
         const double gdt = s->g * (*dt);
         for (long c = 0; c < N; c++)
@@ -735,6 +826,9 @@ int orc_step(const orc_params *p, double *P, double *U, const double *chi_abs, c
   free(F); free(emf); free(vch); free(Uexp); free(Un); free(Pk); free(st); free(stacc);
   free(it);
   free(fl);
+  free(Fs);
+  free(Sn);
+  free(Sexp);
 #undef STEP_FLUXES
   return nbad;
 }

@@ -95,6 +95,7 @@ extern "C" void grrmhd_default_params(grrmhd_params* p) {
   p->scheme = GRRMHD_RK3;
   p->recon = GRRMHD_RECON_MC;
   p->cold = 1;
+  p->cascade = 0;
   p->r_fp64 = 2.0;
   p->tol_pmhd = 1e-12;
   p->tol_urad = 1e-9;
@@ -122,6 +123,7 @@ static int validate(const grrmhd_params* p, bool need_grid) {
     return fail(GRRMHD_EINVAL, "bad metric");
   if (p->scheme < GRRMHD_RK3 || p->scheme > GRRMHD_IMEX3) return fail(GRRMHD_EINVAL, "bad scheme");
   if (p->cold != 0 && p->cold != 1) return fail(GRRMHD_EINVAL, "cold must be 0 or 1");
+  if (p->cascade != 0 && p->cascade != 1) return fail(GRRMHD_EINVAL, "cascade must be 0 or 1");
   if (p->recon != GRRMHD_RECON_MC && p->recon != GRRMHD_RECON_PPM)
     return fail(GRRMHD_EINVAL, "bad reconstruction");
   if (!need_grid) return 0;
@@ -173,6 +175,7 @@ static void fill_ctx(const grrmhd_params* p, Ctx& C) {
   C.flux = p->flux;
   C.recon = p->recon;
   C.cold = p->cold;
+  C.cascade = p->cascade;
   // FP32 face path from the first x1 index i whose cell i-1 has r >= r_fp64
   C.mixed_i = 1 << 30;
   if (p->precision == GRRMHD_MIXED) {

@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIBPATH = os.path.join(HERE, "libgrrmhd.so")
 
 ST_PMHD, ST_URAD, ST_TYPE2_NEG, ST_BASIC, ST_C2P_FAIL, ST_FLOOR, ST_NOT_ACCEPT, ST_FAIL, \
-    ST_NO_GOOD_NB, ST_EXTREME, ST_COLD = (1 << i for i in range(11))
+    ST_NO_GOOD_NB, ST_EXTREME, ST_COLD, ST_PRAD, ST_ENTROPY, ST_STAGED = (1 << i for i in range(14))
 
 _BC = {"outflow": 0, "periodic": 1, "reflect": 2, "polar": 3}
 
@@ -33,7 +33,7 @@ class Params(C.Structure):
         ("max_iter", C.c_int), ("roundoff", C.c_int),
         ("rho_floor", C.c_double), ("u_floor", C.c_double), ("bsq_rho_max", C.c_double),
         ("bsq_u_max", C.c_double), ("u_rho_max", C.c_double), ("erad_floor", C.c_double),
-        ("scheme", C.c_int), ("recon", C.c_int), ("cold", C.c_int),
+        ("scheme", C.c_int), ("recon", C.c_int), ("cold", C.c_int), ("cascade", C.c_int),
     ]
 
 
@@ -70,6 +70,7 @@ def params(d: dict) -> Params:
     p.scheme = SCHEMES[d.get("scheme", "rk3")]
     p.recon = 1 if d.get("recon", "mc") == "ppm" else 0
     p.cold = int(d.get("cold", 1))
+    p.cascade = int(d.get("cascade", 0))
     return p
 
 

@@ -56,7 +56,7 @@ def default_params(**kw) -> dict:
         tol_pmhd=1e-12, tol_urad=1e-9, tol_accept=1e-9, tol_fail=1e-7,
         max_iter=20, roundoff=1,
         rho_floor=1e-20, u_floor=1e-22, bsq_rho_max=200.0, bsq_u_max=1e5,
-        u_rho_max=1e10, erad_floor=1e-150, scheme="rk3", recon="mc", cold=1,
+        u_rho_max=1e10, erad_floor=1e-150, scheme="rk3", recon="mc", cold=1, cascade=0,
     )
     p.update(kw)
     return p
