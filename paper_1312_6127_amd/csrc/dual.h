@@ -96,6 +96,15 @@ GR_HD Dual<N> sqrt(const Dual<N>& a) {
   return r;
 }
 template <int N>
+GR_HD Dual<N> log(const Dual<N>& a) {
+  Dual<N> r;
+  r.v = ::log(a.v);
+  const double h = 1.0 / a.v;
+#pragma unroll
+  for (int i = 0; i < N; i++) r.d[i] = a.d[i] * h;
+  return r;
+}
+template <int N>
 GR_HD Dual<N> exp(const Dual<N>& a) {
   Dual<N> r;
   r.v = ::exp(a.v);

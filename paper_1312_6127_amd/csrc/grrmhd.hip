@@ -356,7 +356,7 @@ static Scheme make_scheme(int which) {
 }
 
 struct WsLayout {
-  size_t F, emf, vch, Uexp, Pa, Ua, err, st, it, Us, M, total;
+  size_t F, emf, vch, Uexp, Pa, Ua, err, st, it, Us, M, Fs, Sn, total;
 };
 
 // IMEX schemes add the stage U's (all but the last) and the kept M^k
@@ -383,6 +383,12 @@ static WsLayout ws_layout(const Ctx& C, int scheme = GRRMHD_RK3) {
     const Scheme S = make_scheme(scheme);
     w.Us = take(round256(sizeof(double) * 12 * N) * (S.ns - 1));
     w.M = take(round256(sizeof(double) * 8 * N) * 4);
+  }
+  // the full cascade's entropy tracer (RK3): face fluxes and U_S(P^n)
+  w.Fs = w.Sn = off;
+  if (C.cascade && scheme == GRRMHD_RK3) {
+    w.Fs = take(sizeof(double) * 3 * N);
+    w.Sn = take(sizeof(double) * N);
   }
   w.total = off;
   return w;
@@ -441,7 +447,8 @@ static void split_x1(const FaceRange& R, int i0, FaceRange& a, FaceRange& b) {
 // earlier sub-steps' (0 at a step's first flux evaluation).
 static int launch_fluxes(grrmhd_grid* g, const double* P, const double* ca, const double* ce,
                          double* F, double* emf, double* vch,
-                         unsigned long long* dtmin = nullptr, int keep_flat = 0) {
+                         unsigned long long* dtmin = nullptr, int keep_flat = 0,
+                         double* Fs = nullptr) {
   const Ctx& C = g->C;
   if (C.recon == GRRMHD_RECON_PPM) {
     long nb = 1;
@@ -468,13 +475,21 @@ static int launch_fluxes(grrmhd_grid* g, const double* P, const double* ca, cons
     }
   }
   if (S64.total > 0) {
-    hipLaunchKernelGGL(k_flux_all<double>, dim3(nblocks(S64.total, 128)), dim3(128), 0, g->stream,
-                       C, S64, P, ca, ce, F, vch, (const double*)g->flat);
+    if (Fs)
+      hipLaunchKernelGGL(k_flux_all_s<double>, dim3(nblocks(S64.total, 128)), dim3(128), 0,
+                         g->stream, C, S64, P, ca, ce, F, vch, (const double*)g->flat, Fs);
+    else
+      hipLaunchKernelGGL(k_flux_all<double>, dim3(nblocks(S64.total, 128)), dim3(128), 0,
+                         g->stream, C, S64, P, ca, ce, F, vch, (const double*)g->flat);
     LAUNCHCHK();
   }
   if (S32.total > 0) {
-    hipLaunchKernelGGL(k_flux_all<float>, dim3(nblocks(S32.total, 128)), dim3(128), 0, g->stream,
-                       C, S32, P, ca, ce, F, vch, (const double*)g->flat);
+    if (Fs)
+      hipLaunchKernelGGL(k_flux_all_s<float>, dim3(nblocks(S32.total, 128)), dim3(128), 0,
+                         g->stream, C, S32, P, ca, ce, F, vch, (const double*)g->flat, Fs);
+    else
+      hipLaunchKernelGGL(k_flux_all<float>, dim3(nblocks(S32.total, 128)), dim3(128), 0,
+                         g->stream, C, S32, P, ca, ce, F, vch, (const double*)g->flat);
     LAUNCHCHK();
   }
   // corner EMFs: union of the edge ranges (n + 1 positions along active axes)
@@ -535,7 +550,8 @@ static unsigned list_blocks(long n) { return (unsigned)std::min<long>(nblocks(n,
 
 static int launch_implicit(grrmhd_grid* g, const double* Ue, const double* Pg, double scale,
                            const double* dt_dev, const double* ca, const double* ce, double* P,
-                           double* U, int* it, int* st, double* err) {
+                           double* U, int* it, int* st, double* err,
+                           const double* Sexp = nullptr) {
   const long n = n_interior(g->C);
   // this launch appends to cnt[cp] (zero: set at creation or by the previous
   // launch's cascade kernel) and its cascade kernel zeroes cnt[cp ^ 1]
@@ -555,7 +571,7 @@ static int launch_implicit(grrmhd_grid* g, const double* Ue, const double* Pg, d
     g->nt++;
   }
   hipLaunchKernelGGL(k_implicit_list, dim3(list_blocks(n)), dim3(64), 0, g->stream, g->C, Ue, Pg,
-                     scale, dt_dev, ca, ce, P, U, it, st, err, W);
+                     scale, dt_dev, ca, ce, P, U, it, st, err, W, Sexp);
   LAUNCHCHK();
   g->W.counter = W.counter;
   g->cp ^= 1;
@@ -756,6 +772,16 @@ extern "C" int grrmhd_step(grrmhd_grid* g, double* P, double* U, const double* c
   const double A[3] = {1.0, 0.75, 1.0 / 3.0}, B[3] = {0.0, 0.25, 2.0 / 3.0},
                Cc[3] = {1.0, 0.25, 2.0 / 3.0};
   int rc;
+  // the full cascade's entropy tracer: U_S(P^n), per stage its face fluxes and
+  // explicit value (row 12 of the explicit state, free until the fix-ups)
+  double* Fs = C.cascade ? (double*)(base + w.Fs) : nullptr;
+  double* Sn = C.cascade ? (double*)(base + w.Sn) : nullptr;
+  double* Sexp = C.cascade ? Ue + 12 * N : nullptr;
+  const long nint = n_interior(C);
+  if (C.cascade) {
+    hipLaunchKernelGGL(k_entropy_field, dim3(nblocks(nint, 256)), dim3(256), 0, g->stream, C, P, Sn);
+    LAUNCHCHK();
+  }
   for (int s = 0; s < 3; s++) {
     double* Pin = (s == 0) ? P : Pa;
     const double* Uprev = (s == 0) ? U : Ua;
@@ -767,11 +793,18 @@ extern "C" int grrmhd_step(grrmhd_grid* g, double* P, double* U, const double* c
     const bool red = (s == 0 && !dt_fixed);
     unsigned long long* dmin = red ? g->dtstep[g->dtp] : nullptr;
     unsigned long long* dnext = red ? g->dtstep[g->dtp ^ 1] : nullptr;
-    if ((rc = launch_fluxes(g, Pin, chi_abs, chi_es, F, emf, vch, dmin, s > 0))) return rc;
+    if ((rc = launch_fluxes(g, Pin, chi_abs, chi_es, F, emf, vch, dmin, s > 0, Fs))) return rc;
     if ((rc = launch_update(g, A[s], B[s], Cc[s], dt_dev, Pin, U, Uprev, F, emf, Ue, dmin, dnext)))
       return rc;
     if (red) g->dtp ^= 1;
-    if ((rc = launch_implicit(g, Ue, Pin, Cc[s], dt_dev, chi_abs, chi_es, Pout, Uout, it, st, err)))
+    if (C.cascade) {
+      hipLaunchKernelGGL(k_entropy_update, dim3(nblocks(nint, 256)), dim3(256), 0, g->stream, C,
+                         A[s], B[s], Cc[s], (const double*)dt_dev, (const double*)Sn,
+                         (const double*)Pin, (const double*)Fs, Sexp);
+      LAUNCHCHK();
+    }
+    if ((rc = launch_implicit(g, Ue, Pin, Cc[s], dt_dev, chi_abs, chi_es, Pout, Uout, it, st, err,
+                              Sexp)))
       return rc;
     if ((rc = launch_fixup(g, Pout, Uout, st, Ue, status, it, iters, s > 0))) return rc;
   }
@@ -1019,6 +1052,8 @@ struct AdjPtrs {
 static int adj_ptrs(grrmhd_grid* g, void* workspace, size_t ws_bytes, AdjPtrs& a) {
   if (g->p.recon != GRRMHD_RECON_MC)
     return fail(GRRMHD_EINVAL, "the adjoint covers MC reconstruction");
+  if (g->p.cascade != 0)
+    return fail(GRRMHD_EINVAL, "the adjoint covers the PMHD/URAD cascade (cascade = 0)");
   const AdjLayout w = adj_layout(g->C, g->p.scheme);
   if (ws_bytes < w.total) return fail(GRRMHD_EINVAL, "workspace too small");
   if (((uintptr_t)workspace) & 255) return fail(GRRMHD_EINVAL, "workspace must be 256-byte aligned");
@@ -1497,8 +1532,14 @@ static int launch_batch(const Ctx& C, long n, const double* U_expl, const double
   hipLaunchKernelGGL(k_implicit_batch_list, dim3(list_blocks(n)), dim3(64), 0, s, C, n, U_expl,
                      P_guess, dt_cell, chi_abs, chi_es, P_out, U_out, iters, status, err, D, K);
   LAUNCHCHK();
-  // cells with no energy solution: the cold MHD limit, one thread each
-  if (C.cold && C.u_floor > 0.0) {
+  // the full cascade's rest for the cells the PMHD and URAD attempts left
+  // unaccepted (K holds their record slots), the cold limit inline
+  if (C.cascade) {
+    hipLaunchKernelGGL(k_rest_batch_list, dim3(list_blocks(n)), dim3(64), 0, s, C, n, U_expl,
+                       P_guess, dt_cell, chi_abs, chi_es, P_out, U_out, iters, status, err, W, K);
+    LAUNCHCHK();
+  } else if (C.cold && C.u_floor > 0.0) {
+    // cells with no energy solution: the cold MHD limit, one thread each
     hipLaunchKernelGGL(k_cold_batch_list, dim3(list_blocks(n)), dim3(64), 0, s, C, n, U_expl,
                        P_guess, dt_cell, chi_abs, chi_es, P_out, U_out, iters, status, err, K);
     LAUNCHCHK();

@@ -27,7 +27,7 @@
 #define GRRMHD_URAD_EXACT 1   // URAD Jacobian: 1 exact (dual numbers), 0 one-sided differences
 #endif
 
-enum { M_PMHD = 0, M_URAD = 1 };
+enum { M_PMHD = 0, M_URAD = 1, M_PRAD = 2 };
 
 struct Cell {
   Metric m;
@@ -35,6 +35,7 @@ struct Cell {
   double Tgi[4], Ri[4];   // explicit gas (T^t_t + rho u^t, T^t_i) and radiation R^t_nu
   double dt, chi_abs, chi_es;
   int cold;               // cold MHD: energy residuals left out of the errors
+  double Si;              // explicit [S u^t]_(i) per sqrt(-g) (NAN: none); entropy methods
 };
 
 struct Eval {
@@ -42,6 +43,8 @@ struct Eval {
   double P[12];
   double Eg[4], Er[4];
   double eT, eIg, eIr;
+  double e0g, e0r;        // normalised errors of the energy (entropy) equation
+  double Es;              // entropy residual (entropy methods)
   int radflags, ok;
 };
 
@@ -70,7 +73,7 @@ DEV double snorm3(const Metric& m, const double V[4]) {
 // parts merged in the normal observer's orthonormal basis plus the energy
 // scale; e_T = 1/4 sum over equations of the larger of the two.
 DEV void norm_errors(const Cell& c, const double Tg[4], const double Rr[4], const double G[4],
-                     Eval& e) {
+                     Eval& e, double es = -1.0) {
   double Gdt[4];
 #pragma unroll
   for (int k = 0; k < 4; k++) Gdt[k] = c.dt * G[k];
@@ -90,7 +93,11 @@ DEV void norm_errors(const Cell& c, const double Tg[4], const double Rr[4], cons
     eg[1 + i] = ::fabs(e.Eg[1 + i]) * w / nsg;
     er[1 + i] = ::fabs(e.Er[1 + i]) * w / nsr;
   }
+  // entropy methods: the entropy equation's error in the energy slot
+  if (es >= 0.0) eg[0] = er[0] = es;
   if ((e.radflags & 1) || c.cold) eg[0] = er[0] = 0.0;
+  e.e0g = eg[0];
+  e.e0r = er[0];
   double t = 0.0, ig = 0.0, ir = 0.0;
 #pragma unroll
   for (int k = 0; k < 4; k++) {
@@ -107,11 +114,36 @@ DEV void norm_errors(const Cell& c, const double Tg[4], const double Rr[4], cons
   }
 }
 
+// Entropy equation (eq. source6 with G_S = -G^mu u_mu / T_gas, eq. GS),
+// weighted by T_gas: E_S = T_gas ([S u^t] - [S u^t]_(i)) + dt G^mu u_mu with
+// S = rho0 ln(p^n / rho0^(n+1)), n = 1/(gam - 1); its norm (returned in ns)
+// is the sum of its terms' magnitudes plus the gas energy scale.
+template <class D>
+DEV D entropy_residual(const Cell& c, double gam, const Gas<D>& s, const D G[4], double ntg,
+                       double& ns) {
+  const double n = 1.0 / (gam - 1.0);
+  const D S = s.rho * (n * log(s.pg) - (n + 1.0) * log(s.rho));
+  const D Sut = S * s.v.ucon[0];
+  const D T = s.pg / s.rho;
+  D Gu = G[0] * s.v.ucon[0];
+#pragma unroll
+  for (int k = 1; k < 4; k++) Gu = Gu + G[k] * s.v.ucon[k];
+  const D TS = T * Sut, TSi = T * c.Si, dGu = c.dt * Gu;
+  ns = ::fabs(val(TS)) + ::fabs(val(TSi)) + ::fabs(val(dGu)) + ntg;
+  return (TS - TSi) + dGu;
+}
+
+// gas energy norm |T^t_t + rho u^t| + |its explicit value| + dt |G_t| (Sec. 4.8)
+DEV double gas_energy_norm(const Cell& c, double Tg0, double G0) {
+  const double n = ::fabs(Tg0) + ::fabs(c.Tgi[0]) + ::fabs(c.dt * G0);
+  return (n > 0.0) ? n : 1e-300;
+}
+
 // PMHD residual (Sec. 4.8, PMHD steps in order): rho0 = (rho u^t)/u^t;
 // T^t_nu from the gas; Delta R = -Delta T; TYPE2 radiation inversion; R
 // recomputed; G; residuals.  With D = Dual<N> one pass seeds Jacobian
 // columns k0..k0+N-1; with D = double it evaluates the residual alone.
-template <class D>
+template <class D, bool ENT = false>
 DEV void pmhd_pass(const Cell& c, const Phys& ph, const double x[4], int k0, Eval& e,
                    double J[4][4]) {
   D ug(x[0]), ut[3] = {D(x[1]), D(x[2]), D(x[3])};
@@ -152,6 +184,15 @@ DEV void pmhd_pass(const Cell& c, const Phys& ph, const double x[4], int k0, Eva
   double Tg[4], Rr[4], Gv[4];
   D Rrow[4];
   rad_row(r, Eb, 0, Rrow);
+  double es = -1.0;
+  D Es(0.0);
+  if constexpr (ENT) {
+    double ns;
+    Es = entropy_residual(c, ph.gam, s, G, gas_energy_norm(c, val(row[1]), val(G[0])), ns);
+    es = ::fabs(val(Es)) / ns;
+    e.Es = val(Es);
+    if (!isfinite(e.Es)) es = INFINITY;
+  }
 #pragma unroll
   for (int k = 0; k < 4; k++) {
     const D Egk = (row[1 + k] - c.Tgi[k]) - c.dt * G[k];
@@ -163,7 +204,7 @@ DEV void pmhd_pass(const Cell& c, const Phys& ph, const double x[4], int k0, Eva
     if constexpr (!std::is_same<D, double>::value) {
       constexpr int N = sizeof(D::d) / sizeof(double);
 #pragma unroll
-      for (int j = 0; j < N; j++) J[k][k0 + j] = Egk.d[j];
+      for (int j = 0; j < N; j++) J[k][k0 + j] = (ENT && k == 0) ? Es.d[j] : Egk.d[j];
     }
   }
   if (k0 == 0) {
@@ -179,19 +220,21 @@ DEV void pmhd_pass(const Cell& c, const Phys& ph, const double x[4], int k0, Eva
     }
     e.P[8] = val(Eb);
     e.ok = 1;
-    norm_errors(c, Tg, Rr, Gv, e);
+    norm_errors(c, Tg, Rr, Gv, e, es);
   }
 }
 
+template <bool ENT = false>
 DEV void eval_pmhd(const Cell& c, const Phys& ph, const double x[4], Eval& e, double J[4][4]) {
 #pragma unroll
-  for (int k0 = 0; k0 < 4; k0 += GRRMHD_NJ) pmhd_pass<Dual<GRRMHD_NJ>>(c, ph, x, k0, e, J);
+  for (int k0 = 0; k0 < 4; k0 += GRRMHD_NJ) pmhd_pass<Dual<GRRMHD_NJ>, ENT>(c, ph, x, k0, e, J);
 }
 
 // Residual alone: a Newton step close to the root reuses the factorised
 // Jacobian of the previous evaluation (chord step).
+template <bool ENT = false>
 DEV void eval_pmhd_value(const Cell& c, const Phys& ph, const double x[4], Eval& e) {
-  pmhd_pass<double>(c, ph, x, 0, e, nullptr);
+  pmhd_pass<double, ENT>(c, ph, x, 0, e, nullptr);
 }
 
 // gas (T^t_t + rho u^t, T^t_i) of primitives P, without sqrt(-g)
@@ -263,6 +306,7 @@ DEV void eval_urad(const Cell& c, const Phys& ph, const double x[4], const doubl
 // URAD residual and its exact Jacobian dE_rad/dx in one dual-number pass:
 // the same steps as eval_urad, the gas inversion differentiated by the
 // implicit-function theorem (mhd_invert_dual).  Values equal eval_urad's.
+template <bool ENT = false>
 DEV void eval_urad_jac(const Cell& c, const Phys& ph, const double x[4], const double Pgas[5],
                        Eval& e, double J[4][4]) {
   using D = Dual<4>;
@@ -299,11 +343,20 @@ DEV void eval_urad_jac(const Cell& c, const Phys& ph, const double x[4], const d
   D G[4];
   four_force(s.v, r, Eb, kabs, kes, lam, G);
   double Tg[4], Rv[4], Gv[4];
+  double es = -1.0;
+  D Es(0.0);
+  if constexpr (ENT) {
+    double ns;
+    Es = entropy_residual(c, ph.gam, s, G, gas_energy_norm(c, row[1].v, G[0].v), ns);
+    es = ::fabs(Es.v) / ns;
+    e.Es = Es.v;
+    if (!isfinite(e.Es)) es = INFINITY;
+  }
 #pragma unroll
   for (int k = 0; k < 4; k++) {
     const D Erk = (Rr[k] - c.Ri[k]) + c.dt * G[k];
 #pragma unroll
-    for (int j = 0; j < 4; j++) J[k][j] = Erk.d[j];
+    for (int j = 0; j < 4; j++) J[k][j] = (ENT && k == 0) ? Es.d[j] : Erk.d[j];
     Tg[k] = row[1 + k].v;
     Rv[k] = Rr[k].v;
     Gv[k] = G[k].v;
@@ -319,7 +372,78 @@ DEV void eval_urad_jac(const Cell& c, const Phys& ph, const double x[4], const d
     e.P[9 + i] = utr[i].v;
   }
   e.P[8] = Eb.v;
-  norm_errors(c, Tg, Rv, Gv, e);
+  norm_errors(c, Tg, Rv, Gv, e, es);
+}
+
+// PRAD residual and its exact Jacobian dE_rad/dx in one dual-number pass
+// (Sec. 4.8, PRAD steps): x = (Ebar, u~^i_rad); R^t_nu from the radiation
+// primitives; the gas from the MHD inversion of T(i) - Delta R (Pgas starts
+// it; its derivatives by the implicit-function theorem); G; residuals.
+template <bool ENT = false>
+DEV void eval_prad_jac(const Cell& c, const Phys& ph, const double x[4], const double Pgas[5],
+                       Eval& e, double J[4][4]) {
+  using D = Dual<4>;
+  e.ok = 1;
+  D Eb = D::var(x[0], 0), utr[3];
+#pragma unroll
+  for (int k = 0; k < 4; k++) e.x[k] = x[k];
+#pragma unroll
+  for (int i = 0; i < 3; i++) utr[i] = D::var(x[1 + i], 1 + i);
+  Vel<D> r;
+  make_vel(c.m, utr, r);
+  D Rr[4];
+  rad_row(r, Eb, 0, Rr);
+  const D Tt[3] = {c.Tgi[1] - (Rr[1] - c.Ri[1]), c.Tgi[2] - (Rr[2] - c.Ri[2]),
+                   c.Tgi[3] - (Rr[3] - c.Ri[3])};
+  const D Eg = c.Tgi[0] - (Rr[0] - c.Ri[0]);
+  D rho, ug, ut[3];
+  if (mhd_invert_dual<4>(c.m, ph.gam, c.rhout, Eg, Tt, c.B, Pgas[1], Pgas + 2, rho, ug, ut)) {
+    e.ok = 0;
+    e.eT = INFINITY;
+    return;
+  }
+  e.radflags = 0;
+  const D B[3] = {D(c.B[0]), D(c.B[1]), D(c.B[2])};
+  Gas<D> s;
+  make_gas(c.m, ph.gam, rho, ug, ut, B, s);
+  D row[8];
+  gas_row(s, B, 0, row);
+  const D Tgas = s.pg / rho;
+  const D kabs = c.chi_abs * rho, kes = c.chi_es * rho;
+  const D lam = kabs * ph.arad * (Tgas * Tgas) * (Tgas * Tgas);
+  D G[4];
+  four_force(s.v, r, Eb, kabs, kes, lam, G);
+  double Tg[4], Rv[4], Gv[4];
+  double es = -1.0;
+  D Es(0.0);
+  if constexpr (ENT) {
+    double ns;
+    Es = entropy_residual(c, ph.gam, s, G, gas_energy_norm(c, row[1].v, G[0].v), ns);
+    es = ::fabs(Es.v) / ns;
+    e.Es = Es.v;
+    if (!isfinite(e.Es)) es = INFINITY;
+  }
+#pragma unroll
+  for (int k = 0; k < 4; k++) {
+    const D Erk = (Rr[k] - c.Ri[k]) + c.dt * G[k];
+#pragma unroll
+    for (int j = 0; j < 4; j++) J[k][j] = (ENT && k == 0) ? Es.d[j] : Erk.d[j];
+    Tg[k] = row[1 + k].v;
+    Rv[k] = Rr[k].v;
+    Gv[k] = G[k].v;
+    e.Eg[k] = (Tg[k] - c.Tgi[k]) - c.dt * Gv[k];
+    e.Er[k] = Erk.v;
+  }
+  e.P[0] = rho.v;
+  e.P[1] = ug.v;
+#pragma unroll
+  for (int i = 0; i < 3; i++) {
+    e.P[2 + i] = ut[i].v;
+    e.P[5 + i] = c.B[i];
+    e.P[9 + i] = x[1 + i];
+  }
+  e.P[8] = x[0];
+  norm_errors(c, Tg, Rv, Gv, e, es);
 }
 
 // 4x4 solve with partial pivoting; 0 on success
@@ -450,9 +574,10 @@ DEV void keep(Best& b, const Eval& e) {
 // record is live: the new iterate is evaluated into it once the step is
 // taken (PMHD needs only x; URAD keeps the five gas values that seed its
 // inner inversion).
-template <int METHOD>
+template <int METHOD, bool ENT = false>
 DEV void newton(const Cell& c, const Phys& ph, const Opts& o, const double x0[4],
                 const double Pg0[5], Best& best, int& iters) {
+  static_assert(METHOD != M_PRAD || GRRMHD_URAD_EXACT, "PRAD uses exact Jacobians only");
   const double tol = (METHOD == M_PMHD) ? o.tol_pmhd : o.tol_urad;
   double x[4] = {x0[0], x0[1], x0[2], x0[3]};
   Eval ev;
@@ -460,8 +585,9 @@ DEV void newton(const Cell& c, const Phys& ph, const Opts& o, const double x0[4]
   int piv[4] = {0, 1, 2, 3};
   bool fresh = true;   // PMHD: J holds a new Jacobian, not yet factorised
   bool jok = true;      // URAD (exact): J holds the Jacobian at x
-  if (METHOD == M_PMHD) eval_pmhd(c, ph, x, ev, J);
-  else if (GRRMHD_URAD_EXACT) eval_urad_jac(c, ph, x, Pg0, ev, J);
+  if (METHOD == M_PMHD) eval_pmhd<ENT>(c, ph, x, ev, J);
+  else if (METHOD == M_PRAD) eval_prad_jac<ENT>(c, ph, x, Pg0, ev, J);
+  else if (GRRMHD_URAD_EXACT) eval_urad_jac<ENT>(c, ph, x, Pg0, ev, J);
   else eval_urad(c, ph, x, Pg0, ev);
   keep(best, ev);
   if (!ev.ok) return;
@@ -481,10 +607,11 @@ DEV void newton(const Cell& c, const Phys& ph, const Opts& o, const double x0[4]
     double Pn[5];
 #pragma unroll
     for (int q = 0; q < 5; q++) Pn[q] = ev.P[q];
-    if (METHOD == M_URAD && GRRMHD_URAD_EXACT) {
+    if (METHOD != M_PMHD && GRRMHD_URAD_EXACT) {
       if (!jok) {                       // after a back-off: the Jacobian at x
         Eval ej;
-        eval_urad_jac(c, ph, x, Pn, ej, J);
+        if (METHOD == M_PRAD) eval_prad_jac<ENT>(c, ph, x, Pn, ej, J);
+        else eval_urad_jac<ENT>(c, ph, x, Pn, ej, J);
         if (!ej.ok) break;
         jok = true;
       }
@@ -526,6 +653,7 @@ DEV void newton(const Cell& c, const Phys& ph, const Opts& o, const double x0[4]
 #pragma unroll
       for (int i = 0; i < 4; i++) r[i] = ev.Eg[i];
     }
+    if (ENT) r[0] = ev.Es;   // the entropy equation in the energy slot
     double dx[4];
     if (METHOD == M_PMHD) {
       if (fresh) {
@@ -542,19 +670,26 @@ DEV void newton(const Cell& c, const Phys& ph, const Opts& o, const double x0[4]
     if (METHOD == M_PMHD) {
       if (xn[0] < 0.0) xn[0] = 0.5 * ::fabs(xn[0]);            // one-sided bisection of u_g
       if (ev.eT < GRRMHD_CHORD_TOL) {
-        eval_pmhd_value(c, ph, xn, ev);
+        eval_pmhd_value<ENT>(c, ph, xn, ev);
       } else {
-        eval_pmhd(c, ph, xn, ev, J);
+        eval_pmhd<ENT>(c, ph, xn, ev, J);
         fresh = true;
       }
     } else {
-      const double Erl = rad_energy_lab(c.m, xn);
-      if (Erl <= 0.0) {                                       // same for the radiation energy
-        const double a2 = c.m.alpha * c.m.alpha;
-        xn[0] = -0.5 * ::fabs(Erl) + a2 * (c.m.up(0, 1) * xn[1] + c.m.up(0, 2) * xn[2] + c.m.up(0, 3) * xn[3]);
+      if (METHOD == M_PRAD) {
+        if (xn[0] < 0.0) xn[0] = 0.5 * ::fabs(xn[0]);          // the same for Ebar
+      } else {
+        const double Erl = rad_energy_lab(c.m, xn);
+        if (Erl <= 0.0) {                                     // same for the radiation energy
+          const double a2 = c.m.alpha * c.m.alpha;
+          xn[0] = -0.5 * ::fabs(Erl) + a2 * (c.m.up(0, 1) * xn[1] + c.m.up(0, 2) * xn[2] + c.m.up(0, 3) * xn[3]);
+        }
       }
-      if (GRRMHD_URAD_EXACT) {
-        eval_urad_jac(c, ph, xn, Pn, ev, J);
+      if (METHOD == M_PRAD) {
+        eval_prad_jac<ENT>(c, ph, xn, Pn, ev, J);
+        jok = ev.ok;
+      } else if (GRRMHD_URAD_EXACT) {
+        eval_urad_jac<ENT>(c, ph, xn, Pn, ev, J);
         jok = ev.ok;
       } else {
         eval_urad(c, ph, xn, Pn, ev);
@@ -565,8 +700,11 @@ DEV void newton(const Cell& c, const Phys& ph, const Opts& o, const double x0[4]
         if (GRRMHD_URAD_EXACT && nfail > 3) break;            // ends below either way
 #pragma unroll
         for (int i = 0; i < 4; i++) xn[i] = 0.5 * (x[i] + xn[i]);
-        if (GRRMHD_URAD_EXACT) {
-          eval_urad_jac(c, ph, xn, Pn, ev, J);
+        if (METHOD == M_PRAD) {
+          eval_prad_jac<ENT>(c, ph, xn, Pn, ev, J);
+          jok = ev.ok;
+        } else if (GRRMHD_URAD_EXACT) {
+          eval_urad_jac<ENT>(c, ph, xn, Pn, ev, J);
           jok = ev.ok;
         } else {
           eval_urad(c, ph, xn, Pn, ev);
@@ -628,6 +766,7 @@ DEV void cell_setup(const Metric& m, const double Ui[12], double dt, double chi_
   c.chi_abs = chi_abs;
   c.chi_es = chi_es;
   c.cold = 0;
+  c.Si = NAN;
 }
 
 DEV void prepare(const Metric& m, const Phys& ph, const double Ui[12], const double Pg[12], double dt,
@@ -673,7 +812,7 @@ DEV void finalize(const Cell& c, const Phys& ph, const Opts& o, const Best& best
                   int status, int iters, const double Ui[12], CellOut& out) {
   const Metric& m = c.m;
   out.iters = iters;
-  status |= (method == M_PMHD) ? GRRMHD_ST_PMHD : GRRMHD_ST_URAD;
+  status |= (method == M_PMHD) ? GRRMHD_ST_PMHD : (method == M_URAD) ? GRRMHD_ST_URAD : GRRMHD_ST_PRAD;
   if (best.eT > o.tol_fail) status |= GRRMHD_ST_FAIL;
   else if (best.eT > o.tol_accept) status |= GRRMHD_ST_NOT_ACCEPT;
   if (best.radflags & 1) status |= GRRMHD_ST_TYPE2_NEG;
@@ -684,6 +823,10 @@ DEV void finalize(const Cell& c, const Phys& ph, const Opts& o, const Best& best
     gas_cons4(m, ph.gam, best.P, Ug);
 #pragma unroll
     for (int k = 0; k < 4; k++) Ur[k] = c.Ri[k] - (Ug[k] - c.Tgi[k]);
+  } else if (method == M_PRAD) {
+    rad_cons4(m, best.P, Ur);
+#pragma unroll
+    for (int k = 0; k < 4; k++) Ug[k] = c.Tgi[k] - (Ur[k] - c.Ri[k]);
   } else {
 #pragma unroll
     for (int k = 0; k < 4; k++) {
@@ -952,6 +1095,321 @@ DEV void implicit_cell(const Metric& m, const Phys& ph, const Opts& o, const dou
   if (bm < 0) failed_out(Ui, Pg, pr.status, iters, out);
   else finalize(c, ph, o, best, bm, pr.status, iters, Ui, out);
   if (try_cold) cold_fallback(m, ph, o, Ui, Pg, dt, chi_abs, chi_es, out);
+}
+
+// ---------------------------------------------------------------------------
+// The paper's full cascade (params.cascade = 1; Sec. 4.10-4.11): PMHD, URAD
+// and PRAD, their staged forms for cells still without an acceptable
+// solution, the same with the entropy equation in place of the gas energy
+// equation, then the cold limit.  Exact dual-number Jacobians throughout.
+// ---------------------------------------------------------------------------
+
+// residual and exact Jacobian of one method at x (Pn starts the inner MHD
+// inversion of URAD and PRAD)
+template <int METHOD, bool ENT>
+DEV void eval_jac(const Cell& c, const Phys& ph, const double x[4], const double Pn[5], Eval& e,
+                  double J[4][4]) {
+  if (METHOD == M_PMHD) eval_pmhd<ENT>(c, ph, x, e, J);
+  else if (METHOD == M_PRAD) eval_prad_jac<ENT>(c, ph, x, Pn, e, J);
+  else eval_urad_jac<ENT>(c, ph, x, Pn, e, J);
+}
+
+template <int METHOD, bool ENT>
+DEV void method_res(const Eval& e, double r[4]) {
+  const double* E = (METHOD == M_PMHD) ? e.Eg : e.Er;
+#pragma unroll
+  for (int k = 0; k < 4; k++) r[k] = E[k];
+  if (ENT) r[0] = e.Es;
+}
+
+// post-step check (Sec. 4.10): a negative u_g (PMHD), lab radiation energy
+// (URAD) or Ebar (PRAD) becomes half its magnitude; true when it acted
+template <int METHOD>
+DEV bool post_step(const Cell& c, double xn[4]) {
+  if (METHOD != M_URAD) {
+    if (xn[0] < 0.0) {
+      xn[0] = 0.5 * ::fabs(xn[0]);
+      return true;
+    }
+    return false;
+  }
+  const double Erl = rad_energy_lab(c.m, xn);
+  if (Erl <= 0.0) {
+    const double a2 = c.m.alpha * c.m.alpha;
+    xn[0] = -0.5 * ::fabs(Erl) + a2 * (c.m.up(0, 1) * xn[1] + c.m.up(0, 2) * xn[2] + c.m.up(0, 3) * xn[3]);
+    return true;
+  }
+  return false;
+}
+
+// The staged attempt (Sec. 4.10): stage 1 one momentum-only step (x_0
+// held) damped by 1/2; stage 2 energy-only (entropy-only) steps on x_0, the
+// first damped by 1/2, until that equation's own error is below the
+// method's tolerance, the step is at round-off or max_iter steps; a
+// post-step correction recurring 2 times (4 with the entropy equation)
+// holds the prior value and ends the stage; stage 3 the 4-D Newton for at
+// most 40 steps, the first damped by 1/4, with newton()'s stopping rules.
+template <int METHOD, bool ENT>
+DEV void newton_staged(const Cell& c, const Phys& ph, const Opts& o, const double x0[4],
+                       const double Pg0[5], Best& best, int& iters) {
+  const double tol = (METHOD == M_PMHD) ? o.tol_pmhd : o.tol_urad;
+  const int nmod_max = ENT ? 4 : 2;
+  double x[4] = {x0[0], x0[1], x0[2], x0[3]};
+  double Pn[5] = {Pg0[0], Pg0[1], Pg0[2], Pg0[3], Pg0[4]};
+  Eval ev;
+  double J[4][4];
+  eval_jac<METHOD, ENT>(c, ph, x, Pn, ev, J);
+  keep(best, ev);
+  if (!ev.ok) return;
+  for (int stage = 1; stage <= 2; stage++) {
+    const int nmax = (stage == 1) ? 1 : o.max_iter;
+    int nmod = 0;
+    for (int it = 0; it < nmax; it++) {
+      if (stage == 2 && ((METHOD == M_PMHD) ? ev.e0g : ev.e0r) < tol) break;
+      double r[4], xn[4] = {x[0], x[1], x[2], x[3]};
+      method_res<METHOD, ENT>(ev, r);
+      const double D = (it == 0) ? 0.5 : 1.0;
+      if (stage == 1) {
+        double A[4][4], dx[4];
+#pragma unroll
+        for (int i = 0; i < 4; i++)
+#pragma unroll
+          for (int j = 0; j < 4; j++) A[i][j] = (i == 0 || j == 0) ? (i == j ? 1.0 : 0.0) : J[i][j];
+        double rm[4] = {0.0, r[1], r[2], r[3]};
+        if (solve4(A, rm, dx)) break;
+#pragma unroll
+        for (int i = 1; i < 4; i++) xn[i] = x[i] - D * dx[i];
+      } else {
+        if (!(::fabs(J[0][0]) > 0.0) || !isfinite(J[0][0])) break;
+        xn[0] = x[0] - D * r[0] / J[0][0];
+      }
+      if (post_step<METHOD>(c, xn)) {
+        if (++nmod >= nmod_max) break;
+      }
+#pragma unroll
+      for (int q = 0; q < 5; q++) Pn[q] = ev.P[q];
+      Eval en;
+      eval_jac<METHOD, ENT>(c, ph, xn, Pn, en, J);
+      iters++;
+      if (!en.ok) {
+        eval_jac<METHOD, ENT>(c, ph, x, Pn, ev, J);   // the Jacobian at the held x
+        break;
+      }
+      bool small = true;
+#pragma unroll
+      for (int i = 0; i < 4; i++)
+        if (::fabs(xn[i] - x[i]) > 10.0 * DBL_EPSILON * ::fabs(x[i])) small = false;
+#pragma unroll
+      for (int i = 0; i < 4; i++) x[i] = xn[i];
+      ev = en;
+      if (ev.eT < best.eT) keep(best, ev);
+      if (small) break;
+    }
+  }
+  double h[5];
+#pragma unroll
+  for (int k = 0; k < 4; k++) h[k] = INFINITY;
+  h[4] = ev.eT;
+  int nrise = 0, extra = 0, conv = 0, nfail = 0;
+  for (int it = 0; it < 40; it++) {
+    if (ev.eT < tol) conv = 1;
+    if (conv) {
+      if (!o.roundoff || extra >= 3) break;
+      extra++;
+    }
+    if (!conv && it >= 5 && ev.eT > 0.5 * (h[0] + h[1] + h[2]) * (1.0 / 3.0)) break;
+    double r[4], dx[4];
+    method_res<METHOD, ENT>(ev, r);
+    if (solve4(J, r, dx)) break;
+    const double D = (it == 0) ? 0.25 : 1.0;
+    double xn[4];
+#pragma unroll
+    for (int i = 0; i < 4; i++) xn[i] = x[i] - D * dx[i];
+    post_step<METHOD>(c, xn);
+#pragma unroll
+    for (int q = 0; q < 5; q++) Pn[q] = ev.P[q];
+    Eval en;
+    double Jn[4][4];
+    eval_jac<METHOD, ENT>(c, ph, xn, Pn, en, Jn);
+    if (METHOD != M_PMHD) {
+      int back = 0;
+      while (!en.ok && back < 20) {
+        nfail++;
+        if (nfail > 3) break;
+#pragma unroll
+        for (int i = 0; i < 4; i++) xn[i] = 0.5 * (x[i] + xn[i]);
+        eval_jac<METHOD, ENT>(c, ph, xn, Pn, en, Jn);
+        back++;
+      }
+      if (!en.ok || nfail > 3) {
+        iters++;
+        break;
+      }
+    }
+    iters++;
+    if (!en.ok) break;
+    bool small = true;
+#pragma unroll
+    for (int i = 0; i < 4; i++)
+      if (::fabs(xn[i] - x[i]) > 10.0 * DBL_EPSILON * ::fabs(x[i])) small = false;
+#pragma unroll
+    for (int i = 0; i < 4; i++) x[i] = xn[i];
+#pragma unroll
+    for (int i = 0; i < 4; i++)
+#pragma unroll
+      for (int j = 0; j < 4; j++) J[i][j] = Jn[i][j];
+    const double prev = h[4];
+#pragma unroll
+    for (int k = 0; k < 4; k++) h[k] = h[k + 1];
+    h[4] = en.eT;
+    ev = en;
+    if (ev.eT < best.eT) keep(best, ev);
+    if (it >= 5 && ev.eT > prev) {
+      nrise++;
+      if (nrise >= 5) break;
+    }
+    if (small) break;
+  }
+}
+
+// One attempt of one method, normal or staged (run-time choice over the
+// compile-time forms).
+template <bool ENT>
+DEV void attempt(int method, bool staged, const Cell& c, const Phys& ph, const Opts& o,
+                 const double x0[4], const double P0[5], Best& b, int& iters) {
+  if (staged) {
+    if (method == M_PMHD) newton_staged<M_PMHD, ENT>(c, ph, o, x0, P0, b, iters);
+    else if (method == M_URAD) newton_staged<M_URAD, ENT>(c, ph, o, x0, P0, b, iters);
+    else newton_staged<M_PRAD, ENT>(c, ph, o, x0, P0, b, iters);
+  } else {
+    if (method == M_PMHD) newton<M_PMHD, ENT>(c, ph, o, x0, P0, b, iters);
+    else if (method == M_URAD) newton<M_URAD, ENT>(c, ph, o, x0, P0, b, iters);
+    else newton<M_PRAD, ENT>(c, ph, o, x0, P0, b, iters);
+  }
+}
+
+// One phase (energy or, with ENT, entropy equation): the normal attempts
+// (PMHD, URAD, PRAD; URAD and PRAD first in the extreme regime) until one
+// is acceptable, then the staged attempts of PMHD, URAD and PRAD.  The
+// first `skip` normal attempts already ran (their best is in best/bm).  Each
+// attempt starts from the best so far when its e_T < 1e-4, else from its
+// own guess: PMHD the thin-limit primitives (staged: u_g from the explicit
+// entropy at the prior rho0), URAD R(P_n), PRAD the thin-limit radiation.
+template <bool ENT>
+DEV void run_phase(const Cell& c, const Phys& ph, const Opts& o, const Prep& pr,
+                   const double Pg[12], const double Pradthin[12], int skip, Best& best, int& bm,
+                   int& staged, int& iters) {
+  const double acc = accept_threshold(o);
+  for (int k = skip; k < 6; k++) {
+    if (best.eT < acc) return;
+    const bool stg = k >= 3;
+    const int kk = k % 3;
+    const int method = stg ? kk : (pr.extreme ? (kk == 0 ? M_URAD : (kk == 1 ? M_PRAD : M_PMHD)) : kk);
+    const bool prev = (bm >= 0 && best.eT < 1e-4);
+    double x0[4], P0[5];
+    if (method == M_PMHD) {
+      const double* src = prev ? best.P : pr.Pthin;
+      x0[0] = src[1]; x0[1] = src[2]; x0[2] = src[3]; x0[3] = src[4];
+#pragma unroll
+      for (int q = 0; q < 5; q++) P0[q] = src[q];
+      if (stg && !prev && isfinite(c.Si) && c.rhout > 0.0) {
+        // u_g from the specific entropy Si/(rho0 u^t) at the prior rho0
+        const double n = 1.0 / (ph.gam - 1.0), rho = pr.Pthin[0];
+        const double pg = ::exp((c.Si / c.rhout + (n + 1.0) * ::log(rho)) / n);
+        if (isfinite(pg) && pg > 0.0) x0[0] = pg / (ph.gam - 1.0);
+      }
+    } else if (method == M_URAD) {
+      const double* src = prev ? best.P : Pg;
+      rad_cons4(c.m, src, x0);
+#pragma unroll
+      for (int q = 0; q < 5; q++) P0[q] = src[q];
+    } else {
+      const double* src = prev ? best.P : Pradthin;
+      x0[0] = src[8]; x0[1] = src[9]; x0[2] = src[10]; x0[3] = src[11];
+#pragma unroll
+      for (int q = 0; q < 5; q++) P0[q] = src[q];
+    }
+    Best b;
+    b.eT = INFINITY;
+    b.ok = 0;
+    attempt<ENT>(method, stg, c, ph, o, x0, P0, b, iters);
+    if (b.ok && b.eT < best.eT) {
+      best = b;
+      bm = method;
+      staged = stg;
+    }
+  }
+}
+
+// Full cascade for one cell.  Si: the explicit entropy sqrt(-g) [S u^t]_(i)
+// (NAN: no entropy phase).  resume 1: the first PMHD attempt ran (record R
+// at `slot`), 2: PMHD and URAD ran (the record holds the better of the two,
+// its method in the record's ok field); 0 from scratch.
+DEV void implicit_cell_full(const Metric& m, const Phys& ph, const Opts& o, const double Ui[12],
+                            double Si, const double Pg[12], double dt, double chi_abs,
+                            double chi_es, CellOut& out, const RecBuf* R = nullptr,
+                            long slot = 0, int resume = 0) {
+  Cell c;
+  Prep pr;
+  prepare(m, ph, Ui, Pg, dt, chi_abs, chi_es, c, pr);
+  c.Si = Si / m.gdet;
+  const double acc = accept_threshold(o);
+  double Pradthin[12];
+#pragma unroll
+  for (int q = 0; q < 12; q++) Pradthin[q] = Pg[q];
+  if (dt * (chi_abs + chi_es) * Pg[0] < 2.0 / 3.0) {
+    double Eb, utr[3];
+    rad_invert(m, ph.gamma_max, ph.ymax, 0, c.Ri, Eb, utr);
+    if (Eb > 0.0 && isfinite(Eb)) {
+      Pradthin[8] = Eb; Pradthin[9] = utr[0]; Pradthin[10] = utr[1]; Pradthin[11] = utr[2];
+    }
+  }
+  Best bE;
+  bE.eT = INFINITY;
+  bE.ok = 0;
+  int mE = -1, sE = 0, iters = 0, skip = 0;
+  if (R && resume && !pr.extreme) {
+    Best b;
+    rec_load(*R, slot, b, iters);
+    const int meth = b.ok >> 1;
+    b.ok &= 1;
+    if (b.ok) {
+      bE = b;
+      mE = meth;
+    }
+    skip = resume;
+  }
+  run_phase<false>(c, ph, o, pr, Pg, Pradthin, skip, bE, mE, sE, iters);
+  const bool eok = mE >= 0 && bE.P[1] > 0.0;
+  int use = -1;
+  Best bS;
+  int mS = -1, sS = 0;
+  if (eok && bE.eT < acc) {
+    use = 0;
+  } else {
+    bS.eT = INFINITY;
+    bS.ok = 0;
+    if (isfinite(c.Si)) run_phase<true>(c, ph, o, pr, Pg, Pradthin, 0, bS, mS, sS, iters);
+    const bool sok = mS >= 0 && bS.P[1] > 0.0;
+    if (sok && bS.eT < acc) use = 1;
+    else {
+      const bool e2 = eok && bE.eT <= o.tol_fail, s2 = sok && bS.eT <= o.tol_fail;
+      if (e2 && s2) use = (bS.eT < bE.eT) ? 1 : 0;
+      else if (e2) use = 0;
+      else if (s2) use = 1;
+    }
+  }
+  if (use == 1) {
+    finalize(c, ph, o, bS, mS, pr.status, iters, Ui, out);
+    out.status |= GRRMHD_ST_ENTROPY | (sS ? GRRMHD_ST_STAGED : 0);
+  } else if (mE >= 0) {
+    finalize(c, ph, o, bE, mE, pr.status, iters, Ui, out);
+    if (use == 0 && sE) out.status |= GRRMHD_ST_STAGED;
+    if (use < 0) out.status |= GRRMHD_ST_FAIL;
+  } else {
+    failed_out(Ui, Pg, pr.status, iters, out);
+  }
+  cold_fallback(m, ph, o, Ui, Pg, dt, chi_abs, chi_es, out);
 }
 
 // ---------------------------------------------------------------------------

@@ -299,11 +299,25 @@ struct FaceRange {
 // arithmetic T (double; float for the FP32-mixed path); fluxes and speeds are
 // stored as double.
 // fl: the PPM flattener [3][gas, radiation][Ntot] (unused for MC)
+// sqrt(-g) S u^t and sqrt(-g) S u^D of the entropy tracer at a face state
+// (S = rho0 ln(p^n / rho0^(n+1)), n = 1/(gam - 1); Sec. 4 lists of U_q, F_q)
 template <int D, class T>
+DEV void entropy_face(const Ctx& C, const MetricT<T>& m, const T* P, T& Us, T& Fs) {
+  Vel<T> v;
+  make_vel(m, P + 2, v);
+  const T n = T(1.0 / (C.gam - 1.0));
+  const T pg = T(C.gam - 1.0) * P[1];
+  const T S = P[0] * (n * log(pg) - (n + T(1.0)) * log(P[0]));
+  Us = m.gdet * S * v.ucon[0];
+  Fs = m.gdet * S * v.ucon[D];
+}
+
+template <int D, class T, bool ENTF = false>
 DEV void flux_at(Ctx C, FaceRange R, const double* __restrict__ P,
                                const double* __restrict__ chi_abs,
                                const double* __restrict__ chi_es, double* __restrict__ F,
-                               double* __restrict__ vchar, const double* __restrict__ fl, long t) {
+                               double* __restrict__ vchar, const double* __restrict__ fl, long t,
+                               double* __restrict__ Fs = nullptr) {
   if (t >= R.total) return;
   const int i = R.lo[0] + t % R.cnt[0];
   const long t2 = t / R.cnt[0];
@@ -361,6 +375,20 @@ DEV void flux_at(Ctx C, FaceRange R, const double* __restrict__ P,
     F[q * C.Ntot + c] = (double)f;
   }
   vchar[c] = (double)fmax(fmax(gmin, gmax), fmax(rmin, rmax));
+  if constexpr (ENTF) {
+    // the entropy tracer's flux, with the gas speeds
+    T UsL, FsL, UsR, FsR, f;
+    entropy_face<D, T>(C, m, PL, UsL, FsL);
+    entropy_face<D, T>(C, m, PR, UsR, FsR);
+    if (C.flux == GRRMHD_FLUX_HLL) {
+      const T den = gmin + gmax;
+      f = (den > zero) ? (gmin * FsR + gmax * FsL - gmin * gmax * (UsR - UsL)) / den
+                       : T(0.5) * (FsL + FsR);
+    } else {
+      f = T(0.5) * (FsR + FsL - fmax(gmin, gmax) * (UsR - UsL));
+    }
+    Fs[c] = (double)f;
+  }
 }
 
 
@@ -375,11 +403,11 @@ struct FluxSegs {
   long total;
 };
 
-template <class T>
+template <class T, bool ENTF = false>
 DEV void flux_all_at(Ctx C, const FluxSegs& S, const double* __restrict__ P,
                      const double* __restrict__ chi_abs, const double* __restrict__ chi_es,
                      double* __restrict__ F, double* __restrict__ vchar,
-                     const double* __restrict__ fl, long t) {
+                     const double* __restrict__ fl, long t, double* __restrict__ Fs = nullptr) {
   if (t >= S.total) return;
   int k = 0;
   if (S.n > 1 && t >= S.start[1]) k = 1;
@@ -388,9 +416,10 @@ DEV void flux_all_at(Ctx C, const FluxSegs& S, const double* __restrict__ P,
   const int D = S.D[k];
   double* Fd = F + (long)(D - 1) * 12 * C.Ntot;
   double* vd = vchar + (long)(D - 1) * C.Ntot;
-  if (D == 1) flux_at<1, T>(C, S.R[k], P, chi_abs, chi_es, Fd, vd, fl, u);
-  else if (D == 2) flux_at<2, T>(C, S.R[k], P, chi_abs, chi_es, Fd, vd, fl, u);
-  else flux_at<3, T>(C, S.R[k], P, chi_abs, chi_es, Fd, vd, fl, u);
+  double* Fsd = ENTF ? Fs + (long)(D - 1) * C.Ntot : nullptr;
+  if (D == 1) flux_at<1, T, ENTF>(C, S.R[k], P, chi_abs, chi_es, Fd, vd, fl, u, Fsd);
+  else if (D == 2) flux_at<2, T, ENTF>(C, S.R[k], P, chi_abs, chi_es, Fd, vd, fl, u, Fsd);
+  else flux_at<3, T, ENTF>(C, S.R[k], P, chi_abs, chi_es, Fd, vd, fl, u, Fsd);
 }
 
 template <class T>
@@ -401,6 +430,79 @@ __global__ void GRRMHD_FLUX_LB k_flux_all(Ctx C, FluxSegs S, const double* __res
                                           const double* __restrict__ fl) {
   flux_all_at<T>(C, S, P, chi_abs, chi_es, F, vchar, fl,
                  xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x);
+}
+
+// The same with the entropy tracer's face fluxes Fs [3][Ntot] (the full
+// implicit cascade's entropy equation)
+template <class T>
+__global__ void GRRMHD_FLUX_LB k_flux_all_s(Ctx C, FluxSegs S, const double* __restrict__ P,
+                                            const double* __restrict__ chi_abs,
+                                            const double* __restrict__ chi_es,
+                                            double* __restrict__ F, double* __restrict__ vchar,
+                                            const double* __restrict__ fl,
+                                            double* __restrict__ Fs) {
+  flux_all_at<T, true>(C, S, P, chi_abs, chi_es, F, vchar, fl,
+                       xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x, Fs);
+}
+
+// sqrt(-g) S u^t of one cell's primitives p (the entropy tracer; NAN where
+// rho0 or u_g is not positive)
+DEV double entropy_cons(double gam, const Metric& m, const double p[5]) {
+  if (!(p[0] > 0.0) || !(p[1] > 0.0)) return NAN;
+  Vel<double> v;
+  make_vel(m, p + 2, v);
+  const double n = 1.0 / (gam - 1.0);
+  const double S = p[0] * (n * ::log((gam - 1.0) * p[1]) - (n + 1.0) * ::log(p[0]));
+  return m.gdet * S * v.ucon[0];
+}
+
+DEV bool interior_ijk(const Ctx& C, long t, int& i, int& j, int& k) {
+  if (t >= (long)C.n[0] * C.n[1] * C.n[2]) return false;
+  i = C.ng[0] + t % C.n[0];
+  const long t2 = t / C.n[0];
+  j = C.ng[1] + t2 % C.n[1];
+  k = C.ng[2] + t2 / C.n[1];
+  return true;
+}
+
+// the entropy tracer of P at interior cells
+__global__ void LB(256) k_entropy_field(Ctx C, const double* __restrict__ P, double* __restrict__ S) {
+  int i, j, k;
+  if (!interior_ijk(C, (long)blockIdx.x * blockDim.x + threadIdx.x, i, j, k)) return;
+  const long c = cell_index(C, i, j, k);
+  Metric m;
+  load_metric(C.geo_c, C.npos, i + C.N[0] * j, m);
+  double p[5];
+#pragma unroll
+  for (int q = 0; q < 5; q++) p[q] = P[q * C.Ntot + c];
+  S[c] = entropy_cons(C.gam, m, p);
+}
+
+// the entropy tracer's explicit stage value at interior cells:
+// a Sn + b U_S(P) + cc dt (-div Fs), Sn = U_S(P^n), P the stage's input
+__global__ void LB(256) k_entropy_update(Ctx C, double a, double b, double cc,
+                                         const double* __restrict__ dt_dev,
+                                         const double* __restrict__ Sn,
+                                         const double* __restrict__ P,
+                                         const double* __restrict__ Fs,
+                                         double* __restrict__ Sexp) {
+  int i, j, k;
+  if (!interior_ijk(C, (long)blockIdx.x * blockDim.x + threadIdx.x, i, j, k)) return;
+  const long c = cell_index(C, i, j, k);
+  double sp = 0.0;
+  if (b != 0.0) {
+    Metric m;
+    load_metric(C.geo_c, C.npos, i + C.N[0] * j, m);
+    double p[5];
+#pragma unroll
+    for (int q = 0; q < 5; q++) p[q] = P[q * C.Ntot + c];
+    sp = entropy_cons(C.gam, m, p);
+  }
+  double div = 0.0;
+  for (int d = 0; d < 3; d++)
+    if (C.n[d] > 1)
+      div += (Fs[(long)d * C.Ntot + c + C.st[d]] - Fs[(long)d * C.Ntot + c]) / C.dx[d];
+  Sexp[c] = a * Sn[c] + (b != 0.0 ? b * sp : 0.0) - cc * (*dt_dev) * div;
 }
 
 // ---------------------------------------------------------------------------
@@ -924,7 +1026,7 @@ __global__ void LB(64) k_implicit_list(Ctx C, const double* __restrict__ Uexp,
                                        const double* __restrict__ chi_es, double* P,
                                        double* __restrict__ U, int* __restrict__ iters,
                                        int* __restrict__ status, double* __restrict__ err,
-                                       Work W) {
+                                       Work W, const double* __restrict__ Sexp) {
   const int n = *W.counter;
   if (W.counter_next && blockIdx.x == 0 && threadIdx.x == 0) *W.counter_next = 0;
   for (long w = (long)blockIdx.x * blockDim.x + threadIdx.x; w < n;
@@ -944,8 +1046,12 @@ __global__ void LB(64) k_implicit_list(Ctx C, const double* __restrict__ Uexp,
       Pg[q] = Pguess[q * C.Ntot + c];
     }
     CellOut o;
-    implicit_cell(m, make_phys(C), make_opts(C), Ui, Pg, dt_scale * (*dt_dev), chi_abs[c],
-                  chi_es[c], o, &W.rec, w);
+    if (C.cascade)
+      implicit_cell_full(m, make_phys(C), make_opts(C), Ui, Sexp ? Sexp[c] : NAN, Pg,
+                         dt_scale * (*dt_dev), chi_abs[c], chi_es[c], o, &W.rec, w, 1);
+    else
+      implicit_cell(m, make_phys(C), make_opts(C), Ui, Pg, dt_scale * (*dt_dev), chi_abs[c],
+                    chi_es[c], o, &W.rec, w);
     store_out(o, c, C.Ntot, P, U, iters, status, err);
   }
 }
@@ -1005,6 +1111,14 @@ __global__ void LB(64) k_implicit_batch_list(Ctx C, long n, const double* __rest
     }
     CellOut o;
     const Opts op = make_opts(C);
+    if (C.cascade) {
+      // the full cascade from scratch, the cold limit inline; a cell without
+      // a grid takes the entropy of its prior primitives
+      implicit_cell_full(m, make_phys(C), op, Ui, entropy_cons(C.gam, m, Pg), Pg, dtc[c],
+                         chi_abs[c], chi_es[c], o);
+      store_out(o, c, n, Po, Uo, iters, status, err);
+      continue;
+    }
     implicit_cell(m, make_phys(C), op, Ui, Pg, dtc[c], chi_abs[c], chi_es[c], o, &W.rec, w, false);
     store_out(o, c, n, Po, Uo, iters, status, err);
     bool cold = false;
@@ -1047,6 +1161,37 @@ __global__ void LB(64) k_cold_batch_list(Ctx C, long n, const double* __restrict
       store_out(o, c, n, Po, Uo, iters, status, err);
     else if (iters)
       iters[c] = it;
+  }
+}
+
+// The full cascade's rest (params.cascade = 1) for batch cells the PMHD and
+// URAD attempts left unaccepted: K lists their record slots; each resumes
+// after both attempts (one thread per cell).
+__global__ void LB(64) k_rest_batch_list(Ctx C, long n, const double* __restrict__ Ui_,
+                                         const double* __restrict__ Pg_,
+                                         const double* __restrict__ dtc,
+                                         const double* __restrict__ chi_abs,
+                                         const double* __restrict__ chi_es,
+                                         double* __restrict__ Po, double* __restrict__ Uo,
+                                         int* __restrict__ iters, int* __restrict__ status,
+                                         double* __restrict__ err, Work W, Work K) {
+  const int cnt = *K.counter;
+  for (long w = (long)blockIdx.x * blockDim.x + threadIdx.x; w < cnt;
+       w += (long)gridDim.x * blockDim.x) {
+    const long slot = K.list[w];
+    const long c = W.list[slot];
+    Metric m;
+    flat_metric(m);
+    double Ui[12], Pg[12];
+#pragma unroll
+    for (int q = 0; q < 12; q++) {
+      Ui[q] = Ui_[q * n + c];
+      Pg[q] = Pg_[q * n + c];
+    }
+    CellOut o;
+    implicit_cell_full(m, make_phys(C), make_opts(C), Ui, entropy_cons(C.gam, m, Pg), Pg, dtc[c],
+                       chi_abs[c], chi_es[c], o, &W.rec, slot, 2);
+    store_out(o, c, n, Po, Uo, iters, status, err);
   }
 }
 
@@ -1150,10 +1295,22 @@ __global__ void LB(64) k_cascade_urad(Ctx C, long n, const double* __restrict__ 
       if (bm < 0) failed_out(Ui, Pg, pst, L.iters, out);
       else finalize(c, ph, o, best, bm, pst, L.iters, Ui, out);
       store_out(out, item, n, Po, Uo, iters, status, err);
-      failed = (out.status & GRRMHD_ST_FAIL) && o.cold && cold_allowed(c, Pg);
+      if (C.cascade) {
+        // not accepted: the rest of the full cascade resumes from the better of
+        // the PMHD and URAD attempts, kept in the cell's record (method in ok)
+        failed = !(bm >= 0 && best.eT < accept_threshold(o));
+        if (failed) {
+          Best kb = best;
+          kb.ok = (bm >= 0 ? 1 : 0) | ((bm >= 0 ? bm : 0) << 1);
+          rec_store(W.rec, slot, kb, L.iters);
+        }
+      } else {
+        failed = (out.status & GRRMHD_ST_FAIL) && o.cold && cold_allowed(c, Pg);
+      }
       active = false;
     }
-    wave_append(failed, (int)item, K.counter, K.list);   // to the cold limit
+    // to the cold limit; with the full cascade, the record slot to its rest
+    wave_append(failed, C.cascade ? (int)slot : (int)item, K.counter, K.list);
     if (!__any(active) && __all(exhausted)) break;
   }
   if ((threadIdx.x & 63) == 0 && useful) {

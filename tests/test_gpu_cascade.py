@@ -1,0 +1,217 @@
+"""The full implicit cascade (params.cascade = 1; Sec. 4.10-4.11) on the GPU
+against the oracle: PRAD, the staged attempts and the entropy methods.
+
+Where several methods reach round-off the method that produced a solution is
+not unique (R16), so the tests compare the kind of solution (energy,
+entropy, cold, none), the solution itself where both sides have the same
+kind, and check every GPU solution against its own equations written out
+independently for flat space.  Tolerances as test_gpu_parity's batch test.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1312_6127_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from test_gpu_parity import CASES, dev, field_err, host, interior_mask  # noqa: E402
+from test_oracle_cascade import _entropy_residual  # noqa: E402
+from test_oracle_pins import _mink_momentum_residual, _mink_residual  # noqa: E402
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def G():
+    from paper_1312_6127_amd import grrmhd
+
+    grrmhd.lib()
+    assert torch.cuda.is_available()
+    return grrmhd
+
+
+FULL = dict(cascade=1)
+
+
+def _batch(orc, n, seed):
+    pd, P, dt, ca, ce = I.implicit_batch(n, seed=seed)
+    g0 = orc.geom(pd, 0.0, 0.0)
+    U = np.stack([orc.p2u(pd, g0, P[:, c]) for c in range(n)], axis=1)
+    Ui = U.copy()
+    Ui[8] *= 1.3
+    Ui[1] -= 0.3 * U[8]
+    return dict(pd, **FULL), P, dt, ca, ce, Ui
+
+
+def _kind(orc, st):
+    """0 energy, 1 entropy, 2 cold, 3 none"""
+    return np.where((st & orc.ST_FAIL) != 0, 3, np.where((st & orc.ST_COLD) != 0, 2,
+                    np.where((st & orc.ST_ENTROPY) != 0, 1, 0)))
+
+
+def _check_solutions(orc, pd, P, Ui, dt, ca, ce, Pg, stg, errg):
+    """Every GPU solution against its own equations (limited radiation
+    excepted); returns the number checked and the worst ratio to 10 e_T +
+    tol_accept."""
+    worst, n = 0.0, 0
+    for c in range(P.shape[1]):
+        s = int(stg[c])
+        if s & (orc.ST_FAIL | orc.ST_TYPE2_NEG | orc.ST_BASIC):
+            continue
+        if np.sqrt(1.0 + Pg[9:12, c] @ Pg[9:12, c]) > 0.9 * pd["gamma_max"]:
+            continue
+        ka, ke = ca[c] * Pg[0, c], ce[c] * Pg[0, c]
+        if s & orc.ST_COLD:
+            r = _mink_momentum_residual(pd, Pg[:, c], Ui[:, c], dt[c], ka, ke)
+        elif s & orc.ST_ENTROPY:
+            Si = orc.entropy(pd, P[:, c]) * np.sqrt(1.0 + P[2:5, c] @ P[2:5, c])
+            r = max(_entropy_residual(pd, Pg[:, c], Ui[:, c], Si, dt[c], ka, ke),
+                    _mink_momentum_residual(pd, Pg[:, c], Ui[:, c], dt[c], ka, ke))
+        else:
+            r = max(_mink_residual(pd, Pg[:, c], Ui[:, c], dt[c], ka, ke))
+        worst = max(worst, r / (10.0 * errg[c] + pd["tol_accept"]))
+        n += 1
+    return n, worst
+
+
+def test_batch_full_cascade(G, orc):
+    say("case batch, full cascade")
+    n = 3001
+    pd, P, dt, ca, ce, Ui = _batch(orc, n, 4)
+    args = [dev(Ui), dev(P), dev(dt), dev(ca), dev(ce)]
+    Pg, Ug, itg, stg, errg = (host(x) for x in G.implicit_source(pd, *args))
+    Pr, Ur, itr, str_ = orc.implicit_batch(pd, Ui, P, dt, ca, ce)
+    st0 = host(G.implicit_source(dict(pd, cascade=0), *args)[3])
+    kg, kr = _kind(orc, stg), _kind(orc, str_)
+    say("  GPU kinds", np.bincount(kg, minlength=4), "oracle", np.bincount(kr, minlength=4),
+        "GPU failed with cascade 0:", int(((st0 & G.ST_FAIL) != 0).sum()))
+    for b, nm in ((G.ST_PRAD, "PRAD"), (G.ST_STAGED, "staged"), (G.ST_ENTROPY, "entropy")):
+        say(f"  {nm}: GPU {int(((stg & b) != 0).sum())} oracle {int(((str_ & b) != 0).sum())}")
+    agree = kg == kr
+    assert agree.mean() > 0.97
+    assert (kg == 3).sum() <= 0.25 * ((st0 & G.ST_FAIL) != 0).sum()
+    nchk, worst = _check_solutions(orc, pd, P, Ui, dt, ca, ce, Pg, stg, errg)
+    say(f"  GPU solutions checked {nchk}, worst residual / (10 e_T + tol_accept) {worst:.2e}")
+    assert nchk > 0.9 * n and worst <= 1.0
+    both = agree & (kg < 3) & (errg < 1e-11)
+    scale = np.abs(Ur[1]) + np.abs(Ur[8]) + np.abs(Ur[2:5]).sum(0) + np.abs(Ur[9:12]).sum(0)
+    d = np.abs(Ug - Ur)[1:12, both].max(axis=0) / scale[both]
+    say(f"  compared {both.sum()}: max |dU|/cell scale {d.max():.2e}")
+    assert both.sum() > 0.6 * n and np.quantile(d, 0.99) < 1e-12 and d.max() < 1e-9
+
+
+FORMS = {"per_iteration": (1, 64, 0), "persistent256": (2, 256, 16)}
+
+
+@pytest.mark.parametrize("form", sorted(FORMS))
+def test_batch_full_cascade_forms_identical(G, orc, form):
+    say("case batch full cascade, form", form)
+    n = 5003
+    pd, P, dt, ca, ce, Ui = _batch(orc, n, 6)
+    args = [dev(Ui), dev(P), dev(dt), dev(ca), dev(ce)]
+    ws0 = G.batch_workspace(n, G.PER_CELL)
+    ref = [host(x) for x in G.implicit_source_ex(pd, *args, G.PER_CELL, 64, 1, ws=ws0)]
+    mode, block, wpc = FORMS[form]
+    ws = G.batch_workspace(n, mode)
+    got = [host(x) for x in G.implicit_source_ex(pd, *args, mode, block, wpc, ws=ws)]
+    for a, b in zip(got, ref):
+        assert np.array_equal(a.view(np.uint8), b.view(np.uint8))
+
+
+def _batch_box(orc, n=256, seed=31):
+    """A periodic 1-D box of batch-recipe cells (flows slowed tenfold,
+    opacities raised a thousandfold): far-from-equilibrium neighbours whose
+    step needs the entropy, staged and PRAD attempts."""
+    pdb, Pb, dtb, cab, ceb = I.implicit_batch(n, seed=seed)
+    pd = I.default_params(n=(n, 1, 1), arad=1.0, tol_pmhd=1e-10, courant=0.4, **FULL)
+    N = I.ncell(pd)
+    g = pd["ng"]
+    P = np.zeros((12, N))
+    P[:, g:g + n] = Pb
+    P[2:5] *= 0.1
+    P[9:12] = P[2:5]
+    ca, ce = np.zeros(N), np.zeros(N)
+    ca[g:g + n], ce[g:g + n] = cab * 1e3, ceb * 1e3
+    P = orc.bc(pd, P)
+    for a in (ca, ce):
+        a[:g], a[-g:] = a[n:n + g], a[g:2 * g]
+    return pd, P, ca, ce
+
+
+def test_step_full_cascade_batch_box(G, orc):
+    """One step of the box: the explicit entropy tracer (face fluxes and
+    stage combination) and the whole cascade on the grid path.  Neighbours
+    far from equilibrium put many cells near the edge of a root's existence,
+    where the two sides may take different methods at some stage and the
+    difference spreads three cells per stage; cells whose neighbourhood of
+    six cells each side has the same final status on both sides, and none
+    failed, limited, extreme or unaccepted, agree per cell to the box's
+    Newton tolerance (1e-10) of the cell's energy scale.  Every GPU cell
+    stays physical."""
+    say("case step, full cascade, batch box")
+    pd, P, ca, ce = _batch_box(orc)
+    U = orc.prim_to_cons(pd, P)
+    P1, U1, dt, st, it, nbad = orc.step(pd, P, U, ca, ce)
+    gr = G.Grid(pd)
+    Pt, Ut = dev(P), dev(U)
+    dtt = torch.zeros(1, dtype=torch.float64, device="cuda")
+    stt = torch.zeros(gr.N, dtype=torch.int32, device="cuda")
+    gr.step(Pt, Ut, dev(ca), dev(ce), dtt, status=stt)
+    stg, Pg, Ug = host(stt), host(Pt), host(Ut)
+    gr.close()
+    m = interior_mask(pd)
+    assert abs(host(dtt)[0] / dt - 1) < 1e-14
+    for b, nm in ((G.ST_PRAD, "PRAD"), (G.ST_STAGED, "staged"), (G.ST_ENTROPY, "entropy"),
+                  (G.ST_FAIL, "failed")):
+        say(f"  {nm}: GPU {int(((stg[m] & b) != 0).sum())} oracle {int(((st[m] & b) != 0).sum())}")
+    assert ((st[m] & G.ST_ENTROPY) != 0).sum() > 0 and ((stg[m] & G.ST_ENTROPY) != 0).sum() > 0
+    assert np.all(np.isfinite(Pg[:, m])) and np.all(Pg[0, m] > 0) and np.all(Pg[1, m] > 0)
+    odd = orc.ST_FAIL | orc.ST_TYPE2_NEG | orc.ST_BASIC | orc.ST_EXTREME | orc.ST_NOT_ACCEPT
+    bad = (stg != st) | ((st & odd) != 0)
+    ok = m.copy()
+    for s in range(-6, 7):
+        ok &= ~np.roll(bad, s)
+    scale = np.abs(U1[1]) + np.abs(U1[8]) + np.abs(U1[2:5]).sum(0) + np.abs(U1[9:12]).sum(0)
+    d = np.abs(Ug - U1)[1:12, ok].max(0) / scale[ok]
+    dD = np.abs(Ug[0, ok] / U1[0, ok] - 1)
+    say(f"  cells compared {ok.sum()} of {m.sum()}: max |dU|/cell scale {d.max():.2e}, "
+        f"|dD|/D {dD.max():.2e}")
+    assert ok.sum() > 60 and d.max() < 1e-10 and dD.max() < 1e-12
+
+
+@pytest.mark.parametrize("case", ["tube1d", "disk3d"])
+def test_step_full_cascade_matches_oracle(G, orc, case):
+    """Where PMHD is accepted everywhere (the disks, the shock tube) the full
+    cascade's step is the usual one: GPU against the oracle's full-cascade
+    step at the one-step tolerance."""
+    say("case", case, "step, full cascade")
+    pd, P, ca, ce = CASES[case]()
+    pd = dict(pd, **FULL)
+    U = orc.prim_to_cons(pd, P)
+    P1, U1, dt, st, it, nbad = orc.step(pd, P, U, ca, ce)
+    gr = G.Grid(pd)
+    Pt, Ut = dev(P), dev(U)
+    dtt = torch.zeros(1, dtype=torch.float64, device="cuda")
+    gr.step(Pt, Ut, dev(ca), dev(ce), dtt)
+    m = interior_mask(pd)
+    eP = field_err(host(Pt), P1, m)
+    eU = field_err(host(Ut), U1, m)
+    gr.close()
+    say("  field errors P", eP.max(), "U", eU.max())
+    assert eP.max() < 1e-12 and eU.max() < 1e-12
+
+
+def test_adjoint_rejects_full_cascade(G):
+    pd, P, ca, ce = CASES["disk3d"]()
+    gr = G.Grid(dict(pd, **FULL))
+    dtt = torch.full((1,), 1e-3, dtype=torch.float64, device="cuda")
+    with pytest.raises(RuntimeError, match="cascade"):
+        gr.step_adjoint(dev(P), dev(ca), dev(ce), dtt, dev(np.ones_like(P)))
+    gr.close()
