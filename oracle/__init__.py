@@ -14,7 +14,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "liboracle.so")
-SOURCES = ["geom.c", "phys.c", "invert.c", "implicit.c", "step.c"]
+SOURCES = ["geom.c", "phys.c", "invert.c", "implicit.c", "step.c", "stag.c"]
 
 ST_PMHD, ST_URAD, ST_TYPE2_NEG, ST_BASIC, ST_C2P_FAIL, ST_FLOOR, ST_NOT_ACCEPT, ST_FAIL, \
     ST_NO_GOOD_NB, ST_EXTREME, ST_COLD, ST_PRAD, ST_ENTROPY, ST_STAGED = (1 << i for i in range(14))
@@ -51,6 +51,7 @@ class Params(C.Structure):
         ("rho_floor", C.c_double), ("u_floor", C.c_double), ("bsq_rho_max", C.c_double),
         ("bsq_u_max", C.c_double), ("u_rho_max", C.c_double), ("erad_floor", C.c_double),
         ("scheme", C.c_int), ("recon", C.c_int), ("cold", C.c_int), ("cascade", C.c_int),
+        ("ct", C.c_int),
     ]
 
 
@@ -85,6 +86,7 @@ def params(d: dict) -> Params:
     p.recon = 1 if d.get("recon", "mc") == "ppm" else 0
     p.cold = int(d.get("cold", 1))
     p.cascade = int(d.get("cascade", 0))
+    p.ct = 1 if d.get("ct", "flux") == "staggered" else 0
     return p
 
 
@@ -138,6 +140,12 @@ def lib():
             "orc_implicit_grid": (None, [PP, _D, _D, C.c_double, _D, _D, _D, _D, _I, _I]),
             "orc_fixup": (None, [PP, _D, _D, _I]),
             "orc_step": (C.c_int, [PP, _D, _D, _D, _D, _D, C.c_int, _I, _I]),
+            "orc_bc_face": (None, [PP, _D]),
+            "orc_face_to_center": (None, [PP, _D, _D, _D]),
+            "orc_fluxes_stag": (None, [PP, _D, _D, _D, _D, _D, _D, _D, _D, _D]),
+            "orc_face_update": (None, [PP, C.c_double, C.c_double, C.c_double, C.c_double,
+                                       _D, _D, _D, _D]),
+            "orc_step_stag": (C.c_int, [PP, _D, _D, _D, _D, _D, _D, C.c_int, _I, _I]),
         }
         for name, (res, args) in sigs.items():
             f = getattr(L, name)
@@ -356,6 +364,63 @@ def fluxes_s(pd, P, chi_abs, chi_es):
     lib().orc_fluxes_s(C.byref(params(pd)), _dp(P), _dp(ca), _dp(ce), None, _dp(F), _dp(emf),
                        _dp(vch), _dp(Fs))
     return F, emf, vch, Fs
+
+
+# ---------------------------------------------------------------------------
+# staggered face field: Bf [3][N], sqrt(-g) B^(p+1) on the lower p-face of each
+# cell (pd["ct"] = "staggered")
+# ---------------------------------------------------------------------------
+
+def bc_face(pd, Bf):
+    Bf = _f64(Bf).copy()
+    lib().orc_bc_face(C.byref(params(pd)), _dp(Bf))
+    return Bf
+
+
+def face_to_center(pd, Bf, P, U):
+    """P, U with the interior cells' field slots set from the faces."""
+    P, U = _f64(P).copy(), _f64(U).copy()
+    lib().orc_face_to_center(C.byref(params(pd)), _dp(_f64(Bf)), _dp(P), _dp(U))
+    return P, U
+
+
+def fluxes_stag(pd, P, Bf, chi_abs, chi_es):
+    """Face fluxes, the four-state corner EMFs and the face speeds of P with
+    the face field Bf (the PPM flattener of P alone, as at a step's start)."""
+    P, Bf, ca, ce = _f64(P), _f64(Bf), _f64(chi_abs), _f64(chi_es)
+    N = P.shape[1]
+    F = np.zeros((3, 12, N))
+    emf = np.zeros((3, N))
+    vch = np.zeros((3, N))
+    fl = None
+    if pd.get("recon", "mc") == "ppm":
+        fl = np.zeros((6, N))
+        lib().orc_flattener(C.byref(params(pd)), _dp(P), _dp(ca), _dp(ce), _dp(fl), 0)
+    lib().orc_fluxes_stag(C.byref(params(pd)), _dp(P), _dp(Bf), _dp(ca), _dp(ce),
+                          _dp(fl) if fl is not None else None, _dp(F), _dp(emf), _dp(vch), None)
+    return F, emf, vch
+
+
+def face_update(pd, a, b, c, dt, Bn, Bprev, emf, Bout=None):
+    Bout = np.zeros_like(_f64(Bn)) if Bout is None else _f64(Bout).copy()
+    lib().orc_face_update(C.byref(params(pd)), a, b, c, dt, _dp(_f64(Bn)), _dp(_f64(Bprev)),
+                          _dp(_f64(emf)), _dp(Bout))
+    return Bout
+
+
+def step_stag(pd, P, U, Bf, chi_abs, chi_es, dt=0.0, dt_fixed=False):
+    """One step with the staggered field: (P, U, Bf, dt, status, iters, nbad)."""
+    P, U, Bf = _f64(P).copy(), _f64(U).copy(), _f64(Bf).copy()
+    ca, ce = _f64(chi_abs), _f64(chi_es)
+    n = P.shape[1]
+    dtv = np.array([dt], dtype=np.float64)
+    st = np.zeros(n, np.int32)
+    it = np.zeros(n, np.int32)
+    nbad = lib().orc_step_stag(C.byref(params(pd)), _dp(P), _dp(U), _dp(Bf), _dp(ca), _dp(ce),
+                               _dp(dtv), 1 if dt_fixed else 0, _ip(st), _ip(it))
+    if nbad < 0:
+        raise ValueError("staggered step needs ct='staggered' and the RK3 scheme")
+    return P, U, Bf, float(dtv[0]), st, it, nbad
 
 
 def flattener(pd, P, chi_abs, chi_es, prev=None):

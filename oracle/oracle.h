@@ -75,6 +75,8 @@ typedef struct {
                              Sec. 4.10-4.11: PMHD, URAD, PRAD, the staged
                              approach in the extreme regime, the entropy-based
                              methods, then cold                               */
+  int ct;                 /* 0: flux-CT on the cell-centred field; 1: the
+                             staggered face field with four-state corner EMFs */
 } orc_params;
 
 /* ---- geometry (Sec. 2; metric of the Kerr-Schild form) ---- */
@@ -177,6 +179,20 @@ void orc_implicit_grid_s(const orc_params *p, const double *Uexp, const double *
                          const double *chi_es, double *Pout, double *Uout, int *iters,
                          int *status);
 void orc_fixup(const orc_params *p, double *P, double *U, int *status);
+
+/* ---- staggered face-centred field (stag.c; layout there) ---- */
+void orc_bc_face(const orc_params *p, double *Bf);
+void orc_face_to_center(const orc_params *p, const double *Bf, double *P, double *U);
+void orc_emf_stag(const orc_params *p, const double *Bf, const double *VF, const double *SP,
+                  double *emf);
+void orc_face_update(const orc_params *p, double a, double b, double c, double dt,
+                     const double *Bn, const double *Bprev, const double *emf, double *Bout);
+/* fluxes and four-state corner EMFs of primitives P with face field Bf */
+void orc_fluxes_stag(const orc_params *p, const double *P, const double *Bf,
+                     const double *chi_abs, const double *chi_es, const double *fl, double *F,
+                     double *emf, double *vchar, double *Fs);
+int orc_step_stag(const orc_params *p, double *P, double *U, double *Bf, const double *chi_abs,
+                  const double *chi_es, double *dt, int dt_fixed, int *status, int *iters);
 /* one full step of the scheme p->scheme; dt in/out (computed from P^n
  * unless dt_fixed) */
 int orc_step(const orc_params *p, double *P, double *U, const double *chi_abs, const double *chi_es,

@@ -252,9 +252,13 @@ static void entropy_cons_flux(const orc_params *p, const orc_geom *g, const doub
   if (Fs) *Fs = g->gdet * S * ucon[dir];
 }
 
-void orc_fluxes_s(const orc_params *p, const double *P, const double *chi_abs,
-                  const double *chi_es, const double *fl, double *F, double *emf, double *vchar,
-                  double *Fs) {
+/* Bf (staggered field, else NULL): the normal field of both face states is
+ * the face's own, the faces extend two cells beyond the interior across
+ * their direction, VF and SP receive the face velocities and gas speeds
+ * (layout in orc_emf_stag) and the flux-CT EMFs are left to the caller. */
+static void fluxes_core(const orc_params *p, const double *P, const double *chi_abs,
+                        const double *chi_es, const double *fl, double *F, double *emf,
+                        double *vchar, double *Fs, const double *Bf, double *VF, double *SP) {
   const long N = orc_ncell_alloc(p);
   memset(F, 0, sizeof(double) * 3 * 12 * N);
   if (Fs) memset(Fs, 0, sizeof(double) * 3 * N);
@@ -266,8 +270,9 @@ void orc_fluxes_s(const orc_params *p, const double *P, const double *chi_abs,
     int lo[3], hi[3];
     for (int e = 0; e < 3; e++) {
       const int ng = orc_ng(p, e);
+      const int ext = Bf ? 2 : 1;
       if (e == d) { lo[e] = ng; hi[e] = ng + p->n[e]; }
-      else if (p->n[e] > 1) { lo[e] = ng - 1; hi[e] = ng + p->n[e]; }
+      else if (p->n[e] > 1) { lo[e] = ng - ext; hi[e] = ng + p->n[e] + ext - 1; }
       else { lo[e] = 0; hi[e] = 0; }
     }
     long st = 1;
@@ -303,6 +308,11 @@ void orc_fluxes_s(const orc_params *p, const double *P, const double *chi_abs,
           orc_face_x(p, d + 1, i, j, &x1, &x2);
           orc_geom g;
           orc_geom_point(p, x1, x2, &g);
+          if (Bf) {
+            /* the face's own normal field (zero where sqrt(-g) vanishes) */
+            const double bn = g.gdet > 0.0 ? Bf[(long)d * N + c] / g.gdet : 0.0;
+            PL[5 + d] = PR[5 + d] = bn;
+          }
           const double sdx = sqrt(g.gcov[d + 1][d + 1]) * dxd;
           double UL[12], UR[12], FL[12], FR[12], vgL[2], vrL[2], vgR[2], vrR[2];
           orc_p2u(p, &g, PL, UL);
@@ -330,6 +340,16 @@ void orc_fluxes_s(const orc_params *p, const double *P, const double *chi_abs,
           }
           Fd[(5 + d) * N + c] = 0.0; /* induction flux of the normal component vanishes */
           vchar[(long)d * N + c] = fmax(fmax(gmin, gmax), fmax(rmin, rmax));
+          if (Bf) {
+            for (int sd = 0; sd < 2; sd++) {
+              double ucon[4];
+              orc_ucon(&g, (sd ? PR : PL) + 2, ucon);
+              for (int m = 0; m < 3; m++)
+                VF[((long)((2 * d + sd) * 3) + m) * N + c] = ucon[m + 1] / ucon[0];
+            }
+            SP[(long)(2 * d) * N + c] = gmin;
+            SP[(long)(2 * d + 1) * N + c] = gmax;
+          }
           if (Fs) {
             /* the entropy tracer's flux, with the gas speeds */
             double UsL, UsR, FsL, FsR, f;
@@ -347,6 +367,7 @@ void orc_fluxes_s(const orc_params *p, const double *P, const double *chi_abs,
           }
         }
   }
+  if (Bf) return;
   /* flux-CT corner EMFs: emf_a = F_c[B_b] = -F_b[B_c], (a, b, c) cyclic */
   for (int a = 0; a < 3; a++) {
     const int b = (a + 1) % 3, cdim = (a + 2) % 3;
@@ -377,6 +398,24 @@ void orc_fluxes_s(const orc_params *p, const double *P, const double *chi_abs,
           emf[(long)a * N + c] = e;
         }
   }
+}
+
+void orc_fluxes_s(const orc_params *p, const double *P, const double *chi_abs,
+                  const double *chi_es, const double *fl, double *F, double *emf, double *vchar,
+                  double *Fs) {
+  fluxes_core(p, P, chi_abs, chi_es, fl, F, emf, vchar, Fs, NULL, NULL, NULL);
+}
+
+void orc_fluxes_stag(const orc_params *p, const double *P, const double *Bf,
+                     const double *chi_abs, const double *chi_es, const double *fl, double *F,
+                     double *emf, double *vchar, double *Fs) {
+  const long N = orc_ncell_alloc(p);
+  double *VF = calloc(18 * N, sizeof(double));
+  double *SP = calloc(6 * N, sizeof(double));
+  fluxes_core(p, P, chi_abs, chi_es, fl, F, emf, vchar, Fs, Bf, VF, SP);
+  orc_emf_stag(p, Bf, VF, SP, emf);
+  free(VF);
+  free(SP);
 }
 
 double orc_timestep(const orc_params *p, const double *vchar) {
@@ -563,7 +602,12 @@ void orc_fixup(const orc_params *p, double *P, double *U, int *status) {
             }
             if (cnt > 0) {
               if (fail)
-                for (int q = 0; q < 12; q++) P[q * N + c] = acc[q] / cnt;
+                for (int q = 0; q < 12; q++) {
+                  /* a staggered field is not a primitive of the solve: the
+                   * cell keeps its face-centred B */
+                  if (p->ct && q >= 5 && q <= 7) continue;
+                  P[q * N + c] = acc[q] / cnt;
+                }
               else
                 P[1 * N + c] = acc[1] / cnt;
               changed = 1;
@@ -712,6 +756,16 @@ static void entropy_update(const orc_params *p, double a, double b, double c, do
  * implicit in its own new value with dt_k = g dt */
 int orc_step(const orc_params *p, double *P, double *U, const double *chi_abs, const double *chi_es,
              double *dt, int dt_fixed, int *status, int *iters) {
+  if (p->ct) return -1;
+  return orc_step_stag(p, P, U, NULL, chi_abs, chi_es, dt, dt_fixed, status, iters);
+}
+
+/* Bf (staggered field, p->ct = 1, RK3): the face field [3][N] in and out;
+ * each stage's faces are a Bf^n + b Bf^(k-1) + c dt (-curl EMF) and the
+ * stage's cell-centred conserved field their mean (Sec. 4.2 steps 8-10) */
+int orc_step_stag(const orc_params *p, double *P, double *U, double *Bf, const double *chi_abs,
+                  const double *chi_es, double *dt, int dt_fixed, int *status, int *iters) {
+  if ((Bf != NULL) != (p->ct != 0) || (Bf && p->scheme != ORC_RK3)) return -1;
   const orc_scheme S = scheme_table(p->scheme);
   const long N = orc_ncell_alloc(p);
   const size_t B12 = sizeof(double) * 12 * N;
@@ -743,6 +797,18 @@ int orc_step(const orc_params *p, double *P, double *U, const double *chi_abs, c
   /* PPM flattener of the step: the largest over its sub-steps so far */
   double *fl = (p->recon == ORC_RECON_PPM) ? calloc(6 * N, sizeof(double)) : NULL;
   int nflux = 0;
+  /* staggered field: Bf^n, each stage's faces, the current stage input */
+  const size_t B3 = sizeof(double) * 3 * N;
+  double *Bn = NULL, *Bst[5] = {NULL}, *Bk = NULL;
+  if (Bf) {
+    Bn = malloc(B3);
+    memcpy(Bn, Bf, B3);
+    for (int i = 0; i < S.ns; i++) {
+      Bst[i] = malloc(B3);
+      memcpy(Bst[i], Bf, B3);
+    }
+    Bk = Bn;
+  }
   /* the full cascade's entropy equation (RK3): the explicit entropy of each
    * stage, a U_S(P^n) + b U_S(P^(k-1)) + c dt (-div F_S), the tracer taken
    * from the primitives at every sub-step (Sec. 4.2 step 2: all U_q from P_q) */
@@ -754,7 +820,12 @@ int orc_step(const orc_params *p, double *P, double *U, const double *chi_abs, c
 #define STEP_FLUXES()                                              \
   do {                                                             \
     if (fl) orc_flattener(p, Pk, chi_abs, chi_es, fl, nflux > 0);  \
-    orc_fluxes_s(p, Pk, chi_abs, chi_es, fl, F, emf, vch, Fs);     \
+    if (Bk) {                                                      \
+      orc_bc_face(p, Bk);                                          \
+      orc_fluxes_stag(p, Pk, Bk, chi_abs, chi_es, fl, F, emf, vch, Fs); \
+    } else {                                                       \
+      orc_fluxes_s(p, Pk, chi_abs, chi_es, fl, F, emf, vch, Fs);   \
+    }                                                              \
     nflux++;                                                       \
   } while (0)
   if (!dt_fixed) {
@@ -774,6 +845,11 @@ int orc_step(const orc_params *p, double *P, double *U, const double *chi_abs, c
       }
       orc_explicit_update(p, s->a, s->b, s->c, *dt, Pk, Un, Uj, F, emf, Uexp);
       if (ent) entropy_update(p, s->a, s->b, s->c, *dt, Sn, Pk, Fs, Sexp);
+      if (Bf) {
+        orc_face_update(p, s->a, s->b, s->c, *dt, Bn, (s->j >= 0) ? Bst[s->j] : Bn, emf, Bst[i]);
+        orc_face_to_center(p, Bst[i], NULL, Uexp);
+        Bk = Bst[i];
+      }
     } else {
       for (long q = 0; q < 12 * N; q++) Uexp[q] = s->a * Un[q] + (s->b != 0.0 ? s->b * Uj[q] : 0.0);
     }
@@ -817,6 +893,11 @@ int orc_step(const orc_params *p, double *P, double *U, const double *chi_abs, c
   /* write back (ghost cells of P keep the last fill) */
   memcpy(P, Pk, B12);
   memcpy(U, Ust[S.ns - 1], B12);
+  if (Bf) {
+    memcpy(Bf, Bst[S.ns - 1], B3);
+    free(Bn);
+    for (int i = 0; i < S.ns; i++) free(Bst[i]);
+  }
   for (long c = 0; c < N; c++)
     if (stacc[c] & ORC_ST_FAIL) nbad++;
   for (int i = 0; i < S.ns; i++) {

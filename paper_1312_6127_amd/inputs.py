@@ -57,6 +57,7 @@ def default_params(**kw) -> dict:
         max_iter=20, roundoff=1,
         rho_floor=1e-20, u_floor=1e-22, bsq_rho_max=200.0, bsq_u_max=1e5,
         u_rho_max=1e10, erad_floor=1e-150, scheme="rk3", recon="mc", cold=1, cascade=0,
+        ct="flux",
     )
     p.update(kw)
     return p
@@ -143,7 +144,7 @@ def _ks_sqrtg(a, r, th):
 
 
 def accretion_disk(n=(128, 64, 1), seed=2, a=0.9375, rin=1.2, rout=40.0, flux="llf",
-                   perturb3d=None, **kw):
+                   perturb3d=None, faces=False, **kw):
     """Synthetic accretion-shaped state on a log-r Kerr-Schild grid.
 
     rho0 = (r/r_in)^-1.5, p = 0.1 rho0/r, radial inflow u~^1 = -sqrt(2/r)/r
@@ -155,7 +156,9 @@ def accretion_disk(n=(128, 64, 1), seed=2, a=0.9375, rin=1.2, rout=40.0, flux="l
     log-uniform in x1 from 1e4 (inner edge) to 1e-3 (outer edge), chi_es = 0.
     With perturb3d: rho0 x (1 + 0.04 (U - 1/2)) and each u~^i += 0.02
     sqrt(2/r) (2U - 1) in orthonormal-magnitude units.  kw: further
-    parameters (e.g. ng=4, recon="ppm")."""
+    parameters (e.g. ng=4, recon="ppm").  faces: also return the face field
+    Bf [3][N] of the same potential (face_field_from_potential with A_3 at
+    the corners, scaled alike) for a staggered-field grid."""
     if perturb3d is None:
         perturb3d = n[2] > 1
     p = disk_params(n=n, a=a, rin=rin, rout=rout, flux=flux, **kw)
@@ -219,7 +222,50 @@ def accretion_disk(n=(128, 64, 1), seed=2, a=0.9375, rin=1.2, rout=40.0, flux="l
     tau = 10.0 ** (4.0 - 7.0 * frac)
     chi_abs = tau / (rho * r * dx1)
     chi_es = np.zeros_like(chi_abs)
-    return p, P.reshape(NPRIM, N), chi_abs.reshape(N), chi_es.reshape(N)
+    out = (p, P.reshape(NPRIM, N), chi_abs.reshape(N), chi_es.reshape(N))
+    if not faces:
+        return out
+    A = np.zeros((3,) + x1.shape)
+    A[2] = norm * Aphi[None, :-1, :-1]
+    return out + (face_field_from_potential(p, A),)
+
+
+def face_field_from_potential(p: dict, A: np.ndarray) -> np.ndarray:
+    """Face field Bf [3][N] (sqrt(-g) B^(d+1) on the lower d-face of each
+    cell) as the discrete curl of an edge potential A [3][N] (A_e on the
+    cell's edge along e, at its lower corner in the other two directions):
+    Bf^p = d_q A_e - d_e A_q for cyclic (p, q, e), differences along
+    inactive dimensions taken as zero.  Its discrete divergence vanishes up
+    to rounding; the last layer along each axis (no upper neighbour) is left
+    zero for the ghost fill."""
+    na = nalloc(p)
+    shape = (na[2], na[1], na[0])
+    A = np.asarray(A, dtype=np.float64).reshape((3,) + shape)
+    dx = [(p["xhi"][d] - p["xlo"][d]) / p["n"][d] for d in range(3)]
+    ax = {0: 2, 1: 1, 2: 0}   # dimension -> numpy axis of [N3, N2, N1]
+
+    def diff(f, d):
+        out = np.zeros_like(f)
+        if p["n"][d] == 1:
+            return out
+        sl_hi = [slice(None)] * 3
+        sl_lo = [slice(None)] * 3
+        sl_hi[ax[d]] = slice(1, None)
+        sl_lo[ax[d]] = slice(None, -1)
+        out[tuple(sl_lo)] = (f[tuple(sl_hi)] - f[tuple(sl_lo)]) / dx[d]
+        return out
+
+    Bf = np.zeros((3,) + shape)
+    for pp in range(3):
+        q, e = (pp + 1) % 3, (pp + 2) % 3
+        Bf[pp] = diff(A[e], q) - diff(A[q], e)
+        # the outermost layer along any active axis lacks a neighbour
+        for d in range(3):
+            if p["n"][d] > 1:
+                sl = [slice(None)] * 3
+                sl[ax[d]] = slice(-1, None)
+                Bf[pp][tuple(sl)] = 0.0
+    return Bf.reshape(3, -1)
 
 
 def implicit_batch(n: int, seed: int = 4, arad: float = 1.0, ugas_scale: float = 1.0):
