@@ -52,6 +52,7 @@ enum { GRRMHD_FLUX_LLF = 0, GRRMHD_FLUX_HLL = 1 };
 enum { GRRMHD_FP64 = 0, GRRMHD_MIXED = 1 };
 enum { GRRMHD_RK3 = 0, GRRMHD_IMEX2 = 1, GRRMHD_IMEX2B = 2, GRRMHD_IMEX3 = 3 };
 enum { GRRMHD_RECON_MC = 0, GRRMHD_RECON_PPM = 1 };
+enum { GRRMHD_CT_FLUX = 0, GRRMHD_CT_STAGGERED = 1 };
 enum { GRRMHD_EINVAL = -1, GRRMHD_EHIP = -2, GRRMHD_ENOMEM = -3 };
 
 /* per-cell status bits written by the implicit solve and the fix-ups */
@@ -145,6 +146,13 @@ typedef struct {
                            explicit state, which grrmhd_step forms for RK3;
                            the batched solve takes each cell's from its guess
                            primitives.                                       */
+  int ct;               /* constrained transport of the field (Sec. 4, Sec.
+                           4.2 steps 8-11): GRRMHD_CT_FLUX (default): flux-CT
+                           on the cell-centred field, stepped by grrmhd_step;
+                           GRRMHD_CT_STAGGERED: the face-centred field with
+                           four-state corner EMFs (Del Zanna et al. 2007),
+                           stepped by grrmhd_step_staggered (RK3 only; the
+                           adjoint is not available).                       */
 } grrmhd_params;
 
 typedef struct grrmhd_grid grrmhd_grid;
@@ -251,6 +259,54 @@ int grrmhd_fixup(grrmhd_grid *g, double *P, double *U, int *status, double *scra
 int grrmhd_step(grrmhd_grid *g, double *P, double *U, const double *chi_abs,
                 const double *chi_es, double *dt_dev, int dt_fixed, int *status, int *iters,
                 void *workspace, size_t ws_bytes);
+
+/* ---- staggered face-centred field (params.ct = GRRMHD_CT_STAGGERED) ----
+ * Bf [3][N] device array: sqrt(-g) B^(p+1) on the lower p-face of each cell
+ * (the cell itself along an inactive dimension p); the evolved faces are
+ * [ng, ng+n] along p ([ng, ng+n) when x_p is periodic) and the interior
+ * range across it; the rest are ghost faces.  Edge e of a cell lies at its
+ * lower corner in p = e+1 and q = e+2 (mod 3), and its EMF is
+ * F^q[B^p] = sqrt(-g)(B^p v^q - B^q v^p) (Sec. 4 list of fluxes).  All
+ * calls are asynchronous on the grid's stream; EINVAL on a flux-CT grid or
+ * for NULL arrays. */
+
+/* Ghost faces of Bf (Sec. 4.2 step 1): across a dimension the cell rule;
+ * along the face's own direction outflow copies the boundary face, periodic
+ * wraps, REFLECT and POLAR mirror about the boundary face with B^p negated
+ * (POLAR: phi shifted by pi); the primitive B is carried (sqrt(-g) of the
+ * ghost face applied). */
+int grrmhd_apply_bc_faces(grrmhd_grid *g, double *Bf);
+
+/* Sec. 4.2 step 8: at interior cells U[5+p] = the mean of sqrt(-g) B^p on
+ * the cell's two p-faces and P[5+p] = U[5+p]/sqrt(-g) at the centre; other
+ * entries untouched.  P or U may be NULL. */
+int grrmhd_face_to_center(grrmhd_grid *g, const double *Bf, double *P, double *U);
+
+/* Sub-steps 4-9 with the staggered field: the face fluxes F [3][12][N] and
+ * speeds vchar [3][N] as grrmhd_fluxes with each face's own normal field in
+ * both states (zero where sqrt(-g) vanishes), and the corner EMFs emf [3][N]
+ * from the four-state HLL/LAXF solution (Del Zanna et al. 2007): sqrt(-g) B^p
+ * interpolated along q and sqrt(-g) B^q along p from the faces, the face
+ * velocity states of each active in-plane direction interpolated along the
+ * other (MC slopes) and averaged, the gas speeds the mean of the two faces
+ * adjacent to the edge (Sec. 4.4); zero on the polar axis.  P's ghost cells
+ * and Bf's ghost faces must be filled.  workspace: as grrmhd_step's
+ * (grrmhd_workspace_bytes(), 256-byte aligned). */
+int grrmhd_fluxes_staggered(grrmhd_grid *g, const double *P, const double *Bf,
+                            const double *chi_abs, const double *chi_es, double *F, double *emf,
+                            double *vchar, void *workspace, size_t ws_bytes);
+
+/* One RK3 step (as grrmhd_step) with the staggered field: each stage's faces
+ * are a Bf^n + b Bf^(k-1) + c dt (-circulation of the corner EMFs round the
+ * face), so the discrete divergence of Bf never changes, and the stage's
+ * cell-centred conserved field is the mean of the new faces; a failed cell's
+ * neighbour average keeps its own field.  Bf in/out (evolved faces; ghost
+ * faces are filled in place at the start).  P, U, dt, status, iters and
+ * workspace as grrmhd_step. */
+int grrmhd_step_staggered(grrmhd_grid *g, double *P, double *U, double *Bf,
+                          const double *chi_abs, const double *chi_es, double *dt_dev,
+                          int dt_fixed, int *status, int *iters, void *workspace,
+                          size_t ws_bytes);
 
 /* Adjoint of one full step (grrmhd_step with dt_fixed): gP_n = dL/dP^n for
  * L = sum over interior cells and fields of gU_next * U^{n+1}(P^n), with

@@ -44,6 +44,7 @@ struct Ctx {
   int recon;           // GRRMHD_RECON_MC or GRRMHD_RECON_PPM
   int cold;            // cold MHD limit for cells with no energy solution
   int cascade;         // 1: the full method cascade (PRAD, staged, entropy)
+  int ct;              // 0: flux-CT on the cell-centred field; 1: staggered face field
   int mixed_i;         // FP32-mixed: cells with x1 index >= mixed_i take the FP32 face path
   double tol_pmhd, tol_urad, tol_accept, tol_fail;
   int max_iter, roundoff;

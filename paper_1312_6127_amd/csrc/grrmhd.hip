@@ -10,6 +10,7 @@
 #include <string>
 
 #include "adjoint.h"
+#include "stag.h"
 
 struct grrmhd_grid {
   grrmhd_params p;
@@ -96,6 +97,7 @@ extern "C" void grrmhd_default_params(grrmhd_params* p) {
   p->recon = GRRMHD_RECON_MC;
   p->cold = 1;
   p->cascade = 0;
+  p->ct = GRRMHD_CT_FLUX;
   p->r_fp64 = 2.0;
   p->tol_pmhd = 1e-12;
   p->tol_urad = 1e-9;
@@ -124,6 +126,10 @@ static int validate(const grrmhd_params* p, bool need_grid) {
   if (p->scheme < GRRMHD_RK3 || p->scheme > GRRMHD_IMEX3) return fail(GRRMHD_EINVAL, "bad scheme");
   if (p->cold != 0 && p->cold != 1) return fail(GRRMHD_EINVAL, "cold must be 0 or 1");
   if (p->cascade != 0 && p->cascade != 1) return fail(GRRMHD_EINVAL, "cascade must be 0 or 1");
+  if (p->ct != GRRMHD_CT_FLUX && p->ct != GRRMHD_CT_STAGGERED)
+    return fail(GRRMHD_EINVAL, "ct must be GRRMHD_CT_FLUX or GRRMHD_CT_STAGGERED");
+  if (p->ct == GRRMHD_CT_STAGGERED && p->scheme != GRRMHD_RK3)
+    return fail(GRRMHD_EINVAL, "the staggered field steps with RK3 only");
   if (p->recon != GRRMHD_RECON_MC && p->recon != GRRMHD_RECON_PPM)
     return fail(GRRMHD_EINVAL, "bad reconstruction");
   if (!need_grid) return 0;
@@ -176,6 +182,7 @@ static void fill_ctx(const grrmhd_params* p, Ctx& C) {
   C.recon = p->recon;
   C.cold = p->cold;
   C.cascade = p->cascade;
+  C.ct = p->ct;
   // FP32 face path from the first x1 index i whose cell i-1 has r >= r_fp64
   C.mixed_i = 1 << 30;
   if (p->precision == GRRMHD_MIXED) {
@@ -243,7 +250,17 @@ extern "C" int grrmhd_init_grid(const grrmhd_params* p, int device, void* hip_st
   g->W.counter_next = nullptr;
   g->W.stats = (unsigned long long*)(tail + 192);
   cascade_layout(tail + TAIL_CASCADE, nint, g->W);
-  if (flat_bytes) g->flat = (double*)(tail + TAIL_CASCADE + cascade_bytes(nint));
+  if (flat_bytes) {
+    // zero outside the flattener's range (cells within one of the interior):
+    // the staggered field's face states two cells out read it there
+    g->flat = (double*)(tail + TAIL_CASCADE + cascade_bytes(nint));
+    e = hipMemsetAsync(g->flat, 0, flat_bytes, g->stream);
+    if (e != hipSuccess) {
+      (void)hipFree(g->geo);
+      delete g;
+      return fail(GRRMHD_EHIP, std::string("flattener set-up: ") + hipGetErrorString(e));
+    }
+  }
   g->C.geo_c = g->geo;
   g->C.geo_f1 = g->geo + tab * GE_NCENTER;
   g->C.geo_f2 = g->geo + tab * (GE_NCENTER + GE_NFACE);
@@ -356,7 +373,7 @@ static Scheme make_scheme(int which) {
 }
 
 struct WsLayout {
-  size_t F, emf, vch, Uexp, Pa, Ua, err, st, it, Us, M, Fs, Sn, total;
+  size_t F, emf, vch, Uexp, Pa, Ua, err, st, it, Us, M, Fs, Sn, VF, SP, B1, B2, total;
 };
 
 // IMEX schemes add the stage U's (all but the last) and the kept M^k
@@ -390,6 +407,14 @@ static WsLayout ws_layout(const Ctx& C, int scheme = GRRMHD_RK3) {
     w.Fs = take(sizeof(double) * 3 * N);
     w.Sn = take(sizeof(double) * N);
   }
+  // the staggered field: face velocities and speeds, stage 1 and 2 faces
+  w.VF = w.SP = w.B1 = w.B2 = off;
+  if (C.ct) {
+    w.VF = take(sizeof(double) * 18 * N);
+    w.SP = take(sizeof(double) * 6 * N);
+    w.B1 = take(sizeof(double) * 3 * N);
+    w.B2 = take(sizeof(double) * 3 * N);
+  }
   w.total = off;
   return w;
 }
@@ -408,12 +433,14 @@ static int launch_bc(grrmhd_grid* g, double* P) {
   return 0;
 }
 
-static FaceRange face_range(const Ctx& C, int d) {
+// faces normal to d: n + 1 along d; across it one cell beyond the interior
+// (ext = 1), or two for the staggered field's corner interpolation (ext = 2)
+static FaceRange face_range(const Ctx& C, int d, int ext = 1) {
   FaceRange R;
   R.total = 1;
   for (int e = 0; e < 3; e++) {
     if (e == d) { R.lo[e] = C.ng[e]; R.cnt[e] = C.n[e] + 1; }
-    else if (C.n[e] > 1) { R.lo[e] = C.ng[e] - 1; R.cnt[e] = C.n[e] + 2; }
+    else if (C.n[e] > 1) { R.lo[e] = C.ng[e] - ext; R.cnt[e] = C.n[e] + 2 * ext; }
     else { R.lo[e] = 0; R.cnt[e] = 1; }
     R.total *= R.cnt[e];
   }
@@ -445,10 +472,14 @@ static void split_x1(const FaceRange& R, int i0, FaceRange& a, FaceRange& b) {
 // dtmin set: the Courant reduction over interior cells runs in the EMF launch.
 // PPM: the flattener of P first; keep_flat: the larger of it and the step's
 // earlier sub-steps' (0 at a step's first flux evaluation).
+// Bf (staggered field): the face states take the faces' normal field, write
+// their velocities and speeds to VF, SP, and the corner EMFs are the
+// four-state ones.
 static int launch_fluxes(grrmhd_grid* g, const double* P, const double* ca, const double* ce,
                          double* F, double* emf, double* vch,
                          unsigned long long* dtmin = nullptr, int keep_flat = 0,
-                         double* Fs = nullptr) {
+                         double* Fs = nullptr, const double* Bf = nullptr, double* VF = nullptr,
+                         double* SP = nullptr) {
   const Ctx& C = g->C;
   if (C.recon == GRRMHD_RECON_PPM) {
     long nb = 1;
@@ -464,7 +495,7 @@ static int launch_fluxes(grrmhd_grid* g, const double* P, const double* ca, cons
   for (int d = 0; d < 3; d++) {
     if (C.n[d] == 1) continue;
     FaceRange r64, r32;
-    split_x1(face_range(C, d), C.mixed_i, r64, r32);
+    split_x1(face_range(C, d, Bf ? 2 : 1), C.mixed_i, r64, r32);
     if (r64.total > 0) {
       S64.R[S64.n] = r64; S64.D[S64.n] = d + 1; S64.start[S64.n] = S64.total;
       S64.total += r64.total; S64.n++;
@@ -473,6 +504,45 @@ static int launch_fluxes(grrmhd_grid* g, const double* P, const double* ca, cons
       S32.R[S32.n] = r32; S32.D[S32.n] = d + 1; S32.start[S32.n] = S32.total;
       S32.total += r32.total; S32.n++;
     }
+  }
+  if (Bf) {
+    const double* flp = (const double*)g->flat;
+    if (S64.total > 0) {
+      if (Fs)
+        hipLaunchKernelGGL((k_flux_all_stag<double, true>), dim3(nblocks(S64.total, 128)), dim3(128),
+                           0, g->stream, C, S64, P, ca, ce, F, vch, flp, Fs, Bf, VF, SP);
+      else
+        hipLaunchKernelGGL((k_flux_all_stag<double, false>), dim3(nblocks(S64.total, 128)),
+                           dim3(128), 0, g->stream, C, S64, P, ca, ce, F, vch, flp, Fs, Bf, VF, SP);
+      LAUNCHCHK();
+    }
+    if (S32.total > 0) {
+      if (Fs)
+        hipLaunchKernelGGL((k_flux_all_stag<float, true>), dim3(nblocks(S32.total, 128)), dim3(128),
+                           0, g->stream, C, S32, P, ca, ce, F, vch, flp, Fs, Bf, VF, SP);
+      else
+        hipLaunchKernelGGL((k_flux_all_stag<float, false>), dim3(nblocks(S32.total, 128)),
+                           dim3(128), 0, g->stream, C, S32, P, ca, ce, F, vch, flp, Fs, Bf, VF, SP);
+      LAUNCHCHK();
+    }
+    // four-state corner EMFs at [ng, ng+n] on each active axis
+    FaceRange R;
+    R.total = 1;
+    for (int e = 0; e < 3; e++) {
+      R.lo[e] = C.ng[e];
+      R.cnt[e] = C.n[e] > 1 ? C.n[e] + 1 : 1;
+      R.total *= R.cnt[e];
+    }
+    if (dtmin) {
+      const long n = std::max<long>(R.total, (long)C.n[0] * C.n[1] * C.n[2]);
+      hipLaunchKernelGGL(k_emf_stag_dt, dim3(nblocks(n, 256)), dim3(256), 0, g->stream, C, R, Bf,
+                         (const double*)VF, (const double*)SP, emf, (const double*)vch, dtmin);
+    } else {
+      hipLaunchKernelGGL(k_emf_stag, dim3(nblocks(R.total, 256)), dim3(256), 0, g->stream, C, R,
+                         Bf, (const double*)VF, (const double*)SP, emf);
+    }
+    LAUNCHCHK();
+    return 0;
   }
   if (S64.total > 0) {
     if (Fs)
@@ -534,13 +604,14 @@ static int launch_timestep(grrmhd_grid* g, const double* vch, double* dt_dev) {
 static int launch_update(grrmhd_grid* g, double a, double b, double c, const double* dt_dev,
                          const double* P, const double* Un, const double* Up, const double* F,
                          const double* emf, double* Ue, const unsigned long long* dtmin = nullptr,
-                         unsigned long long* dtnext = nullptr, const MTerms* mt = nullptr) {
+                         unsigned long long* dtnext = nullptr, const MTerms* mt = nullptr,
+                         const double* Bface = nullptr) {
   MTerms MT;
   memset(&MT, 0, sizeof(MT));
   if (mt) MT = *mt;
   hipLaunchKernelGGL(k_update, dim3(nblocks(n_interior(g->C), 256)), dim3(256), 0, g->stream,
                      g->C, a, b, c, const_cast<double*>(dt_dev), dtmin, dtnext, P, Un, Up, F, emf,
-                     MT, Ue);
+                     MT, Ue, Bface);
   LAUNCHCHK();
   return 0;
 }
@@ -744,19 +815,12 @@ static int imex_step(grrmhd_grid* g, double* P, double* U, const double* chi_abs
   return 0;
 }
 
-extern "C" int grrmhd_step(grrmhd_grid* g, double* P, double* U, const double* chi_abs,
-                           const double* chi_es, double* dt_dev, int dt_fixed, int* status,
-                           int* iters, void* workspace, size_t ws_bytes) {
-  NEEDG();
-  if (!P || !U || !chi_abs || !chi_es || !dt_dev || !workspace)
-    return fail(GRRMHD_EINVAL, "NULL array");
+// One RK3 step; Bf: the staggered field (stage faces in the workspace, the
+// last stage written to Bf in place), else null.
+static int rk3_step(grrmhd_grid* g, double* P, double* U, double* Bf, const double* chi_abs,
+                    const double* chi_es, double* dt_dev, int dt_fixed, int* status, int* iters,
+                    char* base, const WsLayout& w) {
   const Ctx& C = g->C;
-  const WsLayout w = ws_layout(C, g->p.scheme);
-  if (ws_bytes < w.total) return fail(GRRMHD_EINVAL, "workspace too small");
-  if (((uintptr_t)workspace) & 255) return fail(GRRMHD_EINVAL, "workspace must be 256-byte aligned");
-  char* base = (char*)workspace;
-  if (g->p.scheme != GRRMHD_RK3)
-    return imex_step(g, P, U, chi_abs, chi_es, dt_dev, dt_fixed, status, iters, base, w);
   double* F = (double*)(base + w.F);
   double* emf = (double*)(base + w.emf);
   double* vch = (double*)(base + w.vch);
@@ -782,19 +846,47 @@ extern "C" int grrmhd_step(grrmhd_grid* g, double* P, double* U, const double* c
     hipLaunchKernelGGL(k_entropy_field, dim3(nblocks(nint, 256)), dim3(256), 0, g->stream, C, P, Sn);
     LAUNCHCHK();
   }
+  // staggered field: stage inputs Bf, B1, B2; outputs B1, B2, Bf
+  double* VF = Bf ? (double*)(base + w.VF) : nullptr;
+  double* SP = Bf ? (double*)(base + w.SP) : nullptr;
+  double* Bst[3] = {Bf ? (double*)(base + w.B1) : nullptr, Bf ? (double*)(base + w.B2) : nullptr, Bf};
+  FaceRange RF;
+  RF.total = 1;
+  for (int e = 0; e < 3; e++) {
+    RF.lo[e] = C.ng[e];
+    RF.cnt[e] = C.n[e] > 1 ? C.n[e] + 1 : 1;
+    RF.total *= RF.cnt[e];
+  }
   for (int s = 0; s < 3; s++) {
     double* Pin = (s == 0) ? P : Pa;
     const double* Uprev = (s == 0) ? U : Ua;
     double* Pout = (s == 2) ? P : Pa;
     double* Uout = (s == 2) ? U : Ua;
+    double* Bin = Bf ? ((s == 0) ? Bf : Bst[s - 1]) : nullptr;
     if ((rc = launch_bc(g, Pin))) return rc;
+    if (Bf) {
+      hipLaunchKernelGGL(k_bc_faces, dim3(nblocks(3 * C.Ntot, 256)), dim3(256), 0, g->stream, C,
+                         Bin);
+      LAUNCHCHK();
+    }
     // stage 1 without a fixed dt: the Courant reduction rides on the EMF launch
     // and the update takes dt from it (dtstep alternates between steps)
     const bool red = (s == 0 && !dt_fixed);
     unsigned long long* dmin = red ? g->dtstep[g->dtp] : nullptr;
     unsigned long long* dnext = red ? g->dtstep[g->dtp ^ 1] : nullptr;
-    if ((rc = launch_fluxes(g, Pin, chi_abs, chi_es, F, emf, vch, dmin, s > 0, Fs))) return rc;
-    if ((rc = launch_update(g, A[s], B[s], Cc[s], dt_dev, Pin, U, Uprev, F, emf, Ue, dmin, dnext)))
+    if ((rc = launch_fluxes(g, Pin, chi_abs, chi_es, F, emf, vch, dmin, s > 0, Fs, Bin, VF, SP)))
+      return rc;
+    if (Bf) {
+      // the stage's faces (before the cell update, which averages them)
+      hipLaunchKernelGGL(k_face_update, dim3(nblocks(RF.total, 256)), dim3(256), 0, g->stream, C,
+                         RF, A[s], B[s], Cc[s], (const double*)dt_dev,
+                         (const unsigned long long*)dmin, (const double*)Bf,
+                         (const double*)(s > 0 ? Bst[s - 1] : nullptr), (const double*)emf,
+                         Bst[s]);
+      LAUNCHCHK();
+    }
+    if ((rc = launch_update(g, A[s], B[s], Cc[s], dt_dev, Pin, U, Uprev, F, emf, Ue, dmin, dnext,
+                            nullptr, Bf ? Bst[s] : nullptr)))
       return rc;
     if (red) g->dtp ^= 1;
     if (C.cascade) {
@@ -809,6 +901,83 @@ extern "C" int grrmhd_step(grrmhd_grid* g, double* P, double* U, const double* c
     if ((rc = launch_fixup(g, Pout, Uout, st, Ue, status, it, iters, s > 0))) return rc;
   }
   return 0;
+}
+
+static int step_args(grrmhd_grid* g, void* workspace, size_t ws_bytes, WsLayout& w) {
+  w = ws_layout(g->C, g->p.scheme);
+  if (ws_bytes < w.total) return fail(GRRMHD_EINVAL, "workspace too small");
+  if (((uintptr_t)workspace) & 255) return fail(GRRMHD_EINVAL, "workspace must be 256-byte aligned");
+  return 0;
+}
+
+extern "C" int grrmhd_step(grrmhd_grid* g, double* P, double* U, const double* chi_abs,
+                           const double* chi_es, double* dt_dev, int dt_fixed, int* status,
+                           int* iters, void* workspace, size_t ws_bytes) {
+  NEEDG();
+  if (!P || !U || !chi_abs || !chi_es || !dt_dev || !workspace)
+    return fail(GRRMHD_EINVAL, "NULL array");
+  if (g->C.ct) return fail(GRRMHD_EINVAL, "a staggered-field grid steps with grrmhd_step_staggered");
+  WsLayout w;
+  int rc = step_args(g, workspace, ws_bytes, w);
+  if (rc) return rc;
+  char* base = (char*)workspace;
+  if (g->p.scheme != GRRMHD_RK3)
+    return imex_step(g, P, U, chi_abs, chi_es, dt_dev, dt_fixed, status, iters, base, w);
+  return rk3_step(g, P, U, nullptr, chi_abs, chi_es, dt_dev, dt_fixed, status, iters, base, w);
+}
+
+extern "C" int grrmhd_step_staggered(grrmhd_grid* g, double* P, double* U, double* Bf,
+                                     const double* chi_abs, const double* chi_es, double* dt_dev,
+                                     int dt_fixed, int* status, int* iters, void* workspace,
+                                     size_t ws_bytes) {
+  NEEDG();
+  if (!P || !U || !Bf || !chi_abs || !chi_es || !dt_dev || !workspace)
+    return fail(GRRMHD_EINVAL, "NULL array");
+  if (!g->C.ct) return fail(GRRMHD_EINVAL, "grid has the flux-CT field (ct = GRRMHD_CT_FLUX)");
+  WsLayout w;
+  int rc = step_args(g, workspace, ws_bytes, w);
+  if (rc) return rc;
+  return rk3_step(g, P, U, Bf, chi_abs, chi_es, dt_dev, dt_fixed, status, iters, (char*)workspace, w);
+}
+
+extern "C" int grrmhd_apply_bc_faces(grrmhd_grid* g, double* Bf) {
+  NEEDG();
+  if (!Bf) return fail(GRRMHD_EINVAL, "NULL array");
+  if (!g->C.ct) return fail(GRRMHD_EINVAL, "grid has the flux-CT field (ct = GRRMHD_CT_FLUX)");
+  hipLaunchKernelGGL(k_bc_faces, dim3(nblocks(3 * g->C.Ntot, 256)), dim3(256), 0, g->stream, g->C,
+                     Bf);
+  LAUNCHCHK();
+  return 0;
+}
+
+extern "C" int grrmhd_face_to_center(grrmhd_grid* g, const double* Bf, double* P, double* U) {
+  NEEDG();
+  if (!Bf || (!P && !U)) return fail(GRRMHD_EINVAL, "NULL array");
+  if (!g->C.ct) return fail(GRRMHD_EINVAL, "grid has the flux-CT field (ct = GRRMHD_CT_FLUX)");
+  hipLaunchKernelGGL(k_face_center, dim3(nblocks(n_interior(g->C), 256)), dim3(256), 0, g->stream,
+                     g->C, Bf, P, U);
+  LAUNCHCHK();
+  return 0;
+}
+
+extern "C" int grrmhd_fluxes_staggered(grrmhd_grid* g, const double* P, const double* Bf,
+                                       const double* chi_abs, const double* chi_es, double* F,
+                                       double* emf, double* vchar, void* workspace,
+                                       size_t ws_bytes) {
+  NEEDG();
+  if (!P || !Bf || !chi_abs || !chi_es || !F || !emf || !vchar || !workspace)
+    return fail(GRRMHD_EINVAL, "NULL array");
+  if (!g->C.ct) return fail(GRRMHD_EINVAL, "grid has the flux-CT field (ct = GRRMHD_CT_FLUX)");
+  WsLayout w;
+  int rc = step_args(g, workspace, ws_bytes, w);
+  if (rc) return rc;
+  const size_t N = (size_t)g->C.Ntot;
+  HIPCHK(hipMemsetAsync(F, 0, sizeof(double) * 36 * N, g->stream));
+  HIPCHK(hipMemsetAsync(emf, 0, sizeof(double) * 3 * N, g->stream));
+  HIPCHK(hipMemsetAsync(vchar, 0, sizeof(double) * 3 * N, g->stream));
+  char* base = (char*)workspace;
+  return launch_fluxes(g, P, chi_abs, chi_es, F, emf, vchar, nullptr, 0, nullptr, Bf,
+                       (double*)(base + w.VF), (double*)(base + w.SP));
 }
 
 // ---------------------------------------------------------------------------
@@ -1054,6 +1223,8 @@ static int adj_ptrs(grrmhd_grid* g, void* workspace, size_t ws_bytes, AdjPtrs& a
     return fail(GRRMHD_EINVAL, "the adjoint covers MC reconstruction");
   if (g->p.cascade != 0)
     return fail(GRRMHD_EINVAL, "the adjoint covers the PMHD/URAD cascade (cascade = 0)");
+  if (g->C.ct)
+    return fail(GRRMHD_EINVAL, "the adjoint covers the flux-CT field (ct = GRRMHD_CT_FLUX)");
   const AdjLayout w = adj_layout(g->C, g->p.scheme);
   if (ws_bytes < w.total) return fail(GRRMHD_EINVAL, "workspace too small");
   if (((uintptr_t)workspace) & 255) return fail(GRRMHD_EINVAL, "workspace must be 256-byte aligned");

@@ -312,12 +312,19 @@ DEV void entropy_face(const Ctx& C, const MetricT<T>& m, const T* P, T& Us, T& F
   Fs = m.gdet * S * v.ucon[D];
 }
 
-template <int D, class T, bool ENTF = false>
+// STAG (staggered face field Bf [3][Ntot], sqrt(-g) B^d on the lower d-face
+// of each cell): both states take the face's own normal field, and the face
+// velocities v^m = u^m/u^t of each state and the gas v_min, v_max of eq. hll
+// go to VF [(2 (D-1) + side) 3 + m][Ntot] and SP [2 (D-1) + {0, 1}][Ntot]
+// for the corner EMFs.
+template <int D, class T, bool ENTF = false, bool STAG = false>
 DEV void flux_at(Ctx C, FaceRange R, const double* __restrict__ P,
                                const double* __restrict__ chi_abs,
                                const double* __restrict__ chi_es, double* __restrict__ F,
                                double* __restrict__ vchar, const double* __restrict__ fl, long t,
-                               double* __restrict__ Fs = nullptr) {
+                               double* __restrict__ Fs = nullptr,
+                               const double* __restrict__ Bf = nullptr,
+                               double* __restrict__ VF = nullptr, double* __restrict__ SP = nullptr) {
   if (t >= R.total) return;
   const int i = R.lo[0] + t % R.cnt[0];
   const long t2 = t / R.cnt[0];
@@ -353,6 +360,13 @@ DEV void flux_at(Ctx C, FaceRange R, const double* __restrict__ P,
   MetricT<T> m;
   const double* tab = (D == 1) ? C.geo_f1 : ((D == 2) ? C.geo_f2 : C.geo_c);
   load_metric(tab, C.npos, i + C.N[0] * j, m);
+  if constexpr (STAG) {
+    // the face's own normal field (zero where sqrt(-g) vanishes, the axis)
+    const double gd = tab[GE_GDET * C.npos + i + C.N[0] * j];
+    const T bn = (T)(gd > 0.0 ? Bf[(long)(D - 1) * C.Ntot + c] / gd : 0.0);
+    PL[4 + D] = bn;
+    PR[4 + D] = bn;
+  }
   FaceState<T> L, Rs;
   face_state(C, m, D, PL, (T)(chi_abs[c - st] + chi_es[c - st]), L);
   face_state(C, m, D, PR, (T)(chi_abs[c] + chi_es[c]), Rs);
@@ -375,6 +389,18 @@ DEV void flux_at(Ctx C, FaceRange R, const double* __restrict__ P,
     F[q * C.Ntot + c] = (double)f;
   }
   vchar[c] = (double)fmax(fmax(gmin, gmax), fmax(rmin, rmax));
+  if constexpr (STAG) {
+#pragma unroll
+    for (int sd = 0; sd < 2; sd++) {
+      Vel<T> v;
+      make_vel(m, (sd ? PR : PL) + 2, v);
+#pragma unroll
+      for (int q = 0; q < 3; q++)
+        VF[((long)((2 * (D - 1) + sd) * 3) + q) * C.Ntot + c] = (double)(v.ucon[q + 1] / v.ucon[0]);
+    }
+    SP[(long)(2 * (D - 1)) * C.Ntot + c] = (double)gmin;
+    SP[(long)(2 * (D - 1) + 1) * C.Ntot + c] = (double)gmax;
+  }
   if constexpr (ENTF) {
     // the entropy tracer's flux, with the gas speeds
     T UsL, FsL, UsR, FsR, f;
@@ -403,11 +429,13 @@ struct FluxSegs {
   long total;
 };
 
-template <class T, bool ENTF = false>
+template <class T, bool ENTF = false, bool STAG = false>
 DEV void flux_all_at(Ctx C, const FluxSegs& S, const double* __restrict__ P,
                      const double* __restrict__ chi_abs, const double* __restrict__ chi_es,
                      double* __restrict__ F, double* __restrict__ vchar,
-                     const double* __restrict__ fl, long t, double* __restrict__ Fs = nullptr) {
+                     const double* __restrict__ fl, long t, double* __restrict__ Fs = nullptr,
+                     const double* __restrict__ Bf = nullptr, double* __restrict__ VF = nullptr,
+                     double* __restrict__ SP = nullptr) {
   if (t >= S.total) return;
   int k = 0;
   if (S.n > 1 && t >= S.start[1]) k = 1;
@@ -417,9 +445,24 @@ DEV void flux_all_at(Ctx C, const FluxSegs& S, const double* __restrict__ P,
   double* Fd = F + (long)(D - 1) * 12 * C.Ntot;
   double* vd = vchar + (long)(D - 1) * C.Ntot;
   double* Fsd = ENTF ? Fs + (long)(D - 1) * C.Ntot : nullptr;
-  if (D == 1) flux_at<1, T, ENTF>(C, S.R[k], P, chi_abs, chi_es, Fd, vd, fl, u, Fsd);
-  else if (D == 2) flux_at<2, T, ENTF>(C, S.R[k], P, chi_abs, chi_es, Fd, vd, fl, u, Fsd);
-  else flux_at<3, T, ENTF>(C, S.R[k], P, chi_abs, chi_es, Fd, vd, fl, u, Fsd);
+  if (D == 1) flux_at<1, T, ENTF, STAG>(C, S.R[k], P, chi_abs, chi_es, Fd, vd, fl, u, Fsd, Bf, VF, SP);
+  else if (D == 2) flux_at<2, T, ENTF, STAG>(C, S.R[k], P, chi_abs, chi_es, Fd, vd, fl, u, Fsd, Bf, VF, SP);
+  else flux_at<3, T, ENTF, STAG>(C, S.R[k], P, chi_abs, chi_es, Fd, vd, fl, u, Fsd, Bf, VF, SP);
+}
+
+// The same with the staggered field (and, with ENTF, the entropy tracer)
+template <class T, bool ENTF>
+__global__ void GRRMHD_FLUX_LB k_flux_all_stag(Ctx C, FluxSegs S, const double* __restrict__ P,
+                                               const double* __restrict__ chi_abs,
+                                               const double* __restrict__ chi_es,
+                                               double* __restrict__ F, double* __restrict__ vchar,
+                                               const double* __restrict__ fl,
+                                               double* __restrict__ Fs,
+                                               const double* __restrict__ Bf,
+                                               double* __restrict__ VF, double* __restrict__ SP) {
+  flux_all_at<T, ENTF, true>(C, S, P, chi_abs, chi_es, F, vchar, fl,
+                             xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x, Fs, Bf,
+                             VF, SP);
 }
 
 template <class T>
@@ -711,7 +754,7 @@ DEV void update_at(Ctx C, double ca, double cb, double cc, double* dt_dev,
                    const double* __restrict__ P, const double* __restrict__ Un,
                    const double* __restrict__ Uprev, const double* __restrict__ F,
                    const double* __restrict__ emf, const MTerms& MT, double* __restrict__ Uexp,
-                   long t) {
+                   long t, const double* __restrict__ Bface = nullptr) {
   const long nint = (long)C.n[0] * C.n[1] * C.n[2];
   if (t >= nint) return;
   const int i = C.ng[0] + t % C.n[0];
@@ -787,6 +830,15 @@ DEV void update_at(Ctx C, double ca, double cb, double cc, double* dt_dev,
     }
     Uexp[q * C.Ntot + c] = u;
   }
+  if (Bface) {
+    // staggered field: the stage's cell-centred field is the mean of the
+    // cell's two new faces (the face itself on an inactive dimension)
+#pragma unroll
+    for (int q = 0; q < 3; q++) {
+      const double* B = Bface + (long)q * C.Ntot;
+      Uexp[(5 + q) * C.Ntot + c] = (C.n[q] > 1) ? 0.5 * (B[c] + B[c + C.st[q]]) : B[c];
+    }
+  }
 }
 
 __global__ void LB(256) k_update(Ctx C, double ca, double cb, double cc, double* dt_dev,
@@ -794,9 +846,9 @@ __global__ void LB(256) k_update(Ctx C, double ca, double cb, double cc, double*
                                  const double* __restrict__ P, const double* __restrict__ Un,
                                  const double* __restrict__ Uprev, const double* __restrict__ F,
                                  const double* __restrict__ emf, MTerms MT,
-                                 double* __restrict__ Uexp) {
+                                 double* __restrict__ Uexp, const double* __restrict__ Bface) {
   update_at(C, ca, cb, cc, dt_dev, dtmin, dtnext, P, Un, Uprev, F, emf, MT, Uexp,
-            (long)blockIdx.x * blockDim.x + threadIdx.x);
+            (long)blockIdx.x * blockDim.x + threadIdx.x, Bface);
 }
 
 // ---------------------------------------------------------------------------
@@ -1465,7 +1517,11 @@ DEV void fixup_apply_at(Ctx C, double* __restrict__ P, double* __restrict__ U,
   if ((fail || cold) && scr[12 * C.Ntot + c] > 0.0) {
     // failed: the neighbours' mean primitives; cold: their mean u_g alone
 #pragma unroll
-    for (int q = 0; q < 12; q++) p[q] = (fail || q == 1) ? scr[q * C.Ntot + c] : P[q * C.Ntot + c];
+    for (int q = 0; q < 12; q++) {
+      // a staggered field is not a primitive of the solve: the cell keeps its B
+      const bool avg = (fail && !(C.ct && q >= 5 && q <= 7)) || q == 1;
+      p[q] = avg ? scr[q * C.Ntot + c] : P[q * C.Ntot + c];
+    }
     if (scr[12 * C.Ntot + c] > 1.5) st |= GRRMHD_ST_NO_GOOD_NB;
     changed = true;
   } else {

@@ -34,6 +34,7 @@ class Params(C.Structure):
         ("rho_floor", C.c_double), ("u_floor", C.c_double), ("bsq_rho_max", C.c_double),
         ("bsq_u_max", C.c_double), ("u_rho_max", C.c_double), ("erad_floor", C.c_double),
         ("scheme", C.c_int), ("recon", C.c_int), ("cold", C.c_int), ("cascade", C.c_int),
+        ("ct", C.c_int),
     ]
 
 
@@ -71,6 +72,7 @@ def params(d: dict) -> Params:
     p.recon = 1 if d.get("recon", "mc") == "ppm" else 0
     p.cold = int(d.get("cold", 1))
     p.cascade = int(d.get("cascade", 0))
+    p.ct = 1 if d.get("ct", "flux") == "staggered" else 0
     return p
 
 
@@ -127,6 +129,10 @@ def lib():
             "grrmhd_implicit_time": (C.c_int, [_VP, C.POINTER(C.c_double), C.POINTER(C.c_int)]),
             "grrmhd_implicit_source_stats": (C.c_int, [_VP, C.POINTER(C.c_ulonglong), _VP]),
             "grrmhd_implicit_source_cascade_stats": (C.c_int, [_VP, C.POINTER(C.c_ulonglong), _VP]),
+            "grrmhd_apply_bc_faces": (C.c_int, [_VP, _VP]),
+            "grrmhd_face_to_center": (C.c_int, [_VP] * 4),
+            "grrmhd_fluxes_staggered": (C.c_int, [_VP] * 9 + [C.c_size_t]),
+            "grrmhd_step_staggered": (C.c_int, [_VP] * 7 + [C.c_int, _VP, _VP, _VP, C.c_size_t]),
         }
         for name, (res, args) in sigs.items():
             f = getattr(L, name)
@@ -357,6 +363,39 @@ class Grid:
         _check(lib().grrmhd_fixup_vjp(self.h, _ptr(P), _ptr(status), _ptr(gP), _ptr(gU), _ptr(gPp),
                                       _ptr(gUp), _ptr(scratch)))
         return gPp, gUp
+
+    # staggered face field Bf [3][N] (pd["ct"] = "staggered")
+    def apply_bc_faces(self, Bf):
+        self._sync_stream()
+        _check(lib().grrmhd_apply_bc_faces(self.h, _ptr(Bf)))
+        return Bf
+
+    def face_to_center(self, Bf, P=None, U=None):
+        """Interior cells' field slots of P and/or U from the faces."""
+        self._sync_stream()
+        _check(lib().grrmhd_face_to_center(self.h, _ptr(Bf), _ptr(P), _ptr(U)))
+        return P, U
+
+    def fluxes_staggered(self, P, Bf, chi_abs, chi_es):
+        self._sync_stream()
+        F = torch.empty((3, 12, self.N), dtype=torch.float64, device=P.device)
+        emf = torch.empty((3, self.N), dtype=torch.float64, device=P.device)
+        vch = torch.empty((3, self.N), dtype=torch.float64, device=P.device)
+        ws = self.workspace()
+        _check(lib().grrmhd_fluxes_staggered(self.h, _ptr(P), _ptr(Bf), _ptr(chi_abs),
+                                             _ptr(chi_es), _ptr(F), _ptr(emf), _ptr(vch),
+                                             _ptr(ws), self.ws_bytes))
+        return F, emf, vch
+
+    def step_staggered(self, P, U, Bf, chi_abs, chi_es, dt, dt_fixed=False, status=None,
+                       iters=None):
+        """One RK3 step with the staggered field, in place on P, U, Bf."""
+        self._sync_stream()
+        ws = self.workspace()
+        _check(lib().grrmhd_step_staggered(self.h, _ptr(P), _ptr(U), _ptr(Bf), _ptr(chi_abs),
+                                           _ptr(chi_es), _ptr(dt), 1 if dt_fixed else 0,
+                                           _ptr(status), _ptr(iters), _ptr(ws), self.ws_bytes))
+        return P, U, Bf
 
     def step(self, P, U, chi_abs, chi_es, dt, dt_fixed=False, status=None, iters=None):
         """One step of the grid's scheme in place on P, U; dt is a 1-element device
