@@ -311,6 +311,65 @@ def time_steps(G, torch, dev, pd, P, ca, ce, steps, warmup, kernel_timing):
     return res
 
 
+def time_steps_stag(G, torch, dev, pd, P, Bf, ca, ce, steps, warmup):
+    """time_steps for a staggered-field grid (grrmhd_step_staggered), the
+    faces' ghost fill and face-to-centre field set up first."""
+    stream = torch.cuda.current_stream()
+    g = G.Grid(pd)
+    Pt = torch.tensor(P, device=dev)
+    Bt = torch.tensor(Bf, device=dev)
+    g.apply_bc_faces(Bt)
+    g.face_to_center(Bt, Pt, None)
+    g.apply_bc(Pt)
+    Ut = g.prim_to_cons(Pt)
+    cat = torch.tensor(ca, device=dev)
+    cet = torch.tensor(ce, device=dev)
+    dt = torch.zeros(1, dtype=torch.float64, device=dev)
+    for _ in range(warmup):
+        g.step_staggered(Pt, Ut, Bt, cat, cet, dt)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        g.step_staggered(Pt, Ut, Bt, cat, cet, dt)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    res = {"ms": e0.elapsed_time(e1)}
+    g.close()
+    return res
+
+
+def bench_batch_cascade(G, I, torch, dev, n, reps=3):
+    """The batched solve (per-cell form) with the normal and the full
+    cascade: ms per batch and the fraction of cells per outcome."""
+    pd, args = batch_inputs(G, I, torch, dev, n)
+    stream = torch.cuda.current_stream()
+    out = {"cells": n}
+    for cas in (0, 1):
+        pdc = dict(pd, cascade=cas)
+        ws = G.batch_workspace(n, G.PER_CELL)
+        o = G._batch_out(args[0], args[1])
+        G.implicit_source_ex(pdc, *args, G.PER_CELL, 64, 1, out=o, ws=ws)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            G.implicit_source_ex(pdc, *args, G.PER_CELL, 64, 1, out=o, ws=ws)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        st = o[4].cpu().numpy()   # (n, P, U, iters, status, err)
+        frac = lambda b: float(((st & b) != 0).mean())
+        out["full" if cas else "normal"] = {
+            "ms": e0.elapsed_time(e1) / reps, "failed_frac": frac(G.ST_FAIL),
+            "cold_frac": frac(G.ST_COLD), "urad_frac": frac(G.ST_URAD), "prad_frac": frac(G.ST_PRAD),
+            "entropy_frac": frac(G.ST_ENTROPY), "staged_frac": frac(G.ST_STAGED)}
+        del ws, o
+    print(f"batch cascades: failed {out['normal']['failed_frac']:.4f} -> {out['full']['failed_frac']:.4f}",
+          file=sys.stderr, flush=True)
+    return out
+
+
 def gpu_run(G, torch, dev, pd, P, ca, ce, steps):
     """Interior P, U after `steps` steps from the initial state (untimed)."""
     g = G.Grid(pd)
@@ -410,6 +469,19 @@ def main():
              "time_vs_roundoff_mode": rpm["ms"] / r64["ms"],
              "mean_newton_iters_per_cell_step": float(itp.mean()),
              "mean_newton_iters_per_cell_step_roundoff_mode": float(itv.mean())}
+    # the staggered face-centred field with four-state corner EMFs
+    pds, Ps, cas, ces, Bfs = I.accretion_disk(n=n, seed=3, faces=True, ct="staggered")
+    rst = time_steps_stag(G, torch, dev, pds, Ps, Bfs, cas, ces, args.steps, args.warmup)
+    print(f"staggered steps: {rst['ms'] / args.steps:.3f} ms/step", file=sys.stderr, flush=True)
+    stag = {"value": zones * args.steps / (rst["ms"] * 1e-3), "ms_per_step": rst["ms"] / args.steps,
+            "time_vs_flux_ct": rst["ms"] / r64["ms"]}
+    # the full implicit cascade (PRAD, staged, entropy methods) on the disk
+    pdc = dict(pd, cascade=1)
+    rca = time_steps(G, torch, dev, pdc, P, ca, ce, args.steps, args.warmup, kernel_timing=False)
+    print(f"full-cascade steps: {rca['ms'] / args.steps:.3f} ms/step", file=sys.stderr, flush=True)
+    casc = {"value": zones * args.steps / (rca["ms"] * 1e-3), "ms_per_step": rca["ms"] / args.steps,
+            "time_vs_normal_cascade": rca["ms"] / r64["ms"],
+            "batch": bench_batch_cascade(G, I, torch, dev, 1 << 20)}
     fid = None
     if not args.no_fiducial:
         nf = (256, 128, 64)
@@ -516,6 +588,27 @@ def main():
         e = [field_errors(got[0], ref[0]), field_errors(got[1], ref[1])]
         paper["err_vs_oracle_max"] = max(max(e[0].values()), max(e[1].values()))
         paper["err_steps"] = args.imex_err_steps
+        # the staggered field against the oracle's (same few steps)
+        Bh = oracle.bc_face(pds, Bfs)
+        Ph, Uh = oracle.face_to_center(pds, Bh, Ps, np.zeros_like(Ps))
+        Ph = oracle.bc(pds, Ph)
+        Uh = oracle.prim_to_cons(pds, Ph)
+        P0, U0, B0 = Ph, Uh, Bh
+        for _ in range(args.imex_err_steps):
+            Ph, Uh, Bh, dth, sth, ith, nb = oracle.step_stag(pds, Ph, Uh, Bh, cas, ces)
+        gs = G.Grid(pds)
+        Pt, Ut, Bt = (torch.tensor(x, device=dev) for x in (P0, U0, B0))
+        cat, cet = torch.tensor(cas, device=dev), torch.tensor(ces, device=dev)
+        dtt = torch.zeros(1, dtype=torch.float64, device=dev)
+        for _ in range(args.imex_err_steps):
+            gs.step_staggered(Pt, Ut, Bt, cat, cet, dtt)
+        Pg, Ug, Bg = Pt.cpu().numpy(), Ut.cpu().numpy(), Bt.cpu().numpy()
+        gs.close()
+        ref = [x.reshape((12,) + na[::-1])[(slice(None),) + interior].reshape(12, -1) for x in (Ph, Uh)]
+        got = [x.reshape((12,) + na[::-1])[(slice(None),) + interior].reshape(12, -1) for x in (Pg, Ug)]
+        e = [field_errors(got[0], ref[0]), field_errors(got[1], ref[1])]
+        stag["err_vs_oracle_max"] = max(max(e[0].values()), max(e[1].values()))
+        stag["err_steps"] = args.imex_err_steps
         if args.cpu1_steps:
             cpu["one_core"] = oracle_one_core(n, args.cpu1_steps)
 
@@ -543,6 +636,8 @@ def main():
         "imex3": imex,
         "ppm": ppm,
         "paper_stopping_rule": paper,
+        "staggered_field": stag,
+        "full_cascade": casc,
         "fiducial_256x128x64": fid,
         "adjoint": adj,
         "adjoint_imex3": adj3,
