@@ -200,8 +200,20 @@ void orc_flattener(const orc_params *p, const double *P, const double *chi_abs,
           pg[c] = p_g + w * p_r;
           pr[c] = p_r + w * p_g;
           wt[c] = w;
-          vg[c] = P[(2 + d) * N + c];
-          vr[c] = P[(9 + d) * N + c];
+          if (p->metric == ORC_KERR_SCHILD) {
+            /* the specific mass fluxes sqrt(-g) u^d of gas and radiation */
+            double ut[3], ucon[4];
+            for (int m = 0; m < 3; m++) ut[m] = P[(2 + m) * N + c];
+            orc_ucon(&g, ut, ucon);
+            vg[c] = g.gdet * ucon[d + 1];
+            for (int m = 0; m < 3; m++) ut[m] = P[(9 + m) * N + c];
+            orc_ucon(&g, ut, ucon);
+            vr[c] = g.gdet * ucon[d + 1];
+          } else {
+            /* flat space: u^d = u~^d and sqrt(-g) = 1 */
+            vg[c] = P[(2 + d) * N + c];
+            vr[c] = P[(9 + d) * N + c];
+          }
         }
     int lo[3], hi[3];
     for (int e = 0; e < 3; e++) {
@@ -279,6 +291,10 @@ static void fluxes_core(const orc_params *p, const double *P, const double *chi_
     for (int e = 0; e < d; e++) st *= NA[e];
     const double dxd = orc_dx(p, d);
     double *Fd = F + (long)d * 12 * N;
+    /* PPM on Kerr-Schild along r (x1): the vector primitives interpolated
+     * as sqrt(-g) times the value (Sec. 4.3); along phi sqrt(-g) does not
+     * vary, so the weighting is the identity there */
+    const int wgt = (p->recon == ORC_RECON_PPM && p->metric == ORC_KERR_SCHILD && d == 0);
 #pragma omp parallel for collapse(2)
     for (int k = lo[2]; k <= hi[2]; k++)
       for (int j = lo[1]; j <= hi[1]; j++)
@@ -286,15 +302,33 @@ static void fluxes_core(const orc_params *p, const double *P, const double *chi_
           const long c = IDX(p, i, j, k);
           const long m2 = c - 2 * st, m1 = c - st, p1 = c + st;
           double PL[12], PR[12];
+          double x1, x2;
+          orc_face_x(p, d + 1, i, j, &x1, &x2);
+          orc_geom g;
+          orc_geom_point(p, x1, x2, &g);
           if (p->recon == ORC_RECON_PPM) {
             /* left state: right value of cell c - st; right state: left value of c */
+            double gc[6] = {1, 1, 1, 1, 1, 1};   /* sqrt(-g) of cells c-3 .. c+2 */
+            if (wgt)
+              for (int m = 0; m < 6; m++) {
+                double y1, y2;
+                orc_cell_x(p, i + m - 3, j, &y1, &y2);
+                orc_geom gm;
+                orc_geom_point(p, y1, y2, &gm);
+                gc[m] = gm.gdet;
+              }
             for (int q = 0; q < 12; q++) {
               const int kind = q < 8 ? 0 : 1;
+              const int vec = wgt && ((q >= 2 && q <= 7) || q >= 9);
               double a5[5], l, r;
-              for (int m = 0; m < 5; m++) a5[m] = P[q * N + c + (m - 3) * st];
+              for (int m = 0; m < 5; m++) a5[m] = P[q * N + c + (m - 3) * st] * (vec ? gc[m] : 1.0);
               orc_ppm_cell(a5, fl[(long)(2 * d + kind) * N + m1], &l, &PL[q]);
-              for (int m = 0; m < 5; m++) a5[m] = P[q * N + c + (m - 2) * st];
+              for (int m = 0; m < 5; m++) a5[m] = P[q * N + c + (m - 2) * st] * (vec ? gc[m + 1] : 1.0);
               orc_ppm_cell(a5, fl[(long)(2 * d + kind) * N + c], &PR[q], &r);
+              if (vec) {
+                PL[q] /= g.gdet;
+                PR[q] /= g.gdet;
+              }
               (void)l;
               (void)r;
             }
@@ -304,10 +338,6 @@ static void fluxes_core(const orc_params *p, const double *P, const double *chi_
               orc_mc_face(a4, &PL[q], &PR[q]);
             }
           }
-          double x1, x2;
-          orc_face_x(p, d + 1, i, j, &x1, &x2);
-          orc_geom g;
-          orc_geom_point(p, x1, x2, &g);
           if (Bf) {
             /* the face's own normal field (zero where sqrt(-g) vanishes) */
             const double bn = g.gdet > 0.0 ? Bf[(long)d * N + c] / g.gdet : 0.0;
