@@ -338,15 +338,30 @@ DEV void flux_at(Ctx C, FaceRange R, const double* __restrict__ P,
     const double* fg = fl + (long)(2 * (D - 1)) * C.Ntot;
     const double* fr = fg + C.Ntot;
     const T fgL = (T)fg[c - st], frL = (T)fr[c - st], fgR = (T)fg[c], frR = (T)fr[c];
+    // Kerr-Schild, along r: the vector primitives interpolated as sqrt(-g)
+    // times the value (Sec. 4.3); along phi sqrt(-g) is constant and the
+    // weighting the identity
+    const bool wgt = (D == 1) && C.metric == GRRMHD_KERR_SCHILD;
+    double gc[6] = {1.0, 1.0, 1.0, 1.0, 1.0, 1.0}, gface = 1.0;
+    if (wgt) {
+#pragma unroll
+      for (int m = 0; m < 6; m++) gc[m] = C.geo_c[GE_GDET * C.npos + (i + m - 3) + C.N[0] * j];
+      gface = C.geo_f1[GE_GDET * C.npos + i + C.N[0] * j];
+    }
 #pragma unroll
     for (int q = 0; q < 12; q++) {
       const double* p = P + q * C.Ntot;
+      const bool vec = wgt && ((q >= 2 && q <= 7) || q >= 9);
       T a[6];
 #pragma unroll
-      for (int m = 0; m < 6; m++) a[m] = (T)p[c + (m - 3) * st];
+      for (int m = 0; m < 6; m++) a[m] = (T)(vec ? p[c + (m - 3) * st] * gc[m] : p[c + (m - 3) * st]);
       T l, r;
       ppm_cell(a, q < 8 ? fgL : frL, l, PL[q]);
       ppm_cell(a + 1, q < 8 ? fgR : frR, PR[q], r);
+      if (vec) {
+        PL[q] = PL[q] / (T)gface;
+        PR[q] = PR[q] / (T)gface;
+      }
     }
   } else {
 #pragma unroll
@@ -551,7 +566,8 @@ __global__ void LB(256) k_entropy_update(Ctx C, double a, double b, double cc,
 // ---------------------------------------------------------------------------
 // PPM shock flattener (Sec. 4.3; FLASH form with SP0 = 0.75): per cell within
 // one cell of the interior and per active direction d, for gas (pressure
-// (gam-1) u_g, velocity u~^d) and radiation (Ebar/3, u~^d_rad), each pressure
+// (gam-1) u_g, velocity the specific mass flux sqrt(-g) u^d) and radiation
+// (Ebar/3, sqrt(-g) u^d_rad), each pressure
 // raised by w = min(1, 2 tau) times the other, tau = kappa_tot sqrt(g_dd) dx^d:
 //   f = clamp(10 (|dp1|/|dp2| - 0.75), 0, 1) where |dp1| = |p(+1) - p(-1)| >
 //   0.33 min(p(+1), p(-1)) and the flow converges, else 0; then the larger of
@@ -604,8 +620,25 @@ DEV void flatten_at(Ctx C, const double* __restrict__ P, const double* __restric
       pr7[m + 3] = p_r + w * p_g;
       if (m == 0) w0 = w;
       if (m >= -2 && m <= 2) {
-        vg5[m + 2] = P[(2 + d) * C.Ntot + cm];
-        vr5[m + 2] = P[(9 + d) * C.Ntot + cm];
+        if (C.metric == GRRMHD_KERR_SCHILD) {
+          // the specific mass fluxes sqrt(-g) u^d of gas and radiation
+          Metric met;
+          load_metric(C.geo_c, C.npos, pos, met);
+          double ut[3];
+          Vel<double> v;
+#pragma unroll
+          for (int a = 0; a < 3; a++) ut[a] = P[(2 + a) * C.Ntot + cm];
+          make_vel(met, ut, v);
+          vg5[m + 2] = met.gdet * v.ucon[d + 1];
+#pragma unroll
+          for (int a = 0; a < 3; a++) ut[a] = P[(9 + a) * C.Ntot + cm];
+          make_vel(met, ut, v);
+          vr5[m + 2] = met.gdet * v.ucon[d + 1];
+        } else {
+          // flat space: u^d = u~^d, sqrt(-g) = 1
+          vg5[m + 2] = P[(2 + d) * C.Ntot + cm];
+          vr5[m + 2] = P[(9 + d) * C.Ntot + cm];
+        }
       }
     }
     // flat_raw indexes pressures at m +- 2 and velocities at m +- 1 around m
