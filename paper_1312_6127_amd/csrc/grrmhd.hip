@@ -24,6 +24,12 @@ struct grrmhd_grid {
   int dtp = 0;
   int* cnt[2];          // cascade list lengths, alternating (each launch zeroes the other)
   double* flat = nullptr;  // PPM flattener of the step [3][gas, radiation][Ntot]
+  // the implicit kernel's tiles: count, shape, cost keys of the last launch
+  // and the dispatch order of the next one (int [ntiles] each)
+  long ntiles = 0;
+  int tile_i = 0;
+  int* tkeys = nullptr;
+  int* torder = nullptr;
   int cp = 0;
   Work W;               // implicit cascade list (interior indices), records, stats;
                         // W.counter is the list length of the last launch
@@ -234,8 +240,16 @@ extern "C" int grrmhd_init_grid(const grrmhd_params* p, int device, void* hip_st
   // [nd doubles][256 B: dt slot @0, list length @128, stats @192][cascade]
   const size_t flat_bytes =
       (p->recon == GRRMHD_RECON_PPM) ? round256(sizeof(double) * 6 * (size_t)g->C.Ntot) : 0;
+  // wavefront tiles of 16 x 4 cells in (x1, x2); 64 x 1 on one-dimensional grids
+  g->tile_i = (g->C.n[1] > 1) ? GRRMHD_IMPLICIT_TILE_I : 64;
+  {
+    const int tj = 64 / g->tile_i;
+    g->ntiles = (long)((g->C.n[0] + g->tile_i - 1) / g->tile_i) * ((g->C.n[1] + tj - 1) / tj) *
+                g->C.n[2];
+  }
+  const size_t tile_bytes = 2 * round256(sizeof(int) * (size_t)g->ntiles);
   hipError_t e = hipMalloc(&g->geo, nd * sizeof(double) + TAIL_CASCADE + cascade_bytes(nint) +
-                                        flat_bytes);
+                                        flat_bytes + tile_bytes);
   if (e != hipSuccess) {
     delete g;
     return fail(GRRMHD_ENOMEM, std::string("geometry allocation: ") + hipGetErrorString(e));
@@ -250,6 +264,11 @@ extern "C" int grrmhd_init_grid(const grrmhd_params* p, int device, void* hip_st
   g->W.counter_next = nullptr;
   g->W.stats = (unsigned long long*)(tail + 192);
   cascade_layout(tail + TAIL_CASCADE, nint, g->W);
+  {
+    char* tb = tail + TAIL_CASCADE + cascade_bytes(nint) + flat_bytes;
+    g->tkeys = (int*)tb;
+    g->torder = (int*)(tb + round256(sizeof(int) * (size_t)g->ntiles));
+  }
   if (flat_bytes) {
     // zero outside the flattener's range (cells within one of the interior):
     // the staggered field's face states two cells out read it there
@@ -268,6 +287,8 @@ extern "C" int grrmhd_init_grid(const grrmhd_params* p, int device, void* hip_st
                      p->a, p->R0, g->geo, (double*)g->C.geo_f1, (double*)g->C.geo_f2);
   // both list lengths and the lane statistics (bytes 128..223 of the tail)
   hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, g->stream, (int*)(tail + 128), 24);
+  // no costs known yet: the first launch takes the tiles in any order
+  hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, g->stream, g->tkeys, (int)g->ntiles);
   hipLaunchKernelGGL(k_dt_init, dim3(1), dim3(64), 0, g->stream, g->dtslot, 1, 1);
   hipLaunchKernelGGL(k_dt_init, dim3(1), dim3(64), 0, g->stream, g->dtstep[0],
                      2 * GRRMHD_DT_SLOTS, GRRMHD_DT_STRIDE);
@@ -630,19 +651,25 @@ static int launch_implicit(grrmhd_grid* g, const double* Ue, const double* Pg, d
   W.counter = g->cnt[g->cp];
   W.counter_next = g->cnt[g->cp ^ 1];
   const bool timed = g->timing && g->nt < grrmhd_grid::TCAP;
+  // tiles costliest first by the previous launch's trip counts
+  hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(1024), 0, g->stream, g->ntiles,
+                     (const int*)g->tkeys, g->torder);
+  LAUNCHCHK();
   if (timed) HIPCHK(hipEventRecord(g->ev[2 * g->nt], g->stream));
-  // wavefront tiles of 16 x 4 cells in (x1, x2); 64 x 1 on one-dimensional grids
-  const int ti = (g->C.n[1] > 1) ? GRRMHD_IMPLICIT_TILE_I : 64, tj = 64 / ti;
-  const long tiles = (long)((g->C.n[0] + ti - 1) / ti) * ((g->C.n[1] + tj - 1) / tj) * g->C.n[2];
-  hipLaunchKernelGGL(k_implicit, dim3((unsigned)tiles), dim3(64), 0, g->stream, g->C, ti, Ue, Pg,
-                     scale, dt_dev, ca, ce, P, U, it, st, err, W);
+  hipLaunchKernelGGL(k_implicit, dim3((unsigned)g->ntiles), dim3(64), 0, g->stream, g->C,
+                     g->tile_i, Ue, Pg, scale, dt_dev, ca, ce, P, U, it, st, err, W,
+                     (const int*)g->torder, g->tkeys);
   LAUNCHCHK();
   if (timed) {
     HIPCHK(hipEventRecord(g->ev[2 * g->nt + 1], g->stream));
     g->nt++;
   }
-  hipLaunchKernelGGL(k_implicit_list, dim3(list_blocks(n)), dim3(64), 0, g->stream, g->C, Ue, Pg,
-                     scale, dt_dev, ca, ce, P, U, it, st, err, W, Sexp);
+  if (g->C.cascade)
+    hipLaunchKernelGGL(k_implicit_list<true>, dim3(list_blocks(n)), dim3(64), 0, g->stream, g->C,
+                       Ue, Pg, scale, dt_dev, ca, ce, P, U, it, st, err, W, Sexp);
+  else
+    hipLaunchKernelGGL(k_implicit_list<false>, dim3(list_blocks(n)), dim3(64), 0, g->stream, g->C,
+                       Ue, Pg, scale, dt_dev, ca, ce, P, U, it, st, err, W, Sexp);
   LAUNCHCHK();
   g->W.counter = W.counter;
   g->cp ^= 1;

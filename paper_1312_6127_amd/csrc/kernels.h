@@ -1011,8 +1011,9 @@ struct Work {
   RecBuf rec;
 };
 
-// per-wavefront totals of lanes that each ran `trips` trips in lockstep
-DEV void wave_stats(int trips, unsigned long long* stats) {
+// per-wavefront totals of lanes that each ran `trips` trips in lockstep;
+// returns the wavefront's largest count
+DEV int wave_stats(int trips, unsigned long long* stats) {
   int s = trips, mx = trips;
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
@@ -1023,6 +1024,37 @@ DEV void wave_stats(int trips, unsigned long long* stats) {
     atomicAdd(&stats[0], (unsigned long long)s);
     atomicAdd(&stats[1], 64ull * (unsigned long long)mx);
   }
+  return mx;
+}
+
+// Dispatch order of the implicit kernel's tiles: costliest first, by the
+// largest Newton-trip count of each tile's first attempts in the previous
+// launch (keys), one bucket per count up to GRRMHD_ORDER_BUCKETS - 1.  A
+// wavefront costs what its slowest lane costs, and with a few waves per
+// SIMD the launch ends on whichever tiles start last: dispatching the long
+// ones first leaves the short ones to fill the end.  Counting sort in one
+// block (ties in any order; every tile's result is independent of it).
+#define GRRMHD_ORDER_BUCKETS 64
+DEV int order_bucket(int key) { return ::min(::max(key, 0), GRRMHD_ORDER_BUCKETS - 1); }
+
+__global__ void __launch_bounds__(1024) k_tile_order(long ntiles, const int* __restrict__ keys,
+                                                     int* __restrict__ order) {
+  __shared__ int cnt[GRRMHD_ORDER_BUCKETS];
+  for (int b = threadIdx.x; b < GRRMHD_ORDER_BUCKETS; b += blockDim.x) cnt[b] = 0;
+  __syncthreads();
+  for (long t = threadIdx.x; t < ntiles; t += blockDim.x) atomicAdd(&cnt[order_bucket(keys[t])], 1);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int sum = 0;   // exclusive prefix, largest bucket first
+    for (int b = GRRMHD_ORDER_BUCKETS - 1; b >= 0; b--) {
+      const int c = cnt[b];
+      cnt[b] = sum;
+      sum += c;
+    }
+  }
+  __syncthreads();
+  for (long t = threadIdx.x; t < ntiles; t += blockDim.x)
+    order[atomicAdd(&cnt[order_bucket(keys[t])], 1)] = (int)t;
 }
 
 __global__ void k_zero_ints(int* p, int k) {
@@ -1074,13 +1106,16 @@ __global__ void LBI k_implicit(Ctx C, int ti, const double* __restrict__ Uexp, c
                                   const double* __restrict__ chi_abs,
                                   const double* __restrict__ chi_es, double* P,
                                   double* __restrict__ U, int* __restrict__ iters,
-                                  int* __restrict__ status, double* __restrict__ err, Work W) {
+                                  int* __restrict__ status, double* __restrict__ err, Work W,
+                                  const int* __restrict__ order, int* __restrict__ keys) {
   bool need = false, extreme = false;
   Best b;
   int it = 0, trips = 0;
   int i = 0, j = 0, k = 0;
   long t = 0;   // the cell's index in the interior enumeration (x1 fastest)
-  if (tile_cell(C, ti, xcd_block(blockIdx.x, gridDim.x), threadIdx.x, i, j, k)) {
+  // the tile: in the cost order of the previous launch when given
+  const long tile = order ? (long)order[blockIdx.x] : xcd_block(blockIdx.x, gridDim.x);
+  if (tile_cell(C, ti, tile, threadIdx.x, i, j, k)) {
     t = (i - C.ng[0]) + (long)C.n[0] * ((j - C.ng[1]) + (long)C.n[1] * (k - C.ng[2]));
     const long c = cell_index(C, i, j, k);
     Metric m;
@@ -1098,12 +1133,16 @@ __global__ void LBI k_implicit(Ctx C, int ti, const double* __restrict__ Uexp, c
     else
       need = true;
   }
-  wave_stats(trips, W.stats);
+  const int mx = wave_stats(trips, W.stats);
+  if (keys && threadIdx.x == 0) keys[tile] = mx;
   to_cascade(need, extreme, (int)t, b, it, W);
 }
 
 // Rest of the cascade over the work list; grid-stride over a count kept on
 // the device.
+// FULL: the paper's full cascade (params.cascade = 1), a separate
+// instantiation so the normal cascade keeps its smaller register footprint
+template <bool FULL>
 __global__ void LB(64) k_implicit_list(Ctx C, const double* __restrict__ Uexp,
                                        const double* Pguess, double dt_scale,
                                        const double* __restrict__ dt_dev,
@@ -1131,7 +1170,7 @@ __global__ void LB(64) k_implicit_list(Ctx C, const double* __restrict__ Uexp,
       Pg[q] = Pguess[q * C.Ntot + c];
     }
     CellOut o;
-    if (C.cascade)
+    if constexpr (FULL)
       implicit_cell_full(m, make_phys(C), make_opts(C), Ui, Sexp ? Sexp[c] : NAN, Pg,
                          dt_scale * (*dt_dev), chi_abs[c], chi_es[c], o, &W.rec, w, 1);
     else
