@@ -301,6 +301,16 @@ static void fluxes_core(const orc_params *p, const double *P, const double *chi_
         for (int i = lo[0]; i <= hi[0]; i++) {
           const long c = IDX(p, i, j, k);
           const long m2 = c - 2 * st, m1 = c - st, p1 = c + st;
+          /* staggered field: faces two cells beyond the interior across d
+           * serve only the corner interpolation of the face velocities */
+          int outer = 0;
+          {
+            const int idx[3] = {i, j, k};
+            for (int e = 0; e < 3; e++)
+              if (Bf && e != d && p->n[e] > 1 &&
+                  (idx[e] < orc_ng(p, e) - 1 || idx[e] > orc_ng(p, e) + p->n[e]))
+                outer = 1;
+          }
           double PL[12], PR[12];
           double x1, x2;
           orc_face_x(p, d + 1, i, j, &x1, &x2);
@@ -354,7 +364,7 @@ static void fluxes_core(const orc_params *p, const double *P, const double *chi_
           /* eq. hll: v_min = -min(0, v-_L, v-_R), v_max = max(0, v+_L, v+_R) */
           const double gmin = -fmin(0.0, fmin(vgL[0], vgR[0])), gmax = fmax(0.0, fmax(vgL[1], vgR[1]));
           const double rmin = -fmin(0.0, fmin(vrL[0], vrR[0])), rmax = fmax(0.0, fmax(vrL[1], vrR[1]));
-          for (int q = 0; q < 12; q++) {
+          for (int q = 0; q < 12 && !outer; q++) {
             const double vmin = q < 8 ? gmin : rmin, vmax = q < 8 ? gmax : rmax;
             double f;
             if (p->flux == ORC_FLUX_HLL) {
@@ -368,8 +378,10 @@ static void fluxes_core(const orc_params *p, const double *P, const double *chi_
             }
             Fd[q * N + c] = f;
           }
-          Fd[(5 + d) * N + c] = 0.0; /* induction flux of the normal component vanishes */
-          vchar[(long)d * N + c] = fmax(fmax(gmin, gmax), fmax(rmin, rmax));
+          if (!outer) {
+            Fd[(5 + d) * N + c] = 0.0; /* induction flux of the normal component vanishes */
+            vchar[(long)d * N + c] = fmax(fmax(gmin, gmax), fmax(rmin, rmax));
+          }
           if (Bf) {
             for (int sd = 0; sd < 2; sd++) {
               double ucon[4];
@@ -377,10 +389,12 @@ static void fluxes_core(const orc_params *p, const double *P, const double *chi_
               for (int m = 0; m < 3; m++)
                 VF[((long)((2 * d + sd) * 3) + m) * N + c] = ucon[m + 1] / ucon[0];
             }
-            SP[(long)(2 * d) * N + c] = gmin;
-            SP[(long)(2 * d + 1) * N + c] = gmax;
+            if (!outer) {
+              SP[(long)(2 * d) * N + c] = gmin;
+              SP[(long)(2 * d + 1) * N + c] = gmax;
+            }
           }
-          if (Fs) {
+          if (Fs && !outer) {
             /* the entropy tracer's flux, with the gas speeds */
             double UsL, UsR, FsL, FsR, f;
             entropy_cons_flux(p, &g, PL, d + 1, &UsL, &FsL);

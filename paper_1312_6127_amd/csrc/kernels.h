@@ -317,6 +317,59 @@ DEV void entropy_face(const Ctx& C, const MetricT<T>& m, const T* P, T& Us, T& F
 // velocities v^m = u^m/u^t of each state and the gas v_min, v_max of eq. hll
 // go to VF [(2 (D-1) + side) 3 + m][Ntot] and SP [2 (D-1) + {0, 1}][Ntot]
 // for the corner EMFs.
+// The face velocity states alone (the staggered field's outer faces): u~^1..3
+// reconstructed exactly as in flux_at, v^m = u^m/u^t from the face metric.
+template <int D, class T>
+DEV void stag_face_velocities(const Ctx& C, const double* __restrict__ P,
+                              const double* __restrict__ fl, int i, int j, long c, long st,
+                              double* __restrict__ VF) {
+  T uL[3], uR[3];
+  if (C.recon == GRRMHD_RECON_PPM) {
+    const double* fg = fl + (long)(2 * (D - 1)) * C.Ntot;
+    const T fgL = (T)fg[c - st], fgR = (T)fg[c];
+    const bool wgt = (D == 1) && C.metric == GRRMHD_KERR_SCHILD;
+    double gc[6] = {1.0, 1.0, 1.0, 1.0, 1.0, 1.0}, gface = 1.0;
+    if (wgt) {
+#pragma unroll
+      for (int m = 0; m < 6; m++) gc[m] = C.geo_c[GE_GDET * C.npos + (i + m - 3) + C.N[0] * j];
+      gface = C.geo_f1[GE_GDET * C.npos + i + C.N[0] * j];
+    }
+#pragma unroll
+    for (int q = 0; q < 3; q++) {
+      const double* p = P + (2 + q) * C.Ntot;
+      T a[6];
+#pragma unroll
+      for (int m = 0; m < 6; m++) a[m] = (T)(wgt ? p[c + (m - 3) * st] * gc[m] : p[c + (m - 3) * st]);
+      T l, r;
+      ppm_cell(a, fgL, l, uL[q]);
+      ppm_cell(a + 1, fgR, uR[q], r);
+      if (wgt) {
+        uL[q] = uL[q] / (T)gface;
+        uR[q] = uR[q] / (T)gface;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < 3; q++) {
+      const double* p = P + (2 + q) * C.Ntot;
+      const T a = (T)p[c - 2 * st], b = (T)p[c - st], e = (T)p[c], f = (T)p[c + st];
+      uL[q] = b + T(0.5) * mc_slope(b - a, e - b);
+      uR[q] = e - T(0.5) * mc_slope(e - b, f - e);
+    }
+  }
+  MetricT<T> m;
+  const double* tab = (D == 1) ? C.geo_f1 : ((D == 2) ? C.geo_f2 : C.geo_c);
+  load_metric(tab, C.npos, i + C.N[0] * j, m);
+#pragma unroll
+  for (int sd = 0; sd < 2; sd++) {
+    Vel<T> v;
+    make_vel(m, sd ? uR : uL, v);
+#pragma unroll
+    for (int q = 0; q < 3; q++)
+      VF[((long)((2 * (D - 1) + sd) * 3) + q) * C.Ntot + c] = (double)(v.ucon[q + 1] / v.ucon[0]);
+  }
+}
+
 template <int D, class T, bool ENTF = false, bool STAG = false>
 DEV void flux_at(Ctx C, FaceRange R, const double* __restrict__ P,
                                const double* __restrict__ chi_abs,
@@ -332,6 +385,20 @@ DEV void flux_at(Ctx C, FaceRange R, const double* __restrict__ P,
   const int k = R.lo[2] + t2 / R.cnt[1];
   const long c = cell_index(C, i, j, k);
   const long st = C.st[D - 1];
+  if constexpr (STAG) {
+    // faces two cells beyond the interior across D feed only the corner
+    // interpolation of the velocities: reconstruct u~ and store v there
+    const int idx[3] = {i, j, k};
+    bool outer = false;
+#pragma unroll
+    for (int e = 0; e < 3; e++)
+      if (e != D - 1 && C.n[e] > 1 && (idx[e] < C.ng[e] - 1 || idx[e] > C.ng[e] + C.n[e]))
+        outer = true;
+    if (outer) {
+      stag_face_velocities<D, T>(C, P, fl, i, j, c, st, VF);
+      return;
+    }
+  }
   T PL[12], PR[12];
   if (C.recon == GRRMHD_RECON_PPM) {
     // left state: right value of cell c - st; right state: left value of c
