@@ -652,7 +652,7 @@ static int launch_implicit(grrmhd_grid* g, const double* Ue, const double* Pg, d
   W.counter_next = g->cnt[g->cp ^ 1];
   const bool timed = g->timing && g->nt < grrmhd_grid::TCAP;
   // tiles costliest first by the previous launch's trip counts
-  hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(1024), 0, g->stream, g->ntiles,
+  hipLaunchKernelGGL(k_tile_order, dim3(9), dim3(1024), 0, g->stream, g->ntiles,
                      (const int*)g->tkeys, g->torder);
   LAUNCHCHK();
   if (timed) HIPCHK(hipEventRecord(g->ev[2 * g->nt], g->stream));

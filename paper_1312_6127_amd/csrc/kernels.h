@@ -1099,17 +1099,24 @@ DEV int wave_stats(int trips, unsigned long long* stats) {
 // launch (keys), one bucket per count up to GRRMHD_ORDER_BUCKETS - 1.  A
 // wavefront costs what its slowest lane costs, and with a few waves per
 // SIMD the launch ends on whichever tiles start last: dispatching the long
-// ones first leaves the short ones to fill the end.  Counting sort in one
-// block (ties in any order; every tile's result is independent of it).
+// ones first leaves the short ones to fill the end.  The sort keeps the
+// XCD-aware split (xcd_block: XCD x works through the x-th eighth of the
+// tiles, whose neighbours share its L2): each eighth is sorted apart, one
+// block each (a ninth takes the remainder tiles), by counting sort (ties in
+// any order; every tile's result is independent of it).  order[] maps each
+// eighth onto itself.
 #define GRRMHD_ORDER_BUCKETS 64
 DEV int order_bucket(int key) { return ::min(::max(key, 0), GRRMHD_ORDER_BUCKETS - 1); }
 
 __global__ void __launch_bounds__(1024) k_tile_order(long ntiles, const int* __restrict__ keys,
                                                      int* __restrict__ order) {
   __shared__ int cnt[GRRMHD_ORDER_BUCKETS];
+  const long seg = ntiles / 8;
+  const long lo = (blockIdx.x < 8) ? (long)blockIdx.x * seg : 8 * seg;
+  const long hi = (blockIdx.x < 8) ? lo + seg : ntiles;
   for (int b = threadIdx.x; b < GRRMHD_ORDER_BUCKETS; b += blockDim.x) cnt[b] = 0;
   __syncthreads();
-  for (long t = threadIdx.x; t < ntiles; t += blockDim.x) atomicAdd(&cnt[order_bucket(keys[t])], 1);
+  for (long t = lo + threadIdx.x; t < hi; t += blockDim.x) atomicAdd(&cnt[order_bucket(keys[t])], 1);
   __syncthreads();
   if (threadIdx.x == 0) {
     int sum = 0;   // exclusive prefix, largest bucket first
@@ -1120,8 +1127,8 @@ __global__ void __launch_bounds__(1024) k_tile_order(long ntiles, const int* __r
     }
   }
   __syncthreads();
-  for (long t = threadIdx.x; t < ntiles; t += blockDim.x)
-    order[atomicAdd(&cnt[order_bucket(keys[t])], 1)] = (int)t;
+  for (long t = lo + threadIdx.x; t < hi; t += blockDim.x)
+    order[lo + atomicAdd(&cnt[order_bucket(keys[t])], 1)] = (int)t;
 }
 
 __global__ void k_zero_ints(int* p, int k) {
@@ -1180,8 +1187,10 @@ __global__ void LBI k_implicit(Ctx C, int ti, const double* __restrict__ Uexp, c
   int it = 0, trips = 0;
   int i = 0, j = 0, k = 0;
   long t = 0;   // the cell's index in the interior enumeration (x1 fastest)
-  // the tile: in the cost order of the previous launch when given
-  const long tile = order ? (long)order[blockIdx.x] : xcd_block(blockIdx.x, gridDim.x);
+  // the tile: XCD-aware, and within each XCD's eighth in the cost order of
+  // the previous launch when given
+  const long xb = xcd_block(blockIdx.x, gridDim.x);
+  const long tile = order ? (long)order[xb] : xb;
   if (tile_cell(C, ti, tile, threadIdx.x, i, j, k)) {
     t = (i - C.ng[0]) + (long)C.n[0] * ((j - C.ng[1]) + (long)C.n[1] * (k - C.ng[2]));
     const long c = cell_index(C, i, j, k);
