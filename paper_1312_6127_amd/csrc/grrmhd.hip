@@ -238,8 +238,11 @@ extern "C" int grrmhd_init_grid(const grrmhd_params* p, int device, void* hip_st
   const size_t nd = tab * (GE_NCENTER + 2 * GE_NFACE);
   const size_t nint = (size_t)g->C.n[0] * g->C.n[1] * g->C.n[2];
   // [nd doubles][256 B: dt slot @0, list length @128, stats @192][cascade]
+  // PPM: the flattener [3][gas, radiation][Ntot], and on Kerr-Schild the
+  // per-cell mass fluxes it reads [6][Ntot]
+  const size_t flat_n = (p->metric == GRRMHD_KERR_SCHILD) ? 12 : 6;
   const size_t flat_bytes =
-      (p->recon == GRRMHD_RECON_PPM) ? round256(sizeof(double) * 6 * (size_t)g->C.Ntot) : 0;
+      (p->recon == GRRMHD_RECON_PPM) ? round256(sizeof(double) * flat_n * (size_t)g->C.Ntot) : 0;
   // wavefront tiles of 16 x 4 cells in (x1, x2); 64 x 1 on one-dimensional grids
   g->tile_i = (g->C.n[1] > 1) ? GRRMHD_IMPLICIT_TILE_I : 64;
   {
@@ -503,10 +506,16 @@ static int launch_fluxes(grrmhd_grid* g, const double* P, const double* ca, cons
                          double* SP = nullptr) {
   const Ctx& C = g->C;
   if (C.recon == GRRMHD_RECON_PPM) {
+    double* mf = nullptr;
+    if (C.metric == GRRMHD_KERR_SCHILD) {
+      mf = g->flat + 6 * (size_t)C.Ntot;
+      hipLaunchKernelGGL(k_mass_flux, dim3(nblocks(C.Ntot, 256)), dim3(256), 0, g->stream, C, P, mf);
+      LAUNCHCHK();
+    }
     long nb = 1;
     for (int e = 0; e < 3; e++) nb *= C.n[e] > 1 ? C.n[e] + 2 : 1;
     hipLaunchKernelGGL(k_flatten, dim3(nblocks(nb, 256)), dim3(256), 0, g->stream, C, P, ca, ce,
-                       g->flat, keep_flat);
+                       g->flat, keep_flat, (const double*)mf);
     LAUNCHCHK();
   }
   // faces of every direction, FP64 part and FP32 part (split at mixed_i)

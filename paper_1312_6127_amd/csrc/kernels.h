@@ -655,8 +655,32 @@ DEV double flat_tilde(const double* pp, const double* v) {
   return ::fmax(f0, flat_raw(pp, v, up));
 }
 
+// The flattener's velocities on a Kerr-Schild grid, once per cell: the
+// specific mass fluxes sqrt(-g) u^d of the gas (mf[d]) and the radiation
+// (mf[3 + d]), d = 0..2, from the cell's own metric.
+__global__ void LB(256) k_mass_flux(Ctx C, const double* __restrict__ P, double* __restrict__ mf) {
+  const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= C.Ntot) return;
+  Metric met;
+  load_metric(C.geo_c, C.npos, (int)(c % C.npos), met);
+  double ut[3];
+  Vel<double> v;
+#pragma unroll
+  for (int a = 0; a < 3; a++) ut[a] = P[(2 + a) * C.Ntot + c];
+  make_vel(met, ut, v);
+#pragma unroll
+  for (int d = 0; d < 3; d++) mf[(long)d * C.Ntot + c] = met.gdet * v.ucon[d + 1];
+#pragma unroll
+  for (int a = 0; a < 3; a++) ut[a] = P[(9 + a) * C.Ntot + c];
+  make_vel(met, ut, v);
+#pragma unroll
+  for (int d = 0; d < 3; d++) mf[(long)(3 + d) * C.Ntot + c] = met.gdet * v.ucon[d + 1];
+}
+
+// mf: the mass fluxes of k_mass_flux (Kerr-Schild), null in flat space
 DEV void flatten_at(Ctx C, const double* __restrict__ P, const double* __restrict__ chi_abs,
-                    const double* __restrict__ chi_es, double* __restrict__ fl, int keep, long t) {
+                    const double* __restrict__ chi_es, double* __restrict__ fl, int keep, long t,
+                    const double* __restrict__ mf) {
   int lo[3], cnt[3];
 #pragma unroll
   for (int e = 0; e < 3; e++) {
@@ -687,20 +711,10 @@ DEV void flatten_at(Ctx C, const double* __restrict__ P, const double* __restric
       pr7[m + 3] = p_r + w * p_g;
       if (m == 0) w0 = w;
       if (m >= -2 && m <= 2) {
-        if (C.metric == GRRMHD_KERR_SCHILD) {
+        if (mf) {
           // the specific mass fluxes sqrt(-g) u^d of gas and radiation
-          Metric met;
-          load_metric(C.geo_c, C.npos, pos, met);
-          double ut[3];
-          Vel<double> v;
-#pragma unroll
-          for (int a = 0; a < 3; a++) ut[a] = P[(2 + a) * C.Ntot + cm];
-          make_vel(met, ut, v);
-          vg5[m + 2] = met.gdet * v.ucon[d + 1];
-#pragma unroll
-          for (int a = 0; a < 3; a++) ut[a] = P[(9 + a) * C.Ntot + cm];
-          make_vel(met, ut, v);
-          vr5[m + 2] = met.gdet * v.ucon[d + 1];
+          vg5[m + 2] = mf[(long)d * C.Ntot + cm];
+          vr5[m + 2] = mf[(long)(3 + d) * C.Ntot + cm];
         } else {
           // flat space: u^d = u~^d, sqrt(-g) = 1
           vg5[m + 2] = P[(2 + d) * C.Ntot + cm];
@@ -724,8 +738,8 @@ DEV void flatten_at(Ctx C, const double* __restrict__ P, const double* __restric
 __global__ void LB(256) k_flatten(Ctx C, const double* __restrict__ P,
                                   const double* __restrict__ chi_abs,
                                   const double* __restrict__ chi_es, double* __restrict__ fl,
-                                  int keep) {
-  flatten_at(C, P, chi_abs, chi_es, fl, keep, (long)blockIdx.x * blockDim.x + threadIdx.x);
+                                  int keep, const double* __restrict__ mf) {
+  flatten_at(C, P, chi_abs, chi_es, fl, keep, (long)blockIdx.x * blockDim.x + threadIdx.x, mf);
 }
 
 // ---------------------------------------------------------------------------
