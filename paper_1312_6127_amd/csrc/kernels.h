@@ -317,6 +317,76 @@ DEV void entropy_face(const Ctx& C, const MetricT<T>& m, const T* P, T& Us, T& F
 // velocities v^m = u^m/u^t of each state and the gas v_min, v_max of eq. hll
 // go to VF [(2 (D-1) + side) 3 + m][Ntot] and SP [2 (D-1) + {0, 1}][Ntot]
 // for the corner EMFs.
+// Steps 5-7 at one face from its reconstructed left and right primitives
+// (the face's own normal field replaced with the staggered field's): face
+// states, wave speeds, HLL / LAXF, the stores.  Shared by flux_at (stencil
+// from global memory) and the LDS-staged flux kernel.
+template <int D, class T, bool ENTF = false, bool STAG = false>
+DEV void flux_states(const Ctx& C, int i, int j, long c, long st, T PL[12], T PR[12],
+                     const double* __restrict__ chi_abs, const double* __restrict__ chi_es,
+                     double* __restrict__ F, double* __restrict__ vchar,
+                     double* __restrict__ Fs = nullptr, const double* __restrict__ Bf = nullptr,
+                     double* __restrict__ VF = nullptr, double* __restrict__ SP = nullptr) {
+  MetricT<T> m;
+  const double* tab = (D == 1) ? C.geo_f1 : ((D == 2) ? C.geo_f2 : C.geo_c);
+  load_metric(tab, C.npos, i + C.N[0] * j, m);
+  if constexpr (STAG) {
+    // the face's own normal field (zero where sqrt(-g) vanishes, the axis)
+    const double gd = tab[GE_GDET * C.npos + i + C.N[0] * j];
+    const T bn = (T)(gd > 0.0 ? Bf[(long)(D - 1) * C.Ntot + c] / gd : 0.0);
+    PL[4 + D] = bn;
+    PR[4 + D] = bn;
+  }
+  FaceState<T> L, Rs;
+  face_state(C, m, D, PL, (T)(chi_abs[c - st] + chi_es[c - st]), L);
+  face_state(C, m, D, PR, (T)(chi_abs[c] + chi_es[c]), Rs);
+  // eq. hll: v_min = -min(0, v-_L, v-_R), v_max = max(0, v+_L, v+_R)
+  const T zero = T(0.0);
+  const T gmin = -fmin(zero, fmin(L.gm, Rs.gm)), gmax = fmax(zero, fmax(L.gp, Rs.gp));
+  const T rmin = -fmin(zero, fmin(L.rm, Rs.rm)), rmax = fmax(zero, fmax(L.rp, Rs.rp));
+#pragma unroll
+  for (int q = 0; q < 12; q++) {
+    const T vmin = q < 8 ? gmin : rmin, vmax = q < 8 ? gmax : rmax;
+    T f;
+    if (C.flux == GRRMHD_FLUX_HLL) {
+      const T den = vmin + vmax;
+      f = (den > zero) ? (vmin * Rs.F[q] + vmax * L.F[q] - vmin * vmax * (Rs.U[q] - L.U[q])) / den
+                       : T(0.5) * (L.F[q] + Rs.F[q]);
+    } else {
+      f = T(0.5) * (Rs.F[q] + L.F[q] - fmax(vmin, vmax) * (Rs.U[q] - L.U[q]));
+    }
+    if (q == 4 + D) f = zero;   // normal field component has no induction flux
+    F[q * C.Ntot + c] = (double)f;
+  }
+  vchar[c] = (double)fmax(fmax(gmin, gmax), fmax(rmin, rmax));
+  if constexpr (STAG) {
+#pragma unroll
+    for (int sd = 0; sd < 2; sd++) {
+      Vel<T> v;
+      make_vel(m, (sd ? PR : PL) + 2, v);
+#pragma unroll
+      for (int q = 0; q < 3; q++)
+        VF[((long)((2 * (D - 1) + sd) * 3) + q) * C.Ntot + c] = (double)(v.ucon[q + 1] / v.ucon[0]);
+    }
+    SP[(long)(2 * (D - 1)) * C.Ntot + c] = (double)gmin;
+    SP[(long)(2 * (D - 1) + 1) * C.Ntot + c] = (double)gmax;
+  }
+  if constexpr (ENTF) {
+    // the entropy tracer's flux, with the gas speeds
+    T UsL, FsL, UsR, FsR, f;
+    entropy_face<D, T>(C, m, PL, UsL, FsL);
+    entropy_face<D, T>(C, m, PR, UsR, FsR);
+    if (C.flux == GRRMHD_FLUX_HLL) {
+      const T den = gmin + gmax;
+      f = (den > zero) ? (gmin * FsR + gmax * FsL - gmin * gmax * (UsR - UsL)) / den
+                       : T(0.5) * (FsL + FsR);
+    } else {
+      f = T(0.5) * (FsR + FsL - fmax(gmin, gmax) * (UsR - UsL));
+    }
+    Fs[c] = (double)f;
+  }
+}
+
 // The face velocity states alone (the staggered field's outer faces): u~^1..3
 // reconstructed exactly as in flux_at, v^m = u^m/u^t from the face metric.
 template <int D, class T>
@@ -439,64 +509,7 @@ DEV void flux_at(Ctx C, FaceRange R, const double* __restrict__ P,
       PR[q] = e - T(0.5) * mc_slope(e - b, f - e);
     }
   }
-  MetricT<T> m;
-  const double* tab = (D == 1) ? C.geo_f1 : ((D == 2) ? C.geo_f2 : C.geo_c);
-  load_metric(tab, C.npos, i + C.N[0] * j, m);
-  if constexpr (STAG) {
-    // the face's own normal field (zero where sqrt(-g) vanishes, the axis)
-    const double gd = tab[GE_GDET * C.npos + i + C.N[0] * j];
-    const T bn = (T)(gd > 0.0 ? Bf[(long)(D - 1) * C.Ntot + c] / gd : 0.0);
-    PL[4 + D] = bn;
-    PR[4 + D] = bn;
-  }
-  FaceState<T> L, Rs;
-  face_state(C, m, D, PL, (T)(chi_abs[c - st] + chi_es[c - st]), L);
-  face_state(C, m, D, PR, (T)(chi_abs[c] + chi_es[c]), Rs);
-  // eq. hll: v_min = -min(0, v-_L, v-_R), v_max = max(0, v+_L, v+_R)
-  const T zero = T(0.0);
-  const T gmin = -fmin(zero, fmin(L.gm, Rs.gm)), gmax = fmax(zero, fmax(L.gp, Rs.gp));
-  const T rmin = -fmin(zero, fmin(L.rm, Rs.rm)), rmax = fmax(zero, fmax(L.rp, Rs.rp));
-#pragma unroll
-  for (int q = 0; q < 12; q++) {
-    const T vmin = q < 8 ? gmin : rmin, vmax = q < 8 ? gmax : rmax;
-    T f;
-    if (C.flux == GRRMHD_FLUX_HLL) {
-      const T den = vmin + vmax;
-      f = (den > zero) ? (vmin * Rs.F[q] + vmax * L.F[q] - vmin * vmax * (Rs.U[q] - L.U[q])) / den
-                       : T(0.5) * (L.F[q] + Rs.F[q]);
-    } else {
-      f = T(0.5) * (Rs.F[q] + L.F[q] - fmax(vmin, vmax) * (Rs.U[q] - L.U[q]));
-    }
-    if (q == 4 + D) f = zero;   // normal field component has no induction flux
-    F[q * C.Ntot + c] = (double)f;
-  }
-  vchar[c] = (double)fmax(fmax(gmin, gmax), fmax(rmin, rmax));
-  if constexpr (STAG) {
-#pragma unroll
-    for (int sd = 0; sd < 2; sd++) {
-      Vel<T> v;
-      make_vel(m, (sd ? PR : PL) + 2, v);
-#pragma unroll
-      for (int q = 0; q < 3; q++)
-        VF[((long)((2 * (D - 1) + sd) * 3) + q) * C.Ntot + c] = (double)(v.ucon[q + 1] / v.ucon[0]);
-    }
-    SP[(long)(2 * (D - 1)) * C.Ntot + c] = (double)gmin;
-    SP[(long)(2 * (D - 1) + 1) * C.Ntot + c] = (double)gmax;
-  }
-  if constexpr (ENTF) {
-    // the entropy tracer's flux, with the gas speeds
-    T UsL, FsL, UsR, FsR, f;
-    entropy_face<D, T>(C, m, PL, UsL, FsL);
-    entropy_face<D, T>(C, m, PR, UsR, FsR);
-    if (C.flux == GRRMHD_FLUX_HLL) {
-      const T den = gmin + gmax;
-      f = (den > zero) ? (gmin * FsR + gmax * FsL - gmin * gmax * (UsR - UsL)) / den
-                       : T(0.5) * (FsL + FsR);
-    } else {
-      f = T(0.5) * (FsR + FsL - fmax(gmin, gmax) * (UsR - UsL));
-    }
-    Fs[c] = (double)f;
-  }
+  flux_states<D, T, ENTF, STAG>(C, i, j, c, st, PL, PR, chi_abs, chi_es, F, vchar, Fs, Bf, VF, SP);
 }
 
 
