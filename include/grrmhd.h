@@ -255,7 +255,8 @@ int grrmhd_fixup(grrmhd_grid *g, double *P, double *U, int *status, double *scra
  * computed from the wave speeds of P^n and written.  status/iters [N]
  * (nullable): OR of status bits / sum of Newton steps over the stages.
  * workspace: device buffer of grrmhd_workspace_bytes() (which depends on
- * the scheme). */
+ * the scheme).  EINVAL on a staggered-field grid (grrmhd_step_staggered
+ * steps those), for NULL arrays or a small or misaligned workspace. */
 int grrmhd_step(grrmhd_grid *g, double *P, double *U, const double *chi_abs,
                 const double *chi_es, double *dt_dev, int dt_fixed, int *status, int *iters,
                 void *workspace, size_t ws_bytes);
@@ -323,9 +324,10 @@ int grrmhd_step_staggered(grrmhd_grid *g, double *P, double *U, double *Bf,
  * its result (the MHD block by the implicit-function theorem, one
  * transposed 8x8 solve per cell; the radiation block through the limited
  * inversion itself; where the MHD inversion failed, its guess, the stage
- * input, takes the cotangent).  MC reconstruction only (EINVAL on a PPM
- * grid, also for grrmhd_explicit_vjp).  The workspace size depends on the
- * scheme.  P_n [12][N] (interior read; not modified), gU_next
+ * input, takes the cotangent).  MC reconstruction, the normal cascade
+ * (cascade = 0) and the flux-CT field only (EINVAL on a PPM, full-cascade or
+ * staggered-field grid, also for grrmhd_explicit_vjp).  The workspace
+ * size depends on the scheme.  P_n [12][N] (interior read; not modified), gU_next
  * [12][N] (interior read), gP_n [12][N] out (ghosts zero); g_chi (nullable)
  * [2][N] out: dL/dchi_abs, dL/dchi_es at every allocated cell (the per-mass
  * opacities enter the implicit residual through kappa = chi rho0 and the
