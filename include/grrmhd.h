@@ -324,10 +324,15 @@ int grrmhd_step_staggered(grrmhd_grid *g, double *P, double *U, double *Bf,
  * its result (the MHD block by the implicit-function theorem, one
  * transposed 8x8 solve per cell; the radiation block through the limited
  * inversion itself; where the MHD inversion failed, its guess, the stage
- * input, takes the cotangent).  MC reconstruction, the normal cascade
- * (cascade = 0) and the flux-CT field only (EINVAL on a PPM, full-cascade or
- * staggered-field grid, also for grrmhd_explicit_vjp).  The workspace
- * size depends on the scheme.  P_n [12][N] (interior read; not modified), gU_next
+ * input, takes the cotangent).  MC or PPM reconstruction (Sec. 4.3): with
+ * PPM the face states' Jacobian covers the six-cell stencil and the shock
+ * flattener of the two face cells, and the flattener itself (the largest
+ * over the step's flux evaluations) is differentiated at the evaluation
+ * that gave it, inside its ramp through the pressures, densities and
+ * opacities of its seven cells.  The normal cascade (cascade = 0) and the
+ * flux-CT field only (EINVAL on a full-cascade or staggered-field grid;
+ * grrmhd_explicit_vjp also rejects a staggered-field grid).  The workspace
+ * size depends on the scheme and the reconstruction.  P_n [12][N] (interior read; not modified), gU_next
  * [12][N] (interior read), gP_n [12][N] out (ghosts zero); g_chi (nullable)
  * [2][N] out: dL/dchi_abs, dL/dchi_es at every allocated cell (the per-mass
  * opacities enter the implicit residual through kappa = chi rho0 and the
@@ -368,8 +373,11 @@ int grrmhd_step_adjoint_saved(grrmhd_grid *g, const double *chi_abs, const doubl
  *                        three momentum equations with u_g fixed;
  *  grrmhd_explicit_vjp   of grrmhd_fluxes followed by grrmhd_explicit_update
  *                        with stage coefficient c on dt, with respect to the
- *                        ghost-filled P: gP at every allocated cell;
- *                        workspace grrmhd_explicit_vjp_workspace_bytes();
+ *                        ghost-filled P: gP at every allocated cell (PPM:
+ *                        the flattener is P's own, as at a step's first
+ *                        flux evaluation; the call overwrites the grid's
+ *                        flattener buffer); workspace
+ *                        grrmhd_explicit_vjp_workspace_bytes();
  *  grrmhd_bc_vjp         of grrmhd_apply_bc, in place (ghost entries folded
  *                        into their source cells and cleared);
  *  grrmhd_fixup_vjp      of grrmhd_fixup (Sec. 4.11) at its result (P,

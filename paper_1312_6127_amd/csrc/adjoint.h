@@ -11,8 +11,14 @@
 //                    parts exact, the geometric source S by its local
 //                    Jacobian;
 //   fluxes           corner EMFs (linear), then per face the Jacobian of the
-//                    Riemann flux with respect to its four stencil cells
-//                    (MC reconstruction, face states, HLL / LAXF);
+//                    Riemann flux with respect to its stencil cells (four
+//                    for MC, six for PPM) and, for PPM, to the flattener of
+//                    its two cells (face states, HLL / LAXF);
+//   PPM flattener    the flattener a stage read is the largest over the
+//                    step's sub-steps so far: its cotangent goes to the
+//                    sub-step whose value it was, and there through the
+//                    flattener's pressures and weights to the primitives
+//                    and opacities of its seven-cell stencil;
 //   ghost cells      the transpose of the boundary copies (ghost cotangents
 //                    folded into their source cells, dimensions in reverse).
 // Local Jacobians come from Dual<4> passes of the same templated physics as
@@ -611,10 +617,14 @@ DEV void adj_face_side(const Ctx& C, const Metric& m, int D, const double PLR[24
 
 // ---------------------------------------------------------------------------
 // Faces normal to D: the cotangent of the face flux, then its Jacobian with
-// respect to the four stencil cells c-2s, c-s, c, c+s (s the stride along
-// D); the 48 products go to G[(slot*12 + q)][face].
+// respect to the stencil cells c + (m - NSL/2) s, m = 0..NSL-1 (s the stride
+// along D; NSL = 4 for MC, 6 for PPM); the products go to
+// G[(m*12 + q)][face].  PPM also reads the flattener fl of the face's two
+// cells (this sub-step's, as the forward read it); the face's products with
+// those four values (gas and radiation of the left cell, then of the right)
+// go to GF[4][face].
 // ---------------------------------------------------------------------------
-template <int D>
+template <int D, bool PPM>
 DEV void adj_flux_at(Ctx C, FaceRange R, double scale,
                                                  const double* __restrict__ dt_dev,
                                                  const double* __restrict__ P,
@@ -623,7 +633,8 @@ DEV void adj_flux_at(Ctx C, FaceRange R, double scale,
                                                  const double* __restrict__ lamUe,
                                                  const double* __restrict__ lamE,
                                                  double* __restrict__ G, double* __restrict__ Gx,
-                                                 long t) {
+                                                 const double* __restrict__ fl,
+                                                 double* __restrict__ GF, long t) {
   if (t >= R.total) return;
   const int i = R.lo[0] + t % R.cnt[0];
   const long t2 = t / R.cnt[0];
@@ -654,13 +665,44 @@ DEV void adj_flux_at(Ctx C, FaceRange R, double scale,
       lF[q] = direct;
     }
   }
+  // PPM: the flattener of the left and right cells (gas, radiation), and on
+  // Kerr-Schild along r the sqrt(-g) weights of the vector primitives
+  double fgL = 0.0, frL = 0.0, fgR = 0.0, frR = 0.0, gc[6] = {1.0, 1.0, 1.0, 1.0, 1.0, 1.0};
+  double gface = 1.0;
+  const bool wgt = PPM && (D == 1) && C.metric == GRRMHD_KERR_SCHILD;
+  if (PPM) {
+    const double* fg = fl + (long)(2 * d) * C.Ntot;
+    const double* fr = fg + C.Ntot;
+    fgL = fg[f - st];
+    frL = fr[f - st];
+    fgR = fg[f];
+    frR = fr[f];
+    if (wgt) {
+#pragma unroll
+      for (int m = 0; m < 6; m++) gc[m] = C.geo_c[GE_GDET * C.npos + (i + m - 3) + C.N[0] * j];
+      gface = C.geo_f1[GE_GDET * C.npos + i + C.N[0] * j];
+    }
+  }
   double PLR[24];
 #pragma unroll
   for (int q = 0; q < 12; q++) {
     const double* p = P + q * C.Ntot;
-    const double a = p[f - 2 * st], b = p[f - st], e = p[f], ff = p[f + st];
-    PLR[q] = b + 0.5 * mc_slope(b - a, e - b);
-    PLR[12 + q] = e - 0.5 * mc_slope(e - b, ff - e);
+    if (PPM) {
+      const bool vec = wgt && ((q >= 2 && q <= 7) || q >= 9);
+      double a[6], l, r;
+#pragma unroll
+      for (int m = 0; m < 6; m++) a[m] = vec ? p[f + (m - 3) * st] * gc[m] : p[f + (m - 3) * st];
+      ppm_cell(a, q < 8 ? fgL : frL, l, PLR[q]);
+      ppm_cell(a + 1, q < 8 ? fgR : frR, PLR[12 + q], r);
+      if (vec) {
+        PLR[q] = PLR[q] / gface;
+        PLR[12 + q] = PLR[12 + q] / gface;
+      }
+    } else {
+      const double a = p[f - 2 * st], b = p[f - st], e = p[f], ff = p[f + st];
+      PLR[q] = b + 0.5 * mc_slope(b - a, e - b);
+      PLR[12 + q] = e - 0.5 * mc_slope(e - b, ff - e);
+    }
   }
   Metric m;
   const double* tab = (D == 1) ? C.geo_f1 : ((D == 2) ? C.geo_f2 : C.geo_c);
@@ -674,23 +716,51 @@ DEV void adj_flux_at(Ctx C, FaceRange R, double scale,
     Gx[f] = gxL;                 // d/d chi_tot of cell f - e_d
     Gx[C.Ntot + f] = gxR;        // d/d chi_tot of cell f
   }
-  // MC reconstruction, per primitive, with respect to the four stencil cells
+  // the reconstruction, per primitive, with respect to the stencil cells
   // (the stencil is read again rather than held through the face passes)
+  if (PPM) {
+    typedef Dual<8> D8;   // six stencil cells, the left and the right flattener
+    double gf[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-  for (int q = 0; q < 12; q++) {
-    const double* p = P + q * C.Ntot;
-    const double v[4] = {p[f - 2 * st], p[f - st], p[f], p[f + st]};
-    D4 s[4];
-    seed4<4>(v, 0, s);
-    const D4 PL = s[1] + 0.5 * mc_slope(s[1] - s[0], s[2] - s[1]);
-    const D4 PR = s[2] - 0.5 * mc_slope(s[2] - s[1], s[3] - s[2]);
+    for (int q = 0; q < 12; q++) {
+      const double* p = P + q * C.Ntot;
+      const bool vec = wgt && ((q >= 2 && q <= 7) || q >= 9);
+      D8 a[6];
 #pragma unroll
-    for (int slot = 0; slot < 4; slot++)
-      G[(slot * 12 + q) * C.Ntot + f] = lPLR[q] * PL.d[slot] + lPLR[12 + q] * PR.d[slot];
+      for (int s = 0; s < 6; s++) {
+        a[s] = D8(vec ? p[f + (s - 3) * st] * gc[s] : p[f + (s - 3) * st]);
+        a[s].d[s] = vec ? gc[s] : 1.0;
+      }
+      const D8 fL = D8::var(q < 8 ? fgL : frL, 6), fR = D8::var(q < 8 ? fgR : frR, 7);
+      D8 l, r, PL, PR;
+      ppm_cell(a, fL, l, PL);
+      ppm_cell(a + 1, fR, PR, r);
+      const double ig = vec ? 1.0 / gface : 1.0;
+#pragma unroll
+      for (int s = 0; s < 6; s++)
+        G[(s * 12 + q) * C.Ntot + f] = ig * (lPLR[q] * PL.d[s] + lPLR[12 + q] * PR.d[s]);
+      gf[q < 8 ? 0 : 1] += ig * lPLR[q] * PL.d[6];
+      gf[q < 8 ? 2 : 3] += ig * lPLR[12 + q] * PR.d[7];
+    }
+#pragma unroll
+    for (int s = 0; s < 4; s++) GF[s * C.Ntot + f] = gf[s];
+  } else {
+#pragma unroll
+    for (int q = 0; q < 12; q++) {
+      const double* p = P + q * C.Ntot;
+      const double v[4] = {p[f - 2 * st], p[f - st], p[f], p[f + st]};
+      D4 s[4];
+      seed4<4>(v, 0, s);
+      const D4 PL = s[1] + 0.5 * mc_slope(s[1] - s[0], s[2] - s[1]);
+      const D4 PR = s[2] - 0.5 * mc_slope(s[2] - s[1], s[3] - s[2]);
+#pragma unroll
+      for (int slot = 0; slot < 4; slot++)
+        G[(slot * 12 + q) * C.Ntot + f] = lPLR[q] * PL.d[slot] + lPLR[12 + q] * PR.d[slot];
+    }
   }
 }
 
-template <int D>
+template <int D, bool PPM>
 __global__ void __launch_bounds__(64) k_adj_flux(Ctx C, FaceRange R, double scale,
                                                  const double* __restrict__ dt_dev,
                                                  const double* __restrict__ P,
@@ -698,11 +768,12 @@ __global__ void __launch_bounds__(64) k_adj_flux(Ctx C, FaceRange R, double scal
                                                  const double* __restrict__ chi_es,
                                                  const double* __restrict__ lamUe,
                                                  const double* __restrict__ lamE,
-                                                 double* __restrict__ G, double* __restrict__ Gx) {
-  adj_flux_at<D>(C, R, scale, dt_dev, P, chi_abs, chi_es, lamUe, lamE, G, Gx,
-                 (long)blockIdx.x * blockDim.x + threadIdx.x);
+                                                 double* __restrict__ G, double* __restrict__ Gx,
+                                                 const double* __restrict__ fl,
+                                                 double* __restrict__ GF) {
+  adj_flux_at<D, PPM>(C, R, scale, dt_dev, P, chi_abs, chi_es, lamUe, lamE, G, Gx, fl, GF,
+                      (long)blockIdx.x * blockDim.x + threadIdx.x);
 }
-
 
 // ---------------------------------------------------------------------------
 // Per allocated cell: gather the stencil products of the faces that read it;
@@ -715,6 +786,7 @@ struct FaceRanges {
   FaceRange r[3];
 };
 
+template <int NSL>
 DEV void adj_gather_at(Ctx C, FaceRanges FR, const double* __restrict__ G1,
                        const double* __restrict__ G2, const double* __restrict__ G3,
                        double* __restrict__ lamPb, long c) {
@@ -734,10 +806,10 @@ DEV void adj_gather_at(Ctx C, FaceRanges FR, const double* __restrict__ G1,
     for (int e = 0; e < 3; e++)
       if (e != d && (idx[e] < R.lo[e] || idx[e] >= R.lo[e] + R.cnt[e])) trans = false;
     if (!trans) continue;
-    for (int slot = 0; slot < 4; slot++) {
-      const int fd = idx[d] + 2 - slot;   // face whose slot-th stencil cell is c
+    for (int slot = 0; slot < NSL; slot++) {
+      const int fd = idx[d] + NSL / 2 - slot;   // face whose slot-th stencil cell is c
       if (fd < R.lo[d] || fd >= R.lo[d] + R.cnt[d]) continue;
-      const long f = c + (long)(2 - slot) * C.st[d];
+      const long f = c + (long)(NSL / 2 - slot) * C.st[d];
 #pragma unroll
       for (int q = 0; q < 12; q++) acc[q] += G[(slot * 12 + q) * C.Ntot + f];
     }
@@ -746,10 +818,11 @@ DEV void adj_gather_at(Ctx C, FaceRanges FR, const double* __restrict__ G1,
   for (int q = 0; q < 12; q++) lamPb[q * C.Ntot + c] = acc[q];
 }
 
+template <int NSL>
 __global__ void LB(256) k_adj_gather(Ctx C, FaceRanges FR, const double* __restrict__ G1,
                                      const double* __restrict__ G2, const double* __restrict__ G3,
                                      double* __restrict__ lamPb) {
-  adj_gather_at(C, FR, G1, G2, G3, lamPb, (long)blockIdx.x * blockDim.x + threadIdx.x);
+  adj_gather_at<NSL>(C, FR, G1, G2, G3, lamPb, (long)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 // Interior cell t (curved metric): lamPb += c dt (dS/dP)^T lamUe, the
@@ -828,6 +901,116 @@ __global__ void LB(256) k_adj_gather_chi(Ctx C, FaceRanges FR, const double* __r
   }
   gchi[c] += acc;
   gchi[C.Ntot + c] += acc;
+}
+
+// ---------------------------------------------------------------------------
+// PPM flattener.  Forward, a sub-step's flux read fl_k = max(fl_{k-1}, f2_k)
+// (fl_k = f2_k at the step's first flux evaluation), f2_k the flattener of
+// the sub-step's own input.  Per allocated cell, direction and kind: the
+// cotangent of fl_k (from the faces that read it, GF, plus what later
+// sub-steps passed down in LamFl) goes to f2_k where f2_k was the larger
+// (ties: the earlier value, the first argument) and stays in LamFl for the
+// earlier sub-steps otherwise.  Lf2: the cotangent of f2_k, zero where f2_k
+// has no derivative (both kinds zero at the first evaluation: the
+// compression test failed or the ramp is clamped at zero).  prev: fl_{k-1},
+// null at the first evaluation.  GF_d: [4][Ntot] per direction.
+// ---------------------------------------------------------------------------
+__global__ void LB(256) k_adj_flat_cot(Ctx C, FaceRanges FR, const double* __restrict__ GF,
+                                       const double* __restrict__ fl,
+                                       const double* __restrict__ prev,
+                                       double* __restrict__ LamFl, double* __restrict__ Lf2) {
+  const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= C.Ntot) return;
+  int idx[3];
+  idx[0] = c % C.N[0];
+  idx[1] = (c / C.N[0]) % C.N[1];
+  idx[2] = c / ((long)C.N[0] * C.N[1]);
+  for (int d = 0; d < 3; d++) {
+    const long xg = (long)(2 * d) * C.Ntot + c, xr = xg + C.Ntot;
+    if (C.n[d] == 1) {
+      Lf2[xg] = 0.0;
+      Lf2[xr] = 0.0;
+      continue;
+    }
+    const double* G = GF + (long)d * 4 * C.Ntot;
+    const FaceRange& R = FR.r[d];
+    double L[2] = {LamFl[xg], LamFl[xr]};
+    bool trans = true;
+    for (int e = 0; e < 3; e++)
+      if (e != d && (idx[e] < R.lo[e] || idx[e] >= R.lo[e] + R.cnt[e])) trans = false;
+    if (trans) {
+      const int up = idx[d] + 1;   // face c + e_d: c is its left cell
+      const bool left = up >= R.lo[d] && up < R.lo[d] + R.cnt[d];
+      const bool right = idx[d] >= R.lo[d] && idx[d] < R.lo[d] + R.cnt[d];
+#pragma unroll
+      for (int kind = 0; kind < 2; kind++) {
+        if (left) L[kind] += G[(long)kind * C.Ntot + c + C.st[d]];
+        if (right) L[kind] += G[(long)(2 + kind) * C.Ntot + c];
+      }
+    }
+    const long x[2] = {xg, xr};
+    const bool flat0 = !prev && fl[xg] == 0.0 && fl[xr] == 0.0;
+#pragma unroll
+    for (int kind = 0; kind < 2; kind++) {
+      const bool win = !prev || fl[x[kind]] > prev[x[kind]];
+      Lf2[x[kind]] = (win && !flat0) ? L[kind] : 0.0;
+      LamFl[x[kind]] = win ? 0.0 : L[kind];
+    }
+  }
+}
+
+// Transpose of f2: per allocated cell c, every flattener within three cells
+// along a direction whose cotangent Lf2 is not zero, differentiated (one
+// Dual<4> pass of the forward's flattener) with respect to c's u_g, Ebar,
+// rho and total opacity; added to lamPb and (non-null) to both opacity
+// cotangents gchi [2][Ntot].
+__global__ void LB(128) k_adj_flat(Ctx C, const double* __restrict__ P,
+                                   const double* __restrict__ chi_abs,
+                                   const double* __restrict__ chi_es,
+                                   const double* __restrict__ Lf2, double* __restrict__ lamPb,
+                                   double* __restrict__ gchi) {
+  const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= C.Ntot) return;
+  int idx[3];
+  idx[0] = c % C.N[0];
+  idx[1] = (c / C.N[0]) % C.N[1];
+  idx[2] = c / ((long)C.N[0] * C.N[1]);
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  bool any = false;
+#pragma unroll 1
+  for (int d = 0; d < 3; d++) {
+    if (C.n[d] == 1) continue;
+    bool trans = true;   // the flattener range: one cell beyond the interior
+    for (int e = 0; e < 3; e++)
+      if (e != d && C.n[e] > 1 && (idx[e] < C.ng[e] - 1 || idx[e] > C.ng[e] + C.n[e])) trans = false;
+    if (!trans) continue;
+#pragma unroll 1
+    for (int m = -3; m <= 3; m++) {
+      const int id = idx[d] - m;   // c is at offset m of cell cp
+      if (id < C.ng[d] - 1 || id > C.ng[d] + C.n[d]) continue;
+      const long cp = c - (long)m * C.st[d];
+      const double Lg = Lf2[(long)(2 * d) * C.Ntot + cp], Lr = Lf2[(long)(2 * d + 1) * C.Ntot + cp];
+      if (Lg == 0.0 && Lr == 0.0) continue;
+      D4 sd[4];
+      sd[0] = D4::var(P[C.Ntot + c], 0);
+      sd[1] = D4::var(P[8 * C.Ntot + c], 1);
+      sd[2] = D4::var(P[c], 2);
+      sd[3] = D4::var(chi_abs[c] + chi_es[c], 3);
+      D4 f2[2];
+      flat_dir<D4, true>(C, P, chi_abs, chi_es, nullptr, cp, d, m, sd, f2);
+#pragma unroll
+      for (int a = 0; a < 4; a++) acc[a] += Lg * f2[0].d[a] + Lr * f2[1].d[a];
+      any = true;
+    }
+  }
+  if (!any) return;
+  lamPb[C.Ntot + c] += acc[0];
+  lamPb[8 * C.Ntot + c] += acc[1];
+  lamPb[c] += acc[2];
+  if (gchi) {
+    gchi[c] += acc[3];
+    gchi[C.Ntot + c] += acc[3];
+  }
 }
 
 // ---------------------------------------------------------------------------

@@ -499,6 +499,24 @@ static void split_x1(const FaceRange& R, int i0, FaceRange& a, FaceRange& b) {
 // Bf (staggered field): the face states take the faces' normal field, write
 // their velocities and speeds to VF, SP, and the corner EMFs are the
 // four-state ones.
+// PPM flattener of P into the grid's buffer (keep_flat as launch_fluxes)
+static int launch_flattener(grrmhd_grid* g, const double* P, const double* ca, const double* ce,
+                            int keep_flat) {
+  const Ctx& C = g->C;
+  double* mf = nullptr;
+  if (C.metric == GRRMHD_KERR_SCHILD) {
+    mf = g->flat + 6 * (size_t)C.Ntot;
+    hipLaunchKernelGGL(k_mass_flux, dim3(nblocks(C.Ntot, 256)), dim3(256), 0, g->stream, C, P, mf);
+    LAUNCHCHK();
+  }
+  long nb = 1;
+  for (int e = 0; e < 3; e++) nb *= C.n[e] > 1 ? C.n[e] + 2 : 1;
+  hipLaunchKernelGGL(k_flatten, dim3(nblocks(nb, 256)), dim3(256), 0, g->stream, C, P, ca, ce,
+                     g->flat, keep_flat, (const double*)mf);
+  LAUNCHCHK();
+  return 0;
+}
+
 static int launch_fluxes(grrmhd_grid* g, const double* P, const double* ca, const double* ce,
                          double* F, double* emf, double* vch,
                          unsigned long long* dtmin = nullptr, int keep_flat = 0,
@@ -506,17 +524,8 @@ static int launch_fluxes(grrmhd_grid* g, const double* P, const double* ca, cons
                          double* SP = nullptr) {
   const Ctx& C = g->C;
   if (C.recon == GRRMHD_RECON_PPM) {
-    double* mf = nullptr;
-    if (C.metric == GRRMHD_KERR_SCHILD) {
-      mf = g->flat + 6 * (size_t)C.Ntot;
-      hipLaunchKernelGGL(k_mass_flux, dim3(nblocks(C.Ntot, 256)), dim3(256), 0, g->stream, C, P, mf);
-      LAUNCHCHK();
-    }
-    long nb = 1;
-    for (int e = 0; e < 3; e++) nb *= C.n[e] > 1 ? C.n[e] + 2 : 1;
-    hipLaunchKernelGGL(k_flatten, dim3(nblocks(nb, 256)), dim3(256), 0, g->stream, C, P, ca, ce,
-                       g->flat, keep_flat, (const double*)mf);
-    LAUNCHCHK();
+    const int rc = launch_flattener(g, P, ca, ce, keep_flat);
+    if (rc) return rc;
   }
   // faces of every direction, FP64 part and FP32 part (split at mixed_i)
   FluxSegs S64, S32;
@@ -1021,13 +1030,17 @@ extern "C" int grrmhd_fluxes_staggered(grrmhd_grid* g, const double* P, const do
 // ---------------------------------------------------------------------------
 struct AdjLayout {
   size_t F, emf, vch, scr, err, it, Un, Pb, Ue, Pk, Uk, stk, lamP, lamU, lamUe, lamUn, lamPb, lamE,
-      G, Gx, Lam, lamPpre, lamUpre, M, lamUs, lamM, lamPg, Pc, total;
+      G, Gx, Lam, lamPpre, lamUpre, M, lamUs, lamM, lamPg, Pc, FL, GF, LamFl, Lf2, total;
   int ns;   // stages checkpointed
 };
 
+// stencil cells per face of the reconstruction (MC 4, PPM 6)
+static int adj_slots(const Ctx& C) { return C.recon == GRRMHD_RECON_PPM ? 6 : 4; }
+
 // RK3 keeps three stages; an IMEX scheme its own count, plus the stored
 // sources M^k, their cotangents, the per-stage cotangents of U(i) and the
-// final inversion's guess cotangent and result
+// final inversion's guess cotangent and result.  PPM adds the flattener of
+// every stage, the faces' products with it and two flattener cotangents.
 static AdjLayout adj_layout(const Ctx& C, int scheme) {
   AdjLayout w;
   size_t off = 0;
@@ -1058,7 +1071,8 @@ static AdjLayout adj_layout(const Ctx& C, int scheme) {
   w.lamUn = take(D8 * 12 * N);
   w.lamPb = take(D8 * 12 * N);
   w.lamE = take(D8 * 3 * N);
-  w.G = take(D8 * 3 * 48 * N);  // per direction: face products with the 4 stencil cells
+  const bool ppm = C.recon == GRRMHD_RECON_PPM;
+  w.G = take(D8 * 3 * 12 * adj_slots(C) * N);  // per direction: face products with the stencil cells
   w.Gx = take(D8 * 3 * 2 * N);  // per direction: face products with the 2 face cells' opacity
   w.Lam = take(D8 * 12 * N);
   w.lamPpre = take(D8 * 12 * N);
@@ -1068,6 +1082,10 @@ static AdjLayout adj_layout(const Ctx& C, int scheme) {
   w.lamM = take(imex ? D8 * 4 * 8 * N : 0);
   w.lamPg = take(imex ? D8 * 12 * N : 0);
   w.Pc = take(imex ? D8 * 12 * N : 0);
+  w.FL = take(ppm ? D8 * 6 * ns * N : 0);   // per stage: the flattener its fluxes read
+  w.GF = take(ppm ? D8 * 12 * N : 0);       // per direction: face products with the flattener
+  w.LamFl = take(ppm ? D8 * 6 * N : 0);     // cotangent of the flattener read, carried back
+  w.Lf2 = take(ppm ? D8 * 6 * N : 0);       // cotangent of a stage's own flattener
   w.total = off;
   return w;
 }
@@ -1099,16 +1117,31 @@ static int adj_implicit(grrmhd_grid* g, double scale, const double* dt_dev, cons
   return 0;
 }
 
+// PPM: the flattener a stage's fluxes read (fl), the one before it in the
+// step (prev, null at the first flux evaluation) and the buffers of the
+// flattener's transpose (GF [3][4][N], LamFl and Lf2 [3][2][N]).
+struct AdjFlat {
+  const double* fl;
+  const double* prev;
+  double *GF, *LamFl, *Lf2;
+};
+
 // lamPb (every allocated cell) = (d Ue / d Pb)^T lamUe through the fluxes,
-// EMFs and geometric source of a stage with coefficient `scale` on dt
+// EMFs, geometric source and (PPM) flattener of a stage with coefficient
+// `scale` on dt
 // Gx, gchi (nullable together): opacity face products and the cotangents
 // they add to gchi [2][N]
 static int adj_explicit(grrmhd_grid* g, double scale, const double* dt_dev, const double* Pb,
                         const double* ca, const double* ce, const double* lamUe, double* lamE,
-                        double* G, double* lamPb, double* Gx = nullptr, double* gchi = nullptr) {
+                        double* G, double* lamPb, double* Gx, double* gchi, const AdjFlat* FLT) {
   const Ctx& C = g->C;
   const size_t N = (size_t)C.Ntot;
   hipStream_t s = g->stream;
+  const bool ppm = C.recon == GRRMHD_RECON_PPM;
+  const size_t gs = 12 * (size_t)adj_slots(C) * N;
+  if (ppm && !FLT) return fail(GRRMHD_EINVAL, "PPM adjoint without the flattener buffers");
+  const double* fl = ppm ? FLT->fl : nullptr;
+  double* GF = ppm ? FLT->GF : nullptr;
   int rc;
   if ((rc = fill_d(g, lamE, 3 * N, 0.0))) return rc;
   for (int a = 0; a < 3; a++) {
@@ -1123,22 +1156,33 @@ static int adj_explicit(grrmhd_grid* g, double scale, const double* dt_dev, cons
   for (int d = 0; d < 3; d++) {
     if (C.n[d] == 1) continue;
     const FaceRange& R = FR.r[d];
-    double* Gd = G + (size_t)d * 48 * N;
+    double* Gd = G + (size_t)d * gs;
+    double* Gxd = Gx ? Gx + (size_t)d * 2 * N : nullptr;
+    double* GFd = ppm ? GF + (size_t)d * 4 * N : nullptr;
     const dim3 gr(nblocks(R.total, 64)), bl(64);
-    if (d == 0)
-      hipLaunchKernelGGL(k_adj_flux<1>, gr, bl, 0, s, C, R, scale, dt_dev, Pb, ca, ce, lamUe,
-                         (const double*)lamE, Gd, Gx ? Gx + (size_t)d * 2 * N : nullptr);
-    if (d == 1)
-      hipLaunchKernelGGL(k_adj_flux<2>, gr, bl, 0, s, C, R, scale, dt_dev, Pb, ca, ce, lamUe,
-                         (const double*)lamE, Gd, Gx ? Gx + (size_t)d * 2 * N : nullptr);
-    if (d == 2)
-      hipLaunchKernelGGL(k_adj_flux<3>, gr, bl, 0, s, C, R, scale, dt_dev, Pb, ca, ce, lamUe,
-                         (const double*)lamE, Gd, Gx ? Gx + (size_t)d * 2 * N : nullptr);
+#define ADJ_FLUX(D, PPM)                                                                      \
+  hipLaunchKernelGGL((k_adj_flux<D, PPM>), gr, bl, 0, s, C, R, scale, dt_dev, Pb, ca, ce, lamUe, \
+                     (const double*)lamE, Gd, Gxd, fl, GFd)
+    if (ppm) {
+      if (d == 0) ADJ_FLUX(1, true);
+      if (d == 1) ADJ_FLUX(2, true);
+      if (d == 2) ADJ_FLUX(3, true);
+    } else {
+      if (d == 0) ADJ_FLUX(1, false);
+      if (d == 1) ADJ_FLUX(2, false);
+      if (d == 2) ADJ_FLUX(3, false);
+    }
+#undef ADJ_FLUX
     LAUNCHCHK();
   }
-  hipLaunchKernelGGL(k_adj_gather, dim3(nblocks(C.Ntot, 256)), dim3(256), 0, s, C, FR,
-                     (const double*)G, (const double*)(G + 48 * N), (const double*)(G + 96 * N),
-                     lamPb);
+  if (ppm)
+    hipLaunchKernelGGL(k_adj_gather<6>, dim3(nblocks(C.Ntot, 256)), dim3(256), 0, s, C, FR,
+                       (const double*)G, (const double*)(G + gs), (const double*)(G + 2 * gs),
+                       lamPb);
+  else
+    hipLaunchKernelGGL(k_adj_gather<4>, dim3(nblocks(C.Ntot, 256)), dim3(256), 0, s, C, FR,
+                       (const double*)G, (const double*)(G + gs), (const double*)(G + 2 * gs),
+                       lamPb);
   LAUNCHCHK();
   if (C.metric != GRRMHD_MINKOWSKI) {
     const long ncell = (long)C.n[0] * C.n[1] * C.n[2];
@@ -1150,6 +1194,14 @@ static int adj_explicit(grrmhd_grid* g, double scale, const double* dt_dev, cons
     hipLaunchKernelGGL(k_adj_gather_chi, dim3(nblocks(C.Ntot, 256)), dim3(256), 0, s, C, FR,
                        (const double*)Gx, (const double*)(Gx + 2 * N), (const double*)(Gx + 4 * N),
                        gchi);
+    LAUNCHCHK();
+  }
+  if (ppm) {
+    hipLaunchKernelGGL(k_adj_flat_cot, dim3(nblocks(C.Ntot, 256)), dim3(256), 0, s, C, FR,
+                       (const double*)GF, fl, FLT->prev, FLT->LamFl, FLT->Lf2);
+    LAUNCHCHK();
+    hipLaunchKernelGGL(k_adj_flat, dim3(nblocks(C.Ntot, 128)), dim3(128), 0, s, C, Pb, ca, ce,
+                       (const double*)FLT->Lf2, lamPb, gchi);
     LAUNCHCHK();
   }
   return 0;
@@ -1180,8 +1232,16 @@ extern "C" int grrmhd_implicit_vjp(grrmhd_grid* g, const double* Uexp, const dou
                       gUexp);
 }
 
+// lamE [3][N], G [3][12 NSL][N]; PPM also GF [3][4][N], LamFl and Lf2
+// [3][2][N] (each 256-byte aligned)
+static size_t evjp_part(size_t doubles) { return (doubles * sizeof(double) + 255) & ~(size_t)255; }
+
 extern "C" size_t grrmhd_explicit_vjp_workspace_bytes(const grrmhd_grid* g) {
-  return g ? sizeof(double) * (size_t)g->C.Ntot * (3 + 144) + 512 : 0;
+  if (!g) return 0;
+  const size_t N = (size_t)g->C.Ntot;
+  size_t b = evjp_part(3 * N) + evjp_part(36 * (size_t)adj_slots(g->C) * N);
+  if (g->C.recon == GRRMHD_RECON_PPM) b += evjp_part(12 * N) + 2 * evjp_part(6 * N);
+  return b;
 }
 
 extern "C" int grrmhd_explicit_vjp(grrmhd_grid* g, double c, const double* dt_dev,
@@ -1191,14 +1251,32 @@ extern "C" int grrmhd_explicit_vjp(grrmhd_grid* g, double c, const double* dt_de
   NEEDG();
   if (!dt_dev || !P || !chi_abs || !chi_es || !gUexp || !gP || !workspace)
     return fail(GRRMHD_EINVAL, "NULL array");
-  if (g->p.recon != GRRMHD_RECON_MC)
-    return fail(GRRMHD_EINVAL, "the flux adjoint covers MC reconstruction");
+  if (g->C.ct) return fail(GRRMHD_EINVAL, "the flux adjoint covers the flux-CT field");
   if (ws_bytes < grrmhd_explicit_vjp_workspace_bytes(g)) return fail(GRRMHD_EINVAL, "workspace too small");
   if (((uintptr_t)workspace) & 255) return fail(GRRMHD_EINVAL, "workspace must be 256-byte aligned");
-  const size_t N = (size_t)g->C.Ntot;
-  double* lamE = (double*)workspace;
-  double* G = (double*)((char*)workspace + (((3 * N * sizeof(double)) + 255) & ~(size_t)255));
-  return adj_explicit(g, c, dt_dev, P, chi_abs, chi_es, gUexp, lamE, G, gP);
+  const Ctx& C = g->C;
+  const size_t N = (size_t)C.Ntot;
+  char* w = (char*)workspace;
+  double* lamE = (double*)w;
+  w += evjp_part(3 * N);
+  double* G = (double*)w;
+  w += evjp_part(36 * (size_t)adj_slots(C) * N);
+  if (C.recon != GRRMHD_RECON_PPM)
+    return adj_explicit(g, c, dt_dev, P, chi_abs, chi_es, gUexp, lamE, G, gP, nullptr, nullptr,
+                        nullptr);
+  // PPM: the flattener of P alone, as at a step's first flux evaluation
+  AdjFlat F;
+  F.GF = (double*)w;
+  w += evjp_part(12 * N);
+  F.LamFl = (double*)w;
+  w += evjp_part(6 * N);
+  F.Lf2 = (double*)w;
+  int rc;
+  if ((rc = launch_flattener(g, P, chi_abs, chi_es, 0))) return rc;
+  if ((rc = fill_d(g, F.LamFl, 6 * N, 0.0))) return rc;
+  F.fl = g->flat;
+  F.prev = nullptr;
+  return adj_explicit(g, c, dt_dev, P, chi_abs, chi_es, gUexp, lamE, G, gP, nullptr, nullptr, &F);
 }
 
 extern "C" int grrmhd_bc_vjp(grrmhd_grid* g, double* gP) {
@@ -1250,13 +1328,11 @@ extern "C" int grrmhd_con2prim_vjp(grrmhd_grid* g, const double* U, const double
 struct AdjPtrs {
   double *F, *emf, *vch, *scr, *err, *Un, *Pb, *Ue, *Pk, *Uk;
   double *lamP, *lamU, *lamUe, *lamUn, *lamPb, *lamE, *G, *Gx, *Lam, *lamPpre, *lamUpre;
-  double *M, *lamUs, *lamM, *lamPg, *Pc;
+  double *M, *lamUs, *lamM, *lamPg, *Pc, *FL, *GF, *LamFl, *Lf2;
   int *it, *stk;
 };
 
 static int adj_ptrs(grrmhd_grid* g, void* workspace, size_t ws_bytes, AdjPtrs& a) {
-  if (g->p.recon != GRRMHD_RECON_MC)
-    return fail(GRRMHD_EINVAL, "the adjoint covers MC reconstruction");
   if (g->p.cascade != 0)
     return fail(GRRMHD_EINVAL, "the adjoint covers the PMHD/URAD cascade (cascade = 0)");
   if (g->C.ct)
@@ -1293,7 +1369,33 @@ static int adj_ptrs(grrmhd_grid* g, void* workspace, size_t ws_bytes, AdjPtrs& a
   a.lamM = (double*)(base + w.lamM);
   a.lamPg = (double*)(base + w.lamPg);
   a.Pc = (double*)(base + w.Pc);
+  a.FL = (double*)(base + w.FL);
+  a.GF = (double*)(base + w.GF);
+  a.LamFl = (double*)(base + w.LamFl);
+  a.Lf2 = (double*)(base + w.Lf2);
   return 0;
+}
+
+// PPM: keep the flattener stage k's fluxes read
+static int adj_keep_flat(grrmhd_grid* g, const AdjPtrs& a, int k) {
+  if (g->C.recon != GRRMHD_RECON_PPM) return 0;
+  const size_t N6 = 6 * (size_t)g->C.Ntot;
+  HIPCHK(hipMemcpyAsync(a.FL + k * N6, g->flat, sizeof(double) * N6, hipMemcpyDeviceToDevice,
+                        g->stream));
+  return 0;
+}
+
+// PPM: the flattener views of stage k's reverse step (prev_k: the stage of
+// the step's previous flux evaluation, -1 at the first)
+static AdjFlat adj_flat_of(grrmhd_grid* g, const AdjPtrs& a, int k, int prev_k) {
+  const size_t N6 = 6 * (size_t)g->C.Ntot;
+  AdjFlat F;
+  F.fl = a.FL + k * N6;
+  F.prev = prev_k >= 0 ? a.FL + prev_k * N6 : nullptr;
+  F.GF = a.GF;
+  F.LamFl = a.LamFl;
+  F.Lf2 = a.Lf2;
+  return F;
 }
 
 static const double ADJ_A[3] = {1.0, 0.75, 1.0 / 3.0}, ADJ_B[3] = {0.0, 0.25, 2.0 / 3.0},
@@ -1321,7 +1423,8 @@ static int adj_forward(grrmhd_grid* g, const double* P_n, const double* chi_abs,
     int* st = a.stk + k * N;
     if (k > 0) HIPCHK(hipMemcpyAsync(Pin, a.Pk + (k - 1) * N12, B12, hipMemcpyDeviceToDevice, s));
     if ((rc = launch_bc(g, Pin))) return rc;
-    if ((rc = launch_fluxes(g, Pin, chi_abs, chi_es, a.F, a.emf, a.vch))) return rc;
+    if ((rc = launch_fluxes(g, Pin, chi_abs, chi_es, a.F, a.emf, a.vch, nullptr, k > 0))) return rc;
+    if ((rc = adj_keep_flat(g, a, k))) return rc;
     if ((rc = launch_update(g, ADJ_A[k], ADJ_B[k], ADJ_C[k], dt_dev, Pin, a.Un,
                             k == 0 ? a.Un : a.Uk + (k - 1) * N12, a.F, a.emf, Uek)))
       return rc;
@@ -1357,6 +1460,8 @@ static int adj_reverse(grrmhd_grid* g, const double* chi_abs, const double* chi_
   LAUNCHCHK();
   if ((rc = fill_d(g, a.lamP, N12, 0.0)) || (rc = fill_d(g, a.lamUn, N12, 0.0))) return rc;
   if (g_chi && (rc = fill_d(g, g_chi, 2 * N, 0.0))) return rc;
+  const bool ppm = C.recon == GRRMHD_RECON_PPM;
+  if (ppm && (rc = fill_d(g, a.LamFl, 6 * N, 0.0))) return rc;
   for (int k = 2; k >= 0; k--) {
     const double* Pin = a.Pb + k * N12;
     // fix-up of failed and cold cells, then the implicit solve
@@ -1374,8 +1479,9 @@ static int adj_reverse(grrmhd_grid* g, const double* chi_abs, const double* chi_
     hipLaunchKernelGGL(k_adj_stage, dim3(gi), dim3(256), 0, s, C, ADJ_A[k], ADJ_B[k],
                        (const double*)a.lamUe, a.lamUn, a.lamU);
     LAUNCHCHK();
+    const AdjFlat F = adj_flat_of(g, a, k, k - 1);
     if ((rc = adj_explicit(g, ADJ_C[k], dt_dev, Pin, chi_abs, chi_es, a.lamUe, a.lamE, a.G,
-                           a.lamPb, Gx, g_chi)))
+                           a.lamPb, Gx, g_chi, ppm ? &F : nullptr)))
       return rc;
     if ((rc = adj_bc(g, a.lamPb))) return rc;
     hipLaunchKernelGGL(k_copy_interior, dim3(ga), dim3(256), 0, s, C, (const double*)a.lamPb, a.lamP);
@@ -1405,6 +1511,7 @@ static int adj_forward_imex(grrmhd_grid* g, const double* P_n, const double* chi
   HIPCHK(hipMemcpyAsync(a.Pb, P_n, B12, hipMemcpyDeviceToDevice, s));
   hipLaunchKernelGGL(k_p2u, dim3(nblocks(C.Ntot, 256)), dim3(256), 0, s, C, a.Pb, a.Un);
   LAUNCHCHK();
+  int nflux = 0;
   for (int i = 0; i < S.ns; i++) {
     const Stage& x = S.s[i];
     double* Pin = a.Pb + i * N12;
@@ -1415,7 +1522,10 @@ static int adj_forward_imex(grrmhd_grid* g, const double* P_n, const double* chi
     if (i > 0) HIPCHK(hipMemcpyAsync(Pin, a.Pk + (i - 1) * N12, B12, hipMemcpyDeviceToDevice, s));
     if (x.c != 0.0) {
       if ((rc = launch_bc(g, Pin))) return rc;
-      if ((rc = launch_fluxes(g, Pin, chi_abs, chi_es, a.F, a.emf, a.vch))) return rc;
+      if ((rc = launch_fluxes(g, Pin, chi_abs, chi_es, a.F, a.emf, a.vch, nullptr, nflux > 0)))
+        return rc;
+      if ((rc = adj_keep_flat(g, a, i))) return rc;
+      nflux++;
     }
     MTerms MT;
     memset(&MT, 0, sizeof(MT));
@@ -1481,6 +1591,8 @@ static int adj_reverse_imex(grrmhd_grid* g, const double* chi_abs, const double*
       (rc = fill_d(g, a.lamP, N12, 0.0)) || (rc = fill_d(g, a.lamUn, N12, 0.0)))
     return rc;
   if (g_chi && (rc = fill_d(g, g_chi, 2 * N, 0.0))) return rc;
+  const bool ppm = C.recon == GRRMHD_RECON_PPM;
+  if (ppm && (rc = fill_d(g, a.LamFl, 6 * N, 0.0))) return rc;
   hipLaunchKernelGGL(k_copy_interior, dim3(ga), dim3(256), 0, s, C, gU_next,
                      a.lamUs + (S.ns - 1) * N12);
   LAUNCHCHK();
@@ -1538,8 +1650,11 @@ static int adj_reverse_imex(grrmhd_grid* g, const double* chi_abs, const double*
       LAUNCHCHK();
     }
     if (x.c != 0.0) {
+      int prev = i - 1;   // the step's previous flux evaluation
+      while (prev >= 0 && S.s[prev].c == 0.0) prev--;
+      const AdjFlat F = adj_flat_of(g, a, i, prev);
       if ((rc = adj_explicit(g, x.c, dt_dev, Pin, chi_abs, chi_es, a.lamUe, a.lamE, a.G, a.lamPb,
-                             Gx, g_chi)))
+                             Gx, g_chi, ppm ? &F : nullptr)))
         return rc;
       if ((rc = adj_bc(g, a.lamPb))) return rc;
       hipLaunchKernelGGL(k_copy_interior, dim3(ga), dim3(256), 0, s, C, (const double*)a.lamPb,

@@ -221,7 +221,7 @@ DEV void ppm_cell(const T* a, T f, T& aL, T& aR) {
   T r = ppm_iface(a[1], a[2], a[3], a[4]);
   l = f * a0 + (R(1.0) - f) * l;
   r = f * a0 + (R(1.0) - f) * r;
-  if ((r - a0) * (a0 - l) <= R(0.0)) {
+  if (val((r - a0) * (a0 - l)) <= R(0.0)) {
     l = a0;
     r = a0;
   } else {
@@ -655,17 +655,44 @@ __global__ void LB(256) k_entropy_update(Ctx C, double a, double b, double cc,
 //   moves towards the larger of the two by w.  keep: the larger of this and
 //   the stored value (earlier sub-steps of the step).
 // ---------------------------------------------------------------------------
-DEV double flat_raw(const double* pp, const double* v, int m) {
-  const double d1 = pp[m + 1] - pp[m - 1], d2 = pp[m + 2] - pp[m - 2];
-  if (!(::fabs(d1) > 0.33 * ::fmin(pp[m + 1], pp[m - 1])) || !(v[m - 1] - v[m + 1] > 0.0))
-    return 0.0;
-  return ::fmax(0.0, ::fmin(1.0, 10.0 * (::fabs(d1) / ::fmax(::fabs(d2), 1e-300) - 0.75)));
+// f at one cell from the pressures one (p1, m1) and two (p2, m2) cells
+// above and below it and the velocities one cell below and above
+template <class T>
+DEV T flat_raw(const T& p1, const T& m1, const T& p2, const T& m2, double vm, double vp) {
+  const T d1 = p1 - m1, d2 = p2 - m2;
+  if (!(val(fabs(d1)) > 0.33 * val(fmin(p1, m1))) || !(vm - vp > 0.0)) return T(0.0);
+  return fmax(0.0, fmin(1.0, 10.0 * (fabs(d1) / fmax(fabs(d2), 1e-300) - 0.75)));
 }
 
-DEV double flat_tilde(const double* pp, const double* v) {
-  const double f0 = flat_raw(pp, v, 0);
-  const int up = (pp[1] - pp[-1] < 0.0) ? 1 : -1;
-  return ::fmax(f0, flat_raw(pp, v, up));
+// pp[-3..3], v[-2..2] around the cell: f there, then the larger of it and
+// f at the neighbour on the high-pressure side
+template <class T>
+DEV T flat_tilde(const T* pp, const double* v) {
+  const T f0 = flat_raw(pp[1], pp[-1], pp[2], pp[-2], v[-1], v[1]);
+  // both neighbours formed, then the one above or below taken: a select of
+  // operands would become an indexed load and move the arrays to scratch
+  const T fa = flat_raw(pp[2], pp[0], pp[3], pp[-1], v[0], v[2]);
+  const T fb = flat_raw(pp[0], pp[-2], pp[1], pp[-3], v[-2], v[0]);
+  return fmax(f0, val(pp[1] - pp[-1]) < 0.0 ? fa : fb);
+}
+
+// x / 3, the value rounded as the plain division (a dual number's division
+// by a constant multiplies by its reciprocal)
+DEV double third(double x) { return x / 3.0; }
+template <int N>
+DEV Dual<N> third(const Dual<N>& x) {
+  Dual<N> r;
+  r.v = x.v / 3.0;
+#pragma unroll
+  for (int i = 0; i < N; i++) r.d[i] = x.d[i] / 3.0;
+  return r;
+}
+
+// Specific mass flux sqrt(-g) u^d from the cell's own metric and u~
+DEV double mass_flux_of(const Metric& met, const double ut[3], int d) {
+  Vel<double> v;
+  make_vel(met, ut, v);
+  return met.gdet * v.ucon[d + 1];
 }
 
 // The flattener's velocities on a Kerr-Schild grid, once per cell: the
@@ -690,6 +717,71 @@ __global__ void LB(256) k_mass_flux(Ctx C, const double* __restrict__ P, double*
   for (int d = 0; d < 3; d++) mf[(long)(3 + d) * C.Ntot + c] = met.gdet * v.ucon[d + 1];
 }
 
+// The flattener's velocity of one kind (0 gas, 1 radiation) along d at cell
+// cm: on Kerr-Schild the mass flux of k_mass_flux (mf), or with FORM (mf
+// null) formed here the same way; u~^d in flat space.
+template <bool FORM>
+DEV double flat_vel(const Ctx& C, const double* __restrict__ P, const double* __restrict__ mf,
+                    long cm, int d, int kind) {
+  const int base = kind ? 9 : 2;
+  if (!FORM) return mf ? mf[(long)(3 * kind + d) * C.Ntot + cm] : P[(long)(base + d) * C.Ntot + cm];
+  if (C.metric != GRRMHD_KERR_SCHILD) return P[(long)(base + d) * C.Ntot + cm];
+  Metric met;
+  load_metric(C.geo_c, C.npos, (int)(cm % C.npos), met);
+  double ut[3];
+#pragma unroll
+  for (int a = 0; a < 3; a++) ut[a] = P[(long)(base + a) * C.Ntot + cm];
+  return mass_flux_of(met, ut, d);
+}
+
+// Flattener of cell c along d for both kinds (f2[0] gas, f2[1] radiation),
+// before the larger-over-sub-steps rule.  With T a dual number, the cell at
+// offset ms (-3..3) takes (u_g, Ebar, rho, kappa_tot) from sd and every other
+// cell is a constant (the forward passes an ms outside the stencil); the
+// velocities enter only through the compression test (FORM: see flat_vel).
+template <class T, bool FORM>
+DEV void flat_dir(const Ctx& C, const double* __restrict__ P, const double* __restrict__ chi_abs,
+                  const double* __restrict__ chi_es, const double* __restrict__ mf, long c, int d,
+                  int ms, const T* sd, T f2[2]) {
+  const long st = C.st[d];
+  const int sq = sym(d + 1, d + 1);
+  T pg7[7], pr7[7], w0 = T(0.0);
+  double vg5[5], vr5[5];
+#pragma unroll
+  for (int m = -3; m <= 3; m++) {
+    const long cm = c + m * st;
+    const int pos = (int)(cm % ((long)C.N[0] * C.N[1]));
+    const double gdd = C.geo_c[(GE_GCOV + sq) * C.npos + pos];
+    T ug, E, rho, chi;
+    if (m == ms) {
+      ug = sd[0];
+      E = sd[1];
+      rho = sd[2];
+      chi = sd[3];
+    } else {
+      ug = T(P[C.Ntot + cm]);
+      E = T(P[8 * C.Ntot + cm]);
+      rho = T(P[cm]);
+      chi = T(chi_abs[cm] + chi_es[cm]);
+    }
+    const T tau = chi * rho * ::sqrt(gdd) * C.dx[d];
+    const T w = fmin(1.0, 2.0 * tau);
+    const T p_g = (C.gam - 1.0) * ug, p_r = third(E);
+    pg7[m + 3] = p_g + w * p_r;
+    pr7[m + 3] = p_r + w * p_g;
+    if (m == 0) w0 = w;
+    if (m >= -2 && m <= 2) {
+      vg5[m + 2] = flat_vel<FORM>(C, P, mf, cm, d, 0);
+      vr5[m + 2] = flat_vel<FORM>(C, P, mf, cm, d, 1);
+    }
+  }
+  // centred arrays
+  const T fg = flat_tilde(pg7 + 3, vg5 + 2), fr = flat_tilde(pr7 + 3, vr5 + 2);
+  const T fm = fmax(fg, fr);
+  f2[0] = (1.0 - w0) * fg + w0 * fm;
+  f2[1] = (1.0 - w0) * fr + w0 * fm;
+}
+
 // mf: the mass fluxes of k_mass_flux (Kerr-Schild), null in flat space
 DEV void flatten_at(Ctx C, const double* __restrict__ P, const double* __restrict__ chi_abs,
                     const double* __restrict__ chi_es, double* __restrict__ fl, int keep, long t,
@@ -708,38 +800,8 @@ DEV void flatten_at(Ctx C, const double* __restrict__ P, const double* __restric
   const long c = cell_index(C, i, j, k);
   for (int d = 0; d < 3; d++) {
     if (C.n[d] == 1) continue;
-    const long st = C.st[d];
-    const int sq = sym(d + 1, d + 1);
-    double pg7[7], pr7[7], vg5[5], vr5[5], w0 = 0.0;
-#pragma unroll
-    for (int m = -3; m <= 3; m++) {
-      const long cm = c + m * st;
-      const int pos = (int)(cm % ((long)C.N[0] * C.N[1]));
-      const double gdd = C.geo_c[(GE_GCOV + sq) * C.npos + pos];
-      const double rho = P[cm];
-      const double tau = (chi_abs[cm] + chi_es[cm]) * rho * ::sqrt(gdd) * C.dx[d];
-      const double w = ::fmin(1.0, 2.0 * tau);
-      const double p_g = (C.gam - 1.0) * P[C.Ntot + cm], p_r = P[8 * C.Ntot + cm] / 3.0;
-      pg7[m + 3] = p_g + w * p_r;
-      pr7[m + 3] = p_r + w * p_g;
-      if (m == 0) w0 = w;
-      if (m >= -2 && m <= 2) {
-        if (mf) {
-          // the specific mass fluxes sqrt(-g) u^d of gas and radiation
-          vg5[m + 2] = mf[(long)d * C.Ntot + cm];
-          vr5[m + 2] = mf[(long)(3 + d) * C.Ntot + cm];
-        } else {
-          // flat space: u^d = u~^d, sqrt(-g) = 1
-          vg5[m + 2] = P[(2 + d) * C.Ntot + cm];
-          vr5[m + 2] = P[(9 + d) * C.Ntot + cm];
-        }
-      }
-    }
-    // flat_raw indexes pressures at m +- 2 and velocities at m +- 1 around m
-    // in {-1, 0, 1}: centre the arrays
-    const double fg = flat_tilde(pg7 + 3, vg5 + 2), fr = flat_tilde(pr7 + 3, vr5 + 2);
-    const double fm = ::fmax(fg, fr);
-    const double f2[2] = {(1.0 - w0) * fg + w0 * fm, (1.0 - w0) * fr + w0 * fm};
+    double f2[2];
+    flat_dir<double, false>(C, P, chi_abs, chi_es, mf, c, d, 99, nullptr, f2);
 #pragma unroll
     for (int kind = 0; kind < 2; kind++) {
       double* dst = fl + (long)(2 * d + kind) * C.Ntot + c;

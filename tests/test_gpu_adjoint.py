@@ -175,13 +175,13 @@ def test_explicit_vjp_against_fd(G):
     g.close()
 
 
-def _step_check(G, orc, pd, P, ca, ce, ncomp, n_oracle, tol, kinks=0, f=1.0):
+def _step_check(G, orc, pd, P, ca, ce, ncomp, n_oracle, tol, kinks=0, f=1.0, cells=None):
     """f scales the difference step.  kinks > 0: also difference with a step
     a third as long and drop (at most `kinks`) components where the two
     disagree by more than 1e-4: there a step straddles a limiter switch, where
     the step has no derivative, or a small field's step leaves the
     difference to rounding (a test on the differences alone, not on the
-    adjoint)."""
+    adjoint).  cells: the interior cells to sample (default all)."""
     g = G.Grid(pd)
     cat, cet = dev(ca), dev(ce)
     dt, nfail = step_dt(G, g, P, cat, cet)
@@ -205,7 +205,8 @@ def _step_check(G, orc, pd, P, ca, ce, ncomp, n_oracle, tol, kinks=0, f=1.0):
         return host(Uw)[:, idx]
 
     scale = np.abs(P[:, idx]).max(axis=1)
-    comps = [(int(r.integers(12)), int(idx[r.integers(idx.size)])) for _ in range(ncomp)]
+    pool = idx if cells is None else np.asarray(cells)
+    comps = [(int(r.integers(12)), int(pool[r.integers(pool.size)])) for _ in range(ncomp)]
     fdg = fd_rows(comps, P, scale, U_gpu, w[:, idx], f=f)
     if kinks:
         fd3 = fd_rows(comps, P, scale, U_gpu, w[:, idx], f=f / 3)
@@ -303,14 +304,15 @@ def test_autograd_function(G, keep, scheme):
     g.close()
 
 
-def _chi_check(G, orc, pd, P, ca, ce, ncomp, n_oracle, tol, rel_h=1e-6):
+def _chi_check(G, orc, pd, P, ca, ce, ncomp, n_oracle, tol, rel_h=1e-6, cells=None):
     """dL/dchi_abs and dL/dchi_es from the adjoint against central
     differences of the GPU step (and of the oracle's on a few components):
     interior cells and the first ghost layer along x1 (read by the faces).
     The step's response to an opacity is weak where the cell is optically
     thick or thin, so its round-off (ulp-level changes of the implicit
     solutions, ~1e-10 in L) sets the difference quotient's floor: rel_h is
-    the relative step, tol the norm bound it supports."""
+    the relative step, tol the norm bound it supports.  cells: the cells to
+    sample (default the interior and that ghost layer)."""
     g = G.Grid(pd)
     cat, cet = dev(ca), dev(ce)
     dt, _ = step_dt(G, g, P, cat, cet)
@@ -322,7 +324,8 @@ def _chi_check(G, orc, pd, P, ca, ce, ncomp, n_oracle, tol, rel_h=1e-6):
     gc = host(gc)
     na = I.nalloc(pd)
     ghost = idx - 1 if pd["n"][0] > 1 else idx          # x1 neighbour (a ghost at the inner edge)
-    cand = np.concatenate([idx, ghost[idx % na[0] == 2]])
+    cand = (np.concatenate([idx, ghost[idx % na[0] == pd["ng"]]]) if cells is None
+            else np.asarray(cells))
 
     def U_gpu(ca_, ce_):
         Pw = dev(P)

@@ -140,7 +140,5 @@ def test_ppm_guards(G):
     pd, P, ca, ce = CASES["disk3d"]()
     with pytest.raises(RuntimeError):
         G.Grid(dict(pd, ng=2))
-    g = G.Grid(pd)
     with pytest.raises(RuntimeError):
-        g.step_adjoint(dev(P), dev(ca), dev(ce), dev(np.array([0.01])), dev(np.zeros_like(P)))
-    g.close()
+        G.Grid(dict(pd, ng=3))
