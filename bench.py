@@ -19,7 +19,8 @@ events on its stream inside the timed region.  cpu_baseline: the FP64 oracle
 stepping the same workload on the host cores (bounded sample).
 adjoint: the adjoint of one FP64 step of the 96x48x24 Kerr-Schild disk
 (dt held fixed), its time per call next to the forward step's, and a
-directional-derivative check of it on the GPU.  implicit_batch
+directional-derivative check of it on the GPU; the same for IMEX3 and for
+PPM reconstruction.  implicit_batch
 (--batch-cells): the batched implicit solve in each execution form.
 """
 import argparse
@@ -189,9 +190,9 @@ GROUPS = [(0,), (1,), (2, 3, 4), (5, 6, 7), (8,), (9, 10, 11)]
 FIELDS = ["rho", "u_g", "u1", "u2", "u3", "B1", "B2", "B3", "Ebar", "ur1", "ur2", "ur3"]
 
 
-def bench_adjoint(G, I, torch, dev, reps=5, warmup=2, h=1e-7, scheme="rk3"):
-    """Adjoint of one FP64 step (RK3, or the scheme named) of the 96x48x24
-    Kerr-Schild disk, dt held
+def bench_adjoint(G, I, torch, dev, reps=5, warmup=2, h=1e-7, scheme="rk3", recon="mc"):
+    """Adjoint of one FP64 step (RK3, or the scheme named; MC, or PPM with
+    four ghost cells) of the 96x48x24 Kerr-Schild disk, dt held
     fixed (the forward step recomputed with its stage checkpoints, then the
     reverse sweep): ms per call and the forward step's ms, both from HIP
     events on the library's stream; and <gP, v> against the central
@@ -203,7 +204,8 @@ def bench_adjoint(G, I, torch, dev, reps=5, warmup=2, h=1e-7, scheme="rk3"):
     import numpy as np
 
     n = (96, 48, 24)
-    pd, P, ca, ce = I.accretion_disk(n=n, seed=3)
+    kw = dict(ng=4, recon="ppm") if recon == "ppm" else {}
+    pd, P, ca, ce = I.accretion_disk(n=n, seed=3, **kw)
     pd = dict(pd, scheme=scheme)
     P = I.jitter(P, 11)
     g = G.Grid(pd)
@@ -267,7 +269,7 @@ def bench_adjoint(G, I, torch, dev, reps=5, warmup=2, h=1e-7, scheme="rk3"):
     ad = float((gP * vt).sum())
     fd = (L(Pt + h * vt) - L(Pt - h * vt)) / (2 * h)
     g.close()
-    return {"grid": list(n), "scheme": scheme, "ms_per_adjoint": ms_adj, "ms_per_adjoint_with_opacity_grad": ms_adj_chi,
+    return {"grid": list(n), "scheme": scheme, "recon": recon, "ms_per_adjoint": ms_adj, "ms_per_adjoint_with_opacity_grad": ms_adj_chi,
             "ms_forward_step": ms_fwd, "time_vs_forward": ms_adj / ms_fwd,
             "ms_forward_with_checkpoints": ms_ckpt, "ms_reverse_from_checkpoints": ms_rev,
             "directional_check": {"adjoint": ad, "central_difference": fd, "h": h,
@@ -435,7 +437,8 @@ def main():
         return
     if args.adjoint_only:
         print(json.dumps({"adjoint": bench_adjoint(G, I, torch, dev),
-                          "adjoint_imex3": bench_adjoint(G, I, torch, dev, scheme="imex3")}))
+                          "adjoint_imex3": bench_adjoint(G, I, torch, dev, scheme="imex3"),
+                          "adjoint_ppm": bench_adjoint(G, I, torch, dev, recon="ppm")}))
         return
     if args.copy_probe_mb:
         src = torch.ones(args.copy_probe_mb * (1 << 20) // 8, dtype=torch.float64, device=dev)
@@ -511,9 +514,10 @@ def main():
 
     adj = None if args.no_adjoint else bench_adjoint(G, I, torch, dev)
     adj3 = None if args.no_adjoint else bench_adjoint(G, I, torch, dev, scheme="imex3")
+    adjp = None if args.no_adjoint else bench_adjoint(G, I, torch, dev, recon="ppm")
     if adj:
-        print(f"adjoint: {adj['ms_per_adjoint']:.3f} ms/call (IMEX3 {adj3['ms_per_adjoint']:.3f})",
-              file=sys.stderr, flush=True)
+        print(f"adjoint: {adj['ms_per_adjoint']:.3f} ms/call (IMEX3 {adj3['ms_per_adjoint']:.3f}, "
+              f"PPM {adjp['ms_per_adjoint']:.3f})", file=sys.stderr, flush=True)
 
     # dominant kernel: the implicit kernel of each stage, timed with HIP events
     # on its stream inside the timed region
@@ -651,6 +655,7 @@ def main():
         "fiducial_256x128x64": fid,
         "adjoint": adj,
         "adjoint_imex3": adj3,
+        "adjoint_ppm": adjp,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

@@ -963,10 +963,12 @@ __global__ void LB(256) k_adj_flat_cot(Ctx C, FaceRanges FR, const double* __res
 // along a direction whose cotangent Lf2 is not zero, differentiated (one
 // Dual<4> pass of the forward's flattener) with respect to c's u_g, Ebar,
 // rho and total opacity; added to lamPb and (non-null) to both opacity
-// cotangents gchi [2][Ntot].
+// cotangents gchi [2][Ntot].  mf: the mass fluxes of P (k_mass_flux) on a
+// Kerr-Schild grid, null in flat space.
 __global__ void LB(128) k_adj_flat(Ctx C, const double* __restrict__ P,
                                    const double* __restrict__ chi_abs,
                                    const double* __restrict__ chi_es,
+                                   const double* __restrict__ mf,
                                    const double* __restrict__ Lf2, double* __restrict__ lamPb,
                                    double* __restrict__ gchi) {
   const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -997,7 +999,7 @@ __global__ void LB(128) k_adj_flat(Ctx C, const double* __restrict__ P,
       sd[2] = D4::var(P[c], 2);
       sd[3] = D4::var(chi_abs[c] + chi_es[c], 3);
       D4 f2[2];
-      flat_dir<D4, true>(C, P, chi_abs, chi_es, nullptr, cp, d, m, sd, f2);
+      flat_dir<D4>(C, P, chi_abs, chi_es, mf, cp, d, m, sd, f2);
 #pragma unroll
       for (int a = 0; a < 4; a++) acc[a] += Lg * f2[0].d[a] + Lr * f2[1].d[a];
       any = true;

@@ -1200,8 +1200,17 @@ static int adj_explicit(grrmhd_grid* g, double scale, const double* dt_dev, cons
     hipLaunchKernelGGL(k_adj_flat_cot, dim3(nblocks(C.Ntot, 256)), dim3(256), 0, s, C, FR,
                        (const double*)GF, fl, FLT->prev, FLT->LamFl, FLT->Lf2);
     LAUNCHCHK();
+    // the compression test's velocities (no derivative): on Kerr-Schild the
+    // mass fluxes of Pb, formed in the grid's flattener buffer as the forward
+    // does
+    double* mf = nullptr;
+    if (C.metric == GRRMHD_KERR_SCHILD) {
+      mf = g->flat + 6 * N;
+      hipLaunchKernelGGL(k_mass_flux, dim3(nblocks(C.Ntot, 256)), dim3(256), 0, s, C, Pb, mf);
+      LAUNCHCHK();
+    }
     hipLaunchKernelGGL(k_adj_flat, dim3(nblocks(C.Ntot, 128)), dim3(128), 0, s, C, Pb, ca, ce,
-                       (const double*)FLT->Lf2, lamPb, gchi);
+                       (const double*)mf, (const double*)FLT->Lf2, lamPb, gchi);
     LAUNCHCHK();
   }
   return 0;

@@ -688,13 +688,6 @@ DEV Dual<N> third(const Dual<N>& x) {
   return r;
 }
 
-// Specific mass flux sqrt(-g) u^d from the cell's own metric and u~
-DEV double mass_flux_of(const Metric& met, const double ut[3], int d) {
-  Vel<double> v;
-  make_vel(met, ut, v);
-  return met.gdet * v.ucon[d + 1];
-}
-
 // The flattener's velocities on a Kerr-Schild grid, once per cell: the
 // specific mass fluxes sqrt(-g) u^d of the gas (mf[d]) and the radiation
 // (mf[3 + d]), d = 0..2, from the cell's own metric.
@@ -718,28 +711,19 @@ __global__ void LB(256) k_mass_flux(Ctx C, const double* __restrict__ P, double*
 }
 
 // The flattener's velocity of one kind (0 gas, 1 radiation) along d at cell
-// cm: on Kerr-Schild the mass flux of k_mass_flux (mf), or with FORM (mf
-// null) formed here the same way; u~^d in flat space.
-template <bool FORM>
+// cm: the mass flux of k_mass_flux (mf, Kerr-Schild), u~^d in flat space
+// (mf null).
 DEV double flat_vel(const Ctx& C, const double* __restrict__ P, const double* __restrict__ mf,
                     long cm, int d, int kind) {
-  const int base = kind ? 9 : 2;
-  if (!FORM) return mf ? mf[(long)(3 * kind + d) * C.Ntot + cm] : P[(long)(base + d) * C.Ntot + cm];
-  if (C.metric != GRRMHD_KERR_SCHILD) return P[(long)(base + d) * C.Ntot + cm];
-  Metric met;
-  load_metric(C.geo_c, C.npos, (int)(cm % C.npos), met);
-  double ut[3];
-#pragma unroll
-  for (int a = 0; a < 3; a++) ut[a] = P[(long)(base + a) * C.Ntot + cm];
-  return mass_flux_of(met, ut, d);
+  return mf ? mf[(long)(3 * kind + d) * C.Ntot + cm] : P[(long)((kind ? 9 : 2) + d) * C.Ntot + cm];
 }
 
 // Flattener of cell c along d for both kinds (f2[0] gas, f2[1] radiation),
 // before the larger-over-sub-steps rule.  With T a dual number, the cell at
 // offset ms (-3..3) takes (u_g, Ebar, rho, kappa_tot) from sd and every other
 // cell is a constant (the forward passes an ms outside the stencil); the
-// velocities enter only through the compression test (FORM: see flat_vel).
-template <class T, bool FORM>
+// velocities enter only through the compression test.
+template <class T>
 DEV void flat_dir(const Ctx& C, const double* __restrict__ P, const double* __restrict__ chi_abs,
                   const double* __restrict__ chi_es, const double* __restrict__ mf, long c, int d,
                   int ms, const T* sd, T f2[2]) {
@@ -771,8 +755,8 @@ DEV void flat_dir(const Ctx& C, const double* __restrict__ P, const double* __re
     pr7[m + 3] = p_r + w * p_g;
     if (m == 0) w0 = w;
     if (m >= -2 && m <= 2) {
-      vg5[m + 2] = flat_vel<FORM>(C, P, mf, cm, d, 0);
-      vr5[m + 2] = flat_vel<FORM>(C, P, mf, cm, d, 1);
+      vg5[m + 2] = flat_vel(C, P, mf, cm, d, 0);
+      vr5[m + 2] = flat_vel(C, P, mf, cm, d, 1);
     }
   }
   // centred arrays
@@ -801,7 +785,7 @@ DEV void flatten_at(Ctx C, const double* __restrict__ P, const double* __restric
   for (int d = 0; d < 3; d++) {
     if (C.n[d] == 1) continue;
     double f2[2];
-    flat_dir<double, false>(C, P, chi_abs, chi_es, mf, c, d, 99, nullptr, f2);
+    flat_dir<double>(C, P, chi_abs, chi_es, mf, c, d, 99, nullptr, f2);
 #pragma unroll
     for (int kind = 0; kind < 2; kind++) {
       double* dst = fl + (long)(2 * d + kind) * C.Ntot + c;
