@@ -509,8 +509,14 @@ static int launch_flattener(grrmhd_grid* g, const double* P, const double* ca, c
     hipLaunchKernelGGL(k_mass_flux, dim3(nblocks(C.Ntot, 256)), dim3(256), 0, g->stream, C, P, mf);
     LAUNCHCHK();
   }
-  long nb = 1;
-  for (int e = 0; e < 3; e++) nb *= C.n[e] > 1 ? C.n[e] + 2 : 1;
+  long nb = 1;   // (cell, active direction) pairs
+  int nd = 0;
+  for (int e = 0; e < 3; e++) {
+    nb *= C.n[e] > 1 ? C.n[e] + 2 : 1;
+    nd += C.n[e] > 1;
+  }
+  nb *= nd;
+  if (nb == 0) return 0;
   hipLaunchKernelGGL(k_flatten, dim3(nblocks(nb, 256)), dim3(256), 0, g->stream, C, P, ca, ce,
                      g->flat, keep_flat, (const double*)mf);
   LAUNCHCHK();

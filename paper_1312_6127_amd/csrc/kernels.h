@@ -766,7 +766,11 @@ DEV void flat_dir(const Ctx& C, const double* __restrict__ P, const double* __re
   f2[1] = (1.0 - w0) * fr + w0 * fm;
 }
 
-// mf: the mass fluxes of k_mass_flux (Kerr-Schild), null in flat space
+// One thread per (cell, active direction): t runs over the cells within one
+// of the interior for the first active direction, then the next (the
+// directions' chains of loads overlap across threads rather than following
+// one another in a thread).  mf: the mass fluxes of k_mass_flux
+// (Kerr-Schild), null in flat space.
 DEV void flatten_at(Ctx C, const double* __restrict__ P, const double* __restrict__ chi_abs,
                     const double* __restrict__ chi_es, double* __restrict__ fl, int keep, long t,
                     const double* __restrict__ mf) {
@@ -776,21 +780,23 @@ DEV void flatten_at(Ctx C, const double* __restrict__ P, const double* __restric
     lo[e] = C.n[e] > 1 ? C.ng[e] - 1 : 0;
     cnt[e] = C.n[e] > 1 ? C.n[e] + 2 : 1;
   }
-  if (t >= (long)cnt[0] * cnt[1] * cnt[2]) return;
+  const long ncell = (long)cnt[0] * cnt[1] * cnt[2];
+  int slot = (int)(t / ncell), d = -1;
+  for (int e = 0; e < 3; e++)
+    if (C.n[e] > 1 && slot-- == 0) d = e;
+  if (d < 0) return;
+  t -= (t / ncell) * ncell;
   const int i = lo[0] + t % cnt[0];
   const long t2 = t / cnt[0];
   const int j = lo[1] + t2 % cnt[1];
   const int k = lo[2] + t2 / cnt[1];
   const long c = cell_index(C, i, j, k);
-  for (int d = 0; d < 3; d++) {
-    if (C.n[d] == 1) continue;
-    double f2[2];
-    flat_dir<double>(C, P, chi_abs, chi_es, mf, c, d, 99, nullptr, f2);
+  double f2[2];
+  flat_dir<double>(C, P, chi_abs, chi_es, mf, c, d, 99, nullptr, f2);
 #pragma unroll
-    for (int kind = 0; kind < 2; kind++) {
-      double* dst = fl + (long)(2 * d + kind) * C.Ntot + c;
-      *dst = keep ? ::fmax(*dst, f2[kind]) : f2[kind];
-    }
+  for (int kind = 0; kind < 2; kind++) {
+    double* dst = fl + (long)(2 * d + kind) * C.Ntot + c;
+    *dst = keep ? ::fmax(*dst, f2[kind]) : f2[kind];
   }
 }
 
