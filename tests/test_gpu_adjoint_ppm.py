@@ -151,6 +151,19 @@ def test_step_adjoint_ppm_kerr_schild(G, orc):
     _step_check(G, orc, *disk_small_ppm(), ncomp=64, n_oracle=32, tol=1e-6, kinks=6, f=10.0)
 
 
+def test_step_adjoint_ppm_kerr_schild_ramp(G, orc):
+    """The 32x8x4 Kerr-Schild disk, whose steep radial profiles put
+    flattener values on the ramp near the inner edge and further out (the
+    compression test reads the mass fluxes sqrt(-g) u^r): components around
+    them against GPU and oracle differences."""
+    say("case step adjoint, PPM Kerr-Schild 32x8x4, flattener ramp")
+    pd, P, ca, ce = I.accretion_disk(n=(32, 8, 4), seed=3, ng=4, recon="ppm")
+    P = I.jitter(P, 11)
+    cells = _ramp_cells(orc, pd, P, ca, ce)
+    _step_check(G, orc, pd, P, ca, ce, ncomp=48, n_oracle=16, tol=1e-6, kinks=8, f=10.0,
+                cells=cells)
+
+
 @pytest.mark.parametrize("scheme", ["imex2", "imex3"])
 def test_step_adjoint_ppm_imex(G, orc, scheme):
     """IMEX stage tables with PPM: the flattener is the largest over the
