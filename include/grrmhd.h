@@ -151,8 +151,8 @@ typedef struct {
                            on the cell-centred field, stepped by grrmhd_step;
                            GRRMHD_CT_STAGGERED: the face-centred field with
                            four-state corner EMFs (Del Zanna et al. 2007),
-                           stepped by grrmhd_step_staggered (RK3 only; the
-                           adjoint is not available).                       */
+                           stepped by grrmhd_step_staggered (every scheme;
+                           the adjoint is not available).                   */
 } grrmhd_params;
 
 typedef struct grrmhd_grid grrmhd_grid;
@@ -234,8 +234,9 @@ int grrmhd_implicit_grid(grrmhd_grid *g, const double *Uexp, const double *Pgues
  * interior face neighbours if none is good, then GRRMHD_ST_NO_GOOD_NB);
  * cells with GRRMHD_ST_COLD take the same average of u_g alone; then floors
  * on rho0, u_g (b^2/rho0, b^2/u_g, u_g/rho0 limits) and Ebar; U is
- * recomputed where P changed.  `scratch` is device memory of at least 13 N
- * doubles. */
+ * recomputed where P changed.  On a staggered-field grid a failed cell's B
+ * is not averaged: it is its own conserved field over sqrt(-g) (the mean of
+ * its faces).  `scratch` is device memory of at least 13 N doubles. */
 int grrmhd_fixup(grrmhd_grid *g, double *P, double *U, int *status, double *scratch);
 
 /* One full time step of the grid's scheme (Sec. 4.1).  GRRMHD_RK3:
@@ -297,13 +298,16 @@ int grrmhd_fluxes_staggered(grrmhd_grid *g, const double *P, const double *Bf,
                             const double *chi_abs, const double *chi_es, double *F, double *emf,
                             double *vchar, void *workspace, size_t ws_bytes);
 
-/* One RK3 step (as grrmhd_step) with the staggered field: each stage's faces
- * are a Bf^n + b Bf^(k-1) + c dt (-circulation of the corner EMFs round the
- * face), so the discrete divergence of Bf never changes, and the stage's
- * cell-centred conserved field is the mean of the new faces; a failed cell's
- * neighbour average keeps its own field.  Bf in/out (evolved faces; ghost
- * faces are filled in place at the start).  P, U, dt, status, iters and
- * workspace as grrmhd_step. */
+/* One step of the grid's scheme (as grrmhd_step: RK3, or the IMEX tables of
+ * Sec. 4.1) with the staggered field: each stage's faces are a Bf^n +
+ * b Bf^(j) + c dt (-circulation of the corner EMFs round the face) with the
+ * stage's own coefficients (no EMF term in a stage without explicit fluxes;
+ * the implicit part leaves the field alone), so the discrete divergence of
+ * Bf never changes, and the stage's cell-centred conserved field is the mean
+ * of the new faces; a failed cell's neighbour average keeps its own field.
+ * Bf in/out (evolved faces; ghost faces are filled in place at the start).
+ * P, U, dt, status, iters and workspace as grrmhd_step (the workspace holds
+ * the faces of every stage but the last). */
 int grrmhd_step_staggered(grrmhd_grid *g, double *P, double *U, double *Bf,
                           const double *chi_abs, const double *chi_es, double *dt_dev,
                           int dt_fixed, int *status, int *iters, void *workspace,
@@ -386,7 +390,8 @@ int grrmhd_step_adjoint_saved(grrmhd_grid *g, const double *chi_abs, const doubl
  *                        (interior cells; zero at ghosts).  Failed cells'
  *                        neighbour averages and cold cells' u_g averages are
  *                        transposed, U = U(P) at changed cells by its local
- *                        Jacobian, floors as the identity.  scratch: [12][N]
+ *                        Jacobian, floors as the identity (flux-CT grids;
+ *                        EINVAL on a staggered-field grid).  scratch: [12][N]
  *                        doubles; no array may alias another;
  *  grrmhd_con2prim_vjp   of grrmhd_con2prim (Sec. 4.5, 4.6) at its result
  *                        (P, status): gU = (dP/dU)^T gP at interior cells

@@ -402,9 +402,12 @@ def fluxes_stag(pd, P, Bf, chi_abs, chi_es):
 
 
 def face_update(pd, a, b, c, dt, Bn, Bprev, emf, Bout=None):
+    """Faces a Bn + b Bprev + c dt (-curl emf); emf may be None when c = 0."""
     Bout = np.zeros_like(_f64(Bn)) if Bout is None else _f64(Bout).copy()
+    if emf is None and c != 0.0:
+        raise ValueError("face_update needs the EMFs when c != 0")
     lib().orc_face_update(C.byref(params(pd)), a, b, c, dt, _dp(_f64(Bn)), _dp(_f64(Bprev)),
-                          _dp(_f64(emf)), _dp(Bout))
+                          _dp(_f64(emf)) if emf is not None else None, _dp(Bout))
     return Bout
 
 
@@ -419,7 +422,7 @@ def step_stag(pd, P, U, Bf, chi_abs, chi_es, dt=0.0, dt_fixed=False):
     nbad = lib().orc_step_stag(C.byref(params(pd)), _dp(P), _dp(U), _dp(Bf), _dp(ca), _dp(ce),
                                _dp(dtv), 1 if dt_fixed else 0, _ip(st), _ip(it))
     if nbad < 0:
-        raise ValueError("staggered step needs ct='staggered' and the RK3 scheme")
+        raise ValueError("staggered step needs ct='staggered'")
     return P, U, Bf, float(dtv[0]), st, it, nbad
 
 

@@ -286,7 +286,8 @@ void orc_emf_stag(const orc_params *p, const double *Bf, const double *VF, const
  * Bout^p = a Bn^p + b Bprev^p + c dt (-sum_{d != p} d_d F^d[B^p]) on the
  * evolved faces, F^d[B^p] = +Phi_e (e = 3-p-d) when p = e+1 mod 3, else
  * -Phi_e; by Stokes' theorem each face's change is the circulation of the
- * EMF around it, so the discrete divergence of Bf never changes. */
+ * EMF around it, so the discrete divergence of Bf never changes.  c = 0 (an
+ * IMEX stage without explicit fluxes): no EMF term, emf may be NULL. */
 void orc_face_update(const orc_params *p, double a, double b, double c, double dt,
                      const double *Bn, const double *Bprev, const double *emf, double *Bout) {
   const long N = orc_ncell_alloc(p);
@@ -302,7 +303,7 @@ void orc_face_update(const orc_params *p, double a, double b, double c, double d
         for (int i = lo[0]; i <= hi[0]; i++) {
           const long f = IDX(p, i, j, k);
           double curl = 0.0;
-          for (int d = 0; d < 3; d++) {
+          for (int d = 0; d < 3 && c != 0.0; d++) {
             if (d == pd || p->n[d] == 1) continue;
             const int e = 3 - pd - d;
             const double s = ((e + 1) % 3 == pd) ? 1.0 : -1.0;
@@ -310,7 +311,7 @@ void orc_face_update(const orc_params *p, double a, double b, double c, double d
             curl += s * (E[f + stride(p, d)] - E[f]) / orc_dx(p, d);
           }
           const long o = (long)pd * N + f;
-          Bout[o] = a * Bn[o] + (b != 0.0 ? b * Bprev[o] : 0.0) - c * dt * curl;
+          Bout[o] = a * Bn[o] + (b != 0.0 ? b * Bprev[o] : 0.0) - (c != 0.0 ? c * dt * curl : 0.0);
         }
   }
 }

@@ -567,6 +567,9 @@ void orc_con2prim(const orc_params *p, const double *U, const double *Pguess, do
         }
         int st = 0;
         if (orc_mhd_invert(p, &g, Uc, Pg, Pc) != 0) st |= ORC_ST_C2P_FAIL;
+        /* B^i = U_B^i / sqrt(-g) needs no inversion: set also where the MHD
+         * inversion failed and the gas primitives stay at the guess */
+        for (int q = 5; q <= 7; q++) Pc[q] = Uc[q] / g.gdet;
         orc_rad_invert(p, &g, Uc, 0, Pc);
         for (int q = 0; q < 12; q++) P[q * N + c] = Pc[q];
         if (status) status[c] = st;
@@ -663,6 +666,11 @@ void orc_fixup(const orc_params *p, double *P, double *U, int *status) {
         orc_cell_x(p, i, j, &x1, &x2);
         orc_geom g;
         orc_geom_point(p, x1, x2, &g);
+        /* the staggered field of a failed cell: the stage's own (its conserved
+         * field over sqrt(-g), the mean of its new faces), not the guess that
+         * a failed solve or inversion returned */
+        if (fail && p->ct)
+          for (int q = 5; q <= 7; q++) P[q * N + c] = U[q * N + c] / g.gdet;
         double Pc[12];
         for (int q = 0; q < 12; q++) Pc[q] = P[q * N + c];
         /* floors: rho >= max(rho_floor, b^2/bsq_rho_max), u >= max(u_floor,
@@ -804,12 +812,14 @@ int orc_step(const orc_params *p, double *P, double *U, const double *chi_abs, c
   return orc_step_stag(p, P, U, NULL, chi_abs, chi_es, dt, dt_fixed, status, iters);
 }
 
-/* Bf (staggered field, p->ct = 1, RK3): the face field [3][N] in and out;
- * each stage's faces are a Bf^n + b Bf^(k-1) + c dt (-curl EMF) and the
- * stage's cell-centred conserved field their mean (Sec. 4.2 steps 8-10) */
+/* Bf (staggered field, p->ct = 1): the face field [3][N] in and out; each
+ * stage's faces are a Bf^n + b Bf^(j) + c dt (-curl EMF) with the stage's own
+ * coefficients (Sec. 4.1; no EMF term where c = 0, and the implicit part
+ * leaves the field alone), and the stage's cell-centred conserved field their
+ * mean (Sec. 4.2 steps 8-10) */
 int orc_step_stag(const orc_params *p, double *P, double *U, double *Bf, const double *chi_abs,
                   const double *chi_es, double *dt, int dt_fixed, int *status, int *iters) {
-  if ((Bf != NULL) != (p->ct != 0) || (Bf && p->scheme != ORC_RK3)) return -1;
+  if ((Bf != NULL) != (p->ct != 0)) return -1;
   const orc_scheme S = scheme_table(p->scheme);
   const long N = orc_ncell_alloc(p);
   const size_t B12 = sizeof(double) * 12 * N;
@@ -896,6 +906,11 @@ int orc_step_stag(const orc_params *p, double *P, double *U, double *Bf, const d
       }
     } else {
       for (long q = 0; q < 12 * N; q++) Uexp[q] = s->a * Un[q] + (s->b != 0.0 ? s->b * Uj[q] : 0.0);
+      if (Bf) {
+        orc_face_update(p, s->a, s->b, 0.0, *dt, Bn, (s->j >= 0) ? Bst[s->j] : Bn, NULL, Bst[i]);
+        orc_face_to_center(p, Bst[i], NULL, Uexp);
+        Bk = Bst[i];
+      }
     }
     for (int k = 0; k < i && k < 4; k++) {
       if (s->m[k] == 0.0) continue;

@@ -134,8 +134,6 @@ static int validate(const grrmhd_params* p, bool need_grid) {
   if (p->cascade != 0 && p->cascade != 1) return fail(GRRMHD_EINVAL, "cascade must be 0 or 1");
   if (p->ct != GRRMHD_CT_FLUX && p->ct != GRRMHD_CT_STAGGERED)
     return fail(GRRMHD_EINVAL, "ct must be GRRMHD_CT_FLUX or GRRMHD_CT_STAGGERED");
-  if (p->ct == GRRMHD_CT_STAGGERED && p->scheme != GRRMHD_RK3)
-    return fail(GRRMHD_EINVAL, "the staggered field steps with RK3 only");
   if (p->recon != GRRMHD_RECON_MC && p->recon != GRRMHD_RECON_PPM)
     return fail(GRRMHD_EINVAL, "bad reconstruction");
   if (!need_grid) return 0;
@@ -397,7 +395,7 @@ static Scheme make_scheme(int which) {
 }
 
 struct WsLayout {
-  size_t F, emf, vch, Uexp, Pa, Ua, err, st, it, Us, M, Fs, Sn, VF, SP, B1, B2, total;
+  size_t F, emf, vch, Uexp, Pa, Ua, err, st, it, Us, M, Fs, Sn, VF, SP, Bs, total;
 };
 
 // IMEX schemes add the stage U's (all but the last) and the kept M^k
@@ -431,13 +429,14 @@ static WsLayout ws_layout(const Ctx& C, int scheme = GRRMHD_RK3) {
     w.Fs = take(sizeof(double) * 3 * N);
     w.Sn = take(sizeof(double) * N);
   }
-  // the staggered field: face velocities and speeds, stage 1 and 2 faces
-  w.VF = w.SP = w.B1 = w.B2 = off;
+  // the staggered field: face velocities and speeds, and the faces of every
+  // stage but the last (which writes the caller's faces in place)
+  w.VF = w.SP = w.Bs = off;
   if (C.ct) {
+    const int ns = (scheme == GRRMHD_RK3) ? 3 : make_scheme(scheme).ns;
     w.VF = take(sizeof(double) * 18 * N);
     w.SP = take(sizeof(double) * 6 * N);
-    w.B1 = take(sizeof(double) * 3 * N);
-    w.B2 = take(sizeof(double) * 3 * N);
+    w.Bs = take(round256(sizeof(double) * 3 * N) * (ns - 1));
   }
   w.total = off;
   return w;
@@ -791,7 +790,11 @@ extern "C" int grrmhd_fixup(grrmhd_grid* g, double* P, double* U, int* status, d
 // One step of an IMEX scheme (stage table above).  The latest primitives
 // live in P (stage input of stage 0) or Pa; stage U's in the workspace; the
 // last stage writes P and U.
-static int imex_step(grrmhd_grid* g, double* P, double* U, const double* chi_abs,
+// One step of an IMEX stage table; Bf: the staggered field (the faces of
+// each stage a Bf^n + b Bf^(j) + c dt (-curl EMF), no EMF term where c = 0;
+// stage faces in the workspace, the last stage's written to Bf in place),
+// else null.
+static int imex_step(grrmhd_grid* g, double* P, double* U, double* Bf, const double* chi_abs,
                      const double* chi_es, double* dt_dev, int dt_fixed, int* status, int* iters,
                      char* base, const WsLayout& w) {
   const Ctx& C = g->C;
@@ -812,7 +815,19 @@ static int imex_step(grrmhd_grid* g, double* P, double* U, const double* chi_abs
     Mk[k] = (double*)(base + w.M + k * round256(sizeof(double) * 8 * N));
   }
   const long nint = n_interior(C);
+  double* VF = Bf ? (double*)(base + w.VF) : nullptr;
+  double* SP = Bf ? (double*)(base + w.SP) : nullptr;
+  const size_t b3 = round256(sizeof(double) * 3 * N);
+  auto Bst = [&](int i) { return (i == S.ns - 1) ? Bf : (double*)(base + w.Bs + i * b3); };
+  FaceRange RF;
+  RF.total = 1;
+  for (int e = 0; e < 3; e++) {
+    RF.lo[e] = C.ng[e];
+    RF.cnt[e] = C.n[e] > 1 ? C.n[e] + 1 : 1;
+    RF.total *= RF.cnt[e];
+  }
   double* Pcur = P;
+  double* Bcur = Bf;   // the faces of Pcur
   int rc, nflux = 0;
   for (int i = 0; i < S.ns; i++) {
     const Stage& x = S.s[i];
@@ -824,8 +839,24 @@ static int imex_step(grrmhd_grid* g, double* P, double* U, const double* chi_abs
     unsigned long long* dnext = red ? g->dtstep[g->dtp ^ 1] : nullptr;
     if (x.c != 0.0 || red) {
       if ((rc = launch_bc(g, Pcur))) return rc;
-      if ((rc = launch_fluxes(g, Pcur, chi_abs, chi_es, F, emf, vch, dmin, nflux > 0))) return rc;
+      if (Bf) {
+        hipLaunchKernelGGL(k_bc_faces, dim3(nblocks(3 * C.Ntot, 256)), dim3(256), 0, g->stream, C,
+                           Bcur);
+        LAUNCHCHK();
+      }
+      if ((rc = launch_fluxes(g, Pcur, chi_abs, chi_es, F, emf, vch, dmin, nflux > 0, nullptr,
+                              Bcur, VF, SP)))
+        return rc;
       nflux++;
+    }
+    if (Bf) {
+      // the stage's faces (before the cell update, which averages them); Bf
+      // is still Bf^n here (only the last stage writes it, face by face)
+      hipLaunchKernelGGL(k_face_update, dim3(nblocks(RF.total, 256)), dim3(256), 0, g->stream, C,
+                         RF, x.a, x.b, x.c, (const double*)dt_dev, (const unsigned long long*)dmin,
+                         (const double*)Bf, (const double*)(x.j >= 0 ? Bst(x.j) : Bf),
+                         (const double*)emf, Bst(i));
+      LAUNCHCHK();
     }
     MTerms MT;
     memset(&MT, 0, sizeof(MT));
@@ -836,7 +867,8 @@ static int imex_step(grrmhd_grid* g, double* P, double* U, const double* chi_abs
       MT.n++;
     }
     const double* Uj = (x.j >= 0) ? Us[x.j] : U;
-    if ((rc = launch_update(g, x.a, x.b, x.c, dt_dev, Pcur, U, Uj, F, emf, Ue, dmin, dnext, &MT)))
+    if ((rc = launch_update(g, x.a, x.b, x.c, dt_dev, Pcur, U, Uj, F, emf, Ue, dmin, dnext, &MT,
+                            Bf ? Bst(i) : nullptr)))
       return rc;
     if (red) g->dtp ^= 1;
     double* Pout = last ? P : Pa;
@@ -862,6 +894,7 @@ static int imex_step(grrmhd_grid* g, double* P, double* U, const double* chi_abs
       if ((rc = launch_fixup(g, Pout, Uout, st, Ue, status, nullptr, iters, i > 0))) return rc;
     }
     Pcur = Pout;
+    Bcur = Bf ? Bst(i) : nullptr;
   }
   return 0;
 }
@@ -882,7 +915,6 @@ static int rk3_step(grrmhd_grid* g, double* P, double* U, double* Bf, const doub
   int* st = (int*)(base + w.st);
   int* it = (int*)(base + w.it);
   const size_t N = (size_t)C.Ntot;
-  (void)N;
   // Shu-Osher RK3: U(k) = a U^n + b U(k-1) + c dt (X + M(U(k)))
   const double A[3] = {1.0, 0.75, 1.0 / 3.0}, B[3] = {0.0, 0.25, 2.0 / 3.0},
                Cc[3] = {1.0, 0.25, 2.0 / 3.0};
@@ -900,7 +932,9 @@ static int rk3_step(grrmhd_grid* g, double* P, double* U, double* Bf, const doub
   // staggered field: stage inputs Bf, B1, B2; outputs B1, B2, Bf
   double* VF = Bf ? (double*)(base + w.VF) : nullptr;
   double* SP = Bf ? (double*)(base + w.SP) : nullptr;
-  double* Bst[3] = {Bf ? (double*)(base + w.B1) : nullptr, Bf ? (double*)(base + w.B2) : nullptr, Bf};
+  const size_t b3 = round256(sizeof(double) * 3 * N);
+  double* Bst[3] = {Bf ? (double*)(base + w.Bs) : nullptr, Bf ? (double*)(base + w.Bs + b3) : nullptr,
+                    Bf};
   FaceRange RF;
   RF.total = 1;
   for (int e = 0; e < 3; e++) {
@@ -973,7 +1007,7 @@ extern "C" int grrmhd_step(grrmhd_grid* g, double* P, double* U, const double* c
   if (rc) return rc;
   char* base = (char*)workspace;
   if (g->p.scheme != GRRMHD_RK3)
-    return imex_step(g, P, U, chi_abs, chi_es, dt_dev, dt_fixed, status, iters, base, w);
+    return imex_step(g, P, U, nullptr, chi_abs, chi_es, dt_dev, dt_fixed, status, iters, base, w);
   return rk3_step(g, P, U, nullptr, chi_abs, chi_es, dt_dev, dt_fixed, status, iters, base, w);
 }
 
@@ -988,7 +1022,10 @@ extern "C" int grrmhd_step_staggered(grrmhd_grid* g, double* P, double* U, doubl
   WsLayout w;
   int rc = step_args(g, workspace, ws_bytes, w);
   if (rc) return rc;
-  return rk3_step(g, P, U, Bf, chi_abs, chi_es, dt_dev, dt_fixed, status, iters, (char*)workspace, w);
+  char* base = (char*)workspace;
+  if (g->p.scheme != GRRMHD_RK3)
+    return imex_step(g, P, U, Bf, chi_abs, chi_es, dt_dev, dt_fixed, status, iters, base, w);
+  return rk3_step(g, P, U, Bf, chi_abs, chi_es, dt_dev, dt_fixed, status, iters, base, w);
 }
 
 extern "C" int grrmhd_apply_bc_faces(grrmhd_grid* g, double* Bf) {
@@ -1306,6 +1343,7 @@ extern "C" int grrmhd_fixup_vjp(grrmhd_grid* g, const double* P, const int* stat
   NEEDG();
   if (!P || !status || !gP || !gU || !gP_pre || !gU_pre || !scratch)
     return fail(GRRMHD_EINVAL, "NULL array");
+  if (g->C.ct) return fail(GRRMHD_EINVAL, "the fix-up adjoint covers the flux-CT field");
   if (gP_pre == gP || gP_pre == gU || gU_pre == gP || gU_pre == gU || scratch == gP ||
       scratch == gU || scratch == gP_pre || scratch == gU_pre || gP_pre == gU_pre)
     return fail(GRRMHD_EINVAL, "fixup_vjp arrays must not alias");

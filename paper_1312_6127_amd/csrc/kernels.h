@@ -1741,6 +1741,8 @@ DEV void fixup_apply_at(Ctx C, double* __restrict__ P, double* __restrict__ U,
   bool changed = false;
   const bool fail = (st & GRRMHD_ST_FAIL) != 0;
   const bool cold = !fail && (st & GRRMHD_ST_COLD);
+  Metric m;
+  load_metric(C.geo_c, C.npos, i + C.N[0] * j, m);
   if ((fail || cold) && scr[12 * C.Ntot + c] > 0.0) {
     // failed: the neighbours' mean primitives; cold: their mean u_g alone
 #pragma unroll
@@ -1755,8 +1757,14 @@ DEV void fixup_apply_at(Ctx C, double* __restrict__ P, double* __restrict__ U,
 #pragma unroll
     for (int q = 0; q < 12; q++) p[q] = P[q * C.Ntot + c];
   }
-  Metric m;
-  load_metric(C.geo_c, C.npos, i + C.N[0] * j, m);
+  // the staggered field of a failed cell: the stage's own (its conserved
+  // field over sqrt(-g), the mean of its new faces), not the guess that a
+  // failed solve or inversion returned
+  const bool bnew = fail && C.ct;
+  if (bnew) {
+#pragma unroll
+    for (int q = 5; q <= 7; q++) p[q] = U[q * C.Ntot + c] / m.gdet;
+  }
   Gas<double> s;
   make_gas(m, C.gam, p[0], p[1], p + 2, p + 5, s);
   const double rmin = fmax(C.rho_floor, s.bsq / C.bsq_rho_max);
@@ -1775,6 +1783,9 @@ DEV void fixup_apply_at(Ctx C, double* __restrict__ P, double* __restrict__ U,
       P[q * C.Ntot + c] = p[q];
       U[q * C.Ntot + c] = u[q];
     }
+  } else if (bnew) {
+#pragma unroll
+    for (int q = 5; q <= 7; q++) P[q * C.Ntot + c] = p[q];
   }
   status[c] = st;
   if (st_acc) st_acc[c] = accumulate ? (st_acc[c] | st) : st;

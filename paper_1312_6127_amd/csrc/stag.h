@@ -280,7 +280,8 @@ __global__ void LB(256) k_emf_stag_dt(Ctx C, FaceRange R, const double* __restri
 // Sec. 4.2 step 10 for the faces: Bout^p = a Bn^p + b Bprev^p + c dt
 // (-sum_{d != p} d_d F^d[B^p]), F^d[B^p] = +Phi_e (e = 3-p-d) when p = e+1
 // mod 3, else -Phi_e, on the evolved faces ([ng, ng+n] along p, [ng, ng+n)
-// across).  dt: *dt_dev, or courant x the Courant slots' minimum.
+// across).  dt: *dt_dev, or courant x the Courant slots' minimum.  cc = 0
+// (an IMEX stage without explicit fluxes): no EMF term and no EMF read.
 // ---------------------------------------------------------------------------
 __global__ void LB(256) k_face_update(Ctx C, FaceRange R, double a, double b, double cc,
                                       const double* __restrict__ dt_dev,
@@ -299,7 +300,7 @@ __global__ void LB(256) k_face_update(Ctx C, FaceRange R, double a, double b, do
       if (d != pd && C.n[d] > 1 && idx[d] >= C.ng[d] + C.n[d]) in = false;
     if (!in) continue;
     double curl = 0.0;
-    for (int d = 0; d < 3; d++) {
+    for (int d = 0; d < 3 && cc != 0.0; d++) {
       if (d == pd || C.n[d] == 1) continue;
       const int e = 3 - pd - d;
       const double s = ((e + 1) % 3 == pd) ? 1.0 : -1.0;
@@ -307,6 +308,6 @@ __global__ void LB(256) k_face_update(Ctx C, FaceRange R, double a, double b, do
       curl += s * (E[f + C.st[d]] - E[f]) / C.dx[d];
     }
     const long o = (long)pd * C.Ntot + f;
-    Bout[o] = a * Bn[o] + (b != 0.0 ? b * Bprev[o] : 0.0) - cc * dt * curl;
+    Bout[o] = a * Bn[o] + (b != 0.0 ? b * Bprev[o] : 0.0) - (cc != 0.0 ? cc * dt * curl : 0.0);
   }
 }

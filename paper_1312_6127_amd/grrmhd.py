@@ -389,7 +389,8 @@ class Grid:
 
     def step_staggered(self, P, U, Bf, chi_abs, chi_es, dt, dt_fixed=False, status=None,
                        iters=None):
-        """One RK3 step with the staggered field, in place on P, U, Bf."""
+        """One step of the grid's scheme with the staggered field, in place on
+        P, U, Bf."""
         self._sync_stream()
         ws = self.workspace()
         _check(lib().grrmhd_step_staggered(self.h, _ptr(P), _ptr(U), _ptr(Bf), _ptr(chi_abs),

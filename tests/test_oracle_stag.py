@@ -100,8 +100,13 @@ def _consistent(orc, pd, P, Bf):
 # Stokes' theorem
 # ---------------------------------------------------------------------------
 
-def test_divergence_stays_at_roundoff_on_a_periodic_box(orc):
+@pytest.mark.parametrize("scheme", ["rk3", "imex2", "imex2b", "imex3"])
+def test_divergence_stays_at_roundoff_on_a_periodic_box(orc, scheme):
+    """Every stage's faces change by the circulation of its EMFs, also in
+    the IMEX tables (Sec. 4.1), whose stages without explicit fluxes combine
+    earlier faces linearly."""
     pd, P, Bf, ca, ce = _random_box((10, 8, 6), seed=11)
+    pd = dict(pd, scheme=scheme)
     Bf = orc.bc_face(pd, Bf)
     P, U = _consistent(orc, pd, P, Bf)
     scale = np.abs(Bf).max() / 0.1
@@ -197,6 +202,53 @@ def test_one_active_dimension_equals_flux_ct(orc, d, flux):
     assert np.abs(Bf[d, m] - 0.5).max() < 1e-15
     # the field's shock moved
     assert np.abs(Ua[5 + (d + 1) % 3, m] - U[5 + (d + 1) % 3, m]).max() > 0.1
+
+
+@pytest.mark.parametrize("d", [0, 2])
+@pytest.mark.parametrize("scheme", ["imex2", "imex2b", "imex3"])
+def test_one_active_dimension_equals_flux_ct_imex(orc, d, scheme):
+    """The IMEX tables: the faces of a stage without explicit fluxes are
+    a Bf^n + b Bf^(j), as flux-CT combines the cell-centred field."""
+    pd, P, ca, ce = _tube(d)
+    pd = dict(pd, scheme=scheme)
+    U = orc.prim_to_cons(pd, P)
+    ps = _stag(pd)
+    Bf = np.zeros((3, P.shape[1]))
+    Bf[:] = U[5:8]
+    Bf = orc.bc_face(ps, Bf)
+    Pa, Ua, Pb, Ub = P, U, P, U
+    for _ in range(4):
+        Pa, Ua, dta, sa, _, na_ = orc.step(pd, Pa, Ua, ca, ce)
+        Pb, Ub, Bf, dtb, sb, _, nb_ = orc.step_stag(ps, Pb, Ub, Bf, ca, ce)
+        assert na_ == 0 and nb_ == 0 and abs(dta / dtb - 1) < 1e-14
+    m = _interior(pd)
+    for grp in ((0,), (1,), (2, 3, 4), (5, 6, 7), (8,), (9, 10, 11)):
+        for A, B in ((Pa, Pb), (Ua, Ub)):
+            sc = np.abs(A[list(grp)][:, m]).max() + 1e-300
+            assert np.abs(A[list(grp)][:, m] - B[list(grp)][:, m]).max() / sc < 1e-12, grp
+    for t in range(3):
+        if t != d:
+            assert np.abs(Bf[t, m] - Ua[5 + t, m]).max() < 1e-12 * np.abs(Ua[5 + t, m]).max()
+    assert np.abs(Ua[5 + (d + 1) % 3, m] - U[5 + (d + 1) % 3, m]).max() > 0.05
+
+
+def test_face_update_without_fluxes_combines_faces(orc):
+    """c = 0: a Bn + b Bprev exactly on every evolved face, with no EMF
+    read, and nothing written elsewhere."""
+    pd, P, Bf, ca, ce = _random_box((6, 5, 4), seed=3)
+    pd = _stag(pd)
+    B1 = np.random.default_rng(1).standard_normal(Bf.shape)
+    out = orc.face_update(pd, 2.0, -1.0, 0.0, 0.3, Bf, B1, None)
+    want = 2.0 * Bf - 1.0 * B1
+    na = I.nalloc(pd)
+    g = pd["ng"]
+    for p in range(3):
+        ev = np.zeros(tuple(na[::-1]), bool)   # [x3][x2][x1]
+        sl = [slice(g, g + pd["n"][d] + (1 if d == p else 0)) for d in range(3)]
+        ev[sl[2], sl[1], sl[0]] = True
+        ev = ev.reshape(-1)
+        assert np.array_equal(out[p, ev], want[p, ev])
+        assert np.all(out[p, ~ev] == 0.0)
 
 
 # ---------------------------------------------------------------------------
