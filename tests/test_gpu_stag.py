@@ -273,6 +273,8 @@ def test_staggered_entry_points_check_the_grid(G):
         gs.step(Pt, Ut, dev(ca), dev(ce), dtt)
     with pytest.raises(RuntimeError, match="ct"):
         gs.step_adjoint(Pt, dev(ca), dev(ce), dtt, dev(np.ones_like(P)))
+    with pytest.raises(RuntimeError, match="flux-CT"):
+        gs.fixup_vjp(Pt, torch.zeros(gs.N, dtype=torch.int32, device="cuda"), Pt.clone(), Pt.clone())
     gi = G.Grid(dict(pd, scheme="imex3"))
     with pytest.raises(RuntimeError, match="ct"):
         gi.step_adjoint(Pt, dev(ca), dev(ce), dtt, dev(np.ones_like(P)))

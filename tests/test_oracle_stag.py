@@ -251,6 +251,51 @@ def test_face_update_without_fluxes_combines_faces(orc):
         assert np.all(out[p, ~ev] == 0.0)
 
 
+def test_failed_inversion_returns_the_conserved_field(orc):
+    """B^i = U_B^i / sqrt(-g) needs no inversion: a cell whose MHD inversion
+    fails (negative rest-mass density rho u^t) keeps the guess's gas
+    primitives but takes its field from U."""
+    pd, P, Bf, ca, ce = _random_box((6, 5, 4), seed=5)
+    U = orc.prim_to_cons(pd, P)
+    c = _interior_index(pd)
+    Ub = U.copy()
+    Ub[0, c] = -abs(U[0, c])                 # no admissible density
+    Pg = P.copy()
+    Pg[5:8, c] += 0.3                        # a guess with another field
+    Pout, st = orc.con2prim(pd, Ub, Pg)
+    assert st[c] & orc.ST_C2P_FAIL
+    assert np.array_equal(Pout[0:5, c], Pg[0:5, c])
+    assert np.allclose(Pout[5:8, c], U[5:8, c], rtol=1e-15, atol=0)   # flat space: sqrt(-g) = 1
+
+
+def _interior_index(pd):
+    """One interior cell's flat index (the middle of the box)."""
+    na = I.nalloc(pd)
+    g = pd["ng"]
+    i, j, k = (g + pd["n"][d] // 2 for d in range(3))
+    return i + na[0] * (j + na[1] * k)
+
+
+def test_failed_cell_takes_its_own_staggered_field(orc):
+    """Staggered grid: a failed cell's neighbour average leaves B alone and
+    sets it from the cell's conserved field, not from its (stale) guess; on
+    a flux-CT grid B is averaged like the other primitives."""
+    pd, P, Bf, ca, ce = _random_box((6, 5, 4), seed=7)
+    U = orc.prim_to_cons(pd, P)
+    c = _interior_index(pd)
+    st = np.zeros(P.shape[1], np.int32)
+    st[c] = orc.ST_FAIL
+    Pstale = P.copy()
+    Pstale[5:8, c] += 0.25
+    Ps, Us, sts = orc.fixup(_stag(pd), Pstale, U, st)
+    assert np.allclose(Ps[5:8, c], U[5:8, c], rtol=1e-15, atol=0)
+    na = I.nalloc(pd)
+    nbs = [c + s * st_ for st_ in (1, na[0], na[0] * na[1]) for s in (-1, 1)]
+    assert np.allclose(Ps[0, c], np.mean([P[0, n] for n in nbs]), rtol=1e-14)
+    Pf, Uf, stf = orc.fixup(dict(pd, ct="flux"), Pstale, U, st)
+    assert np.allclose(Pf[5:8, c], np.mean([Pstale[5:8, n] for n in nbs], axis=0), rtol=1e-14)
+
+
 # ---------------------------------------------------------------------------
 # symmetry
 # ---------------------------------------------------------------------------
