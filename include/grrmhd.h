@@ -143,9 +143,10 @@ typedef struct {
                            the cold limit (GRRMHD_ST_PRAD, GRRMHD_ST_ENTROPY,
                            GRRMHD_ST_STAGED mark the solutions).  The step's
                            entropy equation needs the entropy tracer's
-                           explicit state, which grrmhd_step forms for RK3;
-                           the batched solve takes each cell's from its guess
-                           primitives.                                       */
+                           explicit state, which grrmhd_step forms for every
+                           scheme (the IMEX tables with the tracer's stored
+                           sources); the batched solve takes each cell's from
+                           its guess primitives.                             */
   int ct;               /* constrained transport of the field (Sec. 4, Sec.
                            4.2 steps 8-11): GRRMHD_CT_FLUX (default): flux-CT
                            on the cell-centred field, stepped by grrmhd_step;

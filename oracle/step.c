@@ -782,7 +782,8 @@ static void entropy_field(const orc_params *p, const double *P, double *S) {
 }
 
 /* the entropy tracer's explicit stage value at interior cells:
- * a Sn + b U_S(Pprev) + c dt (-div Fs); Sn = U_S(P^n) */
+ * a Sn + b U_S(Pprev) + c dt (-div Fs); Sn = U_S(P^n); no flux term (Fs may
+ * be NULL) where c = 0 */
 static void entropy_update(const orc_params *p, double a, double b, double c, double dt,
                            const double *Sn, const double *Pprev, const double *Fs,
                            double *Sexp) {
@@ -797,9 +798,9 @@ static void entropy_update(const orc_params *p, double a, double b, double c, do
       for (int i = orc_ng(p, 0); i < orc_ng(p, 0) + p->n[0]; i++) {
         const long cc = IDX(p, i, j, k);
         double div = 0.0;
-        for (int d = 0; d < 3; d++)
+        for (int d = 0; d < 3 && c != 0.0; d++)
           if (p->n[d] > 1) div += (Fs[(long)d * N + cc + st[d]] - Fs[(long)d * N + cc]) / orc_dx(p, d);
-        Sexp[cc] = a * Sn[cc] + (b != 0.0 ? b * Sp[cc] : 0.0) - c * dt * div;
+        Sexp[cc] = a * Sn[cc] + (b != 0.0 ? b * Sp[cc] : 0.0) - (c != 0.0 ? c * dt * div : 0.0);
       }
   free(Sp);
 }
@@ -863,14 +864,22 @@ int orc_step_stag(const orc_params *p, double *P, double *U, double *Bf, const d
     }
     Bk = Bn;
   }
-  /* the full cascade's entropy equation (RK3): the explicit entropy of each
-   * stage, a U_S(P^n) + b U_S(P^(k-1)) + c dt (-div F_S), the tracer taken
-   * from the primitives at every sub-step (Sec. 4.2 step 2: all U_q from P_q) */
-  const int ent = p->cascade && p->scheme == ORC_RK3;
+  /* the full cascade's entropy equation: the explicit entropy of each stage,
+   * a U_S(P^n) + b U_S(P^(j)) + c dt (-div F_S) + dt sum_k m_k M_S^k, the
+   * tracer taken from the primitives at every sub-step (Sec. 4.2 step 2: all
+   * U_q from P_q; in every table the stage j of a b term is the previous
+   * one), and an implicit stage's entropy source stored as computed, M_S^k =
+   * (U_S(P^k) - explicit)/(g dt) from its solution before the fix-ups (zero
+   * where the solve failed), as the other sources M^k */
+  const int ent = p->cascade;
   double *Fs = ent ? malloc(sizeof(double) * 3 * N) : NULL;
   double *Sn = ent ? malloc(sizeof(double) * N) : NULL;
   double *Sexp = ent ? malloc(sizeof(double) * N) : NULL;
-  if (ent) entropy_field(p, P, Sn);
+  double *MS[4] = {NULL};
+  if (ent) {
+    entropy_field(p, P, Sn);
+    for (int k = 0; k < 4; k++) MS[k] = need_m[k] ? calloc(N, sizeof(double)) : NULL;
+  }
 #define STEP_FLUXES()                                              \
   do {                                                             \
     if (fl) orc_flattener(p, Pk, chi_abs, chi_es, fl, nflux > 0);  \
@@ -906,6 +915,7 @@ int orc_step_stag(const orc_params *p, double *P, double *U, double *Bf, const d
       }
     } else {
       for (long q = 0; q < 12 * N; q++) Uexp[q] = s->a * Un[q] + (s->b != 0.0 ? s->b * Uj[q] : 0.0);
+      if (ent) entropy_update(p, s->a, s->b, 0.0, *dt, Sn, Pk, NULL, Sexp);
       if (Bf) {
         orc_face_update(p, s->a, s->b, 0.0, *dt, Bn, (s->j >= 0) ? Bst[s->j] : Bn, NULL, Bst[i]);
         orc_face_to_center(p, Bst[i], NULL, Uexp);
@@ -915,6 +925,8 @@ int orc_step_stag(const orc_params *p, double *P, double *U, double *Bf, const d
     for (int k = 0; k < i && k < 4; k++) {
       if (s->m[k] == 0.0) continue;
       for (long q = 0; q < 12 * N; q++) Uexp[q] += *dt * s->m[k] * Mst[k][q];
+      if (ent)
+        for (long q = 0; q < N; q++) Sexp[q] += *dt * s->m[k] * MS[k][q];
     }
     if (s->g > 0.0) {
       orc_implicit_grid_s(p, Uexp, ent ? Sexp : NULL, Pk, s->g * (*dt), chi_abs, chi_es, Pk, Ust[i],
@@ -927,6 +939,17 @@ int orc_step_stag(const orc_params *p, double *P, double *U, double *Bf, const d
             Mst[i][q * N + c] = (slot && !(st[c] & ORC_ST_FAIL))
                                     ? (Ust[i][q * N + c] - Uexp[q * N + c]) / gdt : 0.0;
           }
+        if (ent) {
+          double *Sk = malloc(sizeof(double) * N);
+          entropy_field(p, Pk, Sk);
+          for (int k = orc_ng(p, 2); k < orc_ng(p, 2) + p->n[2]; k++)
+            for (int j = orc_ng(p, 1); j < orc_ng(p, 1) + p->n[1]; j++)
+              for (int ii = orc_ng(p, 0); ii < orc_ng(p, 0) + p->n[0]; ii++) {
+                const long c = IDX(p, ii, j, k);
+                MS[i][c] = (st[c] & ORC_ST_FAIL) ? 0.0 : (Sk[c] - Sexp[c]) / gdt;
+              }
+          free(Sk);
+        }
       }
     } else {
       /* final explicit combination: inversions; a failed MHD inversion is a
@@ -969,6 +992,7 @@ int orc_step_stag(const orc_params *p, double *P, double *U, double *Bf, const d
   free(Fs);
   free(Sn);
   free(Sexp);
+  for (int k = 0; k < 4; k++) free(MS[k]);
 #undef STEP_FLUXES
   return nbad;
 }

@@ -395,7 +395,7 @@ static Scheme make_scheme(int which) {
 }
 
 struct WsLayout {
-  size_t F, emf, vch, Uexp, Pa, Ua, err, st, it, Us, M, Fs, Sn, VF, SP, Bs, total;
+  size_t F, emf, vch, Uexp, Pa, Ua, err, st, it, Us, M, Fs, Sn, MS, VF, SP, Bs, total;
 };
 
 // IMEX schemes add the stage U's (all but the last) and the kept M^k
@@ -423,11 +423,13 @@ static WsLayout ws_layout(const Ctx& C, int scheme = GRRMHD_RK3) {
     w.Us = take(round256(sizeof(double) * 12 * N) * (S.ns - 1));
     w.M = take(round256(sizeof(double) * 8 * N) * 4);
   }
-  // the full cascade's entropy tracer (RK3): face fluxes and U_S(P^n)
-  w.Fs = w.Sn = off;
-  if (C.cascade && scheme == GRRMHD_RK3) {
+  // the full cascade's entropy tracer: face fluxes and U_S(P^n); in the IMEX
+  // tables also the stored entropy sources M_S^k
+  w.Fs = w.Sn = w.MS = off;
+  if (C.cascade) {
     w.Fs = take(sizeof(double) * 3 * N);
     w.Sn = take(sizeof(double) * N);
+    if (scheme != GRRMHD_RK3) w.MS = take(round256(sizeof(double) * N) * 4);
   }
   // the staggered field: face velocities and speeds, and the faces of every
   // stage but the last (which writes the caller's faces in place)
@@ -826,6 +828,18 @@ static int imex_step(grrmhd_grid* g, double* P, double* U, double* Bf, const dou
     RF.cnt[e] = C.n[e] > 1 ? C.n[e] + 1 : 1;
     RF.total *= RF.cnt[e];
   }
+  // the full cascade's entropy tracer: U_S(P^n), the stage's face fluxes and
+  // explicit value (row 12 of the explicit state, free until the fix-ups),
+  // and the stored entropy sources
+  double* Fs = C.cascade ? (double*)(base + w.Fs) : nullptr;
+  double* Sn = C.cascade ? (double*)(base + w.Sn) : nullptr;
+  double* Sexp = C.cascade ? Ue + 12 * N : nullptr;
+  const size_t b1 = round256(sizeof(double) * N);
+  auto MSk = [&](int k) { return (double*)(base + w.MS + k * b1); };
+  if (C.cascade) {
+    hipLaunchKernelGGL(k_entropy_field, dim3(nblocks(nint, 256)), dim3(256), 0, g->stream, C, P, Sn);
+    LAUNCHCHK();
+  }
   double* Pcur = P;
   double* Bcur = Bf;   // the faces of Pcur
   int rc, nflux = 0;
@@ -844,8 +858,8 @@ static int imex_step(grrmhd_grid* g, double* P, double* U, double* Bf, const dou
                            Bcur);
         LAUNCHCHK();
       }
-      if ((rc = launch_fluxes(g, Pcur, chi_abs, chi_es, F, emf, vch, dmin, nflux > 0, nullptr,
-                              Bcur, VF, SP)))
+      if ((rc = launch_fluxes(g, Pcur, chi_abs, chi_es, F, emf, vch, dmin, nflux > 0, Fs, Bcur,
+                              VF, SP)))
         return rc;
       nflux++;
     }
@@ -871,15 +885,39 @@ static int imex_step(grrmhd_grid* g, double* P, double* U, double* Bf, const dou
                             Bf ? Bst(i) : nullptr)))
       return rc;
     if (red) g->dtp ^= 1;
+    if (C.cascade && x.g > 0.0) {
+      // every table's b term takes the previous stage, whose primitives are Pcur
+      if (x.b != 0.0 && x.j != i - 1)
+        return fail(GRRMHD_EINVAL, "entropy tracer: a stage's b term must take the previous stage");
+      hipLaunchKernelGGL(k_entropy_update, dim3(nblocks(nint, 256)), dim3(256), 0, g->stream, C,
+                         x.a, x.b, x.c, (const double*)dt_dev, (const double*)Sn,
+                         (const double*)Pcur, (const double*)Fs, Sexp);
+      LAUNCHCHK();
+      if (MT.n > 0) {
+        MTerms MS = MT;
+        for (int q = 0, k = 0; k < i && k < 4; k++)
+          if (x.m[k] != 0.0) MS.M[q++] = MSk(k);
+        hipLaunchKernelGGL(k_entropy_mterms, dim3(nblocks(nint, 256)), dim3(256), 0, g->stream, C,
+                           MS, (const double*)dt_dev, Sexp);
+        LAUNCHCHK();
+      }
+    }
     double* Pout = last ? P : Pa;
     double* Uout = last ? U : Us[i];
     if (x.g > 0.0) {
-      if ((rc = launch_implicit(g, Ue, Pcur, x.g, dt_dev, chi_abs, chi_es, Pout, Uout, it, st, err)))
+      if ((rc = launch_implicit(g, Ue, Pcur, x.g, dt_dev, chi_abs, chi_es, Pout, Uout, it, st, err,
+                                Sexp)))
         return rc;
       if (i < 4 && S.keep_m[i]) {   // the stage's source, before the fix-ups
         hipLaunchKernelGGL(k_stage_m, dim3(nblocks(nint, 256)), dim3(256), 0, g->stream, C, Ue,
                            Uout, st, x.g, dt_dev, Mk[i]);
         LAUNCHCHK();
+        if (C.cascade) {
+          hipLaunchKernelGGL(k_stage_ms, dim3(nblocks(nint, 256)), dim3(256), 0, g->stream, C,
+                             (const double*)Pout, (const double*)Sexp, (const int*)st, x.g,
+                             (const double*)dt_dev, MSk(i));
+          LAUNCHCHK();
+        }
       }
       if ((rc = launch_fixup(g, Pout, Uout, st, Ue, status, it, iters, i > 0))) return rc;
     } else {

@@ -617,7 +617,8 @@ __global__ void LB(256) k_entropy_field(Ctx C, const double* __restrict__ P, dou
 }
 
 // the entropy tracer's explicit stage value at interior cells:
-// a Sn + b U_S(P) + cc dt (-div Fs), Sn = U_S(P^n), P the stage's input
+// a Sn + b U_S(P) + cc dt (-div Fs), Sn = U_S(P^n), P the stage's input (no
+// flux term, and no Fs read, where cc = 0)
 __global__ void LB(256) k_entropy_update(Ctx C, double a, double b, double cc,
                                          const double* __restrict__ dt_dev,
                                          const double* __restrict__ Sn,
@@ -637,10 +638,10 @@ __global__ void LB(256) k_entropy_update(Ctx C, double a, double b, double cc,
     sp = entropy_cons(C.gam, m, p);
   }
   double div = 0.0;
-  for (int d = 0; d < 3; d++)
+  for (int d = 0; d < 3 && cc != 0.0; d++)
     if (C.n[d] > 1)
       div += (Fs[(long)d * C.Ntot + c + C.st[d]] - Fs[(long)d * C.Ntot + c]) / C.dx[d];
-  Sexp[c] = a * Sn[c] + (b != 0.0 ? b * sp : 0.0) - cc * (*dt_dev) * div;
+  Sexp[c] = a * Sn[c] + (b != 0.0 ? b * sp : 0.0) - (cc != 0.0 ? cc * (*dt_dev) * div : 0.0);
 }
 
 // ---------------------------------------------------------------------------
@@ -1673,6 +1674,39 @@ __global__ void LB(256) k_stage_m(Ctx C, const double* __restrict__ Ue,
     const int q = (r < 4) ? 1 + r : 4 + r;
     M[r * C.Ntot + c] = bad ? 0.0 : (Uo[q * C.Ntot + c] - Ue[q * C.Ntot + c]) / gdt;
   }
+}
+
+// The entropy tracer in the IMEX tables: a stage's bracket adds
+// dt sum_k m_k M_S^k (MT's arrays: [N] each), and an implicit stage stores
+// M_S = (U_S(P_out) - explicit)/(g dt) from its solution before the fix-ups
+// (zero where the solve failed), as k_stage_m the other sources.
+__global__ void LB(256) k_entropy_mterms(Ctx C, MTerms MT, const double* __restrict__ dt_dev,
+                                         double* __restrict__ Sexp) {
+  int i, j, k;
+  if (!interior_ijk(C, (long)blockIdx.x * blockDim.x + threadIdx.x, i, j, k)) return;
+  const long c = cell_index(C, i, j, k);
+  double sm = 0.0;
+  for (int q = 0; q < MT.n; q++) sm += MT.m[q] * MT.M[q][c];
+  Sexp[c] += (*dt_dev) * sm;
+}
+
+__global__ void LB(256) k_stage_ms(Ctx C, const double* __restrict__ Po,
+                                   const double* __restrict__ Sexp, const int* __restrict__ status,
+                                   double g, const double* __restrict__ dt_dev,
+                                   double* __restrict__ MS) {
+  int i, j, k;
+  if (!interior_ijk(C, (long)blockIdx.x * blockDim.x + threadIdx.x, i, j, k)) return;
+  const long c = cell_index(C, i, j, k);
+  if (status[c] & GRRMHD_ST_FAIL) {
+    MS[c] = 0.0;
+    return;
+  }
+  Metric m;
+  load_metric(C.geo_c, C.npos, i + C.N[0] * j, m);
+  double p[5];
+#pragma unroll
+  for (int q = 0; q < 5; q++) p[q] = Po[q * C.Ntot + c];
+  MS[c] = (entropy_cons(C.gam, m, p) - Sexp[c]) / (g * (*dt_dev));
 }
 
 // ---------------------------------------------------------------------------

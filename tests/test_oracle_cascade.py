@@ -14,7 +14,11 @@ equations fix rather than against the oracle itself:
   the exchange (T dS = du at fixed density), so a wrong sign or factor in
   G_S fails;
 - the full cascade leaves far fewer batch cells without a solution than
-  PMHD and URAD alone, and changes nothing where PMHD is accepted.
+  PMHD and URAD alone, and changes nothing where PMHD is accepted;
+- in the IMEX tables (Sec. 4.1) the entropy tracer's bracket carries the
+  stored entropy sources: nothing changes where PMHD is accepted, and on a
+  box of far-from-equilibrium cells the entropy methods take cells the
+  energy methods leave.
 """
 import math
 
@@ -208,3 +212,52 @@ def test_entropy_tracer_flux(orc):
     F, emf, vch, Fs = orc.fluxes_s(pd, P, np.zeros(P.shape[1]), np.zeros(P.shape[1]))
     SL = PL[0] * math.log(((pd["gam"] - 1) * PL[1]) ** 1.5 / PL[0] ** 2.5)
     assert abs(Fs[0][g + n // 2] - SL * PL[2]) < 1e-14 * abs(SL * PL[2])
+
+
+def _batch_box(orc, n=256, seed=31, **kw):
+    """A periodic 1-D box of batch-recipe cells (flows slowed tenfold,
+    opacities raised a thousandfold): far-from-equilibrium neighbours whose
+    step needs the entropy, staged and PRAD attempts."""
+    pdb, Pb, dtb, cab, ceb = I.implicit_batch(n, seed=seed)
+    pd = I.default_params(n=(n, 1, 1), arad=1.0, tol_pmhd=1e-10, courant=0.4, cascade=1, **kw)
+    N = I.ncell(pd)
+    g = pd["ng"]
+    P = np.zeros((12, N))
+    P[:, g:g + n] = Pb
+    P[2:5] *= 0.1
+    P[9:12] = P[2:5]
+    ca, ce = np.zeros(N), np.zeros(N)
+    ca[g:g + n], ce[g:g + n] = cab * 1e3, ceb * 1e3
+    P = orc.bc(pd, P)
+    for a in (ca, ce):
+        a[:g], a[-g:] = a[n:n + g], a[g:2 * g]
+    return pd, P, ca, ce
+
+
+@pytest.mark.parametrize("scheme", ["imex2", "imex3"])
+def test_imex_full_cascade_changes_nothing_where_pmhd_is_accepted(orc, scheme):
+    from test_oracle_pins import _periodic_box
+
+    pd, P, ca, ce = _periodic_box((8, 6, 4), seed=7)
+    pd = dict(pd, scheme=scheme)
+    U = orc.prim_to_cons(pd, P)
+    P0, U0, dt0, st0, _, _ = orc.step(pd, P, U, ca, ce)
+    P1, U1, dt1, st1, _, _ = orc.step(dict(pd, cascade=1), P, U, ca, ce)
+    other = orc.ST_FAIL | orc.ST_ENTROPY | orc.ST_PRAD | orc.ST_STAGED | orc.ST_NOT_ACCEPT
+    assert not np.any(st0 & other) and not np.any(st1 & other)
+    assert dt0 == dt1 and np.array_equal(P0, P1) and np.array_equal(U0, U1)
+
+
+@pytest.mark.parametrize("scheme", ["imex2", "imex3"])
+def test_imex_entropy_methods_take_cells_the_energy_methods_leave(orc, scheme):
+    pd, P, ca, ce = _batch_box(orc, scheme=scheme)
+    U = orc.prim_to_cons(pd, P)
+    m = np.zeros(P.shape[1], bool)
+    m[pd["ng"]:pd["ng"] + pd["n"][0]] = True
+    P0, U0, dt0, st0, _, _ = orc.step(dict(pd, cascade=0), P, U, ca, ce)
+    P1, U1, dt1, st1, _, _ = orc.step(pd, P, U, ca, ce)
+    f0 = int(((st0[m] & orc.ST_FAIL) != 0).sum())
+    f1 = int(((st1[m] & orc.ST_FAIL) != 0).sum())
+    ne = int(((st1[m] & orc.ST_ENTROPY) != 0).sum())
+    assert ne > 0 and f1 < f0, (ne, f0, f1)
+    assert np.all(np.isfinite(P1[:, m])) and np.all(P1[0, m] > 0) and np.all(P1[1, m] > 0)
