@@ -834,6 +834,11 @@ static int imex_step(grrmhd_grid* g, double* P, double* U, double* Bf, const dou
   double* Fs = C.cascade ? (double*)(base + w.Fs) : nullptr;
   double* Sn = C.cascade ? (double*)(base + w.Sn) : nullptr;
   double* Sexp = C.cascade ? Ue + 12 * N : nullptr;
+  // the tracer's b term is taken from the stage input's primitives, so it
+  // must be the previous stage's (it is in every table)
+  for (int i = 0; C.cascade && i < S.ns; i++)
+    if (S.s[i].g > 0.0 && S.s[i].b != 0.0 && S.s[i].j != i - 1)
+      return fail(GRRMHD_EINVAL, "entropy tracer: a stage's b term must take the previous stage");
   const size_t b1 = round256(sizeof(double) * N);
   auto MSk = [&](int k) { return (double*)(base + w.MS + k * b1); };
   if (C.cascade) {
@@ -886,9 +891,7 @@ static int imex_step(grrmhd_grid* g, double* P, double* U, double* Bf, const dou
       return rc;
     if (red) g->dtp ^= 1;
     if (C.cascade && x.g > 0.0) {
-      // every table's b term takes the previous stage, whose primitives are Pcur
-      if (x.b != 0.0 && x.j != i - 1)
-        return fail(GRRMHD_EINVAL, "entropy tracer: a stage's b term must take the previous stage");
+      // the b term's stage is the previous one (checked above): Pcur
       hipLaunchKernelGGL(k_entropy_update, dim3(nblocks(nint, 256)), dim3(256), 0, g->stream, C,
                          x.a, x.b, x.c, (const double*)dt_dev, (const double*)Sn,
                          (const double*)Pcur, (const double*)Fs, Sexp);
