@@ -240,6 +240,28 @@ def test_staggered_ppm_and_cascade(G, orc):
     assert eP.max() < 1e-12 and eU.max() < 1e-12 and max(eB) < 1e-12
 
 
+def test_staggered_ppm_cascade_imex3(G, orc):
+    """Every option of the step at once on the 3-D disk: the staggered
+    field, PPM with the flattener, the full cascade with its entropy tracer
+    and the IMEX3 table (stored sources, the tracer's stored sources, the
+    stage faces, the final explicit inversion): one step against the
+    oracle's."""
+    say("case disk3d ppm + cascade + imex3, staggered")
+    pd, P, ca, ce, Bf = _disk((20, 12, 8), ng=4, recon="ppm", cascade=1, scheme="imex3")
+    Bf = orc.bc_face(pd, Bf)
+    P, U = _consistent(orc, pd, P, Bf)
+    Pr, Ur, Br, dt, st, it, nbad = orc.step_stag(pd, P, U, Bf, ca, ce)
+    Pg, Ug, Bg, dtg, stg = _gpu_steps(G, pd, P, U, Bf, ca, ce, 1, status=True)
+    m = interior_mask(pd)
+    ev = _evolved(pd)
+    eP, eU = field_err(Pg, Pr, m), field_err(Ug, Ur, m)
+    eB = [_face_err(Bg[p], Br[p], ev[p]) for p in range(3)]
+    say("  P", eP.max(), "U", eU.max(), "faces", eB, "failed", nbad)
+    assert np.array_equal(stg[m], st[m])
+    assert abs(dtg[0] / dt - 1) < 1e-13
+    assert eP.max() < 1e-12 and eU.max() < 1e-12 and max(eB) < 1e-12
+
+
 def test_staggered_mixed_precision(G, orc):
     say("case disk3d mixed, staggered")
     pd, P, ca, ce, Bf = _disk((24, 12, 8), precision="mixed", r_fp64=2.0)
