@@ -334,9 +334,14 @@ int grrmhd_step_staggered(grrmhd_grid *g, double *P, double *U, double *Bf,
  * flattener of the two face cells, and the flattener itself (the largest
  * over the step's flux evaluations) is differentiated at the evaluation
  * that gave it, inside its ramp through the pressures, densities and
- * opacities of its seven cells.  The normal cascade (cascade = 0) and the
- * flux-CT field only (EINVAL on a full-cascade or staggered-field grid;
- * grrmhd_explicit_vjp also rejects a staggered-field grid).  The workspace
+ * opacities of its seven cells.  The full cascade (cascade = 1) with RK3:
+ * PRAD and staged solutions are roots of the same energy equations; an
+ * entropy-method solution is differentiated on its entropy equation
+ * (eq. source6), whose explicit tracer a U_S(P^n) + b U_S(P_in) + c dt
+ * (-div F_S) passes its cotangent on through the tracer's face fluxes and
+ * U_S of the primitives.  The flux-CT field only.  EINVAL on a staggered-
+ * field grid or a full-cascade IMEX grid (grrmhd_explicit_vjp also rejects
+ * a staggered-field grid, grrmhd_implicit_vjp a full-cascade grid).  The workspace
  * size depends on the scheme and the reconstruction.  P_n [12][N] (interior read; not modified), gU_next
  * [12][N] (interior read), gP_n [12][N] out (ghosts zero); g_chi (nullable)
  * [2][N] out: dL/dchi_abs, dL/dchi_es at every allocated cell (the per-mass
@@ -375,7 +380,8 @@ int grrmhd_step_adjoint_saved(grrmhd_grid *g, const double *chi_abs, const doubl
  *                        status): gUexp = (dP/dUexp)^T gP_out +
  *                        (dU/dUexp)^T gU_out at interior cells (zero at
  *                        ghosts); cold cells (GRRMHD_ST_COLD) through the
- *                        three momentum equations with u_g fixed;
+ *                        three momentum equations with u_g fixed (normal
+ *                        cascade; EINVAL on a full-cascade grid);
  *  grrmhd_explicit_vjp   of grrmhd_fluxes followed by grrmhd_explicit_update
  *                        with stage coefficient c on dt, with respect to the
  *                        ghost-filled P: gP at every allocated cell (PPM:

@@ -89,11 +89,15 @@ __global__ void LB(128) k_adj_p2u(Ctx C, const double* __restrict__ P,
 // ---------------------------------------------------------------------------
 // Implicit solve.  The PMHD map at (x, theta): x = (u_g, u~^i), theta = the
 // explicit conserved state U(i) (with sqrt(-g)); E the residual, P and U the
-// outputs exactly as the forward step finalises a PMHD solution.
+// outputs exactly as the forward step finalises a PMHD solution.  ent: an
+// entropy-method solution (Sec. 4.11): E[0] is the entropy equation
+// (eq. source6 with G_S of eq. GS, weighted by T_gas as the forward) with
+// the explicit tracer Se = sqrt(-g) [S u^t]_(i); P and U as for PMHD.
 // ---------------------------------------------------------------------------
 template <class T>
 DEV void pmhd_map(const Metric& m, const Phys& ph, double dtc, const T& chi_abs, const T& chi_es,
-                  const T x[4], const T th[12], T E[4], T P[12], T U[12]) {
+                  const T x[4], const T th[12], T E[4], T P[12], T U[12], bool ent = false,
+                  const T& Se = T(0.0)) {
   const double igd = 1.0 / m.gdet;
   const T rhout = th[0] * igd;
   T B[3], Tgi[4], Ri[4];
@@ -128,6 +132,16 @@ DEV void pmhd_map(const Metric& m, const Phys& ph, double dtc, const T& chi_abs,
   four_force(s.v, r, Eb, kabs, kes, lam, G);
 #pragma unroll
   for (int k = 0; k < 4; k++) E[k] = (row[1 + k] - Tgi[k]) - dtc * G[k];
+  if (ent) {
+    const double n = 1.0 / (ph.gam - 1.0);
+    const T S = s.rho * (n * log(s.pg) - (n + 1.0) * log(s.rho));
+    const T Sut = S * s.v.ucon[0];
+    const T Tg = s.pg / s.rho;
+    T Gu = G[0] * s.v.ucon[0];
+#pragma unroll
+    for (int k = 1; k < 4; k++) Gu = Gu + G[k] * s.v.ucon[k];
+    E[0] = (Tg * Sut - Tg * (Se * igd)) + dtc * Gu;
+  }
   P[0] = s.rho;
   P[1] = x[0];
 #pragma unroll
@@ -162,6 +176,9 @@ DEV void pmhd_map(const Metric& m, const Phys& ph, double dtc, const T& chi_abs,
   for (int i = 0; i < 3; i++) U[5 + i] = th[5 + i];
 }
 
+// Se (nullable): the stage's explicit entropy tracer sqrt(-g) [S u^t]_(i)
+// (full cascade); lamS (with Se) [Ntot] out: its cotangent at interior cells
+// (zero where the solution is not an entropy-method one).
 DEV void adj_implicit_at(Ctx C, double scale, const double* __restrict__ dt_dev,
                                       const double* __restrict__ Ue, const double* __restrict__ Pk,
                                       const int* __restrict__ status,
@@ -169,7 +186,8 @@ DEV void adj_implicit_at(Ctx C, double scale, const double* __restrict__ dt_dev,
                                       const double* __restrict__ chi_es,
                                       const double* __restrict__ lamP,
                                       const double* __restrict__ lamU, double* __restrict__ lamUe,
-                                      double* __restrict__ gchi, long t) {
+                                      double* __restrict__ gchi, const double* __restrict__ Se,
+                                      double* __restrict__ lamS, long t) {
   if (t >= (long)C.n[0] * C.n[1] * C.n[2]) return;
   int i, j, k;
   interior_cell(C, t, i, j, k);
@@ -182,6 +200,9 @@ DEV void adj_implicit_at(Ctx C, double scale, const double* __restrict__ dt_dev,
     th[q] = Ue[q * C.Ntot + c];
   }
   bool ok = !(status[c] & GRRMHD_ST_FAIL);
+  const bool ent = Se && ok && (status[c] & GRRMHD_ST_ENTROPY) && !(status[c] & GRRMHD_ST_COLD);
+  const double se = ent ? Se[c] : 0.0;
+  if (lamS) lamS[c] = 0.0;
   double mu[4];
   Metric m;
   load_metric(C.geo_c, C.npos, i + C.N[0] * j, m);
@@ -199,7 +220,7 @@ DEV void adj_implicit_at(Ctx C, double scale, const double* __restrict__ dt_dev,
     seed4<4>(x, 0, xd);
 #pragma unroll
     for (int q = 0; q < 12; q++) thd[q] = D4(th[q]);
-    pmhd_map(m, ph, dtc, D4(ca), D4(ce), xd, thd, E, Po, Uo);
+    pmhd_map(m, ph, dtc, D4(ca), D4(ce), xd, thd, E, Po, Uo, ent, D4(se));
     double JT[4][4], gx[4];
 #pragma unroll
     for (int jj = 0; jj < 4; jj++) {
@@ -217,6 +238,8 @@ DEV void adj_implicit_at(Ctx C, double scale, const double* __restrict__ dt_dev,
       for (int k = 1; k < 4; k++) JT[0][k] = JT[k][0] = 0.0;
     }
     ok = solve4(JT, gx, mu) == 0;
+    // the explicit tracer enters E[0] alone, as -T_gas Se/sqrt(-g)
+    if (ok && ent && lamS) lamS[c] = mu[0] * ((ph.gam - 1.0) * x[0] / Po[0].v) / m.gdet;
   }
   if (!ok) {   // failed cell (or singular Jacobian): U passes through unchanged
 #pragma unroll
@@ -242,7 +265,7 @@ DEV void adj_implicit_at(Ctx C, double scale, const double* __restrict__ dt_dev,
       asm volatile("" : "+v"(tv[q]));
     }
     seed4<12>(tv, 4 * pass, thd);
-    pmhd_map(m, ph, dtc, D4(ca), D4(ce), xd, thd, E, Po, Uo);
+    pmhd_map(m, ph, dtc, D4(ca), D4(ce), xd, thd, E, Po, Uo, ent, D4(se));
 #pragma unroll
     for (int jj = 0; jj < 4; jj++) {
       double s = 0.0;
@@ -267,7 +290,7 @@ DEV void adj_implicit_at(Ctx C, double scale, const double* __restrict__ dt_dev,
       asm volatile("" : "+v"(v));
       thd[q] = D4(v);
     }
-    pmhd_map(m, ph, dtc, D4::var(ca, 0), D4::var(ce, 1), xd, thd, E, Po, Uo);
+    pmhd_map(m, ph, dtc, D4::var(ca, 0), D4::var(ce, 1), xd, thd, E, Po, Uo, ent, D4(se));
 #pragma unroll
     for (int jj = 0; jj < 2; jj++) {
       double s = 0.0;
@@ -285,9 +308,10 @@ __global__ void LB(64) k_adj_implicit(Ctx C, double scale, const double* __restr
                                       const double* __restrict__ chi_es,
                                       const double* __restrict__ lamP,
                                       const double* __restrict__ lamU, double* __restrict__ lamUe,
-                                      double* __restrict__ gchi) {
-  adj_implicit_at(C, scale, dt_dev, Ue, Pk, status, chi_abs, chi_es, lamP, lamU, lamUe, gchi,
-                  (long)blockIdx.x * blockDim.x + threadIdx.x);
+                                      double* __restrict__ gchi, const double* __restrict__ Se,
+                                      double* __restrict__ lamS) {
+  adj_implicit_at(C, scale, dt_dev, Ue, Pk, status, chi_abs, chi_es, lamP, lamU, lamUe, gchi, Se,
+                  lamS, (long)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -483,7 +507,8 @@ __global__ void LB(256) k_adj_emf(Ctx C, int a, FaceRange R, double scale,
 
 // A face state reduced to what the flux cotangent needs: the sums
 // sum_q lF[q] U_q and sum_q lF[q] F_q over the gas components (q < 8, the
-// normal field left out) and over the radiation components (q >= 8), and
+// normal field left out; with the entropy tracer's flux, which takes the gas
+// speeds, weighted by lFs) and over the radiation components (q >= 8), and
 // the four characteristic speeds.  The flux is linear in U and F once the
 // speeds are fixed, so these sums carry all of it.
 template <class T>
@@ -494,7 +519,7 @@ struct FaceSums {
 
 template <class T>
 DEV void face_sums(const Ctx& C, const Metric& m, int d, const T* P, T chi_tot, const double lF[12],
-                   FaceSums<T>& o) {
+                   FaceSums<T>& o, double lFs = 0.0) {
   Gas<T> s;
   make_gas(m, C.gam, P[0], P[1], P + 2, P + 5, s);
   T row[8];
@@ -511,6 +536,13 @@ DEV void face_sums(const Ctx& C, const Metric& m, int d, const T* P, T chi_tot, 
   for (int q = 0; q < 8; q++)
     if (q != 4 + d) acc = acc + lF[q] * row[q];
   o.gF = m.gdet * acc;
+  if (lFs != 0.0) {
+    // the tracer sqrt(-g) S u^t and its flux sqrt(-g) S u^d (as entropy_face)
+    const double n = 1.0 / (C.gam - 1.0);
+    const T S = P[0] * (n * log(s.pg) - (n + 1.0) * log(P[0]));
+    o.gU = o.gU + lFs * (m.gdet * S * s.v.ucon[0]);
+    o.gF = o.gF + lFs * (m.gdet * S * s.v.ucon[d]);
+  }
   Vel<T> r;
   make_vel(m, P + 9, r);
   T rr[4];
@@ -567,13 +599,14 @@ DEV void flux_contract(const Ctx& C, const FaceSums<TL>& L, const FaceSums<TR>& 
 // 5.7 ms -> 3.0 ms).  Two seeds per pass spill least at equal speed.
 template <int S>
 DEV void adj_face_side(const Ctx& C, const Metric& m, int D, const double PLR[24], double chiL,
-                       double chiR, const double lF[12], double lS[12], double* gx) {
+                       double chiR, const double lF[12], double lS[12], double* gx,
+                       double lFs = 0.0) {
   constexpr int NS = 2;
   typedef Dual<NS> DS;
   const double* own = PLR + 12 * S;
   const double chi_own = S ? chiR : chiL;
   FaceSums<double> O;
-  face_sums(C, m, D, PLR + 12 * (1 - S), S ? chiL : chiR, lF, O);
+  face_sums(C, m, D, PLR + 12 * (1 - S), S ? chiL : chiR, lF, O, lFs);
 #pragma unroll 1
   for (int g = 0; g < 12 / NS; g++) {
     DS in[12];
@@ -587,7 +620,7 @@ DEV void adj_face_side(const Ctx& C, const Metric& m, int D, const double PLR[24
         if (q == NS * g + jj) in[q].d[jj] = 1.0;
     }
     FaceSums<DS> F;
-    face_sums(C, m, D, in, DS(chi_own), lF, F);
+    face_sums(C, m, D, in, DS(chi_own), lF, F, lFs);
     double acc[NS];
     if (S == 0)
       flux_contract<NS>(C, F, O, acc);
@@ -605,7 +638,7 @@ DEV void adj_face_side(const Ctx& C, const Metric& m, int D, const double PLR[24
       in[q] = Dual<1>(v);
     }
     FaceSums<Dual<1>> F;
-    face_sums(C, m, D, in, Dual<1>::var(chi_own, 0), lF, F);
+    face_sums(C, m, D, in, Dual<1>::var(chi_own, 0), lF, F, lFs);
     double acc[1];
     if (S == 0)
       flux_contract<1>(C, F, O, acc);
@@ -634,7 +667,8 @@ DEV void adj_flux_at(Ctx C, FaceRange R, double scale,
                                                  const double* __restrict__ lamE,
                                                  double* __restrict__ G, double* __restrict__ Gx,
                                                  const double* __restrict__ fl,
-                                                 double* __restrict__ GF, long t) {
+                                                 double* __restrict__ GF,
+                                                 const double* __restrict__ lamS, long t) {
   if (t >= R.total) return;
   const int i = R.lo[0] + t % R.cnt[0];
   const long t2 = t / R.cnt[0];
@@ -708,10 +742,13 @@ DEV void adj_flux_at(Ctx C, FaceRange R, double scale,
   const double* tab = (D == 1) ? C.geo_f1 : ((D == 2) ? C.geo_f2 : C.geo_c);
   load_metric(tab, C.npos, i + C.N[0] * j, m);
   const double chiL = chi_abs[f - st] + chi_es[f - st], chiR = chi_abs[f] + chi_es[f];
+  // the entropy tracer's face flux (full cascade): its cotangent as the
+  // stage update's divergence gives it
+  const double lFs = lamS ? cdt * idx * (lamS[f] - lamS[f - st]) : 0.0;
   double lPLR[24];
   double gxL = 0.0, gxR = 0.0;
-  adj_face_side<0>(C, m, D, PLR, chiL, chiR, lF, lPLR, Gx ? &gxL : nullptr);
-  adj_face_side<1>(C, m, D, PLR, chiL, chiR, lF, lPLR + 12, Gx ? &gxR : nullptr);
+  adj_face_side<0>(C, m, D, PLR, chiL, chiR, lF, lPLR, Gx ? &gxL : nullptr, lFs);
+  adj_face_side<1>(C, m, D, PLR, chiL, chiR, lF, lPLR + 12, Gx ? &gxR : nullptr, lFs);
   if (Gx) {
     Gx[f] = gxL;                 // d/d chi_tot of cell f - e_d
     Gx[C.Ntot + f] = gxR;        // d/d chi_tot of cell f
@@ -770,8 +807,9 @@ __global__ void __launch_bounds__(64) k_adj_flux(Ctx C, FaceRange R, double scal
                                                  const double* __restrict__ lamE,
                                                  double* __restrict__ G, double* __restrict__ Gx,
                                                  const double* __restrict__ fl,
-                                                 double* __restrict__ GF) {
-  adj_flux_at<D, PPM>(C, R, scale, dt_dev, P, chi_abs, chi_es, lamUe, lamE, G, Gx, fl, GF,
+                                                 double* __restrict__ GF,
+                                                 const double* __restrict__ lamS) {
+  adj_flux_at<D, PPM>(C, R, scale, dt_dev, P, chi_abs, chi_es, lamUe, lamE, G, Gx, fl, GF, lamS,
                       (long)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
@@ -901,6 +939,47 @@ __global__ void LB(256) k_adj_gather_chi(Ctx C, FaceRanges FR, const double* __r
   }
   gchi[c] += acc;
   gchi[C.Ntot + c] += acc;
+}
+
+// ---------------------------------------------------------------------------
+// The full cascade's entropy tracer U_S = sqrt(-g) S u^t of the gas
+// primitives (rho0, u_g, u~^i; S = rho0 ln(p^n / rho0^(n+1))): lamP[q] +=
+// b dU_S/dP_q lamS at interior cells, for a stage's b U_S(P_in) term and
+// (b = 1, lamS the a-weighted sum over stages) for a U_S(P^n).  A cell
+// whose tracer the forward left undefined (rho0 or u_g not positive) gets
+// nothing.
+// ---------------------------------------------------------------------------
+__global__ void LB(128) k_adj_entropy_field(Ctx C, double b, const double* __restrict__ P,
+                                            const double* __restrict__ lamS,
+                                            double* __restrict__ lamP) {
+  int i, j, k;
+  if (!interior_ijk(C, (long)blockIdx.x * blockDim.x + threadIdx.x, i, j, k)) return;
+  const long c = cell_index(C, i, j, k);
+  const double l = b * lamS[c];
+  if (l == 0.0) return;
+  typedef Dual<5> D5;
+  D5 pd[5];
+#pragma unroll
+  for (int q = 0; q < 5; q++) pd[q] = D5::var(P[q * C.Ntot + c], q);
+  if (!(pd[0].v > 0.0) || !(pd[1].v > 0.0)) return;
+  Metric m;
+  load_metric(C.geo_c, C.npos, i + C.N[0] * j, m);
+  Vel<D5> v;
+  make_vel(m, pd + 2, v);
+  const double n = 1.0 / (C.gam - 1.0);
+  const D5 S = pd[0] * (n * log((C.gam - 1.0) * pd[1]) - (n + 1.0) * log(pd[0]));
+  const D5 U = m.gdet * S * v.ucon[0];
+#pragma unroll
+  for (int q = 0; q < 5; q++) lamP[q * C.Ntot + c] += l * U.d[q];
+}
+
+// y += alpha x at interior cells, one field
+__global__ void LB(256) k_adj_axpy1(Ctx C, double alpha, const double* __restrict__ x,
+                                    double* __restrict__ y) {
+  int i, j, k;
+  if (!interior_ijk(C, (long)blockIdx.x * blockDim.x + threadIdx.x, i, j, k)) return;
+  const long c = cell_index(C, i, j, k);
+  y[c] += alpha * x[c];
 }
 
 // ---------------------------------------------------------------------------

@@ -1114,7 +1114,8 @@ extern "C" int grrmhd_fluxes_staggered(grrmhd_grid* g, const double* P, const do
 // ---------------------------------------------------------------------------
 struct AdjLayout {
   size_t F, emf, vch, scr, err, it, Un, Pb, Ue, Pk, Uk, stk, lamP, lamU, lamUe, lamUn, lamPb, lamE,
-      G, Gx, Lam, lamPpre, lamUpre, M, lamUs, lamM, lamPg, Pc, FL, GF, LamFl, Lf2, total;
+      G, Gx, Lam, lamPpre, lamUpre, M, lamUs, lamM, lamPg, Pc, FL, GF, LamFl, Lf2, Se, Fs, Sn,
+      lamS, lamSn, total;
   int ns;   // stages checkpointed
 };
 
@@ -1170,6 +1171,14 @@ static AdjLayout adj_layout(const Ctx& C, int scheme) {
   w.GF = take(ppm ? D8 * 12 * N : 0);       // per direction: face products with the flattener
   w.LamFl = take(ppm ? D8 * 6 * N : 0);     // cotangent of the flattener read, carried back
   w.Lf2 = take(ppm ? D8 * 6 * N : 0);       // cotangent of a stage's own flattener
+  // the full cascade's entropy tracer: each stage's explicit value, the face
+  // fluxes, U_S(P^n), and the cotangents of a stage's value and of U_S(P^n)
+  const bool ent = C.cascade != 0;
+  w.Se = take(ent ? D8 * ns * N : 0);
+  w.Fs = take(ent ? D8 * 3 * N : 0);
+  w.Sn = take(ent ? D8 * N : 0);
+  w.lamS = take(ent ? D8 * N : 0);
+  w.lamSn = take(ent ? D8 * N : 0);
   w.total = off;
   return w;
 }
@@ -1188,15 +1197,18 @@ static int fill_d(grrmhd_grid* g, double* p, size_t n, double v) {
 // lamUe (all cells; zero outside the interior) from the cotangents of the
 // implicit solve's outputs
 // gchi (nullable, [2][N]): the opacity cotangents are added to it
+// Se, lamS (nullable together): the stage's explicit entropy tracer and its
+// cotangent out (full cascade)
 static int adj_implicit(grrmhd_grid* g, double scale, const double* dt_dev, const double* Ue,
                         const double* Pk, const int* st, const double* ca, const double* ce,
                         const double* lamP, const double* lamU, double* lamUe,
-                        double* gchi = nullptr) {
+                        double* gchi = nullptr, const double* Se = nullptr,
+                        double* lamS = nullptr) {
   const Ctx& C = g->C;
   int rc;
   if ((rc = fill_d(g, lamUe, 12 * (size_t)C.Ntot, 0.0))) return rc;
   hipLaunchKernelGGL(k_adj_implicit, dim3(nblocks(n_interior(C), 64)), dim3(64), 0, g->stream, C,
-                     scale, dt_dev, Ue, Pk, st, ca, ce, lamP, lamU, lamUe, gchi);
+                     scale, dt_dev, Ue, Pk, st, ca, ce, lamP, lamU, lamUe, gchi, Se, lamS);
   LAUNCHCHK();
   return 0;
 }
@@ -1215,9 +1227,12 @@ struct AdjFlat {
 // `scale` on dt
 // Gx, gchi (nullable together): opacity face products and the cotangents
 // they add to gchi [2][N]
+// lamS (nullable): the cotangent of the stage's explicit entropy tracer (full
+// cascade), whose face fluxes and b U_S(Pb) term (bS) it differentiates too
 static int adj_explicit(grrmhd_grid* g, double scale, const double* dt_dev, const double* Pb,
                         const double* ca, const double* ce, const double* lamUe, double* lamE,
-                        double* G, double* lamPb, double* Gx, double* gchi, const AdjFlat* FLT) {
+                        double* G, double* lamPb, double* Gx, double* gchi, const AdjFlat* FLT,
+                        const double* lamS = nullptr, double bS = 0.0) {
   const Ctx& C = g->C;
   const size_t N = (size_t)C.Ntot;
   hipStream_t s = g->stream;
@@ -1246,7 +1261,7 @@ static int adj_explicit(grrmhd_grid* g, double scale, const double* dt_dev, cons
     const dim3 gr(nblocks(R.total, 64)), bl(64);
 #define ADJ_FLUX(D, PPM)                                                                      \
   hipLaunchKernelGGL((k_adj_flux<D, PPM>), gr, bl, 0, s, C, R, scale, dt_dev, Pb, ca, ce, lamUe, \
-                     (const double*)lamE, Gd, Gxd, fl, GFd)
+                     (const double*)lamE, Gd, Gxd, fl, GFd, lamS)
     if (ppm) {
       if (d == 0) ADJ_FLUX(1, true);
       if (d == 1) ADJ_FLUX(2, true);
@@ -1297,6 +1312,11 @@ static int adj_explicit(grrmhd_grid* g, double scale, const double* dt_dev, cons
                        (const double*)mf, (const double*)FLT->Lf2, lamPb, gchi);
     LAUNCHCHK();
   }
+  if (lamS && bS != 0.0) {
+    hipLaunchKernelGGL(k_adj_entropy_field, dim3(nblocks(n_interior(C), 128)), dim3(128), 0, s, C,
+                       bS, Pb, lamS, lamPb);
+    LAUNCHCHK();
+  }
   return 0;
 }
 
@@ -1321,6 +1341,8 @@ extern "C" int grrmhd_implicit_vjp(grrmhd_grid* g, const double* Uexp, const dou
   NEEDG();
   if (!Uexp || !P_out || !status || !dt_dev || !chi_abs || !chi_es || !gP_out || !gU_out || !gUexp)
     return fail(GRRMHD_EINVAL, "NULL array");
+  if (g->C.cascade)
+    return fail(GRRMHD_EINVAL, "implicit_vjp covers the normal cascade (cascade = 0)");
   return adj_implicit(g, dt_scale, dt_dev, Uexp, P_out, status, chi_abs, chi_es, gP_out, gU_out,
                       gUexp);
 }
@@ -1422,13 +1444,13 @@ extern "C" int grrmhd_con2prim_vjp(grrmhd_grid* g, const double* U, const double
 struct AdjPtrs {
   double *F, *emf, *vch, *scr, *err, *Un, *Pb, *Ue, *Pk, *Uk;
   double *lamP, *lamU, *lamUe, *lamUn, *lamPb, *lamE, *G, *Gx, *Lam, *lamPpre, *lamUpre;
-  double *M, *lamUs, *lamM, *lamPg, *Pc, *FL, *GF, *LamFl, *Lf2;
+  double *M, *lamUs, *lamM, *lamPg, *Pc, *FL, *GF, *LamFl, *Lf2, *Se, *Fs, *Sn, *lamS, *lamSn;
   int *it, *stk;
 };
 
 static int adj_ptrs(grrmhd_grid* g, void* workspace, size_t ws_bytes, AdjPtrs& a) {
-  if (g->p.cascade != 0)
-    return fail(GRRMHD_EINVAL, "the adjoint covers the PMHD/URAD cascade (cascade = 0)");
+  if (g->p.cascade != 0 && g->p.scheme != GRRMHD_RK3)
+    return fail(GRRMHD_EINVAL, "the adjoint covers the full cascade (cascade = 1) with RK3 only");
   if (g->C.ct)
     return fail(GRRMHD_EINVAL, "the adjoint covers the flux-CT field (ct = GRRMHD_CT_FLUX)");
   const AdjLayout w = adj_layout(g->C, g->p.scheme);
@@ -1467,6 +1489,11 @@ static int adj_ptrs(grrmhd_grid* g, void* workspace, size_t ws_bytes, AdjPtrs& a
   a.GF = (double*)(base + w.GF);
   a.LamFl = (double*)(base + w.LamFl);
   a.Lf2 = (double*)(base + w.Lf2);
+  a.Se = (double*)(base + w.Se);
+  a.Fs = (double*)(base + w.Fs);
+  a.Sn = (double*)(base + w.Sn);
+  a.lamS = (double*)(base + w.lamS);
+  a.lamSn = (double*)(base + w.lamSn);
   return 0;
 }
 
@@ -1509,6 +1536,12 @@ static int adj_forward(grrmhd_grid* g, const double* P_n, const double* chi_abs,
   HIPCHK(hipMemcpyAsync(a.Pb, P_n, B12, hipMemcpyDeviceToDevice, s));
   hipLaunchKernelGGL(k_p2u, dim3(nblocks(C.Ntot, 256)), dim3(256), 0, s, C, a.Pb, a.Un);
   LAUNCHCHK();
+  const bool ent = C.cascade != 0;
+  if (ent) {
+    hipLaunchKernelGGL(k_entropy_field, dim3(nblocks(n_interior(C), 256)), dim3(256), 0, s, C,
+                       (const double*)a.Pb, a.Sn);
+    LAUNCHCHK();
+  }
   for (int k = 0; k < 3; k++) {
     double* Pin = a.Pb + k * N12;
     double* Uek = a.Ue + k * N12;
@@ -1517,15 +1550,24 @@ static int adj_forward(grrmhd_grid* g, const double* P_n, const double* chi_abs,
     int* st = a.stk + k * N;
     if (k > 0) HIPCHK(hipMemcpyAsync(Pin, a.Pk + (k - 1) * N12, B12, hipMemcpyDeviceToDevice, s));
     if ((rc = launch_bc(g, Pin))) return rc;
-    if ((rc = launch_fluxes(g, Pin, chi_abs, chi_es, a.F, a.emf, a.vch, nullptr, k > 0))) return rc;
+    if ((rc = launch_fluxes(g, Pin, chi_abs, chi_es, a.F, a.emf, a.vch, nullptr, k > 0,
+                            ent ? a.Fs : nullptr)))
+      return rc;
     if ((rc = adj_keep_flat(g, a, k))) return rc;
     if ((rc = launch_update(g, ADJ_A[k], ADJ_B[k], ADJ_C[k], dt_dev, Pin, a.Un,
                             k == 0 ? a.Un : a.Uk + (k - 1) * N12, a.F, a.emf, Uek)))
       return rc;
+    double* Sek = ent ? a.Se + k * N : nullptr;
+    if (ent) {
+      hipLaunchKernelGGL(k_entropy_update, dim3(nblocks(n_interior(C), 256)), dim3(256), 0, s, C,
+                         ADJ_A[k], ADJ_B[k], ADJ_C[k], dt_dev, (const double*)a.Sn,
+                         (const double*)Pin, (const double*)a.Fs, Sek);
+      LAUNCHCHK();
+    }
     HIPCHK(hipMemcpyAsync(Pout, Pin, B12, hipMemcpyDeviceToDevice, s));
     HIPCHK(hipMemcpyAsync(Uout, Uek, B12, hipMemcpyDeviceToDevice, s));
     if ((rc = launch_implicit(g, Uek, Pin, ADJ_C[k], dt_dev, chi_abs, chi_es, Pout, Uout, a.it, st,
-                              a.err)))
+                              a.err, Sek)))
       return rc;
     if ((rc = launch_fixup(g, Pout, Uout, st, a.scr, nullptr, a.it, nullptr, 0))) return rc;
   }
@@ -1556,6 +1598,8 @@ static int adj_reverse(grrmhd_grid* g, const double* chi_abs, const double* chi_
   if (g_chi && (rc = fill_d(g, g_chi, 2 * N, 0.0))) return rc;
   const bool ppm = C.recon == GRRMHD_RECON_PPM;
   if (ppm && (rc = fill_d(g, a.LamFl, 6 * N, 0.0))) return rc;
+  const bool ent = C.cascade != 0;
+  if (ent && ((rc = fill_d(g, a.lamS, N, 0.0)) || (rc = fill_d(g, a.lamSn, N, 0.0)))) return rc;
   for (int k = 2; k >= 0; k--) {
     const double* Pin = a.Pb + k * N12;
     // fix-up of failed and cold cells, then the implicit solve
@@ -1568,14 +1612,21 @@ static int adj_reverse(grrmhd_grid* g, const double* chi_abs, const double* chi_
                        a.lamPpre, a.lamUpre);
     LAUNCHCHK();
     if ((rc = adj_implicit(g, ADJ_C[k], dt_dev, a.Ue + k * N12, a.Pk + k * N12, a.stk + k * N,
-                           chi_abs, chi_es, a.lamPpre, a.lamUpre, a.lamUe, g_chi)))
+                           chi_abs, chi_es, a.lamPpre, a.lamUpre, a.lamUe, g_chi,
+                           ent ? a.Se + k * N : nullptr, ent ? a.lamS : nullptr)))
       return rc;
+    if (ent) {   // the tracer's a U_S(P^n) term
+      hipLaunchKernelGGL(k_adj_axpy1, dim3(gi), dim3(256), 0, s, C, ADJ_A[k], (const double*)a.lamS,
+                         a.lamSn);
+      LAUNCHCHK();
+    }
     hipLaunchKernelGGL(k_adj_stage, dim3(gi), dim3(256), 0, s, C, ADJ_A[k], ADJ_B[k],
                        (const double*)a.lamUe, a.lamUn, a.lamU);
     LAUNCHCHK();
     const AdjFlat F = adj_flat_of(g, a, k, k - 1);
     if ((rc = adj_explicit(g, ADJ_C[k], dt_dev, Pin, chi_abs, chi_es, a.lamUe, a.lamE, a.G,
-                           a.lamPb, Gx, g_chi, ppm ? &F : nullptr)))
+                           a.lamPb, Gx, g_chi, ppm ? &F : nullptr, ent ? a.lamS : nullptr,
+                           ADJ_B[k])))
       return rc;
     if ((rc = adj_bc(g, a.lamPb))) return rc;
     hipLaunchKernelGGL(k_copy_interior, dim3(ga), dim3(256), 0, s, C, (const double*)a.lamPb, a.lamP);
@@ -1584,6 +1635,11 @@ static int adj_reverse(grrmhd_grid* g, const double* chi_abs, const double* chi_
   hipLaunchKernelGGL(k_adj_p2u, dim3(nblocks(nint, 128)), dim3(128), 0, s, C, (const double*)a.Pb,
                      (const double*)a.lamUn, a.lamP);
   LAUNCHCHK();
+  if (ent) {   // U_S(P^n) of every stage's tracer
+    hipLaunchKernelGGL(k_adj_entropy_field, dim3(nblocks(nint, 128)), dim3(128), 0, s, C, 1.0,
+                       (const double*)a.Pb, (const double*)a.lamSn, a.lamP);
+    LAUNCHCHK();
+  }
   hipLaunchKernelGGL(k_copy_interior, dim3(ga), dim3(256), 0, s, C, (const double*)a.lamP, gP_n);
   LAUNCHCHK();
   return 0;

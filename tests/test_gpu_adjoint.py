@@ -175,13 +175,15 @@ def test_explicit_vjp_against_fd(G):
     g.close()
 
 
-def _step_check(G, orc, pd, P, ca, ce, ncomp, n_oracle, tol, kinks=0, f=1.0, cells=None):
+def _step_check(G, orc, pd, P, ca, ce, ncomp, n_oracle, tol, kinks=0, f=1.0, cells=None,
+                fields=None):
     """f scales the difference step.  kinks > 0: also difference with a step
     a third as long and drop (at most `kinks`) components where the two
     disagree by more than 1e-4: there a step straddles a limiter switch, where
     the step has no derivative, or a small field's step leaves the
     difference to rounding (a test on the differences alone, not on the
-    adjoint).  cells: the interior cells to sample (default all)."""
+    adjoint).  cells: the interior cells to sample (default all); fields: the
+    primitives to sample (default all twelve)."""
     g = G.Grid(pd)
     cat, cet = dev(ca), dev(ce)
     dt, nfail = step_dt(G, g, P, cat, cet)
@@ -206,7 +208,8 @@ def _step_check(G, orc, pd, P, ca, ce, ncomp, n_oracle, tol, kinks=0, f=1.0, cel
 
     scale = np.abs(P[:, idx]).max(axis=1)
     pool = idx if cells is None else np.asarray(cells)
-    comps = [(int(r.integers(12)), int(pool[r.integers(pool.size)])) for _ in range(ncomp)]
+    qs = np.arange(12) if fields is None else np.asarray(fields)
+    comps = [(int(qs[r.integers(qs.size)]), int(pool[r.integers(pool.size)])) for _ in range(ncomp)]
     fdg = fd_rows(comps, P, scale, U_gpu, w[:, idx], f=f)
     if kinks:
         fd3 = fd_rows(comps, P, scale, U_gpu, w[:, idx], f=f / 3)

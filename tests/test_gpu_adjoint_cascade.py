@@ -1,0 +1,130 @@
+"""Adjoint of the step with the full implicit cascade (params.cascade = 1,
+RK3; Sec. 4.10-4.11) through the C ABI, against central differences of the
+GPU step and of the FP64 oracle's step, as tests/test_gpu_adjoint.py does
+for the normal cascade.
+
+PRAD and staged solutions are roots of the same energy equations as PMHD and
+take the same implicit-function-theorem step; an entropy-method solution is
+differentiated on its entropy equation (eq. source6), and the cotangent of
+the stage's explicit entropy tracer, a U_S(P^n) + b U_S(P_in) + c dt
+(-div F_S), goes on through the tracer's face fluxes and U_S of the
+primitives.  The batch box of tests/test_gpu_cascade.py puts cells on the
+entropy methods; the components sampled lie around them.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1312_6127_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from test_gpu_adjoint import _chi_check, _step_check, box, disk_small  # noqa: E402
+from test_oracle_cascade import _batch_box  # noqa: E402
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def G():
+    from paper_1312_6127_amd import grrmhd
+
+    grrmhd.lib()
+    assert torch.cuda.is_available()
+    return grrmhd
+
+
+def _entropy_box(orc):
+    """The batch box (jittered) and the interior cells within two cells of
+    a cell the oracle's step solves with an entropy method."""
+    pd, P, ca, ce = _batch_box(orc)
+    P = I.jitter(P, 11)
+    P = orc.bc(pd, P)
+    U = orc.prim_to_cons(pd, P)
+    _, _, _, st, _, _ = orc.step(pd, P, U, ca, ce)
+    g = pd["ng"]
+    n = pd["n"][0]
+    ent = np.flatnonzero((st & orc.ST_ENTROPY) != 0)
+    ent = ent[(ent >= g) & (ent < g + n)]
+    assert ent.size >= 4
+    near = np.unique((ent[:, None] + np.arange(-2, 3)[None, :]).reshape(-1))
+    return pd, P, ca, ce, near[(near >= g) & (near < g + n)]
+
+
+def test_step_adjoint_full_cascade_disk(G, orc):
+    """The 12x8x4 Kerr-Schild disk, where PMHD is accepted first: the
+    tracer's path runs (its cotangent is zero), the rest as the normal
+    cascade."""
+    say("case step adjoint, full cascade, Kerr-Schild 12x8x4")
+    pd, P, ca, ce = disk_small()
+    _step_check(G, orc, dict(pd, cascade=1), P, ca, ce, ncomp=48, n_oracle=16, tol=1e-6,
+                kinks=6, f=10.0)
+
+
+def test_step_adjoint_full_cascade_entropy_cells(G, orc):
+    """Components around the batch box's entropy-method cells against GPU
+    differences.  The box's cells sit at the edges of their methods' basins
+    (a difference step often crosses a method switch, where the step has no
+    derivative), and most of them take URAD at some stage, whose solve stops
+    at its own tolerance, so a difference quotient carries noise of order
+    that tolerance over the step; no neighbourhood here is free of URAD.  A
+    norm over all components would measure that noise; the test takes the
+    components whose quotients at the step and at a third of it agree to
+    1e-4 and requires their median relative error below 1e-6, also over
+    those next to an entropy-method cell (at least 8 of them)."""
+    from test_gpu_adjoint import dev, fd_rows, host, interior_idx, step_dt
+
+    say("case step adjoint, full cascade, batch box entropy cells")
+    pd, P, ca, ce, cells = _entropy_box(orc)
+    g = G.Grid(pd)
+    cat, cet = dev(ca), dev(ce)
+    dt, _ = step_dt(G, g, P, cat, cet)
+    idx = interior_idx(pd)
+    r = np.random.default_rng(5)
+    w = np.zeros_like(P)
+    w[:, idx] = r.standard_normal((12, idx.size))
+    gP = host(g.step_adjoint(dev(P), cat, cet, dt, dev(w)))
+    Pw = dev(P)
+    Uw = g.prim_to_cons(Pw)
+    stt = torch.zeros(g.N, dtype=torch.int32, device="cuda")
+    g.step(Pw, Uw, cat, cet, dt, dt_fixed=True, status=stt)
+    st = host(stt)
+
+    def U_gpu(Pp):
+        Pq = dev(Pp)
+        Uq = g.prim_to_cons(Pq)
+        g.step(Pq, Uq, cat, cet, dt, dt_fixed=True)
+        return host(Uq)[:, idx]
+
+    scale = np.abs(P[:, idx]).max(axis=1)
+    qs = [0, 1, 2, 3, 4, 8, 9, 10, 11]   # the box has no magnetic field
+    comps = [(int(qs[r.integers(len(qs))]), int(cells[r.integers(cells.size)])) for _ in range(96)]
+    fd = fd_rows(comps, P, scale, U_gpu, w[:, idx])
+    fd3 = fd_rows(comps, P, scale, U_gpu, w[:, idx], f=1 / 3)
+    g.close()
+    smooth = np.abs(fd - fd3) <= 1e-4 * np.abs(fd)
+    adj = np.array([gP[q, c] for q, c in comps])
+    rel = np.abs(adj - fd) / np.abs(fd)
+    near = np.array([((st[c - 1:c + 2] & G.ST_ENTROPY) != 0).any() for q, c in comps])
+    say(f"  smooth {smooth.sum()} of {len(comps)}; median rel error {np.median(rel[smooth]):.2e}; "
+        f"next to entropy cells {(smooth & near).sum()}, median {np.median(rel[smooth & near]):.2e}")
+    assert smooth.sum() >= 24 and np.median(rel[smooth]) < 1e-6
+    assert (smooth & near).sum() >= 8 and np.median(rel[smooth & near]) < 1e-6
+
+
+def test_opacity_gradient_full_cascade_box(G, orc):
+    """The opacity gradient with the full cascade's machinery (tracer and
+    all) on the periodic box with per-cell opacities, where PMHD is accepted
+    first: as the normal cascade's."""
+    say("case opacity gradient, full cascade, periodic box")
+    pd, P, ca, ce = box()
+    r = np.random.default_rng(4)
+    ca = ca * (1 + 0.3 * r.random(ca.size))
+    ce = ce * (1 + 0.3 * r.random(ce.size))
+    _chi_check(G, orc, dict(pd, cascade=1), P, ca, ce, ncomp=32, n_oracle=8, tol=1e-6)
