@@ -176,9 +176,11 @@ DEV void pmhd_map(const Metric& m, const Phys& ph, double dtc, const T& chi_abs,
   for (int i = 0; i < 3; i++) U[5 + i] = th[5 + i];
 }
 
-// Se (nullable): the stage's explicit entropy tracer sqrt(-g) [S u^t]_(i)
-// (full cascade); lamS (with Se) [Ntot] out: its cotangent at interior cells
-// (zero where the solution is not an entropy-method one).
+// ENT (full cascade): Se, the stage's explicit entropy tracer sqrt(-g)
+// [S u^t]_(i); lamS [Ntot] out: its cotangent at interior cells (zero where
+// the solution is not an entropy-method one).  Without ENT both are unused
+// and the entropy row is not compiled in.
+template <bool ENT>
 DEV void adj_implicit_at(Ctx C, double scale, const double* __restrict__ dt_dev,
                                       const double* __restrict__ Ue, const double* __restrict__ Pk,
                                       const int* __restrict__ status,
@@ -200,9 +202,9 @@ DEV void adj_implicit_at(Ctx C, double scale, const double* __restrict__ dt_dev,
     th[q] = Ue[q * C.Ntot + c];
   }
   bool ok = !(status[c] & GRRMHD_ST_FAIL);
-  const bool ent = Se && ok && (status[c] & GRRMHD_ST_ENTROPY) && !(status[c] & GRRMHD_ST_COLD);
+  const bool ent = ENT && ok && (status[c] & GRRMHD_ST_ENTROPY) && !(status[c] & GRRMHD_ST_COLD);
   const double se = ent ? Se[c] : 0.0;
-  if (lamS) lamS[c] = 0.0;
+  if (ENT) lamS[c] = 0.0;
   double mu[4];
   Metric m;
   load_metric(C.geo_c, C.npos, i + C.N[0] * j, m);
@@ -239,7 +241,7 @@ DEV void adj_implicit_at(Ctx C, double scale, const double* __restrict__ dt_dev,
     }
     ok = solve4(JT, gx, mu) == 0;
     // the explicit tracer enters E[0] alone, as -T_gas Se/sqrt(-g)
-    if (ok && ent && lamS) lamS[c] = mu[0] * ((ph.gam - 1.0) * x[0] / Po[0].v) / m.gdet;
+    if (ENT && ok && ent) lamS[c] = mu[0] * ((ph.gam - 1.0) * x[0] / Po[0].v) / m.gdet;
   }
   if (!ok) {   // failed cell (or singular Jacobian): U passes through unchanged
 #pragma unroll
@@ -301,6 +303,7 @@ DEV void adj_implicit_at(Ctx C, double scale, const double* __restrict__ dt_dev,
   }
 }
 
+template <bool ENT>
 __global__ void LB(64) k_adj_implicit(Ctx C, double scale, const double* __restrict__ dt_dev,
                                       const double* __restrict__ Ue, const double* __restrict__ Pk,
                                       const int* __restrict__ status,
@@ -310,8 +313,8 @@ __global__ void LB(64) k_adj_implicit(Ctx C, double scale, const double* __restr
                                       const double* __restrict__ lamU, double* __restrict__ lamUe,
                                       double* __restrict__ gchi, const double* __restrict__ Se,
                                       double* __restrict__ lamS) {
-  adj_implicit_at(C, scale, dt_dev, Ue, Pk, status, chi_abs, chi_es, lamP, lamU, lamUe, gchi, Se,
-                  lamS, (long)blockIdx.x * blockDim.x + threadIdx.x);
+  adj_implicit_at<ENT>(C, scale, dt_dev, Ue, Pk, status, chi_abs, chi_es, lamP, lamU, lamUe, gchi,
+                       Se, lamS, (long)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------

@@ -1207,8 +1207,14 @@ static int adj_implicit(grrmhd_grid* g, double scale, const double* dt_dev, cons
   const Ctx& C = g->C;
   int rc;
   if ((rc = fill_d(g, lamUe, 12 * (size_t)C.Ntot, 0.0))) return rc;
-  hipLaunchKernelGGL(k_adj_implicit, dim3(nblocks(n_interior(C), 64)), dim3(64), 0, g->stream, C,
-                     scale, dt_dev, Ue, Pk, st, ca, ce, lamP, lamU, lamUe, gchi, Se, lamS);
+  if (Se && lamS)
+    hipLaunchKernelGGL(k_adj_implicit<true>, dim3(nblocks(n_interior(C), 64)), dim3(64), 0,
+                       g->stream, C, scale, dt_dev, Ue, Pk, st, ca, ce, lamP, lamU, lamUe, gchi, Se,
+                       lamS);
+  else
+    hipLaunchKernelGGL(k_adj_implicit<false>, dim3(nblocks(n_interior(C), 64)), dim3(64), 0,
+                       g->stream, C, scale, dt_dev, Ue, Pk, st, ca, ce, lamP, lamU, lamUe, gchi,
+                       nullptr, nullptr);
   LAUNCHCHK();
   return 0;
 }
