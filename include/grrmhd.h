@@ -321,8 +321,11 @@ int grrmhd_step_staggered(grrmhd_grid *g, double *P, double *U, double *Bf,
  * implicit-function theorem on the PMHD residual at the converged state
  * (Sec. 4.8; one transposed 4x4 solve per cell), the fluxes, EMFs, source
  * and ghost fill by their local Jacobians (dual numbers) and transposes.
- * Floors are taken as the identity; a failed cell's neighbour average is
- * differentiated (its own failed solve receives nothing).  Every scheme
+ * The fix-ups are differentiated at the state before them: a failed cell's
+ * neighbour average (its own failed solve receives nothing) and the floors
+ * (a floored quantity passes no cotangent back, U recomputed from P passes
+ * none to U before the fix-up), with the implicit solve's transpose taken
+ * at its own output.  Every scheme
  * (RK3; eq. IMEX2, IMEX2B, IMEX3): on an IMEX grid the stored
  * sources M^k = (U(k) - U_e(k))/(g dt) are transposed with the stages that
  * read them, and the final explicit stage's inversion is differentiated at
@@ -334,15 +337,17 @@ int grrmhd_step_staggered(grrmhd_grid *g, double *P, double *U, double *Bf,
  * flattener of the two face cells, and the flattener itself (the largest
  * over the step's flux evaluations) is differentiated at the evaluation
  * that gave it, inside its ramp through the pressures, densities and
- * opacities of its seven cells.  The full cascade (cascade = 1) with RK3:
- * PRAD and staged solutions are roots of the same energy equations; an
- * entropy-method solution is differentiated on its entropy equation
+ * opacities of its seven cells.  The full cascade (cascade = 1), every
+ * scheme: PRAD and staged solutions are roots of the same energy equations;
+ * an entropy-method solution is differentiated on its entropy equation
  * (eq. source6), whose explicit tracer a U_S(P^n) + b U_S(P_in) + c dt
- * (-div F_S) passes its cotangent on through the tracer's face fluxes and
- * U_S of the primitives.  The flux-CT field only.  EINVAL on a staggered-
- * field grid or a full-cascade IMEX grid (grrmhd_explicit_vjp also rejects
- * a staggered-field grid, grrmhd_implicit_vjp a full-cascade grid).  The workspace
- * size depends on the scheme and the reconstruction.  P_n [12][N] (interior read; not modified), gU_next
+ * (-div F_S) (+ dt sum_k m_k M_S^k on an IMEX grid, the stored entropy
+ * sources M_S^k = (U_S(P(k)) - S_e(k))/(g dt) taken at the stage's output
+ * before its fix-ups) passes its cotangent on through the tracer's face
+ * fluxes, U_S of the primitives and the earlier stages' M_S^k.  The flux-CT
+ * field only.  EINVAL on a staggered-field grid (grrmhd_explicit_vjp also
+ * rejects one, grrmhd_implicit_vjp a full-cascade grid).  The workspace
+ * size depends on the scheme, the reconstruction and the cascade.  P_n [12][N] (interior read; not modified), gU_next
  * [12][N] (interior read), gP_n [12][N] out (ghosts zero); g_chi (nullable)
  * [2][N] out: dL/dchi_abs, dL/dchi_es at every allocated cell (the per-mass
  * opacities enter the implicit residual through kappa = chi rho0 and the

@@ -24,8 +24,8 @@
 // Local Jacobians come from Dual<4> passes of the same templated physics as
 // the forward kernels, so each piecewise choice (limiter branch, wave-speed
 // extremum, radiation limiter) is differentiated on the branch the forward
-// step took.  A failed cell's fix-up (the mean of its neighbours) is
-// differentiated as such; floors are taken as the identity.
+// step took.  A failed cell's fix-up (the mean of its neighbours) and the
+// floors are differentiated as such, at the state before the fix-ups.
 #pragma once
 #include "kernels.h"
 
@@ -320,12 +320,16 @@ __global__ void LB(64) k_adj_implicit(Ctx C, double scale, const double* __restr
 // ---------------------------------------------------------------------------
 // Fix-ups: a failed cell takes P_f = mean of its face neighbours' P (those
 // with a good energy solution, neither failed nor cold; all of them when none
-// is good), a cold cell the same mean for u_g alone; then U = U(P).
-// Transpose: Lam = lamP + (dU/dP)^T lamU at a changed cell, spread back over
-// the neighbours that were averaged (all fields from a failed cell, u_g from a
-// cold one); a failed cell's own solve receives nothing, a cold cell's keeps
-// Lam except for u_g.  A cell with no interior neighbour is left unchanged.
-// Floors are taken as the identity.
+// is good), a cold cell the same mean for u_g alone; then the floors F
+// (rho0, u_g from below, u_g/rho0 from above, Ebar from below); then U = U(P)
+// where P changed.  Transpose: Lam = J_F^T (lamP + (dU/dP)^T lamU) at a
+// changed or floored cell (J_F at the state the floors met: the mean, or the
+// solve's own output), spread back over the neighbours that were averaged
+// (all fields from a failed cell, u_g from a cold one); a failed cell's own
+// solve receives nothing, a cold cell's keeps Lam except for u_g, a floored
+// cell's keeps Lam, and U before the fix-up receives nothing where P
+// changed.  A cell with no interior neighbour is not averaged.  Without the
+// state before the fix-ups (Ppre null) floors are taken as the identity.
 // ---------------------------------------------------------------------------
 DEV bool failed_at(const int* st, long c) { return (st[c] & GRRMHD_ST_FAIL) != 0; }
 DEV bool bad_at(const int* st, long c) { return (st[c] & (GRRMHD_ST_FAIL | GRRMHD_ST_COLD)) != 0; }
@@ -360,17 +364,39 @@ DEV bool fixed_at(const Ctx& C, const int* st, const int idx[3]) {
   return fixup_count(C, st, idx, gp) > 0;
 }
 
-DEV void adj_fixup_own_at(Ctx C, const double* __restrict__ P, const int* __restrict__ st,
-                          const double* __restrict__ lamP, const double* __restrict__ lamU,
-                          double* __restrict__ Lam, long t) {
+// the fix-up's floors on primitives p, in place (as the forward fix-up)
+template <class T>
+DEV void floor_map(const Ctx& C, const Metric& m, T p[12]) {
+  Gas<T> s;
+  make_gas(m, C.gam, p[0], p[1], p + 2, p + 5, s);
+  const T br = s.bsq / C.bsq_rho_max, bu = s.bsq / C.bsq_u_max;
+  const T rmin = (val(br) > C.rho_floor) ? br : T(C.rho_floor);
+  const T umin = (val(bu) > C.u_floor) ? bu : T(C.u_floor);
+  if (val(p[0]) < val(rmin)) p[0] = rmin;
+  if (val(p[1]) < val(umin)) p[1] = umin;
+  if (val(p[1]) > C.u_rho_max * val(p[0])) p[1] = C.u_rho_max * p[0];
+  if (!(val(p[8]) >= C.erad_floor)) p[8] = T(C.erad_floor);
+}
+
+// a changed cell: Lam; a floored cell (with Ppre) too
+DEV bool touched_at(const Ctx& C, const int* st, const int idx[3], bool exact_floors) {
+  return fixed_at(C, st, idx) ||
+         (exact_floors && (st[cell_index(C, idx[0], idx[1], idx[2])] & GRRMHD_ST_FLOOR));
+}
+
+DEV void adj_fixup_own_at(Ctx C, const double* __restrict__ P, const double* __restrict__ Ppre,
+                          const int* __restrict__ st, const double* __restrict__ lamP,
+                          const double* __restrict__ lamU, double* __restrict__ Lam, long t) {
   if (t >= (long)C.n[0] * C.n[1] * C.n[2]) return;
   int idx[3];
   interior_cell(C, t, idx[0], idx[1], idx[2]);
   const long c = cell_index(C, idx[0], idx[1], idx[2]);
-  if (!fixed_at(C, st, idx)) return;
+  const bool fixed = fixed_at(C, st, idx);
+  const bool floored = Ppre && (st[c] & GRRMHD_ST_FLOOR);
+  if (!fixed && !floored) return;
   Metric m;
   load_metric(C.geo_c, C.npos, idx[0] + C.N[0] * idx[1], m);
-  double p[12], lu[12];
+  double p[12], lu[12], lo[12];
 #pragma unroll
   for (int q = 0; q < 12; q++) {
     p[q] = P[q * C.Ntot + c];
@@ -385,31 +411,82 @@ DEV void adj_fixup_own_at(Ctx C, const double* __restrict__ P, const int* __rest
       double s = 0.0;
 #pragma unroll
       for (int q = 0; q < 12; q++) s += lu[q] * ud[q].d[jj];
-      Lam[(4 * pass + jj) * C.Ntot + c] = lamP[(4 * pass + jj) * C.Ntot + c] + s;
+      lo[4 * pass + jj] = lamP[(4 * pass + jj) * C.Ntot + c] + s;
+    }
+  }
+  if (!floored) {
+#pragma unroll
+    for (int q = 0; q < 12; q++) Lam[q * C.Ntot + c] = lo[q];
+    return;
+  }
+  // the state the floors met: the solve's output, with the neighbours' mean
+  // where the cell was averaged (as the forward: the same neighbours, sum
+  // then times 1/count)
+  double pp[12];
+#pragma unroll
+  for (int q = 0; q < 12; q++) pp[q] = Ppre[q * C.Ntot + c];
+  if (fixed) {
+    bool good_pass;
+    const int cnt = fixup_count(C, st, idx, good_pass);
+    double acc[12];
+#pragma unroll
+    for (int q = 0; q < 12; q++) acc[q] = 0.0;
+    for (int d = 0; d < 3; d++) {
+      if (C.n[d] == 1) continue;
+      for (int s = -1; s <= 1; s += 2) {
+        const int nid = idx[d] + s;
+        if (nid < C.ng[d] || nid >= C.ng[d] + C.n[d]) continue;
+        const long nb = c + s * C.st[d];
+        if (good_pass && bad_at(st, nb)) continue;
+#pragma unroll
+        for (int q = 0; q < 12; q++) acc[q] += Ppre[q * C.Ntot + nb];
+      }
+    }
+    const double w = 1.0 / cnt;
+    const bool fc = failed_at(st, c);
+#pragma unroll
+    for (int q = 0; q < 12; q++)
+      if (fc || q == 1) pp[q] = acc[q] * w;
+  }
+  for (int pass = 0; pass < 3; pass++) {
+    D4 pd[12];
+    seed4<12>(pp, 4 * pass, pd);
+    floor_map(C, m, pd);
+#pragma unroll
+    for (int jj = 0; jj < 4; jj++) {
+      double s = 0.0;
+#pragma unroll
+      for (int q = 0; q < 12; q++) s += lo[q] * pd[q].d[jj];
+      Lam[(4 * pass + jj) * C.Ntot + c] = s;
     }
   }
 }
 
+// Ppre (nullable): the state before the fix-ups (the floors' transpose)
 __global__ void LB(128) k_adj_fixup_own(Ctx C, const double* __restrict__ P,
+                                        const double* __restrict__ Ppre,
                                         const int* __restrict__ st, const double* __restrict__ lamP,
                                         const double* __restrict__ lamU, double* __restrict__ Lam) {
-  adj_fixup_own_at(C, P, st, lamP, lamU, Lam, (long)blockIdx.x * blockDim.x + threadIdx.x);
+  adj_fixup_own_at(C, P, Ppre, st, lamP, lamU, Lam, (long)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
-DEV void adj_fixup_at(Ctx C, const int* __restrict__ st, const double* __restrict__ Lam,
-                      const double* __restrict__ lamP, const double* __restrict__ lamU,
-                      double* __restrict__ lamPpre, double* __restrict__ lamUpre, long t) {
+DEV void adj_fixup_at(Ctx C, int exact_floors, const int* __restrict__ st,
+                      const double* __restrict__ Lam, const double* __restrict__ lamP,
+                      const double* __restrict__ lamU, double* __restrict__ lamPpre,
+                      double* __restrict__ lamUpre, long t) {
   if (t >= (long)C.n[0] * C.n[1] * C.n[2]) return;
   int idx[3];
   interior_cell(C, t, idx[0], idx[1], idx[2]);
   const long c = cell_index(C, idx[0], idx[1], idx[2]);
   const bool fixed = fixed_at(C, st, idx);
+  const bool touched = touched_at(C, st, idx, exact_floors != 0);
   const bool fc = fixed && failed_at(st, c);
   const bool bc = bad_at(st, c);
   double acc[12];
 #pragma unroll
   for (int q = 0; q < 12; q++)
-    acc[q] = !fixed ? lamP[q * C.Ntot + c] : ((fc || q == 1) ? 0.0 : Lam[q * C.Ntot + c]);
+    acc[q] = !touched ? lamP[q * C.Ntot + c]
+                      : ((fixed && (fc || q == 1)) ? 0.0 : Lam[q * C.Ntot + c]);
   for (int d = 0; d < 3; d++) {
     if (C.n[d] == 1) continue;
     for (int s = -1; s <= 1; s += 2) {
@@ -433,14 +510,17 @@ DEV void adj_fixup_at(Ctx C, const int* __restrict__ st, const double* __restric
 #pragma unroll
   for (int q = 0; q < 12; q++) {
     lamPpre[q * C.Ntot + c] = acc[q];
-    lamUpre[q * C.Ntot + c] = fixed ? 0.0 : lamU[q * C.Ntot + c];
+    lamUpre[q * C.Ntot + c] = touched ? 0.0 : lamU[q * C.Ntot + c];
   }
 }
 
-__global__ void LB(256) k_adj_fixup(Ctx C, const int* __restrict__ st, const double* __restrict__ Lam,
+// exact_floors: Lam holds the floors' transpose (k_adj_fixup_own with Ppre)
+__global__ void LB(256) k_adj_fixup(Ctx C, int exact_floors, const int* __restrict__ st,
+                                    const double* __restrict__ Lam,
                                     const double* __restrict__ lamP, const double* __restrict__ lamU,
                                     double* __restrict__ lamPpre, double* __restrict__ lamUpre) {
-  adj_fixup_at(C, st, Lam, lamP, lamU, lamPpre, lamUpre, (long)blockIdx.x * blockDim.x + threadIdx.x);
+  adj_fixup_at(C, exact_floors, st, Lam, lamP, lamU, lamPpre, lamUpre,
+               (long)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -952,14 +1032,8 @@ __global__ void LB(256) k_adj_gather_chi(Ctx C, FaceRanges FR, const double* __r
 // whose tracer the forward left undefined (rho0 or u_g not positive) gets
 // nothing.
 // ---------------------------------------------------------------------------
-__global__ void LB(128) k_adj_entropy_field(Ctx C, double b, const double* __restrict__ P,
-                                            const double* __restrict__ lamS,
-                                            double* __restrict__ lamP) {
-  int i, j, k;
-  if (!interior_ijk(C, (long)blockIdx.x * blockDim.x + threadIdx.x, i, j, k)) return;
-  const long c = cell_index(C, i, j, k);
-  const double l = b * lamS[c];
-  if (l == 0.0) return;
+DEV void adj_entropy_at(const Ctx& C, int i, int j, long c, const double* __restrict__ P,
+                       double l, double* __restrict__ lamP) {
   typedef Dual<5> D5;
   D5 pd[5];
 #pragma unroll
@@ -976,6 +1050,16 @@ __global__ void LB(128) k_adj_entropy_field(Ctx C, double b, const double* __res
   for (int q = 0; q < 5; q++) lamP[q * C.Ntot + c] += l * U.d[q];
 }
 
+__global__ void LB(128) k_adj_entropy_field(Ctx C, double b, const double* __restrict__ P,
+                                            const double* __restrict__ lamS,
+                                            double* __restrict__ lamP) {
+  int i, j, k;
+  if (!interior_ijk(C, (long)blockIdx.x * blockDim.x + threadIdx.x, i, j, k)) return;
+  const long c = cell_index(C, i, j, k);
+  const double l = b * lamS[c];
+  if (l != 0.0) adj_entropy_at(C, i, j, c, P, l, lamP);
+}
+
 // y += alpha x at interior cells, one field
 __global__ void LB(256) k_adj_axpy1(Ctx C, double alpha, const double* __restrict__ x,
                                     double* __restrict__ y) {
@@ -983,6 +1067,36 @@ __global__ void LB(256) k_adj_axpy1(Ctx C, double alpha, const double* __restric
   if (!interior_ijk(C, (long)blockIdx.x * blockDim.x + threadIdx.x, i, j, k)) return;
   const long c = cell_index(C, i, j, k);
   y[c] += alpha * x[c];
+}
+
+// The IMEX tables' stored entropy source M_S = (U_S(P_out) - Se)/(g dt),
+// zero where the solve failed: its cotangent lamMS handed to one side at
+// the cells whose solve did not fail, side 0 lamP[q] += dU_S/dP_q lamMS /
+// (g dt) (P_out, before the implicit solve's transpose), side 1 lamS -=
+// lamMS / (g dt) (Se, after it).
+__global__ void LB(128) k_adj_stage_ms(Ctx C, int side, double g, const double* __restrict__ dt_dev,
+                                       const int* __restrict__ st, const double* __restrict__ P,
+                                       const double* __restrict__ lamMS,
+                                       double* __restrict__ lamP, double* __restrict__ lamS) {
+  int i, j, k;
+  if (!interior_ijk(C, (long)blockIdx.x * blockDim.x + threadIdx.x, i, j, k)) return;
+  const long c = cell_index(C, i, j, k);
+  if (st[c] & GRRMHD_ST_FAIL) return;
+  const double l = lamMS[c] / (g * (*dt_dev));
+  if (l == 0.0) return;
+  if (side)
+    lamS[c] -= l;
+  else
+    adj_entropy_at(C, i, j, c, P, l, lamP);
+}
+
+// y += m dt x at interior cells, one field (a bracket's dt m_k M_S^k term)
+__global__ void LB(256) k_adj_axpy1_dt(Ctx C, double m, const double* __restrict__ dt_dev,
+                                       const double* __restrict__ x, double* __restrict__ y) {
+  int i, j, k;
+  if (!interior_ijk(C, (long)blockIdx.x * blockDim.x + threadIdx.x, i, j, k)) return;
+  const long c = cell_index(C, i, j, k);
+  y[c] += m * (*dt_dev) * x[c];
 }
 
 // ---------------------------------------------------------------------------

@@ -1114,8 +1114,8 @@ extern "C" int grrmhd_fluxes_staggered(grrmhd_grid* g, const double* P, const do
 // ---------------------------------------------------------------------------
 struct AdjLayout {
   size_t F, emf, vch, scr, err, it, Un, Pb, Ue, Pk, Uk, stk, lamP, lamU, lamUe, lamUn, lamPb, lamE,
-      G, Gx, Lam, lamPpre, lamUpre, M, lamUs, lamM, lamPg, Pc, FL, GF, LamFl, Lf2, Se, Fs, Sn,
-      lamS, lamSn, total;
+      G, Gx, Lam, lamPpre, lamUpre, M, lamUs, lamM, lamPg, Pq, FL, GF, LamFl, Lf2, Se, Fs, Sn,
+      lamS, lamSn, MS, lamMS, total;
   int ns;   // stages checkpointed
 };
 
@@ -1124,7 +1124,7 @@ static int adj_slots(const Ctx& C) { return C.recon == GRRMHD_RECON_PPM ? 6 : 4;
 
 // RK3 keeps three stages; an IMEX scheme its own count, plus the stored
 // sources M^k, their cotangents, the per-stage cotangents of U(i) and the
-// final inversion's guess cotangent and result.  PPM adds the flattener of
+// final inversion's guess cotangent.  PPM adds the flattener of
 // every stage, the faces' products with it and two flattener cotangents.
 static AdjLayout adj_layout(const Ctx& C, int scheme) {
   AdjLayout w;
@@ -1166,19 +1166,22 @@ static AdjLayout adj_layout(const Ctx& C, int scheme) {
   w.lamUs = take(imex ? D8 * 12 * ns * N : 0);
   w.lamM = take(imex ? D8 * 4 * 8 * N : 0);
   w.lamPg = take(imex ? D8 * 12 * N : 0);
-  w.Pc = take(imex ? D8 * 12 * N : 0);
+  w.Pq = take(D8 * 12 * ns * N);   // per stage: output primitives before the fix-ups
   w.FL = take(ppm ? D8 * 6 * ns * N : 0);   // per stage: the flattener its fluxes read
   w.GF = take(ppm ? D8 * 12 * N : 0);       // per direction: face products with the flattener
   w.LamFl = take(ppm ? D8 * 6 * N : 0);     // cotangent of the flattener read, carried back
   w.Lf2 = take(ppm ? D8 * 6 * N : 0);       // cotangent of a stage's own flattener
   // the full cascade's entropy tracer: each stage's explicit value, the face
-  // fluxes, U_S(P^n), and the cotangents of a stage's value and of U_S(P^n)
+  // fluxes, U_S(P^n), and the cotangents of a stage's value and of U_S(P^n);
+  // an IMEX scheme adds the stored entropy sources and their cotangents
   const bool ent = C.cascade != 0;
   w.Se = take(ent ? D8 * ns * N : 0);
   w.Fs = take(ent ? D8 * 3 * N : 0);
   w.Sn = take(ent ? D8 * N : 0);
   w.lamS = take(ent ? D8 * N : 0);
   w.lamSn = take(ent ? D8 * N : 0);
+  w.MS = take(ent && imex ? D8 * 4 * N : 0);
+  w.lamMS = take(ent && imex ? D8 * 4 * N : 0);
   w.total = off;
   return w;
 }
@@ -1422,9 +1425,9 @@ extern "C" int grrmhd_fixup_vjp(grrmhd_grid* g, const double* P, const int* stat
   int rc;
   if ((rc = fill_d(g, gP_pre, N12, 0.0)) || (rc = fill_d(g, gU_pre, N12, 0.0))) return rc;
   hipLaunchKernelGGL(k_adj_fixup_own, dim3(nblocks(nint, 128)), dim3(128), 0, g->stream, C, P,
-                     status, gP, gU, scratch);
+                     (const double*)nullptr, status, gP, gU, scratch);
   LAUNCHCHK();
-  hipLaunchKernelGGL(k_adj_fixup, dim3(nblocks(nint, 256)), dim3(256), 0, g->stream, C, status,
+  hipLaunchKernelGGL(k_adj_fixup, dim3(nblocks(nint, 256)), dim3(256), 0, g->stream, C, 0, status,
                      (const double*)scratch, gP, gU, gP_pre, gU_pre);
   LAUNCHCHK();
   return 0;
@@ -1450,13 +1453,19 @@ extern "C" int grrmhd_con2prim_vjp(grrmhd_grid* g, const double* U, const double
 struct AdjPtrs {
   double *F, *emf, *vch, *scr, *err, *Un, *Pb, *Ue, *Pk, *Uk;
   double *lamP, *lamU, *lamUe, *lamUn, *lamPb, *lamE, *G, *Gx, *Lam, *lamPpre, *lamUpre;
-  double *M, *lamUs, *lamM, *lamPg, *Pc, *FL, *GF, *LamFl, *Lf2, *Se, *Fs, *Sn, *lamS, *lamSn;
+  double *M, *lamUs, *lamM, *lamPg, *Pq, *FL, *GF, *LamFl, *Lf2, *Se, *Fs, *Sn, *lamS, *lamSn;
+  double *MS, *lamMS;
   int *it, *stk;
 };
 
 static int adj_ptrs(grrmhd_grid* g, void* workspace, size_t ws_bytes, AdjPtrs& a) {
-  if (g->p.cascade != 0 && g->p.scheme != GRRMHD_RK3)
-    return fail(GRRMHD_EINVAL, "the adjoint covers the full cascade (cascade = 1) with RK3 only");
+  if (g->p.cascade != 0 && g->p.scheme != GRRMHD_RK3) {
+    // the tracer's b term is the stage input's U_S, the previous stage's
+    const Scheme S = make_scheme(g->p.scheme);
+    for (int i = 0; i < S.ns; i++)
+      if (S.s[i].g > 0.0 && S.s[i].b != 0.0 && S.s[i].j != i - 1)
+        return fail(GRRMHD_EINVAL, "entropy tracer: a stage's b term must take the previous stage");
+  }
   if (g->C.ct)
     return fail(GRRMHD_EINVAL, "the adjoint covers the flux-CT field (ct = GRRMHD_CT_FLUX)");
   const AdjLayout w = adj_layout(g->C, g->p.scheme);
@@ -1490,7 +1499,7 @@ static int adj_ptrs(grrmhd_grid* g, void* workspace, size_t ws_bytes, AdjPtrs& a
   a.lamUs = (double*)(base + w.lamUs);
   a.lamM = (double*)(base + w.lamM);
   a.lamPg = (double*)(base + w.lamPg);
-  a.Pc = (double*)(base + w.Pc);
+  a.Pq = (double*)(base + w.Pq);
   a.FL = (double*)(base + w.FL);
   a.GF = (double*)(base + w.GF);
   a.LamFl = (double*)(base + w.LamFl);
@@ -1500,6 +1509,8 @@ static int adj_ptrs(grrmhd_grid* g, void* workspace, size_t ws_bytes, AdjPtrs& a
   a.Sn = (double*)(base + w.Sn);
   a.lamS = (double*)(base + w.lamS);
   a.lamSn = (double*)(base + w.lamSn);
+  a.MS = (double*)(base + w.MS);
+  a.lamMS = (double*)(base + w.lamMS);
   return 0;
 }
 
@@ -1530,7 +1541,7 @@ static const double ADJ_A[3] = {1.0, 0.75, 1.0 / 3.0}, ADJ_B[3] = {0.0, 0.25, 2.
 
 // Forward step with checkpoints (the same launches as grrmhd_step, dt fixed):
 // per stage the ghost-filled input P, the explicit state, the output P, U
-// and status.  P_next/U_next (nullable) get the result; U_next's ghost
+// and status, and the output P before the fix-ups.  P_next/U_next (nullable) get the result; U_next's ghost
 // entries are those of U(P_n), as grrmhd_step leaves them.
 static int adj_forward(grrmhd_grid* g, const double* P_n, const double* chi_abs,
                        const double* chi_es, const double* dt_dev, double* P_next, double* U_next,
@@ -1575,6 +1586,7 @@ static int adj_forward(grrmhd_grid* g, const double* P_n, const double* chi_abs,
     if ((rc = launch_implicit(g, Uek, Pin, ADJ_C[k], dt_dev, chi_abs, chi_es, Pout, Uout, a.it, st,
                               a.err, Sek)))
       return rc;
+    HIPCHK(hipMemcpyAsync(a.Pq + k * N12, Pout, B12, hipMemcpyDeviceToDevice, s));
     if ((rc = launch_fixup(g, Pout, Uout, st, a.scr, nullptr, a.it, nullptr, 0))) return rc;
   }
   if (P_next) HIPCHK(hipMemcpyAsync(P_next, a.Pk + 2 * N12, B12, hipMemcpyDeviceToDevice, s));
@@ -1609,15 +1621,16 @@ static int adj_reverse(grrmhd_grid* g, const double* chi_abs, const double* chi_
   for (int k = 2; k >= 0; k--) {
     const double* Pin = a.Pb + k * N12;
     // fix-up of failed and cold cells, then the implicit solve
+    const double* Pq = a.Pq + k * N12;   // the solve's output
     hipLaunchKernelGGL(k_adj_fixup_own, dim3(nblocks(nint, 128)), dim3(128), 0, s, C,
-                       (const double*)(a.Pk + k * N12), (const int*)(a.stk + k * N),
+                       (const double*)(a.Pk + k * N12), Pq, (const int*)(a.stk + k * N),
                        (const double*)a.lamP, (const double*)a.lamU, a.Lam);
     LAUNCHCHK();
-    hipLaunchKernelGGL(k_adj_fixup, dim3(gi), dim3(256), 0, s, C, (const int*)(a.stk + k * N),
+    hipLaunchKernelGGL(k_adj_fixup, dim3(gi), dim3(256), 0, s, C, 1, (const int*)(a.stk + k * N),
                        (const double*)a.Lam, (const double*)a.lamP, (const double*)a.lamU,
                        a.lamPpre, a.lamUpre);
     LAUNCHCHK();
-    if ((rc = adj_implicit(g, ADJ_C[k], dt_dev, a.Ue + k * N12, a.Pk + k * N12, a.stk + k * N,
+    if ((rc = adj_implicit(g, ADJ_C[k], dt_dev, a.Ue + k * N12, Pq, a.stk + k * N,
                            chi_abs, chi_es, a.lamPpre, a.lamUpre, a.lamUe, g_chi,
                            ent ? a.Se + k * N : nullptr, ent ? a.lamS : nullptr)))
       return rc;
@@ -1653,8 +1666,9 @@ static int adj_reverse(grrmhd_grid* g, const double* chi_abs, const double* chi_
 
 // IMEX schemes.  Forward: the launches of imex_step with dt fixed, keeping
 // per stage the input P (ghost-filled where the stage has a flux), the
-// explicit state, the output P, U and status, the stored sources M^k, and
-// the final inversion's result before its fix-up.
+// explicit state, the output P, U and status, the output P before the
+// fix-ups, the stored sources M^k; with the full cascade also
+// each implicit stage's explicit entropy tracer and the stored M_S^k.
 static int adj_forward_imex(grrmhd_grid* g, const double* P_n, const double* chi_abs,
                             const double* chi_es, const double* dt_dev, double* P_next,
                             double* U_next, const AdjPtrs& a) {
@@ -1667,6 +1681,12 @@ static int adj_forward_imex(grrmhd_grid* g, const double* P_n, const double* chi
   HIPCHK(hipMemcpyAsync(a.Pb, P_n, B12, hipMemcpyDeviceToDevice, s));
   hipLaunchKernelGGL(k_p2u, dim3(nblocks(C.Ntot, 256)), dim3(256), 0, s, C, a.Pb, a.Un);
   LAUNCHCHK();
+  const bool ent = C.cascade != 0;
+  if (ent) {
+    hipLaunchKernelGGL(k_entropy_field, dim3(nblocks(nint, 256)), dim3(256), 0, s, C,
+                       (const double*)a.Pb, a.Sn);
+    LAUNCHCHK();
+  }
   int nflux = 0;
   for (int i = 0; i < S.ns; i++) {
     const Stage& x = S.s[i];
@@ -1678,7 +1698,8 @@ static int adj_forward_imex(grrmhd_grid* g, const double* P_n, const double* chi
     if (i > 0) HIPCHK(hipMemcpyAsync(Pin, a.Pk + (i - 1) * N12, B12, hipMemcpyDeviceToDevice, s));
     if (x.c != 0.0) {
       if ((rc = launch_bc(g, Pin))) return rc;
-      if ((rc = launch_fluxes(g, Pin, chi_abs, chi_es, a.F, a.emf, a.vch, nullptr, nflux > 0)))
+      if ((rc = launch_fluxes(g, Pin, chi_abs, chi_es, a.F, a.emf, a.vch, nullptr, nflux > 0,
+                              ent ? a.Fs : nullptr)))
         return rc;
       if ((rc = adj_keep_flat(g, a, i))) return rc;
       nflux++;
@@ -1695,23 +1716,45 @@ static int adj_forward_imex(grrmhd_grid* g, const double* P_n, const double* chi
     if ((rc = launch_update(g, x.a, x.b, x.c, dt_dev, Pin, a.Un, Uj, a.F, a.emf, Uei, nullptr,
                             nullptr, &MT)))
       return rc;
+    double* Sei = (ent && x.g > 0.0) ? a.Se + i * N : nullptr;
+    if (Sei) {
+      hipLaunchKernelGGL(k_entropy_update, dim3(nblocks(nint, 256)), dim3(256), 0, s, C, x.a, x.b,
+                         x.c, dt_dev, (const double*)a.Sn, (const double*)Pin,
+                         (const double*)a.Fs, Sei);
+      LAUNCHCHK();
+      if (MT.n > 0) {
+        MTerms MS = MT;
+        for (int q = 0, k = 0; k < i && k < 4; k++)
+          if (x.m[k] != 0.0) MS.M[q++] = a.MS + k * N;
+        hipLaunchKernelGGL(k_entropy_mterms, dim3(nblocks(nint, 256)), dim3(256), 0, s, C, MS,
+                           dt_dev, Sei);
+        LAUNCHCHK();
+      }
+    }
     HIPCHK(hipMemcpyAsync(Pout, Pin, B12, hipMemcpyDeviceToDevice, s));
     HIPCHK(hipMemcpyAsync(Uout, Uei, B12, hipMemcpyDeviceToDevice, s));
     if (x.g > 0.0) {
       if ((rc = launch_implicit(g, Uei, Pin, x.g, dt_dev, chi_abs, chi_es, Pout, Uout, a.it, st,
-                                a.err)))
+                                a.err, Sei)))
         return rc;
+      HIPCHK(hipMemcpyAsync(a.Pq + i * N12, Pout, B12, hipMemcpyDeviceToDevice, s));
       if (i < 4 && S.keep_m[i]) {
         hipLaunchKernelGGL(k_stage_m, dim3(nblocks(nint, 256)), dim3(256), 0, s, C, Uei, Uout, st,
                            x.g, dt_dev, a.M + i * 8 * N);
         LAUNCHCHK();
+        if (ent) {
+          hipLaunchKernelGGL(k_stage_ms, dim3(nblocks(nint, 256)), dim3(256), 0, s, C,
+                             (const double*)Pout, (const double*)Sei, (const int*)st, x.g, dt_dev,
+                             a.MS + i * N);
+          LAUNCHCHK();
+        }
       }
       if ((rc = launch_fixup(g, Pout, Uout, st, a.scr, nullptr, a.it, nullptr, 0))) return rc;
     } else {
       hipLaunchKernelGGL(k_con2prim, dim3(nblocks(nint, 128)), dim3(128), 0, s, C, Uei,
                          (const double*)Pin, Pout, st, (int)GRRMHD_ST_FAIL);
       LAUNCHCHK();
-      HIPCHK(hipMemcpyAsync(a.Pc, Pout, B12, hipMemcpyDeviceToDevice, s));
+      HIPCHK(hipMemcpyAsync(a.Pq + i * N12, Pout, B12, hipMemcpyDeviceToDevice, s));
       if ((rc = launch_fixup(g, Pout, Uout, st, a.scr, nullptr, nullptr, nullptr, 0))) return rc;
     }
   }
@@ -1731,7 +1774,12 @@ static int adj_forward_imex(grrmhd_grid* g, const double* P_n, const double* chi
 // M^i = (U(i) - U_e)/(g dt) taken before the fix-up) or the final
 // inversion's; then the stage bracket U_e = a U^n + b U(j) + c dt X(P_in)
 // + dt sum_k m_k M^k, which hands cotangents to U^n, U(j), the earlier M^k
-// and through the fluxes to the stage input P_in.
+// and through the fluxes to the stage input P_in.  The full cascade's
+// entropy tracer runs beside it: M_S^i = (U_S(P_out) - S_e)/(g dt) splits
+// its cotangent over the solve's output P and its tracer S_e, and the
+// tracer's bracket a U_S(P^n) + b U_S(P_in) + c dt (-div F_S) + dt sum_k m_k
+// M_S^k hands its cotangent to U_S(P^n), P_in (its b term and face fluxes)
+// and the earlier M_S^k.
 static int adj_reverse_imex(grrmhd_grid* g, const double* chi_abs, const double* chi_es,
                             const double* dt_dev, const double* gU_next, double* gP_n,
                             double* g_chi, const AdjPtrs& a) {
@@ -1749,6 +1797,10 @@ static int adj_reverse_imex(grrmhd_grid* g, const double* chi_abs, const double*
   if (g_chi && (rc = fill_d(g, g_chi, 2 * N, 0.0))) return rc;
   const bool ppm = C.recon == GRRMHD_RECON_PPM;
   if (ppm && (rc = fill_d(g, a.LamFl, 6 * N, 0.0))) return rc;
+  const bool ent = C.cascade != 0;
+  if (ent && ((rc = fill_d(g, a.lamS, N, 0.0)) || (rc = fill_d(g, a.lamSn, N, 0.0)) ||
+              (rc = fill_d(g, a.lamMS, 4 * N, 0.0))))
+    return rc;
   hipLaunchKernelGGL(k_copy_interior, dim3(ga), dim3(256), 0, s, C, gU_next,
                      a.lamUs + (S.ns - 1) * N12);
   LAUNCHCHK();
@@ -1759,12 +1811,14 @@ static int adj_reverse_imex(grrmhd_grid* g, const double* chi_abs, const double*
     const double* Uei = a.Ue + i * N12;
     const int* st = a.stk + i * N;
     const double* lamUo = a.lamUs + i * N12;
-    hipLaunchKernelGGL(k_adj_fixup_own, dim3(nblocks(nint, 128)), dim3(128), 0, s, C, Pk, st,
+    const double* Pq = a.Pq + i * N12;   // the solve's or inversion's output
+    hipLaunchKernelGGL(k_adj_fixup_own, dim3(nblocks(nint, 128)), dim3(128), 0, s, C, Pk, Pq, st,
                        (const double*)a.lamP, lamUo, a.Lam);
     LAUNCHCHK();
-    hipLaunchKernelGGL(k_adj_fixup, dim3(gi), dim3(256), 0, s, C, st, (const double*)a.Lam,
+    hipLaunchKernelGGL(k_adj_fixup, dim3(gi), dim3(256), 0, s, C, 1, st, (const double*)a.Lam,
                        (const double*)a.lamP, lamUo, a.lamPpre, a.lamUpre);
     LAUNCHCHK();
+    const bool tr = ent && x.g > 0.0;   // the stage has an entropy tracer
     if (x.g > 0.0) {
       const bool km = i < 4 && S.keep_m[i];
       double* lamMi = a.lamM + i * 8 * N;
@@ -1773,12 +1827,22 @@ static int adj_reverse_imex(grrmhd_grid* g, const double* chi_abs, const double*
                            (const double*)lamMi, a.lamUpre);
         LAUNCHCHK();
       }
-      if ((rc = adj_implicit(g, x.g, dt_dev, Uei, Pk, st, chi_abs, chi_es, a.lamPpre, a.lamUpre,
-                             a.lamUe, g_chi)))
+      if (km && ent) {
+        hipLaunchKernelGGL(k_adj_stage_ms, dim3(nblocks(nint, 128)), dim3(128), 0, s, C, 0, x.g,
+                           dt_dev, st, Pq, (const double*)(a.lamMS + i * N), a.lamPpre, nullptr);
+        LAUNCHCHK();
+      }
+      if ((rc = adj_implicit(g, x.g, dt_dev, Uei, Pq, st, chi_abs, chi_es, a.lamPpre, a.lamUpre,
+                             a.lamUe, g_chi, tr ? a.Se + i * N : nullptr, tr ? a.lamS : nullptr)))
         return rc;
       if (km) {
         hipLaunchKernelGGL(k_adj_mscatter, dim3(gi), dim3(256), 0, s, C, -1.0 / x.g, dt_dev, st,
                            (const double*)lamMi, a.lamUe);
+        LAUNCHCHK();
+      }
+      if (km && ent) {
+        hipLaunchKernelGGL(k_adj_stage_ms, dim3(nblocks(nint, 128)), dim3(128), 0, s, C, 1, x.g,
+                           dt_dev, st, Pq, (const double*)(a.lamMS + i * N), nullptr, a.lamS);
         LAUNCHCHK();
       }
     } else {
@@ -1787,7 +1851,7 @@ static int adj_reverse_imex(grrmhd_grid* g, const double* chi_abs, const double*
       LAUNCHCHK();
       if ((rc = fill_d(g, a.lamPg, N12, 0.0))) return rc;
       hipLaunchKernelGGL(k_adj_c2p, dim3(nblocks(nint, 64)), dim3(64), 0, s, C, Uei,
-                         (const double*)a.Pc, st, (const double*)a.lamPpre, a.lamUe, a.lamPg);
+                         Pq, st, (const double*)a.lamPpre, a.lamUe, a.lamPg);
       LAUNCHCHK();
     }
     hipLaunchKernelGGL(k_adj_axpy12, dim3(gi), dim3(256), 0, s, C, x.a, (const double*)a.lamUe,
@@ -1804,20 +1868,35 @@ static int adj_reverse_imex(grrmhd_grid* g, const double* chi_abs, const double*
       hipLaunchKernelGGL(k_adj_mterm, dim3(gi), dim3(256), 0, s, C, x.m[k], dt_dev,
                          (const double*)a.lamUe, a.lamM + k * 8 * N);
       LAUNCHCHK();
+      if (tr) {
+        hipLaunchKernelGGL(k_adj_axpy1_dt, dim3(gi), dim3(256), 0, s, C, x.m[k], dt_dev,
+                           (const double*)a.lamS, a.lamMS + k * N);
+        LAUNCHCHK();
+      }
+    }
+    if (tr) {   // the tracer's a U_S(P^n) term
+      hipLaunchKernelGGL(k_adj_axpy1, dim3(gi), dim3(256), 0, s, C, x.a, (const double*)a.lamS,
+                         a.lamSn);
+      LAUNCHCHK();
     }
     if (x.c != 0.0) {
       int prev = i - 1;   // the step's previous flux evaluation
       while (prev >= 0 && S.s[prev].c == 0.0) prev--;
       const AdjFlat F = adj_flat_of(g, a, i, prev);
       if ((rc = adj_explicit(g, x.c, dt_dev, Pin, chi_abs, chi_es, a.lamUe, a.lamE, a.G, a.lamPb,
-                             Gx, g_chi, ppm ? &F : nullptr)))
+                             Gx, g_chi, ppm ? &F : nullptr, tr ? a.lamS : nullptr, x.b)))
         return rc;
       if ((rc = adj_bc(g, a.lamPb))) return rc;
       hipLaunchKernelGGL(k_copy_interior, dim3(ga), dim3(256), 0, s, C, (const double*)a.lamPb,
                          a.lamP);
       LAUNCHCHK();
-    } else if ((rc = fill_d(g, a.lamP, N12, 0.0))) {
-      return rc;
+    } else {
+      if ((rc = fill_d(g, a.lamP, N12, 0.0))) return rc;
+      if (tr && x.b != 0.0) {   // the tracer's b U_S(P_in) term without a flux
+        hipLaunchKernelGGL(k_adj_entropy_field, dim3(nblocks(nint, 128)), dim3(128), 0, s, C, x.b,
+                           Pin, (const double*)a.lamS, a.lamP);
+        LAUNCHCHK();
+      }
     }
     if (x.g <= 0.0) {   // a failed inversion's result was its guess, P_in
       hipLaunchKernelGGL(k_adj_axpy12, dim3(gi), dim3(256), 0, s, C, 1.0, (const double*)a.lamPg,
@@ -1828,6 +1907,11 @@ static int adj_reverse_imex(grrmhd_grid* g, const double* chi_abs, const double*
   hipLaunchKernelGGL(k_adj_p2u, dim3(nblocks(nint, 128)), dim3(128), 0, s, C, (const double*)a.Pb,
                      (const double*)a.lamUn, a.lamP);
   LAUNCHCHK();
+  if (ent) {   // U_S(P^n) of every stage's tracer
+    hipLaunchKernelGGL(k_adj_entropy_field, dim3(nblocks(nint, 128)), dim3(128), 0, s, C, 1.0,
+                       (const double*)a.Pb, (const double*)a.lamSn, a.lamP);
+    LAUNCHCHK();
+  }
   hipLaunchKernelGGL(k_copy_interior, dim3(ga), dim3(256), 0, s, C, (const double*)a.lamP, gP_n);
   LAUNCHCHK();
   return 0;
