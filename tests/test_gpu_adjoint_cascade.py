@@ -78,16 +78,27 @@ def test_step_adjoint_full_cascade_entropy_cells(G, orc, scheme):
     derivative), and most of them take URAD at some stage, whose solve stops
     at its own tolerance, so a difference quotient carries noise of order
     that tolerance over the step; no neighbourhood here is free of URAD.  A
-    norm over all components would measure that noise; the test takes the
-    components whose quotients at the step and at a third of it agree to
-    1e-6 (a smooth, converged step's quotients agree far closer, as their
-    truncation error is second order; noise grows as the step shrinks) and
+    norm over all components would measure that noise; the test takes every
+    gas and radiation component of the cells within two of an entropy-method
+    cell, keeps those whose quotients at the step and at a third of it agree
+    to 1e-6 (a smooth, converged step's quotients agree far closer, as their
+    truncation error is second order; noise grows as the step shrinks), and
     requires their median relative error below 1e-6, also over those next
-    to an entropy-method cell (at least 8 of them).  In the IMEX tables a
-    stage's tracer carries the entropy sources M_S^k stored by the earlier
-    implicit stages, so the cotangents also run through them; the IMEX
-    tables floor many of the box's cells (their stages extrapolate with
-    negative weights on U^n), so this also exercises the floors' transpose."""
+    to an entropy-method cell (at least 20).  In the IMEX tables a stage's
+    tracer carries the entropy sources M_S^k stored by the earlier implicit
+    stages, whose cotangents reach the output only through later
+    entropy-method solutions, so a few components carry them, which a
+    median would not see: there the components next to an entropy-method
+    cell also have their 90th percentile below 1e-6 and at most 2% above
+    1e-5 (with the M_S^k transpose dropped the percentile is 5.7e-5 and 10
+    of 79 are above 1e-5).  On RK3's box the one staged entropy-method
+    solution gives the components within seven cells of it errors up to
+    2e-3 that are the same at h, h/3 and h/9: the staged attempt's
+    corrected and best-kept iterate is differentiated as a root of its
+    equations, which it need not be, so the tail bounds are not applied
+    there.  The IMEX tables also floor many of the box's cells (their stages
+    extrapolate with negative weights on U^n), so this exercises the floors'
+    transpose too."""
     from test_gpu_adjoint import dev, fd_rows, host, interior_idx, step_dt
 
     say("case step adjoint, full cascade, batch box entropy cells", scheme)
@@ -114,7 +125,7 @@ def test_step_adjoint_full_cascade_entropy_cells(G, orc, scheme):
 
     scale = np.abs(P[:, idx]).max(axis=1)
     qs = [0, 1, 2, 3, 4, 8, 9, 10, 11]   # the box has no magnetic field
-    comps = [(int(qs[r.integers(len(qs))]), int(cells[r.integers(cells.size)])) for _ in range(96)]
+    comps = [(q, int(c)) for c in cells for q in qs]
     fd = fd_rows(comps, P, scale, U_gpu, w[:, idx])
     fd3 = fd_rows(comps, P, scale, U_gpu, w[:, idx], f=1 / 3)
     g.close()
@@ -122,10 +133,14 @@ def test_step_adjoint_full_cascade_entropy_cells(G, orc, scheme):
     adj = np.array([gP[q, c] for q, c in comps])
     rel = np.abs(adj - fd) / np.abs(fd)
     near = np.array([((st[c - 1:c + 2] & G.ST_ENTROPY) != 0).any() for q, c in comps])
+    sn = rel[smooth & near]
     say(f"  smooth {smooth.sum()} of {len(comps)}; median rel error {np.median(rel[smooth]):.2e}; "
-        f"next to entropy cells {(smooth & near).sum()}, median {np.median(rel[smooth & near]):.2e}")
-    assert smooth.sum() >= 24 and np.median(rel[smooth]) < 1e-6
-    assert (smooth & near).sum() >= 8 and np.median(rel[smooth & near]) < 1e-6
+        f"next to entropy cells {sn.size}: median {np.median(sn):.2e}, 90th percentile "
+        f"{np.quantile(sn, 0.9):.2e}, max {sn.max():.2e}, above 1e-5 {(sn > 1e-5).sum()}")
+    assert smooth.sum() >= 40 and np.median(rel[smooth]) < 1e-6
+    assert sn.size >= 20 and np.median(sn) < 1e-6
+    if scheme != "rk3":
+        assert np.quantile(sn, 0.9) < 1e-6 and (sn > 1e-5).sum() <= 0.02 * sn.size
 
 
 def test_opacity_gradient_full_cascade_box(G, orc):
