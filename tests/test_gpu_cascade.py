@@ -125,7 +125,7 @@ def test_batch_full_cascade_forms_identical(G, orc, form):
         assert np.array_equal(a.view(np.uint8), b.view(np.uint8))
 
 
-@pytest.mark.parametrize("scheme", ["rk3", "imex2", "imex3"])
+@pytest.mark.parametrize("scheme", ["rk3", "imex2", "imex2b", "imex3"])
 def test_step_full_cascade_batch_box(G, orc, scheme):
     """One step of the box: the explicit entropy tracer (face fluxes and
     stage combination) and the whole cascade on the grid path.  Neighbours
