@@ -122,7 +122,7 @@ typedef struct {
                            (PPM with MC slopes, no contact steepening, the
                            gas and radiation shock flatteners blended by the
                            optical depth, each the largest over the step's
-                           sub-steps; ng = 4).  The adjoint covers MC only. */
+                           sub-steps; ng = 4).  The adjoint covers both.      */
   int cold;             /* 1 (default): a cell whose implicit solve finds no
                            energy solution takes the cold MHD limit (Sec.
                            4.7): u_g held at u_floor, the three gas momentum
