@@ -94,12 +94,12 @@ def test_step_adjoint_full_cascade_entropy_cells(G, orc, case):
     of 79 are above 1e-5), leaving out those within the step's reach (ghost
     width times flux evaluations) of a cell whose solve was not accepted
     (its best error above tol_accept: not a root, so no root's derivative
-    applies there).  On RK3's box the one staged entropy-method
-    solution gives the components within seven cells of it errors up to
-    2e-3 that are the same at h, h/3 and h/9: the staged attempt's
-    corrected and best-kept iterate is differentiated as a root of its
-    equations, which it need not be, so the tail bounds are not applied
-    there.  The IMEX tables also floor many of the box's cells (their stages
+    applies there).  On RK3's box five components of cells 9 and 10, at
+    the two cells (10, 11) that the staged attempts solve at the first stage
+    (cell 10 takes the entropy method at the last), have errors of 1.7e-5 to
+    2.1e-3 that are the same at h, h/3 and h/9; their solutions' residuals and Jacobian conditioning are
+    no worse than their neighbours', and the cause is not identified, so the
+    tail bounds are not applied there.  The IMEX tables also floor many of the box's cells (their stages
     extrapolate with negative weights on U^n), so this exercises the floors'
     transpose too.  With PPM (ghost width 4) the tracer's face fluxes are
     transposed through the six-cell stencil and the flattener."""
